@@ -1,0 +1,244 @@
+"""Pins for the oracle residuals against the paper's theorems (Sec. 4-6)."""
+import numpy as np
+import pytest
+
+from oracle import physics as ph
+from oracle.geometry import OracleMesh
+from oracle.residual import OracleScheme
+from paper_2305_07181_amd import workloads as wl
+
+EPS = np.finfo(float).eps
+
+
+def cons_state(m, seed=3, jitter=0.0, L=None):
+    x = m.node_coords()
+    L = m.period[0] if L is None else L
+    rho, V, p = wl.random_smooth_state(np.moveaxis(x, 1, 0), seed=seed, L=L)
+    u = np.moveaxis(wl.conservative(rho, V, p), 0, 1)
+    if jitter:
+        u = u * (1 + jitter * np.random.default_rng(seed).standard_normal(u.shape))
+    return u
+
+
+def rate_tol(scheme, u, r):
+    """Roundoff scale of sum w^T H r: 64 eps sum_nodes H |w|.|r|."""
+    tot = 0.0
+    for e in range(scheme.mesh.ne):
+        w = ph.entropy_vars(u[e], scheme.gas)
+        tot += np.sum(scheme.mesh.geometry(e)["H"] * np.sum(np.abs(w * r[e]), 0))
+    return 64 * EPS * tot
+
+
+CASES = [("tri-affine", lambda: wl.periodic_tri_mesh(3, 3, 2.0), [1, 2, 3, 4]),
+         ("tri-curved", lambda: wl.vortex2d_mesh(3, warp=0.05), [1, 2, 3, 4]),
+         ("tet-affine", lambda: wl.periodic_tet_mesh(2, 1.0), [1, 2, 3])]
+IDS = [c[0] for c in CASES]
+
+
+@pytest.mark.parametrize("name,make,ps", CASES, ids=IDS)
+def test_free_stream(name, make, ps):
+    desc = make()
+    gas = ph.Gas()
+    for p in ps:
+        m = OracleMesh(desc, p)
+        d = m.dim
+        U = np.zeros((m.ne, d + 2, m.n_p))
+        U[:, 0] = 1.2
+        V = np.array([0.3, -0.2, 0.1][:d])
+        U[:, 1:1 + d] = 1.2 * V[None, :, None]
+        U[:, d + 1] = 0.9 / 0.4 + 0.5 * 1.2 * V @ V
+        # roundoff scale of one operator application: n_p eps max|D| max|F|
+        dmax = max(np.abs(m.geometry(e)["Dx"]).max() for e in range(m.ne))
+        tol = 8 * m.n_p * EPS * dmax * np.abs(U).max()
+        for kw in (dict(), dict(form="hadamard"), dict(dissipation=True), dict(viscous=True)):
+            r = OracleScheme(m, ph.Gas(mu=0.01), **kw)(U)
+            assert np.abs(r).max() < tol, (p, kw, np.abs(r).max(), tol)
+
+
+@pytest.mark.parametrize("name,make,ps", CASES, ids=IDS)
+def test_entropy_conservation_and_stability(name, make, ps):
+    """Thm. entropy conservation (split) and the SY Hadamard form: sum w^T H r
+    = 0 to roundoff on periodic meshes, for continuous and discontinuous
+    states; with interface dissipation (Sec. 4.4) and with heat-flux-free
+    viscous BO terms (Thm. entropy stability nse) the rate is <= 0."""
+    desc = make()
+    for p in ps:
+        m = OracleMesh(desc, p)
+        for jitter in (0.0, 0.02):
+            u = cons_state(m, jitter=jitter)
+            for form in ("split", "hadamard"):
+                s = OracleScheme(m, ph.Gas(), form=form)
+                r = s(u)
+                assert abs(s.entropy_rate(u, r)) <= rate_tol(s, u, r), (p, form, jitter)
+            s = OracleScheme(m, ph.Gas(), dissipation=True)
+            r = s(u)
+            rate = s.entropy_rate(u, r)
+            if jitter:
+                assert rate < -1e3 * rate_tol(s, u, r)
+            else:
+                assert abs(rate) <= rate_tol(s, u, r)
+            s = OracleScheme(m, ph.Gas(mu=0.02, heat_flux=False), viscous=True)
+            r = s(u)
+            assert s.entropy_rate(u, r) < 0.0
+
+
+@pytest.mark.parametrize("name,make,ps", CASES, ids=IDS)
+def test_strong_equals_weak(name, make, ps):
+    """The efficient form (Sec. 6.2) is algebraically the strong form (Sec. 4)."""
+    desc = make()
+    for p in ps:
+        m = OracleMesh(desc, p)
+        u = cons_state(m, jitter=0.01)
+        s = OracleScheme(m, ph.Gas())
+        a = s(u)
+        b = s(u, strong=True)
+        assert np.abs(a - b).max() < 1e-12 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("name,make,ps", CASES, ids=IDS)
+def test_volume_entropy_identity(name, make, ps):
+    """w^T H r_vol = sum_i 1^T E_xi psi^(i) per element, for the entropy-split
+    volume term (Lemma entropy conv volume with the weak-form E f term) and
+    for the Hadamard volume term (proof of Thm. switching hybrid)."""
+    desc = make()
+    gas = ph.Gas()
+    for p in ps:
+        m = OracleMesh(desc, p)
+        u = cons_state(m, jitter=0.02)
+        s = OracleScheme(m, gas)
+        for e in range(0, m.ne, max(1, m.ne // 6)):
+            geo = m.geometry(e)
+            U = u[e]
+            w = ph.entropy_vars(U, gas)
+            target = sum(geo["Ex"][i] @ ph.potential_flux(U, i, gas) for i in range(m.dim))
+            for vol in (s.volume_split(U, geo), s.volume_hadamard(U, geo)):
+                got = np.sum(geo["H"] * np.sum(w * vol, 0))
+                scale = np.sum(geo["H"] * np.sum(np.abs(w * vol), 0))
+                assert abs(got - target) < 1e-13 * scale
+
+
+@pytest.mark.parametrize("name,make,ps", CASES, ids=IDS)
+def test_sats_vanish_for_continuous_states(name, make, ps):
+    """Lemma sats vanish: SAT^I = H^-1 sum E f - coupling = 0 when u_k = u_v
+    at shared facet nodes."""
+    desc = make()
+    gas = ph.Gas()
+    for p in ps:
+        m = OracleMesh(desc, p)
+        u = cons_state(m)
+        s = OracleScheme(m, gas)
+        r = s(u)
+        for e in range(0, m.ne, max(1, m.ne // 6)):
+            geo = m.geometry(e)
+            vol = s.volume_split(u[e], geo)
+            ef = sum(geo["Ex"][i][None, :] * ph.flux(u[e], i, gas) for i in range(m.dim)) / geo["H"][None, :]
+            sat = ef + (r[e] - vol)         # H^-1 E f + (coupling term as added to r)
+            assert np.abs(sat).max() < 1e-11 * np.abs(ef).max()
+
+
+@pytest.mark.parametrize("name,make,ps", CASES, ids=IDS)
+def test_hadamard_conservation(name, make, ps):
+    """Thm. switching hybrid: the SY Hadamard form is locally conservative:
+    1^T H_k r_k = -(sum over facet nodes of B n.F*) and sum_k 1^T H_k r_k = 0."""
+    desc = make()
+    gas = ph.Gas()
+    for p in ps:
+        m = OracleMesh(desc, p)
+        u = cons_state(m, jitter=0.02)
+        s = OracleScheme(m, gas, form="hadamard")
+        r = s(u)
+        H = m.H_all()
+        tot = np.einsum("en,ecn->c", H, r)
+        scale = np.einsum("en,ecn->c", H, np.abs(r))
+        assert (np.abs(tot) < 1e-13 * scale.max()).all()
+        ops = m.ops
+        for e in range(0, m.ne, max(1, m.ne // 6)):
+            geo = m.geometry(e)
+            flux_sum = 0.0
+            for f in range(m.n_fac):
+                v, g = m.neighbor(e, f)
+                mk = ops["facet_nodes"][f]
+                mv = ops["facet_nodes"][g][m.facet_perm(e, f)]
+                Fs = ph.sy_flux(u[e][:, mk], u[v][:, mv], gas)
+                flux_sum = flux_sum + np.einsum("jd,dcj->c", geo["Bn"][f], Fs)
+            assert np.abs(H[e] @ r[e].T + flux_sum).max() < 1e-12 * np.abs(flux_sum).max()
+
+
+def _smooth(x, d):
+    """A smooth periodic state on [0,1]^d, complex-step safe."""
+    s = [np.sin(2 * np.pi * x[k]) for k in range(d)]
+    c = [np.cos(2 * np.pi * x[k]) for k in range(d)]
+    rho = 1.0 + 0.2 * s[0] * (c[1] if d > 1 else 1)
+    V = [0.3 * c[0], -0.2 * s[1]] + ([0.1 * c[2]] if d == 3 else [])
+    p = 1.0 + 0.15 * c[0] * s[1]
+    e = p / 0.4 + 0.5 * rho * sum(v * v for v in V)
+    return np.array([rho] + [rho * v for v in V] + [e])
+
+
+def _exact_divergence(x, d, gas, viscous=False):
+    """-(sum_i dF_i/dx_i) (+ viscous divergence) at points x [d, n] by complex
+    step in each coordinate (second derivatives for the viscous flux by
+    nested complex-step/central differences)."""
+    h = 1e-30
+    out = 0.0
+    for i in range(d):
+        xc = x.astype(complex)
+        xc[i] += 1j * h
+        out = out - np.imag(ph.flux(_smooth(xc, d), i, gas)) / h
+    if viscous:
+        hh = 1e-5
+        for i in range(d):
+            def fv(xr):
+                g = []
+                for j in range(d):
+                    xc = xr.astype(complex)
+                    xc[j] += 1j * h
+                    g.append(np.imag(_smooth(xc, d)) / h)
+                return ph.viscous_flux(_smooth(xr, d), np.array(g), gas)[i]
+            xp = x.copy(); xp[i] += hh
+            xm = x.copy(); xm[i] -= hh
+            out = out + (fv(xp) - fv(xm)) / (2 * hh)
+    return out
+
+
+@pytest.mark.parametrize("curved", [False, True])
+def test_design_order_truncation_error(curved):
+    """Thm. high-order: r(u_exact) + div F = O(h^p) in the H-norm on affine
+    and curved triangles (rates measured between successive meshes)."""
+    gas = ph.Gas()
+    rates = {}
+    for p in (1, 2, 3, 4):
+        errs = []
+        hs = []
+        for n in (4, 8, 16):
+            desc = wl.periodic_tri_mesh(n, n, 1.0, warp=0.05 if curved else 0.0)
+            m = OracleMesh(desc, p)
+            x = m.node_coords()
+            u = np.stack([_smooth(x[e], 2) for e in range(m.ne)], 0)
+            r = OracleScheme(m, gas)(u)
+            ex = np.stack([_exact_divergence(x[e], 2, gas) for e in range(m.ne)], 0)
+            H = m.H_all()
+            errs.append(np.sqrt(np.sum(H[:, None, :] * (r - ex) ** 2)))
+            hs.append(1.0 / n)
+        rates[p] = [np.log(errs[k] / errs[k + 1]) / np.log(hs[k] / hs[k + 1]) for k in range(2)]
+    for p, rr in rates.items():
+        assert rr[-1] > p - 0.25, rates
+
+
+def test_viscous_truncation_error():
+    """Viscous volume term with BO SATs approximates div F^V at rate >= p-1
+    (p >= 2) on smooth states; the heat flux is on."""
+    gas = ph.Gas(mu=0.05, Pr=0.71)
+    for p in (2, 3):
+        errs = []
+        for n in (4, 8):
+            desc = wl.periodic_tri_mesh(n, n, 1.0)
+            m = OracleMesh(desc, p)
+            x = m.node_coords()
+            u = np.stack([_smooth(x[e], 2) for e in range(m.ne)], 0)
+            r = OracleScheme(m, gas, viscous=True)(u)
+            ex = np.stack([_exact_divergence(x[e], 2, gas, viscous=True) for e in range(m.ne)], 0)
+            H = m.H_all()
+            errs.append(np.sqrt(np.sum(H[:, None, :] * (r - ex) ** 2)))
+        rate = np.log2(errs[0] / errs[1])
+        assert rate > p - 1.25, (p, errs, rate)
