@@ -1,0 +1,160 @@
+/*
+ * sbp.h -- C ABI of the MI355X entropy-split SBP-SAT residual library.
+ *
+ * The library evaluates the semi-discrete residual du/dt = r(u) of the
+ * entropy-split summation-by-parts discretization of the Euler and
+ * compressible Navier-Stokes equations on periodic triangle and tetrahedral
+ * meshes (Worku & Zingg, efficient form Sec. 6.2, eq. weak form split), and
+ * advances it by relaxation RK4 (Sec. 6.1).  All compute runs in HIP kernels
+ * for gfx950; the host part only prepares mesh tables.
+ *
+ * Conventions
+ *   - Every call returns int: SBP_OK (0) or a negative SBP_E* code; nothing
+ *     throws across the ABI.  sbp_last_error() gives a thread-local message.
+ *   - State layout: for element e with n_p(e) SBP nodes and n_c = dim + 2
+ *     components (rho, rho V_1..rho V_dim, e), the values of element e start
+ *     at double offset node_off[e] * n_c and are stored component-major:
+ *     u[node_off[e]*n_c + c*n_p(e) + j].  For a single-degree mesh this is a
+ *     dense [n_elem][n_c][n_p] array.  node_off is reported by sbp_mesh_info.
+ *   - Device pointers are caller-owned HIP device allocations; the library
+ *     never frees them.  Host arrays passed to sbp_setup_mesh are borrowed for
+ *     the duration of the call only.
+ *   - hip_stream is a hipStream_t (NULL = default stream).  Residual calls are
+ *     asynchronous on that stream; sbp_rrk_step synchronises it.
+ *   - Device-detected non-physical states (rho <= 0, p <= 0 or NaN) raise a
+ *     flag that the next synchronising call (sbp_rrk_step, sbp_mesh_info,
+ *     sbp_check_device) reports as SBP_ENONPHYS.
+ */
+#ifndef SBP_H
+#define SBP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sbp_mesh sbp_mesh; /* opaque, owned by the library */
+
+enum sbp_status {
+  SBP_OK = 0,
+  SBP_EINVAL = -1,   /* invalid argument (reported at once, nothing launched) */
+  SBP_ENOMEM = -2,   /* device or host allocation failed */
+  SBP_EDEVICE = -3,  /* HIP runtime error */
+  SBP_ENOTSUP = -4,  /* combination not supported by this build */
+  SBP_ENONPHYS = -5, /* rho <= 0, p <= 0 or NaN seen on the device */
+  SBP_ERRK = -6      /* relaxation parameter not bracketed / not converged */
+};
+
+enum { SBP_FORM_SPLIT = 0, SBP_FORM_HADAMARD = 1 };
+enum { SBP_FP64 = 0, SBP_FP32 = 1 };
+
+/* Mesh description (paper Sec. 2.1: conforming elements, periodic domain).
+ * Vertices on the periodic boundary may be duplicated; facets are matched by
+ * their vertex centroids and facet nodes by coordinates modulo `period`.   */
+typedef struct {
+  int32_t dim;                 /* 2 = triangles, 3 = tetrahedra                  */
+  int32_t n_vert, n_elem;
+  const double *vert_xyz;      /* [n_vert][dim], host                             */
+  const int32_t *elem_vert;    /* [n_elem][dim+1], positively oriented            */
+  int32_t p_geom;              /* 1 affine; 2 quadratic map (2D only)             */
+  const double *geom_nodes;    /* [n_elem][6][2] P2 map nodes (v0,v1,v2,m01,m12,m20),
+                                  or NULL when p_geom == 1                        */
+  const double *period;        /* [dim] periodic box lengths                      */
+  const int32_t *elem_degree;  /* [n_elem] SBP degree p (2D: 1..4, 3D: 1..3),
+                                  uniform inside each problem                     */
+  const int32_t *problem_off;  /* [n_problems+1] element ranges of independent
+                                  problems (facets never couple two problems),
+                                  or NULL for one problem                         */
+  int32_t n_problems;          /* >= 1                                            */
+} sbp_mesh_desc;
+
+/* Physical and scheme parameters. */
+typedef struct {
+  double gamma;        /* ratio of specific heats (Sec. 2.2: 7/5)                  */
+  double beta;         /* split parameter; alpha = -gamma - beta (gamma-1)
+                          (Sec. 2.4; Sec. 6.3 uses beta = 2.5)                     */
+  int32_t form;        /* SBP_FORM_SPLIT or SBP_FORM_HADAMARD (Sec. 6.2)           */
+  int32_t dissipation; /* 1: matrix interface dissipation (Sec. 4.4)              */
+  int32_t viscous;     /* 1: Navier-Stokes terms with Baumann-Oden SATs (Sec. 5)   */
+  int32_t heat_flux;   /* 1: include kappa grad T in the viscous flux             */
+  double mu, Pr, R;    /* viscosity, Prandtl number, gas constant                  */
+  int32_t precision;   /* SBP_FP64 or SBP_FP32 (residual kernels; reductions FP64) */
+} sbp_physics;
+
+typedef struct {
+  int32_t dim, n_c;
+  int32_t n_elem;
+  int64_t n_nodes;           /* total SBP nodes, sum_e n_p(e)                     */
+  const int64_t *node_off;   /* host array [n_elem+1] owned by the handle         */
+  const int32_t *elem_np;    /* host array [n_elem]: n_p(e)                       */
+  const double *node_xyz;    /* device array [n_nodes*dim], element e at
+                                node_off[e]*dim, layout [dim][n_p(e)]             */
+  const double *node_h;      /* device array [n_nodes]: diagonal of H_k           */
+  double t;                  /* time held by the handle (advanced by RRK steps)   */
+} sbp_info;
+
+typedef struct {
+  double gamma_n;        /* relaxation parameter                                 */
+  double dt;             /* nominal step (the solution advanced by gamma_n dt)   */
+  double t;              /* time after the step                                  */
+  double entropy_before; /* 1^T H s(u_n)                                         */
+  double entropy_after;  /* 1^T H s(u_{n+1})                                     */
+  double entropy_rate_e; /* dt sum_i b_i w_i^T H r_i                             */
+  int32_t newton_iters;  /* gamma root-solve iterations                          */
+} sbp_rrk_report;
+
+/* Build a mesh handle: reference operators (Def. 1), metrics, facet matching,
+ * device tables.  `hip_stream` is used for the uploads.  Paper: Sec. 2.1. */
+int sbp_setup_mesh(const sbp_mesh_desc *desc, const sbp_physics *phys,
+                   void *hip_stream, sbp_mesh **out);
+
+/* Query layout and device tables.  Also reports a pending device error. */
+int sbp_mesh_info(sbp_mesh *mesh, sbp_info *out);
+
+/* r = du/dt at state u (Sec. 6.2, eq. weak form split; Hadamard form eq. weak
+ * form 2pt when phys.form == SBP_FORM_HADAMARD).  u_dev: doubles, r_dev:
+ * doubles (FP64) or floats (FP32), both in the state layout above.  If
+ * entropy_rate_dev != NULL the FP64 scalar sum_k w_k^T H_k r_k is written to
+ * it.  Asynchronous on hip_stream. */
+int sbp_residual(sbp_mesh *mesh, const void *u_dev, void *r_dev,
+                 double *entropy_rate_dev, void *hip_stream);
+
+/* ubar = (dr/du)^T lambda (vector-Jacobian product of sbp_residual).  Not in
+ * the paper.  Layouts as for sbp_residual, all FP64. */
+int sbp_residual_vjp(sbp_mesh *mesh, const void *u_dev, const void *lambda_dev,
+                     void *ubar_dev, void *hip_stream);
+
+/* One relaxation RK4 step in place (Sec. 6.1, eqs. rrk4 gamma_n, rrk_update).
+ * dt > 0: use it; dt <= 0: dt = cfl * min_k h_min,k / |lambda|_max,k
+ * (Sec. 7.1).  rep may be NULL.  Synchronises hip_stream. */
+int sbp_rrk_step(sbp_mesh *mesh, void *u_dev, double dt, double cfl,
+                 sbp_rrk_report *rep, void *hip_stream);
+
+/* FP64 diagnostics on the device, results copied to host (synchronises):
+ * out[0] = 1^T H s(u); out[1..n_c] = sum_k 1^T H_k u_k per component. */
+int sbp_diagnostics(sbp_mesh *mesh, const void *u_dev, double *out_host,
+                    void *hip_stream);
+
+/* Report (and clear) a pending device-side error flag. Synchronises. */
+int sbp_check_device(sbp_mesh *mesh, void *hip_stream);
+
+int sbp_set_time(sbp_mesh *mesh, double t);
+
+int sbp_destroy_mesh(sbp_mesh *mesh);
+
+const char *sbp_last_error(void);
+
+/* Host-only query of the reference-element operator the library builds for
+ * (dim, p) (Def. 1): n_p nodes, n_f nodes per facet.  Arrays (row-major):
+ * nodes [n_p][dim], h [n_p], Q [dim][n_p][n_p], E [dim][n_p],
+ * facet_nodes [dim+1][n_f], facet_w [dim+1][n_f].  Any pointer may be NULL.
+ * No device is touched. */
+int sbp_reference_operator(int32_t dim, int32_t p, int32_t *n_p, int32_t *n_f,
+                           double *nodes, double *h, double *Q, double *E,
+                           int32_t *facet_nodes, double *facet_w);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SBP_H */

@@ -168,9 +168,19 @@ class OracleMesh:
         return geo
 
     def node_coords(self, elements=None):
-        """SBP node coordinates [ne, dim, n_p] (component-first per element)."""
-        els = range(self.ne) if elements is None else elements
-        return np.stack([self.geometry(e)["x"].T for e in els], 0)
+        """SBP node coordinates [ne, dim, n_p] (component-first per element),
+        from the element maps only (no operators), vectorised over elements."""
+        els = np.arange(self.ne) if elements is None else np.asarray(list(elements))
+        xi = self.ops["nodes"]
+        if self.p_geom == 1:
+            v = self.verts[self.elem[els]]                      # [n, dim+1, dim]
+            F = np.stack([v[:, l + 1] - v[:, 0] for l in range(self.dim)], 2)  # [n, i, l]
+            x = v[:, 0][:, None, :] + np.einsum("jl,nil->nji", xi, F)
+        else:
+            N, _ = _p2_basis(xi)
+            g = np.asarray(self.geom_nodes, dtype=np.float64)[els]   # [n,6,2]
+            x = np.einsum("aj,nai->nji", N, g)
+        return np.ascontiguousarray(np.transpose(x, (0, 2, 1)))
 
     def H_all(self):
         return np.stack([self.geometry(e)["H"] for e in range(self.ne)], 0)

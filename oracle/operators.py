@@ -41,6 +41,7 @@ import functools
 import itertools
 from math import factorial
 
+import mpmath
 import numpy as np
 from scipy.optimize import least_squares
 
@@ -115,9 +116,27 @@ def _eval_monomials(X, deg):
 
 
 def gauss_legendre01(n):
-    """n-point Gauss-Legendre rule on [0,1], ascending points, weights sum 1."""
-    t, w = np.polynomial.legendre.leggauss(n)
-    return 0.5 * (t + 1.0), 0.5 * w
+    """n-point Gauss-Legendre rule on [0,1], ascending points, weights sum 1.
+    numpy's nodes are polished by Newton on P_n in 40-digit arithmetic and
+    rounded, so the rule is the correctly rounded one."""
+    t, _ = np.polynomial.legendre.leggauss(n)
+    with mpmath.workdps(40):
+        ts, ws = [], []
+        for x0 in t:
+            x = mpmath.mpf(float(x0))
+            for _ in range(50):
+                pn, pm = mpmath.legendre(n, x), mpmath.legendre(n - 1, x)
+                dp = n * (x * pn - pm) / (x * x - 1)
+                dx = pn / dp
+                x -= dx
+                if abs(dx) < mpmath.mpf("1e-38"):
+                    break
+            pn, pm = mpmath.legendre(n, x), mpmath.legendre(n - 1, x)
+            dp = n * (x * pn - pm) / (x * x - 1)
+            ts.append(float((x + 1) / 2))
+            ws.append(float(1 / ((1 - x * x) * dp * dp)))
+    order = np.argsort(ts)
+    return np.array(ts)[order], np.array(ws)[order]
 
 
 def _solve_orbit_rule(fixed_pts, fixed_gid, n_fixed_groups, orbits, deg, dim):
@@ -157,19 +176,109 @@ def _solve_orbit_rule(fixed_pts, fixed_gid, n_fixed_groups, orbits, deg, dim):
 
     if x0.size:
         x = least_squares(resid, x0, xtol=1e-15, ftol=1e-15, gtol=1e-15).x
+        x = _polish_mp(fixed_pts, fixed_gid, n_fixed_groups, orbits, deg, dim, x,
+                       np.linalg.lstsq(group_matrix(x), mom, rcond=None)[0])
     else:
         x = x0
-    G = group_matrix(x)
-    w = np.linalg.lstsq(G, mom, rcond=None)[0]
-    P, gid, _ = assemble(x)
+    # points from the rounded parameters in double arithmetic; weights by a
+    # 40-digit least-squares solve for exactly these points, then rounded
+    P, gid, ng = assemble(x)
+    Vm = _eval_monomials(P[:, 1:], deg)
+    G = np.stack([Vm[:, gid == g].sum(axis=1) for g in range(ng)], 1)
+    with mpmath.workdps(40):
+        Gm = mpmath.matrix(len(mom), ng)
+        mons = _monomials(deg, dim)
+        for g in range(ng):
+            for q, m in enumerate(mons):
+                acc = mpmath.mpf(0)
+                for row in P[gid == g]:
+                    t = mpmath.mpf(1)
+                    for i in range(dim):
+                        t *= mpmath.mpf(float(row[1 + i])) ** m[i]
+                    acc += t
+                Gm[q, g] = acc
+        mm = mpmath.matrix([_simplex_moment_mp(m) for m in mons])
+        wm = mpmath.lu_solve(Gm.T * Gm, Gm.T * mm)
+        w = np.array([float(wm[g]) for g in range(ng)])
     return P, w[gid], x, np.abs(G @ w - mom).max()
+
+
+def _simplex_moment_mp(e):
+    num = mpmath.mpf(1)
+    for k in e:
+        num *= mpmath.factorial(k)
+    return num / mpmath.factorial(sum(e) + len(e))
+
+
+def _polish_mp(fixed_pts, fixed_gid, n_fixed_groups, orbits, deg, dim, x, w):
+    """Gauss-Newton on the full moment system (parameters and group weights)
+    in 40-digit arithmetic; returns the parameters rounded to doubles."""
+    nbary = dim + 1
+    mons = _monomials(deg, dim)
+    with mpmath.workdps(40):
+        mom = [_simplex_moment_mp(m) for m in mons]
+        fixed = [[mpmath.mpf(float(v)) for v in pt] for pt in fixed_pts]
+
+        def orbit_mp(kind, prm):
+            one = mpmath.mpf(1)
+            if kind == "1":
+                base = [one / nbary] * nbary
+            elif kind == "3":
+                base = [prm[0], prm[0], 1 - 2 * prm[0]]
+            elif kind == "6":
+                base = [prm[0], prm[1], 1 - prm[0] - prm[1]]
+            else:
+                base = [prm[0], prm[0], prm[1], 1 - 2 * prm[0] - prm[1]]
+            return [list(q) for q in set(itertools.permutations(base))] if kind != "1" else [base]
+
+        def residual(z):
+            xs, ws = z[:len(x)], z[len(x):]
+            groups = [[] for _ in range(n_fixed_groups)]
+            for pt, g in zip(fixed, fixed_gid):
+                groups[g].append(pt)
+            k = 0
+            for kind, _ in orbits:
+                n = _npar(kind)
+                groups.append(orbit_mp(kind, xs[k:k + n]))
+                k += n
+            out = []
+            for q, m in enumerate(mons):
+                s = -mom[q]
+                for g, pts in enumerate(groups):
+                    acc = mpmath.mpf(0)
+                    for pt in pts:
+                        t = mpmath.mpf(1)
+                        for i in range(dim):
+                            t *= pt[1 + i] ** m[i]
+                        acc += t
+                    s += ws[g] * acc
+                out.append(s)
+            return out
+
+        z = [mpmath.mpf(float(v)) for v in x] + [mpmath.mpf(float(v)) for v in w]
+        h = mpmath.mpf("1e-28")
+        for _ in range(30):
+            R = residual(z)
+            J = mpmath.matrix(len(R), len(z))
+            for j in range(len(z)):
+                zz = list(z)
+                zz[j] += h
+                Rj = residual(zz)
+                for q in range(len(R)):
+                    J[q, j] = (Rj[q] - R[q]) / h
+            Rm = mpmath.matrix([-r for r in R])
+            dz = mpmath.lu_solve(J.T * J, J.T * Rm)
+            z = [z[j] + dz[j] for j in range(len(z))]
+            if max(abs(dz[j]) for j in range(len(z))) < mpmath.mpf("1e-34"):
+                break
+        return np.array([float(v) for v in z[:len(x)]])
 
 
 def _face_rule(p):
     """Symmetric triangle rule of degree 2p (barycentric points, weights
     summing to one) for the faces of a degree-p tetrahedral operator."""
     P, w, x, res = _solve_orbit_rule([], [], 0, FACE_RULES[p], 2 * p, 2)
-    return P, w / w.sum(), res
+    return P, 2.0 * w, res    # weights of the unit-area rule
 
 
 def _facet_vertices(dim):
@@ -248,33 +357,72 @@ def reference_operator(dim: int, p: int) -> dict:
     for f in range(nb):
         for j, m in enumerate(facet_nodes[f]):
             E[:, m] += facet_w[f, j] * facet_normal[f]
-    # Vandermonde of P^p in centred coordinates and its derivatives
+    # Vandermonde of P^p in centred coordinates and its derivatives; the basis
+    # is orthonormalised (Gram-Schmidt in 40-digit arithmetic) before the
+    # double-precision least-squares solve, which then works with a
+    # well-conditioned system.  S is basis independent.
     c = np.full(dim, 1.0 / nb)
-    Y = X - c
     mons = _monomials(p, dim)
-    V = np.array([np.prod([Y[:, i] ** m[i] for i in range(dim)], axis=0) for m in mons]).T
+    nm = len(mons)
     Hm = np.diag(h)
     Q = np.zeros((dim, n_p, n_p))
     S = np.zeros((dim, n_p, n_p))
     D = np.zeros((dim, n_p, n_p))
+    with mpmath.workdps(40):
+        Y = [[mpmath.mpf(float(X[r, i])) - mpmath.mpf(1) / nb for i in range(dim)] for r in range(n_p)]
+
+        def mono(r, m):
+            t = mpmath.mpf(1)
+            for i in range(dim):
+                t *= Y[r][i] ** m[i]
+            return t
+
+        def dmono(r, m, l):
+            if m[l] == 0:
+                return mpmath.mpf(0)
+            t = mpmath.mpf(m[l])
+            for i in range(dim):
+                t *= Y[r][i] ** (m[i] - (1 if i == l else 0))
+            return t
+        Vm = mpmath.matrix(n_p, nm)
+        for r in range(n_p):
+            for k, m in enumerate(mons):
+                Vm[r, k] = mono(r, m)
+        # modified Gram-Schmidt: V T = Qo with orthonormal columns
+        T = mpmath.eye(nm)
+        Qo = Vm.copy()
+        for k in range(nm):
+            for j in range(k):
+                proj = sum(Qo[r, j] * Qo[r, k] for r in range(n_p))
+                for r in range(n_p):
+                    Qo[r, k] -= proj * Qo[r, j]
+                for q in range(nm):
+                    T[q, k] -= proj * T[q, j]
+            nrm = mpmath.sqrt(sum(Qo[r, k] ** 2 for r in range(n_p)))
+            for r in range(n_p):
+                Qo[r, k] /= nrm
+            for q in range(nm):
+                T[q, k] /= nrm
+        Vo = np.array([[float(Qo[r, k]) for k in range(nm)] for r in range(n_p)])
+        Ao = []
+        for l in range(dim):
+            Am = mpmath.matrix(n_p, nm)
+            for r in range(n_p):
+                for k, m in enumerate(mons):
+                    Am[r, k] = mpmath.mpf(float(h[r])) * dmono(r, m, l) - mpmath.mpf(float(E[l][r])) / 2 * Vm[r, k]
+            AT = Am * T
+            Ao.append(np.array([[float(AT[r, k]) for k in range(nm)] for r in range(n_p)]))
     iu = np.triu_indices(n_p, 1)
     nsk = len(iu[0])
     for l in range(dim):
-        Vl = np.zeros_like(V)
-        for k, m in enumerate(mons):
-            if m[l] == 0:
-                continue
-            mm = list(m)
-            mm[l] -= 1
-            Vl[:, k] = m[l] * np.prod([Y[:, i] ** mm[i] for i in range(dim)], axis=0)
-        A = Hm @ Vl - 0.5 * E[l][:, None] * V
+        V, A = Vo, Ao[l]
         # unknowns: s_ij (i<j); S = sum s_ij (e_i e_j^T - e_j e_i^T).
         # constraint rows: (S V)[r, k] = A[r, k].
-        M = np.zeros((n_p * len(mons), nsk))
+        M = np.zeros((n_p * nm, nsk))
         for q, (i, j) in enumerate(zip(*iu)):
             # column of S V contributed by s_ij: row i gets +V[j,:], row j gets -V[i,:]
-            M[i * len(mons):(i + 1) * len(mons), q] += V[j]
-            M[j * len(mons):(j + 1) * len(mons), q] -= V[i]
+            M[i * nm:(i + 1) * nm, q] += V[j]
+            M[j * nm:(j + 1) * nm, q] -= V[i]
         s = np.linalg.lstsq(M, A.reshape(-1), rcond=None)[0]
         Sl = np.zeros((n_p, n_p))
         Sl[iu] = s

@@ -1,0 +1,773 @@
+// C ABI of the library (include/sbp.h): mesh setup on the host, device
+// tables, residual dispatch, relaxation RK4 driver.
+//
+// Setup (Sec. 2.1): per element the map x(xi) (affine, or quadratic through
+// the vertices and edge midpoints in 2D), metric cofactors Lambda_il =
+// J dxi_l/dx_i, H_k = J H_ref, the minimum node distance h_min (Sec. 7.1);
+// facets matched by vertex centroids modulo the period, facet nodes by
+// coordinates modulo the period, stored as the u offset of the matching
+// neighbour node (the face-node permutation, resolved once).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/sbp.h"
+#include "launch.hpp"
+#include "refops.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? SBP_ENOMEM : SBP_EDEVICE,                \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t n = 0;
+};
+
+struct DegreeClass {
+  int p = 0, np = 0, nf = 0, n_elem = 0;
+  std::vector<int> elems;  // global element ids
+  int *d_uoff = nullptr;
+  double *d_geo = nullptr;
+  int *d_nbr = nullptr;
+  double *d_Hn = nullptr;
+  double *d_hmin = nullptr;
+  void *d_ops = nullptr;  // both precisions
+  sbp::OpTables<double> op64{};
+  sbp::OpTables<float> op32{};
+  int part_off = 0;       // offset of this class in the residual partial buffer
+  int res_blocks = 0;
+  int node_off_blk = 0;   // offset in the node partial buffers
+  int node_blocks = 0;
+};
+
+}  // namespace
+
+struct sbp_mesh {
+  int dim = 0, nc = 0, n_elem = 0;
+  long long n_nodes = 0;
+  long long n_dof = 0;  // doubles in a state vector
+  std::vector<int64_t> node_off;
+  std::vector<int> elem_np;
+  sbp_physics phys{};
+  std::vector<DegreeClass> cls;
+  double *d_node_xyz = nullptr;
+  double *d_node_h = nullptr;
+  double *d_part = nullptr;   // residual partials (sum over classes of blocks)
+  int part_total = 0;
+  double *d_npart = nullptr;  // node-kernel partials [(n_c+1) x node_total]
+  int node_total = 0;
+  double *d_scal = nullptr;   // device scalars
+  int *d_err = nullptr;
+  double *d_y = nullptr, *d_d = nullptr;
+  void *d_r = nullptr;        // RK stage residual
+  double t = 0.0;
+};
+
+namespace {
+
+constexpr int SC_ENT = 0;     // 4 stage entropy rates
+constexpr int SC_RED = 8;     // reduction outputs (up to 8)
+constexpr int SC_TOTAL = 32;
+
+// --------------------------------------------------------------------------
+// geometry helpers
+void p2_dbasis(double x, double y, double dN[2][6]) {
+  const double l[3] = {1.0 - x - y, x, y};
+  const double dl[3][2] = {{-1.0, -1.0}, {1.0, 0.0}, {0.0, 1.0}};
+  for (int k = 0; k < 2; ++k) {
+    for (int a = 0; a < 3; ++a) dN[k][a] = (4.0 * l[a] - 1.0) * dl[a][k];
+    const int pr[3][2] = {{0, 1}, {1, 2}, {2, 0}};
+    for (int q = 0; q < 3; ++q) {
+      const int a = pr[q][0], b = pr[q][1];
+      dN[k][3 + q] = 4.0 * (dl[a][k] * l[b] + l[a] * dl[b][k]);
+    }
+  }
+}
+
+void p2_basis(double x, double y, double N[6]) {
+  const double l0 = 1.0 - x - y, l1 = x, l2 = y;
+  N[0] = l0 * (2 * l0 - 1);
+  N[1] = l1 * (2 * l1 - 1);
+  N[2] = l2 * (2 * l2 - 1);
+  N[3] = 4 * l0 * l1;
+  N[4] = 4 * l1 * l2;
+  N[5] = 4 * l2 * l0;
+}
+
+struct KeyHash {
+  size_t operator()(const std::array<long long, 4> &k) const {
+    size_t h = 1469598103934665603ull;
+    for (long long v : k) h = (h ^ (size_t)v) * 1099511628211ull;
+    return h;
+  }
+};
+
+template <typename T>
+int upload(T *&dst, const std::vector<T> &src, hipStream_t s) {
+  HIPCHK(hipMalloc((void **)&dst, std::max<size_t>(1, src.size()) * sizeof(T)));
+  if (!src.empty()) HIPCHK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return SBP_OK;
+}
+
+// Padded, transposed operator tables of one class for precision T.
+template <typename T>
+void build_tables(const sbp::RefOp &op, int dim, double beta, std::vector<T> &blob, size_t off[8]) {
+  const int NP = op.np;
+  const double cb = 1.0 / (beta + 1.0);
+  auto Q = [&](int l, int i, int j) { return op.Q[((size_t)l * NP + i) * NP + j]; };
+  auto align = [&](size_t n) { return (n + 63) / 64 * 64; };
+  blob.clear();
+  auto push = [&](const std::vector<double> &v) {
+    size_t o = blob.size();
+    blob.resize(align(o + v.size()), (T)0);
+    for (size_t k = 0; k < v.size(); ++k) blob[o + k] = (T)v[k];
+    return o;
+  };
+  if (dim == 3) {
+    const int K1P = sbp::ru(3 * NP, 4), M1P = sbp::ru(NP, 16);
+    const int K2P = sbp::ru(NP, 4), M2P = sbp::ru(3 * NP, 16);
+    std::vector<double> A1(K1P * M1P, 0.0), A2(K2P * M2P, 0.0);
+    for (int l = 0; l < 3; ++l)
+      for (int m = 0; m < NP; ++m)
+        for (int j = 0; j < NP; ++j) {
+          A1[(size_t)(l * NP + j) * M1P + m] = cb * Q(l, m, j) + Q(l, j, m);  // M_l[m][j]
+          A2[(size_t)j * M2P + l * NP + m] = Q(l, m, j) / op.h[m];            // D_l[m][j]
+        }
+    off[0] = push(A1);
+    off[1] = push(A2);
+    off[2] = off[3] = 0;
+  } else {
+    const int KP = sbp::ru(NP, 4), MP = sbp::ru(NP, 16);
+    for (int l = 0; l < 2; ++l) {
+      std::vector<double> Am(KP * MP, 0.0), Aq(KP * MP, 0.0);
+      for (int m = 0; m < NP; ++m)
+        for (int k = 0; k < NP; ++k) {
+          Am[(size_t)k * MP + m] = cb * Q(l, m, k) + Q(l, k, m);
+          Aq[(size_t)k * MP + m] = Q(l, m, k);
+        }
+      off[l] = push(Am);
+      off[2 + l] = push(Aq);
+    }
+  }
+  std::vector<double> S((size_t)dim * NP * NP);
+  for (int l = 0; l < dim; ++l)
+    for (int m = 0; m < NP; ++m)
+      for (int n = 0; n < NP; ++n)
+        S[((size_t)l * NP + m) * NP + n] = Q(l, m, n) - (m == n ? 0.5 * op.E[(size_t)l * NP + m] : 0.0);
+  off[4] = push(S);
+  off[5] = push(op.h);
+  off[6] = push(op.E);
+  std::vector<double> dN;
+  if (dim == 2) {
+    dN.assign((size_t)2 * 6 * NP, 0.0);
+    for (int j = 0; j < NP; ++j) {
+      double d[2][6];
+      p2_dbasis(op.nodes[2 * j], op.nodes[2 * j + 1], d);
+      for (int k = 0; k < 2; ++k)
+        for (int a = 0; a < 6; ++a) dN[((size_t)k * 6 + a) * NP + j] = d[k][a];
+    }
+  } else {
+    dN.assign(1, 0.0);
+  }
+  off[7] = push(dN);
+}
+
+template <typename T>
+sbp::OpTables<T> tables_at(const T *base, const size_t off[8], int dim) {
+  sbp::OpTables<T> t{};
+  t.At1 = base + off[0];
+  t.At2 = base + off[1];
+  t.At3 = dim == 2 ? base + off[2] : nullptr;
+  t.At4 = dim == 2 ? base + off[3] : nullptr;
+  t.S = base + off[4];
+  t.h = base + off[5];
+  t.E = base + off[6];
+  t.dN = base + off[7];
+  return t;
+}
+
+int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp_mesh *M) {
+  const int dim = D->dim;
+  M->dim = dim;
+  M->nc = dim + 2;
+  M->n_elem = D->n_elem;
+  M->phys = *ph;
+  const int nv = dim + 1;
+  const int ne = D->n_elem;
+  std::vector<int> prob_of(ne, 0);
+  if (D->problem_off) {
+    for (int q = 0; q < D->n_problems; ++q) {
+      if (D->problem_off[q] > D->problem_off[q + 1] || D->problem_off[q + 1] > ne)
+        return fail(SBP_EINVAL, "problem_off not monotone within [0, n_elem]");
+      for (int e = D->problem_off[q]; e < D->problem_off[q + 1]; ++e) prob_of[e] = q;
+    }
+    if (D->problem_off[0] != 0 || D->problem_off[D->n_problems] != ne)
+      return fail(SBP_EINVAL, "problem_off must cover [0, n_elem]");
+  }
+  // degree per element, uniform per problem
+  std::vector<int> deg(ne);
+  for (int e = 0; e < ne; ++e) {
+    deg[e] = D->elem_degree[e];
+    if (dim == 2 && (deg[e] < 1 || deg[e] > 4)) return fail(SBP_ENOTSUP, "triangle degree must be 1..4");
+    if (dim == 3 && (deg[e] < 1 || deg[e] > 3)) return fail(SBP_ENOTSUP, "tetrahedron degree must be 1..3");
+    if (e > 0 && prob_of[e] == prob_of[e - 1] && deg[e] != deg[e - 1])
+      return fail(SBP_EINVAL, "degree must be uniform inside a problem");
+  }
+  // layout
+  M->node_off.assign(ne + 1, 0);
+  M->elem_np.assign(ne, 0);
+  for (int e = 0; e < ne; ++e) {
+    const sbp::RefOp &op = sbp::reference_operator(dim, deg[e]);
+    M->elem_np[e] = op.np;
+    M->node_off[e + 1] = M->node_off[e] + op.np;
+  }
+  M->n_nodes = M->node_off[ne];
+  M->n_dof = M->n_nodes * M->nc;
+  if (M->n_dof >= (1ll << 31) - 1) return fail(SBP_ENOTSUP, "state larger than 2^31 doubles");
+  // geometry on the host
+  std::vector<double> xyz((size_t)M->n_nodes * dim);
+  std::vector<double> Hn(M->n_nodes);
+  std::vector<double> geo2, geo3;
+  std::vector<double> hmin(ne);
+  const double *P = D->period;
+  for (int e = 0; e < ne; ++e) {
+    const sbp::RefOp &op = sbp::reference_operator(dim, deg[e]);
+    const int np = op.np;
+    double g[6][3] = {};
+    const int32_t *ev = D->elem_vert + (size_t)e * nv;
+    for (int a = 0; a < nv; ++a) {
+      if (ev[a] < 0 || ev[a] >= D->n_vert) return fail(SBP_EINVAL, "elem_vert out of range");
+      for (int i = 0; i < dim; ++i) g[a][i] = D->vert_xyz[(size_t)ev[a] * dim + i];
+    }
+    double *xe = xyz.data() + (size_t)M->node_off[e] * dim;
+    if (dim == 2) {
+      double gn[6][2];
+      if (D->p_geom == 2) {
+        for (int a = 0; a < 6; ++a)
+          for (int i = 0; i < 2; ++i) gn[a][i] = D->geom_nodes[((size_t)e * 6 + a) * 2 + i];
+      } else {
+        for (int a = 0; a < 3; ++a)
+          for (int i = 0; i < 2; ++i) gn[a][i] = g[a][i];
+        const int pr[3][2] = {{0, 1}, {1, 2}, {2, 0}};
+        for (int q = 0; q < 3; ++q)
+          for (int i = 0; i < 2; ++i) gn[3 + q][i] = 0.5 * (g[pr[q][0]][i] + g[pr[q][1]][i]);
+      }
+      for (int a = 0; a < 6; ++a)
+        for (int i = 0; i < 2; ++i) geo2.push_back(gn[a][i]);
+      for (int j = 0; j < np; ++j) {
+        double N[6], dN[2][6];
+        p2_basis(op.nodes[2 * j], op.nodes[2 * j + 1], N);
+        p2_dbasis(op.nodes[2 * j], op.nodes[2 * j + 1], dN);
+        double F[2][2] = {{0, 0}, {0, 0}}, x[2] = {0, 0};
+        for (int a = 0; a < 6; ++a)
+          for (int i = 0; i < 2; ++i) {
+            x[i] += N[a] * gn[a][i];
+            F[i][0] += dN[0][a] * gn[a][i];
+            F[i][1] += dN[1][a] * gn[a][i];
+          }
+        const double J = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+        if (!(J > 0)) return fail(SBP_EINVAL, "non-positive Jacobian (element " + std::to_string(e) + ")");
+        xe[0 * np + j] = x[0];
+        xe[1 * np + j] = x[1];
+        Hn[M->node_off[e] + j] = J * op.h[j];
+      }
+    } else {
+      if (D->p_geom != 1) return fail(SBP_ENOTSUP, "3D curved maps are not supported");
+      double F[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int l = 0; l < 3; ++l) F[i][l] = g[l + 1][i] - g[0][i];
+      double C[3][3];  // cofactors
+      for (int i = 0; i < 3; ++i)
+        for (int l = 0; l < 3; ++l) {
+          const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, l1 = (l + 1) % 3, l2 = (l + 2) % 3;
+          C[i][l] = F[i1][l1] * F[i2][l2] - F[i1][l2] * F[i2][l1];
+        }
+      const double J = F[0][0] * C[0][0] + F[0][1] * C[0][1] + F[0][2] * C[0][2];
+      if (!(J > 0)) return fail(SBP_EINVAL, "non-positive Jacobian (element " + std::to_string(e) + ")");
+      for (int i = 0; i < 3; ++i)
+        for (int l = 0; l < 3; ++l) geo3.push_back(C[i][l]);
+      geo3.push_back(J);
+      for (int j = 0; j < np; ++j) {
+        for (int i = 0; i < 3; ++i) {
+          double x = g[0][i];
+          for (int l = 0; l < 3; ++l) x += F[i][l] * op.nodes[3 * j + l];
+          xe[i * np + j] = x;
+        }
+        Hn[M->node_off[e] + j] = J * op.h[j];
+      }
+    }
+    double hm = INFINITY;
+    for (int a = 0; a < np; ++a)
+      for (int b = a + 1; b < np; ++b) {
+        double d2 = 0;
+        for (int i = 0; i < dim; ++i) {
+          const double d = xe[i * np + a] - xe[i * np + b];
+          d2 += d * d;
+        }
+        hm = std::min(hm, std::sqrt(d2));
+      }
+    hmin[e] = hm;
+  }
+  // facet matching by centroid keys modulo the period, per problem
+  std::unordered_map<std::array<long long, 4>, std::pair<int, int>, KeyHash> table;
+  table.reserve((size_t)ne * nv);
+  std::vector<int> nb_elem((size_t)ne * nv, -1), nb_fac((size_t)ne * nv, -1);
+  const long long RES = 1ll << 22;
+  for (int e = 0; e < ne; ++e)
+    for (int f = 0; f < nv; ++f) {
+      double c[3] = {0, 0, 0};
+      for (int a = 0; a < nv; ++a) {
+        if (a == f) continue;
+        const int vtx = D->elem_vert[(size_t)e * nv + a];
+        for (int i = 0; i < dim; ++i) c[i] += D->vert_xyz[(size_t)vtx * dim + i] / dim;
+      }
+      std::array<long long, 4> key{0, 0, 0, prob_of[e]};
+      for (int i = 0; i < dim; ++i) {
+        long long q = (long long)std::llround(c[i] / P[i] * (double)RES);
+        key[i] = ((q % RES) + RES) % RES;
+      }
+      auto it = table.find(key);
+      if (it == table.end()) {
+        table.emplace(key, std::make_pair(e, f));
+      } else {
+        const int v = it->second.first, g2 = it->second.second;
+        if (nb_elem[(size_t)v * nv + g2] >= 0) return fail(SBP_EINVAL, "facet shared by more than two elements");
+        nb_elem[(size_t)e * nv + f] = v;
+        nb_fac[(size_t)e * nv + f] = g2;
+        nb_elem[(size_t)v * nv + g2] = e;
+        nb_fac[(size_t)v * nv + g2] = f;
+      }
+    }
+  for (size_t k = 0; k < nb_elem.size(); ++k)
+    if (nb_elem[k] < 0) return fail(SBP_EINVAL, "unmatched facet (mesh not periodic/conforming)");
+  // degree classes
+  std::vector<int> class_of_p(5, -1);
+  for (int e = 0; e < ne; ++e) {
+    if (class_of_p[deg[e]] < 0) {
+      class_of_p[deg[e]] = (int)M->cls.size();
+      DegreeClass c;
+      c.p = deg[e];
+      const sbp::RefOp &op = sbp::reference_operator(dim, deg[e]);
+      c.np = op.np;
+      c.nf = op.nf;
+      M->cls.push_back(c);
+    }
+    M->cls[class_of_p[deg[e]]].elems.push_back(e);
+  }
+  int part_total = 0, node_total = 0;
+  const int prec = ph->precision;
+  for (auto &c : M->cls) {
+    c.n_elem = (int)c.elems.size();
+    const sbp::RefOp &op = sbp::reference_operator(dim, c.p);
+    const int np = c.np, nf = c.nf;
+    std::vector<int> uoff(c.n_elem), nbr((size_t)c.n_elem * nv * nf);
+    std::vector<double> geo, hn((size_t)c.n_elem * np), hm(c.n_elem);
+    const int gsz = dim == 2 ? 12 : 10;
+    for (int k = 0; k < c.n_elem; ++k) {
+      const int e = c.elems[k];
+      uoff[k] = (int)(M->node_off[e] * M->nc);
+      const std::vector<double> &G = dim == 2 ? geo2 : geo3;
+      geo.insert(geo.end(), G.begin() + (size_t)e * gsz, G.begin() + (size_t)(e + 1) * gsz);
+      for (int j = 0; j < np; ++j) hn[(size_t)k * np + j] = Hn[M->node_off[e] + j];
+      hm[k] = hmin[e];
+      const double *xe = xyz.data() + (size_t)M->node_off[e] * dim;
+      for (int f = 0; f < nv; ++f) {
+        const int v = nb_elem[(size_t)e * nv + f], g2 = nb_fac[(size_t)e * nv + f];
+        const double *xv = xyz.data() + (size_t)M->node_off[v] * dim;
+        const int npv = M->elem_np[v];
+        for (int j = 0; j < nf; ++j) {
+          const int m = op.facet_nodes[(size_t)f * nf + j];
+          int best = -1;
+          double bd = INFINITY;
+          for (int jj = 0; jj < nf; ++jj) {
+            const int mv = op.facet_nodes[(size_t)g2 * nf + jj];
+            double d2 = 0;
+            for (int i = 0; i < dim; ++i) {
+              double d = xe[i * np + m] - xv[i * npv + mv];
+              d -= P[i] * std::nearbyint(d / P[i]);
+              d2 += d * d;
+            }
+            if (d2 < bd) { bd = d2; best = mv; }
+          }
+          if (!(std::sqrt(bd) <= 1e-8 * std::max(hmin[e], 1.0)))
+            return fail(SBP_EINVAL, "facet nodes do not match (element " + std::to_string(e) + ")");
+          nbr[((size_t)k * nv + f) * nf + j] = (int)(M->node_off[v] * M->nc) + best;
+        }
+      }
+    }
+    int rc;
+    if ((rc = upload(c.d_uoff, uoff, s))) return rc;
+    if ((rc = upload(c.d_geo, geo, s))) return rc;
+    if ((rc = upload(c.d_nbr, nbr, s))) return rc;
+    if ((rc = upload(c.d_Hn, hn, s))) return rc;
+    if ((rc = upload(c.d_hmin, hm, s))) return rc;
+    std::vector<double> b64;
+    std::vector<float> b32;
+    size_t o64[8], o32[8];
+    build_tables<double>(op, dim, ph->beta, b64, o64);
+    build_tables<float>(op, dim, ph->beta, b32, o32);
+    const size_t bytes64 = b64.size() * sizeof(double), bytes32 = b32.size() * sizeof(float);
+    HIPCHK(hipMalloc(&c.d_ops, bytes64 + bytes32));
+    HIPCHK(hipMemcpyAsync(c.d_ops, b64.data(), bytes64, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync((char *)c.d_ops + bytes64, b32.data(), bytes32, hipMemcpyHostToDevice, s));
+    c.op64 = tables_at<double>((const double *)c.d_ops, o64, dim);
+    c.op32 = tables_at<float>((const float *)((char *)c.d_ops + bytes64), o32, dim);
+    c.res_blocks = std::max(sbp::residual_blocks(dim, c.p, 0, ph->form, c.n_elem),
+                            sbp::residual_blocks(dim, c.p, 1, ph->form, c.n_elem));
+    c.part_off = part_total;
+    part_total += c.res_blocks;
+    c.node_blocks = sbp::node_blocks(c.n_elem, np);
+    c.node_off_blk = node_total;
+    node_total += c.node_blocks;
+  }
+  (void)prec;
+  M->part_total = part_total;
+  M->node_total = node_total;
+  int rc;
+  if ((rc = upload(M->d_node_xyz, xyz, s))) return rc;
+  if ((rc = upload(M->d_node_h, Hn, s))) return rc;
+  HIPCHK(hipMalloc((void **)&M->d_part, sizeof(double) * std::max(1, part_total)));
+  HIPCHK(hipMalloc((void **)&M->d_npart, sizeof(double) * (M->nc + 1) * std::max(1, node_total)));
+  HIPCHK(hipMalloc((void **)&M->d_scal, sizeof(double) * SC_TOTAL));
+  HIPCHK(hipMemsetAsync(M->d_scal, 0, sizeof(double) * SC_TOTAL, s));
+  HIPCHK(hipMalloc((void **)&M->d_err, sizeof(int)));
+  HIPCHK(hipMemsetAsync(M->d_err, 0, sizeof(int), s));
+  HIPCHK(hipStreamSynchronize(s));
+  return SBP_OK;
+}
+
+sbp::NodeArgs node_args(const sbp_mesh *M, const DegreeClass &c, const double *u, const double *d) {
+  sbp::NodeArgs A{};
+  A.u = u;
+  A.d = d;
+  A.uoff = c.d_uoff;
+  A.Hn = c.d_Hn;
+  A.hmin = c.d_hmin;
+  A.n_elem = c.n_elem;
+  A.np = c.np;
+  A.dim = M->dim;
+  A.gamma = M->phys.gamma;
+  A.beta = M->phys.beta;
+  A.pstride = M->node_total;
+  return A;
+}
+
+int residual_impl(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStream_t s) {
+  const sbp_physics &ph = M->phys;
+  for (auto &c : M->cls) {
+    if (ph.precision == SBP_FP64) {
+      sbp::KArgs<double> A{};
+      A.u = u;
+      A.r = (double *)r;
+      A.geo = c.d_geo;
+      A.nbr = c.d_nbr;
+      A.uoff = c.d_uoff;
+      A.n_elem = c.n_elem;
+      A.diss = ph.dissipation;
+      A.op = c.op64;
+      A.G = sbp::make_gas<double>(ph.gamma, ph.beta);
+      A.ent_part = M->d_part + c.part_off;
+      A.err = M->d_err;
+      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, A, s));
+    } else {
+      sbp::KArgs<float> A{};
+      A.u = u;
+      A.r = (float *)r;
+      A.geo = c.d_geo;
+      A.nbr = c.d_nbr;
+      A.uoff = c.d_uoff;
+      A.n_elem = c.n_elem;
+      A.diss = ph.dissipation;
+      A.op = c.op32;
+      A.G = sbp::make_gas<float>(ph.gamma, ph.beta);
+      A.ent_part = M->d_part + c.part_off;
+      A.err = M->d_err;
+      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, A, s));
+    }
+  }
+  if (ent_dev) {
+    // classes whose actual grid is smaller than res_blocks leave stale
+    // partials; sum only the written ones
+    for (size_t ci = 0; ci < M->cls.size(); ++ci) {
+      auto &c = M->cls[ci];
+      const int nb = sbp::residual_blocks(M->dim, c.p, ph.precision, ph.form, c.n_elem);
+      HIPCHK(sbp::launch_reduce(M->d_part + c.part_off, nb, 1, 0, M->d_scal + SC_RED + ci, s));
+    }
+    if (M->cls.size() == 1) {
+      HIPCHK(hipMemcpyAsync(ent_dev, M->d_scal + SC_RED, sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+      HIPCHK(sbp::launch_reduce(M->d_scal + SC_RED, (int)M->cls.size(), 1, 0, ent_dev, s));
+    }
+  }
+  return SBP_OK;
+}
+
+// Sum node-kernel partials of all classes; nv values.  Returns host values.
+int reduce_nodes(sbp_mesh *M, int nv, int op, double *host, hipStream_t s) {
+  HIPCHK(sbp::launch_reduce(M->d_npart, M->node_total, nv, op, M->d_scal + SC_RED, s));
+  HIPCHK(hipMemcpyAsync(host, M->d_scal + SC_RED, sizeof(double) * nv, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return SBP_OK;
+}
+
+int check_err(sbp_mesh *M, hipStream_t s) {
+  int h = 0;
+  HIPCHK(hipMemcpyAsync(&h, M->d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (h) {
+    HIPCHK(hipMemsetAsync(M->d_err, 0, sizeof(int), s));
+    HIPCHK(hipStreamSynchronize(s));
+    return fail(SBP_ENONPHYS, "non-physical state (rho <= 0, p <= 0 or NaN) seen on the device");
+  }
+  return SBP_OK;
+}
+
+int entropy_gap(sbp_mesh *M, const double *u, const double *d, double g, double out[2], hipStream_t s) {
+  for (auto &c : M->cls) {
+    sbp::NodeArgs A = node_args(M, c, u, d);
+    HIPCHK(sbp::launch_entropy_gap(A, g, M->d_npart + c.node_off_blk, s));
+  }
+  return reduce_nodes(M, 2, 0, out, s);
+}
+
+int diagnostics_impl(sbp_mesh *M, const double *u, double *out, hipStream_t s) {
+  for (auto &c : M->cls) {
+    sbp::NodeArgs A = node_args(M, c, u, nullptr);
+    HIPCHK(sbp::launch_diagnostics(A, M->d_npart + c.node_off_blk, s));
+  }
+  return reduce_nodes(M, M->nc + 1, 0, out, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sbp_last_error(void) { return g_err.c_str(); }
+
+int sbp_setup_mesh(const sbp_mesh_desc *desc, const sbp_physics *phys, void *hip_stream, sbp_mesh **out) {
+  if (!desc || !phys || !out) return fail(SBP_EINVAL, "null argument");
+  *out = nullptr;
+  if (desc->dim != 2 && desc->dim != 3) return fail(SBP_EINVAL, "dim must be 2 or 3");
+  if (desc->n_elem <= 0 || desc->n_vert <= 0 || !desc->vert_xyz || !desc->elem_vert || !desc->period ||
+      !desc->elem_degree)
+    return fail(SBP_EINVAL, "incomplete mesh description");
+  if (desc->p_geom != 1 && !(desc->p_geom == 2 && desc->dim == 2 && desc->geom_nodes))
+    return fail(SBP_ENOTSUP, "p_geom must be 1, or 2 with geom_nodes in 2D");
+  if (desc->n_problems < 1) return fail(SBP_EINVAL, "n_problems must be >= 1");
+  for (int i = 0; i < desc->dim; ++i)
+    if (!(desc->period[i] > 0)) return fail(SBP_EINVAL, "period must be positive");
+  if (!(phys->gamma > 1.0) || !(phys->beta > 0.0)) return fail(SBP_EINVAL, "need gamma > 1 and beta > 0");
+  if (phys->form != SBP_FORM_SPLIT && phys->form != SBP_FORM_HADAMARD) return fail(SBP_EINVAL, "bad form");
+  if (phys->precision != SBP_FP64 && phys->precision != SBP_FP32) return fail(SBP_EINVAL, "bad precision");
+  if (phys->viscous) return fail(SBP_ENOTSUP, "viscous terms are not available in this build");
+  sbp_mesh *M = new (std::nothrow) sbp_mesh();
+  if (!M) return fail(SBP_ENOMEM, "host allocation failed");
+  int rc;
+  try {
+    rc = setup_impl(desc, phys, (hipStream_t)hip_stream, M);
+  } catch (const std::exception &ex) {
+    rc = fail(SBP_EINVAL, std::string("setup: ") + ex.what());
+  }
+  if (rc != SBP_OK) {
+    sbp_destroy_mesh(M);
+    return rc;
+  }
+  *out = M;
+  return SBP_OK;
+}
+
+int sbp_mesh_info(sbp_mesh *M, sbp_info *out) {
+  if (!M || !out) return fail(SBP_EINVAL, "null argument");
+  out->dim = M->dim;
+  out->n_c = M->nc;
+  out->n_elem = M->n_elem;
+  out->n_nodes = M->n_nodes;
+  out->node_off = M->node_off.data();
+  out->elem_np = M->elem_np.data();
+  out->node_xyz = M->d_node_xyz;
+  out->node_h = M->d_node_h;
+  out->t = M->t;
+  return check_err(M, nullptr);
+}
+
+int sbp_residual(sbp_mesh *M, const void *u, void *r, double *ent_dev, void *stream) {
+  if (!M || !u || !r) return fail(SBP_EINVAL, "null argument");
+  return residual_impl(M, (const double *)u, r, ent_dev, (hipStream_t)stream);
+}
+
+int sbp_residual_vjp(sbp_mesh *M, const void *u, const void *lam, void *ubar, void *stream) {
+  (void)stream;
+  if (!M || !u || !lam || !ubar) return fail(SBP_EINVAL, "null argument");
+  return fail(SBP_ENOTSUP, "residual VJP is not available in this build");
+}
+
+int sbp_diagnostics(sbp_mesh *M, const void *u, double *out_host, void *stream) {
+  if (!M || !u || !out_host) return fail(SBP_EINVAL, "null argument");
+  return diagnostics_impl(M, (const double *)u, out_host, (hipStream_t)stream);
+}
+
+int sbp_check_device(sbp_mesh *M, void *stream) {
+  if (!M) return fail(SBP_EINVAL, "null argument");
+  return check_err(M, (hipStream_t)stream);
+}
+
+int sbp_set_time(sbp_mesh *M, double t) {
+  if (!M) return fail(SBP_EINVAL, "null argument");
+  M->t = t;
+  return SBP_OK;
+}
+
+int sbp_rrk_step(sbp_mesh *M, void *u_dev, double dt, double cfl, sbp_rrk_report *rep, void *stream) {
+  if (!M || !u_dev) return fail(SBP_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  double *u = (double *)u_dev;
+  const long long n = M->n_dof;
+  const int f32 = M->phys.precision == SBP_FP32;
+  if (!M->d_y) {
+    HIPCHK(hipMalloc((void **)&M->d_y, sizeof(double) * n));
+    HIPCHK(hipMalloc((void **)&M->d_d, sizeof(double) * n));
+    HIPCHK(hipMalloc(&M->d_r, (f32 ? sizeof(float) : sizeof(double)) * n));
+  }
+  int rc;
+  if (!(dt > 0.0)) {
+    if (!(cfl > 0.0)) return fail(SBP_EINVAL, "need dt > 0 or cfl > 0");
+    for (auto &c : M->cls) {
+      sbp::NodeArgs A = node_args(M, c, u, nullptr);
+      HIPCHK(sbp::launch_dt(A, M->d_npart + c.node_off_blk, s));
+    }
+    double hmin_over_lam;
+    if ((rc = reduce_nodes(M, 1, 1, &hmin_over_lam, s))) return rc;
+    dt = cfl * hmin_over_lam;
+    if (!(dt > 0.0) || !std::isfinite(dt)) {
+      if ((rc = check_err(M, s))) return rc;
+      return fail(SBP_ENONPHYS, "time step is not positive (non-physical state)");
+    }
+  }
+  const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+  const double cst[4] = {0.0, 0.5, 0.5, 1.0};
+  HIPCHK(hipMemsetAsync(M->d_d, 0, sizeof(double) * n, s));
+  for (int i = 0; i < 4; ++i) {
+    const double *y = u;
+    if (i > 0) {
+      HIPCHK(sbp::launch_axpy(M->d_y, u, M->d_r, f32, cst[i] * dt, n, s));
+      y = M->d_y;
+    }
+    if ((rc = residual_impl(M, y, M->d_r, M->d_scal + SC_ENT + i, s))) return rc;
+    HIPCHK(sbp::launch_accum(M->d_d, M->d_r, f32, b[i] * dt, n, s));
+  }
+  double ent[4];
+  HIPCHK(hipMemcpyAsync(ent, M->d_scal + SC_ENT, sizeof(ent), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if ((rc = check_err(M, s))) return rc;
+  double e = 0.0;
+  for (int i = 0; i < 4; ++i) e += dt * b[i] * ent[i];
+  // relaxation parameter: root near 1 of r(g) = sum H [s(u + g d) - s(u)] - g e,
+  // Newton steps safeguarded by the bracket [0.5, 1.5] (bisection fallback)
+  double lo = 0.5, hi = 1.5, g = 1.0;
+  double fv[2];
+  if ((rc = entropy_gap(M, u, M->d_d, lo, fv, s))) return rc;
+  const double flo = fv[0] - lo * e;
+  if ((rc = entropy_gap(M, u, M->d_d, hi, fv, s))) return rc;
+  const double fhi = fv[0] - hi * e;
+  if (!(flo < 0.0 && fhi > 0.0)) return fail(SBP_ERRK, "relaxation root not bracketed in [0.5, 1.5]");
+  int it = 0;
+  for (; it < 100; ++it) {
+    if ((rc = entropy_gap(M, u, M->d_d, g, fv, s))) return rc;
+    const double f = fv[0] - g * e;
+    const double df = fv[1] - e;
+    if (f == 0.0) break;
+    if (f < 0.0) lo = g; else hi = g;
+    double gn = g - f / df;
+    if (!(df > 0.0) || !(gn > lo && gn < hi)) gn = 0.5 * (lo + hi);
+    if (gn == g || hi - lo <= 4.0 * 2.220446049250313e-16 * g) { g = gn; break; }
+    if (std::fabs(gn - g) <= 2.220446049250313e-16 * g) { g = gn; break; }
+    g = gn;
+  }
+  if (it >= 100) return fail(SBP_ERRK, "relaxation root solve did not converge");
+  double diag0[1 + 5] = {0}, diag1[1 + 5] = {0};
+  if (rep) {
+    if ((rc = diagnostics_impl(M, u, diag0, s))) return rc;
+  }
+  HIPCHK(sbp::launch_accum(u, M->d_d, 0, g, n, s));
+  M->t += g * dt;
+  if (rep) {
+    if ((rc = diagnostics_impl(M, u, diag1, s))) return rc;
+    rep->gamma_n = g;
+    rep->dt = dt;
+    rep->t = M->t;
+    rep->entropy_before = diag0[0];
+    rep->entropy_after = diag1[0];
+    rep->entropy_rate_e = e;
+    rep->newton_iters = it + 1;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return check_err(M, s);
+}
+
+int sbp_destroy_mesh(sbp_mesh *M) {
+  if (!M) return SBP_OK;
+  for (auto &c : M->cls) {
+    (void)hipFree(c.d_uoff);
+    (void)hipFree(c.d_geo);
+    (void)hipFree(c.d_nbr);
+    (void)hipFree(c.d_Hn);
+    (void)hipFree(c.d_hmin);
+    (void)hipFree(c.d_ops);
+  }
+  (void)hipFree(M->d_node_xyz);
+  (void)hipFree(M->d_node_h);
+  (void)hipFree(M->d_part);
+  (void)hipFree(M->d_npart);
+  (void)hipFree(M->d_scal);
+  (void)hipFree(M->d_err);
+  (void)hipFree(M->d_y);
+  (void)hipFree(M->d_d);
+  (void)hipFree(M->d_r);
+  delete M;
+  return SBP_OK;
+}
+
+int sbp_reference_operator(int32_t dim, int32_t p, int32_t *n_p, int32_t *n_f, double *nodes, double *h,
+                           double *Q, double *E, int32_t *facet_nodes, double *facet_w) {
+  try {
+    const sbp::RefOp &op = sbp::reference_operator(dim, p);
+    if (n_p) *n_p = op.np;
+    if (n_f) *n_f = op.nf;
+    if (nodes) std::memcpy(nodes, op.nodes.data(), op.nodes.size() * sizeof(double));
+    if (h) std::memcpy(h, op.h.data(), op.h.size() * sizeof(double));
+    if (Q) std::memcpy(Q, op.Q.data(), op.Q.size() * sizeof(double));
+    if (E) std::memcpy(E, op.E.data(), op.E.size() * sizeof(double));
+    if (facet_nodes)
+      for (size_t k = 0; k < op.facet_nodes.size(); ++k) facet_nodes[k] = op.facet_nodes[k];
+    if (facet_w) std::memcpy(facet_w, op.facet_w.data(), op.facet_w.size() * sizeof(double));
+  } catch (const std::invalid_argument &ex) {
+    return fail(SBP_ENOTSUP, ex.what());
+  } catch (const std::exception &ex) {
+    return fail(SBP_EINVAL, ex.what());
+  }
+  return SBP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,253 @@
+// Pointwise device functions of the entropy-split scheme (HIP, gfx950).
+//
+// Paper references: fluxes and EOS (Sec. 2.2); Harten entropy and entropy
+// variables (Sec. 2.4, Sec. 3); Sjogreen-Yee two-point flux with arithmetic
+// and exponential averages (Sec. 4); matrix interface dissipation (Sec. 4.4).
+//
+// Computation route (differs from a dense-matrix formulation on purpose):
+//   * A~_i g = dF^(i)/dW g is a forward-mode directional derivative through
+//     the inverse map U(W) (temperature and W_nc formulas of Sec. 3);
+//   * the dissipation X|Lambda|S X^T dw is applied column by column with the
+//     shear part in tangent-free form |V.n| eta (0, T q, V.T q),
+//     T = I - n n^T, q = dw_V + dw_E V (valid in 2D and 3D);
+//   * all powers come from per-node logarithms: z1 = exp(ln rho - ln p +
+//     (ln p - gamma ln rho)/(alpha+gamma)), z1^r1, p^r2 as exps.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace sbp {
+
+template <typename T>
+struct GasC {
+  T g, gm1, a, cb;       // gamma, gamma-1, alpha, 1/(beta+1)
+  T inv_apg;             // 1/(alpha+gamma)
+  T r1, r2;              // -gamma/alpha, (1-gamma)/alpha
+  T wfirst;              // -alpha/(gamma-1)
+  T ja, jb_inv;          // (1-alpha-gamma)/(alpha+gamma), (alpha+gamma)/(1-gamma)
+  T sfac;                // (gamma-1)(gamma+alpha)/(gamma alpha)
+  T ggm1;                // gamma/(gamma-1)
+};
+
+template <typename T>
+__host__ GasC<T> make_gas(double gamma, double beta) {
+  double alpha = -gamma - beta * (gamma - 1.0);
+  GasC<T> G;
+  G.g = (T)gamma;
+  G.gm1 = (T)(gamma - 1.0);
+  G.a = (T)alpha;
+  G.cb = (T)(1.0 / (beta + 1.0));
+  G.inv_apg = (T)(1.0 / (alpha + gamma));
+  G.r1 = (T)(-gamma / alpha);
+  G.r2 = (T)((1.0 - gamma) / alpha);
+  G.wfirst = (T)(-alpha / (gamma - 1.0));
+  G.ja = (T)((1.0 - alpha - gamma) / (alpha + gamma));
+  G.jb_inv = (T)((alpha + gamma) / (1.0 - gamma));
+  G.sfac = (T)((gamma - 1.0) * (gamma + alpha) / (gamma * alpha));
+  G.ggm1 = (T)(gamma / (gamma - 1.0));
+  return G;
+}
+
+__device__ __forceinline__ double dexp(double x) { return exp(x); }
+__device__ __forceinline__ float dexp(float x) { return expf(x); }
+__device__ __forceinline__ double dlog(double x) { return log(x); }
+__device__ __forceinline__ float dlog(float x) { return logf(x); }
+__device__ __forceinline__ double dsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float dsqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double dabs(double x) { return fabs(x); }
+__device__ __forceinline__ float dabs(float x) { return fabsf(x); }
+
+// Node quantities shared by the volume and facet terms.
+template <int D, typename T>
+struct Node {
+  T rho, V[D], p;
+  T lrho, lp;   // logarithms
+  T z1;         // (rho/p)(p rho^-gamma)^(1/(alpha+gamma)) = -W_nc
+  T P1, P2;     // z1^r1, p^r2 (powers entering the two-point flux averages)
+  T w[D + 2];   // entropy variables
+  bool ok;      // rho > 0 and p > 0 and finite
+};
+
+template <int D, typename T>
+__device__ __forceinline__ void node_from_u(const T *u, const GasC<T> &G, Node<D, T> &n) {
+  n.rho = u[0];
+  T q2 = 0;
+  T irho = (T)1 / n.rho;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    n.V[i] = u[1 + i] * irho;
+    q2 += n.V[i] * n.V[i];
+  }
+  n.p = G.gm1 * (u[D + 1] - (T)0.5 * n.rho * q2);
+  n.ok = (n.rho > (T)0) && (n.p > (T)0) && (n.rho < (T)1e300) && (n.p < (T)1e300);
+  n.lrho = dlog(n.rho);
+  n.lp = dlog(n.p);
+  T lz1 = n.lrho - n.lp + (n.lp - G.g * n.lrho) * G.inv_apg;
+  n.z1 = dexp(lz1);
+  n.P1 = dexp(G.r1 * lz1);
+  n.P2 = dexp(G.r2 * n.lp);
+  T theta = n.p * irho;
+  n.w[0] = n.z1 * (G.wfirst * theta - (T)0.5 * q2);
+#pragma unroll
+  for (int i = 0; i < D; ++i) n.w[1 + i] = n.z1 * n.V[i];
+  n.w[D + 1] = -n.z1;
+}
+
+// F^(i) from primitives.
+template <int D, typename T>
+__device__ __forceinline__ void flux_i(const Node<D, T> &n, T E, int i, T *f) {
+  T m = n.rho * n.V[i];
+  f[0] = m;
+#pragma unroll
+  for (int j = 0; j < D; ++j) f[1 + j] = m * n.V[j] + (j == i ? n.p : (T)0);
+  f[D + 1] = (E + n.p) * n.V[i];
+}
+
+// out = A~_i g = dF^(i)/dW [g] (forward-mode derivative through U(W)).
+template <int D, typename T>
+__device__ __forceinline__ void jvp_flux(const Node<D, T> &n, const GasC<T> &G, int i, const T *g, T *out) {
+  const T Wn = n.w[D + 1];
+  const T iWn = (T)1 / Wn;
+  T dV[D];
+  T q2 = 0, Vg = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    dV[k] = -(g[1 + k] + n.V[k] * g[D + 1]) * iWn;
+    q2 += n.V[k] * n.V[k];
+    Vg += n.V[k] * g[1 + k];
+  }
+  const T theta = n.p / n.rho;
+  const T c1 = G.gm1 / G.a * iWn;  // (gamma-1)/(alpha W_nc)
+  const T dtheta = c1 * (g[0] + Vg) + (-theta + (T)0.5 * G.gm1 / G.a * q2) * iWn * g[D + 1];
+  // ln(-W_nc) = ja ln(theta) + jb ln(rho)
+  const T drho = n.rho * (g[D + 1] * iWn - G.ja * dtheta / theta) * G.jb_inv;
+  const T dp = theta * drho + n.rho * dtheta;
+  T VdV = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) VdV += n.V[k] * dV[k];
+  out[0] = drho * n.V[i] + n.rho * dV[i];
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+    out[1 + j] = drho * n.V[i] * n.V[j] + n.rho * (dV[i] * n.V[j] + n.V[i] * dV[j]) + (j == i ? dp : (T)0);
+  const T ep = G.ggm1 * n.p + (T)0.5 * n.rho * q2;  // e + p
+  out[D + 1] = dV[i] * ep + n.V[i] * (G.ggm1 * dp + (T)0.5 * q2 * drho + n.rho * VdV);
+}
+
+// Exponential average {x^{r-1}}_e from values a, b and their r-th powers.
+template <typename T>
+__device__ __forceinline__ T exp_avg(T a, T b, T ar, T br, T r) {
+  const T s = a + b;
+  const T eps = (a - b) / s;
+  if (dabs(eps) <= (T)1e-2) {
+    const T m = (T)0.5 * s;
+    const T e2 = eps * eps;
+    const T c1 = (r - (T)1) * (r - (T)2) / (T)6;
+    const T c2 = c1 * (r - (T)3) * (r - (T)4) / (T)20;
+    const T c3 = c2 * (r - (T)5) * (r - (T)6) / (T)42;
+    const T c4 = c3 * (r - (T)7) * (r - (T)8) / (T)72;
+    const T mr = dexp((r - (T)1) * dlog(m));
+    return mr * ((T)1 + e2 * (c1 + e2 * (c2 + e2 * (c3 + e2 * c4))));
+  }
+  return (ar - br) / (r * (a - b));
+}
+
+// Facet term at one facet node pair, own side k, neighbour v, area-normal
+// a = B n (length B, direction the unit outward normal of k):
+//   out = a . F*(u_k, u_v)  [+ 1/2 |a| X|Lambda|S X^T (w_k - w_v)]
+// The residual receives -out / H_m.
+template <int D, typename T>
+__device__ __forceinline__ void facet_term(const Node<D, T> &k, const Node<D, T> &v, const T *a,
+                                           const GasC<T> &G, bool diss, T *out) {
+  constexpr int NC = D + 2;
+  const T P1k = k.P1, P1v = v.P1, P2k = k.P2, P2v = v.P2;
+  const T Ep = exp_avg(k.p, v.p, P2k, P2v, G.r2);
+  const T Ez = exp_avg(k.z1, v.z1, P1k, P1v, G.r1);
+  const T Dn = (T)0.5 * (P1k + P1v) * Ep;
+  const T iD = (T)1 / Dn;
+  T an = 0;  // a . {z1 V} / D
+  T Vav[D];
+  T q2av = 0, Vav2 = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    an += a[i] * (T)0.5 * (k.z1 * k.V[i] + v.z1 * v.V[i]);
+    Vav[i] = (T)0.5 * (k.V[i] + v.V[i]);
+    Vav2 += Vav[i] * Vav[i];
+    q2av += (T)0.5 * (k.V[i] * k.V[i] + v.V[i] * v.V[i]);
+  }
+  const T mass = an * iD;
+  const T pav = (T)0.5 * (k.p + v.p);
+  out[0] = mass;
+#pragma unroll
+  for (int j = 0; j < D; ++j) out[1 + j] = mass * Vav[j] + a[j] * pav;
+  out[NC - 1] = mass * (G.ggm1 * (T)0.5 * (P2k + P2v) * Ez + Vav2 - (T)0.5 * q2av);
+  if (!diss) return;
+  // intermediate state (Sec. 4.4)
+  const T z1a = (T)0.5 * (k.z1 + v.z1);
+  const T rho_h = z1a * iD;
+  T Vh[D];
+  T Vh2 = 0, B2 = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    Vh[i] = (T)0.5 * (k.z1 * k.V[i] + v.z1 * v.V[i]) / z1a;
+    Vh2 += Vh[i] * Vh[i];
+    B2 += a[i] * a[i];
+  }
+  const T B = dsqrt(B2);
+  const T iB = (T)1 / B;
+  T n[D];
+  T Vn = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    n[i] = a[i] * iB;
+    Vn += Vh[i] * n[i];
+  }
+  const T theta = rho_h / (pav * Dn);
+  const T eta = (T)1 / (z1a * Ez * Ep);
+  const T ah = dsqrt(G.g * pav / rho_h);
+  const T Hh = ah * ah / G.gm1 + (T)0.5 * Vh2;
+  T dw[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) dw[c] = k.w[c] - v.w[c];
+  // projections on the acoustic and entropy columns
+  T xdV = 0, ndV = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    xdV += Vh[i] * dw[1 + i];
+    ndV += n[i] * dw[1 + i];
+  }
+  const T pm = dw[0] + xdV - ah * ndV + (Hh - ah * Vn) * dw[NC - 1];   // x_-^T dw
+  const T pp = dw[0] + xdV + ah * ndV + (Hh + ah * Vn) * dw[NC - 1];   // x_+^T dw
+  const T p0 = dw[0] + xdV + (T)0.5 * Vh2 * dw[NC - 1];               // x_0^T dw
+  const T sa = theta / ((T)2 * G.g);
+  const T cm = dabs(Vn - ah) * sa * pm;
+  const T cp = dabs(Vn + ah) * sa * pp;
+  const T c0 = dabs(Vn) * G.sfac * theta * p0;
+  // shear: |Vn| eta (0, T q, V.T q), q = dw_V + dw_E V
+  T q[D];
+  T nq = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    q[i] = dw[1 + i] + dw[NC - 1] * Vh[i];
+    nq += n[i] * q[i];
+  }
+  const T cs = dabs(Vn) * eta;
+  T y[NC];
+  y[0] = cm + c0 + cp;
+  T VTq = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    T tq = q[i] - n[i] * nq;
+    VTq += Vh[i] * tq;
+    y[1 + i] = cm * (Vh[i] - ah * n[i]) + c0 * Vh[i] + cp * (Vh[i] + ah * n[i]) + cs * tq;
+  }
+  y[NC - 1] = cm * (Hh - ah * Vn) + c0 * (T)0.5 * Vh2 + cp * (Hh + ah * Vn) + cs * VTq;
+  const T hb = (T)0.5 * B;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) out[c] += hb * y[c];
+}
+
+// Harten entropy S = beta rho (p rho^-gamma)^(1/(alpha+gamma)) in FP64.
+__device__ __forceinline__ double entropy_harten(double rho, double p, double beta, double g, double inv_apg) {
+  return beta * rho * exp((log(p) - g * log(rho)) * inv_apg);
+}
+
+}  // namespace sbp

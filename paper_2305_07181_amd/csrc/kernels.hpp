@@ -1,0 +1,57 @@
+// Kernel-side shapes and argument blocks shared by the HIP translation units
+// and the host launch code.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device_physics.hpp"
+
+namespace sbp {
+
+constexpr int ru(int x, int m) { return (x + m - 1) / m * m; }
+
+// Node counts of the operators built by refops.cpp.
+template <int DIM, int P>
+struct Shape;
+template <> struct Shape<2, 1> { static constexpr int NP = 6, NF = 2; };
+template <> struct Shape<2, 2> { static constexpr int NP = 10, NF = 3; };
+template <> struct Shape<2, 3> { static constexpr int NP = 18, NF = 4; };
+template <> struct Shape<2, 4> { static constexpr int NP = 22, NF = 5; };
+template <> struct Shape<3, 1> { static constexpr int NP = 12, NF = 3; };
+template <> struct Shape<3, 2> { static constexpr int NP = 25, NF = 6; };
+template <> struct Shape<3, 3> { static constexpr int NP = 60, NF = 12; };
+
+// Device tables of one degree class (pointers into one device allocation).
+template <typename T>
+struct OpTables {
+  // entropy split, 3D affine: At1 = [M_1 M_2 M_3]^T (K1P x M1P), At2 = [D_1;D_2;D_3]^T
+  // entropy split, 2D mapped: At1..At4 = M_1^T, M_2^T, Q_1^T, Q_2^T (KP x MP)
+  // (M_l = c_b Q_xi_l + Q_xi_l^T; A^T stored k-major, zero padded)
+  const T *At1, *At2, *At3, *At4;
+  const T *S;   // Hadamard: S_xi_l [dim][NP][NP]
+  const T *h;   // [NP]
+  const T *E;   // [dim][NP] diagonal of E_xi_l
+  const T *dN;  // 2D: [2][6][NP] derivatives of the quadratic map basis at the nodes
+};
+
+template <typename T>
+struct KArgs {
+  const double *u;     // state (FP64)
+  T *r;                // residual (T)
+  const double *geo;   // 2D: [n_elem][12] map nodes; 3D: [n_elem][10] Lambda (row i, col l), J
+  const int *nbr;      // [n_elem][NFAC*NF] u offset of the matching neighbour node (component 0)
+  const int *uoff;     // [n_elem] u offset of each element of the class
+  int n_elem;
+  int diss;
+  OpTables<T> op;
+  GasC<T> G;
+  double *ent_part;    // [gridDim.x] partial sums of w^T H r (may be null)
+  int *err;            // non-physical state flag
+};
+
+// Elements per workgroup for each kernel (LDS budget <= 160 KiB on gfx950).
+template <int DIM, int P, typename T, int FORM>
+struct Tile;
+
+}  // namespace sbp

@@ -1,0 +1,43 @@
+// Host-callable kernel launchers (implemented in the .hip translation units).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace sbp {
+
+// Residual of one degree class (form 0: entropy split, 1: Hadamard).
+hipError_t launch_residual(int dim, int p, int form, const KArgs<double> &A, hipStream_t s);
+hipError_t launch_residual(int dim, int p, int form, const KArgs<float> &A, hipStream_t s);
+int residual_blocks(int dim, int p, int precision, int form, int n_elem);
+
+// Per-node pointwise work over one degree class.
+struct NodeArgs {
+  const double *u;     // state
+  const double *d;     // direction (entropy gap) or null
+  const int *uoff;     // [n_elem] element offsets into u
+  const double *Hn;    // [n_elem*np] diagonal of H_k
+  const double *hmin;  // [n_elem] minimum node distance (time step)
+  int n_elem, np, dim;
+  double gamma, beta;
+  int pstride;         // stride between the partial-sum rows of one launch
+};
+constexpr int kNodeThreads = 256;
+inline int node_blocks(int n_elem, int np) { return (n_elem * np + kNodeThreads - 1) / kNodeThreads; }
+
+// part[v*pstride + b], v = 0,1: sum_nodes H [s(u + g d) - s(u)], sum_nodes H w(u + g d).d
+hipError_t launch_entropy_gap(const NodeArgs &A, double g, double *part, hipStream_t s);
+// part[v*pstride + b], v = 0: sum H s(u); v = 1..n_c: sum H u_c
+hipError_t launch_diagnostics(const NodeArgs &A, double *part, hipStream_t s);
+// part[b] = min over the block's elements of hmin / max_nodes(|V| + a)
+hipError_t launch_dt(const NodeArgs &A, double *part, hipStream_t s);
+// out[v] = reduction over part[v*nb + b], b < nb (op 0: sum, 1: min); fixed order.
+hipError_t launch_reduce(const double *part, int nb, int nv, int op, double *out, hipStream_t s);
+// y = x + a z, z double or float (z_f32), n doubles
+hipError_t launch_axpy(double *y, const double *x, const void *z, int z_f32, double a, long long n, hipStream_t s);
+// y = y + a z (accumulate), z double or float
+hipError_t launch_accum(double *y, const void *z, int z_f32, double a, long long n, hipStream_t s);
+// out[slot] = sum_k coef_k * in[k] for k < nk (device scalars)
+hipError_t launch_scalar_combine(const double *in, const double *coef_dev, int nk, double *out, hipStream_t s);
+
+}  // namespace sbp

@@ -1,0 +1,614 @@
+// Residual kernels of the entropy-split SBP-SAT scheme for gfx950 (CDNA4).
+//
+// One workgroup (4 wave64) handles a tile of EB elements of one degree class:
+//   1. stage u (and the element geometry) in LDS;
+//   2. pointwise: primitives, entropy variables w, fluxes f^(i) and their
+//      contravariant combinations, written as the B operand of the operator
+//      contractions (columns = element x component);
+//   3. MFMA contractions with the reference operators shared by all elements
+//      of the class (v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4): the volume
+//      operator M = c_b Q + Q^T (Sec. 6.2, eq. weak form split) and the
+//      derivative operators (D or Q) acting on w;
+//   4. per node: H^-1 (volume) - c_b sum_i A~_i D_xi w with A~_i applied as a
+//      directional derivative, then at facet nodes the entropy-conservative
+//      SAT with the Sjogreen-Yee two-point flux (Sec. 4, eq. sats inv) and the
+//      optional matrix interface dissipation (Sec. 4.4), the neighbour state
+//      gathered through the precomputed face-node map; write r once;
+//   5. FP64 partial of sum w^T H r per workgroup (deterministic).
+// Each facet node belongs to exactly one facet, so every node's residual is
+// written by exactly one thread (no atomics, no second pass).
+//
+// The Hadamard-form comparator (Sec. 6.2, eq. weak form 2pt) evaluates every
+// node pair of an element once (upper triangle of S), stores the pair fluxes
+// in LDS and forms row sums in a fixed order (deterministic), then shares the
+// facet epilogue.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "launch.hpp"
+
+namespace sbp {
+
+template <> struct Tile<3, 1, double, 0> { static constexpr int EB = 16; };
+template <> struct Tile<3, 2, double, 0> { static constexpr int EB = 16; };
+template <> struct Tile<3, 3, double, 0> { static constexpr int EB = 6; };
+template <> struct Tile<3, 1, float, 0> { static constexpr int EB = 32; };
+template <> struct Tile<3, 2, float, 0> { static constexpr int EB = 32; };
+template <> struct Tile<3, 3, float, 0> { static constexpr int EB = 12; };
+template <> struct Tile<2, 1, double, 0> { static constexpr int EB = 16; };
+template <> struct Tile<2, 2, double, 0> { static constexpr int EB = 16; };
+template <> struct Tile<2, 3, double, 0> { static constexpr int EB = 8; };
+template <> struct Tile<2, 4, double, 0> { static constexpr int EB = 8; };
+template <> struct Tile<2, 1, float, 0> { static constexpr int EB = 32; };
+template <> struct Tile<2, 2, float, 0> { static constexpr int EB = 32; };
+template <> struct Tile<2, 3, float, 0> { static constexpr int EB = 16; };
+template <> struct Tile<2, 4, float, 0> { static constexpr int EB = 16; };
+// Hadamard form
+template <> struct Tile<3, 1, double, 1> { static constexpr int EB = 24; };
+template <> struct Tile<3, 2, double, 1> { static constexpr int EB = 8; };
+template <> struct Tile<3, 3, double, 1> { static constexpr int EB = 1; };
+template <> struct Tile<3, 1, float, 1> { static constexpr int EB = 32; };
+template <> struct Tile<3, 2, float, 1> { static constexpr int EB = 16; };
+template <> struct Tile<3, 3, float, 1> { static constexpr int EB = 2; };
+template <> struct Tile<2, 1, double, 1> { static constexpr int EB = 64; };
+template <> struct Tile<2, 2, double, 1> { static constexpr int EB = 32; };
+template <> struct Tile<2, 3, double, 1> { static constexpr int EB = 16; };
+template <> struct Tile<2, 4, double, 1> { static constexpr int EB = 12; };
+template <> struct Tile<2, 1, float, 1> { static constexpr int EB = 64; };
+template <> struct Tile<2, 2, float, 1> { static constexpr int EB = 64; };
+template <> struct Tile<2, 3, float, 1> { static constexpr int EB = 32; };
+template <> struct Tile<2, 4, float, 1> { static constexpr int EB = 24; };
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+// ---------------------------------------------------------------------------
+// MFMA 16x16x4 wrappers.  Lane l holds A[l%16][k0 + l/16], B[k0 + l/16][l%16]
+// and D[4*(l/16) + i][l%16], i = 0..3.
+template <typename T>
+struct MF;
+template <>
+struct MF<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct MF<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+// C[MP x NCP] = A[MP x KP] B[KP x NCP].  A^T in global memory (At[k*MP+m],
+// shared by all workgroups, L2 resident), B and C in LDS (row-major, leading
+// dimension NCP).  Output tiles are dealt round-robin to the waves; a wave
+// keeps all its accumulators in registers and interleaves their MFMAs in the
+// k loop.  Stores happen after a barrier, so C may alias B.
+template <typename T, int MP, int KP, int NCP>
+__device__ __forceinline__ void gemm_AtB(const T *__restrict__ At, const T *B, T *C) {
+  constexpr int MT = MP / 16, NT = NCP / 16, NTILE = MT * NT;
+  constexpr int TPW = (NTILE + kWaves - 1) / kWaves;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, kr = lane >> 4;
+  typename MF<T>::v4 acc[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) acc[t] = typename MF<T>::v4{0, 0, 0, 0};
+#pragma unroll 4
+  for (int k = 0; k < KP; k += 4) {
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int tile = wave + t * kWaves;
+      if (tile < NTILE) {
+        const int mt = tile % MT, nt = tile / MT;
+        const T a = At[(k + kr) * MP + mt * 16 + col];
+        const T b = B[(k + kr) * NCP + nt * 16 + col];
+        acc[t] = MF<T>::mma(a, b, acc[t]);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int tile = wave + t * kWaves;
+    if (tile < NTILE) {
+      const int mt = tile % MT, nt = tile / MT;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) C[(mt * 16 + 4 * kr + i) * NCP + nt * 16 + col] = acc[t][i];
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void block_sum_store(double v, double *out) {
+  __shared__ double red[kWaves];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kWaves; ++w) s += red[w];
+    if (out) out[blockIdx.x] = s;
+  }
+}
+
+// Facet SAT (+ dissipation), store of r, entropy-rate accumulation.
+template <int D, int NP, int NF, typename T>
+__device__ __forceinline__ void finish_node(const KArgs<T> &A, int eg, int i, const Node<D, T> &n,
+                                            T H, const T *avec, T *r, double &ent) {
+  constexpr int NC = D + 2, NFAC = D + 1;
+  const T iH = (T)1 / H;
+  if (i < NFAC * NF) {
+    const int off = A.nbr[(size_t)eg * NFAC * NF + i];
+    T uv[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) uv[c] = (T)A.u[off + c * NP];
+    Node<D, T> nv;
+    node_from_u<D, T>(uv, A.G, nv);
+    if (!nv.ok) atomicOr(A.err, 1);
+    T ft[NC];
+    facet_term<D, T>(n, nv, avec, A.G, A.diss != 0, ft);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) r[c] -= ft[c] * iH;
+  }
+  const int uo = A.uoff[eg];
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    A.r[uo + c * NP + i] = r[c];
+    s += (double)n.w[c] * (double)r[c];
+  }
+  ent += (double)H * s;
+}
+
+// ---------------------------------------------------------------------------
+// Entropy split, 3D affine tetrahedra.
+//   vol = sum_l M_l fhat_l, fhat_l = sum_i Lambda_il f^(i)     (one GEMM, K = 3 NP)
+//   D_xi w = sum_l (Lambda_il / J) D_xi_l w                   (one GEMM, M = 3 NP)
+template <int P, typename T>
+__global__ __launch_bounds__(kThreads) void k_split3(KArgs<T> A) {
+  constexpr int D = 3, NC = 5, NFAC = 4;
+  constexpr int NP = Shape<3, P>::NP, NF = Shape<3, P>::NF;
+  constexpr int EB = Tile<3, P, T, 0>::EB;
+  constexpr int NCOL = EB * NC, NCP = ru(NCOL, 16);
+  constexpr int K1P = ru(3 * NP, 4), M1P = ru(NP, 16);
+  constexpr int K2P = ru(NP, 4), M2P = ru(3 * NP, 16);
+  __shared__ T B1[K1P * NCP];
+  __shared__ T B2[K2P * NCP];
+  __shared__ T C1[M1P * NCP];
+  __shared__ T C2[M2P * NCP];
+  __shared__ T us[EB * NC * NP];
+  __shared__ T gs[EB * 10];
+  __shared__ T hs[NP];
+  __shared__ T Es[3 * NP];
+  const int tid = threadIdx.x;
+  const int e0 = blockIdx.x * EB;
+  const int ne = min(EB, A.n_elem - e0);
+  for (int x = tid; x < EB * 10; x += kThreads) {
+    const int e = x / 10;
+    gs[x] = e < ne ? (T)A.geo[(size_t)(e0 + e) * 10 + x % 10] : (T)0;
+  }
+  for (int x = tid; x < NP; x += kThreads) hs[x] = A.op.h[x];
+  for (int x = tid; x < 3 * NP; x += kThreads) Es[x] = A.op.E[x];
+  for (int x = tid; x < ne * NC * NP; x += kThreads) {
+    const int e = x / (NC * NP);
+    us[x] = (T)A.u[A.uoff[e0 + e] + x % (NC * NP)];
+  }
+  for (int x = tid; x < K1P * NCP; x += kThreads) B1[x] = (T)0;
+  for (int x = tid; x < K2P * NCP; x += kThreads) B2[x] = (T)0;
+  __syncthreads();
+  // pointwise: contravariant fluxes and entropy variables
+  for (int x = tid; x < ne * NP; x += kThreads) {
+    const int e = x / NP, j = x % NP;
+    T uu[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + j];
+    Node<D, T> n;
+    node_from_u<D, T>(uu, A.G, n);
+    if (!n.ok) atomicOr(A.err, 1);
+    T f[D][NC];
+#pragma unroll
+    for (int i = 0; i < D; ++i) flux_i<D, T>(n, uu[NC - 1], i, f[i]);
+    const T *Lam = gs + e * 10;
+#pragma unroll
+    for (int l = 0; l < D; ++l)
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        B1[(l * NP + j) * NCP + e * NC + c] = Lam[0 * 3 + l] * f[0][c] + Lam[1 * 3 + l] * f[1][c] + Lam[2 * 3 + l] * f[2][c];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) B2[j * NCP + e * NC + c] = n.w[c];
+  }
+  __syncthreads();
+  gemm_AtB<T, M1P, K1P, NCP>(A.op.At1, B1, C1);
+  gemm_AtB<T, M2P, K2P, NCP>(A.op.At2, B2, C2);
+  double ent = 0.0;
+  for (int x = tid; x < ne * NP; x += kThreads) {
+    const int e = x / NP, i = x % NP;
+    T uu[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + i];
+    Node<D, T> n;
+    node_from_u<D, T>(uu, A.G, n);
+    const T *Lam = gs + e * 10;
+    const T J = Lam[9];
+    const T iJ = (T)1 / J;
+    const T H = J * hs[i];
+    const T iH = (T)1 / H;
+    T r[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) r[c] = C1[i * NCP + e * NC + c] * iH;
+#pragma unroll
+    for (int dir = 0; dir < D; ++dir) {
+      T g[NC], t[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        T s = 0;
+#pragma unroll
+        for (int l = 0; l < D; ++l) s += Lam[dir * 3 + l] * C2[(l * NP + i) * NCP + e * NC + c];
+        g[c] = s * iJ;
+      }
+      jvp_flux<D, T>(n, A.G, dir, g, t);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) r[c] -= A.G.cb * t[c];
+    }
+    T avec[D];
+#pragma unroll
+    for (int dir = 0; dir < D; ++dir) {
+      T s = 0;
+#pragma unroll
+      for (int l = 0; l < D; ++l) s += Lam[dir * 3 + l] * Es[l * NP + i];
+      avec[dir] = s;
+    }
+    finish_node<D, NP, NF, T>(A, e0 + e, i, n, H, avec, r, ent);
+  }
+  block_sum_store(ent, A.ent_part);
+}
+
+// ---------------------------------------------------------------------------
+// Entropy split, 2D triangles with per-node metrics of a quadratic map.
+//   sum_i [c_b Q_xi + Q_xi^T] f^(i) = 1/2 sum_l [ sum_i Lambda_il o (M_l f^(i)) + M_l fhat_l ]
+//   Q_xi w                           = 1/2 sum_l [ Lambda_il o (Q_l w) + Q_l (Lambda_il o w) ]
+// One pass per reference direction l (two GEMMs, 3 NC columns per element).
+template <int P, typename T>
+__global__ __launch_bounds__(kThreads) void k_split2(KArgs<T> A) {
+  constexpr int D = 2, NC = 4, NFAC = 3;
+  constexpr int NP = Shape<2, P>::NP, NF = Shape<2, P>::NF;
+  constexpr int EB = Tile<2, P, T, 0>::EB;
+  constexpr int NCOL = EB * 3 * NC, NCP = ru(NCOL, 16);
+  constexpr int KP = ru(NP, 4), MP = ru(NP, 16);
+  __shared__ T BM[KP * NCP];
+  __shared__ T BQ[KP * NCP];
+  __shared__ T CM[MP * NCP];
+  __shared__ T CQ[MP * NCP];
+  __shared__ T acc[EB * NP * 3 * NC];  // [e][i][vol(NC), Qx_0 w (NC), Qx_1 w (NC)]
+  __shared__ T us[EB * NC * NP];
+  __shared__ T met[EB * NP * 5];       // Lambda_00, Lambda_01, Lambda_10, Lambda_11, J
+  __shared__ T hs[NP];
+  __shared__ T Es[2 * NP];
+  const int tid = threadIdx.x;
+  const int e0 = blockIdx.x * EB;
+  const int ne = min(EB, A.n_elem - e0);
+  for (int x = tid; x < NP; x += kThreads) hs[x] = A.op.h[x];
+  for (int x = tid; x < 2 * NP; x += kThreads) Es[x] = A.op.E[x];
+  for (int x = tid; x < ne * NC * NP; x += kThreads) {
+    const int e = x / (NC * NP);
+    us[x] = (T)A.u[A.uoff[e0 + e] + x % (NC * NP)];
+  }
+  for (int x = tid; x < EB * NP * 3 * NC; x += kThreads) acc[x] = (T)0;
+  // metrics at the nodes: F[i][l] = dx_i/dxi_l, Lambda_il = J dxi_l/dx_i
+  for (int x = tid; x < ne * NP; x += kThreads) {
+    const int e = x / NP, j = x % NP;
+    const double *g = A.geo + (size_t)(e0 + e) * 12;
+    T F[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      const T d0 = A.op.dN[(0 * 6 + a) * NP + j], d1 = A.op.dN[(1 * 6 + a) * NP + j];
+      const T gx = (T)g[2 * a], gy = (T)g[2 * a + 1];
+      F[0][0] += d0 * gx;
+      F[0][1] += d1 * gx;
+      F[1][0] += d0 * gy;
+      F[1][1] += d1 * gy;
+    }
+    T *m = met + (e * NP + j) * 5;
+    m[0] = F[1][1];   // Lambda_00
+    m[1] = -F[1][0];  // Lambda_01
+    m[2] = -F[0][1];  // Lambda_10
+    m[3] = F[0][0];   // Lambda_11
+    m[4] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  }
+  __syncthreads();
+  for (int l = 0; l < 2; ++l) {
+    for (int x = tid; x < KP * NCP; x += kThreads) {
+      BM[x] = (T)0;
+      BQ[x] = (T)0;
+    }
+    __syncthreads();
+    for (int x = tid; x < ne * NP; x += kThreads) {
+      const int e = x / NP, j = x % NP;
+      T uu[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + j];
+      Node<D, T> n;
+      node_from_u<D, T>(uu, A.G, n);
+      if (l == 0 && !n.ok) atomicOr(A.err, 1);
+      T f0[NC], f1[NC];
+      flux_i<D, T>(n, uu[NC - 1], 0, f0);
+      flux_i<D, T>(n, uu[NC - 1], 1, f1);
+      const T *m = met + (e * NP + j) * 5;
+      const T L0l = m[0 * 2 + l], L1l = m[1 * 2 + l];
+      const int base = j * NCP + e * 3 * NC;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        BM[base + 0 * NC + c] = f0[c];
+        BM[base + 1 * NC + c] = f1[c];
+        BM[base + 2 * NC + c] = L0l * f0[c] + L1l * f1[c];
+        BQ[base + 0 * NC + c] = n.w[c];
+        BQ[base + 1 * NC + c] = L0l * n.w[c];
+        BQ[base + 2 * NC + c] = L1l * n.w[c];
+      }
+    }
+    __syncthreads();
+    gemm_AtB<T, MP, KP, NCP>(l == 0 ? A.op.At1 : A.op.At2, BM, CM);
+    gemm_AtB<T, MP, KP, NCP>(l == 0 ? A.op.At3 : A.op.At4, BQ, CQ);
+    for (int x = tid; x < ne * NP; x += kThreads) {
+      const int e = x / NP, i = x % NP;
+      const T *m = met + (e * NP + i) * 5;
+      const T L0l = m[0 * 2 + l], L1l = m[1 * 2 + l];
+      const int base = i * NCP + e * 3 * NC;
+      T *ac = acc + (e * NP + i) * 3 * NC;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        ac[c] += (T)0.5 * (L0l * CM[base + 0 * NC + c] + L1l * CM[base + 1 * NC + c] + CM[base + 2 * NC + c]);
+        ac[NC + c] += (T)0.5 * (L0l * CQ[base + 0 * NC + c] + CQ[base + 1 * NC + c]);
+        ac[2 * NC + c] += (T)0.5 * (L1l * CQ[base + 0 * NC + c] + CQ[base + 2 * NC + c]);
+      }
+    }
+    __syncthreads();
+  }
+  double ent = 0.0;
+  for (int x = tid; x < ne * NP; x += kThreads) {
+    const int e = x / NP, i = x % NP;
+    T uu[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + i];
+    Node<D, T> n;
+    node_from_u<D, T>(uu, A.G, n);
+    const T *m = met + (e * NP + i) * 5;
+    const T H = m[4] * hs[i];
+    const T iH = (T)1 / H;
+    const T *ac = acc + (e * NP + i) * 3 * NC;
+    T r[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) r[c] = ac[c] * iH;
+#pragma unroll
+    for (int dir = 0; dir < D; ++dir) {
+      T g[NC], t[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) g[c] = ac[(1 + dir) * NC + c] * iH;
+      jvp_flux<D, T>(n, A.G, dir, g, t);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) r[c] -= A.G.cb * t[c];
+    }
+    T avec[D];
+    avec[0] = m[0] * Es[i] + m[1] * Es[NP + i];
+    avec[1] = m[2] * Es[i] + m[3] * Es[NP + i];
+    finish_node<D, NP, NF, T>(A, e0 + e, i, n, H, avec, r, ent);
+  }
+  block_sum_store(ent, A.ent_part);
+}
+
+// ---------------------------------------------------------------------------
+// Hadamard form (comparator): r_m = -H_m^-1 sum_{n != m} sum_l S_l[m][n]
+//   sum_i (Lambda_il(m) + Lambda_il(n)) F*_i(u_m, u_n), pairs evaluated once.
+template <int DIM, int P, typename T>
+__global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
+  constexpr int D = DIM, NC = D + 2, NFAC = D + 1;
+  constexpr int NP = Shape<DIM, P>::NP, NF = Shape<DIM, P>::NF;
+  constexpr int EB = Tile<DIM, P, T, 1>::EB;
+  constexpr int NPAIR = NP * (NP - 1) / 2;
+  constexpr int NV = D + 5;  // rho, V, p, z1, P1, P2
+  constexpr int NMET = D * D + 1;
+  __shared__ T Gp[EB * NPAIR * NC];
+  __shared__ T nd[EB * NP * NV];
+  __shared__ T met[EB * NP * NMET];
+  __shared__ T us[EB * NC * NP];
+  __shared__ short2 pairs[NPAIR];
+  __shared__ T hs[NP];
+  __shared__ T Es[D * NP];
+  const int tid = threadIdx.x;
+  const int e0 = blockIdx.x * EB;
+  const int ne = min(EB, A.n_elem - e0);
+  for (int q = tid; q < NPAIR; q += kThreads) {
+    int m = 0, rem = q;
+    while (rem >= NP - 1 - m) {
+      rem -= NP - 1 - m;
+      ++m;
+    }
+    pairs[q] = make_short2((short)m, (short)(m + 1 + rem));
+  }
+  for (int x = tid; x < NP; x += kThreads) hs[x] = A.op.h[x];
+  for (int x = tid; x < D * NP; x += kThreads) Es[x] = A.op.E[x];
+  for (int x = tid; x < ne * NC * NP; x += kThreads) {
+    const int e = x / (NC * NP);
+    us[x] = (T)A.u[A.uoff[e0 + e] + x % (NC * NP)];
+  }
+  // metrics per node: Lambda (row i, col l) and J
+  for (int x = tid; x < ne * NP; x += kThreads) {
+    const int e = x / NP, j = x % NP;
+    T *m = met + (e * NP + j) * NMET;
+    if constexpr (D == 3) {
+      const double *g = A.geo + (size_t)(e0 + e) * 10;
+#pragma unroll
+      for (int k = 0; k < 10; ++k) m[k] = (T)g[k];
+    } else {
+      const double *g = A.geo + (size_t)(e0 + e) * 12;
+      T F[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        const T d0 = A.op.dN[(0 * 6 + a) * NP + j], d1 = A.op.dN[(1 * 6 + a) * NP + j];
+        F[0][0] += d0 * (T)g[2 * a];
+        F[0][1] += d1 * (T)g[2 * a];
+        F[1][0] += d0 * (T)g[2 * a + 1];
+        F[1][1] += d1 * (T)g[2 * a + 1];
+      }
+      m[0] = F[1][1];
+      m[1] = -F[1][0];
+      m[2] = -F[0][1];
+      m[3] = F[0][0];
+      m[4] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+    }
+  }
+  __syncthreads();
+  for (int x = tid; x < ne * NP; x += kThreads) {
+    const int e = x / NP, j = x % NP;
+    T uu[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + j];
+    Node<D, T> n;
+    node_from_u<D, T>(uu, A.G, n);
+    if (!n.ok) atomicOr(A.err, 1);
+    T *v = nd + (e * NP + j) * NV;
+    v[0] = n.rho;
+#pragma unroll
+    for (int i = 0; i < D; ++i) v[1 + i] = n.V[i];
+    v[D + 1] = n.p;
+    v[D + 2] = n.z1;
+    v[D + 3] = n.P1;
+    v[D + 4] = n.P2;
+  }
+  __syncthreads();
+  for (int x = tid; x < ne * NPAIR; x += kThreads) {
+    const int e = x / NPAIR, q = x % NPAIR;
+    const short2 mn = pairs[q];
+    const int m = mn.x, nn = mn.y;
+    Node<D, T> a, b;
+    const T *va = nd + (e * NP + m) * NV;
+    const T *vb = nd + (e * NP + nn) * NV;
+    a.rho = va[0];
+    b.rho = vb[0];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      a.V[i] = va[1 + i];
+      b.V[i] = vb[1 + i];
+    }
+    a.p = va[D + 1];
+    b.p = vb[D + 1];
+    a.z1 = va[D + 2];
+    b.z1 = vb[D + 2];
+    a.P1 = va[D + 3];
+    b.P1 = vb[D + 3];
+    a.P2 = va[D + 4];
+    b.P2 = vb[D + 4];
+    const T *ma = met + (e * NP + m) * NMET;
+    const T *mb = met + (e * NP + nn) * NMET;
+    T cvec[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      T s = 0;
+#pragma unroll
+      for (int l = 0; l < D; ++l) s += A.op.S[(l * NP + m) * NP + nn] * (ma[i * D + l] + mb[i * D + l]);
+      cvec[i] = s;
+    }
+    T out[NC];
+    facet_term<D, T>(a, b, cvec, A.G, false, out);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) Gp[(e * NPAIR + q) * NC + c] = out[c];
+  }
+  __syncthreads();
+  double ent = 0.0;
+  for (int x = tid; x < ne * NP; x += kThreads) {
+    const int e = x / NP, i = x % NP;
+    T uu[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + i];
+    Node<D, T> n;
+    node_from_u<D, T>(uu, A.G, n);
+    const T *m = met + (e * NP + i) * NMET;
+    const T H = m[D * D] * hs[i];
+    const T iH = (T)1 / H;
+    T r[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) r[c] = 0;
+    // pairs (k, i) with k < i contribute -G_ki, pairs (i, k) with k > i +G_ik
+    for (int k = 0; k < i; ++k) {
+      const int q = k * NP - k * (k + 1) / 2 + (i - k - 1);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) r[c] += Gp[(e * NPAIR + q) * NC + c];
+    }
+    for (int k = i + 1; k < NP; ++k) {
+      const int q = i * NP - i * (i + 1) / 2 + (k - i - 1);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) r[c] -= Gp[(e * NPAIR + q) * NC + c];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) r[c] *= iH;
+    T avec[D];
+#pragma unroll
+    for (int dir = 0; dir < D; ++dir) {
+      T s = 0;
+#pragma unroll
+      for (int l = 0; l < D; ++l) s += m[dir * D + l] * Es[l * NP + i];
+      avec[dir] = s;
+    }
+    finish_node<D, NP, NF, T>(A, e0 + e, i, n, H, avec, r, ent);
+  }
+  block_sum_store(ent, A.ent_part);
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+int tile_elems(int dim, int p, int form) {
+#define SBP_TILE(DI, PP) \
+  if (dim == DI && p == PP) return form ? Tile<DI, PP, T, 1>::EB : Tile<DI, PP, T, 0>::EB;
+  SBP_TILE(2, 1) SBP_TILE(2, 2) SBP_TILE(2, 3) SBP_TILE(2, 4)
+  SBP_TILE(3, 1) SBP_TILE(3, 2) SBP_TILE(3, 3)
+#undef SBP_TILE
+  return 0;
+}
+
+int residual_blocks(int dim, int p, int precision, int form, int n_elem) {
+  const int eb = precision == 0 ? tile_elems<double>(dim, p, form) : tile_elems<float>(dim, p, form);
+  if (eb <= 0) return 0;
+  return (n_elem + eb - 1) / eb;
+}
+
+template <typename T>
+static hipError_t launch_t(int dim, int p, int form, const KArgs<T> &A, hipStream_t s) {
+  const int nb = residual_blocks(dim, p, sizeof(T) == 8 ? 0 : 1, form, A.n_elem);
+  if (nb <= 0) return hipErrorInvalidValue;
+  dim3 grid(nb), block(kThreads);
+#define SBP_LAUNCH(DI, PP)                                                 \
+  if (dim == DI && p == PP) {                                              \
+    if (form == 1)                                                         \
+      hipLaunchKernelGGL((k_hadamard<DI, PP, T>), grid, block, 0, s, A);   \
+    else                                                                   \
+      hipLaunchKernelGGL((k_split2<PP, T>), grid, block, 0, s, A);         \
+    return hipGetLastError();                                              \
+  }
+  SBP_LAUNCH(2, 1) SBP_LAUNCH(2, 2) SBP_LAUNCH(2, 3) SBP_LAUNCH(2, 4)
+#undef SBP_LAUNCH
+#define SBP_LAUNCH3(PP)                                                  \
+  if (dim == 3 && p == PP) {                                             \
+    if (form == 1)                                                       \
+      hipLaunchKernelGGL((k_hadamard<3, PP, T>), grid, block, 0, s, A);  \
+    else                                                                 \
+      hipLaunchKernelGGL((k_split3<PP, T>), grid, block, 0, s, A);       \
+    return hipGetLastError();                                            \
+  }
+  SBP_LAUNCH3(1) SBP_LAUNCH3(2) SBP_LAUNCH3(3)
+#undef SBP_LAUNCH3
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_residual(int dim, int p, int form, const KArgs<double> &A, hipStream_t s) {
+  return launch_t<double>(dim, p, form, A, s);
+}
+hipError_t launch_residual(int dim, int p, int form, const KArgs<float> &A, hipStream_t s) {
+  return launch_t<float>(dim, p, form, A, s);
+}
+
+}  // namespace sbp

@@ -1,0 +1,253 @@
+// Time-integration kernels: relaxation RK4 stages, FP64 entropy sums, the
+// relaxation root function, the time step and diagnostics (Sec. 6.1, 7.1).
+//
+// All reductions are two-stage and deterministic: every workgroup writes one
+// partial per quantity, a single workgroup combines the partials in a fixed
+// order.  Entropy differences are summed node by node,
+// H_m [s(u_m + g d_m) - s(u_m)], to avoid cancellation of two global sums.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "launch.hpp"
+
+namespace sbp {
+
+namespace {
+
+constexpr int kT = kNodeThreads;
+
+__device__ __forceinline__ double block_reduce_sum(double v, double *red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  return s;
+}
+
+__device__ __forceinline__ double block_reduce_min(double v, double *red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_down(v, o, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = INFINITY;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s = fmin(s, red[w]);
+  return s;
+}
+
+// Harten entropy and entropy variables in FP64 from a conservative state.
+template <int D>
+__device__ __forceinline__ bool ent_state(const double *u, double g, double beta, double *S, double *w) {
+  const double alpha = -g - beta * (g - 1.0);
+  const double rho = u[0];
+  double q2 = 0.0, V[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    V[i] = u[1 + i] / rho;
+    q2 += V[i] * V[i];
+  }
+  const double p = (g - 1.0) * (u[D + 1] - 0.5 * rho * q2);
+  const double phi = exp((log(p) - g * log(rho)) / (alpha + g));  // (p rho^-g)^(1/(a+g))
+  *S = beta * rho * phi;
+  if (w) {
+    const double z1 = rho / p * phi;
+    w[0] = z1 * (-alpha / (g - 1.0) * p / rho - 0.5 * q2);
+#pragma unroll
+    for (int i = 0; i < D; ++i) w[1 + i] = z1 * V[i];
+    w[D + 1] = -z1;
+  }
+  return rho > 0.0 && p > 0.0;
+}
+
+template <int D>
+__global__ __launch_bounds__(kT) void k_entropy_gap(NodeArgs A, double gam, double *part) {
+  constexpr int NC = D + 2;
+  __shared__ double red[kT / 64];
+  const int x = blockIdx.x * kT + threadIdx.x;
+  double a = 0.0, b = 0.0;
+  if (x < A.n_elem * A.np) {
+    const int e = x / A.np, j = x % A.np;
+    const int base = A.uoff[e] + j;
+    double u0[NC], u1[NC], dd[NC], w1[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      u0[c] = A.u[base + c * A.np];
+      dd[c] = A.d[base + c * A.np];
+      u1[c] = u0[c] + gam * dd[c];
+    }
+    double s0, s1;
+    ent_state<D>(u0, A.gamma, A.beta, &s0, nullptr);
+    ent_state<D>(u1, A.gamma, A.beta, &s1, w1);
+    const double H = A.Hn[x];
+    a = H * (s1 - s0);
+    double wd = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) wd += w1[c] * dd[c];
+    b = H * wd;
+  }
+  const double sa = block_reduce_sum(a, red);
+  const double sb = block_reduce_sum(b, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = sa;
+    part[A.pstride + blockIdx.x] = sb;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kT) void k_diagnostics(NodeArgs A, double *part) {
+  constexpr int NC = D + 2;
+  __shared__ double red[kT / 64];
+  const int x = blockIdx.x * kT + threadIdx.x;
+  double v[NC + 1];
+#pragma unroll
+  for (int c = 0; c <= NC; ++c) v[c] = 0.0;
+  if (x < A.n_elem * A.np) {
+    const int e = x / A.np, j = x % A.np;
+    const int base = A.uoff[e] + j;
+    double u0[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) u0[c] = A.u[base + c * A.np];
+    double s;
+    ent_state<D>(u0, A.gamma, A.beta, &s, nullptr);
+    const double H = A.Hn[x];
+    v[0] = H * s;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[1 + c] = H * u0[c];
+  }
+#pragma unroll
+  for (int c = 0; c <= NC; ++c) {
+    const double t = block_reduce_sum(v[c], red);
+    if (threadIdx.x == 0) part[c * A.pstride + blockIdx.x] = t;
+  }
+}
+
+// One thread per node computes |V| + a; the element minimum of
+// hmin / lambda_max equals min over its nodes of hmin / (|V| + a).
+template <int D>
+__global__ __launch_bounds__(kT) void k_dt(NodeArgs A, double *part) {
+  constexpr int NC = D + 2;
+  __shared__ double red[kT / 64];
+  const int x = blockIdx.x * kT + threadIdx.x;
+  double v = INFINITY;
+  if (x < A.n_elem * A.np) {
+    const int e = x / A.np, j = x % A.np;
+    const int base = A.uoff[e] + j;
+    double u0[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) u0[c] = A.u[base + c * A.np];
+    const double rho = u0[0];
+    double q2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) q2 += (u0[1 + i] / rho) * (u0[1 + i] / rho);
+    const double p = (A.gamma - 1.0) * (u0[NC - 1] - 0.5 * rho * q2);
+    const double lam = sqrt(q2) + sqrt(A.gamma * p / rho);
+    v = A.hmin[e] / lam;
+    if (!(v > 0.0)) v = 0.0;  // non-physical state: forces dt = 0, reported by the caller
+  }
+  const double m = block_reduce_min(v, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(kT) void k_reduce(const double *part, int nb, int op, double *out) {
+  __shared__ double red[kT / 64];
+  const int v = blockIdx.x;
+  double acc = op == 0 ? 0.0 : INFINITY;
+  for (int b = threadIdx.x; b < nb; b += kT) {
+    const double x = part[(size_t)v * nb + b];
+    acc = op == 0 ? acc + x : fmin(acc, x);
+  }
+  const double r = op == 0 ? block_reduce_sum(acc, red) : block_reduce_min(acc, red);
+  if (threadIdx.x == 0) out[v] = r;
+}
+
+template <typename Z>
+__global__ __launch_bounds__(kT) void k_axpy(double *y, const double *x, const Z *z, double a, long long n) {
+  for (long long i = blockIdx.x * (long long)kT + threadIdx.x; i < n; i += (long long)gridDim.x * kT)
+    y[i] = x[i] + a * (double)z[i];
+}
+
+template <typename Z>
+__global__ __launch_bounds__(kT) void k_accum(double *y, const Z *z, double a, long long n) {
+  for (long long i = blockIdx.x * (long long)kT + threadIdx.x; i < n; i += (long long)gridDim.x * kT)
+    y[i] += a * (double)z[i];
+}
+
+__global__ void k_scalar_combine(const double *in, const double *coef, int nk, double *out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < nk; ++k) s += coef[k] * in[k];
+    out[0] = s;
+  }
+}
+
+int grid_for(long long n) {
+  long long b = (n + kT - 1) / kT;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+}  // namespace
+
+hipError_t launch_entropy_gap(const NodeArgs &A, double g, double *part, hipStream_t s) {
+  const int nb = node_blocks(A.n_elem, A.np);
+  if (A.dim == 2)
+    hipLaunchKernelGGL(k_entropy_gap<2>, dim3(nb), dim3(kT), 0, s, A, g, part);
+  else
+    hipLaunchKernelGGL(k_entropy_gap<3>, dim3(nb), dim3(kT), 0, s, A, g, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_diagnostics(const NodeArgs &A, double *part, hipStream_t s) {
+  const int nb = node_blocks(A.n_elem, A.np);
+  if (A.dim == 2)
+    hipLaunchKernelGGL(k_diagnostics<2>, dim3(nb), dim3(kT), 0, s, A, part);
+  else
+    hipLaunchKernelGGL(k_diagnostics<3>, dim3(nb), dim3(kT), 0, s, A, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_dt(const NodeArgs &A, double *part, hipStream_t s) {
+  const int nb = node_blocks(A.n_elem, A.np);
+  if (A.dim == 2)
+    hipLaunchKernelGGL(k_dt<2>, dim3(nb), dim3(kT), 0, s, A, part);
+  else
+    hipLaunchKernelGGL(k_dt<3>, dim3(nb), dim3(kT), 0, s, A, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double *part, int nb, int nv, int op, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(kT), 0, s, part, nb, op, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(double *y, const double *x, const void *z, int z_f32, double a, long long n, hipStream_t s) {
+  if (z_f32)
+    hipLaunchKernelGGL(k_axpy<float>, dim3(grid_for(n)), dim3(kT), 0, s, y, x, (const float *)z, a, n);
+  else
+    hipLaunchKernelGGL(k_axpy<double>, dim3(grid_for(n)), dim3(kT), 0, s, y, x, (const double *)z, a, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_accum(double *y, const void *z, int z_f32, double a, long long n, hipStream_t s) {
+  if (z_f32)
+    hipLaunchKernelGGL(k_accum<float>, dim3(grid_for(n)), dim3(kT), 0, s, y, (const float *)z, a, n);
+  else
+    hipLaunchKernelGGL(k_accum<double>, dim3(grid_for(n)), dim3(kT), 0, s, y, (const double *)z, a, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scalar_combine(const double *in, const double *coef_dev, int nk, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_scalar_combine, dim3(1), dim3(64), 0, s, in, coef_dev, nk, out);
+  return hipGetLastError();
+}
+
+}  // namespace sbp

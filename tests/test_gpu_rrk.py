@@ -1,0 +1,69 @@
+"""GPU relaxation RK4 against the oracle's (Sec. 6.1): the 128-triangle p=2
+isentropic vortex, EC SATs, CFL 0.1, 20 steps; and fully discrete entropy
+conservation on the GPU."""
+import numpy as np
+import pytest
+
+from tests.gpu_common import say, state
+
+pytestmark = pytest.mark.gpu
+
+
+def test_rrk_vortex_20_steps_parity():
+    import torch
+    from oracle import physics as ph
+    from oracle import rrk
+    from oracle.geometry import OracleMesh
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say("[rrk vortex 20 steps]")
+    desc = wl.vortex2d_mesh(8)
+    m = OracleMesh(desc, 2)
+    sch = OracleScheme(m, ph.Gas())
+    u = state(m, "vortex")
+    mesh = sbp.Mesh(desc, 2)
+    ud = torch.from_numpy(u).cuda()
+    s0 = sch.total_entropy(u)
+    uo = u.copy()
+    for step in range(20):
+        dt_o = sch.timestep(uo, 0.1)
+        rep = mesh.rrk_step(ud, cfl=0.1)
+        assert abs(rep["dt"] - dt_o) <= 1e-13 * dt_o, (rep["dt"], dt_o)
+        uo, g, d, e = rrk.rrk4_step(sch, uo, dt_o)
+        ug = ud.cpu().numpy()
+        err = np.abs(ug - uo).max(axis=(0, 2)) / np.abs(uo).max(axis=(0, 2))
+        ds = (rep["entropy_after"] - s0) / abs(s0)
+        say(f"   step {step}: gamma gpu {rep['gamma']:.16f} oracle {g:.16f} | rel err {err.max():.2e} "
+            f"| entropy change {ds:.2e} | iters {rep['iters']}")
+        assert (err <= 1e-12).all(), err
+        assert abs(ds) <= 1e-13
+        assert abs(rep["gamma"] - g) <= 1e-6
+    assert abs(mesh.set_time(0.0) or 0) == 0
+    mesh.close()
+
+
+@pytest.mark.parametrize("dim,p", [(2, 3), (3, 2)])
+def test_rrk_entropy_dissipation_and_conservation(dim, p):
+    """With dissipation the step removes entropy by exactly gamma e; without,
+    the total entropy is constant to roundoff (GPU FP64 sums)."""
+    import torch
+    from oracle.geometry import OracleMesh
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say(f"[rrk entropy] dim={dim} p={p}")
+    desc = wl.vortex2d_mesh(4, warp=0.05) if dim == 2 else wl.periodic_tet_mesh(2, 1.0)
+    m = OracleMesh(desc, p)
+    u = state(m, "random", seed=2, jitter=0.01)
+    for diss in (False, True):
+        mesh = sbp.Mesh(desc, p, dissipation=diss)
+        ud = torch.from_numpy(u).cuda()
+        reps = [mesh.rrk_step(ud, cfl=0.1) for _ in range(3)]
+        for rep in reps:
+            ds = rep["entropy_after"] - rep["entropy_before"]
+            scale = abs(rep["entropy_before"])
+            assert abs(ds - rep["gamma"] * rep["e"]) <= 64 * 2.2e-16 * scale
+            if diss:
+                assert rep["e"] < 0
+            else:
+                assert abs(ds) <= 64 * 2.2e-16 * scale
+        say("   diss", diss, "gammas", [r["gamma"] for r in reps])
+        mesh.close()
