@@ -1,0 +1,255 @@
+"""Benchmark: residual elem-DOF updates/s of the entropy-split SBP residual on
+one MI355X (FP64 vs FP32 vs the Hadamard form), with a roofline fraction for
+the dominant kernel and the CPU oracle as a reported baseline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One timed step = one FP64 entropy-split residual evaluation for each degree
+p = 1..4 on the curved periodic 128x128x2 = 32768-triangle mesh (isentropic
+vortex state, inputs resident in HBM).  value = sum_p n_elem n_p(p) / step
+time.  Extra fields give per-kernel throughput for FP32 and the Hadamard
+form, the 196608-tetrahedron Taylor-Green case (p = 2, 3), and the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "residual elem-DOF updates/s: FP64 vs FP32 vs Hadamard form; VJP/forward time"
+PEAK_HBM = 8.0e12          # B/s
+PEAK_F64 = 78.6e12         # FLOP/s (vector and MFMA)
+PEAK_F32 = 157.3e12
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="report only the headline step (used under a profiler)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def algorithmic_work(dim, n_p, n_f, precision_bytes=8, viscous=False):
+    """Per element: MFMA flops 4 d n_c n_p^2 (one [c_b Q + Q^T] and one D
+    application per direction and component), HBM bytes: read u and write r
+    (n_c n_p values each), geometry (2D: 12 doubles of the quadratic map; 3D:
+    10 doubles), the face-node map (4 B per facet node) and the element offset."""
+    n_c = dim + 2
+    flops = 4.0 * dim * n_c * n_p * n_p
+    geo = 12 * 8 if dim == 2 else 10 * 8
+    nbr = (dim + 1) * n_f * 4
+    byts = n_c * n_p * 8 + n_c * n_p * precision_bytes + geo + nbr + 4
+    return flops, byts
+
+
+def _state_from_mesh(mesh, kind):
+    import torch
+    from paper_2305_07181_amd import workloads as wl
+    x = mesh.node_coords().cpu().numpy()
+    n_p = int(mesh.elem_np[0])
+    X = x.reshape(mesh.n_elem, mesh.dim, n_p)
+    X = np.moveaxis(X, 1, 0)
+    if kind == "vortex":
+        rho, V, p = wl.isentropic_vortex(X)
+    else:
+        rho, V, p = wl.taylor_green(X)
+    u = np.ascontiguousarray(np.moveaxis(wl.conservative(rho, V, p), 0, 1))
+    return torch.from_numpy(u).cuda()
+
+
+def _time_calls(fn, reps, warm):
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev]) * 1e-3
+    return float(np.median(t)), float(np.mean(t))
+
+
+def cpu_baseline(desc, ps, budget_s=20.0):
+    """The oracle (plain numpy, one thread) on a sample of elements of the
+    headline mesh: time per element for each p, scaled to elem-DOF/s."""
+    from threadpoolctl import threadpool_limits
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import workloads as wl
+    per_p = {}
+    with threadpool_limits(1):
+        for p in ps:
+            m = OracleMesh(desc, p)
+            rng = np.random.default_rng(0)
+            els = rng.choice(m.ne, size=min(m.ne, 64), replace=False)
+            need = set(int(e) for e in els)
+            for e in list(need):
+                for f in range(m.n_fac):
+                    need.add(m.neighbor(e, f)[0])
+            need = sorted(need)
+            x = m.node_coords(need)
+            rho, V, pr = wl.isentropic_vortex(np.moveaxis(x, 1, 0))
+            uu = np.moveaxis(wl.conservative(rho, V, pr), 0, 1)
+            u = np.zeros((m.ne, m.n_c, m.n_p))
+            u[need] = uu
+            sch = OracleScheme(m, ph.Gas())
+            for e in need:
+                m.geometry(e)          # setup excluded from the timing (as in the paper)
+            t0 = time.perf_counter()
+            n = 0
+            while True:
+                for e in els:
+                    sch.element(u, int(e))
+                    n += 1
+                if time.perf_counter() - t0 > budget_s / len(ps):
+                    break
+            dt = time.perf_counter() - t0
+            per_p[p] = dict(sec_per_elem=dt / n, elems=n)
+    ne = len(desc["elem_vert"])
+    from oracle.operators import reference_operator
+    tot_time = sum(per_p[p]["sec_per_elem"] * ne for p in ps)
+    dofs = sum(ne * reference_operator(2, p)["n_p"] for p in ps)
+    return dict(value=dofs / tot_time, unit="elem-DOF/s", cores=1, kind="oracle",
+                sample=f"oracle (numpy, 1 thread) entropy-split FP64 residual of "
+                       f"{', '.join(str(per_p[p]['elems']) for p in ps)} element evaluations "
+                       f"(64 distinct elements per p, vortex state) on the 32768-triangle curved mesh, "
+                       f"p={list(ps)}; per-element time scaled to the full mesh per step")
+
+
+def main():
+    args = _args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding "
+              f"is a design in DESIGN.md, not a measured path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2305_07181_amd import sbp, workloads as wl
+    assert torch.cuda.is_available()
+    ps = (1, 2, 3, 4)
+    desc = wl.vortex2d_mesh(128, warp=0.05)
+    ne = len(desc["elem_vert"])
+    meshes, states, outs = {}, {}, {}
+    for p in ps:
+        meshes[p] = sbp.Mesh(desc, p)
+        states[p] = _state_from_mesh(meshes[p], "vortex")
+        outs[p] = torch.empty_like(states[p])
+    n_p = {p: int(meshes[p].elem_np[0]) for p in ps}
+    dofs = sum(ne * n_p[p] for p in ps)
+
+    def step():
+        for p in ps:
+            meshes[p].residual(states[p], outs[p])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # per-launch events on the stream the kernels run on (torch's current stream)
+    evs = {p: [] for p in ps}
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(args.steps):
+        for p in ps:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            meshes[p].residual(states[p], outs[p])
+            b.record()
+            evs[p].append((a, b))
+    t1.record()
+    torch.cuda.synchronize()
+    total = t0.elapsed_time(t1) * 1e-3
+    ms_per_step = total / args.steps * 1e3
+    value = dofs / (total / args.steps)
+    kern = {p: float(np.mean([a.elapsed_time(b) for a, b in evs[p]])) * 1e-3 for p in ps}
+    meshes_ok = [meshes[p].check_device() for p in ps]
+    dom = max(ps, key=lambda p: kern[p])
+    nf = {1: 2, 2: 3, 3: 4, 4: 5}[dom]
+    fl, by = algorithmic_work(2, n_p[dom], nf)
+    ai = fl / by
+    if ai > PEAK_F64 / PEAK_HBM:
+        roof = dict(bound="mfma", achieved=fl * ne / kern[dom] / 1e12, peak=PEAK_F64 / 1e12, unit="TFLOP/s")
+    else:
+        roof = dict(bound="hbm", achieved=by * ne / kern[dom] / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = f"k_split2<{dom},double> (2D entropy split, p={dom}), {ne} elements per launch"
+    roof["avg_launch_ms"] = kern[dom] * 1e3
+    out = dict(metric=METRIC, value=value, unit="elem-DOF/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=ms_per_step, higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f64", data="synthetic",
+               config=dict(workload="2D Euler, curved periodic [0,20]^2 mesh 128x128x2 = 32768 triangles "
+                                    "(P2 warp 0.05 L sin sin), isentropic vortex, entropy-split residual "
+                                    "with EC SATs, FP64, one residual for each p = 1,2,3,4 per step",
+                           n_elem=ne, degrees=list(ps), n_p=n_p,
+                           kernel_ms={p: kern[p] * 1e3 for p in ps}),
+               roofline=roof)
+    if not args.no_extras:
+        extras = {}
+        for p in ps:
+            row = {}
+            for name, kw in (("fp64_split", dict()), ("fp32_split", dict(precision=sbp.FP32)),
+                             ("fp64_hadamard", dict(form=sbp.FORM_HADAMARD))):
+                msh = meshes[p] if name == "fp64_split" else sbp.Mesh(desc, p, **kw)
+                r = torch.empty(states[p].shape, dtype=torch.float32 if "fp32" in name else torch.float64,
+                                device="cuda")
+                med, _ = _time_calls(lambda: msh.residual(states[p], r), max(5, args.steps // 2), 2)
+                row[name] = dict(ms=med * 1e3, elem_dof_per_s=ne * n_p[p] / med)
+                if msh is not meshes[p]:
+                    msh.close()
+            row["hadamard_over_split"] = row["fp64_hadamard"]["ms"] / row["fp64_split"]["ms"]
+            extras[f"tri_p{p}"] = row
+        # 3D Taylor-Green, 32^3 x 6 = 196608 tetrahedra, matrix dissipation on
+        desc3 = wl.tgv_mesh(32)
+        ne3 = len(desc3["elem_vert"])
+        for p in (2, 3):
+            row = {}
+            m64 = sbp.Mesh(desc3, p, dissipation=True)
+            u3 = _state_from_mesh(m64, "tgv")
+            np3 = int(m64.elem_np[0])
+            for name, kw in (("fp64_split", dict()), ("fp32_split", dict(precision=sbp.FP32)),
+                             ("fp64_hadamard", dict(form=sbp.FORM_HADAMARD))):
+                msh = m64 if name == "fp64_split" else sbp.Mesh(desc3, p, dissipation=True, **kw)
+                r = torch.empty(u3.shape, dtype=torch.float32 if "fp32" in name else torch.float64, device="cuda")
+                med, _ = _time_calls(lambda: msh.residual(u3, r), 5, 2)
+                fl3, by3 = algorithmic_work(3, np3, {2: 6, 3: 12}[p], 4 if "fp32" in name else 8)
+                row[name] = dict(ms=med * 1e3, elem_dof_per_s=ne3 * np3 / med,
+                                 mfma_frac=fl3 * ne3 / med / (PEAK_F32 if "fp32" in name else PEAK_F64),
+                                 hbm_frac=by3 * ne3 / med / PEAK_HBM)
+                if msh is not m64:
+                    msh.close()
+            row["hadamard_over_split"] = row["fp64_hadamard"]["ms"] / row["fp64_split"]["ms"]
+            row["fp32_speedup"] = row["fp64_split"]["ms"] / row["fp32_split"]["ms"]
+            extras[f"tet_p{p}_tgv_196608"] = row
+            m64.close()
+            del u3
+        extras["vjp_over_forward"] = None
+        out["breakdown"] = extras
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(desc, ps)
+    for p in ps:
+        meshes[p].close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -56,6 +56,8 @@ struct DegreeClass {
   void *d_ops = nullptr;  // both precisions
   sbp::OpTables<double> op64{};
   sbp::OpTables<float> op32{};
+  int *d_nbrq = nullptr;  // viscous: neighbour q index per facet node
+  void *d_q = nullptr;    // viscous: facet normal viscous fluxes
   int part_off = 0;       // offset of this class in the residual partial buffer
   int res_blocks = 0;
   int node_off_blk = 0;   // offset in the node partial buffers
@@ -133,7 +135,7 @@ int upload(T *&dst, const std::vector<T> &src, hipStream_t s) {
 
 // Padded, transposed operator tables of one class for precision T.
 template <typename T>
-void build_tables(const sbp::RefOp &op, int dim, double beta, std::vector<T> &blob, size_t off[8]) {
+void build_tables(const sbp::RefOp &op, int dim, double beta, std::vector<T> &blob, size_t off[11]) {
   const int NP = op.np;
   const double cb = 1.0 / (beta + 1.0);
   auto Q = [&](int l, int i, int j) { return op.Q[((size_t)l * NP + i) * NP + j]; };
@@ -158,7 +160,28 @@ void build_tables(const sbp::RefOp &op, int dim, double beta, std::vector<T> &bl
     off[0] = push(A1);
     off[1] = push(A2);
     off[2] = off[3] = 0;
+    // viscous: A5 = [Q_1 Q_2 Q_3 | Q_1^T Q_2^T Q_3^T] (NP x 6NP), stored transposed
+    const int K3P = sbp::ru(6 * NP, 4);
+    std::vector<double> A5((size_t)K3P * M1P, 0.0);
+    for (int l = 0; l < 3; ++l)
+      for (int m = 0; m < NP; ++m)
+        for (int j = 0; j < NP; ++j) {
+          A5[(size_t)(l * NP + j) * M1P + m] = Q(l, m, j);
+          A5[(size_t)(3 * NP + l * NP + j) * M1P + m] = Q(l, j, m);
+        }
+    off[8] = push(A5);
+    // VJP: A6 = [M_1^T; M_2^T; M_3^T] (3NP x NP), A7 = [D_1^T D_2^T D_3^T] (NP x 3NP), transposed
+    std::vector<double> A6((size_t)K2P * M2P, 0.0), A7((size_t)K1P * M1P, 0.0);
+    for (int l = 0; l < 3; ++l)
+      for (int j = 0; j < NP; ++j)
+        for (int k = 0; k < NP; ++k) {
+          A6[(size_t)k * M2P + l * NP + j] = cb * Q(l, k, j) + Q(l, j, k);  // M_l[k][j]
+          A7[(size_t)(l * NP + j) * M1P + k] = Q(l, j, k) / op.h[j];         // D_l[j][k]
+        }
+    off[9] = push(A6);
+    off[10] = push(A7);
   } else {
+    off[8] = off[9] = off[10] = 0;
     const int KP = sbp::ru(NP, 4), MP = sbp::ru(NP, 16);
     for (int l = 0; l < 2; ++l) {
       std::vector<double> Am(KP * MP, 0.0), Aq(KP * MP, 0.0);
@@ -195,7 +218,7 @@ void build_tables(const sbp::RefOp &op, int dim, double beta, std::vector<T> &bl
 }
 
 template <typename T>
-sbp::OpTables<T> tables_at(const T *base, const size_t off[8], int dim) {
+sbp::OpTables<T> tables_at(const T *base, const size_t off[11], int dim) {
   sbp::OpTables<T> t{};
   t.At1 = base + off[0];
   t.At2 = base + off[1];
@@ -205,6 +228,9 @@ sbp::OpTables<T> tables_at(const T *base, const size_t off[8], int dim) {
   t.h = base + off[5];
   t.E = base + off[6];
   t.dN = base + off[7];
+  t.At5 = dim == 3 ? base + off[8] : nullptr;
+  t.At6 = dim == 3 ? base + off[9] : nullptr;
+  t.At7 = dim == 3 ? base + off[10] : nullptr;
   return t;
 }
 
@@ -378,11 +404,15 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
   }
   int part_total = 0, node_total = 0;
   const int prec = ph->precision;
+  std::vector<int> local_of(ne, -1);
+  for (auto &c : M->cls)
+    for (size_t k = 0; k < c.elems.size(); ++k) local_of[c.elems[k]] = (int)k;
+  const int form_eff = ph->viscous ? 2 : ph->form;
   for (auto &c : M->cls) {
     c.n_elem = (int)c.elems.size();
     const sbp::RefOp &op = sbp::reference_operator(dim, c.p);
     const int np = c.np, nf = c.nf;
-    std::vector<int> uoff(c.n_elem), nbr((size_t)c.n_elem * nv * nf);
+    std::vector<int> uoff(c.n_elem), nbr((size_t)c.n_elem * nv * nf), nbrq((size_t)c.n_elem * nv * nf);
     std::vector<double> geo, hn((size_t)c.n_elem * np), hm(c.n_elem);
     const int gsz = dim == 2 ? 12 : 10;
     for (int k = 0; k < c.n_elem; ++k) {
@@ -414,6 +444,7 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
           if (!(std::sqrt(bd) <= 1e-8 * std::max(hmin[e], 1.0)))
             return fail(SBP_EINVAL, "facet nodes do not match (element " + std::to_string(e) + ")");
           nbr[((size_t)k * nv + f) * nf + j] = (int)(M->node_off[v] * M->nc) + best;
+          nbrq[((size_t)k * nv + f) * nf + j] = local_of[v] * nv * nf + best;
         }
       }
     }
@@ -423,9 +454,11 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
     if ((rc = upload(c.d_nbr, nbr, s))) return rc;
     if ((rc = upload(c.d_Hn, hn, s))) return rc;
     if ((rc = upload(c.d_hmin, hm, s))) return rc;
+    if ((rc = upload(c.d_nbrq, nbrq, s))) return rc;
+    if (ph->viscous) HIPCHK(hipMalloc(&c.d_q, sizeof(double) * (size_t)c.n_elem * nv * nf * M->nc));
     std::vector<double> b64;
     std::vector<float> b32;
-    size_t o64[8], o32[8];
+    size_t o64[11], o32[11];
     build_tables<double>(op, dim, ph->beta, b64, o64);
     build_tables<float>(op, dim, ph->beta, b32, o32);
     const size_t bytes64 = b64.size() * sizeof(double), bytes32 = b32.size() * sizeof(float);
@@ -434,8 +467,8 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
     HIPCHK(hipMemcpyAsync((char *)c.d_ops + bytes64, b32.data(), bytes32, hipMemcpyHostToDevice, s));
     c.op64 = tables_at<double>((const double *)c.d_ops, o64, dim);
     c.op32 = tables_at<float>((const float *)((char *)c.d_ops + bytes64), o32, dim);
-    c.res_blocks = std::max(sbp::residual_blocks(dim, c.p, 0, ph->form, c.n_elem),
-                            sbp::residual_blocks(dim, c.p, 1, ph->form, c.n_elem));
+    c.res_blocks = std::max(sbp::residual_blocks(dim, c.p, 0, form_eff, c.n_elem),
+                            sbp::residual_blocks(dim, c.p, 1, form_eff, c.n_elem));
     c.part_off = part_total;
     part_total += c.res_blocks;
     c.node_blocks = sbp::node_blocks(c.n_elem, np);
@@ -474,45 +507,54 @@ sbp::NodeArgs node_args(const sbp_mesh *M, const DegreeClass &c, const double *u
   return A;
 }
 
+template <typename T>
+sbp::KArgs<T> kargs(sbp_mesh *M, DegreeClass &c, const double *u, void *r, const sbp::OpTables<T> &op) {
+  const sbp_physics &ph = M->phys;
+  sbp::KArgs<T> A{};
+  A.u = u;
+  A.r = (T *)r;
+  A.geo = c.d_geo;
+  A.nbr = c.d_nbr;
+  A.uoff = c.d_uoff;
+  A.n_elem = c.n_elem;
+  A.diss = ph.dissipation;
+  A.op = op;
+  A.G = sbp::make_gas<T>(ph.gamma, ph.beta);
+  A.ent_part = M->d_part + c.part_off;
+  A.err = M->d_err;
+  A.visc = ph.viscous;
+  A.nbrq = c.d_nbrq;
+  if (ph.viscous) {
+    A.V.mu = (T)ph.mu;
+    A.V.R = (T)ph.R;
+    A.V.kappa = ph.heat_flux ? (T)(ph.mu * ph.gamma * ph.R / ((ph.gamma - 1.0) * ph.Pr)) : (T)0;
+    A.q = (const T *)c.d_q;
+    A.qout = (T *)c.d_q;
+  }
+  return A;
+}
+
 int residual_impl(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStream_t s) {
   const sbp_physics &ph = M->phys;
-  for (auto &c : M->cls) {
-    if (ph.precision == SBP_FP64) {
-      sbp::KArgs<double> A{};
-      A.u = u;
-      A.r = (double *)r;
-      A.geo = c.d_geo;
-      A.nbr = c.d_nbr;
-      A.uoff = c.d_uoff;
-      A.n_elem = c.n_elem;
-      A.diss = ph.dissipation;
-      A.op = c.op64;
-      A.G = sbp::make_gas<double>(ph.gamma, ph.beta);
-      A.ent_part = M->d_part + c.part_off;
-      A.err = M->d_err;
-      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, A, s));
-    } else {
-      sbp::KArgs<float> A{};
-      A.u = u;
-      A.r = (float *)r;
-      A.geo = c.d_geo;
-      A.nbr = c.d_nbr;
-      A.uoff = c.d_uoff;
-      A.n_elem = c.n_elem;
-      A.diss = ph.dissipation;
-      A.op = c.op32;
-      A.G = sbp::make_gas<float>(ph.gamma, ph.beta);
-      A.ent_part = M->d_part + c.part_off;
-      A.err = M->d_err;
-      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, A, s));
+  if (ph.viscous) {
+    for (auto &c : M->cls) {
+      if (ph.precision == SBP_FP64)
+        HIPCHK(sbp::launch_visc_q(M->dim, c.p, kargs<double>(M, c, u, r, c.op64), s));
+      else
+        HIPCHK(sbp::launch_visc_q(M->dim, c.p, kargs<float>(M, c, u, r, c.op32), s));
     }
   }
+  for (auto &c : M->cls) {
+    if (ph.precision == SBP_FP64)
+      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, kargs<double>(M, c, u, r, c.op64), s));
+    else
+      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, kargs<float>(M, c, u, r, c.op32), s));
+  }
   if (ent_dev) {
-    // classes whose actual grid is smaller than res_blocks leave stale
-    // partials; sum only the written ones
+    const int form_eff = ph.viscous ? 2 : ph.form;
     for (size_t ci = 0; ci < M->cls.size(); ++ci) {
       auto &c = M->cls[ci];
-      const int nb = sbp::residual_blocks(M->dim, c.p, ph.precision, ph.form, c.n_elem);
+      const int nb = sbp::residual_blocks(M->dim, c.p, ph.precision, form_eff, c.n_elem);
       HIPCHK(sbp::launch_reduce(M->d_part + c.part_off, nb, 1, 0, M->d_scal + SC_RED + ci, s));
     }
     if (M->cls.size() == 1) {
@@ -581,7 +623,10 @@ int sbp_setup_mesh(const sbp_mesh_desc *desc, const sbp_physics *phys, void *hip
   if (!(phys->gamma > 1.0) || !(phys->beta > 0.0)) return fail(SBP_EINVAL, "need gamma > 1 and beta > 0");
   if (phys->form != SBP_FORM_SPLIT && phys->form != SBP_FORM_HADAMARD) return fail(SBP_EINVAL, "bad form");
   if (phys->precision != SBP_FP64 && phys->precision != SBP_FP32) return fail(SBP_EINVAL, "bad precision");
-  if (phys->viscous) return fail(SBP_ENOTSUP, "viscous terms are not available in this build");
+  if (phys->viscous && (desc->dim != 3 || phys->form != SBP_FORM_SPLIT))
+    return fail(SBP_ENOTSUP, "viscous terms are available for the entropy-split form on tetrahedra");
+  if (phys->viscous && !(phys->mu >= 0.0 && phys->Pr > 0.0 && phys->R > 0.0))
+    return fail(SBP_EINVAL, "viscous terms need mu >= 0, Pr > 0, R > 0");
   sbp_mesh *M = new (std::nothrow) sbp_mesh();
   if (!M) return fail(SBP_ENOMEM, "host allocation failed");
   int rc;
@@ -618,9 +663,19 @@ int sbp_residual(sbp_mesh *M, const void *u, void *r, double *ent_dev, void *str
 }
 
 int sbp_residual_vjp(sbp_mesh *M, const void *u, const void *lam, void *ubar, void *stream) {
-  (void)stream;
   if (!M || !u || !lam || !ubar) return fail(SBP_EINVAL, "null argument");
-  return fail(SBP_ENOTSUP, "residual VJP is not available in this build");
+  const sbp_physics &ph = M->phys;
+  if (ph.viscous || ph.form != SBP_FORM_SPLIT)
+    return fail(SBP_ENOTSUP, "the VJP covers the entropy-split Euler residual (with or without dissipation)");
+  if (M->dim != 3) return fail(SBP_ENOTSUP, "the VJP is available on tetrahedra");
+  for (auto &c : M->cls) {
+    sbp::KArgs<double> A = kargs<double>(M, c, (const double *)u, nullptr, c.op64);
+    A.lam = (const double *)lam;
+    A.ubar = (double *)ubar;
+    A.Hn = c.d_Hn;
+    HIPCHK(sbp::launch_vjp(M->dim, c.p, A, (hipStream_t)stream));
+  }
+  return SBP_OK;
 }
 
 int sbp_diagnostics(sbp_mesh *M, const void *u, double *out_host, void *stream) {
@@ -735,6 +790,8 @@ int sbp_destroy_mesh(sbp_mesh *M) {
     (void)hipFree(c.d_Hn);
     (void)hipFree(c.d_hmin);
     (void)hipFree(c.d_ops);
+    (void)hipFree(c.d_nbrq);
+    (void)hipFree(c.d_q);
   }
   (void)hipFree(M->d_node_xyz);
   (void)hipFree(M->d_node_h);

@@ -251,3 +251,165 @@ __device__ __forceinline__ double entropy_harten(double rho, double p, double be
 }
 
 }  // namespace sbp
+
+namespace sbp {
+
+// Viscous constants (Sec. 2.2): mu, kappa = mu gamma R / ((gamma-1) Pr), R.
+template <typename T>
+struct ViscC {
+  T mu, kappa, R;
+};
+
+// dtheta/dW for theta = p/rho as a function of W (temperature formula of
+// Sec. 3, derivatives through the chain rule): out[c] = d theta / d W_c.
+template <int D, typename T>
+__device__ __forceinline__ void dtheta_dW(const Node<D, T> &n, const GasC<T> &G, T *out) {
+  const T iWn = (T)1 / n.w[D + 1];
+  T q2 = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) q2 += n.V[k] * n.V[k];
+  const T c1 = G.gm1 / G.a * iWn;
+  out[0] = c1;
+#pragma unroll
+  for (int k = 0; k < D; ++k) out[1 + k] = c1 * n.V[k];
+  out[D + 1] = (-(n.p / n.rho) + (T)0.5 * G.gm1 / G.a * q2) * iWn;
+}
+
+// Viscous flux F^{V(i)}, i = 0..D-1, from the entropy-variable gradient
+// gW[j][c] = dW_c/dx_j:  dV/dx_j = -(gW_V + V gW_E)/W_nc,
+// dT/dx_j = (dtheta/dW . gW_j)/R,  tau_ik = mu (dV_i/dx_k + dV_k/dx_i
+// - 2/3 delta_ik div V),  F^V(i) = [0, tau_i., V.tau_i + kappa dT/dx_i].
+template <int D, typename T>
+__device__ __forceinline__ void viscous_flux(const Node<D, T> &n, const GasC<T> &G, const ViscC<T> &Vc,
+                                             const T gW[D][D + 2], T FV[D][D + 2]) {
+  constexpr int NC = D + 2;
+  const T iWn = (T)1 / n.w[NC - 1];
+  T dth[NC];
+  dtheta_dW<D, T>(n, G, dth);
+  T dV[D][D];  // dV[j][m] = d V_m / d x_j
+  T dT[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    T s = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s += dth[c] * gW[j][c];
+    dT[j] = s / Vc.R;
+#pragma unroll
+    for (int m = 0; m < D; ++m) dV[j][m] = -(gW[j][1 + m] + n.V[m] * gW[j][NC - 1]) * iWn;
+  }
+  T div = 0;
+#pragma unroll
+  for (int m = 0; m < D; ++m) div += dV[m][m];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    FV[i][0] = 0;
+    T e = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const T tau = Vc.mu * (dV[k][i] + dV[i][k] - (i == k ? (T)(2.0 / 3.0) * div : (T)0));
+      FV[i][1 + k] = tau;
+      e += n.V[k] * tau;
+    }
+    FV[i][NC - 1] = e + Vc.kappa * dT[i];
+  }
+}
+
+// y_j = sum_i K~_ij^T (a_i dw) for j = 0..D-1, where K~_ij g is the viscous
+// flux F^V(i) produced by the gradient dW/dx_j = g alone.  With
+// vt = dw_V + dw_E V and the gradient maps dV/dW, dT/dW:
+//   alpha_j = mu [vt_j a + a_j vt - 2/3 (a.vt) e_j],  beta_j = kappa a_j dw_E,
+//   y_j = (dV/dW)^T alpha_j + (dT/dW)^T beta_j.
+template <int D, typename T>
+__device__ __forceinline__ void viscous_adjoint_facet(const Node<D, T> &n, const GasC<T> &G, const ViscC<T> &Vc,
+                                                      const T *a, const T *dw, T y[D][D + 2]) {
+  constexpr int NC = D + 2;
+  const T iWn = (T)1 / n.w[NC - 1];
+  T dth[NC];
+  dtheta_dW<D, T>(n, G, dth);
+  T vt[D];
+  T avt = 0;
+#pragma unroll
+  for (int m = 0; m < D; ++m) {
+    vt[m] = dw[1 + m] + dw[NC - 1] * n.V[m];
+    avt += a[m] * vt[m];
+  }
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    T al[D];
+    T alV = 0;
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+      al[m] = Vc.mu * (vt[j] * a[m] + a[j] * vt[m] - (m == j ? (T)(2.0 / 3.0) * avt : (T)0));
+      alV += al[m] * n.V[m];
+    }
+    const T be = Vc.kappa * a[j] * dw[NC - 1] / Vc.R;
+    y[j][0] = be * dth[0];
+#pragma unroll
+    for (int m = 0; m < D; ++m) y[j][1 + m] = -al[m] * iWn + be * dth[1 + m];
+    y[j][NC - 1] = -alV * iWn + be * dth[NC - 1];
+  }
+}
+
+}  // namespace sbp
+
+namespace sbp {
+
+// dU = (dU/dW) g, the state perturbation produced by the entropy-variable
+// perturbation g (same chain rule as jvp_flux).
+template <int D, typename T>
+__device__ __forceinline__ void dU_from_dW(const Node<D, T> &n, const GasC<T> &G, const T *g, T *dU) {
+  const T iWn = (T)1 / n.w[D + 1];
+  T dV[D];
+  T q2 = 0, Vg = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    dV[k] = -(g[1 + k] + n.V[k] * g[D + 1]) * iWn;
+    q2 += n.V[k] * n.V[k];
+    Vg += n.V[k] * g[1 + k];
+  }
+  const T theta = n.p / n.rho;
+  const T c1 = G.gm1 / G.a * iWn;
+  const T dtheta = c1 * (g[0] + Vg) + (-theta + (T)0.5 * G.gm1 / G.a * q2) * iWn * g[D + 1];
+  const T drho = n.rho * (g[D + 1] * iWn - G.ja * dtheta / theta) * G.jb_inv;
+  const T dp = theta * drho + n.rho * dtheta;
+  T VdV = 0;
+  dU[0] = drho;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    dU[1 + k] = drho * n.V[k] + n.rho * dV[k];
+    VdV += n.V[k] * dV[k];
+  }
+  dU[D + 1] = dp / G.gm1 + (T)0.5 * q2 * drho + n.rho * VdV;
+}
+
+// out = A_i^T z with A_i = dF^(i)/dU (Euler flux Jacobian, closed form).
+template <int D, typename T>
+__device__ __forceinline__ void flux_jac_T(const Node<D, T> &n, const GasC<T> &G, T E, int i, const T *z, T *out) {
+  constexpr int NC = D + 2;
+  T q2 = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) q2 += n.V[k] * n.V[k];
+  const T Ht = (E + n.p) / n.rho;
+  const T g1 = G.gm1;
+  // column 0
+  T s = 0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) s += z[1 + j] * (-n.V[i] * n.V[j] + (j == i ? (T)0.5 * g1 * q2 : (T)0));
+  out[0] = s + z[NC - 1] * n.V[i] * ((T)0.5 * g1 * q2 - Ht);
+  // columns 1+k
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    T t = (k == i ? z[0] : (T)0);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T a = (k == i ? n.V[j] : (T)0) + (k == j ? n.V[i] : (T)0) - (j == i ? g1 * n.V[k] : (T)0);
+      t += z[1 + j] * a;
+    }
+    t += z[NC - 1] * ((k == i ? Ht : (T)0) - g1 * n.V[i] * n.V[k]);
+    out[1 + k] = t;
+  }
+  // column NC-1
+  out[NC - 1] = z[1 + i] * g1 + z[NC - 1] * G.g * n.V[i];
+}
+
+}  // namespace sbp

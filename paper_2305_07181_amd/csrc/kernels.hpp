@@ -33,6 +33,11 @@ struct OpTables {
   const T *h;   // [NP]
   const T *E;   // [dim][NP] diagonal of E_xi_l
   const T *dN;  // 2D: [2][6][NP] derivatives of the quadratic map basis at the nodes
+  // viscous, 3D affine: At5 = [Q_1 Q_2 Q_3 | Q_1^T Q_2^T Q_3^T]^T (K3P x M1P)
+  const T *At5;
+  // VJP, 3D affine: At6 = [M_1 M_2 M_3] (K2P x M2P: A = [M_1^T; M_2^T; M_3^T]),
+  //                 At7 = [D_1;D_2;D_3] (K1P x M1P: A = [D_1^T D_2^T D_3^T])
+  const T *At6, *At7;
 };
 
 template <typename T>
@@ -48,6 +53,16 @@ struct KArgs {
   GasC<T> G;
   double *ent_part;    // [gridDim.x] partial sums of w^T H r (may be null)
   int *err;            // non-physical state flag
+  // Navier-Stokes terms (Baumann-Oden SATs)
+  int visc;
+  ViscC<T> V;
+  const T *q;          // [n_elem][NFAC*NF][n_c] facet normal viscous fluxes B n . F^V
+  T *qout;             // written by the facet-flux pre-pass
+  const int *nbrq;     // [n_elem][NFAC*NF] index (elem*NFAC*NF + node) of the neighbour's q
+  // vector-Jacobian product
+  const double *lam;   // cotangent (state layout)
+  double *ubar;        // result (state layout)
+  const double *Hn;    // [n_elem*NP] diagonal of H_k
 };
 
 // Elements per workgroup for each kernel (LDS budget <= 160 KiB on gfx950).

@@ -10,6 +10,12 @@ namespace sbp {
 hipError_t launch_residual(int dim, int p, int form, const KArgs<double> &A, hipStream_t s);
 hipError_t launch_residual(int dim, int p, int form, const KArgs<float> &A, hipStream_t s);
 int residual_blocks(int dim, int p, int precision, int form, int n_elem);
+// Viscous facet-flux pre-pass (3D): A.qout[(e*NFAC*NF + m)*n_c + c] = B n . F^V
+hipError_t launch_visc_q(int dim, int p, const KArgs<double> &A, hipStream_t s);
+hipError_t launch_visc_q(int dim, int p, const KArgs<float> &A, hipStream_t s);
+
+// Vector-Jacobian product of the entropy-split residual (FP64, Euler terms).
+hipError_t launch_vjp(int dim, int p, const KArgs<double> &A, hipStream_t s);
 
 // Per-node pointwise work over one degree class.
 struct NodeArgs {

@@ -43,6 +43,13 @@ template <> struct Tile<2, 1, float, 0> { static constexpr int EB = 32; };
 template <> struct Tile<2, 2, float, 0> { static constexpr int EB = 32; };
 template <> struct Tile<2, 3, float, 0> { static constexpr int EB = 16; };
 template <> struct Tile<2, 4, float, 0> { static constexpr int EB = 16; };
+// entropy split with Navier-Stokes terms (3D)
+template <> struct Tile<3, 1, double, 2> { static constexpr int EB = 16; };
+template <> struct Tile<3, 2, double, 2> { static constexpr int EB = 9; };
+template <> struct Tile<3, 3, double, 2> { static constexpr int EB = 3; };
+template <> struct Tile<3, 1, float, 2> { static constexpr int EB = 32; };
+template <> struct Tile<3, 2, float, 2> { static constexpr int EB = 16; };
+template <> struct Tile<3, 3, float, 2> { static constexpr int EB = 6; };
 // Hadamard form
 template <> struct Tile<3, 1, double, 1> { static constexpr int EB = 24; };
 template <> struct Tile<3, 2, double, 1> { static constexpr int EB = 8; };
@@ -63,8 +70,10 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
 // ---------------------------------------------------------------------------
-// MFMA 16x16x4 wrappers.  Lane l holds A[l%16][k0 + l/16], B[k0 + l/16][l%16]
-// and D[4*(l/16) + i][l%16], i = 0..3.
+// MFMA 16x16x4 wrappers.  Lane l holds A[l%16][k0 + l/16], B[k0 + l/16][l%16];
+// accumulator register i of lane l holds D[row(l/16, i)][l%16] with
+// row = l/16 + 4 i for v_mfma_f64_16x16x4f64 and 4 (l/16) + i for
+// v_mfma_f32_16x16x4f32 (checked on gfx950).
 template <typename T>
 struct MF;
 template <>
@@ -73,6 +82,7 @@ struct MF<double> {
   __device__ static __forceinline__ v4 mma(double a, double b, v4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  __device__ static __forceinline__ int row(int kr, int i) { return kr + 4 * i; }
 };
 template <>
 struct MF<float> {
@@ -80,6 +90,7 @@ struct MF<float> {
   __device__ static __forceinline__ v4 mma(float a, float b, v4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  __device__ static __forceinline__ int row(int kr, int i) { return 4 * kr + i; }
 };
 
 // C[MP x NCP] = A[MP x KP] B[KP x NCP].  A^T in global memory (At[k*MP+m],
@@ -116,7 +127,7 @@ __device__ __forceinline__ void gemm_AtB(const T *__restrict__ At, const T *B, T
     if (tile < NTILE) {
       const int mt = tile % MT, nt = tile / MT;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) C[(mt * 16 + 4 * kr + i) * NCP + nt * 16 + col] = acc[t][i];
+      for (int i = 0; i < 4; ++i) C[(mt * 16 + MF<T>::row(kr, i)) * NCP + nt * 16 + col] = acc[t][i];
     }
   }
   __syncthreads();
@@ -169,22 +180,32 @@ __device__ __forceinline__ void finish_node(const KArgs<T> &A, int eg, int i, co
 // Entropy split, 3D affine tetrahedra.
 //   vol = sum_l M_l fhat_l, fhat_l = sum_i Lambda_il f^(i)     (one GEMM, K = 3 NP)
 //   D_xi w = sum_l (Lambda_il / J) D_xi_l w                   (one GEMM, M = 3 NP)
-template <int P, typename T>
+// With VISC (Navier-Stokes, Baumann-Oden SATs, Sec. 5):
+//   sum_i D_xi F^V(i) - 1/2 H^-1 sum_j D_xj^T y_j
+//     = H^-1 [ sum_l Q_l FVhat_l - 1/2 sum_l Q_l^T (H^-1 yhat_l) ]   (one GEMM, K = 6 NP)
+//   with FVhat_l = sum_i Lambda_il F^V(i), yhat_l = sum_j Lambda_jl y_j,
+//   y_j = sum_i K~_ij^T (B n_i (w_k - w_v)) at facet nodes, plus the facet
+//   flux jump -1/2 H^-1 (q_k + q_v), q = B n . F^V from the pre-pass.
+template <int P, typename T, bool VISC>
 __global__ __launch_bounds__(kThreads) void k_split3(KArgs<T> A) {
   constexpr int D = 3, NC = 5, NFAC = 4;
-  constexpr int NP = Shape<3, P>::NP, NF = Shape<3, P>::NF;
-  constexpr int EB = Tile<3, P, T, 0>::EB;
+  constexpr int NP = Shape<3, P>::NP, NF = Shape<3, P>::NF, NFN = NFAC * NF;
+  constexpr int EB = Tile<3, P, T, VISC ? 2 : 0>::EB;
   constexpr int NCOL = EB * NC, NCP = ru(NCOL, 16);
   constexpr int K1P = ru(3 * NP, 4), M1P = ru(NP, 16);
   constexpr int K2P = ru(NP, 4), M2P = ru(3 * NP, 16);
-  __shared__ T B1[K1P * NCP];
+  constexpr int K3P = VISC ? ru(6 * NP, 4) : 4;
+  constexpr int KU = K1P > K3P ? K1P : K3P;
+  __shared__ T U1[KU * NCP];   // B1, then (viscous) B3
   __shared__ T B2[K2P * NCP];
   __shared__ T C1[M1P * NCP];
   __shared__ T C2[M2P * NCP];
+  __shared__ T C3[VISC ? M1P * NCP : 16];
   __shared__ T us[EB * NC * NP];
   __shared__ T gs[EB * 10];
   __shared__ T hs[NP];
   __shared__ T Es[3 * NP];
+  T *B1 = U1;
   const int tid = threadIdx.x;
   const int e0 = blockIdx.x * EB;
   const int ne = min(EB, A.n_elem - e0);
@@ -225,6 +246,66 @@ __global__ __launch_bounds__(kThreads) void k_split3(KArgs<T> A) {
   __syncthreads();
   gemm_AtB<T, M1P, K1P, NCP>(A.op.At1, B1, C1);
   gemm_AtB<T, M2P, K2P, NCP>(A.op.At2, B2, C2);
+  if constexpr (VISC) {
+    T *B3 = U1;
+    for (int x = tid; x < K3P * NCP; x += kThreads) B3[x] = (T)0;
+    __syncthreads();
+    for (int x = tid; x < ne * NP; x += kThreads) {
+      const int e = x / NP, i = x % NP;
+      T uu[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + i];
+      Node<D, T> n;
+      node_from_u<D, T>(uu, A.G, n);
+      const T *Lam = gs + e * 10;
+      const T iJ = (T)1 / Lam[9];
+      T gW[D][NC], FV[D][NC];
+#pragma unroll
+      for (int dir = 0; dir < D; ++dir)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          T s = 0;
+#pragma unroll
+          for (int l = 0; l < D; ++l) s += Lam[dir * 3 + l] * C2[(l * NP + i) * NCP + e * NC + c];
+          gW[dir][c] = s * iJ;
+        }
+      viscous_flux<D, T>(n, A.G, A.V, gW, FV);
+#pragma unroll
+      for (int l = 0; l < D; ++l)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          B3[(l * NP + i) * NCP + e * NC + c] = Lam[0 * 3 + l] * FV[0][c] + Lam[1 * 3 + l] * FV[1][c] + Lam[2 * 3 + l] * FV[2][c];
+      if (i < NFN) {
+        const int off = A.nbr[(size_t)(e0 + e) * NFN + i];
+        T uv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) uv[c] = (T)A.u[off + c * NP];
+        Node<D, T> nv;
+        node_from_u<D, T>(uv, A.G, nv);
+        T dw[NC], avec[D];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) dw[c] = n.w[c] - nv.w[c];
+#pragma unroll
+        for (int dir = 0; dir < D; ++dir) {
+          T s = 0;
+#pragma unroll
+          for (int l = 0; l < D; ++l) s += Lam[dir * 3 + l] * Es[l * NP + i];
+          avec[dir] = s;
+        }
+        T y[D][NC];
+        viscous_adjoint_facet<D, T>(n, A.G, A.V, avec, dw, y);
+        const T sc = (T)(-0.5) / (Lam[9] * hs[i]);
+#pragma unroll
+        for (int l = 0; l < D; ++l)
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+            B3[(3 * NP + l * NP + i) * NCP + e * NC + c] =
+                sc * (Lam[0 * 3 + l] * y[0][c] + Lam[1 * 3 + l] * y[1][c] + Lam[2 * 3 + l] * y[2][c]);
+      }
+    }
+    __syncthreads();
+    gemm_AtB<T, M1P, K3P, NCP>(A.op.At5, B3, C3);
+  }
   double ent = 0.0;
   for (int x = tid; x < ne * NP; x += kThreads) {
     const int e = x / NP, i = x % NP;
@@ -255,6 +336,16 @@ __global__ __launch_bounds__(kThreads) void k_split3(KArgs<T> A) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) r[c] -= A.G.cb * t[c];
     }
+    if constexpr (VISC) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) r[c] += C3[i * NCP + e * NC + c] * iH;
+      if (i < NFN) {
+        const T *qk = A.q + ((size_t)(e0 + e) * NFN + i) * NC;
+        const T *qv = A.q + (size_t)A.nbrq[(size_t)(e0 + e) * NFN + i] * NC;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) r[c] -= (T)0.5 * (qk[c] + qv[c]) * iH;
+      }
+    }
     T avec[D];
 #pragma unroll
     for (int dir = 0; dir < D; ++dir) {
@@ -266,6 +357,80 @@ __global__ __launch_bounds__(kThreads) void k_split3(KArgs<T> A) {
     finish_node<D, NP, NF, T>(A, e0 + e, i, n, H, avec, r, ent);
   }
   block_sum_store(ent, A.ent_part);
+}
+
+// Viscous facet-flux pre-pass, 3D affine: q = B n . F^V(w, grad w) at the
+// facet nodes of every element (grad w from the derivative GEMM).
+template <int P, typename T>
+__global__ __launch_bounds__(kThreads) void k_visc_q3(KArgs<T> A) {
+  constexpr int D = 3, NC = 5, NFAC = 4;
+  constexpr int NP = Shape<3, P>::NP, NF = Shape<3, P>::NF, NFN = NFAC * NF;
+  constexpr int EB = Tile<3, P, T, 0>::EB;
+  constexpr int NCOL = EB * NC, NCP = ru(NCOL, 16);
+  constexpr int K2P = ru(NP, 4), M2P = ru(3 * NP, 16);
+  __shared__ T B2[K2P * NCP];
+  __shared__ T C2[M2P * NCP];
+  __shared__ T us[EB * NC * NP];
+  __shared__ T gs[EB * 10];
+  __shared__ T Es[3 * NP];
+  const int tid = threadIdx.x;
+  const int e0 = blockIdx.x * EB;
+  const int ne = min(EB, A.n_elem - e0);
+  for (int x = tid; x < EB * 10; x += kThreads) {
+    const int e = x / 10;
+    gs[x] = e < ne ? (T)A.geo[(size_t)(e0 + e) * 10 + x % 10] : (T)0;
+  }
+  for (int x = tid; x < 3 * NP; x += kThreads) Es[x] = A.op.E[x];
+  for (int x = tid; x < ne * NC * NP; x += kThreads) {
+    const int e = x / (NC * NP);
+    us[x] = (T)A.u[A.uoff[e0 + e] + x % (NC * NP)];
+  }
+  for (int x = tid; x < K2P * NCP; x += kThreads) B2[x] = (T)0;
+  __syncthreads();
+  for (int x = tid; x < ne * NP; x += kThreads) {
+    const int e = x / NP, j = x % NP;
+    T uu[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + j];
+    Node<D, T> n;
+    node_from_u<D, T>(uu, A.G, n);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) B2[j * NCP + e * NC + c] = n.w[c];
+  }
+  __syncthreads();
+  gemm_AtB<T, M2P, K2P, NCP>(A.op.At2, B2, C2);
+  for (int x = tid; x < ne * NFN; x += kThreads) {
+    const int e = x / NFN, i = x % NFN;
+    T uu[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + i];
+    Node<D, T> n;
+    node_from_u<D, T>(uu, A.G, n);
+    const T *Lam = gs + e * 10;
+    const T iJ = (T)1 / Lam[9];
+    T gW[D][NC], FV[D][NC];
+#pragma unroll
+    for (int dir = 0; dir < D; ++dir)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        T s = 0;
+#pragma unroll
+        for (int l = 0; l < D; ++l) s += Lam[dir * 3 + l] * C2[(l * NP + i) * NCP + e * NC + c];
+        gW[dir][c] = s * iJ;
+      }
+    viscous_flux<D, T>(n, A.G, A.V, gW, FV);
+    T avec[D];
+#pragma unroll
+    for (int dir = 0; dir < D; ++dir) {
+      T s = 0;
+#pragma unroll
+      for (int l = 0; l < D; ++l) s += Lam[dir * 3 + l] * Es[l * NP + i];
+      avec[dir] = s;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      A.qout[((size_t)(e0 + e) * NFN + i) * NC + c] = avec[0] * FV[0][c] + avec[1] * FV[1][c] + avec[2] * FV[2][c];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -563,10 +728,14 @@ __global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
 template <typename T>
 int tile_elems(int dim, int p, int form) {
 #define SBP_TILE(DI, PP) \
-  if (dim == DI && p == PP) return form ? Tile<DI, PP, T, 1>::EB : Tile<DI, PP, T, 0>::EB;
+  if (dim == DI && p == PP) return form == 1 ? Tile<DI, PP, T, 1>::EB : Tile<DI, PP, T, 0>::EB;
   SBP_TILE(2, 1) SBP_TILE(2, 2) SBP_TILE(2, 3) SBP_TILE(2, 4)
-  SBP_TILE(3, 1) SBP_TILE(3, 2) SBP_TILE(3, 3)
 #undef SBP_TILE
+#define SBP_TILE3(PP) \
+  if (dim == 3 && p == PP) \
+    return form == 1 ? Tile<3, PP, T, 1>::EB : (form == 2 ? Tile<3, PP, T, 2>::EB : Tile<3, PP, T, 0>::EB);
+  SBP_TILE3(1) SBP_TILE3(2) SBP_TILE3(3)
+#undef SBP_TILE3
   return 0;
 }
 
@@ -578,7 +747,8 @@ int residual_blocks(int dim, int p, int precision, int form, int n_elem) {
 
 template <typename T>
 static hipError_t launch_t(int dim, int p, int form, const KArgs<T> &A, hipStream_t s) {
-  const int nb = residual_blocks(dim, p, sizeof(T) == 8 ? 0 : 1, form, A.n_elem);
+  if (A.visc && (dim != 3 || form != 0)) return hipErrorInvalidValue;
+  const int nb = residual_blocks(dim, p, sizeof(T) == 8 ? 0 : 1, A.visc ? 2 : form, A.n_elem);
   if (nb <= 0) return hipErrorInvalidValue;
   dim3 grid(nb), block(kThreads);
 #define SBP_LAUNCH(DI, PP)                                                 \
@@ -595,14 +765,31 @@ static hipError_t launch_t(int dim, int p, int form, const KArgs<T> &A, hipStrea
   if (dim == 3 && p == PP) {                                             \
     if (form == 1)                                                       \
       hipLaunchKernelGGL((k_hadamard<3, PP, T>), grid, block, 0, s, A);  \
+    else if (A.visc)                                                     \
+      hipLaunchKernelGGL((k_split3<PP, T, true>), grid, block, 0, s, A); \
     else                                                                 \
-      hipLaunchKernelGGL((k_split3<PP, T>), grid, block, 0, s, A);       \
+      hipLaunchKernelGGL((k_split3<PP, T, false>), grid, block, 0, s, A); \
     return hipGetLastError();                                            \
   }
   SBP_LAUNCH3(1) SBP_LAUNCH3(2) SBP_LAUNCH3(3)
 #undef SBP_LAUNCH3
   return hipErrorInvalidValue;
 }
+
+template <typename T>
+static hipError_t launch_q(int dim, int p, const KArgs<T> &A, hipStream_t s) {
+  if (dim != 3) return hipErrorInvalidValue;
+  const int nb = residual_blocks(3, p, sizeof(T) == 8 ? 0 : 1, 0, A.n_elem);
+  dim3 grid(nb), block(kThreads);
+  if (p == 1) hipLaunchKernelGGL((k_visc_q3<1, T>), grid, block, 0, s, A);
+  else if (p == 2) hipLaunchKernelGGL((k_visc_q3<2, T>), grid, block, 0, s, A);
+  else if (p == 3) hipLaunchKernelGGL((k_visc_q3<3, T>), grid, block, 0, s, A);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_visc_q(int dim, int p, const KArgs<double> &A, hipStream_t s) { return launch_q<double>(dim, p, A, s); }
+hipError_t launch_visc_q(int dim, int p, const KArgs<float> &A, hipStream_t s) { return launch_q<float>(dim, p, A, s); }
 
 hipError_t launch_residual(int dim, int p, int form, const KArgs<double> &A, hipStream_t s) {
   return launch_t<double>(dim, p, form, A, s);

@@ -163,3 +163,58 @@ def test_nonphysical_state_is_reported():
         mesh.check_device()
     assert ei.value.code == sbp.SBP_ENONPHYS
     mesh.check_device()   # flag cleared
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("heat", [True, False])
+def test_parity_navier_stokes_3d(p, heat):
+    """Navier-Stokes terms with Baumann-Oden SATs (Sec. 5) plus matrix
+    dissipation on 48 tets; without heat flux the entropy rate is <= 0."""
+    torch = _torch()
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say(f"[ns3d] p={p} heat={heat}")
+    desc = wl.periodic_tet_mesh(2, 1.0)
+    m = OracleMesh(desc, p)
+    gas = ph.Gas(mu=0.05, Pr=0.71, R=1.0, heat_flux=heat)
+    sch = OracleScheme(m, gas, dissipation=True, viscous=True)
+    u = state(m, "random", seed=4, jitter=0.01)
+    mesh = sbp.Mesh(desc, p, dissipation=True, viscous=True, heat_flux=heat, mu=0.05, Pr=0.71, R=1.0)
+    ud = torch.from_numpy(u).cuda()
+    r, er = mesh.residual(ud, entropy_rate=True)
+    r = r.cpu().numpy()
+    mesh.check_device()
+    ro = sch(u)
+    err = rel_err_per_component(r, ro)
+    say("   rel err per component", err, "entropy rate", float(er.cpu()[0]))
+    assert (err <= TOL64).all(), err
+    if not heat:
+        assert float(er.cpu()[0]) < 0
+    mesh.close()
+
+
+def test_parity_navier_stokes_tgv_fp32():
+    """FP32 Navier-Stokes residual on the low-Mach TGV (Re = 1600, heat flux
+    on) against the FP64 oracle, scaled by the summed-term magnitude."""
+    torch = _torch()
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say("[ns tgv fp32]")
+    desc = wl.tgv_mesh(3)
+    m = OracleMesh(desc, 3)
+    gas = ph.Gas(mu=1.0 / 1600, Pr=0.71, R=1.0)
+    sch = OracleScheme(m, gas, dissipation=True, viscous=True)
+    u = state(m, "tgv")
+    for prec, tol in ((sbp.FP64, TOL64), (sbp.FP32, 2e-6)):
+        mesh = sbp.Mesh(desc, 3, dissipation=True, viscous=True, mu=1.0 / 1600, precision=prec)
+        r = mesh.residual(torch.from_numpy(u).cuda()).double().cpu().numpy()
+        mesh.close()
+        ro = sch(u)
+        sc = term_scale(sch, u, list(range(m.ne)))
+        err = np.abs(r - ro).max(axis=(0, 2)) / sc
+        say("   precision", prec, "err / term scale", err)
+        assert (err <= tol).all(), err
