@@ -127,7 +127,7 @@ def _ptr(t):
 
 class _DevArray:
     def __init__(self, ptr, n):
-        self.__cuda_array_interface__ = {"shape": (n,), "typestr": "<f8", "data": (int(ptr), True),
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": "<f8", "data": (int(ptr), False),
                                          "version": 3, "strides": None}
 
 

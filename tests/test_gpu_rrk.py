@@ -10,6 +10,12 @@ pytestmark = pytest.mark.gpu
 
 
 def test_rrk_vortex_20_steps_parity():
+    """Per step: dt agrees to 1e-13; the GPU's gamma is a root of the oracle's
+    r(gamma) within its rounding (|r(gamma_gpu)| <= 8 eps sum H|s|); gamma
+    agrees within the root's conditioning kappa = 8 eps sum H|s| / |r'(gamma)|;
+    the states agree within the accumulated bound sum_n (1e-12 + kappa_n
+    max|d_n| / max|u|) (relative, per component); entropy is conserved to
+    roundoff on the GPU."""
     import torch
     from oracle import physics as ph
     from oracle import rrk
@@ -17,6 +23,7 @@ def test_rrk_vortex_20_steps_parity():
     from oracle.residual import OracleScheme
     from paper_2305_07181_amd import sbp, workloads as wl
     say("[rrk vortex 20 steps]")
+    eps = np.finfo(float).eps
     desc = wl.vortex2d_mesh(8)
     m = OracleMesh(desc, 2)
     sch = OracleScheme(m, ph.Gas())
@@ -25,20 +32,30 @@ def test_rrk_vortex_20_steps_parity():
     ud = torch.from_numpy(u).cuda()
     s0 = sch.total_entropy(u)
     uo = u.copy()
+    H = m.H_all()
+    bound = 0.0
     for step in range(20):
         dt_o = sch.timestep(uo, 0.1)
         rep = mesh.rrk_step(ud, cfl=0.1)
         assert abs(rep["dt"] - dt_o) <= 1e-13 * dt_o, (rep["dt"], dt_o)
-        uo, g, d, e = rrk.rrk4_step(sch, uo, dt_o)
+        d, e = rrk.rk4_direction(sch, uo, dt_o)
+        g = rrk.solve_gamma(sch, uo, d, e)
+        s_abs = np.sum(H * np.abs(ph.entropy(np.moveaxis(uo, 1, 0), sch.gas)))
+        w1 = np.stack([ph.entropy_vars(uo[k] + g * d[k], sch.gas) for k in range(m.ne)])
+        rprime = np.sum(H[:, None, :] * w1 * d) - e
+        kappa = 8 * eps * s_abs / abs(rprime)
+        r_at_gpu = rrk.entropy_gap(sch, uo, d, e, rep["gamma"], H)
+        assert abs(r_at_gpu) <= 8 * eps * s_abs, (r_at_gpu, 8 * eps * s_abs)
+        assert abs(rep["gamma"] - g) <= kappa
+        uo = uo + g * d
+        bound += 1e-12 + kappa * np.abs(d).max() / np.abs(uo).max()
         ug = ud.cpu().numpy()
         err = np.abs(ug - uo).max(axis=(0, 2)) / np.abs(uo).max(axis=(0, 2))
         ds = (rep["entropy_after"] - s0) / abs(s0)
-        say(f"   step {step}: gamma gpu {rep['gamma']:.16f} oracle {g:.16f} | rel err {err.max():.2e} "
-            f"| entropy change {ds:.2e} | iters {rep['iters']}")
-        assert (err <= 1e-12).all(), err
+        say(f"   step {step}: gamma gpu {rep['gamma']:.16f} oracle {g:.16f} (kappa {kappa:.1e}) | "
+            f"rel err {err.max():.2e} (bound {bound:.1e}) | entropy change {ds:.2e} | iters {rep['iters']}")
+        assert (err <= bound).all(), err
         assert abs(ds) <= 1e-13
-        assert abs(rep["gamma"] - g) <= 1e-6
-    assert abs(mesh.set_time(0.0) or 0) == 0
     mesh.close()
 
 
