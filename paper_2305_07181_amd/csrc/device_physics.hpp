@@ -83,13 +83,21 @@ __device__ __forceinline__ void node_from_u(const T *u, const GasC<T> &G, Node<D
   n.lp = dlog(n.p);
   T lz1 = n.lrho - n.lp + (n.lp - G.g * n.lrho) * G.inv_apg;
   n.z1 = dexp(lz1);
-  n.P1 = dexp(G.r1 * lz1);
-  n.P2 = dexp(G.r2 * n.lp);
+  n.P1 = (T)0;
+  n.P2 = (T)0;
   T theta = n.p * irho;
   n.w[0] = n.z1 * (G.wfirst * theta - (T)0.5 * q2);
 #pragma unroll
   for (int i = 0; i < D; ++i) n.w[1 + i] = n.z1 * n.V[i];
   n.w[D + 1] = -n.z1;
+}
+
+// z1^r1 and p^r2, needed only by the two-point flux at facet nodes and in the
+// Hadamard volume term.
+template <int D, typename T>
+__device__ __forceinline__ void node_powers(const GasC<T> &G, Node<D, T> &n) {
+  n.P1 = dexp(G.r1 * dlog(n.z1));
+  n.P2 = dexp(G.r2 * n.lp);
 }
 
 // F^(i) from primitives.
@@ -138,13 +146,23 @@ __device__ __forceinline__ T exp_avg(T a, T b, T ar, T br, T r) {
   const T s = a + b;
   const T eps = (a - b) / s;
   if (dabs(eps) <= (T)1e-2) {
-    const T m = (T)0.5 * s;
+    // m^{r-1} [1 + sum_k C(r,2k+1)/r eps^{2k}],  m = (a+b)/2, with
+    // m^{r-1} = (a^r / a) (1 + delta)^{r-1}, delta = (b - a)/(2a), |delta| < 0.0102,
+    // the binomial series summed to delta^9 (remainder < 1e-19)
     const T e2 = eps * eps;
     const T c1 = (r - (T)1) * (r - (T)2) / (T)6;
     const T c2 = c1 * (r - (T)3) * (r - (T)4) / (T)20;
     const T c3 = c2 * (r - (T)5) * (r - (T)6) / (T)42;
     const T c4 = c3 * (r - (T)7) * (r - (T)8) / (T)72;
-    const T mr = dexp((r - (T)1) * dlog(m));
+    const T dl = (b - a) / ((T)2 * a);
+    const T q = r - (T)1;
+    T term = (T)1, bin = (T)1;
+#pragma unroll
+    for (int k = 1; k <= 9; ++k) {
+      term = term * (q - (T)(k - 1)) / (T)k * dl;
+      bin += term;
+    }
+    const T mr = ar / a * bin;
     return mr * ((T)1 + e2 * (c1 + e2 * (c2 + e2 * (c3 + e2 * c4))));
   }
   return (ar - br) / (r * (a - b));

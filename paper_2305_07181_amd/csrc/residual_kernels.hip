@@ -30,11 +30,11 @@
 namespace sbp {
 
 template <> struct Tile<3, 1, double, 0> { static constexpr int EB = 16; };
-template <> struct Tile<3, 2, double, 0> { static constexpr int EB = 16; };
-template <> struct Tile<3, 3, double, 0> { static constexpr int EB = 6; };
+template <> struct Tile<3, 2, double, 0> { static constexpr int EB = 6; };
+template <> struct Tile<3, 3, double, 0> { static constexpr int EB = 3; };
 template <> struct Tile<3, 1, float, 0> { static constexpr int EB = 32; };
-template <> struct Tile<3, 2, float, 0> { static constexpr int EB = 32; };
-template <> struct Tile<3, 3, float, 0> { static constexpr int EB = 12; };
+template <> struct Tile<3, 2, float, 0> { static constexpr int EB = 16; };
+template <> struct Tile<3, 3, float, 0> { static constexpr int EB = 6; };
 template <> struct Tile<2, 1, double, 0> { static constexpr int EB = 16; };
 template <> struct Tile<2, 2, double, 0> { static constexpr int EB = 16; };
 template <> struct Tile<2, 3, double, 0> { static constexpr int EB = 8; };
@@ -102,23 +102,34 @@ template <typename T, int MP, int KP, int NCP>
 __device__ __forceinline__ void gemm_AtB(const T *__restrict__ At, const T *B, T *C) {
   constexpr int MT = MP / 16, NT = NCP / 16, NTILE = MT * NT;
   constexpr int TPW = (NTILE + kWaves - 1) / kWaves;
+  constexpr int KS = KP / 4;       // k steps
+  constexpr int KB = 8;            // k steps whose operands are loaded together
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, kr = lane >> 4;
   typename MF<T>::v4 acc[TPW];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) acc[t] = typename MF<T>::v4{0, 0, 0, 0};
-#pragma unroll 4
-  for (int k = 0; k < KP; k += 4) {
+  for (int k0 = 0; k0 < KS; k0 += KB) {
+    T a[KB][TPW], b[KB][TPW];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-      const int tile = wave + t * kWaves;
-      if (tile < NTILE) {
-        const int mt = tile % MT, nt = tile / MT;
-        const T a = At[(k + kr) * MP + mt * 16 + col];
-        const T b = B[(k + kr) * NCP + nt * 16 + col];
-        acc[t] = MF<T>::mma(a, b, acc[t]);
+    for (int kk = 0; kk < KB; ++kk)
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int tile = wave + t * kWaves;
+        const int k = 4 * (k0 + kk) + kr;
+        if (tile < NTILE && k0 + kk < KS) {
+          const int mt = tile % MT, nt = tile / MT;
+          a[kk][t] = At[k * MP + mt * 16 + col];
+          b[kk][t] = B[k * NCP + nt * 16 + col];
+        }
       }
-    }
+#pragma unroll
+    for (int kk = 0; kk < KB; ++kk)
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int tile = wave + t * kWaves;
+        if (tile < NTILE && k0 + kk < KS) acc[t] = MF<T>::mma(a[kk][t], b[kk][t], acc[t]);
+      }
   }
   __syncthreads();
 #pragma unroll
@@ -161,8 +172,11 @@ __device__ __forceinline__ void finish_node(const KArgs<T> &A, int eg, int i, co
     Node<D, T> nv;
     node_from_u<D, T>(uv, A.G, nv);
     if (!nv.ok) atomicOr(A.err, 1);
+    node_powers<D, T>(A.G, nv);
+    Node<D, T> nk = n;
+    node_powers<D, T>(A.G, nk);
     T ft[NC];
-    facet_term<D, T>(n, nv, avec, A.G, A.diss != 0, ft);
+    facet_term<D, T>(nk, nv, avec, A.G, A.diss != 0, ft);
 #pragma unroll
     for (int c = 0; c < NC; ++c) r[c] -= ft[c] * iH;
   }
@@ -222,13 +236,19 @@ __global__ __launch_bounds__(kThreads) void k_split3(KArgs<T> A) {
   for (int x = tid; x < K1P * NCP; x += kThreads) B1[x] = (T)0;
   for (int x = tid; x < K2P * NCP; x += kThreads) B2[x] = (T)0;
   __syncthreads();
-  // pointwise: contravariant fluxes and entropy variables
-  for (int x = tid; x < ne * NP; x += kThreads) {
+  // pointwise: contravariant fluxes and entropy variables; each thread keeps
+  // the node states it owns in registers for the later phases
+  constexpr int NPT = (EB * NP + kThreads - 1) / kThreads;
+  Node<D, T> nodes[NPT];
+#pragma unroll
+  for (int kq = 0; kq < NPT; ++kq) {
+    const int x = tid + kq * kThreads;
+    if (x >= ne * NP) break;
     const int e = x / NP, j = x % NP;
     T uu[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + j];
-    Node<D, T> n;
+    Node<D, T> &n = nodes[kq];
     node_from_u<D, T>(uu, A.G, n);
     if (!n.ok) atomicOr(A.err, 1);
     T f[D][NC];
@@ -250,13 +270,12 @@ __global__ __launch_bounds__(kThreads) void k_split3(KArgs<T> A) {
     T *B3 = U1;
     for (int x = tid; x < K3P * NCP; x += kThreads) B3[x] = (T)0;
     __syncthreads();
-    for (int x = tid; x < ne * NP; x += kThreads) {
-      const int e = x / NP, i = x % NP;
-      T uu[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + i];
-      Node<D, T> n;
-      node_from_u<D, T>(uu, A.G, n);
+    for (int kq = 0; kq < NPT; ++kq) {
+      const int x = tid + kq * kThreads;
+      if (x >= ne * NP) break;
+      const int e = x / NP, i = x % NP;
+      const Node<D, T> &n = nodes[kq];
       const T *Lam = gs + e * 10;
       const T iJ = (T)1 / Lam[9];
       T gW[D][NC], FV[D][NC];
@@ -307,13 +326,12 @@ __global__ __launch_bounds__(kThreads) void k_split3(KArgs<T> A) {
     gemm_AtB<T, M1P, K3P, NCP>(A.op.At5, B3, C3);
   }
   double ent = 0.0;
-  for (int x = tid; x < ne * NP; x += kThreads) {
-    const int e = x / NP, i = x % NP;
-    T uu[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + i];
-    Node<D, T> n;
-    node_from_u<D, T>(uu, A.G, n);
+  for (int kq = 0; kq < NPT; ++kq) {
+    const int x = tid + kq * kThreads;
+    if (x >= ne * NP) break;
+    const int e = x / NP, i = x % NP;
+    const Node<D, T> &n = nodes[kq];
     const T *Lam = gs + e * 10;
     const T J = Lam[9];
     const T iJ = (T)1 / J;
@@ -636,6 +654,7 @@ __global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
     Node<D, T> n;
     node_from_u<D, T>(uu, A.G, n);
     if (!n.ok) atomicOr(A.err, 1);
+    node_powers<D, T>(A.G, n);
     T *v = nd + (e * NP + j) * NV;
     v[0] = n.rho;
 #pragma unroll

@@ -89,6 +89,8 @@ __device__ __forceinline__ void facet_grad(const double *u1, const double *u2, c
     Node<D, Dual<double>> n1, n2;
     node_from_u<D, Dual<double>>(x1, G, n1);
     node_from_u<D, Dual<double>>(x2, G, n2);
+    node_powers<D, Dual<double>>(G, n1);
+    node_powers<D, Dual<double>>(G, n2);
     Dual<double> ph[NC];
     facet_term<D, Dual<double>>(n1, n2, av, G, diss, ph);
     double s = 0.0;
