@@ -17,6 +17,16 @@
 
 namespace sbp {
 
+// Constants of the exponential average {x^(r-1)}_e for one exponent r:
+// odd-power series coefficients C(r, 2k+1)/r, k = 1..4, and the binomial
+// coefficients of (1 + delta)^(r-1), powers 1..9.
+template <typename T>
+struct ExpAvgC {
+  T r;
+  T c[4];
+  T bn[9];
+};
+
 template <typename T>
 struct GasC {
   T g, gm1, a, cb;       // gamma, gamma-1, alpha, 1/(beta+1)
@@ -26,7 +36,28 @@ struct GasC {
   T ja, jb_inv;          // (1-alpha-gamma)/(alpha+gamma), (alpha+gamma)/(1-gamma)
   T sfac;                // (gamma-1)(gamma+alpha)/(gamma alpha)
   T ggm1;                // gamma/(gamma-1)
+  ExpAvgC<T> e1, e2;     // exponential averages of z1 (r1) and p (r2)
 };
+
+template <typename T>
+__host__ ExpAvgC<T> make_exp_avg(double r) {
+  ExpAvgC<T> C;
+  C.r = (T)r;
+  double c = (r - 1.0) * (r - 2.0) / 6.0;
+  C.c[0] = (T)c;
+  c *= (r - 3.0) * (r - 4.0) / 20.0;
+  C.c[1] = (T)c;
+  c *= (r - 5.0) * (r - 6.0) / 42.0;
+  C.c[2] = (T)c;
+  c *= (r - 7.0) * (r - 8.0) / 72.0;
+  C.c[3] = (T)c;
+  double b = 1.0;
+  for (int k = 1; k <= 9; ++k) {
+    b *= (r - 1.0 - (k - 1)) / k;
+    C.bn[k - 1] = (T)b;
+  }
+  return C;
+}
 
 template <typename T>
 __host__ GasC<T> make_gas(double gamma, double beta) {
@@ -44,6 +75,8 @@ __host__ GasC<T> make_gas(double gamma, double beta) {
   G.jb_inv = (T)((alpha + gamma) / (1.0 - gamma));
   G.sfac = (T)((gamma - 1.0) * (gamma + alpha) / (gamma * alpha));
   G.ggm1 = (T)(gamma / (gamma - 1.0));
+  G.e1 = make_exp_avg<T>(-gamma / alpha);
+  G.e2 = make_exp_avg<T>((1.0 - gamma) / alpha);
   return G;
 }
 
@@ -60,7 +93,7 @@ __device__ __forceinline__ float dabs(float x) { return fabsf(x); }
 template <int D, typename T>
 struct Node {
   T rho, V[D], p;
-  T lrho, lp;   // logarithms
+  T lrho, lp, lz1;  // logarithms of rho, p, z1
   T z1;         // (rho/p)(p rho^-gamma)^(1/(alpha+gamma)) = -W_nc
   T P1, P2;     // z1^r1, p^r2 (powers entering the two-point flux averages)
   T w[D + 2];   // entropy variables
@@ -81,8 +114,8 @@ __device__ __forceinline__ void node_from_u(const T *u, const GasC<T> &G, Node<D
   n.ok = (n.rho > (T)0) && (n.p > (T)0) && (n.rho < (T)1e300) && (n.p < (T)1e300);
   n.lrho = dlog(n.rho);
   n.lp = dlog(n.p);
-  T lz1 = n.lrho - n.lp + (n.lp - G.g * n.lrho) * G.inv_apg;
-  n.z1 = dexp(lz1);
+  n.lz1 = n.lrho - n.lp + (n.lp - G.g * n.lrho) * G.inv_apg;
+  n.z1 = dexp(n.lz1);
   n.P1 = (T)0;
   n.P2 = (T)0;
   T theta = n.p * irho;
@@ -96,7 +129,7 @@ __device__ __forceinline__ void node_from_u(const T *u, const GasC<T> &G, Node<D
 // Hadamard volume term.
 template <int D, typename T>
 __device__ __forceinline__ void node_powers(const GasC<T> &G, Node<D, T> &n) {
-  n.P1 = dexp(G.r1 * dlog(n.z1));
+  n.P1 = dexp(G.r1 * n.lz1);
   n.P2 = dexp(G.r2 * n.lp);
 }
 
@@ -140,32 +173,26 @@ __device__ __forceinline__ void jvp_flux(const Node<D, T> &n, const GasC<T> &G, 
   out[D + 1] = dV[i] * ep + n.V[i] * (G.ggm1 * dp + (T)0.5 * q2 * drho + n.rho * VdV);
 }
 
-// Exponential average {x^{r-1}}_e from values a, b and their r-th powers.
+// Exponential average {x^{r-1}}_e = (a^r - b^r) / (r (a - b)) from values
+// a, b and their r-th powers; near a = b the series form
+//   m^{r-1} [1 + sum_k C(r,2k+1)/r eps^{2k}],  m = (a+b)/2,  eps = (a-b)/(a+b),
+// with m^{r-1} = (a^r / a) (1 + delta)^{r-1}, delta = (b - a)/(2a),
+// |delta| < 0.0102, the binomial series summed to delta^9 (remainder < 1e-19).
 template <typename T>
-__device__ __forceinline__ T exp_avg(T a, T b, T ar, T br, T r) {
+__device__ __forceinline__ T exp_avg(T a, T b, T ar, T br, const ExpAvgC<T> &C) {
   const T s = a + b;
   const T eps = (a - b) / s;
   if (dabs(eps) <= (T)1e-2) {
-    // m^{r-1} [1 + sum_k C(r,2k+1)/r eps^{2k}],  m = (a+b)/2, with
-    // m^{r-1} = (a^r / a) (1 + delta)^{r-1}, delta = (b - a)/(2a), |delta| < 0.0102,
-    // the binomial series summed to delta^9 (remainder < 1e-19)
-    const T e2 = eps * eps;
-    const T c1 = (r - (T)1) * (r - (T)2) / (T)6;
-    const T c2 = c1 * (r - (T)3) * (r - (T)4) / (T)20;
-    const T c3 = c2 * (r - (T)5) * (r - (T)6) / (T)42;
-    const T c4 = c3 * (r - (T)7) * (r - (T)8) / (T)72;
-    const T dl = (b - a) / ((T)2 * a);
-    const T q = r - (T)1;
-    T term = (T)1, bin = (T)1;
+    const T ia = (T)1 / a;
+    const T dl = (T)0.5 * (b - a) * ia;
+    T bin = C.bn[8];
 #pragma unroll
-    for (int k = 1; k <= 9; ++k) {
-      term = term * (q - (T)(k - 1)) / (T)k * dl;
-      bin += term;
-    }
-    const T mr = ar / a * bin;
-    return mr * ((T)1 + e2 * (c1 + e2 * (c2 + e2 * (c3 + e2 * c4))));
+    for (int k = 7; k >= 0; --k) bin = C.bn[k] + dl * bin;
+    bin = (T)1 + dl * bin;
+    const T e2 = eps * eps;
+    return ar * ia * bin * ((T)1 + e2 * (C.c[0] + e2 * (C.c[1] + e2 * (C.c[2] + e2 * C.c[3]))));
   }
-  return (ar - br) / (r * (a - b));
+  return (ar - br) / (C.r * (a - b));
 }
 
 // Facet term at one facet node pair, own side k, neighbour v, area-normal
@@ -177,8 +204,8 @@ __device__ __forceinline__ void facet_term(const Node<D, T> &k, const Node<D, T>
                                            const GasC<T> &G, bool diss, T *out) {
   constexpr int NC = D + 2;
   const T P1k = k.P1, P1v = v.P1, P2k = k.P2, P2v = v.P2;
-  const T Ep = exp_avg(k.p, v.p, P2k, P2v, G.r2);
-  const T Ez = exp_avg(k.z1, v.z1, P1k, P1v, G.r1);
+  const T Ep = exp_avg(k.p, v.p, P2k, P2v, G.e2);
+  const T Ez = exp_avg(k.z1, v.z1, P1k, P1v, G.e1);
   const T Dn = (T)0.5 * (P1k + P1v) * Ep;
   const T iD = (T)1 / Dn;
   T an = 0;  // a . {z1 V} / D

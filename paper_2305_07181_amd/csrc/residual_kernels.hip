@@ -35,14 +35,6 @@ template <> struct Tile<3, 3, double, 0> { static constexpr int EB = 3; };
 template <> struct Tile<3, 1, float, 0> { static constexpr int EB = 32; };
 template <> struct Tile<3, 2, float, 0> { static constexpr int EB = 16; };
 template <> struct Tile<3, 3, float, 0> { static constexpr int EB = 6; };
-template <> struct Tile<2, 1, double, 0> { static constexpr int EB = 16; };
-template <> struct Tile<2, 2, double, 0> { static constexpr int EB = 16; };
-template <> struct Tile<2, 3, double, 0> { static constexpr int EB = 8; };
-template <> struct Tile<2, 4, double, 0> { static constexpr int EB = 8; };
-template <> struct Tile<2, 1, float, 0> { static constexpr int EB = 32; };
-template <> struct Tile<2, 2, float, 0> { static constexpr int EB = 32; };
-template <> struct Tile<2, 3, float, 0> { static constexpr int EB = 16; };
-template <> struct Tile<2, 4, float, 0> { static constexpr int EB = 16; };
 // entropy split with Navier-Stokes terms (3D)
 template <> struct Tile<3, 1, double, 2> { static constexpr int EB = 16; };
 template <> struct Tile<3, 2, double, 2> { static constexpr int EB = 9; };
@@ -453,133 +445,320 @@ __global__ __launch_bounds__(kThreads) void k_visc_q3(KArgs<T> A) {
 
 // ---------------------------------------------------------------------------
 // Entropy split, 2D triangles with per-node metrics of a quadratic map.
+//
+// With Q_l = S_l + E_l/2 (S_l skew, E_l diagonal for diagonal-E operators)
+// and M_l = c_b Q_l + Q_l^T = (c_b - 1) S_l + (c_b + 1)/2 E_l, the curved
+// split terms
 //   sum_i [c_b Q_xi + Q_xi^T] f^(i) = 1/2 sum_l [ sum_i Lambda_il o (M_l f^(i)) + M_l fhat_l ]
 //   Q_xi w                           = 1/2 sum_l [ Lambda_il o (Q_l w) + Q_l (Lambda_il o w) ]
-// One pass per reference direction l (two GEMMs, 3 NC columns per element).
+// become
+//   vol   = (c_b - 1)/2 V + (c_b + 1)/2 sum_i a_i f^(i),
+//           V = sum_l [ Lambda_0l o S_l f0 + Lambda_1l o S_l f1 + S_l fhat_l ]
+//   Q_xi w = 1/2 X_i + 1/2 a_i w,  X_i = sum_l [ Lambda_il o S_l w + S_l (Lambda_il o w) ]
+// with a_i = sum_l Lambda_il E_l (the facet B n_i, zero off the facets).  Only
+// the two skew operators enter the MFMA contractions, so every wave keeps
+// their A fragments in registers for the whole (persistent) launch.
+//
+// Each wave works alone on groups of EW = 4 CT elements (16 MFMA columns =
+// 4 elements x 4 components per column tile) with its own LDS region, so the
+// four waves of a workgroup drift apart and overlap MFMA and VALU phases.
+template <int P, typename T> struct Wave2;
+template <> struct Wave2<1, double> { static constexpr int CT = 2; };
+template <> struct Wave2<2, double> { static constexpr int CT = 2; };
+template <> struct Wave2<3, double> { static constexpr int CT = 1; };
+template <> struct Wave2<4, double> { static constexpr int CT = 1; };
+template <> struct Wave2<1, float> { static constexpr int CT = 4; };
+template <> struct Wave2<2, float> { static constexpr int CT = 2; };
+template <> struct Wave2<3, float> { static constexpr int CT = 1; };
+template <> struct Wave2<4, float> { static constexpr int CT = 1; };
+
+// LDS writes of a wave become visible to all its lanes (no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Node record from stored primitives and z1 (entropy variables rebuilt
+// without transcendentals); P1, P2 are filled by the caller where needed.
+template <int D, typename T>
+__device__ __forceinline__ void node_from_prims(T rho, const T *V, T p, T z1, const GasC<T> &G, Node<D, T> &n) {
+  n.rho = rho;
+  T q2 = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    n.V[i] = V[i];
+    q2 += V[i] * V[i];
+  }
+  n.p = p;
+  n.z1 = z1;
+  n.lrho = n.lp = n.lz1 = n.P1 = n.P2 = (T)0;
+  n.ok = true;
+  n.w[0] = z1 * (G.wfirst * (p / rho) - (T)0.5 * q2);
+#pragma unroll
+  for (int i = 0; i < D; ++i) n.w[1 + i] = z1 * V[i];
+  n.w[D + 1] = -z1;
+}
+
 template <int P, typename T>
 __global__ __launch_bounds__(kThreads) void k_split2(KArgs<T> A) {
   constexpr int D = 2, NC = 4, NFAC = 3;
-  constexpr int NP = Shape<2, P>::NP, NF = Shape<2, P>::NF;
-  constexpr int EB = Tile<2, P, T, 0>::EB;
-  constexpr int NCOL = EB * 3 * NC, NCP = ru(NCOL, 16);
-  constexpr int KP = ru(NP, 4), MP = ru(NP, 16);
-  __shared__ T BM[KP * NCP];
-  __shared__ T BQ[KP * NCP];
-  __shared__ T CM[MP * NCP];
-  __shared__ T CQ[MP * NCP];
-  __shared__ T acc[EB * NP * 3 * NC];  // [e][i][vol(NC), Qx_0 w (NC), Qx_1 w (NC)]
-  __shared__ T us[EB * NC * NP];
-  __shared__ T met[EB * NP * 5];       // Lambda_00, Lambda_01, Lambda_10, Lambda_11, J
-  __shared__ T hs[NP];
-  __shared__ T Es[2 * NP];
-  const int tid = threadIdx.x;
-  const int e0 = blockIdx.x * EB;
-  const int ne = min(EB, A.n_elem - e0);
-  for (int x = tid; x < NP; x += kThreads) hs[x] = A.op.h[x];
-  for (int x = tid; x < 2 * NP; x += kThreads) Es[x] = A.op.E[x];
-  for (int x = tid; x < ne * NC * NP; x += kThreads) {
-    const int e = x / (NC * NP);
-    us[x] = (T)A.u[A.uoff[e0 + e] + x % (NC * NP)];
-  }
-  for (int x = tid; x < EB * NP * 3 * NC; x += kThreads) acc[x] = (T)0;
-  // metrics at the nodes: F[i][l] = dx_i/dxi_l, Lambda_il = J dxi_l/dx_i
-  for (int x = tid; x < ne * NP; x += kThreads) {
-    const int e = x / NP, j = x % NP;
-    const double *g = A.geo + (size_t)(e0 + e) * 12;
-    T F[2][2] = {{0, 0}, {0, 0}};
-#pragma unroll
-    for (int a = 0; a < 6; ++a) {
-      const T d0 = A.op.dN[(0 * 6 + a) * NP + j], d1 = A.op.dN[(1 * 6 + a) * NP + j];
-      const T gx = (T)g[2 * a], gy = (T)g[2 * a + 1];
-      F[0][0] += d0 * gx;
-      F[0][1] += d1 * gx;
-      F[1][0] += d0 * gy;
-      F[1][1] += d1 * gy;
-    }
-    T *m = met + (e * NP + j) * 5;
-    m[0] = F[1][1];   // Lambda_00
-    m[1] = -F[1][0];  // Lambda_01
-    m[2] = -F[0][1];  // Lambda_10
-    m[3] = F[0][0];   // Lambda_11
-    m[4] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
-  }
-  __syncthreads();
-  for (int l = 0; l < 2; ++l) {
-    for (int x = tid; x < KP * NCP; x += kThreads) {
-      BM[x] = (T)0;
-      BQ[x] = (T)0;
-    }
-    __syncthreads();
-    for (int x = tid; x < ne * NP; x += kThreads) {
-      const int e = x / NP, j = x % NP;
-      T uu[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + j];
-      Node<D, T> n;
-      node_from_u<D, T>(uu, A.G, n);
-      if (l == 0 && !n.ok) atomicOr(A.err, 1);
-      T f0[NC], f1[NC];
-      flux_i<D, T>(n, uu[NC - 1], 0, f0);
-      flux_i<D, T>(n, uu[NC - 1], 1, f1);
-      const T *m = met + (e * NP + j) * 5;
-      const T L0l = m[0 * 2 + l], L1l = m[1 * 2 + l];
-      const int base = j * NCP + e * 3 * NC;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        BM[base + 0 * NC + c] = f0[c];
-        BM[base + 1 * NC + c] = f1[c];
-        BM[base + 2 * NC + c] = L0l * f0[c] + L1l * f1[c];
-        BQ[base + 0 * NC + c] = n.w[c];
-        BQ[base + 1 * NC + c] = L0l * n.w[c];
-        BQ[base + 2 * NC + c] = L1l * n.w[c];
-      }
-    }
-    __syncthreads();
-    gemm_AtB<T, MP, KP, NCP>(l == 0 ? A.op.At1 : A.op.At2, BM, CM);
-    gemm_AtB<T, MP, KP, NCP>(l == 0 ? A.op.At3 : A.op.At4, BQ, CQ);
-    for (int x = tid; x < ne * NP; x += kThreads) {
-      const int e = x / NP, i = x % NP;
-      const T *m = met + (e * NP + i) * 5;
-      const T L0l = m[0 * 2 + l], L1l = m[1 * 2 + l];
-      const int base = i * NCP + e * 3 * NC;
-      T *ac = acc + (e * NP + i) * 3 * NC;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        ac[c] += (T)0.5 * (L0l * CM[base + 0 * NC + c] + L1l * CM[base + 1 * NC + c] + CM[base + 2 * NC + c]);
-        ac[NC + c] += (T)0.5 * (L0l * CQ[base + 0 * NC + c] + CQ[base + 1 * NC + c]);
-        ac[2 * NC + c] += (T)0.5 * (L1l * CQ[base + 0 * NC + c] + CQ[base + 2 * NC + c]);
-      }
-    }
-    __syncthreads();
-  }
+  constexpr int NP = Shape<2, P>::NP, NF = Shape<2, P>::NF, NFN = NFAC * NF;
+  constexpr int KP = ru(NP, 4), MP = ru(NP, 16), MT = MP / 16, KS = KP / 4;
+  constexpr int CT = Wave2<P, T>::CT, EW = 4 * CT, LD = 16 * CT;
+  constexpr int NPW = EW * NP, NFW = EW * NFN;
+  typedef typename MF<T>::v4 V4;
+  // per wave: [f0 | f1 | w][node][element x component], later [V | X_0 | X_1],
+  // then the volume part of r at the facet nodes (slot 0)
+  __shared__ T Bs[kWaves][3][KP][LD];
+  // per wave: Lambda_00, Lambda_01, Lambda_10, Lambda_11, J at [node][element]
+  __shared__ T Lm[kWaves][5][NP][EW];
+  // per wave: rho, V_0, V_1, p, z1, E at [node][element]
+  __shared__ T Pm[kWaves][6][NP][EW];
+  // per wave: z1^r1, p^r2 at the facet nodes; neighbour state at the facet nodes
+  __shared__ T Fm[kWaves][2][NFN][EW];
+  __shared__ T Um[kWaves][NC][NFN][EW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, kr = lane >> 4;
+  T(*B)[KP][LD] = Bs[wave];
+  T(*L)[NP][EW] = Lm[wave];
+  T(*Pr)[NP][EW] = Pm[wave];
+  T(*FP)[NFN][EW] = Fm[wave];
+  T(*NU)[NFN][EW] = Um[wave];
+  for (int x = lane; x < 3 * KP * LD; x += 64) (&B[0][0][0])[x] = (T)0;
+  const T cb = A.G.cb;
+  const T hv = (T)0.5 * (cb - (T)1), he = (T)0.5 * (cb + (T)1);
   double ent = 0.0;
-  for (int x = tid; x < ne * NP; x += kThreads) {
-    const int e = x / NP, i = x % NP;
-    T uu[NC];
+  const int ngroups = (A.n_elem + EW - 1) / EW;
+  for (int grp = blockIdx.x * kWaves + wave; grp < ngroups; grp += gridDim.x * kWaves) {
+    const int e0 = grp * EW;
+    wave_lds_sync();
+    // neighbour states at the facet nodes
+    for (int x = lane; x < NFW; x += 64) {
+      const int e = x / NFN, m = x % NFN, eg = e0 + e;
+      if (eg < A.n_elem) {
+        const int off = A.nbr[(size_t)eg * NFN + m];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + i];
-    Node<D, T> n;
-    node_from_u<D, T>(uu, A.G, n);
-    const T *m = met + (e * NP + i) * 5;
-    const T H = m[4] * hs[i];
-    const T iH = (T)1 / H;
-    const T *ac = acc + (e * NP + i) * 3 * NC;
-    T r[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) r[c] = ac[c] * iH;
-#pragma unroll
-    for (int dir = 0; dir < D; ++dir) {
-      T g[NC], t[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) g[c] = ac[(1 + dir) * NC + c] * iH;
-      jvp_flux<D, T>(n, A.G, dir, g, t);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) r[c] -= A.G.cb * t[c];
+        for (int c = 0; c < NC; ++c) NU[c][m][e] = (T)A.u[off + c * NP];
+      }
     }
-    T avec[D];
-    avec[0] = m[0] * Es[i] + m[1] * Es[NP + i];
-    avec[1] = m[2] * Es[i] + m[3] * Es[NP + i];
-    finish_node<D, NP, NF, T>(A, e0 + e, i, n, H, avec, r, ent);
+    // pointwise: metrics, primitives, fluxes and entropy variables (zeros past
+    // the last element), flux powers at the facet nodes
+    for (int x = lane; x < NPW; x += 64) {
+      const int e = x / NP, j = x % NP, eg = e0 + e;
+      T f0[NC], f1[NC], w[NC], lam[5];
+      if (eg < A.n_elem) {
+        const double *g = A.geo + (size_t)eg * 12;
+        T F[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+          const T d0 = A.op.dN[(0 * 6 + a) * NP + j], d1 = A.op.dN[(1 * 6 + a) * NP + j];
+          const T gx = (T)g[2 * a], gy = (T)g[2 * a + 1];
+          F[0][0] += d0 * gx;
+          F[0][1] += d1 * gx;
+          F[1][0] += d0 * gy;
+          F[1][1] += d1 * gy;
+        }
+        lam[0] = F[1][1];   // Lambda_00 = J dxi_0/dx_0
+        lam[1] = -F[1][0];  // Lambda_01
+        lam[2] = -F[0][1];  // Lambda_10
+        lam[3] = F[0][0];   // Lambda_11
+        lam[4] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+        const int uo = A.uoff[eg];
+        T uu[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) uu[c] = (T)A.u[uo + c * NP + j];
+        Node<D, T> n;
+        node_from_u<D, T>(uu, A.G, n);
+        if (!n.ok) atomicOr(A.err, 1);
+        flux_i<D, T>(n, uu[NC - 1], 0, f0);
+        flux_i<D, T>(n, uu[NC - 1], 1, f1);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) w[c] = n.w[c];
+        Pr[0][j][e] = n.rho;
+        Pr[1][j][e] = n.V[0];
+        Pr[2][j][e] = n.V[1];
+        Pr[3][j][e] = n.p;
+        Pr[4][j][e] = n.z1;
+        Pr[5][j][e] = uu[NC - 1];
+        if (j < NFN) {
+          node_powers<D, T>(A.G, n);
+          FP[0][j][e] = n.P1;
+          FP[1][j][e] = n.P2;
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) f0[c] = f1[c] = w[c] = (T)0;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) lam[q] = (T)0;
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        B[0][j][e * NC + c] = f0[c];
+        B[1][j][e * NC + c] = f1[c];
+        B[2][j][e * NC + c] = w[c];
+      }
+#pragma unroll
+      for (int q = 0; q < 5; ++q) L[q][j][e] = lam[q];
+    }
+    // A fragments of S_0, S_1: lane holds S_l[mt*16 + col][4 ks + kr]
+    T sf[2][MT][KS];
+#pragma unroll
+    for (int l = 0; l < 2; ++l)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const int m = mt * 16 + col, k = 4 * ks + kr;
+          sf[l][mt][ks] = (m < NP && k < NP) ? A.op.S[(l * NP + m) * NP + k] : (T)0;
+        }
+    wave_lds_sync();
+    // skew contractions: V, X_0, X_1 per column tile, rows in the accumulators.
+    // Column groups g: S_l f0, S_l f1, S_l fhat_l, S_l w, S_l (Lambda_0l w),
+    // S_l (Lambda_1l w); one group at a time keeps few accumulators live.
+    V4 vo[CT][MT], x0[CT][MT], x1[CT][MT];
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const int cc = t * 16 + col, el = t * 4 + (col >> 2);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) vo[t][mt] = x0[t][mt] = x1[t][mt] = V4{0, 0, 0, 0};
+#pragma unroll
+      for (int l = 0; l < 2; ++l)
+#pragma unroll
+        for (int g = 0; g < 6; ++g) {
+          V4 acc[MT];
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) acc[mt] = V4{0, 0, 0, 0};
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) {
+            const int k = 4 * ks + kr;
+            // rows k >= NP of B are zero; Lambda is not stored there
+            const bool in = 4 * ks + 3 < NP || k < NP;
+            const T la = in ? L[l][k][el] : (T)0, lb = in ? L[2 + l][k][el] : (T)0;
+            T b;
+            if (g == 0) b = B[0][k][cc];
+            else if (g == 1) b = B[1][k][cc];
+            else if (g == 2) b = la * B[0][k][cc] + lb * B[1][k][cc];
+            else if (g == 3) b = B[2][k][cc];
+            else if (g == 4) b = la * B[2][k][cc];
+            else b = lb * B[2][k][cc];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt] = MF<T>::mma(sf[l][mt][ks], b, acc[mt]);
+          }
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii) {
+              const int row = mt * 16 + MF<T>::row(kr, ii);
+              if (row < NP) {
+                const T v = acc[mt][ii];
+                if (g == 0) vo[t][mt][ii] += L[l][row][el] * v;
+                else if (g == 1) vo[t][mt][ii] += L[2 + l][row][el] * v;
+                else if (g == 2) vo[t][mt][ii] += v;
+                else if (g == 3) {
+                  x0[t][mt][ii] += L[l][row][el] * v;
+                  x1[t][mt][ii] += L[2 + l][row][el] * v;
+                } else if (g == 4) x0[t][mt][ii] += v;
+                else x1[t][mt][ii] += v;
+              }
+            }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int t = 0; t < CT; ++t)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int row = mt * 16 + MF<T>::row(kr, ii);
+          if (row < NP) {
+            B[0][row][t * 16 + col] = vo[t][mt][ii];
+            B[1][row][t * 16 + col] = x0[t][mt][ii];
+            B[2][row][t * 16 + col] = x1[t][mt][ii];
+          }
+        }
+    wave_lds_sync();
+    // per node: combine and apply A~_i as directional derivatives; interior
+    // nodes are final, facet nodes keep their volume part in LDS
+    for (int x = lane; x < NPW; x += 64) {
+      const int e = x / NP, i = x % NP, eg = e0 + e;
+      if (eg >= A.n_elem) continue;
+      const T Vn[2] = {Pr[1][i][e], Pr[2][i][e]};
+      Node<D, T> n;
+      node_from_prims<D, T>(Pr[0][i][e], Vn, Pr[3][i][e], Pr[4][i][e], A.G, n);
+      T f0[NC], f1[NC];
+      flux_i<D, T>(n, Pr[5][i][e], 0, f0);
+      flux_i<D, T>(n, Pr[5][i][e], 1, f1);
+      const T E0 = A.op.E[i], E1 = A.op.E[NP + i];
+      T avec[D];
+      avec[0] = L[0][i][e] * E0 + L[1][i][e] * E1;
+      avec[1] = L[2][i][e] * E0 + L[3][i][e] * E1;
+      const T H = L[4][i][e] * A.op.h[i];
+      const T iH = (T)1 / H;
+      T r[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        r[c] = iH * (hv * B[0][i][e * NC + c] + he * (avec[0] * f0[c] + avec[1] * f1[c]));
+#pragma unroll
+      for (int dir = 0; dir < D; ++dir) {
+        T g[NC], tt[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) g[c] = (T)0.5 * iH * (B[1 + dir][i][e * NC + c] + avec[dir] * n.w[c]);
+        jvp_flux<D, T>(n, A.G, dir, g, tt);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) r[c] -= cb * tt[c];
+      }
+      if (i < NFN) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) B[0][i][e * NC + c] = r[c];
+      } else {
+        const int uo = A.uoff[eg];
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          A.r[uo + c * NP + i] = r[c];
+          s += (double)n.w[c] * (double)r[c];
+        }
+        ent += (double)H * s;
+      }
+    }
+    wave_lds_sync();
+    // facet SATs (Sec. 4): one lane per facet node
+    for (int x = lane; x < NFW; x += 64) {
+      const int e = x / NFN, i = x % NFN, eg = e0 + e;
+      if (eg >= A.n_elem) continue;
+      const T Vn[2] = {Pr[1][i][e], Pr[2][i][e]};
+      Node<D, T> n;
+      node_from_prims<D, T>(Pr[0][i][e], Vn, Pr[3][i][e], Pr[4][i][e], A.G, n);
+      n.P1 = FP[0][i][e];
+      n.P2 = FP[1][i][e];
+      T uv[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) uv[c] = NU[c][i][e];
+      Node<D, T> nv;
+      node_from_u<D, T>(uv, A.G, nv);
+      if (!nv.ok) atomicOr(A.err, 1);
+      node_powers<D, T>(A.G, nv);
+      const T E0 = A.op.E[i], E1 = A.op.E[NP + i];
+      T avec[D];
+      avec[0] = L[0][i][e] * E0 + L[1][i][e] * E1;
+      avec[1] = L[2][i][e] * E0 + L[3][i][e] * E1;
+      const T H = L[4][i][e] * A.op.h[i];
+      const T iH = (T)1 / H;
+      T ft[NC];
+      facet_term<D, T>(n, nv, avec, A.G, A.diss != 0, ft);
+      const int uo = A.uoff[eg];
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const T r = B[0][i][e * NC + c] - ft[c] * iH;
+        A.r[uo + c * NP + i] = r;
+        s += (double)n.w[c] * (double)r;
+      }
+      ent += (double)H * s;
+    }
   }
   block_sum_store(ent, A.ent_part);
 }
@@ -747,7 +926,7 @@ __global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
 template <typename T>
 int tile_elems(int dim, int p, int form) {
 #define SBP_TILE(DI, PP) \
-  if (dim == DI && p == PP) return form == 1 ? Tile<DI, PP, T, 1>::EB : Tile<DI, PP, T, 0>::EB;
+  if (dim == DI && p == PP) return form == 1 ? Tile<DI, PP, T, 1>::EB : 0;
   SBP_TILE(2, 1) SBP_TILE(2, 2) SBP_TILE(2, 3) SBP_TILE(2, 4)
 #undef SBP_TILE
 #define SBP_TILE3(PP) \
@@ -758,7 +937,34 @@ int tile_elems(int dim, int p, int form) {
   return 0;
 }
 
+// Persistent grid of the 2D split kernel: at most as many workgroups as the
+// device keeps resident at once.
+template <int P, typename T>
+static int split2_grid(int n_elem) {
+  static int cap = 0;
+  if (cap == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_split2<P, T>, kThreads, 0) != hipSuccess ||
+        cus <= 0 || per <= 0)
+      cap = 1024;
+    else
+      cap = cus * per;
+  }
+  const int per_block = kWaves * 4 * Wave2<P, T>::CT;
+  return std::min((n_elem + per_block - 1) / per_block, cap);
+}
+
 int residual_blocks(int dim, int p, int precision, int form, int n_elem) {
+  if (n_elem <= 0) return 0;
+  if (dim == 2 && form == 0) {
+#define SBP_G2(PP) \
+  if (p == PP) return precision == 0 ? split2_grid<PP, double>(n_elem) : split2_grid<PP, float>(n_elem);
+    SBP_G2(1) SBP_G2(2) SBP_G2(3) SBP_G2(4)
+#undef SBP_G2
+    return 0;
+  }
   const int eb = precision == 0 ? tile_elems<double>(dim, p, form) : tile_elems<float>(dim, p, form);
   if (eb <= 0) return 0;
   return (n_elem + eb - 1) / eb;

@@ -10,7 +10,9 @@ pytestmark = pytest.mark.gpu
 
 
 def test_rrk_vortex_20_steps_parity():
-    """Per step: dt agrees to 1e-13; the GPU's gamma is a root of the oracle's
+    """Per step: dt agrees to 1e-13 plus four times the states' relative
+    difference after the previous step (dt = CFL min h / (|V| + a) moves with
+    the state, relative sensitivity below 2); the GPU's gamma is a root of the oracle's
     r(gamma) within its rounding (|r(gamma_gpu)| <= 8 eps sum H|s|); gamma
     agrees within the root's conditioning kappa = 8 eps sum H|s| / |r'(gamma)|;
     the states agree within the accumulated bound sum_n (1e-12 + kappa_n
@@ -34,10 +36,11 @@ def test_rrk_vortex_20_steps_parity():
     uo = u.copy()
     H = m.H_all()
     bound = 0.0
+    err_prev = 0.0
     for step in range(20):
         dt_o = sch.timestep(uo, 0.1)
         rep = mesh.rrk_step(ud, cfl=0.1)
-        assert abs(rep["dt"] - dt_o) <= 1e-13 * dt_o, (rep["dt"], dt_o)
+        assert abs(rep["dt"] - dt_o) <= (1e-13 + 4 * err_prev) * dt_o, (rep["dt"], dt_o, err_prev)
         d, e = rrk.rk4_direction(sch, uo, dt_o)
         g = rrk.solve_gamma(sch, uo, d, e)
         s_abs = np.sum(H * np.abs(ph.entropy(np.moveaxis(uo, 1, 0), sch.gas)))
@@ -56,6 +59,7 @@ def test_rrk_vortex_20_steps_parity():
             f"rel err {err.max():.2e} (bound {bound:.1e}) | entropy change {ds:.2e} | iters {rep['iters']}")
         assert (err <= bound).all(), err
         assert abs(ds) <= 1e-13
+        err_prev = float(err.max())
     mesh.close()
 
 
