@@ -667,7 +667,6 @@ int sbp_residual_vjp(sbp_mesh *M, const void *u, const void *lam, void *ubar, vo
   const sbp_physics &ph = M->phys;
   if (ph.viscous || ph.form != SBP_FORM_SPLIT)
     return fail(SBP_ENOTSUP, "the VJP covers the entropy-split Euler residual (with or without dissipation)");
-  if (M->dim != 3) return fail(SBP_ENOTSUP, "the VJP is available on tetrahedra");
   for (auto &c : M->cls) {
     sbp::KArgs<double> A = kargs<double>(M, c, (const double *)u, nullptr, c.op64);
     A.lam = (const double *)lam;

@@ -26,6 +26,7 @@
 
 #include "kernels.hpp"
 #include "launch.hpp"
+#include "mfma.hpp"
 
 namespace sbp {
 
@@ -60,30 +61,6 @@ template <> struct Tile<2, 4, float, 1> { static constexpr int EB = 24; };
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-
-// ---------------------------------------------------------------------------
-// MFMA 16x16x4 wrappers.  Lane l holds A[l%16][k0 + l/16], B[k0 + l/16][l%16];
-// accumulator register i of lane l holds D[row(l/16, i)][l%16] with
-// row = l/16 + 4 i for v_mfma_f64_16x16x4f64 and 4 (l/16) + i for
-// v_mfma_f32_16x16x4f32 (checked on gfx950).
-template <typename T>
-struct MF;
-template <>
-struct MF<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  __device__ static __forceinline__ v4 mma(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  __device__ static __forceinline__ int row(int kr, int i) { return kr + 4 * i; }
-};
-template <>
-struct MF<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  __device__ static __forceinline__ v4 mma(float a, float b, v4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  __device__ static __forceinline__ int row(int kr, int i) { return 4 * kr + i; }
-};
 
 // C[MP x NCP] = A[MP x KP] B[KP x NCP].  A^T in global memory (At[k*MP+m],
 // shared by all workgroups, L2 resident), B and C in LDS (row-major, leading
@@ -471,13 +448,6 @@ template <> struct Wave2<1, float> { static constexpr int CT = 4; };
 template <> struct Wave2<2, float> { static constexpr int CT = 2; };
 template <> struct Wave2<3, float> { static constexpr int CT = 1; };
 template <> struct Wave2<4, float> { static constexpr int CT = 1; };
-
-// LDS writes of a wave become visible to all its lanes (no workgroup barrier).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
 
 // Node record from stored primitives and z1 (entropy variables rebuilt
 // without transcendentals); P1, P2 are filled by the caller where needed.

@@ -36,6 +36,61 @@ def test_vjp_3d_vs_oracle(p, diss):
     assert err <= 1e-12, err
 
 
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("diss", [False, True])
+def test_vjp_2d_curved_vs_oracle(p, diss):
+    """Curved (P2-mapped) periodic triangles; several groups of elements per
+    wave and a ragged last group (50 elements)."""
+    import torch
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from oracle.jacobian import vjp_elements
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say(f"[vjp2d] p={p} diss={diss}")
+    desc = wl.vortex2d_mesh(5, warp=0.05)
+    m = OracleMesh(desc, p)
+    u = state(m, "random", seed=7, jitter=0.01)
+    lam = np.random.default_rng(2100 + p).standard_normal(u.shape)
+    mesh = sbp.Mesh(desc, p, dissipation=diss)
+    ub = mesh.vjp(torch.from_numpy(u).cuda(), torch.from_numpy(lam).cuda()).cpu().numpy()
+    mesh.check_device()
+    mesh.close()
+    sch = OracleScheme(m, ph.Gas(), dissipation=diss)
+    els = [0, 13, 31, m.ne - 1]
+    ref = vjp_elements(sch, u, lam, els)
+    scale = max(np.abs(ref[e]).max() for e in els)
+    err = max(np.abs(ub[e] - ref[e]).max() for e in els) / scale
+    say("   rel err", err)
+    assert err <= 1e-12, err
+
+
+def test_vjp_2d_finite_difference():
+    """v . ubar against central differences of lambda . r on 12x12x2 curved
+    triangles, p = 4, EC SATs (FP64)."""
+    import torch
+    from oracle.geometry import OracleMesh
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say("[vjp2d fd]")
+    desc = wl.vortex2d_mesh(12, warp=0.05)
+    m = OracleMesh(desc, 4)
+    u = state(m, "random", seed=9, jitter=0.01)
+    rng = np.random.default_rng(3001)
+    lam = rng.standard_normal(u.shape)
+    v = rng.standard_normal(u.shape) * np.abs(u)
+    mesh = sbp.Mesh(desc, 4)
+    ud, ld, vd = (torch.from_numpy(a).cuda() for a in (u, lam, v))
+    ub = mesh.vjp(ud, ld)
+    h = 1e-6
+    rp = mesh.residual(ud + h * vd)
+    rm = mesh.residual(ud - h * vd)
+    fd = float(torch.sum(ld * (rp - rm)) / (2 * h))
+    ad = float(torch.sum(vd * ub))
+    say("   fd", fd, "ad", ad, "rel", abs(fd - ad) / abs(ad))
+    assert abs(fd - ad) <= 1e-6 * abs(ad)
+    mesh.close()
+
+
 def test_vjp_finite_difference_and_cost():
     """v . ubar against (lambda . r(u + h v) - lambda . r(u - h v)) / 2h, h = 1e-6,
     on a 3^3 x 6 TGV-like random state (FP64)."""
