@@ -78,6 +78,7 @@ struct sbp_mesh {
   double *d_node_h = nullptr;
   double *d_part = nullptr;   // residual partials (sum over classes of blocks)
   int part_total = 0;
+  int batch_blocks = 0;       // 2D entropy split with several degree classes: one launch
   double *d_npart = nullptr;  // node-kernel partials [(n_c+1) x node_total]
   int node_total = 0;
   double *d_scal = nullptr;   // device scalars
@@ -476,6 +477,12 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
     node_total += c.node_blocks;
   }
   (void)prec;
+  if (dim == 2 && form_eff == 0 && M->cls.size() > 1) {
+    int ne_p[4] = {0, 0, 0, 0};
+    for (auto &c : M->cls) ne_p[c.p - 1] = c.n_elem;
+    M->batch_blocks = std::max(sbp::residual2_batch_blocks(ne_p, 0), sbp::residual2_batch_blocks(ne_p, 1));
+    part_total = std::max(part_total, M->batch_blocks);
+  }
   M->part_total = part_total;
   M->node_total = node_total;
   int rc;
@@ -543,6 +550,33 @@ int residual_impl(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStr
       else
         HIPCHK(sbp::launch_visc_q(M->dim, c.p, kargs<float>(M, c, u, r, c.op32), s));
     }
+  }
+  if (M->batch_blocks > 0 && ph.form == SBP_FORM_SPLIT && !ph.viscous) {
+    // every degree class in one persistent launch
+    sbp::KArgs<double> a64[4];
+    sbp::KArgs<float> a32[4];
+    const sbp::KArgs<double> *p64[4] = {nullptr, nullptr, nullptr, nullptr};
+    const sbp::KArgs<float> *p32[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (auto &c : M->cls) {
+      if (ph.precision == SBP_FP64) {
+        a64[c.p - 1] = kargs<double>(M, c, u, r, c.op64);
+        p64[c.p - 1] = &a64[c.p - 1];
+      } else {
+        a32[c.p - 1] = kargs<float>(M, c, u, r, c.op32);
+        p32[c.p - 1] = &a32[c.p - 1];
+      }
+    }
+    if (ph.precision == SBP_FP64)
+      HIPCHK(sbp::launch_residual2_batch(p64, M->d_part, s));
+    else
+      HIPCHK(sbp::launch_residual2_batch(p32, M->d_part, s));
+    if (ent_dev) {
+      int ne_p[4] = {0, 0, 0, 0};
+      for (auto &c : M->cls) ne_p[c.p - 1] = c.n_elem;
+      const int nb = sbp::residual2_batch_blocks(ne_p, ph.precision == SBP_FP64 ? 0 : 1);
+      HIPCHK(sbp::launch_reduce(M->d_part, nb, 1, 0, ent_dev, s));
+    }
+    return SBP_OK;
   }
   for (auto &c : M->cls) {
     if (ph.precision == SBP_FP64)
@@ -667,6 +701,21 @@ int sbp_residual_vjp(sbp_mesh *M, const void *u, const void *lam, void *ubar, vo
   const sbp_physics &ph = M->phys;
   if (ph.viscous || ph.form != SBP_FORM_SPLIT)
     return fail(SBP_ENOTSUP, "the VJP covers the entropy-split Euler residual (with or without dissipation)");
+  if (M->dim == 2 && M->cls.size() > 1) {
+    // every degree class in one persistent launch
+    sbp::KArgs<double> a[4];
+    const sbp::KArgs<double> *pa[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (auto &c : M->cls) {
+      sbp::KArgs<double> &A = a[c.p - 1];
+      A = kargs<double>(M, c, (const double *)u, nullptr, c.op64);
+      A.lam = (const double *)lam;
+      A.ubar = (double *)ubar;
+      A.Hn = c.d_Hn;
+      pa[c.p - 1] = &A;
+    }
+    HIPCHK(sbp::launch_vjp2_batch(pa, (hipStream_t)stream));
+    return SBP_OK;
+  }
   for (auto &c : M->cls) {
     sbp::KArgs<double> A = kargs<double>(M, c, (const double *)u, nullptr, c.op64);
     A.lam = (const double *)lam;

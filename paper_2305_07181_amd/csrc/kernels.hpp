@@ -65,6 +65,16 @@ struct KArgs {
   const double *Hn;    // [n_elem*NP] diagonal of H_k
 };
 
+// All degree classes of a 2D mesh in one launch: c[p-1] holds the arguments
+// of the class of degree p (n_elem = 0 if absent), g0[p-1] its first group in
+// the launch-wide group index, g0[4] the number of groups.
+template <typename T>
+struct Batch2 {
+  KArgs<T> c[4];
+  int g0[5];
+  double *ent_part;  // [gridDim.x] partial sums of w^T H r (may be null)
+};
+
 // Elements per workgroup for each kernel (LDS budget <= 160 KiB on gfx950).
 template <int DIM, int P, typename T, int FORM>
 struct Tile;

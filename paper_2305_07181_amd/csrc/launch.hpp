@@ -10,12 +10,19 @@ namespace sbp {
 hipError_t launch_residual(int dim, int p, int form, const KArgs<double> &A, hipStream_t s);
 hipError_t launch_residual(int dim, int p, int form, const KArgs<float> &A, hipStream_t s);
 int residual_blocks(int dim, int p, int precision, int form, int n_elem);
+// 2D entropy split, every degree class in one persistent launch: cls[p-1] is
+// the class of degree p or null.  Workgroups of the launch (partial sums):
+int residual2_batch_blocks(const int n_elem_of_p[4], int precision);
+hipError_t launch_residual2_batch(const KArgs<double> *const cls[4], double *ent_part, hipStream_t s);
+hipError_t launch_residual2_batch(const KArgs<float> *const cls[4], double *ent_part, hipStream_t s);
 // Viscous facet-flux pre-pass (3D): A.qout[(e*NFAC*NF + m)*n_c + c] = B n . F^V
 hipError_t launch_visc_q(int dim, int p, const KArgs<double> &A, hipStream_t s);
 hipError_t launch_visc_q(int dim, int p, const KArgs<float> &A, hipStream_t s);
 
 // Vector-Jacobian product of the entropy-split residual (FP64, Euler terms).
 hipError_t launch_vjp(int dim, int p, const KArgs<double> &A, hipStream_t s);
+// 2D, every degree class in one persistent launch (cls[p-1] or null)
+hipError_t launch_vjp2_batch(const KArgs<double> *const cls[4], hipStream_t s);
 
 // Per-node pointwise work over one degree class.
 struct NodeArgs {

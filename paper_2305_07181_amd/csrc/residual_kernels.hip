@@ -471,37 +471,44 @@ __device__ __forceinline__ void node_from_prims(T rho, const T *V, T p, T z1, co
 }
 
 template <int P, typename T>
-__global__ __launch_bounds__(kThreads) void k_split2(KArgs<T> A) {
-  constexpr int D = 2, NC = 4, NFAC = 3;
-  constexpr int NP = Shape<2, P>::NP, NF = Shape<2, P>::NF, NFN = NFAC * NF;
-  constexpr int KP = ru(NP, 4), MP = ru(NP, 16), MT = MP / 16, KS = KP / 4;
-  constexpr int CT = Wave2<P, T>::CT, EW = 4 * CT, LD = 16 * CT;
-  constexpr int NPW = EW * NP, NFW = EW * NFN;
-  typedef typename MF<T>::v4 V4;
-  // per wave: [f0 | f1 | w][node][element x component], later [V | X_0 | X_1],
-  // then the volume part of r at the facet nodes (slot 0)
-  __shared__ T Bs[kWaves][3][KP][LD];
-  // per wave: Lambda_00, Lambda_01, Lambda_10, Lambda_11, J at [node][element]
-  __shared__ T Lm[kWaves][5][NP][EW];
-  // per wave: rho, V_0, V_1, p, z1, E at [node][element]
-  __shared__ T Pm[kWaves][6][NP][EW];
-  // per wave: z1^r1, p^r2 at the facet nodes; neighbour state at the facet nodes
-  __shared__ T Fm[kWaves][2][NFN][EW];
-  __shared__ T Um[kWaves][NC][NFN][EW];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int col = lane & 15, kr = lane >> 4;
-  T(*B)[KP][LD] = Bs[wave];
-  T(*L)[NP][EW] = Lm[wave];
-  T(*Pr)[NP][EW] = Pm[wave];
-  T(*FP)[NFN][EW] = Fm[wave];
-  T(*NU)[NFN][EW] = Um[wave];
-  for (int x = lane; x < 3 * KP * LD; x += 64) (&B[0][0][0])[x] = (T)0;
-  const T cb = A.G.cb;
-  const T hv = (T)0.5 * (cb - (T)1), he = (T)0.5 * (cb + (T)1);
-  double ent = 0.0;
-  const int ngroups = (A.n_elem + EW - 1) / EW;
-  for (int grp = blockIdx.x * kWaves + wave; grp < ngroups; grp += gridDim.x * kWaves) {
+struct Split2 {
+  static constexpr int D = 2, NC = 4, NFAC = 3;
+  static constexpr int NP = Shape<2, P>::NP, NF = Shape<2, P>::NF, NFN = NFAC * NF;
+  static constexpr int KP = ru(NP, 4), MP = ru(NP, 16), MT = MP / 16, KS = KP / 4;
+  static constexpr int CT = Wave2<P, T>::CT, EW = 4 * CT, LD = 16 * CT;
+  static constexpr int NPW = EW * NP, NFW = EW * NFN;
+  // wave-private LDS of one group
+  struct Lds {
+    // [f0 | f1 | w][node][element x component], later [V | X_0 | X_1], then
+    // the volume part of r at the facet nodes (slot 0)
+    T B[3][KP][LD];
+    // Lambda_00, Lambda_01, Lambda_10, Lambda_11, J at [node][element]
+    T L[5][NP][EW];
+    // rho, V_0, V_1, p, z1, E at [node][element]
+    T Pr[6][NP][EW];
+    // z1^r1, p^r2 and the neighbour state at the facet nodes
+    T FP[2][NFN][EW];
+    T NU[NC][NFN][EW];
+  };
+
+  // Residual of the EW elements of group grp; ent accumulates w^T H r.
+  __device__ static __forceinline__ void group(const KArgs<T> &A, Lds &S, int grp, int lane, double &ent) {
+    typedef typename MF<T>::v4 V4;
+    const int col = lane & 15, kr = lane >> 4;
+    T(*B)[KP][LD] = S.B;
+    T(*L)[NP][EW] = S.L;
+    T(*Pr)[NP][EW] = S.Pr;
+    T(*FP)[NFN][EW] = S.FP;
+    T(*NU)[NFN][EW] = S.NU;
+    const T cb = A.G.cb;
+    const T hv = (T)0.5 * (cb - (T)1), he = (T)0.5 * (cb + (T)1);
     const int e0 = grp * EW;
+    wave_lds_sync();
+    // the padding rows k >= NP of B stay zero through the group
+    for (int x = lane; x < 3 * (KP - NP) * LD; x += 64) {
+      const int q = x / ((KP - NP) * LD), y = x % ((KP - NP) * LD);
+      B[q][NP + y / LD][y % LD] = (T)0;
+    }
     wave_lds_sync();
     // neighbour states at the facet nodes
     for (int x = lane; x < NFW; x += 64) {
@@ -730,7 +737,50 @@ __global__ __launch_bounds__(kThreads) void k_split2(KArgs<T> A) {
       ent += (double)H * s;
     }
   }
+};
+
+template <int P, typename T>
+__global__ __launch_bounds__(kThreads) void k_split2(KArgs<T> A) {
+  typedef Split2<P, T> K;
+  __shared__ typename K::Lds lds[kWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double ent = 0.0;
+  const int ngroups = (A.n_elem + K::EW - 1) / K::EW;
+  for (int grp = blockIdx.x * kWaves + wave; grp < ngroups; grp += gridDim.x * kWaves)
+    K::group(A, lds[wave], grp, lane, ent);
   block_sum_store(ent, A.ent_part);
+}
+
+// All degree classes of a 2D mesh (batched problems) in one persistent
+// launch: the group index runs over the classes in degree order and every
+// wave dispatches on the degree of its group.
+template <typename T>
+constexpr size_t split2_lds_max() {
+  size_t m = sizeof(typename Split2<1, T>::Lds);
+  m = m > sizeof(typename Split2<2, T>::Lds) ? m : sizeof(typename Split2<2, T>::Lds);
+  m = m > sizeof(typename Split2<3, T>::Lds) ? m : sizeof(typename Split2<3, T>::Lds);
+  m = m > sizeof(typename Split2<4, T>::Lds) ? m : sizeof(typename Split2<4, T>::Lds);
+  return m;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_split2_batch(Batch2<T> Bt) {
+  constexpr size_t LW = (split2_lds_max<T>() + 15) / 16 * 16;
+  __shared__ __align__(16) unsigned char raw[kWaves * LW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  void *mine = raw + wave * LW;
+  double ent = 0.0;
+  for (int g = blockIdx.x * kWaves + wave; g < Bt.g0[4]; g += gridDim.x * kWaves) {
+    if (g < Bt.g0[1])
+      Split2<1, T>::group(Bt.c[0], *(typename Split2<1, T>::Lds *)mine, g, lane, ent);
+    else if (g < Bt.g0[2])
+      Split2<2, T>::group(Bt.c[1], *(typename Split2<2, T>::Lds *)mine, g - Bt.g0[1], lane, ent);
+    else if (g < Bt.g0[3])
+      Split2<3, T>::group(Bt.c[2], *(typename Split2<3, T>::Lds *)mine, g - Bt.g0[2], lane, ent);
+    else
+      Split2<4, T>::group(Bt.c[3], *(typename Split2<4, T>::Lds *)mine, g - Bt.g0[3], lane, ent);
+  }
+  block_sum_store(ent, Bt.ent_part);
 }
 
 // ---------------------------------------------------------------------------
@@ -985,6 +1035,72 @@ static hipError_t launch_q(int dim, int p, const KArgs<T> &A, hipStream_t s) {
 
 hipError_t launch_visc_q(int dim, int p, const KArgs<double> &A, hipStream_t s) { return launch_q<double>(dim, p, A, s); }
 hipError_t launch_visc_q(int dim, int p, const KArgs<float> &A, hipStream_t s) { return launch_q<float>(dim, p, A, s); }
+
+template <typename T>
+static int split2_batch_cap() {
+  static int cap = 0;
+  if (cap == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_split2_batch<T>, kThreads, 0) != hipSuccess ||
+        cus <= 0 || per <= 0)
+      cap = 1024;
+    else
+      cap = cus * per;
+  }
+  return cap;
+}
+
+template <typename T>
+static int split2_ew(int p) {
+  switch (p) {
+    case 1: return Split2<1, T>::EW;
+    case 2: return Split2<2, T>::EW;
+    case 3: return Split2<3, T>::EW;
+    default: return Split2<4, T>::EW;
+  }
+}
+
+template <typename T>
+static int batch_groups(const int n_elem_of_p[4], int g0[5]) {
+  g0[0] = 0;
+  for (int q = 0; q < 4; ++q) {
+    const int ew = split2_ew<T>(q + 1);
+    g0[q + 1] = g0[q] + (n_elem_of_p[q] + ew - 1) / ew;
+  }
+  return g0[4];
+}
+
+int residual2_batch_blocks(const int n_elem_of_p[4], int precision) {
+  int g0[5];
+  const int ng = precision == 0 ? batch_groups<double>(n_elem_of_p, g0) : batch_groups<float>(n_elem_of_p, g0);
+  const int cap = precision == 0 ? split2_batch_cap<double>() : split2_batch_cap<float>();
+  return std::min((ng + kWaves - 1) / kWaves, cap);
+}
+
+template <typename T>
+static hipError_t launch_batch2_t(const KArgs<T> *const cls[4], double *ent_part, hipStream_t s) {
+  Batch2<T> Bt{};
+  int ne[4];
+  for (int q = 0; q < 4; ++q) {
+    ne[q] = cls[q] ? cls[q]->n_elem : 0;
+    if (cls[q]) Bt.c[q] = *cls[q];
+  }
+  const int ng = batch_groups<T>(ne, Bt.g0);
+  if (ng == 0) return hipSuccess;
+  Bt.ent_part = ent_part;
+  const int nb = residual2_batch_blocks(ne, sizeof(T) == 8 ? 0 : 1);
+  hipLaunchKernelGGL((k_split2_batch<T>), dim3(nb), dim3(kThreads), 0, s, Bt);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual2_batch(const KArgs<double> *const cls[4], double *ent_part, hipStream_t s) {
+  return launch_batch2_t<double>(cls, ent_part, s);
+}
+hipError_t launch_residual2_batch(const KArgs<float> *const cls[4], double *ent_part, hipStream_t s) {
+  return launch_batch2_t<float>(cls, ent_part, s);
+}
 
 hipError_t launch_residual(int dim, int p, int form, const KArgs<double> &A, hipStream_t s) {
   return launch_t<double>(dim, p, form, A, s);

@@ -304,52 +304,182 @@ template <int P> struct VjpWave2 { static constexpr int CT = P <= 2 ? 2 : 1; };
 // 2D curved triangles, one wave per group of EW = 4 CT elements (wave-private
 // LDS, persistent waves, as in the forward 2D kernel).
 template <int P>
-__global__ __launch_bounds__(kT) void k_vjp2(KArgs<double> A) {
-  constexpr int D = 2, NC = 4, NFAC = 3;
-  constexpr int NP = Shape<2, P>::NP, NF = Shape<2, P>::NF, NFN = NFAC * NF;
-  constexpr int KP = ru(NP, 4), MP = ru(NP, 16), MT = MP / 16, KS = KP / 4;
-  constexpr int CT = VjpWave2<P>::CT, EW = 4 * CT, LD = 16 * CT;
-  constexpr int NPW = EW * NP;
-  typedef MF<double>::v4 V4;
-  // slots: inputs mu, s_0, s_1, w (0..3); outputs Z_1 (0), V_s (1), X_0 (2), X_1 (3), Z_0 (4)
-  __shared__ double Bs[kW][5][KP][LD];
-  __shared__ double Lm[kW][5][NP][EW];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int col = lane & 15, kr = lane >> 4;
-  double(*B)[KP][LD] = Bs[wave];
-  double(*L)[NP][EW] = Lm[wave];
-  for (int x = lane; x < 5 * KP * LD; x += 64) (&B[0][0][0])[x] = 0.0;
-  const GasC<double> &G = A.G;
-  const GasC<Dual<double>> GD = dual_gas(G);
-  const double cb = G.cb, he = 0.5 * (1.0 + cb), hz = 0.5 * (1.0 - cb);
-  // metrics of element eg at node j: Lambda (4) and J
-  auto metrics = [&](int eg, int j, double *lam) {
-    const double *g = A.geo + (size_t)eg * 12;
-    double F[2][2] = {{0, 0}, {0, 0}};
-#pragma unroll
-    for (int a = 0; a < 6; ++a) {
-      const double d0 = A.op.dN[(0 * 6 + a) * NP + j], d1 = A.op.dN[(1 * 6 + a) * NP + j];
-      F[0][0] += d0 * g[2 * a];
-      F[0][1] += d1 * g[2 * a];
-      F[1][0] += d0 * g[2 * a + 1];
-      F[1][1] += d1 * g[2 * a + 1];
-    }
-    lam[0] = F[1][1];
-    lam[1] = -F[1][0];
-    lam[2] = -F[0][1];
-    lam[3] = F[0][0];
-    lam[4] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+struct Vjp2 {
+  static constexpr int D = 2, NC = 4, NFAC = 3;
+  static constexpr int NP = Shape<2, P>::NP, NF = Shape<2, P>::NF, NFN = NFAC * NF;
+  static constexpr int KP = ru(NP, 4), MP = ru(NP, 16), MT = MP / 16, KS = KP / 4;
+  static constexpr int CT = VjpWave2<P>::CT, EW = 4 * CT, LD = 16 * CT;
+  static constexpr int NPW = EW * NP;
+  struct Lds {
+    // inputs mu, s_0, s_1, w (0..3); outputs Z_1 (0), V_s (1), X_0 (2), X_1 (3), Z_0 (4)
+    double B[5][KP][LD];
+    double L[5][NP][EW];
   };
-  const int ngroups = (A.n_elem + EW - 1) / EW;
-  for (int grp = blockIdx.x * kW + wave; grp < ngroups; grp += gridDim.x * kW) {
+
+  __device__ static __forceinline__ void group(const KArgs<double> &A, Lds &S, int grp, int lane) {
+    typedef MF<double>::v4 V4;
+    const int col = lane & 15, kr = lane >> 4;
+    double(*B)[KP][LD] = S.B;
+    double(*L)[NP][EW] = S.L;
+    const GasC<double> &G = A.G;
+    const GasC<Dual<double>> GD = dual_gas(G);
+    const double cb = G.cb, he = 0.5 * (1.0 + cb), hz = 0.5 * (1.0 - cb);
+    // metrics of element eg at node j: Lambda (4) and J
+    auto metrics = [&](int eg, int j, double *lam) {
+      const double *g = A.geo + (size_t)eg * 12;
+      double F[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        const double d0 = A.op.dN[(0 * 6 + a) * NP + j], d1 = A.op.dN[(1 * 6 + a) * NP + j];
+        F[0][0] += d0 * g[2 * a];
+        F[0][1] += d1 * g[2 * a];
+        F[1][0] += d0 * g[2 * a + 1];
+        F[1][1] += d1 * g[2 * a + 1];
+      }
+      lam[0] = F[1][1];
+      lam[1] = -F[1][0];
+      lam[2] = -F[0][1];
+      lam[3] = F[0][0];
+      lam[4] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+    };
     const int e0 = grp * EW;
     wave_lds_sync();
-    // pointwise: mu = H^-1 lambda, s_i = H^-1 A~_i lambda, w
-    for (int x = lane; x < NPW; x += 64) {
-      const int e = x / NP, j = x % NP, eg = e0 + e;
-      double in[4][NC], lam[5];
-      if (eg < A.n_elem) {
-        metrics(eg, j, lam);
+    for (int x = lane; x < 5 * (KP - NP) * LD; x += 64) {
+      const int q = x / ((KP - NP) * LD), y = x % ((KP - NP) * LD);
+      B[q][NP + y / LD][y % LD] = 0.0;
+    }
+      wave_lds_sync();
+      // pointwise: mu = H^-1 lambda, s_i = H^-1 A~_i lambda, w
+      for (int x = lane; x < NPW; x += 64) {
+        const int e = x / NP, j = x % NP, eg = e0 + e;
+        double in[4][NC], lam[5];
+        if (eg < A.n_elem) {
+          metrics(eg, j, lam);
+          const int uo = A.uoff[eg];
+          double uu[NC], lm[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            uu[c] = A.u[uo + c * NP + j];
+            lm[c] = A.lam[uo + c * NP + j];
+          }
+          Node<D, double> n;
+          node_from_u<D, double>(uu, G, n);
+          if (!n.ok) atomicOr(A.err, 1);
+          const double iH = 1.0 / (lam[4] * A.op.h[j]);
+#pragma unroll
+          for (int i = 0; i < D; ++i) jvp_flux<D, double>(n, G, i, lm, in[1 + i]);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            in[0][c] = lm[c] * iH;
+            in[1][c] *= iH;
+            in[2][c] *= iH;
+            in[3][c] = n.w[c];
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) in[q][c] = 0.0;
+#pragma unroll
+          for (int q = 0; q < 5; ++q) lam[q] = 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) B[q][j][e * NC + c] = in[q][c];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) L[q][j][e] = lam[q];
+      }
+      double sf[2][MT][KS];
+#pragma unroll
+      for (int l = 0; l < 2; ++l)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) {
+            const int m = mt * 16 + col, k = 4 * ks + kr;
+            sf[l][mt][ks] = (m < NP && k < NP) ? A.op.S[(l * NP + m) * NP + k] : 0.0;
+          }
+      wave_lds_sync();
+      // Three families of column groups (input slot q = 0 mu, 1..2 s_i, 3 w):
+      //   mu: S_l mu, S_l (Lambda_0l mu), S_l (Lambda_1l mu) -> Z_0, Z_1 (= 2 K_i mu)
+      //   s : S_l s_0, S_l s_1, S_l (Lambda_0l s_0 + Lambda_1l s_1) -> V_s (= 2 sum_i K_i s_i)
+      //   w : S_l w, S_l (Lambda_0l w), S_l (Lambda_1l w) -> X_0, X_1 (= 2 K_i w)
+#pragma unroll
+      for (int t = 0; t < CT; ++t) {
+        const int cc = t * 16 + col, el = t * 4 + (col >> 2);
+#pragma unroll
+        for (int fam = 0; fam < 3; ++fam) {
+          V4 o0[MT], o1[MT];
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) o0[mt] = o1[mt] = V4{0, 0, 0, 0};
+#pragma unroll
+          for (int l = 0; l < 2; ++l)
+#pragma unroll
+            for (int g = 0; g < 3; ++g) {
+              V4 acc[MT];
+#pragma unroll
+              for (int mt = 0; mt < MT; ++mt) acc[mt] = V4{0, 0, 0, 0};
+#pragma unroll
+              for (int ks = 0; ks < KS; ++ks) {
+                const int k = 4 * ks + kr;
+                const bool in = 4 * ks + 3 < NP || k < NP;
+                const double la = in ? L[l][k][el] : 0.0, lb = in ? L[2 + l][k][el] : 0.0;
+                double b;
+                if (fam == 1) {
+                  if (g == 0) b = B[1][k][cc];
+                  else if (g == 1) b = B[2][k][cc];
+                  else b = la * B[1][k][cc] + lb * B[2][k][cc];
+                } else {
+                  const double v = B[fam == 0 ? 0 : 3][k][cc];
+                  b = g == 0 ? v : (g == 1 ? la * v : lb * v);
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt] = MF<double>::mma(sf[l][mt][ks], b, acc[mt]);
+              }
+#pragma unroll
+              for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int ii = 0; ii < 4; ++ii) {
+                  const int row = mt * 16 + MF<double>::row(kr, ii);
+                  if (row < NP) {
+                    const double v = acc[mt][ii];
+                    if (fam == 1) {
+                      if (g == 0) o0[mt][ii] += L[l][row][el] * v;
+                      else if (g == 1) o0[mt][ii] += L[2 + l][row][el] * v;
+                      else o0[mt][ii] += v;
+                    } else if (g == 0) {
+                      o0[mt][ii] += L[l][row][el] * v;
+                      o1[mt][ii] += L[2 + l][row][el] * v;
+                    } else if (g == 1) {
+                      o0[mt][ii] += v;
+                    } else {
+                      o1[mt][ii] += v;
+                    }
+                  }
+                }
+              __builtin_amdgcn_sched_barrier(0);
+            }
+          // the family's inputs are no longer read: store its outputs
+          wave_lds_sync();
+          const int s0 = fam == 0 ? 4 : (fam == 1 ? 1 : 2), s1 = fam == 0 ? 0 : 3;
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii) {
+              const int row = mt * 16 + MF<double>::row(kr, ii);
+              if (row < NP) {
+                B[s0][row][cc] = o0[mt][ii];
+                if (fam != 1) B[s1][row][cc] = o1[mt][ii];
+              }
+            }
+        }
+      }
+      wave_lds_sync();
+      // per node: volume, non-conservative and facet parts of ubar
+      for (int x = lane; x < NPW; x += 64) {
+        const int e = x / NP, j = x % NP, eg = e0 + e;
+        if (eg >= A.n_elem) continue;
         const int uo = A.uoff[eg];
         double uu[NC], lm[NC];
 #pragma unroll
@@ -359,209 +489,134 @@ __global__ __launch_bounds__(kT) void k_vjp2(KArgs<double> A) {
         }
         Node<D, double> n;
         node_from_u<D, double>(uu, G, n);
-        if (!n.ok) atomicOr(A.err, 1);
-        const double iH = 1.0 / (lam[4] * A.op.h[j]);
+        const double E0 = A.op.E[j], E1 = A.op.E[NP + j];
+        double ak[D];
+        ak[0] = L[0][j][e] * E0 + L[1][j][e] * E1;
+        ak[1] = L[2][j][e] * E0 + L[3][j][e] * E1;
+        const double H = L[4][j][e] * A.op.h[j], iH = 1.0 / H;
+        double ub[NC];
 #pragma unroll
-        for (int i = 0; i < D; ++i) jvp_flux<D, double>(n, G, i, lm, in[1 + i]);
+        for (int c = 0; c < NC; ++c) ub[c] = 0.0;
+        // volume: sum_i A_i^T z_i, z_i = (1 - c_b)/2 Z_i + (1 + c_b)/2 a_i mu
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          in[0][c] = lm[c] * iH;
-          in[1][c] *= iH;
-          in[2][c] *= iH;
-          in[3][c] = n.w[c];
+        for (int i = 0; i < D; ++i) {
+          double zi[NC], o[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) zi[c] = hz * B[i == 0 ? 4 : 0][j][e * NC + c] + he * ak[i] * lm[c] * iH;
+          flux_jac_T<D, double>(n, G, uu[NC - 1], i, zi, o);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) ub[c] += o[c];
         }
-      } else {
+        // non-conservative: y = sum_i Q_xi^T s_i + sum_i d/de A~_i(w + e g_i) lambda,
+        // sum_i Q_xi^T s_i = -V_s/2 + 1/2 sum_i a_i s_i,  g_i = H^-1 (X_i + a_i w)/2
+        double y[NC], s[D][NC];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int i = 0; i < D; ++i) jvp_flux<D, double>(n, G, i, lm, s[i]);
 #pragma unroll
-          for (int c = 0; c < NC; ++c) in[q][c] = 0.0;
+        for (int c = 0; c < NC; ++c) y[c] = -0.5 * B[1][j][e * NC + c] + 0.5 * iH * (ak[0] * s[0][c] + ak[1] * s[1][c]);
 #pragma unroll
-        for (int q = 0; q < 5; ++q) lam[q] = 0.0;
-      }
+        for (int i = 0; i < D; ++i) {
+          double gi[NC], du[NC];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+          for (int c = 0; c < NC; ++c) gi[c] = 0.5 * iH * (B[2 + i][j][e * NC + c] + ak[i] * n.w[c]);
+          dU_from_dW<D, double>(n, G, gi, du);
+          Dual<double> xd[NC], lmd[NC], hv[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) B[q][j][e * NC + c] = in[q][c];
-#pragma unroll
-      for (int q = 0; q < 5; ++q) L[q][j][e] = lam[q];
-    }
-    double sf[2][MT][KS];
-#pragma unroll
-    for (int l = 0; l < 2; ++l)
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          const int m = mt * 16 + col, k = 4 * ks + kr;
-          sf[l][mt][ks] = (m < NP && k < NP) ? A.op.S[(l * NP + m) * NP + k] : 0.0;
-        }
-    wave_lds_sync();
-    // Three families of column groups (input slot q = 0 mu, 1..2 s_i, 3 w):
-    //   mu: S_l mu, S_l (Lambda_0l mu), S_l (Lambda_1l mu) -> Z_0, Z_1 (= 2 K_i mu)
-    //   s : S_l s_0, S_l s_1, S_l (Lambda_0l s_0 + Lambda_1l s_1) -> V_s (= 2 sum_i K_i s_i)
-    //   w : S_l w, S_l (Lambda_0l w), S_l (Lambda_1l w) -> X_0, X_1 (= 2 K_i w)
-#pragma unroll
-    for (int t = 0; t < CT; ++t) {
-      const int cc = t * 16 + col, el = t * 4 + (col >> 2);
-#pragma unroll
-      for (int fam = 0; fam < 3; ++fam) {
-        V4 o0[MT], o1[MT];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) o0[mt] = o1[mt] = V4{0, 0, 0, 0};
-#pragma unroll
-        for (int l = 0; l < 2; ++l)
-#pragma unroll
-          for (int g = 0; g < 3; ++g) {
-            V4 acc[MT];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) acc[mt] = V4{0, 0, 0, 0};
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-              const int k = 4 * ks + kr;
-              const bool in = 4 * ks + 3 < NP || k < NP;
-              const double la = in ? L[l][k][el] : 0.0, lb = in ? L[2 + l][k][el] : 0.0;
-              double b;
-              if (fam == 1) {
-                if (g == 0) b = B[1][k][cc];
-                else if (g == 1) b = B[2][k][cc];
-                else b = la * B[1][k][cc] + lb * B[2][k][cc];
-              } else {
-                const double v = B[fam == 0 ? 0 : 3][k][cc];
-                b = g == 0 ? v : (g == 1 ? la * v : lb * v);
-              }
-#pragma unroll
-              for (int mt = 0; mt < MT; ++mt) acc[mt] = MF<double>::mma(sf[l][mt][ks], b, acc[mt]);
-            }
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-              for (int ii = 0; ii < 4; ++ii) {
-                const int row = mt * 16 + MF<double>::row(kr, ii);
-                if (row < NP) {
-                  const double v = acc[mt][ii];
-                  if (fam == 1) {
-                    if (g == 0) o0[mt][ii] += L[l][row][el] * v;
-                    else if (g == 1) o0[mt][ii] += L[2 + l][row][el] * v;
-                    else o0[mt][ii] += v;
-                  } else if (g == 0) {
-                    o0[mt][ii] += L[l][row][el] * v;
-                    o1[mt][ii] += L[2 + l][row][el] * v;
-                  } else if (g == 1) {
-                    o0[mt][ii] += v;
-                  } else {
-                    o1[mt][ii] += v;
-                  }
-                }
-              }
-            __builtin_amdgcn_sched_barrier(0);
+          for (int c = 0; c < NC; ++c) {
+            xd[c] = Dual<double>(uu[c], du[c]);
+            lmd[c] = Dual<double>(lm[c]);
           }
-        // the family's inputs are no longer read: store its outputs
-        wave_lds_sync();
-        const int s0 = fam == 0 ? 4 : (fam == 1 ? 1 : 2), s1 = fam == 0 ? 0 : 3;
+          Node<D, Dual<double>> nd;
+          node_from_u<D, Dual<double>>(xd, GD, nd);
+          jvp_flux<D, Dual<double>>(nd, GD, i, lmd, hv);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+          for (int c = 0; c < NC; ++c) y[c] += hv[c].d;
+        }
+        double wy[NC];
+        dWdU_apply<D>(uu, y, GD, wy);
 #pragma unroll
-          for (int ii = 0; ii < 4; ++ii) {
-            const int row = mt * 16 + MF<double>::row(kr, ii);
-            if (row < NP) {
-              B[s0][row][cc] = o0[mt][ii];
-              if (fam != 1) B[s1][row][cc] = o1[mt][ii];
-            }
+        for (int c = 0; c < NC; ++c) ub[c] -= cb * wy[c];
+        // facet SATs: own term and the neighbour's term at this node
+        if (j < NFN) {
+          const int off = A.nbr[(size_t)eg * NFN + j];
+          double uv[NC], lv[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            uv[c] = A.u[off + c * NP];
+            lv[c] = A.lam[off + c * NP];
           }
-      }
-    }
-    wave_lds_sync();
-    // per node: volume, non-conservative and facet parts of ubar
-    for (int x = lane; x < NPW; x += 64) {
-      const int e = x / NP, j = x % NP, eg = e0 + e;
-      if (eg >= A.n_elem) continue;
-      const int uo = A.uoff[eg];
-      double uu[NC], lm[NC];
+          const int q = A.nbrq[(size_t)eg * NFN + j];
+          const int vk = q / NFN, nn = q % NFN;
+          double lv5[5];
+          metrics(vk, nn, lv5);
+          const double F0 = A.op.E[nn], F1 = A.op.E[NP + nn];
+          double av[D];
+          av[0] = lv5[0] * F0 + lv5[1] * F1;
+          av[1] = lv5[2] * F0 + lv5[3] * F1;
+          const double Hv = A.Hn[(size_t)vk * NP + nn];
+          double g1[NC], g2[NC];
+          facet_grad<D>(uu, uv, ak, lm, GD, A.diss != 0, 0, g1);
+          facet_grad<D>(uv, uu, av, lv, GD, A.diss != 0, 1, g2);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        uu[c] = A.u[uo + c * NP + j];
-        lm[c] = A.lam[uo + c * NP + j];
-      }
-      Node<D, double> n;
-      node_from_u<D, double>(uu, G, n);
-      const double E0 = A.op.E[j], E1 = A.op.E[NP + j];
-      double ak[D];
-      ak[0] = L[0][j][e] * E0 + L[1][j][e] * E1;
-      ak[1] = L[2][j][e] * E0 + L[3][j][e] * E1;
-      const double H = L[4][j][e] * A.op.h[j], iH = 1.0 / H;
-      double ub[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) ub[c] = 0.0;
-      // volume: sum_i A_i^T z_i, z_i = (1 - c_b)/2 Z_i + (1 + c_b)/2 a_i mu
-#pragma unroll
-      for (int i = 0; i < D; ++i) {
-        double zi[NC], o[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) zi[c] = hz * B[i == 0 ? 4 : 0][j][e * NC + c] + he * ak[i] * lm[c] * iH;
-        flux_jac_T<D, double>(n, G, uu[NC - 1], i, zi, o);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) ub[c] += o[c];
-      }
-      // non-conservative: y = sum_i Q_xi^T s_i + sum_i d/de A~_i(w + e g_i) lambda,
-      // sum_i Q_xi^T s_i = -V_s/2 + 1/2 sum_i a_i s_i,  g_i = H^-1 (X_i + a_i w)/2
-      double y[NC], s[D][NC];
-#pragma unroll
-      for (int i = 0; i < D; ++i) jvp_flux<D, double>(n, G, i, lm, s[i]);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) y[c] = -0.5 * B[1][j][e * NC + c] + 0.5 * iH * (ak[0] * s[0][c] + ak[1] * s[1][c]);
-#pragma unroll
-      for (int i = 0; i < D; ++i) {
-        double gi[NC], du[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) gi[c] = 0.5 * iH * (B[2 + i][j][e * NC + c] + ak[i] * n.w[c]);
-        dU_from_dW<D, double>(n, G, gi, du);
-        Dual<double> xd[NC], lmd[NC], hv[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          xd[c] = Dual<double>(uu[c], du[c]);
-          lmd[c] = Dual<double>(lm[c]);
+          for (int c = 0; c < NC; ++c) ub[c] -= g1[c] * iH + g2[c] / Hv;
         }
-        Node<D, Dual<double>> nd;
-        node_from_u<D, Dual<double>>(xd, GD, nd);
-        jvp_flux<D, Dual<double>>(nd, GD, i, lmd, hv);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) y[c] += hv[c].d;
+        for (int c = 0; c < NC; ++c) A.ubar[uo + c * NP + j] = ub[c];
       }
-      double wy[NC];
-      dWdU_apply<D>(uu, y, GD, wy);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) ub[c] -= cb * wy[c];
-      // facet SATs: own term and the neighbour's term at this node
-      if (j < NFN) {
-        const int off = A.nbr[(size_t)eg * NFN + j];
-        double uv[NC], lv[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          uv[c] = A.u[off + c * NP];
-          lv[c] = A.lam[off + c * NP];
-        }
-        const int q = A.nbrq[(size_t)eg * NFN + j];
-        const int vk = q / NFN, nn = q % NFN;
-        double lv5[5];
-        metrics(vk, nn, lv5);
-        const double F0 = A.op.E[nn], F1 = A.op.E[NP + nn];
-        double av[D];
-        av[0] = lv5[0] * F0 + lv5[1] * F1;
-        av[1] = lv5[2] * F0 + lv5[3] * F1;
-        const double Hv = A.Hn[(size_t)vk * NP + nn];
-        double g1[NC], g2[NC];
-        facet_grad<D>(uu, uv, ak, lm, GD, A.diss != 0, 0, g1);
-        facet_grad<D>(uv, uu, av, lv, GD, A.diss != 0, 1, g2);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) ub[c] -= g1[c] * iH + g2[c] / Hv;
-      }
-#pragma unroll
-      for (int c = 0; c < NC; ++c) A.ubar[uo + c * NP + j] = ub[c];
-    }
+  }
+};
+
+template <int P>
+__global__ __launch_bounds__(kT) void k_vjp2(KArgs<double> A) {
+  typedef Vjp2<P> K;
+  __shared__ typename K::Lds lds[kW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ngroups = (A.n_elem + K::EW - 1) / K::EW;
+  for (int grp = blockIdx.x * kW + wave; grp < ngroups; grp += gridDim.x * kW) K::group(A, lds[wave], grp, lane);
+}
+
+constexpr size_t vjp2_lds_max() {
+  size_t m = sizeof(Vjp2<1>::Lds);
+  m = m > sizeof(Vjp2<2>::Lds) ? m : sizeof(Vjp2<2>::Lds);
+  m = m > sizeof(Vjp2<3>::Lds) ? m : sizeof(Vjp2<3>::Lds);
+  m = m > sizeof(Vjp2<4>::Lds) ? m : sizeof(Vjp2<4>::Lds);
+  return m;
+}
+
+// every degree class of a 2D mesh in one persistent launch
+__global__ __launch_bounds__(kT) void k_vjp2_batch(Batch2<double> Bt) {
+  constexpr size_t LW = (vjp2_lds_max() + 15) / 16 * 16;
+  __shared__ __align__(16) unsigned char raw[kW * LW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  void *mine = raw + wave * LW;
+  for (int g = blockIdx.x * kW + wave; g < Bt.g0[4]; g += gridDim.x * kW) {
+    if (g < Bt.g0[1])
+      Vjp2<1>::group(Bt.c[0], *(Vjp2<1>::Lds *)mine, g, lane);
+    else if (g < Bt.g0[2])
+      Vjp2<2>::group(Bt.c[1], *(Vjp2<2>::Lds *)mine, g - Bt.g0[1], lane);
+    else if (g < Bt.g0[3])
+      Vjp2<3>::group(Bt.c[2], *(Vjp2<3>::Lds *)mine, g - Bt.g0[2], lane);
+    else
+      Vjp2<4>::group(Bt.c[3], *(Vjp2<4>::Lds *)mine, g - Bt.g0[3], lane);
   }
 }
 
 }  // namespace
+
+hipError_t launch_vjp2_batch(const KArgs<double> *const cls[4], hipStream_t s) {
+  Batch2<double> Bt{};
+  Bt.g0[0] = 0;
+  for (int q = 0; q < 4; ++q) {
+    const int ew = 4 * (q + 1 <= 2 ? 2 : 1);
+    const int ne = cls[q] ? cls[q]->n_elem : 0;
+    if (cls[q]) Bt.c[q] = *cls[q];
+    Bt.g0[q + 1] = Bt.g0[q] + (ne + ew - 1) / ew;
+  }
+  if (Bt.g0[4] == 0) return hipSuccess;
+  const dim3 grid(std::min((Bt.g0[4] + kW - 1) / kW, 2048));
+  hipLaunchKernelGGL(k_vjp2_batch, grid, dim3(kT), 0, s, Bt);
+  return hipGetLastError();
+}
 
 hipError_t launch_vjp(int dim, int p, const KArgs<double> &A, hipStream_t s) {
   dim3 block(kT);

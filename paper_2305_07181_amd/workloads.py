@@ -246,3 +246,38 @@ def batch_problem_specs(n_problems: int = 48, seed: int = 0):
         ny = max(2, int(round(ne / (2 * nx))))
         out.append(dict(p=p, nx=nx, ny=ny, seed=1000 + b))
     return out
+
+
+def batch_mesh(specs, warp: float = 0.0):
+    """The problems of ``batch_problem_specs`` as one mesh description: each
+    an nx x ny periodic grid of triangles on [0,1]^2 with its own vertices.
+    Returns (desc, degree[n_elem], problem_off[n_problems + 1])."""
+    verts, elems, geoms, degs, off = [], [], [], [], [0]
+    nv = 0
+    for sp in specs:
+        d = periodic_tri_mesh(sp["nx"], sp["ny"], 1.0, 1.0, warp)
+        verts.append(d["vert_xyz"])
+        elems.append(d["elem_vert"] + nv)
+        nv += len(d["vert_xyz"])
+        if warp != 0.0:
+            geoms.append(d["geom_nodes"])
+        degs.append(np.full(len(d["elem_vert"]), sp["p"], dtype=np.int32))
+        off.append(off[-1] + len(d["elem_vert"]))
+    desc = dict(dim=2, vert_xyz=np.concatenate(verts), elem_vert=np.concatenate(elems).astype(np.int32),
+                period=np.array([1.0, 1.0]), p_geom=2 if warp != 0.0 else 1,
+                geom_nodes=np.concatenate(geoms) if warp != 0.0 else None)
+    return desc, np.concatenate(degs), np.array(off, dtype=np.int32)
+
+
+def sub_mesh(desc: dict, lo: int, hi: int) -> dict:
+    """Elements [lo, hi) of a batched description as a mesh of their own."""
+    ev = desc["elem_vert"][lo:hi]
+    used = np.unique(ev)
+    remap = np.full(len(desc["vert_xyz"]), -1, dtype=np.int64)
+    remap[used] = np.arange(len(used))
+    out = dict(desc)
+    out["vert_xyz"] = desc["vert_xyz"][used]
+    out["elem_vert"] = remap[ev].astype(np.int32)
+    if desc.get("geom_nodes") is not None:
+        out["geom_nodes"] = desc["geom_nodes"][lo:hi]
+    return out
