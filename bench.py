@@ -7,9 +7,11 @@ the dominant kernel and the CPU oracle as a reported baseline.
 One timed step = one FP64 entropy-split residual evaluation for each degree
 p = 1..4 on the curved periodic 128x128x2 = 32768-triangle mesh (isentropic
 vortex state, inputs resident in HBM).  value = sum_p n_elem n_p(p) / step
-time.  Extra fields give per-kernel throughput for FP32 and the Hadamard
-form, the 196608-tetrahedron Taylor-Green case (p = 2, 3), and the CPU oracle
-timed on a bounded sample of the same workload.
+time.  Extra fields give per-kernel throughput for FP32, the Hadamard form
+and the VJP (VJP/forward time ratio), the 196608-tetrahedron Taylor-Green
+case (p = 2, 3), the 48-problem mixed-degree batch (one launch each for the
+forward residual and the VJP), and the CPU oracle timed on a bounded sample
+of the same workload.
 """
 from __future__ import annotations
 
@@ -84,6 +86,40 @@ def _time_calls(fn, reps, warm):
     torch.cuda.synchronize()
     t = np.array([a.elapsed_time(b) for a, b in ev]) * 1e-3
     return float(np.median(t)), float(np.mean(t))
+
+
+def batch_rows(args):
+    """48 independent periodic problems on [0,1]^2, p ~ U{1..4}, n_e ~ logU[256,
+    16384] (seed 0), random smooth states (seed 1000+b): one batched forward
+    launch and one batched VJP launch (lambda ~ N(0,1))."""
+    import torch
+    from paper_2305_07181_amd import sbp, workloads as wl
+    specs = wl.batch_problem_specs(48, 0)
+    desc, deg, off = wl.batch_mesh(specs)
+    mesh = sbp.Mesh(desc, deg, problem_off=off)
+    x = mesh.node_coords().cpu().numpy()
+    u = np.zeros(int(mesh.n_nodes * mesh.n_c))
+    for b, sp in enumerate(specs):
+        n_p = int(mesh.elem_np[off[b]])
+        e0, e1 = int(off[b]), int(off[b + 1])
+        xs = x[int(mesh.node_off[e0]) * 2:int(mesh.node_off[e1]) * 2].reshape(e1 - e0, 2, n_p)
+        rho, V, p = wl.random_smooth_state(np.moveaxis(xs, 1, 0), seed=1000 + b, L=1.0, K=4, amp=0.1, vamp=0.3)
+        ub = np.moveaxis(wl.conservative(rho, V, p), 0, 1)
+        u[int(mesh.node_off[e0]) * 4:int(mesh.node_off[e1]) * 4] = ub.ravel()
+    ud = torch.from_numpy(u).cuda()
+    lam = torch.randn(ud.shape, dtype=torch.float64, device="cuda",
+                      generator=torch.Generator(device="cuda").manual_seed(2000))
+    r = torch.empty_like(ud)
+    ubar = torch.empty_like(ud)
+    fmed, _ = _time_calls(lambda: mesh.residual(ud, r), max(5, args.steps // 2), 2)
+    bmed, _ = _time_calls(lambda: mesh.vjp(ud, lam, ubar), max(5, args.steps // 2), 2)
+    mesh.check_device()
+    ndof = int(mesh.n_nodes)
+    mesh.close()
+    return dict(n_problems=48, n_elem=int(off[-1]), n_dof_nodes=ndof,
+                degrees={str(q): int(sum(1 for s in specs if s["p"] == q)) for q in (1, 2, 3, 4)},
+                forward_ms=fmed * 1e3, vjp_ms=bmed * 1e3, forward_elem_dof_per_s=ndof / fmed,
+                vjp_elem_dof_per_s=ndof / bmed, vjp_over_forward=bmed / fmed)
 
 
 def cpu_baseline(desc, ps, budget_s=20.0):
@@ -217,6 +253,12 @@ def main():
                 if msh is not meshes[p]:
                     msh.close()
             row["hadamard_over_split"] = row["fp64_hadamard"]["ms"] / row["fp64_split"]["ms"]
+            lam = torch.randn(states[p].shape, dtype=torch.float64, device="cuda",
+                              generator=torch.Generator(device="cuda").manual_seed(2000 + p))
+            ub = torch.empty_like(states[p])
+            med, _ = _time_calls(lambda: meshes[p].vjp(states[p], lam, ub), max(5, args.steps // 2), 2)
+            row["fp64_vjp"] = dict(ms=med * 1e3, elem_dof_per_s=ne * n_p[p] / med)
+            row["vjp_over_forward"] = row["fp64_vjp"]["ms"] / row["fp64_split"]["ms"]
             extras[f"tri_p{p}"] = row
         # 3D Taylor-Green, 32^3 x 6 = 196608 tetrahedra, matrix dissipation on
         desc3 = wl.tgv_mesh(32)
@@ -239,10 +281,22 @@ def main():
                     msh.close()
             row["hadamard_over_split"] = row["fp64_hadamard"]["ms"] / row["fp64_split"]["ms"]
             row["fp32_speedup"] = row["fp64_split"]["ms"] / row["fp32_split"]["ms"]
+            lam3 = torch.randn(u3.shape, dtype=torch.float64, device="cuda",
+                               generator=torch.Generator(device="cuda").manual_seed(2100 + p))
+            ub3 = torch.empty_like(u3)
+            med, _ = _time_calls(lambda: m64.vjp(u3, lam3, ub3), 5, 2)
+            row["fp64_vjp"] = dict(ms=med * 1e3, elem_dof_per_s=ne3 * np3 / med)
+            row["vjp_over_forward"] = row["fp64_vjp"]["ms"] / row["fp64_split"]["ms"]
             extras[f"tet_p{p}_tgv_196608"] = row
             m64.close()
-            del u3
-        extras["vjp_over_forward"] = None
+            del u3, lam3, ub3
+        extras["batch48"] = batch_rows(args)
+        fw = sum(extras[f"tri_p{p}"]["fp64_split"]["ms"] for p in ps)
+        bw = sum(extras[f"tri_p{p}"]["fp64_vjp"]["ms"] for p in ps)
+        extras["vjp_over_forward"] = dict(
+            headline=bw / fw, batch48=extras["batch48"]["vjp_over_forward"],
+            note="FP64 VJP time / FP64 entropy-split residual time; headline = sum over p = 1..4 "
+                 "on the 32768-triangle mesh")
         out["breakdown"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(desc, ps)
