@@ -160,188 +160,281 @@ __device__ __forceinline__ void finish_node(const KArgs<T> &A, int eg, int i, co
 }
 
 // ---------------------------------------------------------------------------
-// Entropy split, 3D affine tetrahedra.
-//   vol = sum_l M_l fhat_l, fhat_l = sum_i Lambda_il f^(i)     (one GEMM, K = 3 NP)
-//   D_xi w = sum_l (Lambda_il / J) D_xi_l w                   (one GEMM, M = 3 NP)
+// Entropy split, 3D affine tetrahedra.  With Q_l = S_l + E_l/2 (S_l skew,
+// E_l diagonal) every contraction uses the skew reference operators:
+//   vol    = sum_l M_l fhat_l = (c_b - 1) sum_l S_l fhat_l + (c_b + 1)/2 sum_l E_l fhat_l,
+//            fhat_l = sum_i Lambda_il f^(i)
+//   D_xi w = J^-1 sum_l Lambda_il h^-1 (S_l w + E_l w / 2)
 // With VISC (Navier-Stokes, Baumann-Oden SATs, Sec. 5):
 //   sum_i D_xi F^V(i) - 1/2 H^-1 sum_j D_xj^T y_j
-//     = H^-1 [ sum_l Q_l FVhat_l - 1/2 sum_l Q_l^T (H^-1 yhat_l) ]   (one GEMM, K = 6 NP)
-//   with FVhat_l = sum_i Lambda_il F^V(i), yhat_l = sum_j Lambda_jl y_j,
+//     = H^-1 [ sum_l Q_l FVhat_l + sum_l Q_l^T y'_l ]
+//     = H^-1 [ sum_l S_l (FVhat_l - y'_l) + 1/2 sum_l E_l (FVhat_l + y'_l) ]
+//   with FVhat_l = sum_i Lambda_il F^V(i), y'_l = -1/2 H^-1 sum_j Lambda_jl y_j,
 //   y_j = sum_i K~_ij^T (B n_i (w_k - w_v)) at facet nodes, plus the facet
 //   flux jump -1/2 H^-1 (q_k + q_v), q = B n . F^V from the pre-pass.
+//
+// A workgroup takes a tile of CT column tiles (3 elements x 5 components per
+// 16 columns); wave w owns row tile mt = w % MT of the operators (its A
+// fragments of S_1, S_2, S_3 stay in registers for the whole persistent
+// launch) and the column tiles t = w / MT (mod 4 / MT).
+template <int P, typename T> struct Wave3;
+template <> struct Wave3<1, double> { static constexpr int CT = 4; };
+template <> struct Wave3<2, double> { static constexpr int CT = 2; };
+template <> struct Wave3<3, double> { static constexpr int CT = 1; };
+template <> struct Wave3<1, float> { static constexpr int CT = 8; };
+template <> struct Wave3<2, float> { static constexpr int CT = 4; };
+template <> struct Wave3<3, float> { static constexpr int CT = 2; };
+
 template <int P, typename T, bool VISC>
 __global__ __launch_bounds__(kThreads) void k_split3(KArgs<T> A) {
   constexpr int D = 3, NC = 5, NFAC = 4;
   constexpr int NP = Shape<3, P>::NP, NF = Shape<3, P>::NF, NFN = NFAC * NF;
-  constexpr int EB = Tile<3, P, T, VISC ? 2 : 0>::EB;
-  constexpr int NCOL = EB * NC, NCP = ru(NCOL, 16);
-  constexpr int K1P = ru(3 * NP, 4), M1P = ru(NP, 16);
-  constexpr int K2P = ru(NP, 4), M2P = ru(3 * NP, 16);
-  constexpr int K3P = VISC ? ru(6 * NP, 4) : 4;
-  constexpr int KU = K1P > K3P ? K1P : K3P;
-  __shared__ T U1[KU * NCP];   // B1, then (viscous) B3
-  __shared__ T B2[K2P * NCP];
-  __shared__ T C1[M1P * NCP];
-  __shared__ T C2[M2P * NCP];
-  __shared__ T C3[VISC ? M1P * NCP : 16];
-  __shared__ T us[EB * NC * NP];
-  __shared__ T gs[EB * 10];
-  __shared__ T hs[NP];
-  __shared__ T Es[3 * NP];
-  T *B1 = U1;
-  const int tid = threadIdx.x;
-  const int e0 = blockIdx.x * EB;
-  const int ne = min(EB, A.n_elem - e0);
-  for (int x = tid; x < EB * 10; x += kThreads) {
-    const int e = x / 10;
-    gs[x] = e < ne ? (T)A.geo[(size_t)(e0 + e) * 10 + x % 10] : (T)0;
-  }
-  for (int x = tid; x < NP; x += kThreads) hs[x] = A.op.h[x];
-  for (int x = tid; x < 3 * NP; x += kThreads) Es[x] = A.op.E[x];
-  for (int x = tid; x < ne * NC * NP; x += kThreads) {
-    const int e = x / (NC * NP);
-    us[x] = (T)A.u[A.uoff[e0 + e] + x % (NC * NP)];
-  }
-  for (int x = tid; x < K1P * NCP; x += kThreads) B1[x] = (T)0;
-  for (int x = tid; x < K2P * NCP; x += kThreads) B2[x] = (T)0;
-  __syncthreads();
-  // pointwise: contravariant fluxes and entropy variables; each thread keeps
-  // the node states it owns in registers for the later phases
+  constexpr int KP = ru(NP, 4), MP = ru(NP, 16), MT = MP / 16, KS = KP / 4;
+  constexpr int WPM = kWaves / MT;  // waves per row tile
+  constexpr int CT = Wave3<P, T>::CT, EB = 3 * CT, NCOL = 16 * CT;
+  constexpr int NG = VISC ? 5 : 4;  // output slots: S fhat, S_l w (3), [S z]
   constexpr int NPT = (EB * NP + kThreads - 1) / kThreads;
-  Node<D, T> nodes[NPT];
+  static_assert(CT % WPM == 0, "column tiles must split evenly over the waves of a row tile");
+  typedef typename MF<T>::v4 V4;
+  constexpr int MR = KP > MP ? KP : MP;
+  // inputs [fhat_1 fhat_2 fhat_3 w][node < KP][column] (VISC: later z_l in slots 0..2);
+  // without VISC the outputs reuse this buffer (MR rows per slot)
+  __shared__ T Bi[4][MR][NCOL];
+  // outputs [S fhat | S_1 w | S_2 w | S_3 w | S z][row][column]
+  __shared__ T Bo[VISC ? NG : 1][VISC ? MP : 1][VISC ? NCOL : 1];
+  __shared__ T gs[EB][10];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, kr = lane >> 4;
+  const int mt = wave % MT;
+  T(*Out)[MP][NCOL] = VISC ? reinterpret_cast<T(*)[MP][NCOL]>(&Bo[0][0][0])
+                           : reinterpret_cast<T(*)[MP][NCOL]>(&Bi[0][0][0]);
+  // A fragments of S_1, S_2, S_3 for row tile mt: lane holds S_l[mt*16 + col][4 ks + kr]
+  T sf[3][KS];
 #pragma unroll
-  for (int kq = 0; kq < NPT; ++kq) {
-    const int x = tid + kq * kThreads;
-    if (x >= ne * NP) break;
-    const int e = x / NP, j = x % NP;
-    T uu[NC];
+  for (int l = 0; l < 3; ++l)
 #pragma unroll
-    for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + j];
-    Node<D, T> &n = nodes[kq];
-    node_from_u<D, T>(uu, A.G, n);
-    if (!n.ok) atomicOr(A.err, 1);
-    T f[D][NC];
-#pragma unroll
-    for (int i = 0; i < D; ++i) flux_i<D, T>(n, uu[NC - 1], i, f[i]);
-    const T *Lam = gs + e * 10;
-#pragma unroll
-    for (int l = 0; l < D; ++l)
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-        B1[(l * NP + j) * NCP + e * NC + c] = Lam[0 * 3 + l] * f[0][c] + Lam[1 * 3 + l] * f[1][c] + Lam[2 * 3 + l] * f[2][c];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) B2[j * NCP + e * NC + c] = n.w[c];
-  }
-  __syncthreads();
-  gemm_AtB<T, M1P, K1P, NCP>(A.op.At1, B1, C1);
-  gemm_AtB<T, M2P, K2P, NCP>(A.op.At2, B2, C2);
-  if constexpr (VISC) {
-    T *B3 = U1;
-    for (int x = tid; x < K3P * NCP; x += kThreads) B3[x] = (T)0;
+    for (int ks = 0; ks < KS; ++ks) {
+      const int m = mt * 16 + col, k = 4 * ks + kr;
+      sf[l][ks] = (m < NP && k < NP) ? A.op.S[(l * NP + m) * NP + k] : (T)0;
+    }
+  const T cb = A.G.cb;
+  const T hv = cb - (T)1, he = (T)0.5 * (cb + (T)1);
+  double ent = 0.0;
+  const int ntiles = (A.n_elem + EB - 1) / EB;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int e0 = tile * EB;
+    const int ne = min(EB, A.n_elem - e0);
     __syncthreads();
+    for (int x = tid; x < EB * 10; x += kThreads) {
+      const int e = x / 10;
+      gs[e][x % 10] = e < ne ? (T)A.geo[(size_t)(e0 + e) * 10 + x % 10] : (T)0;
+    }
+    // zero the inputs (padding rows and columns, ragged elements)
+    for (int x = tid; x < 4 * MR * NCOL; x += kThreads) (&Bi[0][0][0])[x] = (T)0;
+    __syncthreads();
+    // pointwise: contravariant fluxes and entropy variables; node states kept
+    // in registers for the later phases
+    Node<D, T> nodes[NPT];
+#pragma unroll
+    for (int kq = 0; kq < NPT; ++kq) {
+      const int x = tid + kq * kThreads;
+      if (x >= ne * NP) break;
+      const int e = x / NP, j = x % NP;
+      const int cc = (e / 3) * 16 + (e % 3) * NC;
+      const int uo = A.uoff[e0 + e];
+      T uu[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) uu[c] = (T)A.u[uo + c * NP + j];
+      Node<D, T> &n = nodes[kq];
+      node_from_u<D, T>(uu, A.G, n);
+      if (!n.ok) atomicOr(A.err, 1);
+      T f[D][NC];
+#pragma unroll
+      for (int i = 0; i < D; ++i) flux_i<D, T>(n, uu[NC - 1], i, f[i]);
+      const T *Lam = gs[e];
+#pragma unroll
+      for (int l = 0; l < D; ++l)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          Bi[l][j][cc + c] = Lam[0 * 3 + l] * f[0][c] + Lam[1 * 3 + l] * f[1][c] + Lam[2 * 3 + l] * f[2][c];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) Bi[3][j][cc + c] = n.w[c];
+    }
+    __syncthreads();
+    // skew contractions: S fhat (K = 3 KP) and S_l w (l = 1..3)
+    {
+      V4 acc[CT / WPM][4];
+#pragma unroll
+      for (int tt = 0; tt < CT / WPM; ++tt)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) acc[tt][g] = V4{0, 0, 0, 0};
+#pragma unroll
+      for (int tt = 0; tt < CT / WPM; ++tt) {
+        const int cc = (wave / MT + tt * WPM) * 16 + col;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const int k = 4 * ks + kr;
+          const T b0 = Bi[0][k][cc], b1 = Bi[1][k][cc], b2 = Bi[2][k][cc], bw = Bi[3][k][cc];
+          acc[tt][0] = MF<T>::mma(sf[0][ks], b0, acc[tt][0]);
+          acc[tt][1] = MF<T>::mma(sf[0][ks], bw, acc[tt][1]);
+          acc[tt][0] = MF<T>::mma(sf[1][ks], b1, acc[tt][0]);
+          acc[tt][2] = MF<T>::mma(sf[1][ks], bw, acc[tt][2]);
+          acc[tt][0] = MF<T>::mma(sf[2][ks], b2, acc[tt][0]);
+          acc[tt][3] = MF<T>::mma(sf[2][ks], bw, acc[tt][3]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int tt = 0; tt < CT / WPM; ++tt) {
+        const int cc = (wave / MT + tt * WPM) * 16 + col;
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) Out[g][mt * 16 + MF<T>::row(kr, ii)][cc] = acc[tt][g][ii];
+      }
+      __syncthreads();
+    }
+    T ev[NPT][NC];  // VISC: pointwise part 1/2 sum_l E_l (FVhat_l + y'_l)
+    if constexpr (VISC) {
+      for (int x = tid; x < 3 * MR * NCOL; x += kThreads) (&Bi[0][0][0])[x] = (T)0;
+      __syncthreads();
+#pragma unroll
+      for (int kq = 0; kq < NPT; ++kq) {
+        const int x = tid + kq * kThreads;
+        if (x >= ne * NP) break;
+        const int e = x / NP, i = x % NP;
+        const int cc = (e / 3) * 16 + (e % 3) * NC;
+        const Node<D, T> &n = nodes[kq];
+        const T *Lam = gs[e];
+        const T iJ = (T)1 / Lam[9], ih = (T)1 / (T)A.op.h[i];
+        T El[D];
+#pragma unroll
+        for (int l = 0; l < D; ++l) El[l] = A.op.E[l * NP + i];
+        T Dw[D][NC];  // D_xi_l w
+#pragma unroll
+        for (int l = 0; l < D; ++l)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) Dw[l][c] = (Out[1 + l][i][cc + c] + (T)0.5 * El[l] * n.w[c]) * ih;
+        T gW[D][NC], FV[D][NC];
+#pragma unroll
+        for (int dir = 0; dir < D; ++dir)
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+            gW[dir][c] = (Lam[dir * 3 + 0] * Dw[0][c] + Lam[dir * 3 + 1] * Dw[1][c] + Lam[dir * 3 + 2] * Dw[2][c]) * iJ;
+        viscous_flux<D, T>(n, A.G, A.V, gW, FV);
+        T z[D][NC], yp[D][NC];
+#pragma unroll
+        for (int l = 0; l < D; ++l)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            z[l][c] = Lam[0 * 3 + l] * FV[0][c] + Lam[1 * 3 + l] * FV[1][c] + Lam[2 * 3 + l] * FV[2][c];
+            yp[l][c] = (T)0;
+          }
+        if (i < NFN) {
+          const int off = A.nbr[(size_t)(e0 + e) * NFN + i];
+          T uv[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) uv[c] = (T)A.u[off + c * NP];
+          Node<D, T> nv;
+          node_from_u<D, T>(uv, A.G, nv);
+          T dw[NC], avec[D];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) dw[c] = n.w[c] - nv.w[c];
+#pragma unroll
+          for (int dir = 0; dir < D; ++dir)
+            avec[dir] = Lam[dir * 3 + 0] * El[0] + Lam[dir * 3 + 1] * El[1] + Lam[dir * 3 + 2] * El[2];
+          T y[D][NC];
+          viscous_adjoint_facet<D, T>(n, A.G, A.V, avec, dw, y);
+          const T sc = (T)(-0.5) / (Lam[9] * (T)A.op.h[i]);
+#pragma unroll
+          for (int l = 0; l < D; ++l)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+              yp[l][c] = sc * (Lam[0 * 3 + l] * y[0][c] + Lam[1 * 3 + l] * y[1][c] + Lam[2 * 3 + l] * y[2][c]);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          T s = 0;
+#pragma unroll
+          for (int l = 0; l < D; ++l) {
+            Bi[l][i][cc + c] = z[l][c] - yp[l][c];
+            s += El[l] * (z[l][c] + yp[l][c]);
+          }
+          ev[kq][c] = (T)0.5 * s;
+        }
+      }
+      __syncthreads();
+      V4 acc[CT / WPM];
+#pragma unroll
+      for (int tt = 0; tt < CT / WPM; ++tt) {
+        const int cc = (wave / MT + tt * WPM) * 16 + col;
+        acc[tt] = V4{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const int k = 4 * ks + kr;
+#pragma unroll
+          for (int l = 0; l < 3; ++l) acc[tt] = MF<T>::mma(sf[l][ks], Bi[l][k][cc], acc[tt]);
+        }
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) Out[4][mt * 16 + MF<T>::row(kr, ii)][cc] = acc[tt][ii];
+      }
+      __syncthreads();
+    }
+    // per node: combine, A~_i as directional derivatives, viscous terms, facet SATs
 #pragma unroll
     for (int kq = 0; kq < NPT; ++kq) {
       const int x = tid + kq * kThreads;
       if (x >= ne * NP) break;
       const int e = x / NP, i = x % NP;
+      const int cc = (e / 3) * 16 + (e % 3) * NC;
       const Node<D, T> &n = nodes[kq];
-      const T *Lam = gs + e * 10;
-      const T iJ = (T)1 / Lam[9];
-      T gW[D][NC], FV[D][NC];
+      const T *Lam = gs[e];
+      const T J = Lam[9];
+      const T iJ = (T)1 / J, ih = (T)1 / (T)A.op.h[i];
+      const T H = J * (T)A.op.h[i];
+      const T iH = (T)1 / H;
+      T El[D];
+#pragma unroll
+      for (int l = 0; l < D; ++l) El[l] = A.op.E[l * NP + i];
+      T avec[D];
 #pragma unroll
       for (int dir = 0; dir < D; ++dir)
+        avec[dir] = Lam[dir * 3 + 0] * El[0] + Lam[dir * 3 + 1] * El[1] + Lam[dir * 3 + 2] * El[2];
+      // E part of the volume term: (c_b + 1)/2 sum_l E_l fhat_l = (c_b + 1)/2 sum_i a_i f^(i)
+      T f[D][NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          T s = 0;
+      for (int d = 0; d < D; ++d) flux_i<D, T>(n, (T)A.u[A.uoff[e0 + e] + (NC - 1) * NP + i], d, f[d]);
+      T r[NC];
 #pragma unroll
-          for (int l = 0; l < D; ++l) s += Lam[dir * 3 + l] * C2[(l * NP + i) * NCP + e * NC + c];
-          gW[dir][c] = s * iJ;
-        }
-      viscous_flux<D, T>(n, A.G, A.V, gW, FV);
+      for (int c = 0; c < NC; ++c)
+        r[c] = iH * (hv * Out[0][i][cc + c] + he * (avec[0] * f[0][c] + avec[1] * f[1][c] + avec[2] * f[2][c]));
+      T Dw[D][NC];
 #pragma unroll
       for (int l = 0; l < D; ++l)
 #pragma unroll
+        for (int c = 0; c < NC; ++c) Dw[l][c] = (Out[1 + l][i][cc + c] + (T)0.5 * El[l] * n.w[c]) * ih;
+#pragma unroll
+      for (int dir = 0; dir < D; ++dir) {
+        T g[NC], t[NC];
+#pragma unroll
         for (int c = 0; c < NC; ++c)
-          B3[(l * NP + i) * NCP + e * NC + c] = Lam[0 * 3 + l] * FV[0][c] + Lam[1 * 3 + l] * FV[1][c] + Lam[2 * 3 + l] * FV[2][c];
-      if (i < NFN) {
-        const int off = A.nbr[(size_t)(e0 + e) * NFN + i];
-        T uv[NC];
+          g[c] = (Lam[dir * 3 + 0] * Dw[0][c] + Lam[dir * 3 + 1] * Dw[1][c] + Lam[dir * 3 + 2] * Dw[2][c]) * iJ;
+        jvp_flux<D, T>(n, A.G, dir, g, t);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) uv[c] = (T)A.u[off + c * NP];
-        Node<D, T> nv;
-        node_from_u<D, T>(uv, A.G, nv);
-        T dw[NC], avec[D];
+        for (int c = 0; c < NC; ++c) r[c] -= cb * t[c];
+      }
+      if constexpr (VISC) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) dw[c] = n.w[c] - nv.w[c];
+        for (int c = 0; c < NC; ++c) r[c] += (Out[4][i][cc + c] + ev[kq][c]) * iH;
+        if (i < NFN) {
+          const T *qk = A.q + ((size_t)(e0 + e) * NFN + i) * NC;
+          const T *qv = A.q + (size_t)A.nbrq[(size_t)(e0 + e) * NFN + i] * NC;
 #pragma unroll
-        for (int dir = 0; dir < D; ++dir) {
-          T s = 0;
-#pragma unroll
-          for (int l = 0; l < D; ++l) s += Lam[dir * 3 + l] * Es[l * NP + i];
-          avec[dir] = s;
+          for (int c = 0; c < NC; ++c) r[c] -= (T)0.5 * (qk[c] + qv[c]) * iH;
         }
-        T y[D][NC];
-        viscous_adjoint_facet<D, T>(n, A.G, A.V, avec, dw, y);
-        const T sc = (T)(-0.5) / (Lam[9] * hs[i]);
-#pragma unroll
-        for (int l = 0; l < D; ++l)
-#pragma unroll
-          for (int c = 0; c < NC; ++c)
-            B3[(3 * NP + l * NP + i) * NCP + e * NC + c] =
-                sc * (Lam[0 * 3 + l] * y[0][c] + Lam[1 * 3 + l] * y[1][c] + Lam[2 * 3 + l] * y[2][c]);
       }
+      finish_node<D, NP, NF, T>(A, e0 + e, i, n, H, avec, r, ent);
     }
-    __syncthreads();
-    gemm_AtB<T, M1P, K3P, NCP>(A.op.At5, B3, C3);
-  }
-  double ent = 0.0;
-#pragma unroll
-  for (int kq = 0; kq < NPT; ++kq) {
-    const int x = tid + kq * kThreads;
-    if (x >= ne * NP) break;
-    const int e = x / NP, i = x % NP;
-    const Node<D, T> &n = nodes[kq];
-    const T *Lam = gs + e * 10;
-    const T J = Lam[9];
-    const T iJ = (T)1 / J;
-    const T H = J * hs[i];
-    const T iH = (T)1 / H;
-    T r[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) r[c] = C1[i * NCP + e * NC + c] * iH;
-#pragma unroll
-    for (int dir = 0; dir < D; ++dir) {
-      T g[NC], t[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        T s = 0;
-#pragma unroll
-        for (int l = 0; l < D; ++l) s += Lam[dir * 3 + l] * C2[(l * NP + i) * NCP + e * NC + c];
-        g[c] = s * iJ;
-      }
-      jvp_flux<D, T>(n, A.G, dir, g, t);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) r[c] -= A.G.cb * t[c];
-    }
-    if constexpr (VISC) {
-#pragma unroll
-      for (int c = 0; c < NC; ++c) r[c] += C3[i * NCP + e * NC + c] * iH;
-      if (i < NFN) {
-        const T *qk = A.q + ((size_t)(e0 + e) * NFN + i) * NC;
-        const T *qv = A.q + (size_t)A.nbrq[(size_t)(e0 + e) * NFN + i] * NC;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) r[c] -= (T)0.5 * (qk[c] + qv[c]) * iH;
-      }
-    }
-    T avec[D];
-#pragma unroll
-    for (int dir = 0; dir < D; ++dir) {
-      T s = 0;
-#pragma unroll
-      for (int l = 0; l < D; ++l) s += Lam[dir * 3 + l] * Es[l * NP + i];
-      avec[dir] = s;
-    }
-    finish_node<D, NP, NF, T>(A, e0 + e, i, n, H, avec, r, ent);
   }
   block_sum_store(ent, A.ent_part);
 }
@@ -976,8 +1069,37 @@ static int split2_grid(int n_elem) {
   return std::min((n_elem + per_block - 1) / per_block, cap);
 }
 
+// Persistent grid of the 3D split kernel.
+template <int P, typename T, bool VISC>
+static int split3_grid(int n_elem) {
+  static int cap = 0;
+  if (cap == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_split3<P, T, VISC>, kThreads, 0) != hipSuccess ||
+        cus <= 0 || per <= 0)
+      cap = 1024;
+    else
+      cap = cus * per;
+  }
+  const int eb = 3 * Wave3<P, T>::CT;
+  return std::min((n_elem + eb - 1) / eb, cap);
+}
+
 int residual_blocks(int dim, int p, int precision, int form, int n_elem) {
   if (n_elem <= 0) return 0;
+  if (dim == 3 && (form == 0 || form == 2)) {
+#define SBP_G3(PP)                                                                            \
+  if (p == PP) {                                                                              \
+    if (form == 2)                                                                            \
+      return precision == 0 ? split3_grid<PP, double, true>(n_elem) : split3_grid<PP, float, true>(n_elem); \
+    return precision == 0 ? split3_grid<PP, double, false>(n_elem) : split3_grid<PP, float, false>(n_elem); \
+  }
+    SBP_G3(1) SBP_G3(2) SBP_G3(3)
+#undef SBP_G3
+    return 0;
+  }
   if (dim == 2 && form == 0) {
 #define SBP_G2(PP) \
   if (p == PP) return precision == 0 ? split2_grid<PP, double>(n_elem) : split2_grid<PP, float>(n_elem);
@@ -1024,8 +1146,9 @@ static hipError_t launch_t(int dim, int p, int form, const KArgs<T> &A, hipStrea
 template <typename T>
 static hipError_t launch_q(int dim, int p, const KArgs<T> &A, hipStream_t s) {
   if (dim != 3) return hipErrorInvalidValue;
-  const int nb = residual_blocks(3, p, sizeof(T) == 8 ? 0 : 1, 0, A.n_elem);
-  dim3 grid(nb), block(kThreads);
+  const int eb = tile_elems<T>(3, p, 0);
+  if (eb <= 0 || A.n_elem <= 0) return hipErrorInvalidValue;
+  dim3 grid((A.n_elem + eb - 1) / eb), block(kThreads);
   if (p == 1) hipLaunchKernelGGL((k_visc_q3<1, T>), grid, block, 0, s, A);
   else if (p == 2) hipLaunchKernelGGL((k_visc_q3<2, T>), grid, block, 0, s, A);
   else if (p == 3) hipLaunchKernelGGL((k_visc_q3<3, T>), grid, block, 0, s, A);
