@@ -127,9 +127,21 @@ int sbp_residual_vjp(sbp_mesh *mesh, const void *u_dev, const void *lambda_dev,
 
 /* One relaxation RK4 step in place (Sec. 6.1, eqs. rrk4 gamma_n, rrk_update).
  * dt > 0: use it; dt <= 0: dt = cfl * min_k h_min,k / |lambda|_max,k
- * (Sec. 7.1).  rep may be NULL.  Synchronises hip_stream. */
+ * (Sec. 7.1).  rep may be NULL.  Synchronises hip_stream.
+ * The four RK stages (residuals, stage states, direction d) are captured once
+ * per state pointer as a HIP graph on a private stream of the handle and
+ * replayed on hip_stream (see sbp_use_graphs).  The relaxation parameter is
+ * the root near 1 of sum H [s(u + g d) - s(u)] - g e, e = dt sum_i b_i w_i^T H
+ * r_i, found by Newton steps from g = 1 safeguarded by bisection on [0.5,
+ * 1.5]; SBP_ERRK if the root is not bracketed there.  On any error u is left
+ * unchanged. */
 int sbp_rrk_step(sbp_mesh *mesh, void *u_dev, double dt, double cfl,
                  sbp_rrk_report *rep, void *hip_stream);
+
+/* enable != 0 (default): sbp_rrk_step replays its captured stage graph;
+ * enable == 0: the stages are launched one by one (for callers that capture
+ * the stream themselves).  Not in the paper.  SBP_EINVAL for a null handle. */
+int sbp_use_graphs(sbp_mesh *mesh, int enable);
 
 /* FP64 diagnostics on the device, results copied to host (synchronises):
  * out[0] = 1^T H s(u); out[1..n_c] = sum_k 1^T H_k u_k per component. */

@@ -86,12 +86,19 @@ struct sbp_mesh {
   double *d_y = nullptr, *d_d = nullptr;
   void *d_r = nullptr;        // RK stage residual
   double t = 0.0;
+  // RRK stages captured once as a HIP graph (per state pointer), replayed on
+  // the caller's stream; captured on a private stream of default priority
+  int use_graphs = 1;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t rk_exec = nullptr;
+  const void *rk_u = nullptr;
 };
 
 namespace {
 
 constexpr int SC_ENT = 0;     // 4 stage entropy rates
 constexpr int SC_RED = 8;     // reduction outputs (up to 8)
+constexpr int SC_DT = 16;     // time step of the current RRK step
 constexpr int SC_TOTAL = 32;
 
 // --------------------------------------------------------------------------
@@ -591,11 +598,7 @@ int residual_impl(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStr
       const int nb = sbp::residual_blocks(M->dim, c.p, ph.precision, form_eff, c.n_elem);
       HIPCHK(sbp::launch_reduce(M->d_part + c.part_off, nb, 1, 0, M->d_scal + SC_RED + ci, s));
     }
-    if (M->cls.size() == 1) {
-      HIPCHK(hipMemcpyAsync(ent_dev, M->d_scal + SC_RED, sizeof(double), hipMemcpyDeviceToDevice, s));
-    } else {
-      HIPCHK(sbp::launch_reduce(M->d_scal + SC_RED, (int)M->cls.size(), 1, 0, ent_dev, s));
-    }
+    HIPCHK(sbp::launch_reduce(M->d_scal + SC_RED, (int)M->cls.size(), 1, 0, ent_dev, s));
   }
   return SBP_OK;
 }
@@ -620,12 +623,64 @@ int check_err(sbp_mesh *M, hipStream_t s) {
   return SBP_OK;
 }
 
-int entropy_gap(sbp_mesh *M, const double *u, const double *d, double g, double out[2], hipStream_t s) {
+// out = { sum H [s(u + g d) - s(u)], sum H w(u + g d).d, sum H |s(u + g d)| }
+int entropy_gap(sbp_mesh *M, const double *u, const double *d, double g, double out[3], hipStream_t s) {
   for (auto &c : M->cls) {
     sbp::NodeArgs A = node_args(M, c, u, d);
     HIPCHK(sbp::launch_entropy_gap(A, g, M->d_npart + c.node_off_blk, s));
   }
-  return reduce_nodes(M, 2, 0, out, s);
+  return reduce_nodes(M, 3, 0, out, s);
+}
+
+// The four RK stages of one step (Sec. 6.1): y_i = u + c_i dt r_{i-1},
+// r_i = r(y_i) with its entropy rate, d = dt sum_i b_i r_i; dt is the device
+// scalar SC_DT so that the same sequence can be captured once and replayed.
+int rk_stages(sbp_mesh *M, const double *u, hipStream_t s) {
+  const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+  const double cst[4] = {0.0, 0.5, 0.5, 1.0};
+  const long long n = M->n_dof;
+  const int f32 = M->phys.precision == SBP_FP32;
+  const double *dtp = M->d_scal + SC_DT;
+  int rc;
+  for (int i = 0; i < 4; ++i) {
+    const double *y = u;
+    if (i > 0) {
+      HIPCHK(sbp::launch_axpy(M->d_y, u, M->d_r, f32, cst[i], n, s, dtp));
+      y = M->d_y;
+    }
+    if ((rc = residual_impl(M, y, M->d_r, M->d_scal + SC_ENT + i, s))) return rc;
+    if (i == 0)
+      HIPCHK(sbp::launch_axpy(M->d_d, nullptr, M->d_r, f32, b[i], n, s, dtp));
+    else
+      HIPCHK(sbp::launch_accum(M->d_d, M->d_r, f32, b[i], n, s, dtp));
+  }
+  return SBP_OK;
+}
+
+int rk_stages_graph(sbp_mesh *M, const double *u, hipStream_t s) {
+  if (!M->use_graphs) return rk_stages(M, u, s);
+  if (M->rk_exec && M->rk_u != (const void *)u) {
+    (void)hipGraphExecDestroy(M->rk_exec);
+    M->rk_exec = nullptr;
+  }
+  if (!M->rk_exec) {
+    if (!M->cap_stream) HIPCHK(hipStreamCreateWithFlags(&M->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(M->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = rk_stages(M, u, M->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(M->cap_stream, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    HIPCHK(ec);
+    const hipError_t ei = hipGraphInstantiate(&M->rk_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHK(ei);
+    M->rk_u = u;
+  }
+  HIPCHK(hipGraphLaunch(M->rk_exec, s));
+  return SBP_OK;
 }
 
 int diagnostics_impl(sbp_mesh *M, const double *u, double *out, hipStream_t s) {
@@ -736,6 +791,17 @@ int sbp_check_device(sbp_mesh *M, void *stream) {
   return check_err(M, (hipStream_t)stream);
 }
 
+int sbp_use_graphs(sbp_mesh *M, int enable) {
+  if (!M) return fail(SBP_EINVAL, "null argument");
+  M->use_graphs = enable ? 1 : 0;
+  if (!M->use_graphs && M->rk_exec) {
+    (void)hipGraphExecDestroy(M->rk_exec);
+    M->rk_exec = nullptr;
+    M->rk_u = nullptr;
+  }
+  return SBP_OK;
+}
+
 int sbp_set_time(sbp_mesh *M, double t) {
   if (!M) return fail(SBP_EINVAL, "null argument");
   M->t = t;
@@ -769,46 +835,53 @@ int sbp_rrk_step(sbp_mesh *M, void *u_dev, double dt, double cfl, sbp_rrk_report
     }
   }
   const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
-  const double cst[4] = {0.0, 0.5, 0.5, 1.0};
-  HIPCHK(hipMemsetAsync(M->d_d, 0, sizeof(double) * n, s));
-  for (int i = 0; i < 4; ++i) {
-    const double *y = u;
-    if (i > 0) {
-      HIPCHK(sbp::launch_axpy(M->d_y, u, M->d_r, f32, cst[i] * dt, n, s));
-      y = M->d_y;
-    }
-    if ((rc = residual_impl(M, y, M->d_r, M->d_scal + SC_ENT + i, s))) return rc;
-    HIPCHK(sbp::launch_accum(M->d_d, M->d_r, f32, b[i] * dt, n, s));
-  }
+  HIPCHK(sbp::launch_scalar_set(M->d_scal + SC_DT, dt, s));
+  if ((rc = rk_stages_graph(M, u, s))) return rc;
   double ent[4];
   HIPCHK(hipMemcpyAsync(ent, M->d_scal + SC_ENT, sizeof(ent), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if ((rc = check_err(M, s))) return rc;
   double e = 0.0;
   for (int i = 0; i < 4; ++i) e += dt * b[i] * ent[i];
-  // relaxation parameter: root near 1 of r(g) = sum H [s(u + g d) - s(u)] - g e,
-  // Newton steps safeguarded by the bracket [0.5, 1.5] (bisection fallback)
+  // relaxation parameter: root near 1 of r(g) = sum H [s(u + g d) - s(u)] - g e.
+  // Newton from g = 1, stopped once |r(g)| reaches the rounding level of its
+  // evaluation (eps sum H |s|) or the step stalls; the bracket [0.5, 1.5] is
+  // evaluated only if a Newton step leaves it (then bisection safeguards).
+  constexpr double eps = 2.220446049250313e-16;
   double lo = 0.5, hi = 1.5, g = 1.0;
-  double fv[2];
-  if ((rc = entropy_gap(M, u, M->d_d, lo, fv, s))) return rc;
-  const double flo = fv[0] - lo * e;
-  if ((rc = entropy_gap(M, u, M->d_d, hi, fv, s))) return rc;
-  const double fhi = fv[0] - hi * e;
-  if (!(flo < 0.0 && fhi > 0.0)) return fail(SBP_ERRK, "relaxation root not bracketed in [0.5, 1.5]");
+  bool bracketed = false;
+  double fv[3];
   int it = 0;
   for (; it < 100; ++it) {
     if ((rc = entropy_gap(M, u, M->d_d, g, fv, s))) return rc;
     const double f = fv[0] - g * e;
     const double df = fv[1] - e;
-    if (f == 0.0) break;
-    if (f < 0.0) lo = g; else hi = g;
+    if (std::fabs(f) <= eps * fv[2]) break;
+    if (bracketed) {
+      if (f < 0.0) lo = g; else hi = g;
+    }
     double gn = g - f / df;
-    if (!(df > 0.0) || !(gn > lo && gn < hi)) gn = 0.5 * (lo + hi);
-    if (gn == g || hi - lo <= 4.0 * 2.220446049250313e-16 * g) { g = gn; break; }
-    if (std::fabs(gn - g) <= 2.220446049250313e-16 * g) { g = gn; break; }
+    if (!(df > 0.0) || !(gn > lo && gn < hi)) {
+      if (!bracketed) {
+        double fb[3];
+        if ((rc = entropy_gap(M, u, M->d_d, lo, fb, s))) return rc;
+        const double flo = fb[0] - lo * e;
+        if ((rc = entropy_gap(M, u, M->d_d, hi, fb, s))) return rc;
+        const double fhi = fb[0] - hi * e;
+        if (!(flo < 0.0 && fhi > 0.0)) return fail(SBP_ERRK, "relaxation root not bracketed in [0.5, 1.5]");
+        bracketed = true;
+        if (f < 0.0) lo = g; else hi = g;
+      }
+      if (!(df > 0.0) || !(gn > lo && gn < hi)) gn = 0.5 * (lo + hi);
+    }
+    if (gn == g || std::fabs(gn - g) <= eps * g || (bracketed && hi - lo <= 4.0 * eps * g)) {
+      g = gn;
+      break;
+    }
     g = gn;
   }
   if (it >= 100) return fail(SBP_ERRK, "relaxation root solve did not converge");
+  if (!(g > 0.5 && g < 1.5)) return fail(SBP_ERRK, "relaxation parameter outside [0.5, 1.5]");
   double diag0[1 + 5] = {0}, diag1[1 + 5] = {0};
   if (rep) {
     if ((rc = diagnostics_impl(M, u, diag0, s))) return rc;
@@ -850,6 +923,8 @@ int sbp_destroy_mesh(sbp_mesh *M) {
   (void)hipFree(M->d_y);
   (void)hipFree(M->d_d);
   (void)hipFree(M->d_r);
+  if (M->rk_exec) (void)hipGraphExecDestroy(M->rk_exec);
+  if (M->cap_stream) (void)hipStreamDestroy(M->cap_stream);
   delete M;
   return SBP_OK;
 }

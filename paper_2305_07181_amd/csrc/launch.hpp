@@ -38,7 +38,8 @@ struct NodeArgs {
 constexpr int kNodeThreads = 256;
 inline int node_blocks(int n_elem, int np) { return (n_elem * np + kNodeThreads - 1) / kNodeThreads; }
 
-// part[v*pstride + b], v = 0,1: sum_nodes H [s(u + g d) - s(u)], sum_nodes H w(u + g d).d
+// part[v*pstride + b], v = 0,1,2: sum_nodes H [s(u + g d) - s(u)], sum_nodes H w(u + g d).d,
+// sum_nodes H |s(u + g d)|
 hipError_t launch_entropy_gap(const NodeArgs &A, double g, double *part, hipStream_t s);
 // part[v*pstride + b], v = 0: sum H s(u); v = 1..n_c: sum H u_c
 hipError_t launch_diagnostics(const NodeArgs &A, double *part, hipStream_t s);
@@ -46,10 +47,15 @@ hipError_t launch_diagnostics(const NodeArgs &A, double *part, hipStream_t s);
 hipError_t launch_dt(const NodeArgs &A, double *part, hipStream_t s);
 // out[v] = reduction over part[v*nb + b], b < nb (op 0: sum, 1: min); fixed order.
 hipError_t launch_reduce(const double *part, int nb, int nv, int op, double *out, hipStream_t s);
-// y = x + a z, z double or float (z_f32), n doubles
-hipError_t launch_axpy(double *y, const double *x, const void *z, int z_f32, double a, long long n, hipStream_t s);
-// y = y + a z (accumulate), z double or float
-hipError_t launch_accum(double *y, const void *z, int z_f32, double a, long long n, hipStream_t s);
+// y = x + a s z (x null: y = a s z), z double or float (z_f32), n doubles,
+// s = *scale (a device scalar read by the kernel) or 1 if scale is null
+hipError_t launch_axpy(double *y, const double *x, const void *z, int z_f32, double a, long long n, hipStream_t s,
+                       const double *scale = nullptr);
+// y = y + a s z (accumulate), z double or float
+hipError_t launch_accum(double *y, const void *z, int z_f32, double a, long long n, hipStream_t s,
+                        const double *scale = nullptr);
+// out[0] = v (device scalar written in stream order)
+hipError_t launch_scalar_set(double *out, double v, hipStream_t s);
 // out[slot] = sum_k coef_k * in[k] for k < nk (device scalars)
 hipError_t launch_scalar_combine(const double *in, const double *coef_dev, int nk, double *out, hipStream_t s);
 

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kT) void k_entropy_gap(NodeArgs A, double gam, doub
   constexpr int NC = D + 2;
   __shared__ double red[kT / 64];
   const int x = blockIdx.x * kT + threadIdx.x;
-  double a = 0.0, b = 0.0;
+  double a = 0.0, b = 0.0, m = 0.0;
   if (x < A.n_elem * A.np) {
     const int e = x / A.np, j = x % A.np;
     const int base = A.uoff[e] + j;
@@ -92,12 +92,15 @@ __global__ __launch_bounds__(kT) void k_entropy_gap(NodeArgs A, double gam, doub
 #pragma unroll
     for (int c = 0; c < NC; ++c) wd += w1[c] * dd[c];
     b = H * wd;
+    m = H * fabs(s1);
   }
   const double sa = block_reduce_sum(a, red);
   const double sb = block_reduce_sum(b, red);
+  const double sm = block_reduce_sum(m, red);
   if (threadIdx.x == 0) {
     part[blockIdx.x] = sa;
     part[A.pstride + blockIdx.x] = sb;
+    part[2 * A.pstride + blockIdx.x] = sm;
   }
 }
 
@@ -168,16 +171,24 @@ __global__ __launch_bounds__(kT) void k_reduce(const double *part, int nb, int o
   if (threadIdx.x == 0) out[v] = r;
 }
 
+// y = x + a s z (x null: y = a s z), s = *scale if scale is not null, else 1
 template <typename Z>
-__global__ __launch_bounds__(kT) void k_axpy(double *y, const double *x, const Z *z, double a, long long n) {
+__global__ __launch_bounds__(kT) void k_axpy(double *y, const double *x, const Z *z, double a, const double *scale,
+                                             long long n) {
+  const double as = scale ? a * scale[0] : a;
   for (long long i = blockIdx.x * (long long)kT + threadIdx.x; i < n; i += (long long)gridDim.x * kT)
-    y[i] = x[i] + a * (double)z[i];
+    y[i] = (x ? x[i] : 0.0) + as * (double)z[i];
 }
 
 template <typename Z>
-__global__ __launch_bounds__(kT) void k_accum(double *y, const Z *z, double a, long long n) {
+__global__ __launch_bounds__(kT) void k_accum(double *y, const Z *z, double a, const double *scale, long long n) {
+  const double as = scale ? a * scale[0] : a;
   for (long long i = blockIdx.x * (long long)kT + threadIdx.x; i < n; i += (long long)gridDim.x * kT)
-    y[i] += a * (double)z[i];
+    y[i] += as * (double)z[i];
+}
+
+__global__ void k_scalar_set(double *out, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = v;
 }
 
 __global__ void k_scalar_combine(const double *in, const double *coef, int nk, double *out) {
@@ -229,19 +240,26 @@ hipError_t launch_reduce(const double *part, int nb, int nv, int op, double *out
   return hipGetLastError();
 }
 
-hipError_t launch_axpy(double *y, const double *x, const void *z, int z_f32, double a, long long n, hipStream_t s) {
+hipError_t launch_axpy(double *y, const double *x, const void *z, int z_f32, double a, long long n, hipStream_t s,
+                       const double *scale) {
   if (z_f32)
-    hipLaunchKernelGGL(k_axpy<float>, dim3(grid_for(n)), dim3(kT), 0, s, y, x, (const float *)z, a, n);
+    hipLaunchKernelGGL(k_axpy<float>, dim3(grid_for(n)), dim3(kT), 0, s, y, x, (const float *)z, a, scale, n);
   else
-    hipLaunchKernelGGL(k_axpy<double>, dim3(grid_for(n)), dim3(kT), 0, s, y, x, (const double *)z, a, n);
+    hipLaunchKernelGGL(k_axpy<double>, dim3(grid_for(n)), dim3(kT), 0, s, y, x, (const double *)z, a, scale, n);
   return hipGetLastError();
 }
 
-hipError_t launch_accum(double *y, const void *z, int z_f32, double a, long long n, hipStream_t s) {
+hipError_t launch_accum(double *y, const void *z, int z_f32, double a, long long n, hipStream_t s,
+                        const double *scale) {
   if (z_f32)
-    hipLaunchKernelGGL(k_accum<float>, dim3(grid_for(n)), dim3(kT), 0, s, y, (const float *)z, a, n);
+    hipLaunchKernelGGL(k_accum<float>, dim3(grid_for(n)), dim3(kT), 0, s, y, (const float *)z, a, scale, n);
   else
-    hipLaunchKernelGGL(k_accum<double>, dim3(grid_for(n)), dim3(kT), 0, s, y, (const double *)z, a, n);
+    hipLaunchKernelGGL(k_accum<double>, dim3(grid_for(n)), dim3(kT), 0, s, y, (const double *)z, a, scale, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scalar_set(double *out, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_scalar_set, dim3(1), dim3(64), 0, s, out, v);
   return hipGetLastError();
 }
 

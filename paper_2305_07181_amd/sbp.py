@@ -23,7 +23,7 @@ FP64, FP32 = 0, 1
 
 SYMBOLS = ["sbp_setup_mesh", "sbp_mesh_info", "sbp_residual", "sbp_residual_vjp", "sbp_rrk_step",
            "sbp_diagnostics", "sbp_check_device", "sbp_set_time", "sbp_destroy_mesh",
-           "sbp_last_error", "sbp_reference_operator"]
+           "sbp_last_error", "sbp_reference_operator", "sbp_use_graphs"]
 
 
 class SbpError(RuntimeError):
@@ -72,6 +72,7 @@ def load_library(path: str = _LIB_PATH):
     lib.sbp_diagnostics.argtypes = [P, P, C.POINTER(C.c_double), P]
     lib.sbp_check_device.argtypes = [P, P]
     lib.sbp_set_time.argtypes = [P, C.c_double]
+    lib.sbp_use_graphs.argtypes = [P, C.c_int]
     lib.sbp_destroy_mesh.argtypes = [P]
     lib.sbp_last_error.restype = C.c_char_p
     lib.sbp_reference_operator.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -225,6 +226,9 @@ class Mesh:
         _check(_lib.sbp_rrk_step(self._h, _ptr(u), float(dt), float(cfl), C.byref(rep), _stream_ptr(stream)))
         return dict(gamma=rep.gamma_n, dt=rep.dt, t=rep.t, entropy_before=rep.entropy_before,
                     entropy_after=rep.entropy_after, e=rep.entropy_rate_e, iters=rep.newton_iters)
+
+    def use_graphs(self, enable=True):
+        _check(_lib.sbp_use_graphs(self._h, int(bool(enable))))
 
     def diagnostics(self, u, stream=None):
         out = np.zeros(self.n_c + 1)
