@@ -32,6 +32,13 @@ METRIC = "residual elem-DOF updates/s: FP64 vs FP32 vs Hadamard form; VJP/forwar
 PEAK_HBM = 8.0e12          # B/s
 PEAK_F64 = 78.6e12         # FLOP/s (vector and MFMA)
 PEAK_F32 = 157.3e12
+# HBM bytes per launch of the 2D split kernels (FP64, 32768 curved triangles)
+# from FETCH_SIZE / WRITE_SIZE counter runs calibrated against a 256 MiB copy
+# (profiles/k_split2_tri32768_hbm_bytes.md); valid only for the kernel sources
+# they were taken on (sha256 prefix of the concatenated sources below).
+TRAFFIC_SOURCES = ["residual_kernels.hip", "device_physics.hpp", "mfma.hpp", "kernels.hpp"]
+TRAFFIC_SHA = "b2476555b4222fd8"
+TRAFFIC_BYTES = {1: 17.51e6, 2: 26.62e6, 3: 45.87e6, 4: 54.87e6}
 
 
 def _args():
@@ -42,7 +49,20 @@ def _args():
     ap.add_argument("--no-extras", action="store_true",
                     help="report only the headline step (used under a profiler)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def measured_traffic(p):
+    """Counter-measured HBM bytes per launch of the p kernel, or None once the
+    kernel sources differ from those the counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2305_07181_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC_BYTES.get(p) if h.hexdigest()[:16] == TRAFFIC_SHA else None
 
 
 def algorithmic_work(dim, n_p, n_f, precision_bytes=8, viscous=False):
@@ -86,6 +106,48 @@ def _time_calls(fn, reps, warm):
     torch.cuda.synchronize()
     t = np.array([a.elapsed_time(b) for a, b in ev]) * 1e-3
     return float(np.median(t)), float(np.mean(t))
+
+
+def ns_rows(args):
+    """Navier-Stokes Taylor-Green vortex on 24^3 x 6 = 82944 tetrahedra, p = 3,
+    M = 0.1, Re = 1600, Pr = 0.71, heat flux and matrix dissipation on: the
+    residual in FP64 and FP32, and RRK4 steps (FP32 residuals, FP64 state and
+    relaxation) with the captured stage graph and with eager launches."""
+    import time as _t
+    import torch
+    from paper_2305_07181_amd import sbp, workloads as wl
+    desc = wl.tgv_mesh(24)
+    ne = len(desc["elem_vert"])
+    kw = dict(dissipation=True, viscous=True, heat_flux=True, mu=1.0 / 1600, Pr=0.71, R=1.0)
+    row = dict(n_elem=ne)
+    for name, prec in (("fp64", sbp.FP64), ("fp32", sbp.FP32)):
+        m = sbp.Mesh(desc, 3, precision=prec, **kw)
+        u = _state_from_mesh(m, "tgv")
+        r = torch.empty(u.shape, dtype=torch.float64 if prec == sbp.FP64 else torch.float32, device="cuda")
+        med, _ = _time_calls(lambda: m.residual(u, r), 5, 2)
+        row[f"residual_{name}_ms"] = med * 1e3
+        row[f"residual_{name}_elem_dof_per_s"] = ne * int(m.elem_np[0]) / med
+        m.close()
+    m = sbp.Mesh(desc, 3, precision=sbp.FP32, **kw)
+    u = _state_from_mesh(m, "tgv")
+    for mode in ("graph", "eager"):
+        m.use_graphs(mode == "graph")
+        m.rrk_step(u, cfl=0.5)                     # warm-up (and capture)
+        torch.cuda.synchronize()
+        reps = []
+        t0 = _t.perf_counter()
+        for _ in range(10):
+            reps.append(m.rrk_step(u, cfl=0.5))
+        torch.cuda.synchronize()
+        row[f"rrk_step_fp32_{mode}_ms"] = (_t.perf_counter() - t0) / 10 * 1e3
+        if mode == "graph":
+            row["newton_iters_mean"] = float(np.mean([q["iters"] for q in reps]))
+            row["gamma_min"] = float(min(q["gamma"] for q in reps))
+            row["gamma_max"] = float(max(q["gamma"] for q in reps))
+            row["entropy_nonincreasing"] = bool(all(q["entropy_after"] <= q["entropy_before"] for q in reps))
+            row["dt"] = float(reps[-1]["dt"])
+    m.close()
+    return row
 
 
 def batch_rows(args):
@@ -227,7 +289,7 @@ def main():
     else:
         roof = dict(bound="hbm", achieved=by * ne / kern[dom] / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom)
     roof["kernel"] = f"k_split2<{dom},double> (2D entropy split, p={dom}), {ne} elements per launch"
     roof["avg_launch_ms"] = kern[dom] * 1e3
     out = dict(metric=METRIC, value=value, unit="elem-DOF/s", n_gpus=1, steps=args.steps,
@@ -290,6 +352,7 @@ def main():
             extras[f"tet_p{p}_tgv_196608"] = row
             m64.close()
             del u3, lam3, ub3
+        extras["ns_tgv_82944_p3"] = ns_rows(args)
         extras["batch48"] = batch_rows(args)
         fw = sum(extras[f"tri_p{p}"]["fp64_split"]["ms"] for p in ps)
         bw = sum(extras[f"tri_p{p}"]["fp64_vjp"]["ms"] for p in ps)
@@ -298,6 +361,13 @@ def main():
             note="FP64 VJP time / FP64 entropy-split residual time; headline = sum over p = 1..4 "
                  "on the 32768-triangle mesh")
         out["breakdown"] = extras
+    if args.copy_probe:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = dict(read=src.numel() * 8, write=dst.numel() * 8)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(desc, ps)
     for p in ps:
