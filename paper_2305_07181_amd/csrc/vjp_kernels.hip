@@ -8,10 +8,13 @@
 //                = -c_b (dW/dU) [ sum_i D_xi^T (A~_i lambda) + sum_i d/de A~_i(w + e g_i) lambda ]
 //              (A~_i and dW/dU symmetric; the last term is a Hessian-vector
 //               product, evaluated with dual numbers)
-//   facets     each facet node receives the derivative of its own SAT with
-//              respect to its own state and the derivative of the matching
-//              neighbour's SAT with respect to this node's state (both by dual
-//              numbers, one pass per component), gathered without atomics.
+//   facets     each facet node receives the derivative of its own SAT and of
+//              the matching neighbour's SAT with respect to its own state;
+//              the neighbour's SAT is the negative of its own (antisymmetric
+//              two-point flux and dissipation, opposite B n), so both are one
+//              gradient of Phi(u_k, u_v) with cotangent lambda_k/H_k -
+//              lambda_v/H_v (dual numbers, one pass per component), gathered
+//              without atomics.
 // The transposed operators are applied as MFMA contractions like the forward
 // kernel: [M_1^T; M_2^T; M_3^T] mu, [D_1^T D_2^T D_3^T] s, and D w.
 //
@@ -79,32 +82,46 @@ __device__ __forceinline__ void gemm64(const double *__restrict__ At, const doub
   __syncthreads();
 }
 
-// gradient of lambda . Phi(u1, u2; a) with respect to u1 (which = 0) or u2
-// (which = 1), Phi = facet_term (two-point flux [+ dissipation]).
+// gradient of mu . Phi(u1, u2; a) with respect to u1, Phi = facet_term
+// (two-point flux [+ dissipation]); one dual-number pass per component of
+// u1, the neighbour state u2 evaluated once in plain arithmetic.
 template <int D>
-__device__ __forceinline__ void facet_grad(const double *u1, const double *u2, const double *a, const double *lam,
-                                           const GasC<Dual<double>> &G, bool diss, int which, double *out) {
+__device__ __forceinline__ void facet_grad(const double *u1, const double *u2, const double *a, const double *mu,
+                                           const GasC<double> &G0, const GasC<Dual<double>> &G, bool diss,
+                                           double *out) {
   constexpr int NC = D + 2;
   Dual<double> av[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) av[i] = Dual<double>(a[i]);
-  for (int c = 0; c < NC; ++c) {
-    Dual<double> x1[NC], x2[NC];
+  Node<D, double> m2;
+  node_from_u<D, double>(u2, G0, m2);
+  node_powers<D, double>(G0, m2);
+  Node<D, Dual<double>> n2;
+  n2.rho = m2.rho;
 #pragma unroll
-    for (int q = 0; q < NC; ++q) {
-      x1[q] = Dual<double>(u1[q], (which == 0 && q == c) ? 1.0 : 0.0);
-      x2[q] = Dual<double>(u2[q], (which == 1 && q == c) ? 1.0 : 0.0);
-    }
-    Node<D, Dual<double>> n1, n2;
+  for (int i = 0; i < D; ++i) n2.V[i] = m2.V[i];
+  n2.p = m2.p;
+  n2.lrho = m2.lrho;
+  n2.lp = m2.lp;
+  n2.lz1 = m2.lz1;
+  n2.z1 = m2.z1;
+  n2.P1 = m2.P1;
+  n2.P2 = m2.P2;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) n2.w[c] = m2.w[c];
+  n2.ok = m2.ok;
+  for (int c = 0; c < NC; ++c) {
+    Dual<double> x1[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) x1[q] = Dual<double>(u1[q], q == c ? 1.0 : 0.0);
+    Node<D, Dual<double>> n1;
     node_from_u<D, Dual<double>>(x1, G, n1);
-    node_from_u<D, Dual<double>>(x2, G, n2);
     node_powers<D, Dual<double>>(G, n1);
-    node_powers<D, Dual<double>>(G, n2);
     Dual<double> ph[NC];
     facet_term<D, Dual<double>>(n1, n2, av, G, diss, ph);
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < NC; ++q) s += lam[q] * ph[q].d;
+    for (int q = 0; q < NC; ++q) s += mu[q] * ph[q].d;
     out[c] = s;
   }
 }
@@ -275,23 +292,18 @@ __global__ __launch_bounds__(kT) void k_vjp3(KArgs<double> A) {
         for (int l = 0; l < D; ++l) s += Lam[i * 3 + l] * Es[l * NP + j];
         ak[i] = s;
       }
+      // the neighbour's SAT is the negative of this node's (antisymmetric
+      // two-point flux and dissipation, opposite B n), so both derivatives
+      // are one gradient of Phi(u_k, u_v) with the cotangent
+      // lambda_k / H_k - lambda_v / H_v
       const int q = A.nbrq[(size_t)eg * NFN + j];
-      const int vk = q / NFN, nn = q % NFN;
-      const double *Lv = A.geo + (size_t)vk * 10;
-      double av[D];
+      const double Hv = A.Hn[(size_t)(q / NFN) * NP + q % NFN];
+      double mu[NC], g1[NC];
 #pragma unroll
-      for (int i = 0; i < D; ++i) {
-        double s = 0.0;
+      for (int c = 0; c < NC; ++c) mu[c] = lm[c] / H - lv[c] / Hv;
+      facet_grad<D>(uu, uv, ak, mu, G, GD, A.diss != 0, g1);
 #pragma unroll
-        for (int l = 0; l < D; ++l) s += Lv[i * 3 + l] * Es[l * NP + nn];
-        av[i] = s;
-      }
-      const double Hv = A.Hn[(size_t)vk * NP + nn];
-      double g1[NC], g2[NC];
-      facet_grad<D>(uu, uv, ak, lm, GD, A.diss != 0, 0, g1);
-      facet_grad<D>(uv, uu, av, lv, GD, A.diss != 0, 1, g2);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) ub[c] -= g1[c] / H + g2[c] / Hv;
+      for (int c = 0; c < NC; ++c) ub[c] -= g1[c];
     }
     const int uo = A.uoff[eg];
 #pragma unroll
@@ -545,20 +557,16 @@ struct Vjp2 {
             uv[c] = A.u[off + c * NP];
             lv[c] = A.lam[off + c * NP];
           }
+          // one gradient of this node's SAT with the combined cotangent
+          // (the neighbour's SAT is its negative)
           const int q = A.nbrq[(size_t)eg * NFN + j];
-          const int vk = q / NFN, nn = q % NFN;
-          double lv5[5];
-          metrics(vk, nn, lv5);
-          const double F0 = A.op.E[nn], F1 = A.op.E[NP + nn];
-          double av[D];
-          av[0] = lv5[0] * F0 + lv5[1] * F1;
-          av[1] = lv5[2] * F0 + lv5[3] * F1;
-          const double Hv = A.Hn[(size_t)vk * NP + nn];
-          double g1[NC], g2[NC];
-          facet_grad<D>(uu, uv, ak, lm, GD, A.diss != 0, 0, g1);
-          facet_grad<D>(uv, uu, av, lv, GD, A.diss != 0, 1, g2);
+          const double Hv = A.Hn[(size_t)(q / NFN) * NP + q % NFN];
+          double mu[NC], g1[NC];
 #pragma unroll
-          for (int c = 0; c < NC; ++c) ub[c] -= g1[c] * iH + g2[c] / Hv;
+          for (int c = 0; c < NC; ++c) mu[c] = lm[c] * iH - lv[c] / Hv;
+          facet_grad<D>(uu, uv, ak, mu, G, GD, A.diss != 0, g1);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) ub[c] -= g1[c];
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) A.ubar[uo + c * NP + j] = ub[c];
