@@ -44,20 +44,6 @@ template <> struct Tile<3, 1, float, 2> { static constexpr int EB = 32; };
 template <> struct Tile<3, 2, float, 2> { static constexpr int EB = 16; };
 template <> struct Tile<3, 3, float, 2> { static constexpr int EB = 6; };
 // Hadamard form
-template <> struct Tile<3, 1, double, 1> { static constexpr int EB = 24; };
-template <> struct Tile<3, 2, double, 1> { static constexpr int EB = 8; };
-template <> struct Tile<3, 3, double, 1> { static constexpr int EB = 1; };
-template <> struct Tile<3, 1, float, 1> { static constexpr int EB = 32; };
-template <> struct Tile<3, 2, float, 1> { static constexpr int EB = 16; };
-template <> struct Tile<3, 3, float, 1> { static constexpr int EB = 2; };
-template <> struct Tile<2, 1, double, 1> { static constexpr int EB = 64; };
-template <> struct Tile<2, 2, double, 1> { static constexpr int EB = 32; };
-template <> struct Tile<2, 3, double, 1> { static constexpr int EB = 16; };
-template <> struct Tile<2, 4, double, 1> { static constexpr int EB = 12; };
-template <> struct Tile<2, 1, float, 1> { static constexpr int EB = 64; };
-template <> struct Tile<2, 2, float, 1> { static constexpr int EB = 64; };
-template <> struct Tile<2, 3, float, 1> { static constexpr int EB = 32; };
-template <> struct Tile<2, 4, float, 1> { static constexpr int EB = 24; };
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
@@ -521,332 +507,143 @@ __global__ __launch_bounds__(kThreads) void k_visc_q3(KArgs<T> A) {
 // split terms
 //   sum_i [c_b Q_xi + Q_xi^T] f^(i) = 1/2 sum_l [ sum_i Lambda_il o (M_l f^(i)) + M_l fhat_l ]
 //   Q_xi w                           = 1/2 sum_l [ Lambda_il o (Q_l w) + Q_l (Lambda_il o w) ]
-// become
-//   vol   = (c_b - 1)/2 V + (c_b + 1)/2 sum_i a_i f^(i),
-//           V = sum_l [ Lambda_0l o S_l f0 + Lambda_1l o S_l f1 + S_l fhat_l ]
-//   Q_xi w = 1/2 X_i + 1/2 a_i w,  X_i = sum_l [ Lambda_il o S_l w + S_l (Lambda_il o w) ]
-// with a_i = sum_l Lambda_il E_l (the facet B n_i, zero off the facets).  Only
-// the two skew operators enter the MFMA contractions, so every wave keeps
-// their A fragments in registers for the whole (persistent) launch.
-//
-// Each wave works alone on groups of EW = 4 CT elements (16 MFMA columns =
-// 4 elements x 4 components per column tile) with its own LDS region, so the
-// four waves of a workgroup drift apart and overlap MFMA and VALU phases.
-template <int P, typename T> struct Wave2;
-template <> struct Wave2<1, double> { static constexpr int CT = 2; };
-template <> struct Wave2<2, double> { static constexpr int CT = 2; };
-template <> struct Wave2<3, double> { static constexpr int CT = 1; };
-template <> struct Wave2<4, double> { static constexpr int CT = 1; };
-template <> struct Wave2<1, float> { static constexpr int CT = 4; };
-template <> struct Wave2<2, float> { static constexpr int CT = 2; };
-template <> struct Wave2<3, float> { static constexpr int CT = 1; };
-template <> struct Wave2<4, float> { static constexpr int CT = 1; };
-
-// Node record from stored primitives and z1 (entropy variables rebuilt
-// without transcendentals); P1, P2 are filled by the caller where needed.
-template <int D, typename T>
-__device__ __forceinline__ void node_from_prims(T rho, const T *V, T p, T z1, const GasC<T> &G, Node<D, T> &n) {
-  n.rho = rho;
-  T q2 = 0;
-#pragma unroll
-  for (int i = 0; i < D; ++i) {
-    n.V[i] = V[i];
-    q2 += V[i] * V[i];
-  }
-  n.p = p;
-  n.z1 = z1;
-  n.lrho = n.lp = n.lz1 = n.P1 = n.P2 = (T)0;
-  n.ok = true;
-  n.w[0] = z1 * (G.wfirst * (p / rho) - (T)0.5 * q2);
-#pragma unroll
-  for (int i = 0; i < D; ++i) n.w[1 + i] = z1 * V[i];
-  n.w[D + 1] = -z1;
-}
+// become, with a_i = sum_l Lambda_il E_l (the facet B n_i, zero off the facets),
+//   vol    = (c_b - 1)/2 V + (c_b + 1)/2 sum_m a_m f^(m)
+//   Q_xi w = 1/2 X_i + 1/2 a_i w
+// and, per node pair (i, j), onto the metric average Lambda(i) + Lambda(j):
+//   V_i   = sum_j sum_l S_l[i][j] sum_m (Lambda_ml(i) + Lambda_ml(j)) f^(m)_j
+//   X_k,i = sum_j sum_l S_l[i][j] (Lambda_kl(i) + Lambda_kl(j)) w_j
+// (20 FMAs per pair).  On MI355X an FP64 MFMA has the throughput of the FP64
+// vector ALUs, and the contraction form of the same terms issues about five
+// times these flops (six column groups per direction for curved metrics,
+// 16-row padding), so the pair sums run on the vector ALUs: one lane per node
+// row, the skew operators in LDS, the tile's node values (f^(0), f^(1), w,
+// Lambda) in LDS rows of 16 values per node.
+template <int P, typename T> struct VTile2;
+template <typename T> struct VTile2<1, T> { static constexpr int EB = 42; };
+template <typename T> struct VTile2<2, T> { static constexpr int EB = 25; };
+template <typename T> struct VTile2<3, T> { static constexpr int EB = 14; };
+template <typename T> struct VTile2<4, T> { static constexpr int EB = 11; };
 
 template <int P, typename T>
 struct Split2 {
   static constexpr int D = 2, NC = 4, NFAC = 3;
-  static constexpr int NP = Shape<2, P>::NP, NF = Shape<2, P>::NF, NFN = NFAC * NF;
-  static constexpr int KP = ru(NP, 4), MP = ru(NP, 16), MT = MP / 16, KS = KP / 4;
-  static constexpr int CT = Wave2<P, T>::CT, EW = 4 * CT, LD = 16 * CT;
-  static constexpr int NPW = EW * NP, NFW = EW * NFN;
-  // wave-private LDS of one group
+  static constexpr int NP = Shape<2, P>::NP, NF = Shape<2, P>::NF;
+  static constexpr int EB = VTile2<P, T>::EB;
+  static_assert(EB * NP <= kThreads, "one node per lane");
   struct Lds {
-    // [f0 | f1 | w][node][element x component], later [V | X_0 | X_1], then
-    // the volume part of r at the facet nodes (slot 0)
-    T B[3][KP][LD];
-    // Lambda_00, Lambda_01, Lambda_10, Lambda_11, J at [node][element]
-    T L[5][NP][EW];
-    // rho, V_0, V_1, p, z1, E at [node][element]
-    T Pr[6][NP][EW];
-    // z1^r1, p^r2 and the neighbour state at the facet nodes
-    T FP[2][NFN][EW];
-    T NU[NC][NFN][EW];
+    T S[2][NP][NP];
+    __align__(16) T nd[EB][NP][16];  // f0[4] f1[4] w[4] Lambda_00 _01 _10 _11
   };
 
-  // Residual of the EW elements of group grp; ent accumulates w^T H r.
-  __device__ static __forceinline__ void group(const KArgs<T> &A, Lds &S, int grp, int lane, double &ent) {
-    typedef typename MF<T>::v4 V4;
-    const int col = lane & 15, kr = lane >> 4;
-    T(*B)[KP][LD] = S.B;
-    T(*L)[NP][EW] = S.L;
-    T(*Pr)[NP][EW] = S.Pr;
-    T(*FP)[NFN][EW] = S.FP;
-    T(*NU)[NFN][EW] = S.NU;
+  __device__ static __forceinline__ void load_ops(const KArgs<T> &A, Lds &L) {
+    for (int x = threadIdx.x; x < 2 * NP * NP; x += kThreads) (&L.S[0][0][0])[x] = A.op.S[x];
+  }
+
+  // Residual of the elements [tile*EB, tile*EB + EB); ent accumulates w^T H r.
+  // Call with the operators loaded (load_ops, then a barrier).
+  __device__ static __forceinline__ void tile(const KArgs<T> &A, Lds &L, int tl, double &ent) {
+    const int tid = threadIdx.x;
+    const int e0 = tl * EB;
+    const int ne = min(EB, A.n_elem - e0);
+    const bool act = tid < ne * NP;
+    const int e = tid / NP, i = tid % NP;
     const T cb = A.G.cb;
     const T hv = (T)0.5 * (cb - (T)1), he = (T)0.5 * (cb + (T)1);
-    const int e0 = grp * EW;
-    wave_lds_sync();
-    // the padding rows k >= NP of B stay zero through the group
-    for (int x = lane; x < 3 * (KP - NP) * LD; x += 64) {
-      const int q = x / ((KP - NP) * LD), y = x % ((KP - NP) * LD);
-      B[q][NP + y / LD][y % LD] = (T)0;
-    }
-    wave_lds_sync();
-    // neighbour states at the facet nodes
-    for (int x = lane; x < NFW; x += 64) {
-      const int e = x / NFN, m = x % NFN, eg = e0 + e;
-      if (eg < A.n_elem) {
-        const int off = A.nbr[(size_t)eg * NFN + m];
+    Node<D, T> n;
+    T lam[4], J = (T)1, f0[NC], f1[NC];
+    if (act) {
+      const double *g = A.geo + (size_t)(e0 + e) * 12;
+      T F[2][2] = {{0, 0}, {0, 0}};
 #pragma unroll
-        for (int c = 0; c < NC; ++c) NU[c][m][e] = (T)A.u[off + c * NP];
+      for (int a = 0; a < 6; ++a) {
+        const T d0 = A.op.dN[(0 * 6 + a) * NP + i], d1 = A.op.dN[(1 * 6 + a) * NP + i];
+        const T gx = (T)g[2 * a], gy = (T)g[2 * a + 1];
+        F[0][0] += d0 * gx;
+        F[0][1] += d1 * gx;
+        F[1][0] += d0 * gy;
+        F[1][1] += d1 * gy;
       }
-    }
-    // pointwise: metrics, primitives, fluxes and entropy variables (zeros past
-    // the last element), flux powers at the facet nodes
-    for (int x = lane; x < NPW; x += 64) {
-      const int e = x / NP, j = x % NP, eg = e0 + e;
-      T f0[NC], f1[NC], w[NC], lam[5];
-      if (eg < A.n_elem) {
-        const double *g = A.geo + (size_t)eg * 12;
-        T F[2][2] = {{0, 0}, {0, 0}};
+      lam[0] = F[1][1];   // Lambda_00 = J dxi_0/dx_0
+      lam[1] = -F[1][0];  // Lambda_01
+      lam[2] = -F[0][1];  // Lambda_10
+      lam[3] = F[0][0];   // Lambda_11
+      J = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+      const int uo = A.uoff[e0 + e];
+      T uu[NC];
 #pragma unroll
-        for (int a = 0; a < 6; ++a) {
-          const T d0 = A.op.dN[(0 * 6 + a) * NP + j], d1 = A.op.dN[(1 * 6 + a) * NP + j];
-          const T gx = (T)g[2 * a], gy = (T)g[2 * a + 1];
-          F[0][0] += d0 * gx;
-          F[0][1] += d1 * gx;
-          F[1][0] += d0 * gy;
-          F[1][1] += d1 * gy;
-        }
-        lam[0] = F[1][1];   // Lambda_00 = J dxi_0/dx_0
-        lam[1] = -F[1][0];  // Lambda_01
-        lam[2] = -F[0][1];  // Lambda_10
-        lam[3] = F[0][0];   // Lambda_11
-        lam[4] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
-        const int uo = A.uoff[eg];
-        T uu[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) uu[c] = (T)A.u[uo + c * NP + j];
-        Node<D, T> n;
-        node_from_u<D, T>(uu, A.G, n);
-        if (!n.ok) atomicOr(A.err, 1);
-        flux_i<D, T>(n, uu[NC - 1], 0, f0);
-        flux_i<D, T>(n, uu[NC - 1], 1, f1);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) w[c] = n.w[c];
-        Pr[0][j][e] = n.rho;
-        Pr[1][j][e] = n.V[0];
-        Pr[2][j][e] = n.V[1];
-        Pr[3][j][e] = n.p;
-        Pr[4][j][e] = n.z1;
-        Pr[5][j][e] = uu[NC - 1];
-        if (j < NFN) {
-          node_powers<D, T>(A.G, n);
-          FP[0][j][e] = n.P1;
-          FP[1][j][e] = n.P2;
-        }
-      } else {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) f0[c] = f1[c] = w[c] = (T)0;
-#pragma unroll
-        for (int q = 0; q < 5; ++q) lam[q] = (T)0;
-      }
+      for (int c = 0; c < NC; ++c) uu[c] = (T)A.u[uo + c * NP + i];
+      node_from_u<D, T>(uu, A.G, n);
+      if (!n.ok) atomicOr(A.err, 1);
+      flux_i<D, T>(n, uu[NC - 1], 0, f0);
+      flux_i<D, T>(n, uu[NC - 1], 1, f1);
+      T *v = L.nd[e][i];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        B[0][j][e * NC + c] = f0[c];
-        B[1][j][e * NC + c] = f1[c];
-        B[2][j][e * NC + c] = w[c];
+        v[c] = f0[c];
+        v[4 + c] = f1[c];
+        v[8 + c] = n.w[c];
       }
 #pragma unroll
-      for (int q = 0; q < 5; ++q) L[q][j][e] = lam[q];
+      for (int q = 0; q < 4; ++q) v[12 + q] = lam[q];
     }
-    // A fragments of S_0, S_1: lane holds S_l[mt*16 + col][4 ks + kr]
-    T sf[2][MT][KS];
+    __syncthreads();
+    if (act) {
+      T V[NC], X0[NC], X1[NC];
 #pragma unroll
-    for (int l = 0; l < 2; ++l)
+      for (int c = 0; c < NC; ++c) V[c] = X0[c] = X1[c] = (T)0;
+#pragma unroll 2
+      for (int j = 0; j < NP; ++j) {
+        const T s0 = L.S[0][i][j], s1 = L.S[1][i][j];
+        const T *v = L.nd[e][j];
+        const T c0 = s0 * (lam[0] + v[12]) + s1 * (lam[1] + v[13]);
+        const T c1 = s0 * (lam[2] + v[14]) + s1 * (lam[3] + v[15]);
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          const int m = mt * 16 + col, k = 4 * ks + kr;
-          sf[l][mt][ks] = (m < NP && k < NP) ? A.op.S[(l * NP + m) * NP + k] : (T)0;
+        for (int c = 0; c < NC; ++c) {
+          V[c] += c0 * v[c] + c1 * v[4 + c];
+          X0[c] += c0 * v[8 + c];
+          X1[c] += c1 * v[8 + c];
         }
-    wave_lds_sync();
-    // skew contractions: V, X_0, X_1 per column tile, rows in the accumulators.
-    // Column groups g: S_l f0, S_l f1, S_l fhat_l, S_l w, S_l (Lambda_0l w),
-    // S_l (Lambda_1l w); one group at a time keeps few accumulators live.
-    V4 vo[CT][MT], x0[CT][MT], x1[CT][MT];
-#pragma unroll
-    for (int t = 0; t < CT; ++t) {
-      const int cc = t * 16 + col, el = t * 4 + (col >> 2);
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) vo[t][mt] = x0[t][mt] = x1[t][mt] = V4{0, 0, 0, 0};
-#pragma unroll
-      for (int l = 0; l < 2; ++l)
-#pragma unroll
-        for (int g = 0; g < 6; ++g) {
-          V4 acc[MT];
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt) acc[mt] = V4{0, 0, 0, 0};
-#pragma unroll
-          for (int ks = 0; ks < KS; ++ks) {
-            const int k = 4 * ks + kr;
-            // rows k >= NP of B are zero; Lambda is not stored there
-            const bool in = 4 * ks + 3 < NP || k < NP;
-            const T la = in ? L[l][k][el] : (T)0, lb = in ? L[2 + l][k][el] : (T)0;
-            T b;
-            if (g == 0) b = B[0][k][cc];
-            else if (g == 1) b = B[1][k][cc];
-            else if (g == 2) b = la * B[0][k][cc] + lb * B[1][k][cc];
-            else if (g == 3) b = B[2][k][cc];
-            else if (g == 4) b = la * B[2][k][cc];
-            else b = lb * B[2][k][cc];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) acc[mt] = MF<T>::mma(sf[l][mt][ks], b, acc[mt]);
-          }
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int ii = 0; ii < 4; ++ii) {
-              const int row = mt * 16 + MF<T>::row(kr, ii);
-              if (row < NP) {
-                const T v = acc[mt][ii];
-                if (g == 0) vo[t][mt][ii] += L[l][row][el] * v;
-                else if (g == 1) vo[t][mt][ii] += L[2 + l][row][el] * v;
-                else if (g == 2) vo[t][mt][ii] += v;
-                else if (g == 3) {
-                  x0[t][mt][ii] += L[l][row][el] * v;
-                  x1[t][mt][ii] += L[2 + l][row][el] * v;
-                } else if (g == 4) x0[t][mt][ii] += v;
-                else x1[t][mt][ii] += v;
-              }
-            }
-          __builtin_amdgcn_sched_barrier(0);
-        }
-    }
-    wave_lds_sync();
-#pragma unroll
-    for (int t = 0; t < CT; ++t)
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int ii = 0; ii < 4; ++ii) {
-          const int row = mt * 16 + MF<T>::row(kr, ii);
-          if (row < NP) {
-            B[0][row][t * 16 + col] = vo[t][mt][ii];
-            B[1][row][t * 16 + col] = x0[t][mt][ii];
-            B[2][row][t * 16 + col] = x1[t][mt][ii];
-          }
-        }
-    wave_lds_sync();
-    // per node: combine and apply A~_i as directional derivatives; interior
-    // nodes are final, facet nodes keep their volume part in LDS
-    for (int x = lane; x < NPW; x += 64) {
-      const int e = x / NP, i = x % NP, eg = e0 + e;
-      if (eg >= A.n_elem) continue;
-      const T Vn[2] = {Pr[1][i][e], Pr[2][i][e]};
-      Node<D, T> n;
-      node_from_prims<D, T>(Pr[0][i][e], Vn, Pr[3][i][e], Pr[4][i][e], A.G, n);
-      T f0[NC], f1[NC];
-      flux_i<D, T>(n, Pr[5][i][e], 0, f0);
-      flux_i<D, T>(n, Pr[5][i][e], 1, f1);
+      }
       const T E0 = A.op.E[i], E1 = A.op.E[NP + i];
       T avec[D];
-      avec[0] = L[0][i][e] * E0 + L[1][i][e] * E1;
-      avec[1] = L[2][i][e] * E0 + L[3][i][e] * E1;
-      const T H = L[4][i][e] * A.op.h[i];
+      avec[0] = lam[0] * E0 + lam[1] * E1;
+      avec[1] = lam[2] * E0 + lam[3] * E1;
+      const T H = J * (T)A.op.h[i];
       const T iH = (T)1 / H;
       T r[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        r[c] = iH * (hv * B[0][i][e * NC + c] + he * (avec[0] * f0[c] + avec[1] * f1[c]));
+      for (int c = 0; c < NC; ++c) r[c] = iH * (hv * V[c] + he * (avec[0] * f0[c] + avec[1] * f1[c]));
 #pragma unroll
       for (int dir = 0; dir < D; ++dir) {
-        T g[NC], tt[NC];
+        T gg[NC], tt[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) g[c] = (T)0.5 * iH * (B[1 + dir][i][e * NC + c] + avec[dir] * n.w[c]);
-        jvp_flux<D, T>(n, A.G, dir, g, tt);
+        for (int c = 0; c < NC; ++c) gg[c] = (T)0.5 * iH * ((dir == 0 ? X0[c] : X1[c]) + avec[dir] * n.w[c]);
+        jvp_flux<D, T>(n, A.G, dir, gg, tt);
 #pragma unroll
         for (int c = 0; c < NC; ++c) r[c] -= cb * tt[c];
       }
-      if (i < NFN) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) B[0][i][e * NC + c] = r[c];
-      } else {
-        const int uo = A.uoff[eg];
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          A.r[uo + c * NP + i] = r[c];
-          s += (double)n.w[c] * (double)r[c];
-        }
-        ent += (double)H * s;
-      }
+      finish_node<D, NP, NF, T>(A, e0 + e, i, n, H, avec, r, ent);
     }
-    wave_lds_sync();
-    // facet SATs (Sec. 4): one lane per facet node
-    for (int x = lane; x < NFW; x += 64) {
-      const int e = x / NFN, i = x % NFN, eg = e0 + e;
-      if (eg >= A.n_elem) continue;
-      const T Vn[2] = {Pr[1][i][e], Pr[2][i][e]};
-      Node<D, T> n;
-      node_from_prims<D, T>(Pr[0][i][e], Vn, Pr[3][i][e], Pr[4][i][e], A.G, n);
-      n.P1 = FP[0][i][e];
-      n.P2 = FP[1][i][e];
-      T uv[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) uv[c] = NU[c][i][e];
-      Node<D, T> nv;
-      node_from_u<D, T>(uv, A.G, nv);
-      if (!nv.ok) atomicOr(A.err, 1);
-      node_powers<D, T>(A.G, nv);
-      const T E0 = A.op.E[i], E1 = A.op.E[NP + i];
-      T avec[D];
-      avec[0] = L[0][i][e] * E0 + L[1][i][e] * E1;
-      avec[1] = L[2][i][e] * E0 + L[3][i][e] * E1;
-      const T H = L[4][i][e] * A.op.h[i];
-      const T iH = (T)1 / H;
-      T ft[NC];
-      facet_term<D, T>(n, nv, avec, A.G, A.diss != 0, ft);
-      const int uo = A.uoff[eg];
-      double s = 0.0;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const T r = B[0][i][e * NC + c] - ft[c] * iH;
-        A.r[uo + c * NP + i] = r;
-        s += (double)n.w[c] * (double)r;
-      }
-      ent += (double)H * s;
-    }
+    __syncthreads();
   }
 };
 
 template <int P, typename T>
-__global__ __launch_bounds__(kThreads) void k_split2(KArgs<T> A) {
+__global__ __launch_bounds__(kThreads, P == 1 ? 2 : 3) void k_split2(KArgs<T> A) {
   typedef Split2<P, T> K;
-  __shared__ typename K::Lds lds[kWaves];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ typename K::Lds lds;
+  K::load_ops(A, lds);
+  __syncthreads();
   double ent = 0.0;
-  const int ngroups = (A.n_elem + K::EW - 1) / K::EW;
-  for (int grp = blockIdx.x * kWaves + wave; grp < ngroups; grp += gridDim.x * kWaves)
-    K::group(A, lds[wave], grp, lane, ent);
+  const int ntiles = (A.n_elem + K::EB - 1) / K::EB;
+  for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) K::tile(A, lds, tl, ent);
   block_sum_store(ent, A.ent_part);
 }
 
 // All degree classes of a 2D mesh (batched problems) in one persistent
-// launch: the group index runs over the classes in degree order and every
-// wave dispatches on the degree of its group.
+// launch: the tile index runs over the classes in degree order; a workgroup
+// restages the skew operators when its tile changes degree.
 template <typename T>
 constexpr size_t split2_lds_max() {
   size_t m = sizeof(typename Split2<1, T>::Lds);
@@ -857,180 +654,174 @@ constexpr size_t split2_lds_max() {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_split2_batch(Batch2<T> Bt) {
-  constexpr size_t LW = (split2_lds_max<T>() + 15) / 16 * 16;
-  __shared__ __align__(16) unsigned char raw[kWaves * LW];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  void *mine = raw + wave * LW;
+__global__ __launch_bounds__(kThreads, 2) void k_split2_batch(Batch2<T> Bt) {
+  __shared__ __align__(16) unsigned char raw[split2_lds_max<T>()];
   double ent = 0.0;
-  for (int g = blockIdx.x * kWaves + wave; g < Bt.g0[4]; g += gridDim.x * kWaves) {
-    if (g < Bt.g0[1])
-      Split2<1, T>::group(Bt.c[0], *(typename Split2<1, T>::Lds *)mine, g, lane, ent);
-    else if (g < Bt.g0[2])
-      Split2<2, T>::group(Bt.c[1], *(typename Split2<2, T>::Lds *)mine, g - Bt.g0[1], lane, ent);
-    else if (g < Bt.g0[3])
-      Split2<3, T>::group(Bt.c[2], *(typename Split2<3, T>::Lds *)mine, g - Bt.g0[2], lane, ent);
-    else
-      Split2<4, T>::group(Bt.c[3], *(typename Split2<4, T>::Lds *)mine, g - Bt.g0[3], lane, ent);
+  int cur = -1;
+  for (int g = blockIdx.x; g < Bt.g0[4]; g += gridDim.x) {
+    const int q = g < Bt.g0[1] ? 0 : (g < Bt.g0[2] ? 1 : (g < Bt.g0[3] ? 2 : 3));
+    if (q != cur) {
+      __syncthreads();
+      if (q == 0) Split2<1, T>::load_ops(Bt.c[0], *(typename Split2<1, T>::Lds *)raw);
+      else if (q == 1) Split2<2, T>::load_ops(Bt.c[1], *(typename Split2<2, T>::Lds *)raw);
+      else if (q == 2) Split2<3, T>::load_ops(Bt.c[2], *(typename Split2<3, T>::Lds *)raw);
+      else Split2<4, T>::load_ops(Bt.c[3], *(typename Split2<4, T>::Lds *)raw);
+      __syncthreads();
+      cur = q;
+    }
+    if (q == 0) Split2<1, T>::tile(Bt.c[0], *(typename Split2<1, T>::Lds *)raw, g, ent);
+    else if (q == 1) Split2<2, T>::tile(Bt.c[1], *(typename Split2<2, T>::Lds *)raw, g - Bt.g0[1], ent);
+    else if (q == 2) Split2<3, T>::tile(Bt.c[2], *(typename Split2<3, T>::Lds *)raw, g - Bt.g0[2], ent);
+    else Split2<4, T>::tile(Bt.c[3], *(typename Split2<4, T>::Lds *)raw, g - Bt.g0[3], ent);
   }
   block_sum_store(ent, Bt.ent_part);
 }
 
 // ---------------------------------------------------------------------------
 // Hadamard form (comparator): r_m = -H_m^-1 sum_{n != m} sum_l S_l[m][n]
-//   sum_i (Lambda_il(m) + Lambda_il(n)) F*_i(u_m, u_n), pairs evaluated once.
+//   sum_i (Lambda_il(m) + Lambda_il(n)) F*_i(u_m, u_n).
+// One lane per node row: the lane sums the two-point fluxes of its row over
+// all other nodes of the element (each pair is evaluated by both of its
+// rows; no atomics, fixed order, no pair buffer).  The skew operators are
+// staged in LDS once per persistent workgroup; node values (V, p, z1 and the
+// flux powers) of the tile sit in LDS with the node index fastest.
+template <int DIM, int P, typename T> struct HadTile;
+template <> struct HadTile<2, 1, double> { static constexpr int EB = 42; };
+template <> struct HadTile<2, 2, double> { static constexpr int EB = 25; };
+template <> struct HadTile<2, 3, double> { static constexpr int EB = 14; };
+template <> struct HadTile<2, 4, double> { static constexpr int EB = 11; };
+template <> struct HadTile<3, 1, double> { static constexpr int EB = 21; };
+template <> struct HadTile<3, 2, double> { static constexpr int EB = 20; };
+template <> struct HadTile<3, 3, double> { static constexpr int EB = 8; };
+template <> struct HadTile<2, 1, float> { static constexpr int EB = 42; };
+template <> struct HadTile<2, 2, float> { static constexpr int EB = 25; };
+template <> struct HadTile<2, 3, float> { static constexpr int EB = 14; };
+template <> struct HadTile<2, 4, float> { static constexpr int EB = 11; };
+template <> struct HadTile<3, 1, float> { static constexpr int EB = 21; };
+template <> struct HadTile<3, 2, float> { static constexpr int EB = 20; };
+template <> struct HadTile<3, 3, float> { static constexpr int EB = 8; };
+
 template <int DIM, int P, typename T>
 __global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
-  constexpr int D = DIM, NC = D + 2, NFAC = D + 1;
+  constexpr int D = DIM, NC = D + 2;
   constexpr int NP = Shape<DIM, P>::NP, NF = Shape<DIM, P>::NF;
-  constexpr int EB = Tile<DIM, P, T, 1>::EB;
-  constexpr int NPAIR = NP * (NP - 1) / 2;
-  constexpr int NV = D + 5;  // rho, V, p, z1, P1, P2
-  constexpr int NMET = D * D + 1;
-  __shared__ T Gp[EB * NPAIR * NC];
-  __shared__ T nd[EB * NP * NV];
-  __shared__ T met[EB * NP * NMET];
-  __shared__ T us[EB * NC * NP];
-  __shared__ short2 pairs[NPAIR];
-  __shared__ T hs[NP];
-  __shared__ T Es[D * NP];
+  constexpr int EB = HadTile<DIM, P, T>::EB;
+  constexpr int NV = D + 4;  // V, p, z1, P1, P2
+  constexpr int NT = (EB * NP + kThreads - 1) / kThreads;
+  constexpr int NM = DIM == 2 ? 5 : 1;
+  __shared__ T Ss[D][NP][NP];
+  __shared__ T nd[NV][EB][NP];
+  __shared__ T met[NM][EB][DIM == 2 ? NP : 1];  // 2D: Lambda_00, _01, _10, _11, J per node
+  __shared__ T gm[EB][10];                      // 3D: Lambda (row i, col l), J per element
   const int tid = threadIdx.x;
-  const int e0 = blockIdx.x * EB;
-  const int ne = min(EB, A.n_elem - e0);
-  for (int q = tid; q < NPAIR; q += kThreads) {
-    int m = 0, rem = q;
-    while (rem >= NP - 1 - m) {
-      rem -= NP - 1 - m;
-      ++m;
-    }
-    pairs[q] = make_short2((short)m, (short)(m + 1 + rem));
-  }
-  for (int x = tid; x < NP; x += kThreads) hs[x] = A.op.h[x];
-  for (int x = tid; x < D * NP; x += kThreads) Es[x] = A.op.E[x];
-  for (int x = tid; x < ne * NC * NP; x += kThreads) {
-    const int e = x / (NC * NP);
-    us[x] = (T)A.u[A.uoff[e0 + e] + x % (NC * NP)];
-  }
-  // metrics per node: Lambda (row i, col l) and J
-  for (int x = tid; x < ne * NP; x += kThreads) {
-    const int e = x / NP, j = x % NP;
-    T *m = met + (e * NP + j) * NMET;
-    if constexpr (D == 3) {
-      const double *g = A.geo + (size_t)(e0 + e) * 10;
-#pragma unroll
-      for (int k = 0; k < 10; ++k) m[k] = (T)g[k];
-    } else {
-      const double *g = A.geo + (size_t)(e0 + e) * 12;
-      T F[2][2] = {{0, 0}, {0, 0}};
-#pragma unroll
-      for (int a = 0; a < 6; ++a) {
-        const T d0 = A.op.dN[(0 * 6 + a) * NP + j], d1 = A.op.dN[(1 * 6 + a) * NP + j];
-        F[0][0] += d0 * (T)g[2 * a];
-        F[0][1] += d1 * (T)g[2 * a];
-        F[1][0] += d0 * (T)g[2 * a + 1];
-        F[1][1] += d1 * (T)g[2 * a + 1];
-      }
-      m[0] = F[1][1];
-      m[1] = -F[1][0];
-      m[2] = -F[0][1];
-      m[3] = F[0][0];
-      m[4] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
-    }
-  }
-  __syncthreads();
-  for (int x = tid; x < ne * NP; x += kThreads) {
-    const int e = x / NP, j = x % NP;
-    T uu[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + j];
-    Node<D, T> n;
-    node_from_u<D, T>(uu, A.G, n);
-    if (!n.ok) atomicOr(A.err, 1);
-    node_powers<D, T>(A.G, n);
-    T *v = nd + (e * NP + j) * NV;
-    v[0] = n.rho;
-#pragma unroll
-    for (int i = 0; i < D; ++i) v[1 + i] = n.V[i];
-    v[D + 1] = n.p;
-    v[D + 2] = n.z1;
-    v[D + 3] = n.P1;
-    v[D + 4] = n.P2;
-  }
-  __syncthreads();
-  for (int x = tid; x < ne * NPAIR; x += kThreads) {
-    const int e = x / NPAIR, q = x % NPAIR;
-    const short2 mn = pairs[q];
-    const int m = mn.x, nn = mn.y;
-    Node<D, T> a, b;
-    const T *va = nd + (e * NP + m) * NV;
-    const T *vb = nd + (e * NP + nn) * NV;
-    a.rho = va[0];
-    b.rho = vb[0];
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      a.V[i] = va[1 + i];
-      b.V[i] = vb[1 + i];
-    }
-    a.p = va[D + 1];
-    b.p = vb[D + 1];
-    a.z1 = va[D + 2];
-    b.z1 = vb[D + 2];
-    a.P1 = va[D + 3];
-    b.P1 = vb[D + 3];
-    a.P2 = va[D + 4];
-    b.P2 = vb[D + 4];
-    const T *ma = met + (e * NP + m) * NMET;
-    const T *mb = met + (e * NP + nn) * NMET;
-    T cvec[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      T s = 0;
-#pragma unroll
-      for (int l = 0; l < D; ++l) s += A.op.S[(l * NP + m) * NP + nn] * (ma[i * D + l] + mb[i * D + l]);
-      cvec[i] = s;
-    }
-    T out[NC];
-    facet_term<D, T>(a, b, cvec, A.G, false, out);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) Gp[(e * NPAIR + q) * NC + c] = out[c];
-  }
-  __syncthreads();
+  for (int x = tid; x < D * NP * NP; x += kThreads) (&Ss[0][0][0])[x] = A.op.S[x];
   double ent = 0.0;
-  for (int x = tid; x < ne * NP; x += kThreads) {
-    const int e = x / NP, i = x % NP;
-    T uu[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + i];
-    Node<D, T> n;
-    node_from_u<D, T>(uu, A.G, n);
-    const T *m = met + (e * NP + i) * NMET;
-    const T H = m[D * D] * hs[i];
-    const T iH = (T)1 / H;
-    T r[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) r[c] = 0;
-    // pairs (k, i) with k < i contribute -G_ki, pairs (i, k) with k > i +G_ik
-    for (int k = 0; k < i; ++k) {
-      const int q = k * NP - k * (k + 1) / 2 + (i - k - 1);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) r[c] += Gp[(e * NPAIR + q) * NC + c];
+  const int ntiles = (A.n_elem + EB - 1) / EB;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int e0 = tile * EB;
+    const int ne = min(EB, A.n_elem - e0);
+    __syncthreads();
+    if constexpr (DIM == 3) {
+      for (int x = tid; x < ne * 10; x += kThreads) gm[x / 10][x % 10] = (T)A.geo[(size_t)(e0 + x / 10) * 10 + x % 10];
     }
-    for (int k = i + 1; k < NP; ++k) {
-      const int q = i * NP - i * (i + 1) / 2 + (k - i - 1);
+    Node<D, T> nodes[NT];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) r[c] -= Gp[(e * NPAIR + q) * NC + c];
+    for (int kq = 0; kq < NT; ++kq) {
+      const int x = tid + kq * kThreads;
+      if (x >= ne * NP) break;
+      const int e = x / NP, j = x % NP;
+      const int uo = A.uoff[e0 + e];
+      T uu[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) uu[c] = (T)A.u[uo + c * NP + j];
+      Node<D, T> &n = nodes[kq];
+      node_from_u<D, T>(uu, A.G, n);
+      if (!n.ok) atomicOr(A.err, 1);
+      node_powers<D, T>(A.G, n);
+#pragma unroll
+      for (int i = 0; i < D; ++i) nd[i][e][j] = n.V[i];
+      nd[D][e][j] = n.p;
+      nd[D + 1][e][j] = n.z1;
+      nd[D + 2][e][j] = n.P1;
+      nd[D + 3][e][j] = n.P2;
+      if constexpr (DIM == 2) {
+        const double *g = A.geo + (size_t)(e0 + e) * 12;
+        T F[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+          const T d0 = A.op.dN[(0 * 6 + a) * NP + j], d1 = A.op.dN[(1 * 6 + a) * NP + j];
+          F[0][0] += d0 * (T)g[2 * a];
+          F[0][1] += d1 * (T)g[2 * a];
+          F[1][0] += d0 * (T)g[2 * a + 1];
+          F[1][1] += d1 * (T)g[2 * a + 1];
+        }
+        met[0][e][j] = F[1][1];
+        met[1][e][j] = -F[1][0];
+        met[2][e][j] = -F[0][1];
+        met[3][e][j] = F[0][0];
+        met[4][e][j] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+      }
     }
+    __syncthreads();
 #pragma unroll
-    for (int c = 0; c < NC; ++c) r[c] *= iH;
-    T avec[D];
+    for (int kq = 0; kq < NT; ++kq) {
+      const int x = tid + kq * kThreads;
+      if (x >= ne * NP) break;
+      const int e = x / NP, m = x % NP;
+      const Node<D, T> &a = nodes[kq];
+      T Lm[D][D], J;
+      if constexpr (DIM == 2) {
 #pragma unroll
-    for (int dir = 0; dir < D; ++dir) {
-      T s = 0;
+        for (int q = 0; q < 4; ++q) Lm[q / 2][q % 2] = met[q][e][m];
+        J = met[4][e][m];
+      } else {
 #pragma unroll
-      for (int l = 0; l < D; ++l) s += m[dir * D + l] * Es[l * NP + i];
-      avec[dir] = s;
+        for (int q = 0; q < 9; ++q) Lm[q / 3][q % 3] = gm[e][q];
+        J = gm[e][9];
+      }
+      T acc[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] = (T)0;
+      for (int nn = 0; nn < NP; ++nn) {
+        if (nn == m) continue;
+        Node<D, T> b;
+#pragma unroll
+        for (int i = 0; i < D; ++i) b.V[i] = nd[i][e][nn];
+        b.p = nd[D][e][nn];
+        b.z1 = nd[D + 1][e][nn];
+        b.P1 = nd[D + 2][e][nn];
+        b.P2 = nd[D + 3][e][nn];
+        T cvec[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          T s = 0;
+#pragma unroll
+          for (int l = 0; l < D; ++l) {
+            const T lsum = DIM == 2 ? Lm[i][l] + met[i * 2 + l][e][nn] : (T)2 * Lm[i][l];
+            s += Ss[l][m][nn] * lsum;
+          }
+          cvec[i] = s;
+        }
+        T out[NC];
+        facet_term<D, T>(a, b, cvec, A.G, false, out);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] += out[c];
+      }
+      const T H = J * (T)A.op.h[m];
+      const T iH = (T)1 / H;
+      T r[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) r[c] = -acc[c] * iH;
+      T avec[D];
+#pragma unroll
+      for (int dir = 0; dir < D; ++dir) {
+        T s = 0;
+#pragma unroll
+        for (int l = 0; l < D; ++l) s += Lm[dir][l] * (T)A.op.E[l * NP + m];
+        avec[dir] = s;
+      }
+      finish_node<D, NP, NF, T>(A, e0 + e, m, a, H, avec, r, ent);
     }
-    finish_node<D, NP, NF, T>(A, e0 + e, i, n, H, avec, r, ent);
   }
   block_sum_store(ent, A.ent_part);
 }
@@ -1039,12 +830,12 @@ __global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
 template <typename T>
 int tile_elems(int dim, int p, int form) {
 #define SBP_TILE(DI, PP) \
-  if (dim == DI && p == PP) return form == 1 ? Tile<DI, PP, T, 1>::EB : 0;
+  if (dim == DI && p == PP) return form == 1 ? HadTile<DI, PP, T>::EB : 0;
   SBP_TILE(2, 1) SBP_TILE(2, 2) SBP_TILE(2, 3) SBP_TILE(2, 4)
 #undef SBP_TILE
 #define SBP_TILE3(PP) \
   if (dim == 3 && p == PP) \
-    return form == 1 ? Tile<3, PP, T, 1>::EB : (form == 2 ? Tile<3, PP, T, 2>::EB : Tile<3, PP, T, 0>::EB);
+    return form == 1 ? HadTile<3, PP, T>::EB : (form == 2 ? Tile<3, PP, T, 2>::EB : Tile<3, PP, T, 0>::EB);
   SBP_TILE3(1) SBP_TILE3(2) SBP_TILE3(3)
 #undef SBP_TILE3
   return 0;
@@ -1065,7 +856,7 @@ static int split2_grid(int n_elem) {
     else
       cap = cus * per;
   }
-  const int per_block = kWaves * 4 * Wave2<P, T>::CT;
+  const int per_block = VTile2<P, T>::EB;
   return std::min((n_elem + per_block - 1) / per_block, cap);
 }
 
@@ -1087,8 +878,34 @@ static int split3_grid(int n_elem) {
   return std::min((n_elem + eb - 1) / eb, cap);
 }
 
+// Persistent grid of the Hadamard kernel.
+template <int DIM, int P, typename T>
+static int hadamard_grid(int n_elem) {
+  static int cap = 0;
+  if (cap == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_hadamard<DIM, P, T>, kThreads, 0) != hipSuccess ||
+        cus <= 0 || per <= 0)
+      cap = 1024;
+    else
+      cap = cus * per;
+  }
+  const int eb = HadTile<DIM, P, T>::EB;
+  return std::min((n_elem + eb - 1) / eb, cap);
+}
+
 int residual_blocks(int dim, int p, int precision, int form, int n_elem) {
   if (n_elem <= 0) return 0;
+  if (form == 1) {
+#define SBP_GH(DI, PP) \
+  if (dim == DI && p == PP) \
+    return precision == 0 ? hadamard_grid<DI, PP, double>(n_elem) : hadamard_grid<DI, PP, float>(n_elem);
+    SBP_GH(2, 1) SBP_GH(2, 2) SBP_GH(2, 3) SBP_GH(2, 4) SBP_GH(3, 1) SBP_GH(3, 2) SBP_GH(3, 3)
+#undef SBP_GH
+    return 0;
+  }
   if (dim == 3 && (form == 0 || form == 2)) {
 #define SBP_G3(PP)                                                                            \
   if (p == PP) {                                                                              \
@@ -1178,10 +995,10 @@ static int split2_batch_cap() {
 template <typename T>
 static int split2_ew(int p) {
   switch (p) {
-    case 1: return Split2<1, T>::EW;
-    case 2: return Split2<2, T>::EW;
-    case 3: return Split2<3, T>::EW;
-    default: return Split2<4, T>::EW;
+    case 1: return Split2<1, T>::EB;
+    case 2: return Split2<2, T>::EB;
+    case 3: return Split2<3, T>::EB;
+    default: return Split2<4, T>::EB;
   }
 }
 
@@ -1199,7 +1016,7 @@ int residual2_batch_blocks(const int n_elem_of_p[4], int precision) {
   int g0[5];
   const int ng = precision == 0 ? batch_groups<double>(n_elem_of_p, g0) : batch_groups<float>(n_elem_of_p, g0);
   const int cap = precision == 0 ? split2_batch_cap<double>() : split2_batch_cap<float>();
-  return std::min((ng + kWaves - 1) / kWaves, cap);
+  return std::min(ng, cap);
 }
 
 template <typename T>

@@ -84,6 +84,12 @@ def load_library(path: str = _LIB_PATH):
     return lib
 
 
+# torch is imported before the library is loaded so that one HIP runtime
+# serves both: libsbp.so binds to the runtime torch has already loaded.  If
+# the library were loaded first, the process would hold two HIP runtimes and
+# the library's would find no device.
+import torch  # noqa: E402,F401
+
 _lib = load_library()
 
 
