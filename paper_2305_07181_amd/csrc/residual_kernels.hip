@@ -425,6 +425,117 @@ __global__ __launch_bounds__(kThreads) void k_split3(KArgs<T> A) {
   block_sum_store(ent, A.ent_part);
 }
 
+// Entropy split on affine tetrahedra, row form on the vector ALUs (Euler
+// terms): per node pair (i, j)
+//   V_i   = sum_j sum_l S_l[i][j] fhat_l,j,   G_l,i = sum_j S_l[i][j] w_j
+// (30 FMAs per pair), then vol = (c_b - 1) V + (c_b + 1)/2 sum_l E_l fhat_l and
+// D_xi_l w = h^-1 (G_l + E_l w / 2).  One lane per node row; the skew
+// operators in LDS for the persistent launch; the tile's fhat and w in LDS.
+template <int P, typename T> struct VTile3;
+template <typename T> struct VTile3<1, T> { static constexpr int EB = 21; };
+template <typename T> struct VTile3<2, T> { static constexpr int EB = 10; };
+template <typename T> struct VTile3<3, T> { static constexpr int EB = 4; };
+
+template <int P, typename T>
+__global__ __launch_bounds__(kThreads, 2) void k_split3v(KArgs<T> A) {
+  constexpr int D = 3, NC = 5;
+  constexpr int NP = Shape<3, P>::NP, NF = Shape<3, P>::NF;
+  constexpr int EB = VTile3<P, T>::EB;
+  static_assert(EB * NP <= kThreads, "one node per lane");
+  __shared__ T Ss[3][NP][NP];
+  __shared__ T nd[EB][NP][20];  // fhat_1[5] fhat_2[5] fhat_3[5] w[5]
+  __shared__ T gs[EB][10];
+  const int tid = threadIdx.x;
+  for (int x = tid; x < 3 * NP * NP; x += kThreads) (&Ss[0][0][0])[x] = A.op.S[x];
+  const T cb = A.G.cb;
+  const T hv = cb - (T)1, he = (T)0.5 * (cb + (T)1);
+  double ent = 0.0;
+  const int ntiles = (A.n_elem + EB - 1) / EB;
+  const int e = tid / NP, i = tid % NP;
+  for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    const int e0 = tl * EB;
+    const int ne = min(EB, A.n_elem - e0);
+    const bool act = tid < ne * NP;
+    __syncthreads();
+    for (int x = tid; x < ne * 10; x += kThreads) gs[x / 10][x % 10] = (T)A.geo[(size_t)(e0 + x / 10) * 10 + x % 10];
+    __syncthreads();
+    Node<D, T> n;
+    T f[D][NC];
+    if (act) {
+      const int uo = A.uoff[e0 + e];
+      T uu[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) uu[c] = (T)A.u[uo + c * NP + i];
+      node_from_u<D, T>(uu, A.G, n);
+      if (!n.ok) atomicOr(A.err, 1);
+#pragma unroll
+      for (int m = 0; m < D; ++m) flux_i<D, T>(n, uu[NC - 1], m, f[m]);
+      const T *Lam = gs[e];
+      T *v = nd[e][i];
+#pragma unroll
+      for (int l = 0; l < D; ++l)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[l * NC + c] = Lam[0 * 3 + l] * f[0][c] + Lam[1 * 3 + l] * f[1][c] + Lam[2 * 3 + l] * f[2][c];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[15 + c] = n.w[c];
+    }
+    __syncthreads();
+    if (act) {
+      T V[NC], G[D][NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        V[c] = (T)0;
+#pragma unroll
+        for (int l = 0; l < D; ++l) G[l][c] = (T)0;
+      }
+#pragma unroll 2
+      for (int j = 0; j < NP; ++j) {
+        const T s0 = Ss[0][i][j], s1 = Ss[1][i][j], s2 = Ss[2][i][j];
+        const T *v = nd[e][j];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          V[c] += s0 * v[c] + s1 * v[5 + c] + s2 * v[10 + c];
+          G[0][c] += s0 * v[15 + c];
+          G[1][c] += s1 * v[15 + c];
+          G[2][c] += s2 * v[15 + c];
+        }
+      }
+      const T *Lam = gs[e];
+      const T J = Lam[9], iJ = (T)1 / J;
+      const T h = (T)A.op.h[i], ih = (T)1 / h;
+      const T H = J * h, iH = (T)1 / H;
+      T El[D];
+#pragma unroll
+      for (int l = 0; l < D; ++l) El[l] = A.op.E[l * NP + i];
+      T avec[D];
+#pragma unroll
+      for (int dir = 0; dir < D; ++dir)
+        avec[dir] = Lam[dir * 3 + 0] * El[0] + Lam[dir * 3 + 1] * El[1] + Lam[dir * 3 + 2] * El[2];
+      T r[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        r[c] = iH * (hv * V[c] + he * (avec[0] * f[0][c] + avec[1] * f[1][c] + avec[2] * f[2][c]));
+      T Dw[D][NC];
+#pragma unroll
+      for (int l = 0; l < D; ++l)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Dw[l][c] = (G[l][c] + (T)0.5 * El[l] * n.w[c]) * ih;
+#pragma unroll
+      for (int dir = 0; dir < D; ++dir) {
+        T g[NC], t[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          g[c] = (Lam[dir * 3 + 0] * Dw[0][c] + Lam[dir * 3 + 1] * Dw[1][c] + Lam[dir * 3 + 2] * Dw[2][c]) * iJ;
+        jvp_flux<D, T>(n, A.G, dir, g, t);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) r[c] -= cb * t[c];
+      }
+      finish_node<D, NP, NF, T>(A, e0 + e, i, n, H, avec, r, ent);
+    }
+  }
+  block_sum_store(ent, A.ent_part);
+}
+
 // Viscous facet-flux pre-pass, 3D affine: q = B n . F^V(w, grad w) at the
 // facet nodes of every element (grad w from the derivative GEMM).
 template <int P, typename T>
@@ -896,6 +1007,33 @@ static int hadamard_grid(int n_elem) {
   return std::min((n_elem + eb - 1) / eb, cap);
 }
 
+// Which form evaluates the 3D Euler split terms (measured on MI355X): the row
+// form, except at p = 3 in FP64, where its three 60 x 60 skew operators take
+// 86 KB of LDS and the contraction form with register-resident fragments is
+// faster.
+template <int P, typename T>
+constexpr bool row_form3() {
+  return !(P == 3 && sizeof(T) == 8);
+}
+
+// Persistent grid of the 3D row-form split kernel.
+template <int P, typename T>
+static int split3v_grid(int n_elem) {
+  static int cap = 0;
+  if (cap == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_split3v<P, T>, kThreads, 0) != hipSuccess ||
+        cus <= 0 || per <= 0)
+      cap = 1024;
+    else
+      cap = cus * per;
+  }
+  const int eb = VTile3<P, T>::EB;
+  return std::min((n_elem + eb - 1) / eb, cap);
+}
+
 int residual_blocks(int dim, int p, int precision, int form, int n_elem) {
   if (n_elem <= 0) return 0;
   if (form == 1) {
@@ -911,7 +1049,9 @@ int residual_blocks(int dim, int p, int precision, int form, int n_elem) {
   if (p == PP) {                                                                              \
     if (form == 2)                                                                            \
       return precision == 0 ? split3_grid<PP, double, true>(n_elem) : split3_grid<PP, float, true>(n_elem); \
-    return precision == 0 ? split3_grid<PP, double, false>(n_elem) : split3_grid<PP, float, false>(n_elem); \
+    if (precision == 0)                                                                       \
+      return row_form3<PP, double>() ? split3v_grid<PP, double>(n_elem) : split3_grid<PP, double, false>(n_elem); \
+    return row_form3<PP, float>() ? split3v_grid<PP, float>(n_elem) : split3_grid<PP, float, false>(n_elem); \
   }
     SBP_G3(1) SBP_G3(2) SBP_G3(3)
 #undef SBP_G3
@@ -951,6 +1091,8 @@ static hipError_t launch_t(int dim, int p, int form, const KArgs<T> &A, hipStrea
       hipLaunchKernelGGL((k_hadamard<3, PP, T>), grid, block, 0, s, A);  \
     else if (A.visc)                                                     \
       hipLaunchKernelGGL((k_split3<PP, T, true>), grid, block, 0, s, A); \
+    else if (row_form3<PP, T>())                                         \
+      hipLaunchKernelGGL((k_split3v<PP, T>), grid, block, 0, s, A);       \
     else                                                                 \
       hipLaunchKernelGGL((k_split3<PP, T, false>), grid, block, 0, s, A); \
     return hipGetLastError();                                            \
