@@ -443,7 +443,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_split3v(KArgs<T> A) {
   constexpr int EB = VTile3<P, T>::EB;
   static_assert(EB * NP <= kThreads, "one node per lane");
   __shared__ T Ss[3][NP][NP];
-  __shared__ T nd[EB][NP][20];  // fhat_1[5] fhat_2[5] fhat_3[5] w[5]
+  // per node: fhat_1[5] fhat_2[5] fhat_3[5] w[5]; element blocks padded so
+  // that the elements sharing a wave read different LDS banks
+  constexpr int NDS = NP * 20 + 4;
+  __shared__ T nd[EB * NDS];
   __shared__ T gs[EB][10];
   const int tid = threadIdx.x;
   for (int x = tid; x < 3 * NP * NP; x += kThreads) (&Ss[0][0][0])[x] = A.op.S[x];
@@ -471,7 +474,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_split3v(KArgs<T> A) {
 #pragma unroll
       for (int m = 0; m < D; ++m) flux_i<D, T>(n, uu[NC - 1], m, f[m]);
       const T *Lam = gs[e];
-      T *v = nd[e][i];
+      T *v = nd + e * NDS + i * 20;
 #pragma unroll
       for (int l = 0; l < D; ++l)
 #pragma unroll
@@ -491,7 +494,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_split3v(KArgs<T> A) {
 #pragma unroll 2
       for (int j = 0; j < NP; ++j) {
         const T s0 = Ss[0][i][j], s1 = Ss[1][i][j], s2 = Ss[2][i][j];
-        const T *v = nd[e][j];
+        const T *v = nd + e * NDS + j * 20;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           V[c] += s0 * v[c] + s1 * v[5 + c] + s2 * v[10 + c];
@@ -642,9 +645,12 @@ struct Split2 {
   static constexpr int NP = Shape<2, P>::NP, NF = Shape<2, P>::NF;
   static constexpr int EB = VTile2<P, T>::EB;
   static_assert(EB * NP <= kThreads, "one node per lane");
+  // node rows of 16 values; element blocks padded by 4 values so that the
+  // rows of the elements sharing a wave fall in different LDS banks
+  static constexpr int NDS = NP * 16 + 4;
   struct Lds {
     T S[2][NP][NP];
-    __align__(16) T nd[EB][NP][16];  // f0[4] f1[4] w[4] Lambda_00 _01 _10 _11
+    __align__(16) T nd[EB * NDS];  // per node: f0[4] f1[4] w[4] Lambda_00 _01 _10 _11
   };
 
   __device__ static __forceinline__ void load_ops(const KArgs<T> &A, Lds &L) {
@@ -688,7 +694,7 @@ struct Split2 {
       if (!n.ok) atomicOr(A.err, 1);
       flux_i<D, T>(n, uu[NC - 1], 0, f0);
       flux_i<D, T>(n, uu[NC - 1], 1, f1);
-      T *v = L.nd[e][i];
+      T *v = L.nd + e * NDS + i * 16;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         v[c] = f0[c];
@@ -703,10 +709,10 @@ struct Split2 {
       T V[NC], X0[NC], X1[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) V[c] = X0[c] = X1[c] = (T)0;
-#pragma unroll 2
+#pragma unroll 1
       for (int j = 0; j < NP; ++j) {
         const T s0 = L.S[0][i][j], s1 = L.S[1][i][j];
-        const T *v = L.nd[e][j];
+        const T *v = L.nd + e * NDS + j * 16;
         const T c0 = s0 * (lam[0] + v[12]) + s1 * (lam[1] + v[13]);
         const T c1 = s0 * (lam[2] + v[14]) + s1 * (lam[3] + v[15]);
 #pragma unroll
