@@ -37,8 +37,8 @@ PEAK_F32 = 157.3e12
 # (profiles/k_split2_tri32768_hbm_bytes.md); valid only for the kernel sources
 # they were taken on (sha256 prefix of the concatenated sources below).
 TRAFFIC_SOURCES = ["residual_kernels.hip", "device_physics.hpp", "mfma.hpp", "kernels.hpp"]
-TRAFFIC_SHA = "c08bd3da2c97f368"
-TRAFFIC_BYTES = {1: 25.88e6, 2: 51.87e6, 3: 79.61e6, 4: 83.15e6}
+TRAFFIC_SHA = "2cf268317daf89c9"
+TRAFFIC_BYTES = {1: 25.88e6, 2: 39.67e6, 3: 65.56e6, 4: 69.74e6}
 
 
 def _args():
@@ -346,8 +346,9 @@ def main():
                 r = torch.empty(u3.shape, dtype=torch.float32 if "fp32" in name else torch.float64, device="cuda")
                 med, _ = _time_calls(lambda: msh.residual(u3, r), 5, 2)
                 fl3, by3 = algorithmic_work(3, np3, {2: 6, 3: 12}[p], 4 if "fp32" in name else 8)
+                # fraction of the FP64 (or FP32) peak, vector and MFMA alike
                 row[name] = dict(ms=med * 1e3, elem_dof_per_s=ne3 * np3 / med,
-                                 mfma_frac=fl3 * ne3 / med / (PEAK_F32 if "fp32" in name else PEAK_F64),
+                                 flop_frac=fl3 * ne3 / med / (PEAK_F32 if "fp32" in name else PEAK_F64),
                                  hbm_frac=by3 * ne3 / med / PEAK_HBM)
                 if msh is not m64:
                     msh.close()
