@@ -159,8 +159,10 @@ __device__ __forceinline__ void finish_node(const KArgs<T> &A, int eg, int i, co
 //   y_j = sum_i K~_ij^T (B n_i (w_k - w_v)) at facet nodes, plus the facet
 //   flux jump -1/2 H^-1 (q_k + q_v), q = B n . F^V from the pre-pass.
 //
-// A workgroup takes a tile of CT column tiles (3 elements x 5 components per
-// 16 columns); wave w owns row tile mt = w % MT of the operators (its A
+// This contraction kernel serves the Navier-Stokes residual (VISC); the Euler
+// terms alone run in the row form (k_split3v).  A workgroup takes a tile of
+// CT column tiles (3 elements x 5 components per 16 columns); wave w owns row
+// tile mt = w % MT of the operators (its A
 // fragments of S_1, S_2, S_3 stay in registers for the whole persistent
 // launch) and the column tiles t = w / MT (mod 4 / MT).
 template <int P, typename T> struct Wave3;
@@ -436,20 +438,22 @@ template <typename T> struct VTile3<1, T> { static constexpr int EB = 21; };
 template <typename T> struct VTile3<2, T> { static constexpr int EB = 10; };
 template <typename T> struct VTile3<3, T> { static constexpr int EB = 4; };
 
-template <int P, typename T>
+template <int P, typename T, bool SG = false>
 __global__ __launch_bounds__(kThreads, 2) void k_split3v(KArgs<T> A) {
   constexpr int D = 3, NC = 5;
   constexpr int NP = Shape<3, P>::NP, NF = Shape<3, P>::NF;
   constexpr int EB = VTile3<P, T>::EB;
   static_assert(EB * NP <= kThreads, "one node per lane");
-  __shared__ T Ss[3][NP][NP];
+  // SG: the skew operators are read through the caches instead of LDS
+  __shared__ T Ss[SG ? 1 : 3][SG ? 1 : NP][SG ? 1 : NP];
   // per node: fhat_1[5] fhat_2[5] fhat_3[5] w[5]; element blocks padded so
   // that the elements sharing a wave read different LDS banks
   constexpr int NDS = NP * 20 + 4;
   __shared__ T nd[EB * NDS];
   __shared__ T gs[EB][10];
   const int tid = threadIdx.x;
-  for (int x = tid; x < 3 * NP * NP; x += kThreads) (&Ss[0][0][0])[x] = A.op.S[x];
+  if constexpr (!SG)
+    for (int x = tid; x < 3 * NP * NP; x += kThreads) (&Ss[0][0][0])[x] = A.op.S[x];
   const T cb = A.G.cb;
   const T hv = cb - (T)1, he = (T)0.5 * (cb + (T)1);
   double ent = 0.0;
@@ -493,7 +497,16 @@ __global__ __launch_bounds__(kThreads, 2) void k_split3v(KArgs<T> A) {
       }
 #pragma unroll 2
       for (int j = 0; j < NP; ++j) {
-        const T s0 = Ss[0][i][j], s1 = Ss[1][i][j], s2 = Ss[2][i][j];
+        T s0, s1, s2;
+        if constexpr (SG) {
+          s0 = A.op.S[(0 * NP + i) * NP + j];
+          s1 = A.op.S[(1 * NP + i) * NP + j];
+          s2 = A.op.S[(2 * NP + i) * NP + j];
+        } else {
+          s0 = Ss[0][i][j];
+          s1 = Ss[1][i][j];
+          s2 = Ss[2][i][j];
+        }
         const T *v = nd + e * NDS + j * 20;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -1013,13 +1026,13 @@ static int hadamard_grid(int n_elem) {
   return std::min((n_elem + eb - 1) / eb, cap);
 }
 
-// Which form evaluates the 3D Euler split terms (measured on MI355X): the row
-// form, except at p = 3 in FP64, where its three 60 x 60 skew operators take
-// 86 KB of LDS and the contraction form with register-resident fragments is
-// faster.
+// The 3D Euler split terms run in the row form.  At p = 3 in FP64 its three
+// 60 x 60 skew operators would take 86 KB of LDS (one wave per SIMD); there
+// they are read through the caches instead (measured on MI355X: 2.82 ms
+// against 2.97 ms for the contraction form on 196608 tetrahedra).
 template <int P, typename T>
-constexpr bool row_form3() {
-  return !(P == 3 && sizeof(T) == 8);
+constexpr bool skew_from_cache3() {
+  return P == 3 && sizeof(T) == 8;
 }
 
 // Persistent grid of the 3D row-form split kernel.
@@ -1030,7 +1043,7 @@ static int split3v_grid(int n_elem) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_split3v<P, T>, kThreads, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_split3v<P, T, skew_from_cache3<P, T>()>, kThreads, 0) != hipSuccess ||
         cus <= 0 || per <= 0)
       cap = 1024;
     else
@@ -1055,9 +1068,7 @@ int residual_blocks(int dim, int p, int precision, int form, int n_elem) {
   if (p == PP) {                                                                              \
     if (form == 2)                                                                            \
       return precision == 0 ? split3_grid<PP, double, true>(n_elem) : split3_grid<PP, float, true>(n_elem); \
-    if (precision == 0)                                                                       \
-      return row_form3<PP, double>() ? split3v_grid<PP, double>(n_elem) : split3_grid<PP, double, false>(n_elem); \
-    return row_form3<PP, float>() ? split3v_grid<PP, float>(n_elem) : split3_grid<PP, float, false>(n_elem); \
+    return precision == 0 ? split3v_grid<PP, double>(n_elem) : split3v_grid<PP, float>(n_elem); \
   }
     SBP_G3(1) SBP_G3(2) SBP_G3(3)
 #undef SBP_G3
@@ -1097,10 +1108,8 @@ static hipError_t launch_t(int dim, int p, int form, const KArgs<T> &A, hipStrea
       hipLaunchKernelGGL((k_hadamard<3, PP, T>), grid, block, 0, s, A);  \
     else if (A.visc)                                                     \
       hipLaunchKernelGGL((k_split3<PP, T, true>), grid, block, 0, s, A); \
-    else if (row_form3<PP, T>())                                         \
-      hipLaunchKernelGGL((k_split3v<PP, T>), grid, block, 0, s, A);       \
     else                                                                 \
-      hipLaunchKernelGGL((k_split3<PP, T, false>), grid, block, 0, s, A); \
+      hipLaunchKernelGGL((k_split3v<PP, T, skew_from_cache3<PP, T>()>), grid, block, 0, s, A); \
     return hipGetLastError();                                            \
   }
   SBP_LAUNCH3(1) SBP_LAUNCH3(2) SBP_LAUNCH3(3)
