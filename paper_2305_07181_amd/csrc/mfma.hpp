@@ -1,5 +1,4 @@
-// MFMA fragment helpers and wave-level LDS ordering shared by the HIP
-// translation units (gfx950).
+// MFMA fragment helpers of the contraction kernels (gfx950).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -27,12 +26,5 @@ struct MF<float> {
   }
   __device__ static __forceinline__ int row(int kr, int i) { return 4 * kr + i; }
 };
-
-// LDS writes of a wave become visible to all its lanes (no workgroup barrier).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
 
 }  // namespace sbp

@@ -22,7 +22,7 @@
 // K_i = 1/2 sum_l (Lambda_il S_l + S_l Lambda_il) and a_i = sum_l Lambda_il E_l:
 //   Q_xi = K_i + a_i/2,  Q_xi^T = -K_i + a_i/2,
 //   M_xi^T mu = (1 - c_b) K_i mu + (1 + c_b)/2 a_i mu,
-// so every contraction uses the reference skew operators S_l only.
+// so only the reference skew operators S_l enter, as per-node-pair sums.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,7 +30,6 @@
 #include "dual.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
-#include "mfma.hpp"
 
 namespace sbp {
 
@@ -311,33 +310,41 @@ __global__ __launch_bounds__(kT) void k_vjp3(KArgs<double> A) {
   }
 }
 
-template <int P> struct VjpWave2 { static constexpr int CT = P <= 2 ? 2 : 1; };
+// 2D curved triangles, row form (as the forward 2D kernel): one lane per node
+// row; per node pair (i, j), with c_m = sum_l S_l[i][j] (Lambda_ml(i) + Lambda_ml(j)),
+//   Z_m += c_m mu_j,  V_s += c_0 s_0,j + c_1 s_1,j,  X_m += c_m w_j
+// (Z_m = 2 K_m mu, V_s = 2 sum_m K_m s_m, X_m = 2 K_m w), then the pointwise
+// transposed-Jacobian, Hessian-vector and facet-derivative terms per node.
+template <int P> struct VTileV2 { static constexpr int EB = P == 1 ? 42 : (P == 2 ? 25 : (P == 3 ? 14 : 11)); };
 
-// 2D curved triangles, one wave per group of EW = 4 CT elements (wave-private
-// LDS, persistent waves, as in the forward 2D kernel).
 template <int P>
 struct Vjp2 {
   static constexpr int D = 2, NC = 4, NFAC = 3;
   static constexpr int NP = Shape<2, P>::NP, NF = Shape<2, P>::NF, NFN = NFAC * NF;
-  static constexpr int KP = ru(NP, 4), MP = ru(NP, 16), MT = MP / 16, KS = KP / 4;
-  static constexpr int CT = VjpWave2<P>::CT, EW = 4 * CT, LD = 16 * CT;
-  static constexpr int NPW = EW * NP;
+  static constexpr int EB = VTileV2<P>::EB;
+  static_assert(EB * NP <= kT, "one node per lane");
+  static constexpr int NDS = NP * 20 + 4;  // padded element blocks (LDS banks)
   struct Lds {
-    // inputs mu, s_0, s_1, w (0..3); outputs Z_1 (0), V_s (1), X_0 (2), X_1 (3), Z_0 (4)
-    double B[5][KP][LD];
-    double L[5][NP][EW];
+    double S[2][NP][NP];
+    double nd[EB * NDS];  // per node: mu[4] s_0[4] s_1[4] w[4] Lambda_00 _01 _10 _11
   };
 
-  __device__ static __forceinline__ void group(const KArgs<double> &A, Lds &S, int grp, int lane) {
-    typedef MF<double>::v4 V4;
-    const int col = lane & 15, kr = lane >> 4;
-    double(*B)[KP][LD] = S.B;
-    double(*L)[NP][EW] = S.L;
+  __device__ static __forceinline__ void load_ops(const KArgs<double> &A, Lds &L) {
+    for (int x = threadIdx.x; x < 2 * NP * NP; x += kT) (&L.S[0][0][0])[x] = A.op.S[x];
+  }
+
+  __device__ static __forceinline__ void tile(const KArgs<double> &A, Lds &L, int tl) {
+    const int tid = threadIdx.x;
+    const int e0 = tl * EB;
+    const int ne = min(EB, A.n_elem - e0);
+    const bool act = tid < ne * NP;
+    const int e = tid / NP, j = tid % NP, eg = e0 + e;
     const GasC<double> &G = A.G;
     const GasC<Dual<double>> GD = dual_gas(G);
     const double cb = G.cb, he = 0.5 * (1.0 + cb), hz = 0.5 * (1.0 - cb);
-    // metrics of element eg at node j: Lambda (4) and J
-    auto metrics = [&](int eg, int j, double *lam) {
+    double uu[NC], lm[NC], lam[4], H = 1.0, s[D][NC];
+    Node<D, double> n;
+    if (act) {
       const double *g = A.geo + (size_t)eg * 12;
       double F[2][2] = {{0, 0}, {0, 0}};
 #pragma unroll
@@ -352,235 +359,129 @@ struct Vjp2 {
       lam[1] = -F[1][0];
       lam[2] = -F[0][1];
       lam[3] = F[0][0];
-      lam[4] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
-    };
-    const int e0 = grp * EW;
-    wave_lds_sync();
-    for (int x = lane; x < 5 * (KP - NP) * LD; x += 64) {
-      const int q = x / ((KP - NP) * LD), y = x % ((KP - NP) * LD);
-      B[q][NP + y / LD][y % LD] = 0.0;
+      H = (F[0][0] * F[1][1] - F[0][1] * F[1][0]) * A.op.h[j];
+      const int uo = A.uoff[eg];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        uu[c] = A.u[uo + c * NP + j];
+        lm[c] = A.lam[uo + c * NP + j];
+      }
+      node_from_u<D, double>(uu, G, n);
+      if (!n.ok) atomicOr(A.err, 1);
+#pragma unroll
+      for (int i = 0; i < D; ++i) jvp_flux<D, double>(n, G, i, lm, s[i]);
+      const double iH = 1.0 / H;
+      double *v = L.nd + e * NDS + j * 20;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        v[c] = lm[c] * iH;
+        v[4 + c] = s[0][c] * iH;
+        v[8 + c] = s[1][c] * iH;
+        v[12 + c] = n.w[c];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[16 + q] = lam[q];
     }
-      wave_lds_sync();
-      // pointwise: mu = H^-1 lambda, s_i = H^-1 A~_i lambda, w
-      for (int x = lane; x < NPW; x += 64) {
-        const int e = x / NP, j = x % NP, eg = e0 + e;
-        double in[4][NC], lam[5];
-        if (eg < A.n_elem) {
-          metrics(eg, j, lam);
-          const int uo = A.uoff[eg];
-          double uu[NC], lm[NC];
+    __syncthreads();
+    if (act) {
+      double Z0[NC], Z1[NC], Vs[NC], X0[NC], X1[NC];
 #pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            uu[c] = A.u[uo + c * NP + j];
-            lm[c] = A.lam[uo + c * NP + j];
-          }
-          Node<D, double> n;
-          node_from_u<D, double>(uu, G, n);
-          if (!n.ok) atomicOr(A.err, 1);
-          const double iH = 1.0 / (lam[4] * A.op.h[j]);
-#pragma unroll
-          for (int i = 0; i < D; ++i) jvp_flux<D, double>(n, G, i, lm, in[1 + i]);
-#pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            in[0][c] = lm[c] * iH;
-            in[1][c] *= iH;
-            in[2][c] *= iH;
-            in[3][c] = n.w[c];
-          }
-        } else {
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) in[q][c] = 0.0;
-#pragma unroll
-          for (int q = 0; q < 5; ++q) lam[q] = 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int c = 0; c < NC; ++c) B[q][j][e * NC + c] = in[q][c];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) L[q][j][e] = lam[q];
-      }
-      double sf[2][MT][KS];
-#pragma unroll
-      for (int l = 0; l < 2; ++l)
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-          for (int ks = 0; ks < KS; ++ks) {
-            const int m = mt * 16 + col, k = 4 * ks + kr;
-            sf[l][mt][ks] = (m < NP && k < NP) ? A.op.S[(l * NP + m) * NP + k] : 0.0;
-          }
-      wave_lds_sync();
-      // Three families of column groups (input slot q = 0 mu, 1..2 s_i, 3 w):
-      //   mu: S_l mu, S_l (Lambda_0l mu), S_l (Lambda_1l mu) -> Z_0, Z_1 (= 2 K_i mu)
-      //   s : S_l s_0, S_l s_1, S_l (Lambda_0l s_0 + Lambda_1l s_1) -> V_s (= 2 sum_i K_i s_i)
-      //   w : S_l w, S_l (Lambda_0l w), S_l (Lambda_1l w) -> X_0, X_1 (= 2 K_i w)
-#pragma unroll
-      for (int t = 0; t < CT; ++t) {
-        const int cc = t * 16 + col, el = t * 4 + (col >> 2);
-#pragma unroll
-        for (int fam = 0; fam < 3; ++fam) {
-          V4 o0[MT], o1[MT];
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt) o0[mt] = o1[mt] = V4{0, 0, 0, 0};
-#pragma unroll
-          for (int l = 0; l < 2; ++l)
-#pragma unroll
-            for (int g = 0; g < 3; ++g) {
-              V4 acc[MT];
-#pragma unroll
-              for (int mt = 0; mt < MT; ++mt) acc[mt] = V4{0, 0, 0, 0};
-#pragma unroll
-              for (int ks = 0; ks < KS; ++ks) {
-                const int k = 4 * ks + kr;
-                const bool in = 4 * ks + 3 < NP || k < NP;
-                const double la = in ? L[l][k][el] : 0.0, lb = in ? L[2 + l][k][el] : 0.0;
-                double b;
-                if (fam == 1) {
-                  if (g == 0) b = B[1][k][cc];
-                  else if (g == 1) b = B[2][k][cc];
-                  else b = la * B[1][k][cc] + lb * B[2][k][cc];
-                } else {
-                  const double v = B[fam == 0 ? 0 : 3][k][cc];
-                  b = g == 0 ? v : (g == 1 ? la * v : lb * v);
-                }
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) acc[mt] = MF<double>::mma(sf[l][mt][ks], b, acc[mt]);
-              }
-#pragma unroll
-              for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int ii = 0; ii < 4; ++ii) {
-                  const int row = mt * 16 + MF<double>::row(kr, ii);
-                  if (row < NP) {
-                    const double v = acc[mt][ii];
-                    if (fam == 1) {
-                      if (g == 0) o0[mt][ii] += L[l][row][el] * v;
-                      else if (g == 1) o0[mt][ii] += L[2 + l][row][el] * v;
-                      else o0[mt][ii] += v;
-                    } else if (g == 0) {
-                      o0[mt][ii] += L[l][row][el] * v;
-                      o1[mt][ii] += L[2 + l][row][el] * v;
-                    } else if (g == 1) {
-                      o0[mt][ii] += v;
-                    } else {
-                      o1[mt][ii] += v;
-                    }
-                  }
-                }
-              __builtin_amdgcn_sched_barrier(0);
-            }
-          // the family's inputs are no longer read: store its outputs
-          wave_lds_sync();
-          const int s0 = fam == 0 ? 4 : (fam == 1 ? 1 : 2), s1 = fam == 0 ? 0 : 3;
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int ii = 0; ii < 4; ++ii) {
-              const int row = mt * 16 + MF<double>::row(kr, ii);
-              if (row < NP) {
-                B[s0][row][cc] = o0[mt][ii];
-                if (fam != 1) B[s1][row][cc] = o1[mt][ii];
-              }
-            }
-        }
-      }
-      wave_lds_sync();
-      // per node: volume, non-conservative and facet parts of ubar
-      for (int x = lane; x < NPW; x += 64) {
-        const int e = x / NP, j = x % NP, eg = e0 + e;
-        if (eg >= A.n_elem) continue;
-        const int uo = A.uoff[eg];
-        double uu[NC], lm[NC];
+      for (int c = 0; c < NC; ++c) Z0[c] = Z1[c] = Vs[c] = X0[c] = X1[c] = 0.0;
+#pragma unroll 1
+      for (int k = 0; k < NP; ++k) {
+        const double s0 = L.S[0][j][k], s1 = L.S[1][j][k];
+        const double *v = L.nd + e * NDS + k * 20;
+        const double c0 = s0 * (lam[0] + v[16]) + s1 * (lam[1] + v[17]);
+        const double c1 = s0 * (lam[2] + v[18]) + s1 * (lam[3] + v[19]);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          uu[c] = A.u[uo + c * NP + j];
-          lm[c] = A.lam[uo + c * NP + j];
+          Z0[c] += c0 * v[c];
+          Z1[c] += c1 * v[c];
+          Vs[c] += c0 * v[4 + c] + c1 * v[8 + c];
+          X0[c] += c0 * v[12 + c];
+          X1[c] += c1 * v[12 + c];
         }
-        Node<D, double> n;
-        node_from_u<D, double>(uu, G, n);
-        const double E0 = A.op.E[j], E1 = A.op.E[NP + j];
-        double ak[D];
-        ak[0] = L[0][j][e] * E0 + L[1][j][e] * E1;
-        ak[1] = L[2][j][e] * E0 + L[3][j][e] * E1;
-        const double H = L[4][j][e] * A.op.h[j], iH = 1.0 / H;
-        double ub[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) ub[c] = 0.0;
-        // volume: sum_i A_i^T z_i, z_i = (1 - c_b)/2 Z_i + (1 + c_b)/2 a_i mu
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-          double zi[NC], o[NC];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) zi[c] = hz * B[i == 0 ? 4 : 0][j][e * NC + c] + he * ak[i] * lm[c] * iH;
-          flux_jac_T<D, double>(n, G, uu[NC - 1], i, zi, o);
-#pragma unroll
-          for (int c = 0; c < NC; ++c) ub[c] += o[c];
-        }
-        // non-conservative: y = sum_i Q_xi^T s_i + sum_i d/de A~_i(w + e g_i) lambda,
-        // sum_i Q_xi^T s_i = -V_s/2 + 1/2 sum_i a_i s_i,  g_i = H^-1 (X_i + a_i w)/2
-        double y[NC], s[D][NC];
-#pragma unroll
-        for (int i = 0; i < D; ++i) jvp_flux<D, double>(n, G, i, lm, s[i]);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) y[c] = -0.5 * B[1][j][e * NC + c] + 0.5 * iH * (ak[0] * s[0][c] + ak[1] * s[1][c]);
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-          double gi[NC], du[NC];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) gi[c] = 0.5 * iH * (B[2 + i][j][e * NC + c] + ak[i] * n.w[c]);
-          dU_from_dW<D, double>(n, G, gi, du);
-          Dual<double> xd[NC], lmd[NC], hv[NC];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            xd[c] = Dual<double>(uu[c], du[c]);
-            lmd[c] = Dual<double>(lm[c]);
-          }
-          Node<D, Dual<double>> nd;
-          node_from_u<D, Dual<double>>(xd, GD, nd);
-          jvp_flux<D, Dual<double>>(nd, GD, i, lmd, hv);
-#pragma unroll
-          for (int c = 0; c < NC; ++c) y[c] += hv[c].d;
-        }
-        double wy[NC];
-        dWdU_apply<D>(uu, y, GD, wy);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) ub[c] -= cb * wy[c];
-        // facet SATs: own term and the neighbour's term at this node
-        if (j < NFN) {
-          const int off = A.nbr[(size_t)eg * NFN + j];
-          double uv[NC], lv[NC];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            uv[c] = A.u[off + c * NP];
-            lv[c] = A.lam[off + c * NP];
-          }
-          // one gradient of this node's SAT with the combined cotangent
-          // (the neighbour's SAT is its negative)
-          const int q = A.nbrq[(size_t)eg * NFN + j];
-          const double Hv = A.Hn[(size_t)(q / NFN) * NP + q % NFN];
-          double mu[NC], g1[NC];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) mu[c] = lm[c] * iH - lv[c] / Hv;
-          facet_grad<D>(uu, uv, ak, mu, G, GD, A.diss != 0, g1);
-#pragma unroll
-          for (int c = 0; c < NC; ++c) ub[c] -= g1[c];
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) A.ubar[uo + c * NP + j] = ub[c];
       }
+      const double E0 = A.op.E[j], E1 = A.op.E[NP + j];
+      double ak[D];
+      ak[0] = lam[0] * E0 + lam[1] * E1;
+      ak[1] = lam[2] * E0 + lam[3] * E1;
+      const double iH = 1.0 / H;
+      double ub[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) ub[c] = 0.0;
+      // volume: sum_i A_i^T z_i, z_i = (1 - c_b)/2 Z_i + (1 + c_b)/2 a_i mu
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        double zi[NC], o[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) zi[c] = hz * (i == 0 ? Z0[c] : Z1[c]) + he * ak[i] * lm[c] * iH;
+        flux_jac_T<D, double>(n, G, uu[NC - 1], i, zi, o);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ub[c] += o[c];
+      }
+      // non-conservative: y = sum_i Q_xi^T s_i + sum_i d/de A~_i(w + e g_i) lambda,
+      // sum_i Q_xi^T s_i = -V_s/2 + 1/2 sum_i a_i s_i,  g_i = H^-1 (X_i + a_i w)/2
+      double y[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) y[c] = -0.5 * Vs[c] + 0.5 * iH * (ak[0] * s[0][c] + ak[1] * s[1][c]);
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        double gi[NC], du[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) gi[c] = 0.5 * iH * ((i == 0 ? X0[c] : X1[c]) + ak[i] * n.w[c]);
+        dU_from_dW<D, double>(n, G, gi, du);
+        Dual<double> xd[NC], lmd[NC], hv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          xd[c] = Dual<double>(uu[c], du[c]);
+          lmd[c] = Dual<double>(lm[c]);
+        }
+        Node<D, Dual<double>> nd;
+        node_from_u<D, Dual<double>>(xd, GD, nd);
+        jvp_flux<D, Dual<double>>(nd, GD, i, lmd, hv);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) y[c] += hv[c].d;
+      }
+      double wy[NC];
+      dWdU_apply<D>(uu, y, GD, wy);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) ub[c] -= cb * wy[c];
+      // facet SATs: one gradient of this node's SAT with the combined
+      // cotangent lambda_k/H_k - lambda_v/H_v (the neighbour's SAT is its negative)
+      if (j < NFN) {
+        const int off = A.nbr[(size_t)eg * NFN + j];
+        double uv[NC], lv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          uv[c] = A.u[off + c * NP];
+          lv[c] = A.lam[off + c * NP];
+        }
+        const int q = A.nbrq[(size_t)eg * NFN + j];
+        const double Hv = A.Hn[(size_t)(q / NFN) * NP + q % NFN];
+        double mu[NC], g1[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) mu[c] = lm[c] * iH - lv[c] / Hv;
+        facet_grad<D>(uu, uv, ak, mu, G, GD, A.diss != 0, g1);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ub[c] -= g1[c];
+      }
+      const int uo = A.uoff[eg];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) A.ubar[uo + c * NP + j] = ub[c];
+    }
+    __syncthreads();
   }
 };
 
 template <int P>
 __global__ __launch_bounds__(kT) void k_vjp2(KArgs<double> A) {
   typedef Vjp2<P> K;
-  __shared__ typename K::Lds lds[kW];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int ngroups = (A.n_elem + K::EW - 1) / K::EW;
-  for (int grp = blockIdx.x * kW + wave; grp < ngroups; grp += gridDim.x * kW) K::group(A, lds[wave], grp, lane);
+  __shared__ typename K::Lds lds;
+  K::load_ops(A, lds);
+  __syncthreads();
+  const int ntiles = (A.n_elem + K::EB - 1) / K::EB;
+  for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) K::tile(A, lds, tl);
 }
 
 constexpr size_t vjp2_lds_max() {
@@ -591,21 +492,26 @@ constexpr size_t vjp2_lds_max() {
   return m;
 }
 
-// every degree class of a 2D mesh in one persistent launch
+// every degree class of a 2D mesh in one persistent launch (tiles in degree
+// order; a workgroup restages S_l when its tile changes degree)
 __global__ __launch_bounds__(kT) void k_vjp2_batch(Batch2<double> Bt) {
-  constexpr size_t LW = (vjp2_lds_max() + 15) / 16 * 16;
-  __shared__ __align__(16) unsigned char raw[kW * LW];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  void *mine = raw + wave * LW;
-  for (int g = blockIdx.x * kW + wave; g < Bt.g0[4]; g += gridDim.x * kW) {
-    if (g < Bt.g0[1])
-      Vjp2<1>::group(Bt.c[0], *(Vjp2<1>::Lds *)mine, g, lane);
-    else if (g < Bt.g0[2])
-      Vjp2<2>::group(Bt.c[1], *(Vjp2<2>::Lds *)mine, g - Bt.g0[1], lane);
-    else if (g < Bt.g0[3])
-      Vjp2<3>::group(Bt.c[2], *(Vjp2<3>::Lds *)mine, g - Bt.g0[2], lane);
-    else
-      Vjp2<4>::group(Bt.c[3], *(Vjp2<4>::Lds *)mine, g - Bt.g0[3], lane);
+  __shared__ __align__(16) unsigned char raw[vjp2_lds_max()];
+  int cur = -1;
+  for (int g = blockIdx.x; g < Bt.g0[4]; g += gridDim.x) {
+    const int q = g < Bt.g0[1] ? 0 : (g < Bt.g0[2] ? 1 : (g < Bt.g0[3] ? 2 : 3));
+    if (q != cur) {
+      __syncthreads();
+      if (q == 0) Vjp2<1>::load_ops(Bt.c[0], *(Vjp2<1>::Lds *)raw);
+      else if (q == 1) Vjp2<2>::load_ops(Bt.c[1], *(Vjp2<2>::Lds *)raw);
+      else if (q == 2) Vjp2<3>::load_ops(Bt.c[2], *(Vjp2<3>::Lds *)raw);
+      else Vjp2<4>::load_ops(Bt.c[3], *(Vjp2<4>::Lds *)raw);
+      __syncthreads();
+      cur = q;
+    }
+    if (q == 0) Vjp2<1>::tile(Bt.c[0], *(Vjp2<1>::Lds *)raw, g);
+    else if (q == 1) Vjp2<2>::tile(Bt.c[1], *(Vjp2<2>::Lds *)raw, g - Bt.g0[1]);
+    else if (q == 2) Vjp2<3>::tile(Bt.c[2], *(Vjp2<3>::Lds *)raw, g - Bt.g0[2]);
+    else Vjp2<4>::tile(Bt.c[3], *(Vjp2<4>::Lds *)raw, g - Bt.g0[3]);
   }
 }
 
@@ -614,14 +520,14 @@ __global__ __launch_bounds__(kT) void k_vjp2_batch(Batch2<double> Bt) {
 hipError_t launch_vjp2_batch(const KArgs<double> *const cls[4], hipStream_t s) {
   Batch2<double> Bt{};
   Bt.g0[0] = 0;
+  const int eb[4] = {VTileV2<1>::EB, VTileV2<2>::EB, VTileV2<3>::EB, VTileV2<4>::EB};
   for (int q = 0; q < 4; ++q) {
-    const int ew = 4 * (q + 1 <= 2 ? 2 : 1);
     const int ne = cls[q] ? cls[q]->n_elem : 0;
     if (cls[q]) Bt.c[q] = *cls[q];
-    Bt.g0[q + 1] = Bt.g0[q] + (ne + ew - 1) / ew;
+    Bt.g0[q + 1] = Bt.g0[q] + (ne + eb[q] - 1) / eb[q];
   }
   if (Bt.g0[4] == 0) return hipSuccess;
-  const dim3 grid(std::min((Bt.g0[4] + kW - 1) / kW, 2048));
+  const dim3 grid(std::min(Bt.g0[4], 2048));
   hipLaunchKernelGGL(k_vjp2_batch, grid, dim3(kT), 0, s, Bt);
   return hipGetLastError();
 }
@@ -630,9 +536,9 @@ hipError_t launch_vjp(int dim, int p, const KArgs<double> &A, hipStream_t s) {
   dim3 block(kT);
   if (A.n_elem <= 0) return hipSuccess;
   if (dim == 2) {
-    // persistent waves: at most as many workgroups as 256 CUs keep resident
-    const int per_block = kW * 4 * (p <= 2 ? 2 : 1);
-    const dim3 grid(std::min((A.n_elem + per_block - 1) / per_block, 2048));
+    // persistent workgroups: at most about as many as 256 CUs keep resident
+    const int eb = p == 1 ? VTileV2<1>::EB : (p == 2 ? VTileV2<2>::EB : (p == 3 ? VTileV2<3>::EB : VTileV2<4>::EB));
+    const dim3 grid(std::min((A.n_elem + eb - 1) / eb, 2048));
     switch (p) {
       case 1: hipLaunchKernelGGL(k_vjp2<1>, grid, block, 0, s, A); break;
       case 2: hipLaunchKernelGGL(k_vjp2<2>, grid, block, 0, s, A); break;
