@@ -15,8 +15,8 @@
 //              gradient of Phi(u_k, u_v) with cotangent lambda_k/H_k -
 //              lambda_v/H_v (dual numbers, one pass per component), gathered
 //              without atomics.
-// The transposed operators are applied as MFMA contractions like the forward
-// kernel: [M_1^T; M_2^T; M_3^T] mu, [D_1^T D_2^T D_3^T] s, and D w.
+// The transposed operators enter as per-node-pair sums over the reference
+// skew operators S_l (Q_l = S_l + E_l/2), as in the forward row-form kernels.
 //
 // On curved triangles the physical operators are written with the skew parts
 // K_i = 1/2 sum_l (Lambda_il S_l + S_l Lambda_il) and a_i = sum_l Lambda_il E_l:
@@ -36,50 +36,6 @@ namespace sbp {
 namespace {
 
 constexpr int kT = 256;
-constexpr int kW = kT / 64;
-
-template <int P> struct VjpTile;
-template <> struct VjpTile<1> { static constexpr int EB = 16; };
-template <> struct VjpTile<2> { static constexpr int EB = 9; };
-template <> struct VjpTile<3> { static constexpr int EB = 3; };
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-// Same MFMA contraction as the forward kernels (f64 16x16x4; accumulator
-// register i of lane l holds row l/16 + 4 i, column l%16).
-template <int MP, int KP, int NCP>
-__device__ __forceinline__ void gemm64(const double *__restrict__ At, const double *B, double *C) {
-  constexpr int MT = MP / 16, NT = NCP / 16, NTILE = MT * NT;
-  constexpr int TPW = (NTILE + kW - 1) / kW;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int col = lane & 15, kr = lane >> 4;
-  v4d acc[TPW];
-#pragma unroll
-  for (int t = 0; t < TPW; ++t) acc[t] = v4d{0, 0, 0, 0};
-#pragma unroll 4
-  for (int k = 0; k < KP; k += 4) {
-#pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-      const int tile = wave + t * kW;
-      if (tile < NTILE) {
-        const int mt = tile % MT, nt = tile / MT;
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(At[(k + kr) * MP + mt * 16 + col],
-                                                       B[(k + kr) * NCP + nt * 16 + col], acc[t], 0, 0, 0);
-      }
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    const int tile = wave + t * kW;
-    if (tile < NTILE) {
-      const int mt = tile % MT, nt = tile / MT;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) C[(mt * 16 + kr + 4 * i) * NCP + nt * 16 + col] = acc[t][i];
-    }
-  }
-  __syncthreads();
-}
 
 // gradient of mu . Phi(u1, u2; a) with respect to u1, Phi = facet_term
 // (two-point flux [+ dissipation]); one dual-number pass per component of
@@ -109,6 +65,9 @@ __device__ __forceinline__ void facet_grad(const double *u1, const double *u2, c
 #pragma unroll
   for (int c = 0; c < NC; ++c) n2.w[c] = m2.w[c];
   n2.ok = m2.ok;
+  // one pass at a time: unrolled, the passes' dual states would be live
+  // together (several hundred registers)
+#pragma unroll 1
   for (int c = 0; c < NC; ++c) {
     Dual<double> x1[NC];
 #pragma unroll
@@ -121,7 +80,8 @@ __device__ __forceinline__ void facet_grad(const double *u1, const double *u2, c
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < NC; ++q) s += mu[q] * ph[q].d;
-    out[c] = s;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) out[q] = q == c ? s : out[q];
   }
 }
 
@@ -138,175 +98,182 @@ __device__ __forceinline__ void dWdU_apply(const double *u, const double *y, con
   for (int q = 0; q < NC; ++q) out[q] = n.w[q].d;
 }
 
+// 3D affine tetrahedra, row form: one lane per node row; per node pair (i, j)
+//   Z_l += S_l[i][j] mu_j,  V_s += sum_l S_l[i][j] shat_l,j,  G_l += S_l[i][j] w_j
+// (45 FMAs per pair; shat_l = s_l / h), then per node
+//   M_l^T mu = (1 - c_b) Z_l + (1 + c_b)/2 E_l mu,
+//   sum_l D_l^T s_l = -V_s + 1/2 sum_l E_l shat_l,   D_l w = h^-1 (G_l + E_l w / 2).
+// At p = 3 (60 x 60 operators) S_l is read through the caches, as in the
+// forward kernel.
+template <int P> struct VTileV3 { static constexpr int EB = P == 1 ? 21 : (P == 2 ? 10 : 4); };
+
 template <int P>
-__global__ __launch_bounds__(kT) void k_vjp3(KArgs<double> A) {
+__global__ __launch_bounds__(kT) void k_vjp3v(KArgs<double> A) {
   constexpr int D = 3, NC = 5, NFAC = 4;
   constexpr int NP = Shape<3, P>::NP, NF = Shape<3, P>::NF, NFN = NFAC * NF;
-  constexpr int EB = VjpTile<P>::EB;
-  constexpr int NCP = ru(EB * NC, 16);
-  constexpr int K1P = ru(3 * NP, 4), M1P = ru(NP, 16);
-  constexpr int K2P = ru(NP, 4), M2P = ru(3 * NP, 16);
-  __shared__ double Bmu[K2P * NCP];
-  __shared__ double Bw[K2P * NCP];
-  __shared__ double Bs[K1P * NCP];
-  __shared__ double Z[M2P * NCP];
-  __shared__ double C2[M2P * NCP];
-  __shared__ double Qo[M1P * NCP];
-  __shared__ double us[EB * NC * NP];
-  __shared__ double ls[EB * NC * NP];
-  __shared__ double gs[EB * 10];
-  __shared__ double hs[NP];
-  __shared__ double Es[3 * NP];
+  constexpr int EB = VTileV3<P>::EB;
+  constexpr bool SG = P == 3;
+  static_assert(EB * NP <= kT, "one node per lane");
+  constexpr int NDS = NP * 25 + 4;  // per node: mu[5] shat_1..3[15] w[5]
+  __shared__ double Ss[SG ? 1 : 3][SG ? 1 : NP][SG ? 1 : NP];
+  __shared__ double nd[EB * NDS];
+  __shared__ double gs[EB][10];
   const int tid = threadIdx.x;
-  const int e0 = blockIdx.x * EB;
-  const int ne = min(EB, A.n_elem - e0);
+  if constexpr (!SG)
+    for (int x = tid; x < 3 * NP * NP; x += kT) (&Ss[0][0][0])[x] = A.op.S[x];
   const GasC<double> &G = A.G;
   const GasC<Dual<double>> GD = dual_gas(G);
-  for (int x = tid; x < EB * 10; x += kT) {
-    const int e = x / 10;
-    gs[x] = e < ne ? A.geo[(size_t)(e0 + e) * 10 + x % 10] : 0.0;
-  }
-  for (int x = tid; x < NP; x += kT) hs[x] = A.op.h[x];
-  for (int x = tid; x < 3 * NP; x += kT) Es[x] = A.op.E[x];
-  for (int x = tid; x < ne * NC * NP; x += kT) {
-    const int e = x / (NC * NP);
-    const int o = A.uoff[e0 + e] + x % (NC * NP);
-    us[x] = A.u[o];
-    ls[x] = A.lam[o];
-  }
-  for (int x = tid; x < K2P * NCP; x += kT) {
-    Bmu[x] = 0.0;
-    Bw[x] = 0.0;
-  }
-  for (int x = tid; x < K1P * NCP; x += kT) Bs[x] = 0.0;
-  __syncthreads();
-  for (int x = tid; x < ne * NP; x += kT) {
-    const int e = x / NP, j = x % NP;
+  const double cb = G.cb, he = 0.5 * (1.0 + cb), hz = 1.0 - cb;
+  const int ntiles = (A.n_elem + EB - 1) / EB;
+  const int e = tid / NP, i = tid % NP;
+  for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    const int e0 = tl * EB;
+    const int ne = min(EB, A.n_elem - e0);
+    const bool act = tid < ne * NP;
+    const int eg = e0 + e;
+    __syncthreads();
+    for (int x = tid; x < ne * 10; x += kT) gs[x / 10][x % 10] = A.geo[(size_t)(e0 + x / 10) * 10 + x % 10];
+    __syncthreads();
     double uu[NC], lm[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      uu[c] = us[(e * NC + c) * NP + j];
-      lm[c] = ls[(e * NC + c) * NP + j];
-    }
     Node<D, double> n;
-    node_from_u<D, double>(uu, G, n);
-    if (!n.ok) atomicOr(A.err, 1);
-    const double *Lam = gs + e * 10;
+    const double *Lam = gs[act ? e : 0];
     const double J = Lam[9], iJ = 1.0 / J;
-    const double iH = 1.0 / (J * hs[j]);
-    double t[D][NC];
+    const double h = A.op.h[i], ih = 1.0 / h, iH = iJ * ih;
+    if (act) {
+      const int uo = A.uoff[eg];
 #pragma unroll
-    for (int i = 0; i < D; ++i) jvp_flux<D, double>(n, G, i, lm, t[i]);
+      for (int c = 0; c < NC; ++c) {
+        uu[c] = A.u[uo + c * NP + i];
+        lm[c] = A.lam[uo + c * NP + i];
+      }
+      node_from_u<D, double>(uu, G, n);
+      if (!n.ok) atomicOr(A.err, 1);
+      double t[D][NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      Bmu[j * NCP + e * NC + c] = lm[c] * iH;
-      Bw[j * NCP + e * NC + c] = n.w[c];
+      for (int m = 0; m < D; ++m) jvp_flux<D, double>(n, G, m, lm, t[m]);
+      double *v = nd + e * NDS + i * 25;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        v[c] = lm[c] * iH;
+        v[20 + c] = n.w[c];
+      }
 #pragma unroll
       for (int l = 0; l < D; ++l)
-        Bs[(l * NP + j) * NCP + e * NC + c] =
-            (Lam[0 * 3 + l] * t[0][c] + Lam[1 * 3 + l] * t[1][c] + Lam[2 * 3 + l] * t[2][c]) * iJ;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          v[5 + l * NC + c] = (Lam[0 * 3 + l] * t[0][c] + Lam[1 * 3 + l] * t[1][c] + Lam[2 * 3 + l] * t[2][c]) * iH;
     }
-  }
-  __syncthreads();
-  gemm64<M2P, K2P, NCP>(A.op.At6, Bmu, Z);   // z_l = M_l^T mu, rows l*NP + j
-  gemm64<M2P, K2P, NCP>(A.op.At2, Bw, C2);   // D_l w
-  gemm64<M1P, K1P, NCP>(A.op.At7, Bs, Qo);   // sum_l D_l^T s_l
-  for (int x = tid; x < ne * NP; x += kT) {
-    const int e = x / NP, j = x % NP;
-    const int eg = e0 + e;
-    double uu[NC], lm[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      uu[c] = us[(e * NC + c) * NP + j];
-      lm[c] = ls[(e * NC + c) * NP + j];
-    }
-    Node<D, double> n;
-    node_from_u<D, double>(uu, G, n);
-    const double *Lam = gs + e * 10;
-    const double J = Lam[9], iJ = 1.0 / J;
-    const double H = J * hs[j];
-    double ub[NC];
-    // volume: sum_l sum_i Lambda_il A_i^T z_l
-#pragma unroll
-    for (int c = 0; c < NC; ++c) ub[c] = 0.0;
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      double zi[NC], o[NC];
+    __syncthreads();
+    if (act) {
+      double Z[D][NC], Vs[NC], Gw[D][NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        double s = 0.0;
+        Vs[c] = 0.0;
 #pragma unroll
-        for (int l = 0; l < D; ++l) s += Lam[i * 3 + l] * Z[(l * NP + j) * NCP + e * NC + c];
-        zi[c] = s;
+        for (int l = 0; l < D; ++l) Z[l][c] = Gw[l][c] = 0.0;
       }
-      flux_jac_T<D, double>(n, G, uu[NC - 1], i, zi, o);
+#pragma unroll 1
+      for (int j = 0; j < NP; ++j) {
+        double s0, s1, s2;
+        if constexpr (SG) {
+          s0 = A.op.S[(0 * NP + i) * NP + j];
+          s1 = A.op.S[(1 * NP + i) * NP + j];
+          s2 = A.op.S[(2 * NP + i) * NP + j];
+        } else {
+          s0 = Ss[0][i][j];
+          s1 = Ss[1][i][j];
+          s2 = Ss[2][i][j];
+        }
+        const double *v = nd + e * NDS + j * 25;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) ub[c] += o[c];
+        for (int c = 0; c < NC; ++c) {
+          Z[0][c] += s0 * v[c];
+          Z[1][c] += s1 * v[c];
+          Z[2][c] += s2 * v[c];
+          Vs[c] += s0 * v[5 + c] + s1 * v[10 + c] + s2 * v[15 + c];
+          Gw[0][c] += s0 * v[20 + c];
+          Gw[1][c] += s1 * v[20 + c];
+          Gw[2][c] += s2 * v[20 + c];
+        }
+      }
+      const double *v = nd + e * NDS + i * 25;
+      double El[D], ak[D];
+#pragma unroll
+      for (int l = 0; l < D; ++l) El[l] = A.op.E[l * NP + i];
+#pragma unroll
+      for (int m = 0; m < D; ++m) ak[m] = Lam[m * 3 + 0] * El[0] + Lam[m * 3 + 1] * El[1] + Lam[m * 3 + 2] * El[2];
+      double ub[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) ub[c] = 0.0;
+      // volume: sum_m A_m^T sum_l Lambda_ml (M_l^T mu)
+#pragma unroll
+      for (int l = 0; l < D; ++l)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Z[l][c] = hz * Z[l][c] + he * El[l] * v[c];
+#pragma unroll
+      for (int m = 0; m < D; ++m) {
+        double zm[NC], o[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) zm[c] = Lam[m * 3 + 0] * Z[0][c] + Lam[m * 3 + 1] * Z[1][c] + Lam[m * 3 + 2] * Z[2][c];
+        flux_jac_T<D, double>(n, G, uu[NC - 1], m, zm, o);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ub[c] += o[c];
+      }
+      // non-conservative: y = sum_l D_l^T s_l + sum_m d/de A~_m(w + e g_m) lambda,
+      // s_l = J^-1 sum_m Lambda_ml A~_m lambda, g_m = J^-1 sum_l Lambda_ml D_l w
+      double y[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) y[c] = -Vs[c] + 0.5 * (El[0] * v[5 + c] + El[1] * v[10 + c] + El[2] * v[15 + c]);
+#pragma unroll
+      for (int l = 0; l < D; ++l)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Gw[l][c] = (Gw[l][c] + 0.5 * El[l] * n.w[c]) * ih;
+#pragma unroll
+      for (int m = 0; m < D; ++m) {
+        double gm[NC], du[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          gm[c] = (Lam[m * 3 + 0] * Gw[0][c] + Lam[m * 3 + 1] * Gw[1][c] + Lam[m * 3 + 2] * Gw[2][c]) * iJ;
+        dU_from_dW<D, double>(n, G, gm, du);
+        Dual<double> xd[NC], lmd[NC], hv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          xd[c] = Dual<double>(uu[c], du[c]);
+          lmd[c] = Dual<double>(lm[c]);
+        }
+        Node<D, Dual<double>> ndu;
+        node_from_u<D, Dual<double>>(xd, GD, ndu);
+        jvp_flux<D, Dual<double>>(ndu, GD, m, lmd, hv);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) y[c] += hv[c].d;
+      }
+      double wy[NC];
+      dWdU_apply<D>(uu, y, GD, wy);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) ub[c] -= cb * wy[c];
+      // facet SATs: one gradient of this node's SAT with the combined
+      // cotangent lambda_k/H_k - lambda_v/H_v (the neighbour's SAT is its negative)
+      if (i < NFN) {
+        const int off = A.nbr[(size_t)eg * NFN + i];
+        double uv[NC], lv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          uv[c] = A.u[off + c * NP];
+          lv[c] = A.lam[off + c * NP];
+        }
+        const int q = A.nbrq[(size_t)eg * NFN + i];
+        const double Hv = A.Hn[(size_t)(q / NFN) * NP + q % NFN];
+        double mu[NC], g1[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) mu[c] = lm[c] * iH - lv[c] / Hv;
+        facet_grad<D>(uu, uv, ak, mu, G, GD, A.diss != 0, g1);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ub[c] -= g1[c];
+      }
+      const int uo = A.uoff[eg];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) A.ubar[uo + c * NP + i] = ub[c];
     }
-    // non-conservative: -c_b dW/dU [ sum_i D_xi^T (A~_i lambda) + HVP ]
-    double y[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) y[c] = Qo[j * NCP + e * NC + c];
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      double gi[NC], du[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        double s = 0.0;
-#pragma unroll
-        for (int l = 0; l < D; ++l) s += Lam[i * 3 + l] * C2[(l * NP + j) * NCP + e * NC + c];
-        gi[c] = s * iJ;
-      }
-      dU_from_dW<D, double>(n, G, gi, du);
-      Dual<double> x[NC], lmd[NC], hv[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        x[c] = Dual<double>(uu[c], du[c]);
-        lmd[c] = Dual<double>(lm[c]);
-      }
-      Node<D, Dual<double>> nd;
-      node_from_u<D, Dual<double>>(x, GD, nd);
-      jvp_flux<D, Dual<double>>(nd, GD, i, lmd, hv);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) y[c] += hv[c].d;
-    }
-    double wy[NC];
-    dWdU_apply<D>(uu, y, GD, wy);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) ub[c] -= G.cb * wy[c];
-    // facet SATs: own term and the neighbour's term at this node
-    if (j < NFN) {
-      const int off = A.nbr[(size_t)eg * NFN + j];
-      double uv[NC], lv[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        uv[c] = A.u[off + c * NP];
-        lv[c] = A.lam[off + c * NP];
-      }
-      double ak[D];
-#pragma unroll
-      for (int i = 0; i < D; ++i) {
-        double s = 0.0;
-#pragma unroll
-        for (int l = 0; l < D; ++l) s += Lam[i * 3 + l] * Es[l * NP + j];
-        ak[i] = s;
-      }
-      // the neighbour's SAT is the negative of this node's (antisymmetric
-      // two-point flux and dissipation, opposite B n), so both derivatives
-      // are one gradient of Phi(u_k, u_v) with the cotangent
-      // lambda_k / H_k - lambda_v / H_v
-      const int q = A.nbrq[(size_t)eg * NFN + j];
-      const double Hv = A.Hn[(size_t)(q / NFN) * NP + q % NFN];
-      double mu[NC], g1[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) mu[c] = lm[c] / H - lv[c] / Hv;
-      facet_grad<D>(uu, uv, ak, mu, G, GD, A.diss != 0, g1);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) ub[c] -= g1[c];
-    }
-    const int uo = A.uoff[eg];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) A.ubar[uo + c * NP + j] = ub[c];
   }
 }
 
@@ -515,6 +482,24 @@ __global__ __launch_bounds__(kT) void k_vjp2_batch(Batch2<double> Bt) {
   }
 }
 
+// Persistent grid of the 3D row-form kernel: as many workgroups as the
+// device keeps resident, at most one per tile.
+template <int P>
+int vjp3v_grid(int n_elem) {
+  static int cap = 0;
+  if (cap == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_vjp3v<P>, kT, 0) != hipSuccess || cus <= 0 || per <= 0)
+      cap = 1024;
+    else
+      cap = cus * per;
+  }
+  const int eb = VTileV3<P>::EB;
+  return std::min((n_elem + eb - 1) / eb, cap);
+}
+
 }  // namespace
 
 hipError_t launch_vjp2_batch(const KArgs<double> *const cls[4], hipStream_t s) {
@@ -550,9 +535,9 @@ hipError_t launch_vjp(int dim, int p, const KArgs<double> &A, hipStream_t s) {
   }
   if (dim != 3) return hipErrorInvalidValue;
   switch (p) {
-    case 1: hipLaunchKernelGGL(k_vjp3<1>, dim3((A.n_elem + VjpTile<1>::EB - 1) / VjpTile<1>::EB), block, 0, s, A); break;
-    case 2: hipLaunchKernelGGL(k_vjp3<2>, dim3((A.n_elem + VjpTile<2>::EB - 1) / VjpTile<2>::EB), block, 0, s, A); break;
-    case 3: hipLaunchKernelGGL(k_vjp3<3>, dim3((A.n_elem + VjpTile<3>::EB - 1) / VjpTile<3>::EB), block, 0, s, A); break;
+    case 1: hipLaunchKernelGGL(k_vjp3v<1>, dim3(vjp3v_grid<1>(A.n_elem)), block, 0, s, A); break;
+    case 2: hipLaunchKernelGGL(k_vjp3v<2>, dim3(vjp3v_grid<2>(A.n_elem)), block, 0, s, A); break;
+    case 3: hipLaunchKernelGGL(k_vjp3v<3>, dim3(vjp3v_grid<3>(A.n_elem)), block, 0, s, A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
