@@ -143,9 +143,8 @@ int upload(T *&dst, const std::vector<T> &src, hipStream_t s) {
 
 // Padded, transposed operator tables of one class for precision T.
 template <typename T>
-void build_tables(const sbp::RefOp &op, int dim, double beta, std::vector<T> &blob, size_t off[11]) {
+void build_tables(const sbp::RefOp &op, int dim, std::vector<T> &blob, size_t off[11]) {
   const int NP = op.np;
-  const double cb = 1.0 / (beta + 1.0);
   auto Q = [&](int l, int i, int j) { return op.Q[((size_t)l * NP + i) * NP + j]; };
   auto align = [&](size_t n) { return (n + 63) / 64 * 64; };
   blob.clear();
@@ -155,52 +154,15 @@ void build_tables(const sbp::RefOp &op, int dim, double beta, std::vector<T> &bl
     for (size_t k = 0; k < v.size(); ++k) blob[o + k] = (T)v[k];
     return o;
   };
+  off[1] = 0;
   if (dim == 3) {
-    const int K1P = sbp::ru(3 * NP, 4), M1P = sbp::ru(NP, 16);
+    // viscous pre-pass: [D_1; D_2; D_3] (3NP x NP), stored transposed and zero padded
     const int K2P = sbp::ru(NP, 4), M2P = sbp::ru(3 * NP, 16);
-    std::vector<double> A1(K1P * M1P, 0.0), A2(K2P * M2P, 0.0);
+    std::vector<double> A2(K2P * M2P, 0.0);
     for (int l = 0; l < 3; ++l)
       for (int m = 0; m < NP; ++m)
-        for (int j = 0; j < NP; ++j) {
-          A1[(size_t)(l * NP + j) * M1P + m] = cb * Q(l, m, j) + Q(l, j, m);  // M_l[m][j]
-          A2[(size_t)j * M2P + l * NP + m] = Q(l, m, j) / op.h[m];            // D_l[m][j]
-        }
-    off[0] = push(A1);
+        for (int j = 0; j < NP; ++j) A2[(size_t)j * M2P + l * NP + m] = Q(l, m, j) / op.h[m];  // D_l[m][j]
     off[1] = push(A2);
-    off[2] = off[3] = 0;
-    // viscous: A5 = [Q_1 Q_2 Q_3 | Q_1^T Q_2^T Q_3^T] (NP x 6NP), stored transposed
-    const int K3P = sbp::ru(6 * NP, 4);
-    std::vector<double> A5((size_t)K3P * M1P, 0.0);
-    for (int l = 0; l < 3; ++l)
-      for (int m = 0; m < NP; ++m)
-        for (int j = 0; j < NP; ++j) {
-          A5[(size_t)(l * NP + j) * M1P + m] = Q(l, m, j);
-          A5[(size_t)(3 * NP + l * NP + j) * M1P + m] = Q(l, j, m);
-        }
-    off[8] = push(A5);
-    // VJP: A6 = [M_1^T; M_2^T; M_3^T] (3NP x NP), A7 = [D_1^T D_2^T D_3^T] (NP x 3NP), transposed
-    std::vector<double> A6((size_t)K2P * M2P, 0.0), A7((size_t)K1P * M1P, 0.0);
-    for (int l = 0; l < 3; ++l)
-      for (int j = 0; j < NP; ++j)
-        for (int k = 0; k < NP; ++k) {
-          A6[(size_t)k * M2P + l * NP + j] = cb * Q(l, k, j) + Q(l, j, k);  // M_l[k][j]
-          A7[(size_t)(l * NP + j) * M1P + k] = Q(l, j, k) / op.h[j];         // D_l[j][k]
-        }
-    off[9] = push(A6);
-    off[10] = push(A7);
-  } else {
-    off[8] = off[9] = off[10] = 0;
-    const int KP = sbp::ru(NP, 4), MP = sbp::ru(NP, 16);
-    for (int l = 0; l < 2; ++l) {
-      std::vector<double> Am(KP * MP, 0.0), Aq(KP * MP, 0.0);
-      for (int m = 0; m < NP; ++m)
-        for (int k = 0; k < NP; ++k) {
-          Am[(size_t)k * MP + m] = cb * Q(l, m, k) + Q(l, k, m);
-          Aq[(size_t)k * MP + m] = Q(l, m, k);
-        }
-      off[l] = push(Am);
-      off[2 + l] = push(Aq);
-    }
   }
   std::vector<double> S((size_t)dim * NP * NP);
   for (int l = 0; l < dim; ++l)
@@ -228,17 +190,11 @@ void build_tables(const sbp::RefOp &op, int dim, double beta, std::vector<T> &bl
 template <typename T>
 sbp::OpTables<T> tables_at(const T *base, const size_t off[11], int dim) {
   sbp::OpTables<T> t{};
-  t.At1 = base + off[0];
-  t.At2 = base + off[1];
-  t.At3 = dim == 2 ? base + off[2] : nullptr;
-  t.At4 = dim == 2 ? base + off[3] : nullptr;
+  t.Dt = dim == 3 ? base + off[1] : nullptr;
   t.S = base + off[4];
   t.h = base + off[5];
   t.E = base + off[6];
   t.dN = base + off[7];
-  t.At5 = dim == 3 ? base + off[8] : nullptr;
-  t.At6 = dim == 3 ? base + off[9] : nullptr;
-  t.At7 = dim == 3 ? base + off[10] : nullptr;
   return t;
 }
 
@@ -467,8 +423,8 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
     std::vector<double> b64;
     std::vector<float> b32;
     size_t o64[11], o32[11];
-    build_tables<double>(op, dim, ph->beta, b64, o64);
-    build_tables<float>(op, dim, ph->beta, b32, o32);
+    build_tables<double>(op, dim, b64, o64);
+    build_tables<float>(op, dim, b32, o32);
     const size_t bytes64 = b64.size() * sizeof(double), bytes32 = b32.size() * sizeof(float);
     HIPCHK(hipMalloc(&c.d_ops, bytes64 + bytes32));
     HIPCHK(hipMemcpyAsync(c.d_ops, b64.data(), bytes64, hipMemcpyHostToDevice, s));

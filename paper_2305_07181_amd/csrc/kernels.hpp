@@ -25,19 +25,12 @@ template <> struct Shape<3, 3> { static constexpr int NP = 60, NF = 12; };
 // Device tables of one degree class (pointers into one device allocation).
 template <typename T>
 struct OpTables {
-  // entropy split, 3D affine: At1 = [M_1 M_2 M_3]^T (K1P x M1P), At2 = [D_1;D_2;D_3]^T
-  // entropy split, 2D mapped: At1..At4 = M_1^T, M_2^T, Q_1^T, Q_2^T (KP x MP)
-  // (M_l = c_b Q_xi_l + Q_xi_l^T; A^T stored k-major, zero padded)
-  const T *At1, *At2, *At3, *At4;
-  const T *S;   // Hadamard: S_xi_l [dim][NP][NP]
+  // 3D viscous pre-pass: Dt = [D_1; D_2; D_3]^T (K2P x M2P, k-major, zero padded)
+  const T *Dt;
+  const T *S;   // skew parts S_xi_l = Q_xi_l - E_xi_l / 2, [dim][NP][NP]
   const T *h;   // [NP]
   const T *E;   // [dim][NP] diagonal of E_xi_l
   const T *dN;  // 2D: [2][6][NP] derivatives of the quadratic map basis at the nodes
-  // viscous, 3D affine: At5 = [Q_1 Q_2 Q_3 | Q_1^T Q_2^T Q_3^T]^T (K3P x M1P)
-  const T *At5;
-  // VJP, 3D affine: At6 = [M_1 M_2 M_3] (K2P x M2P: A = [M_1^T; M_2^T; M_3^T]),
-  //                 At7 = [D_1;D_2;D_3] (K1P x M1P: A = [D_1^T D_2^T D_3^T])
-  const T *At6, *At7;
 };
 
 template <typename T>

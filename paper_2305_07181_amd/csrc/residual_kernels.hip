@@ -591,7 +591,7 @@ __global__ __launch_bounds__(kThreads) void k_visc_q3(KArgs<T> A) {
     for (int c = 0; c < NC; ++c) B2[j * NCP + e * NC + c] = n.w[c];
   }
   __syncthreads();
-  gemm_AtB<T, M2P, K2P, NCP>(A.op.At2, B2, C2);
+  gemm_AtB<T, M2P, K2P, NCP>(A.op.Dt, B2, C2);
   for (int x = tid; x < ne * NFN; x += kThreads) {
     const int e = x / NFN, i = x % NFN;
     T uu[NC];
