@@ -13,7 +13,7 @@
 //              the neighbour's SAT is the negative of its own (antisymmetric
 //              two-point flux and dissipation, opposite B n), so both are one
 //              gradient of Phi(u_k, u_v) with cotangent lambda_k/H_k -
-//              lambda_v/H_v (dual numbers, one pass per component), gathered
+//              lambda_v/H_v (reverse mode, facet_adjoint.hpp), gathered
 //              without atomics.
 // The transposed operators enter as per-node-pair sums over the reference
 // skew operators S_l (Q_l = S_l + E_l/2), as in the forward row-form kernels.
@@ -28,6 +28,7 @@
 #include <algorithm>
 
 #include "dual.hpp"
+#include "facet_adjoint.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
 
@@ -36,54 +37,6 @@ namespace sbp {
 namespace {
 
 constexpr int kT = 256;
-
-// gradient of mu . Phi(u1, u2; a) with respect to u1, Phi = facet_term
-// (two-point flux [+ dissipation]); one dual-number pass per component of
-// u1, the neighbour state u2 evaluated once in plain arithmetic.
-template <int D>
-__device__ __forceinline__ void facet_grad(const double *u1, const double *u2, const double *a, const double *mu,
-                                           const GasC<double> &G0, const GasC<Dual<double>> &G, bool diss,
-                                           double *out) {
-  constexpr int NC = D + 2;
-  Dual<double> av[D];
-#pragma unroll
-  for (int i = 0; i < D; ++i) av[i] = Dual<double>(a[i]);
-  Node<D, double> m2;
-  node_from_u<D, double>(u2, G0, m2);
-  node_powers<D, double>(G0, m2);
-  Node<D, Dual<double>> n2;
-  n2.rho = m2.rho;
-#pragma unroll
-  for (int i = 0; i < D; ++i) n2.V[i] = m2.V[i];
-  n2.p = m2.p;
-  n2.lrho = m2.lrho;
-  n2.lp = m2.lp;
-  n2.lz1 = m2.lz1;
-  n2.z1 = m2.z1;
-  n2.P1 = m2.P1;
-  n2.P2 = m2.P2;
-#pragma unroll
-  for (int c = 0; c < NC; ++c) n2.w[c] = m2.w[c];
-  n2.ok = m2.ok;
-  // one pass at a time: unrolled, the passes' dual states would be live
-  // together (several hundred registers)
-#pragma unroll 1
-  for (int c = 0; c < NC; ++c) {
-    Dual<double> x1[NC];
-#pragma unroll
-    for (int q = 0; q < NC; ++q) x1[q] = Dual<double>(u1[q], q == c ? 1.0 : 0.0);
-    Node<D, Dual<double>> n1;
-    node_from_u<D, Dual<double>>(x1, G, n1);
-    node_powers<D, Dual<double>>(G, n1);
-    Dual<double> ph[NC];
-    facet_term<D, Dual<double>>(n1, n2, av, G, diss, ph);
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < NC; ++q) s += mu[q] * ph[q].d;
-#pragma unroll
-    for (int q = 0; q < NC; ++q) out[q] = q == c ? s : out[q];
-  }
-}
 
 // (dW/dU) y as the derivative of w(u + e y)
 template <int D>
@@ -107,8 +60,11 @@ __device__ __forceinline__ void dWdU_apply(const double *u, const double *y, con
 // forward kernel.
 template <int P> struct VTileV3 { static constexpr int EB = P == 1 ? 21 : (P == 2 ? 10 : 4); };
 
+// two waves per SIMD (register cap 256) except at p = 1, where the cap spills
+// (measured on MI355X, 196608 tetrahedra: with the cap p = 3 takes 5.04 instead
+// of 5.77 ms, p = 1 0.87 instead of 0.60 ms)
 template <int P>
-__global__ __launch_bounds__(kT) void k_vjp3v(KArgs<double> A) {
+__global__ __launch_bounds__(kT, P == 1 ? 1 : 2) void k_vjp3v(KArgs<double> A) {
   constexpr int D = 3, NC = 5, NFAC = 4;
   constexpr int NP = Shape<3, P>::NP, NF = Shape<3, P>::NF, NFN = NFAC * NF;
   constexpr int EB = VTileV3<P>::EB;
@@ -266,7 +222,11 @@ __global__ __launch_bounds__(kT) void k_vjp3v(KArgs<double> A) {
         double mu[NC], g1[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) mu[c] = lm[c] * iH - lv[c] / Hv;
-        facet_grad<D>(uu, uv, ak, mu, G, GD, A.diss != 0, g1);
+        Node<D, double> nk = n, nv;
+        node_powers<D, double>(G, nk);
+        node_from_u<D, double>(uv, G, nv);
+        node_powers<D, double>(G, nv);
+        facet_grad_rev<D>(nk, nv, ak, mu, G, A.diss != 0, g1);
 #pragma unroll
         for (int c = 0; c < NC; ++c) ub[c] -= g1[c];
       }
@@ -429,7 +389,11 @@ struct Vjp2 {
         double mu[NC], g1[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) mu[c] = lm[c] * iH - lv[c] / Hv;
-        facet_grad<D>(uu, uv, ak, mu, G, GD, A.diss != 0, g1);
+        Node<D, double> nk = n, nv;
+        node_powers<D, double>(G, nk);
+        node_from_u<D, double>(uv, G, nv);
+        node_powers<D, double>(G, nv);
+        facet_grad_rev<D>(nk, nv, ak, mu, G, A.diss != 0, g1);
 #pragma unroll
         for (int c = 0; c < NC; ++c) ub[c] -= g1[c];
       }
@@ -441,8 +405,9 @@ struct Vjp2 {
   }
 };
 
+// two waves per SIMD (measured on MI355X, 32768 triangles: p = 4 170 -> 136 us)
 template <int P>
-__global__ __launch_bounds__(kT) void k_vjp2(KArgs<double> A) {
+__global__ __launch_bounds__(kT, 2) void k_vjp2(KArgs<double> A) {
   typedef Vjp2<P> K;
   __shared__ typename K::Lds lds;
   K::load_ops(A, lds);
