@@ -143,6 +143,48 @@ int sbp_rrk_step(sbp_mesh *mesh, void *u_dev, double dt, double cfl,
  * the stream themselves).  Not in the paper.  SBP_EINVAL for a null handle. */
 int sbp_use_graphs(sbp_mesh *mesh, int enable);
 
+/* One kernel slot tuned by sbp_autotune. */
+typedef struct {
+  int32_t kind;         /* 0: residual, 1: VJP                                    */
+  int32_t p;            /* degree class; 0: all classes of a 2D mesh in one launch */
+  int32_t variant;      /* chosen kernel variant (0: the built-in choice)         */
+  int32_t grid;         /* chosen grid: k > 0 -> k x resident workgroups (at most
+                           one per tile); 0 -> one workgroup per tile             */
+  int32_t n_candidates; /* launch shapes timed                                    */
+  double ms_builtin;    /* mean launch time of variant 0, grid 1                  */
+  double ms_best;       /* mean launch time of the chosen shape                   */
+} sbp_tune_slot;
+
+typedef struct {
+  int32_t n_slots;
+  sbp_tune_slot slot[8];
+} sbp_tune_report;
+
+/* Autotuner (not in the paper): for every kernel slot of the handle (each
+ * degree class of sbp_residual, or its single batched launch on a 2D mesh
+ * with several degrees; likewise of sbp_residual_vjp when lambda_dev != NULL)
+ * time each launch shape -- kernel variant (3D entropy split: skew operators
+ * in LDS or read through the caches; VJP: register budget of one or two
+ * waves per SIMD) times persistent grid (1x or 2x the resident workgroups, or
+ * one workgroup per tile) -- on the state u_dev and keep the fastest for
+ * later calls.  Results of all shapes agree up to the summation order of the
+ * FP64 entropy rate.  Choices are remembered for the process per workload
+ * (dimension, degree, precision, form, physics flags, element count, device);
+ * handles set up later with the same workload start from them.  A captured
+ * RRK stage graph is re-captured on the next sbp_rrk_step.  rep may be NULL.
+ * Synchronises hip_stream; overwrites the handle's RK work buffers.
+ * SBP_EINVAL for a null handle or state; SBP_EDEVICE if a launch fails. */
+int sbp_autotune(sbp_mesh *mesh, const void *u_dev, const void *lambda_dev, sbp_tune_report *rep,
+                 void *hip_stream);
+
+/* Read or pin the launch shape of one kernel slot: kind 0 residual, 1 VJP;
+ * p the degree class, or 0 for the batched launch of a 2D mesh with several
+ * degrees; variant < the slot's variant count (3D entropy split and VJP: 2,
+ * otherwise 1); grid 0..64 as in sbp_tune_slot.  Not in the paper.
+ * SBP_EINVAL for a slot the handle does not have or a value out of range. */
+int sbp_get_launch_shape(sbp_mesh *mesh, int32_t kind, int32_t p, int32_t *variant, int32_t *grid);
+int sbp_set_launch_shape(sbp_mesh *mesh, int32_t kind, int32_t p, int32_t variant, int32_t grid);
+
 /* FP64 diagnostics on the device, results copied to host (synchronises):
  * out[0] = 1^T H s(u); out[1..n_c] = sum_k 1^T H_k u_k per component. */
 int sbp_diagnostics(sbp_mesh *mesh, const void *u_dev, double *out_host,

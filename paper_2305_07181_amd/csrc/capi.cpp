@@ -14,6 +14,8 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <unordered_map>
@@ -59,7 +61,8 @@ struct DegreeClass {
   int *d_nbrq = nullptr;  // viscous: neighbour q index per facet node
   void *d_q = nullptr;    // viscous: facet normal viscous fluxes
   int part_off = 0;       // offset of this class in the residual partial buffer
-  int res_blocks = 0;
+  int res_blocks = 0;     // partial sums reserved: the largest grid of any launch shape
+  sbp::LaunchCfg res_cfg, vjp_cfg;  // launch shapes (autotuner)
   int node_off_blk = 0;   // offset in the node partial buffers
   int node_blocks = 0;
 };
@@ -79,6 +82,7 @@ struct sbp_mesh {
   double *d_part = nullptr;   // residual partials (sum over classes of blocks)
   int part_total = 0;
   int batch_blocks = 0;       // 2D entropy split with several degree classes: one launch
+  int batch_grid = 1, vjp_batch_grid = 1;  // grid choices of the batched launches (autotuner)
   double *d_npart = nullptr;  // node-kernel partials [(n_c+1) x node_total]
   int node_total = 0;
   double *d_scal = nullptr;   // device scalars
@@ -197,6 +201,8 @@ sbp::OpTables<T> tables_at(const T *base, const size_t off[11], int dim) {
   t.dN = base + off[7];
   return t;
 }
+
+void apply_tuned(sbp_mesh *M);
 
 int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp_mesh *M) {
   const int dim = D->dim;
@@ -431,8 +437,10 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
     HIPCHK(hipMemcpyAsync((char *)c.d_ops + bytes64, b32.data(), bytes32, hipMemcpyHostToDevice, s));
     c.op64 = tables_at<double>((const double *)c.d_ops, o64, dim);
     c.op32 = tables_at<float>((const float *)((char *)c.d_ops + bytes64), o32, dim);
-    c.res_blocks = std::max(sbp::residual_blocks(dim, c.p, 0, form_eff, c.n_elem),
-                            sbp::residual_blocks(dim, c.p, 1, form_eff, c.n_elem));
+    c.res_blocks = 0;
+    for (int pr = 0; pr < 2; ++pr)
+      for (int v = 0; v < sbp::residual_variants(dim, c.p, pr, form_eff); ++v)
+        c.res_blocks = std::max(c.res_blocks, sbp::residual_blocks(dim, c.p, pr, form_eff, c.n_elem, {v, 0}));
     c.part_off = part_total;
     part_total += c.res_blocks;
     c.node_blocks = sbp::node_blocks(c.n_elem, np);
@@ -443,7 +451,7 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
   if (dim == 2 && form_eff == 0 && M->cls.size() > 1) {
     int ne_p[4] = {0, 0, 0, 0};
     for (auto &c : M->cls) ne_p[c.p - 1] = c.n_elem;
-    M->batch_blocks = std::max(sbp::residual2_batch_blocks(ne_p, 0), sbp::residual2_batch_blocks(ne_p, 1));
+    M->batch_blocks = std::max(sbp::residual2_batch_blocks(ne_p, 0, 0), sbp::residual2_batch_blocks(ne_p, 1, 0));
     part_total = std::max(part_total, M->batch_blocks);
   }
   M->part_total = part_total;
@@ -458,6 +466,7 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
   HIPCHK(hipMalloc((void **)&M->d_err, sizeof(int)));
   HIPCHK(hipMemsetAsync(M->d_err, 0, sizeof(int), s));
   HIPCHK(hipStreamSynchronize(s));
+  apply_tuned(M);
   return SBP_OK;
 }
 
@@ -530,28 +539,28 @@ int residual_impl(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStr
       }
     }
     if (ph.precision == SBP_FP64)
-      HIPCHK(sbp::launch_residual2_batch(p64, M->d_part, s));
+      HIPCHK(sbp::launch_residual2_batch(p64, M->d_part, s, M->batch_grid));
     else
-      HIPCHK(sbp::launch_residual2_batch(p32, M->d_part, s));
+      HIPCHK(sbp::launch_residual2_batch(p32, M->d_part, s, M->batch_grid));
     if (ent_dev) {
       int ne_p[4] = {0, 0, 0, 0};
       for (auto &c : M->cls) ne_p[c.p - 1] = c.n_elem;
-      const int nb = sbp::residual2_batch_blocks(ne_p, ph.precision == SBP_FP64 ? 0 : 1);
+      const int nb = sbp::residual2_batch_blocks(ne_p, ph.precision == SBP_FP64 ? 0 : 1, M->batch_grid);
       HIPCHK(sbp::launch_reduce(M->d_part, nb, 1, 0, ent_dev, s));
     }
     return SBP_OK;
   }
   for (auto &c : M->cls) {
     if (ph.precision == SBP_FP64)
-      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, kargs<double>(M, c, u, r, c.op64), s));
+      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, kargs<double>(M, c, u, r, c.op64), s, c.res_cfg));
     else
-      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, kargs<float>(M, c, u, r, c.op32), s));
+      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, kargs<float>(M, c, u, r, c.op32), s, c.res_cfg));
   }
   if (ent_dev) {
     const int form_eff = ph.viscous ? 2 : ph.form;
     for (size_t ci = 0; ci < M->cls.size(); ++ci) {
       auto &c = M->cls[ci];
-      const int nb = sbp::residual_blocks(M->dim, c.p, ph.precision, form_eff, c.n_elem);
+      const int nb = sbp::residual_blocks(M->dim, c.p, ph.precision, form_eff, c.n_elem, c.res_cfg);
       HIPCHK(sbp::launch_reduce(M->d_part + c.part_off, nb, 1, 0, M->d_scal + SC_RED + ci, s));
     }
     HIPCHK(sbp::launch_reduce(M->d_scal + SC_RED, (int)M->cls.size(), 1, 0, ent_dev, s));
@@ -586,6 +595,17 @@ int entropy_gap(sbp_mesh *M, const double *u, const double *d, double g, double 
     HIPCHK(sbp::launch_entropy_gap(A, g, M->d_npart + c.node_off_blk, s));
   }
   return reduce_nodes(M, 3, 0, out, s);
+}
+
+// RK work buffers (stage state, direction, stage residual), allocated on
+// first use by sbp_rrk_step or sbp_autotune.
+int ensure_rk_buffers(sbp_mesh *M) {
+  const size_t n = (size_t)M->n_dof;
+  const size_t rsz = M->phys.precision == SBP_FP32 ? sizeof(float) : sizeof(double);
+  if (!M->d_y) HIPCHK(hipMalloc((void **)&M->d_y, sizeof(double) * n));
+  if (!M->d_d) HIPCHK(hipMalloc((void **)&M->d_d, sizeof(double) * n));
+  if (!M->d_r) HIPCHK(hipMalloc(&M->d_r, rsz * n));
+  return SBP_OK;
 }
 
 // The four RK stages of one step (Sec. 6.1): y_i = u + c_i dt r_{i-1},
@@ -645,6 +665,205 @@ int diagnostics_impl(sbp_mesh *M, const double *u, double *out, hipStream_t s) {
     HIPCHK(sbp::launch_diagnostics(A, M->d_npart + c.node_off_blk, s));
   }
   return reduce_nodes(M, M->nc + 1, 0, out, s);
+}
+
+// --------------------------------------------------------------------------
+// Autotuner.  Every kernel slot of a handle (one degree class of the
+// residual or of the VJP, or the batched launch of all classes of a 2D mesh)
+// has a launch shape (kernel variant x grid, sbp::LaunchCfg).  sbp_autotune
+// times each candidate on the caller's state and keeps the fastest; the
+// choice is remembered for the process per workload key, and handles set up
+// later with the same key start from it.
+enum { TUNE_RES = 0, TUNE_VJP = 1 };
+
+typedef std::array<long long, 9> TuneKey;
+
+std::mutex g_tune_mu;
+std::map<TuneKey, sbp::LaunchCfg> g_tune;
+
+TuneKey tune_key(const sbp_mesh *M, int kind, int p, long long n_elem) {
+  const sbp_physics &ph = M->phys;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  return {kind, M->dim, p, ph.precision, ph.form, ph.viscous, ph.dissipation, n_elem, dev};
+}
+
+bool tune_lookup(const TuneKey &k, sbp::LaunchCfg &cfg) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  const auto it = g_tune.find(k);
+  if (it == g_tune.end()) return false;
+  cfg = it->second;
+  return true;
+}
+
+void tune_store(const TuneKey &k, const sbp::LaunchCfg &cfg) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune[k] = cfg;
+}
+
+// launch shapes remembered for this workload (called at the end of setup)
+void apply_tuned(sbp_mesh *M) {
+  sbp::LaunchCfg cfg;
+  if (M->batch_blocks > 0) {
+    if (tune_lookup(tune_key(M, TUNE_RES, 0, M->n_elem), cfg)) M->batch_grid = cfg.grid;
+    if (tune_lookup(tune_key(M, TUNE_VJP, 0, M->n_elem), cfg)) M->vjp_batch_grid = cfg.grid;
+  }
+  for (auto &c : M->cls) {
+    if (tune_lookup(tune_key(M, TUNE_RES, c.p, c.n_elem), cfg)) c.res_cfg = cfg;
+    if (tune_lookup(tune_key(M, TUNE_VJP, c.p, c.n_elem), cfg)) c.vjp_cfg = cfg;
+  }
+}
+
+// mean time in ms of `reps` launches after two untimed ones; < 0 on error
+template <typename F>
+double time_launches(F launch, hipStream_t s, int reps) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess) return -1.0;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return -1.0;
+  }
+  double ms = -1.0;
+  bool ok = launch() == hipSuccess && launch() == hipSuccess && hipEventRecord(e0, s) == hipSuccess;
+  for (int i = 0; ok && i < reps; ++i) ok = launch() == hipSuccess;
+  float t = 0.0f;
+  if (ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+      hipEventElapsedTime(&t, e0, e1) == hipSuccess)
+    ms = (double)t / reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms;
+}
+
+// Try every (variant, grid) of one slot; `run(cfg)` launches it.  Returns
+// SBP_OK and fills the report slot, or the launch error.
+template <typename F>
+int tune_slot(int nvar, F run, hipStream_t s, sbp::LaunchCfg &best, sbp_tune_slot *out) {
+  constexpr int kReps = 5;
+  double best_ms = -1.0, builtin_ms = -1.0;
+  int n = 0;
+  sbp::LaunchCfg pick = best;
+  for (int v = 0; v < nvar; ++v)
+    for (int g : sbp::kGridChoices) {
+      const sbp::LaunchCfg cfg{v, g};
+      const double ms = time_launches([&]() { return run(cfg); }, s, kReps);
+      if (ms < 0.0) {
+        const hipError_t e = hipGetLastError();
+        return fail(SBP_EDEVICE, std::string("autotune launch failed: ") + hipGetErrorString(e));
+      }
+      ++n;
+      if (v == 0 && g == 1) builtin_ms = ms;
+      if (best_ms < 0.0 || ms < best_ms) {
+        best_ms = ms;
+        pick = cfg;
+      }
+    }
+  best = pick;
+  if (out) {
+    out->variant = pick.variant;
+    out->grid = pick.grid;
+    out->n_candidates = n;
+    out->ms_builtin = builtin_ms;
+    out->ms_best = best_ms;
+  }
+  return SBP_OK;
+}
+
+int autotune_impl(sbp_mesh *M, const double *u, const double *lam, sbp_tune_report *rep, hipStream_t s) {
+  const sbp_physics &ph = M->phys;
+  const int f32 = ph.precision == SBP_FP32;
+  const int form_eff = ph.viscous ? 2 : ph.form;
+  sbp_tune_report local{};
+  sbp_tune_report &R = rep ? *rep : local;
+  R.n_slots = 0;
+  int rc;
+  // outputs of the timed launches go to the RK work buffers
+  if ((rc = ensure_rk_buffers(M))) return rc;
+  auto next_slot = [&](int kind, int p) -> sbp_tune_slot * {
+    if (R.n_slots >= (int)(sizeof(R.slot) / sizeof(R.slot[0]))) return nullptr;
+    sbp_tune_slot *t = &R.slot[R.n_slots++];
+    *t = sbp_tune_slot{};
+    t->kind = kind;
+    t->p = p;
+    return t;
+  };
+  if (ph.viscous)  // the Navier-Stokes kernel reads the facet fluxes of this state
+    for (auto &c : M->cls) {
+      if (!f32)
+        HIPCHK(sbp::launch_visc_q(M->dim, c.p, kargs<double>(M, c, u, M->d_r, c.op64), s));
+      else
+        HIPCHK(sbp::launch_visc_q(M->dim, c.p, kargs<float>(M, c, u, M->d_r, c.op32), s));
+    }
+  if (M->batch_blocks > 0 && ph.form == SBP_FORM_SPLIT && !ph.viscous) {
+    sbp::KArgs<double> a64[4];
+    sbp::KArgs<float> a32[4];
+    const sbp::KArgs<double> *p64[4] = {nullptr, nullptr, nullptr, nullptr};
+    const sbp::KArgs<float> *p32[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (auto &c : M->cls) {
+      a64[c.p - 1] = kargs<double>(M, c, u, M->d_r, c.op64);
+      a32[c.p - 1] = kargs<float>(M, c, u, M->d_r, c.op32);
+      p64[c.p - 1] = &a64[c.p - 1];
+      p32[c.p - 1] = &a32[c.p - 1];
+    }
+    sbp::LaunchCfg cfg{0, M->batch_grid};
+    auto run = [&](sbp::LaunchCfg k) {
+      return f32 ? sbp::launch_residual2_batch(p32, M->d_part, s, k.grid)
+                 : sbp::launch_residual2_batch(p64, M->d_part, s, k.grid);
+    };
+    if ((rc = tune_slot(1, run, s, cfg, next_slot(TUNE_RES, 0)))) return rc;
+    M->batch_grid = cfg.grid;
+    tune_store(tune_key(M, TUNE_RES, 0, M->n_elem), cfg);
+  } else {
+    for (auto &c : M->cls) {
+      const sbp::KArgs<double> A64 = kargs<double>(M, c, u, M->d_r, c.op64);
+      const sbp::KArgs<float> A32 = kargs<float>(M, c, u, M->d_r, c.op32);
+      auto run = [&](sbp::LaunchCfg k) {
+        return f32 ? sbp::launch_residual(M->dim, c.p, ph.form, A32, s, k)
+                   : sbp::launch_residual(M->dim, c.p, ph.form, A64, s, k);
+      };
+      if ((rc = tune_slot(sbp::residual_variants(M->dim, c.p, ph.precision, form_eff), run, s, c.res_cfg,
+                          next_slot(TUNE_RES, c.p))))
+        return rc;
+      tune_store(tune_key(M, TUNE_RES, c.p, c.n_elem), c.res_cfg);
+    }
+  }
+  if (lam && !ph.viscous && ph.form == SBP_FORM_SPLIT) {
+    auto vargs = [&](DegreeClass &c) {
+      sbp::KArgs<double> A = kargs<double>(M, c, u, nullptr, c.op64);
+      A.lam = lam;
+      A.ubar = M->d_y;
+      A.Hn = c.d_Hn;
+      return A;
+    };
+    if (M->dim == 2 && M->cls.size() > 1) {
+      sbp::KArgs<double> a[4];
+      const sbp::KArgs<double> *pa[4] = {nullptr, nullptr, nullptr, nullptr};
+      for (auto &c : M->cls) {
+        a[c.p - 1] = vargs(c);
+        pa[c.p - 1] = &a[c.p - 1];
+      }
+      sbp::LaunchCfg cfg{0, M->vjp_batch_grid};
+      auto run = [&](sbp::LaunchCfg k) { return sbp::launch_vjp2_batch(pa, s, k.grid); };
+      if ((rc = tune_slot(1, run, s, cfg, next_slot(TUNE_VJP, 0)))) return rc;
+      M->vjp_batch_grid = cfg.grid;
+      tune_store(tune_key(M, TUNE_VJP, 0, M->n_elem), cfg);
+    } else {
+      for (auto &c : M->cls) {
+        const sbp::KArgs<double> A = vargs(c);
+        auto run = [&](sbp::LaunchCfg k) { return sbp::launch_vjp(M->dim, c.p, A, s, k); };
+        if ((rc = tune_slot(sbp::vjp_variants(M->dim, c.p), run, s, c.vjp_cfg, next_slot(TUNE_VJP, c.p)))) return rc;
+        tune_store(tune_key(M, TUNE_VJP, c.p, c.n_elem), c.vjp_cfg);
+      }
+    }
+  }
+  // the captured RK stages hold the old launch shapes
+  if (M->rk_exec) {
+    (void)hipGraphExecDestroy(M->rk_exec);
+    M->rk_exec = nullptr;
+    M->rk_u = nullptr;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return check_err(M, s);
 }
 
 }  // namespace
@@ -724,7 +943,7 @@ int sbp_residual_vjp(sbp_mesh *M, const void *u, const void *lam, void *ubar, vo
       A.Hn = c.d_Hn;
       pa[c.p - 1] = &A;
     }
-    HIPCHK(sbp::launch_vjp2_batch(pa, (hipStream_t)stream));
+    HIPCHK(sbp::launch_vjp2_batch(pa, (hipStream_t)stream, M->vjp_batch_grid));
     return SBP_OK;
   }
   for (auto &c : M->cls) {
@@ -732,7 +951,7 @@ int sbp_residual_vjp(sbp_mesh *M, const void *u, const void *lam, void *ubar, vo
     A.lam = (const double *)lam;
     A.ubar = (double *)ubar;
     A.Hn = c.d_Hn;
-    HIPCHK(sbp::launch_vjp(M->dim, c.p, A, (hipStream_t)stream));
+    HIPCHK(sbp::launch_vjp(M->dim, c.p, A, (hipStream_t)stream, c.vjp_cfg));
   }
   return SBP_OK;
 }
@@ -758,6 +977,65 @@ int sbp_use_graphs(sbp_mesh *M, int enable) {
   return SBP_OK;
 }
 
+int sbp_autotune(sbp_mesh *M, const void *u, const void *lam, sbp_tune_report *rep, void *stream) {
+  if (!M || !u) return fail(SBP_EINVAL, "null argument");
+  return autotune_impl(M, (const double *)u, (const double *)lam, rep, (hipStream_t)stream);
+}
+
+namespace {
+
+// the slot (kind, p) of the handle: its config, or nullptr; grid-only slots
+// (batched launches) report nvar = 1
+sbp::LaunchCfg *find_slot(sbp_mesh *M, int kind, int p, int &nvar, int *&grid_only) {
+  grid_only = nullptr;
+  const sbp_physics &ph = M->phys;
+  const int form_eff = ph.viscous ? 2 : ph.form;
+  if (kind == TUNE_VJP && (ph.viscous || ph.form != SBP_FORM_SPLIT)) return nullptr;
+  const bool batched = kind == TUNE_RES ? (M->batch_blocks > 0 && ph.form == SBP_FORM_SPLIT && !ph.viscous)
+                                        : (M->dim == 2 && M->cls.size() > 1);
+  if (batched) {
+    if (p != 0) return nullptr;
+    nvar = 1;
+    grid_only = kind == TUNE_RES ? &M->batch_grid : &M->vjp_batch_grid;
+    return nullptr;
+  }
+  for (auto &c : M->cls)
+    if (c.p == p) {
+      nvar = kind == TUNE_RES ? sbp::residual_variants(M->dim, p, ph.precision, form_eff) : sbp::vjp_variants(M->dim, p);
+      return kind == TUNE_RES ? &c.res_cfg : &c.vjp_cfg;
+    }
+  return nullptr;
+}
+
+}  // namespace
+
+int sbp_get_launch_shape(sbp_mesh *M, int32_t kind, int32_t p, int32_t *variant, int32_t *grid) {
+  if (!M || (kind != 0 && kind != 1)) return fail(SBP_EINVAL, "bad handle or kind");
+  int nvar = 0, *g = nullptr;
+  sbp::LaunchCfg *c = find_slot(M, kind, p, nvar, g);
+  if (!c && !g) return fail(SBP_EINVAL, "no such kernel slot");
+  if (variant) *variant = c ? c->variant : 0;
+  if (grid) *grid = c ? c->grid : *g;
+  return SBP_OK;
+}
+
+int sbp_set_launch_shape(sbp_mesh *M, int32_t kind, int32_t p, int32_t variant, int32_t grid) {
+  if (!M || (kind != 0 && kind != 1)) return fail(SBP_EINVAL, "bad handle or kind");
+  int nvar = 0, *g = nullptr;
+  sbp::LaunchCfg *c = find_slot(M, kind, p, nvar, g);
+  if (!c && !g) return fail(SBP_EINVAL, "no such kernel slot");
+  if (variant < 0 || variant >= nvar) return fail(SBP_EINVAL, "variant out of range");
+  if (grid < 0 || grid > 64) return fail(SBP_EINVAL, "grid must be 0..64");
+  if (c) *c = sbp::LaunchCfg{variant, grid};
+  else *g = grid;
+  if (M->rk_exec) {
+    (void)hipGraphExecDestroy(M->rk_exec);
+    M->rk_exec = nullptr;
+    M->rk_u = nullptr;
+  }
+  return SBP_OK;
+}
+
 int sbp_set_time(sbp_mesh *M, double t) {
   if (!M) return fail(SBP_EINVAL, "null argument");
   M->t = t;
@@ -770,12 +1048,8 @@ int sbp_rrk_step(sbp_mesh *M, void *u_dev, double dt, double cfl, sbp_rrk_report
   double *u = (double *)u_dev;
   const long long n = M->n_dof;
   const int f32 = M->phys.precision == SBP_FP32;
-  if (!M->d_y) {
-    HIPCHK(hipMalloc((void **)&M->d_y, sizeof(double) * n));
-    HIPCHK(hipMalloc((void **)&M->d_d, sizeof(double) * n));
-    HIPCHK(hipMalloc(&M->d_r, (f32 ? sizeof(float) : sizeof(double)) * n));
-  }
   int rc;
+  if ((rc = ensure_rk_buffers(M))) return rc;
   if (!(dt > 0.0)) {
     if (!(cfl > 0.0)) return fail(SBP_EINVAL, "need dt > 0 or cfl > 0");
     for (auto &c : M->cls) {

@@ -6,23 +6,46 @@
 
 namespace sbp {
 
-// Residual of one degree class (form 0: entropy split, 1: Hadamard).
-hipError_t launch_residual(int dim, int p, int form, const KArgs<double> &A, hipStream_t s);
-hipError_t launch_residual(int dim, int p, int form, const KArgs<float> &A, hipStream_t s);
-int residual_blocks(int dim, int p, int precision, int form, int n_elem);
+// Launch shape of one kernel slot.  Every residual and VJP kernel is
+// persistent (its workgroups loop over the element tiles), so any grid is
+// correct; grid and kernel variant only change the speed and are picked by
+// the autotuner (capi.cpp, sbp_autotune).
+struct LaunchCfg {
+  int variant = 0;  // 0: the built-in choice; 1: the alternative (see *_variants)
+  int grid = 1;     // k > 0: k x (CUs x resident workgroups per CU), capped at
+                    // one workgroup per tile; 0: one workgroup per tile
+};
+constexpr int kGridChoices[3] = {1, 2, 0};
+
+// Workgroups that the device keeps resident for `kernel` (256 threads),
+// cached per device and kernel; launch_grid applies LaunchCfg::grid.
+int resident_blocks(const void *kernel);
+int launch_grid(const void *kernel, int ntiles, int grid);
+
+// Residual of one degree class (form 0: entropy split, 1: Hadamard; the
+// Navier-Stokes terms are selected by A.visc).
+hipError_t launch_residual(int dim, int p, int form, const KArgs<double> &A, hipStream_t s, LaunchCfg cfg = {});
+hipError_t launch_residual(int dim, int p, int form, const KArgs<float> &A, hipStream_t s, LaunchCfg cfg = {});
+// form_eff: 0 entropy split, 1 Hadamard, 2 entropy split with Navier-Stokes terms
+int residual_blocks(int dim, int p, int precision, int form_eff, int n_elem, LaunchCfg cfg = {});
+// kernel variants of a slot: 3D entropy split (Euler): skew operators in LDS
+// or read through the caches; otherwise one
+int residual_variants(int dim, int p, int precision, int form_eff);
 // 2D entropy split, every degree class in one persistent launch: cls[p-1] is
 // the class of degree p or null.  Workgroups of the launch (partial sums):
-int residual2_batch_blocks(const int n_elem_of_p[4], int precision);
-hipError_t launch_residual2_batch(const KArgs<double> *const cls[4], double *ent_part, hipStream_t s);
-hipError_t launch_residual2_batch(const KArgs<float> *const cls[4], double *ent_part, hipStream_t s);
+int residual2_batch_blocks(const int n_elem_of_p[4], int precision, int grid = 1);
+hipError_t launch_residual2_batch(const KArgs<double> *const cls[4], double *ent_part, hipStream_t s, int grid = 1);
+hipError_t launch_residual2_batch(const KArgs<float> *const cls[4], double *ent_part, hipStream_t s, int grid = 1);
 // Viscous facet-flux pre-pass (3D): A.qout[(e*NFAC*NF + m)*n_c + c] = B n . F^V
 hipError_t launch_visc_q(int dim, int p, const KArgs<double> &A, hipStream_t s);
 hipError_t launch_visc_q(int dim, int p, const KArgs<float> &A, hipStream_t s);
 
 // Vector-Jacobian product of the entropy-split residual (FP64, Euler terms).
-hipError_t launch_vjp(int dim, int p, const KArgs<double> &A, hipStream_t s);
+// Variants: register budget of one or two waves per SIMD.
+hipError_t launch_vjp(int dim, int p, const KArgs<double> &A, hipStream_t s, LaunchCfg cfg = {});
+int vjp_variants(int dim, int p);
 // 2D, every degree class in one persistent launch (cls[p-1] or null)
-hipError_t launch_vjp2_batch(const KArgs<double> *const cls[4], hipStream_t s);
+hipError_t launch_vjp2_batch(const KArgs<double> *const cls[4], hipStream_t s, int grid = 1);
 
 // Per-node pointwise work over one degree class.
 struct NodeArgs {

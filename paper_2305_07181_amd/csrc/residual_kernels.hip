@@ -24,6 +24,11 @@
 // facet epilogue.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "kernels.hpp"
 #include "launch.hpp"
 #include "mfma.hpp"
@@ -971,150 +976,94 @@ int tile_elems(int dim, int p, int form) {
   return 0;
 }
 
-// Persistent grid of the 2D split kernel: at most as many workgroups as the
-// device keeps resident at once.
-template <int P, typename T>
-static int split2_grid(int n_elem) {
-  static int cap = 0;
-  if (cap == 0) {
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_split2<P, T>, kThreads, 0) != hipSuccess ||
-        cus <= 0 || per <= 0)
-      cap = 1024;
-    else
-      cap = cus * per;
-  }
-  const int per_block = VTile2<P, T>::EB;
-  return std::min((n_elem + per_block - 1) / per_block, cap);
-}
-
-// Persistent grid of the 3D split kernel.
-template <int P, typename T, bool VISC>
-static int split3_grid(int n_elem) {
-  static int cap = 0;
-  if (cap == 0) {
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_split3<P, T, VISC>, kThreads, 0) != hipSuccess ||
-        cus <= 0 || per <= 0)
-      cap = 1024;
-    else
-      cap = cus * per;
-  }
-  const int eb = 3 * Wave3<P, T>::CT;
-  return std::min((n_elem + eb - 1) / eb, cap);
-}
-
-// Persistent grid of the Hadamard kernel.
-template <int DIM, int P, typename T>
-static int hadamard_grid(int n_elem) {
-  static int cap = 0;
-  if (cap == 0) {
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_hadamard<DIM, P, T>, kThreads, 0) != hipSuccess ||
-        cus <= 0 || per <= 0)
-      cap = 1024;
-    else
-      cap = cus * per;
-  }
-  const int eb = HadTile<DIM, P, T>::EB;
-  return std::min((n_elem + eb - 1) / eb, cap);
-}
-
 // The 3D Euler split terms run in the row form.  At p = 3 in FP64 its three
 // 60 x 60 skew operators would take 86 KB of LDS (one wave per SIMD); there
-// they are read through the caches instead (measured on MI355X: 2.82 ms
-// against 2.97 ms for the contraction form on 196608 tetrahedra).
+// the built-in choice reads them through the caches instead (measured on
+// MI355X: 2.82 ms against 2.97 ms for the contraction form on 196608
+// tetrahedra).  The autotuner may pick the other variant.
 template <int P, typename T>
 constexpr bool skew_from_cache3() {
   return P == 3 && sizeof(T) == 8;
 }
 
-// Persistent grid of the 3D row-form split kernel.
-template <int P, typename T>
-static int split3v_grid(int n_elem) {
-  static int cap = 0;
-  if (cap == 0) {
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_split3v<P, T, skew_from_cache3<P, T>()>, kThreads, 0) != hipSuccess ||
-        cus <= 0 || per <= 0)
-      cap = 1024;
-    else
-      cap = cus * per;
+struct KernelRef {
+  const void *fn;
+  int eb;  // elements per tile
+};
+
+// Kernel of a residual slot; form_eff 0: entropy split (Euler), 1: Hadamard,
+// 2: entropy split with the Navier-Stokes terms.
+template <typename T>
+static KernelRef residual_kernel(int dim, int p, int form_eff, int variant) {
+#define SBP_K2(PP)                                                                              \
+  if (dim == 2 && p == PP) {                                                                    \
+    if (form_eff == 1) return {reinterpret_cast<const void *>(&k_hadamard<2, PP, T>), HadTile<2, PP, T>::EB}; \
+    if (form_eff == 0) return {reinterpret_cast<const void *>(&k_split2<PP, T>), VTile2<PP, T>::EB};         \
+    return {nullptr, 0};                                                                        \
   }
-  const int eb = VTile3<P, T>::EB;
-  return std::min((n_elem + eb - 1) / eb, cap);
+  SBP_K2(1) SBP_K2(2) SBP_K2(3) SBP_K2(4)
+#undef SBP_K2
+#define SBP_K3(PP)                                                                              \
+  if (dim == 3 && p == PP) {                                                                    \
+    if (form_eff == 1) return {reinterpret_cast<const void *>(&k_hadamard<3, PP, T>), HadTile<3, PP, T>::EB}; \
+    if (form_eff == 2) return {reinterpret_cast<const void *>(&k_split3<PP, T, true>), 3 * Wave3<PP, T>::CT}; \
+    const bool sg = skew_from_cache3<PP, T>() != (variant == 1);                                \
+    return {sg ? reinterpret_cast<const void *>(&k_split3v<PP, T, true>)                        \
+               : reinterpret_cast<const void *>(&k_split3v<PP, T, false>),                      \
+            VTile3<PP, T>::EB};                                                                 \
+  }
+  SBP_K3(1) SBP_K3(2) SBP_K3(3)
+#undef SBP_K3
+  return {nullptr, 0};
 }
 
-int residual_blocks(int dim, int p, int precision, int form, int n_elem) {
+int resident_blocks(const void *kernel) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void *>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_pair(dev, kernel);
+  const auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int cus = 0, per = 0, cap = 1024;
+  if (dev >= 0 && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kThreads, 0) == hipSuccess && cus > 0 && per > 0)
+    cap = cus * per;
+  cache[key] = cap;
+  return cap;
+}
+
+int launch_grid(const void *kernel, int ntiles, int grid) {
+  if (ntiles <= 0) return 0;
+  if (grid <= 0) return ntiles;
+  const long long cap = (long long)grid * resident_blocks(kernel);
+  return (int)std::min<long long>(ntiles, cap);
+}
+
+int residual_variants(int dim, int p, int precision, int form_eff) {
+  (void)p;
+  (void)precision;
+  return dim == 3 && form_eff == 0 ? 2 : 1;
+}
+
+int residual_blocks(int dim, int p, int precision, int form_eff, int n_elem, LaunchCfg cfg) {
   if (n_elem <= 0) return 0;
-  if (form == 1) {
-#define SBP_GH(DI, PP) \
-  if (dim == DI && p == PP) \
-    return precision == 0 ? hadamard_grid<DI, PP, double>(n_elem) : hadamard_grid<DI, PP, float>(n_elem);
-    SBP_GH(2, 1) SBP_GH(2, 2) SBP_GH(2, 3) SBP_GH(2, 4) SBP_GH(3, 1) SBP_GH(3, 2) SBP_GH(3, 3)
-#undef SBP_GH
-    return 0;
-  }
-  if (dim == 3 && (form == 0 || form == 2)) {
-#define SBP_G3(PP)                                                                            \
-  if (p == PP) {                                                                              \
-    if (form == 2)                                                                            \
-      return precision == 0 ? split3_grid<PP, double, true>(n_elem) : split3_grid<PP, float, true>(n_elem); \
-    return precision == 0 ? split3v_grid<PP, double>(n_elem) : split3v_grid<PP, float>(n_elem); \
-  }
-    SBP_G3(1) SBP_G3(2) SBP_G3(3)
-#undef SBP_G3
-    return 0;
-  }
-  if (dim == 2 && form == 0) {
-#define SBP_G2(PP) \
-  if (p == PP) return precision == 0 ? split2_grid<PP, double>(n_elem) : split2_grid<PP, float>(n_elem);
-    SBP_G2(1) SBP_G2(2) SBP_G2(3) SBP_G2(4)
-#undef SBP_G2
-    return 0;
-  }
-  const int eb = precision == 0 ? tile_elems<double>(dim, p, form) : tile_elems<float>(dim, p, form);
-  if (eb <= 0) return 0;
-  return (n_elem + eb - 1) / eb;
+  const KernelRef k = precision == 0 ? residual_kernel<double>(dim, p, form_eff, cfg.variant)
+                                     : residual_kernel<float>(dim, p, form_eff, cfg.variant);
+  if (!k.fn) return 0;
+  return launch_grid(k.fn, (n_elem + k.eb - 1) / k.eb, cfg.grid);
 }
 
 template <typename T>
-static hipError_t launch_t(int dim, int p, int form, const KArgs<T> &A, hipStream_t s) {
+static hipError_t launch_t(int dim, int p, int form, const KArgs<T> &A, hipStream_t s, LaunchCfg cfg) {
   if (A.visc && (dim != 3 || form != 0)) return hipErrorInvalidValue;
-  const int nb = residual_blocks(dim, p, sizeof(T) == 8 ? 0 : 1, A.visc ? 2 : form, A.n_elem);
-  if (nb <= 0) return hipErrorInvalidValue;
-  dim3 grid(nb), block(kThreads);
-#define SBP_LAUNCH(DI, PP)                                                 \
-  if (dim == DI && p == PP) {                                              \
-    if (form == 1)                                                         \
-      hipLaunchKernelGGL((k_hadamard<DI, PP, T>), grid, block, 0, s, A);   \
-    else                                                                   \
-      hipLaunchKernelGGL((k_split2<PP, T>), grid, block, 0, s, A);         \
-    return hipGetLastError();                                              \
-  }
-  SBP_LAUNCH(2, 1) SBP_LAUNCH(2, 2) SBP_LAUNCH(2, 3) SBP_LAUNCH(2, 4)
-#undef SBP_LAUNCH
-#define SBP_LAUNCH3(PP)                                                  \
-  if (dim == 3 && p == PP) {                                             \
-    if (form == 1)                                                       \
-      hipLaunchKernelGGL((k_hadamard<3, PP, T>), grid, block, 0, s, A);  \
-    else if (A.visc)                                                     \
-      hipLaunchKernelGGL((k_split3<PP, T, true>), grid, block, 0, s, A); \
-    else                                                                 \
-      hipLaunchKernelGGL((k_split3v<PP, T, skew_from_cache3<PP, T>()>), grid, block, 0, s, A); \
-    return hipGetLastError();                                            \
-  }
-  SBP_LAUNCH3(1) SBP_LAUNCH3(2) SBP_LAUNCH3(3)
-#undef SBP_LAUNCH3
-  return hipErrorInvalidValue;
+  const KernelRef k = residual_kernel<T>(dim, p, A.visc ? 2 : form, cfg.variant);
+  if (!k.fn || A.n_elem <= 0) return hipErrorInvalidValue;
+  const int nb = launch_grid(k.fn, (A.n_elem + k.eb - 1) / k.eb, cfg.grid);
+  KArgs<T> a = A;
+  void *args[] = {&a};
+  return hipLaunchKernel(k.fn, dim3(nb), dim3(kThreads), args, 0, s);
 }
 
 template <typename T>
@@ -1132,22 +1081,6 @@ static hipError_t launch_q(int dim, int p, const KArgs<T> &A, hipStream_t s) {
 
 hipError_t launch_visc_q(int dim, int p, const KArgs<double> &A, hipStream_t s) { return launch_q<double>(dim, p, A, s); }
 hipError_t launch_visc_q(int dim, int p, const KArgs<float> &A, hipStream_t s) { return launch_q<float>(dim, p, A, s); }
-
-template <typename T>
-static int split2_batch_cap() {
-  static int cap = 0;
-  if (cap == 0) {
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_split2_batch<T>, kThreads, 0) != hipSuccess ||
-        cus <= 0 || per <= 0)
-      cap = 1024;
-    else
-      cap = cus * per;
-  }
-  return cap;
-}
 
 template <typename T>
 static int split2_ew(int p) {
@@ -1169,15 +1102,15 @@ static int batch_groups(const int n_elem_of_p[4], int g0[5]) {
   return g0[4];
 }
 
-int residual2_batch_blocks(const int n_elem_of_p[4], int precision) {
+int residual2_batch_blocks(const int n_elem_of_p[4], int precision, int grid) {
   int g0[5];
-  const int ng = precision == 0 ? batch_groups<double>(n_elem_of_p, g0) : batch_groups<float>(n_elem_of_p, g0);
-  const int cap = precision == 0 ? split2_batch_cap<double>() : split2_batch_cap<float>();
-  return std::min(ng, cap);
+  if (precision == 0)
+    return launch_grid(reinterpret_cast<const void *>(&k_split2_batch<double>), batch_groups<double>(n_elem_of_p, g0), grid);
+  return launch_grid(reinterpret_cast<const void *>(&k_split2_batch<float>), batch_groups<float>(n_elem_of_p, g0), grid);
 }
 
 template <typename T>
-static hipError_t launch_batch2_t(const KArgs<T> *const cls[4], double *ent_part, hipStream_t s) {
+static hipError_t launch_batch2_t(const KArgs<T> *const cls[4], double *ent_part, hipStream_t s, int grid) {
   Batch2<T> Bt{};
   int ne[4];
   for (int q = 0; q < 4; ++q) {
@@ -1187,23 +1120,23 @@ static hipError_t launch_batch2_t(const KArgs<T> *const cls[4], double *ent_part
   const int ng = batch_groups<T>(ne, Bt.g0);
   if (ng == 0) return hipSuccess;
   Bt.ent_part = ent_part;
-  const int nb = residual2_batch_blocks(ne, sizeof(T) == 8 ? 0 : 1);
+  const int nb = residual2_batch_blocks(ne, sizeof(T) == 8 ? 0 : 1, grid);
   hipLaunchKernelGGL((k_split2_batch<T>), dim3(nb), dim3(kThreads), 0, s, Bt);
   return hipGetLastError();
 }
 
-hipError_t launch_residual2_batch(const KArgs<double> *const cls[4], double *ent_part, hipStream_t s) {
-  return launch_batch2_t<double>(cls, ent_part, s);
+hipError_t launch_residual2_batch(const KArgs<double> *const cls[4], double *ent_part, hipStream_t s, int grid) {
+  return launch_batch2_t<double>(cls, ent_part, s, grid);
 }
-hipError_t launch_residual2_batch(const KArgs<float> *const cls[4], double *ent_part, hipStream_t s) {
-  return launch_batch2_t<float>(cls, ent_part, s);
+hipError_t launch_residual2_batch(const KArgs<float> *const cls[4], double *ent_part, hipStream_t s, int grid) {
+  return launch_batch2_t<float>(cls, ent_part, s, grid);
 }
 
-hipError_t launch_residual(int dim, int p, int form, const KArgs<double> &A, hipStream_t s) {
-  return launch_t<double>(dim, p, form, A, s);
+hipError_t launch_residual(int dim, int p, int form, const KArgs<double> &A, hipStream_t s, LaunchCfg cfg) {
+  return launch_t<double>(dim, p, form, A, s, cfg);
 }
-hipError_t launch_residual(int dim, int p, int form, const KArgs<float> &A, hipStream_t s) {
-  return launch_t<float>(dim, p, form, A, s);
+hipError_t launch_residual(int dim, int p, int form, const KArgs<float> &A, hipStream_t s, LaunchCfg cfg) {
+  return launch_t<float>(dim, p, form, A, s, cfg);
 }
 
 }  // namespace sbp

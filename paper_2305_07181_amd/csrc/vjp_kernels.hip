@@ -60,11 +60,14 @@ __device__ __forceinline__ void dWdU_apply(const double *u, const double *y, con
 // forward kernel.
 template <int P> struct VTileV3 { static constexpr int EB = P == 1 ? 21 : (P == 2 ? 10 : 4); };
 
-// two waves per SIMD (register cap 256) except at p = 1, where the cap spills
-// (measured on MI355X, 196608 tetrahedra: with the cap p = 3 takes 5.04 instead
-// of 5.77 ms, p = 1 0.87 instead of 0.60 ms)
-template <int P>
-__global__ __launch_bounds__(kT, P == 1 ? 1 : 2) void k_vjp3v(KArgs<double> A) {
+// W: waves per SIMD the register budget allows (1: up to 512 registers,
+// 2: 256).  The built-in choice is W = 2 except at p = 1, where the cap
+// spills (measured on MI355X, 196608 tetrahedra: with the cap p = 3 takes
+// 5.04 instead of 5.77 ms, p = 1 0.87 instead of 0.60 ms).
+template <int P> constexpr int vjp3_waves() { return P == 1 ? 1 : 2; }
+
+template <int P, int W>
+__global__ __launch_bounds__(kT, W) void k_vjp3v(KArgs<double> A) {
   constexpr int D = 3, NC = 5, NFAC = 4;
   constexpr int NP = Shape<3, P>::NP, NF = Shape<3, P>::NF, NFN = NFAC * NF;
   constexpr int EB = VTileV3<P>::EB;
@@ -405,9 +408,10 @@ struct Vjp2 {
   }
 };
 
-// two waves per SIMD (measured on MI355X, 32768 triangles: p = 4 170 -> 136 us)
-template <int P>
-__global__ __launch_bounds__(kT, 2) void k_vjp2(KArgs<double> A) {
+// W as for k_vjp3v; built-in W = 2 (measured on MI355X, 32768 triangles:
+// p = 4 170 -> 136 us against W = 1)
+template <int P, int W>
+__global__ __launch_bounds__(kT, W) void k_vjp2(KArgs<double> A) {
   typedef Vjp2<P> K;
   __shared__ typename K::Lds lds;
   K::load_ops(A, lds);
@@ -447,27 +451,9 @@ __global__ __launch_bounds__(kT) void k_vjp2_batch(Batch2<double> Bt) {
   }
 }
 
-// Persistent grid of the 3D row-form kernel: as many workgroups as the
-// device keeps resident, at most one per tile.
-template <int P>
-int vjp3v_grid(int n_elem) {
-  static int cap = 0;
-  if (cap == 0) {
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_vjp3v<P>, kT, 0) != hipSuccess || cus <= 0 || per <= 0)
-      cap = 1024;
-    else
-      cap = cus * per;
-  }
-  const int eb = VTileV3<P>::EB;
-  return std::min((n_elem + eb - 1) / eb, cap);
-}
-
 }  // namespace
 
-hipError_t launch_vjp2_batch(const KArgs<double> *const cls[4], hipStream_t s) {
+hipError_t launch_vjp2_batch(const KArgs<double> *const cls[4], hipStream_t s, int grid) {
   Batch2<double> Bt{};
   Bt.g0[0] = 0;
   const int eb[4] = {VTileV2<1>::EB, VTileV2<2>::EB, VTileV2<3>::EB, VTileV2<4>::EB};
@@ -477,35 +463,53 @@ hipError_t launch_vjp2_batch(const KArgs<double> *const cls[4], hipStream_t s) {
     Bt.g0[q + 1] = Bt.g0[q] + (ne + eb[q] - 1) / eb[q];
   }
   if (Bt.g0[4] == 0) return hipSuccess;
-  const dim3 grid(std::min(Bt.g0[4], 2048));
-  hipLaunchKernelGGL(k_vjp2_batch, grid, dim3(kT), 0, s, Bt);
+  const int nb = launch_grid(reinterpret_cast<const void *>(&k_vjp2_batch), Bt.g0[4], grid);
+  hipLaunchKernelGGL(k_vjp2_batch, dim3(nb), dim3(kT), 0, s, Bt);
   return hipGetLastError();
 }
 
-hipError_t launch_vjp(int dim, int p, const KArgs<double> &A, hipStream_t s) {
-  dim3 block(kT);
+int vjp_variants(int dim, int p) {
+  (void)dim;
+  (void)p;
+  return 2;
+}
+
+namespace {
+
+// kernel of a VJP slot: variant 0 the built-in register budget, 1 the other
+const void *vjp_kernel(int dim, int p, int variant, int &eb) {
+#define SBP_V2(PP)                                                                        \
+  if (dim == 2 && p == PP) {                                                              \
+    eb = VTileV2<PP>::EB;                                                                 \
+    return variant == 1 ? reinterpret_cast<const void *>(&k_vjp2<PP, 1>)                 \
+                        : reinterpret_cast<const void *>(&k_vjp2<PP, 2>);                 \
+  }
+  SBP_V2(1) SBP_V2(2) SBP_V2(3) SBP_V2(4)
+#undef SBP_V2
+#define SBP_V3(PP)                                                                        \
+  if (dim == 3 && p == PP) {                                                              \
+    eb = VTileV3<PP>::EB;                                                                 \
+    return (vjp3_waves<PP>() == 2) != (variant == 1)                                      \
+               ? reinterpret_cast<const void *>(&k_vjp3v<PP, 2>)                          \
+               : reinterpret_cast<const void *>(&k_vjp3v<PP, 1>);                         \
+  }
+  SBP_V3(1) SBP_V3(2) SBP_V3(3)
+#undef SBP_V3
+  eb = 0;
+  return nullptr;
+}
+
+}  // namespace
+
+hipError_t launch_vjp(int dim, int p, const KArgs<double> &A, hipStream_t s, LaunchCfg cfg) {
   if (A.n_elem <= 0) return hipSuccess;
-  if (dim == 2) {
-    // persistent workgroups: at most about as many as 256 CUs keep resident
-    const int eb = p == 1 ? VTileV2<1>::EB : (p == 2 ? VTileV2<2>::EB : (p == 3 ? VTileV2<3>::EB : VTileV2<4>::EB));
-    const dim3 grid(std::min((A.n_elem + eb - 1) / eb, 2048));
-    switch (p) {
-      case 1: hipLaunchKernelGGL(k_vjp2<1>, grid, block, 0, s, A); break;
-      case 2: hipLaunchKernelGGL(k_vjp2<2>, grid, block, 0, s, A); break;
-      case 3: hipLaunchKernelGGL(k_vjp2<3>, grid, block, 0, s, A); break;
-      case 4: hipLaunchKernelGGL(k_vjp2<4>, grid, block, 0, s, A); break;
-      default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-  }
-  if (dim != 3) return hipErrorInvalidValue;
-  switch (p) {
-    case 1: hipLaunchKernelGGL(k_vjp3v<1>, dim3(vjp3v_grid<1>(A.n_elem)), block, 0, s, A); break;
-    case 2: hipLaunchKernelGGL(k_vjp3v<2>, dim3(vjp3v_grid<2>(A.n_elem)), block, 0, s, A); break;
-    case 3: hipLaunchKernelGGL(k_vjp3v<3>, dim3(vjp3v_grid<3>(A.n_elem)), block, 0, s, A); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  int eb = 0;
+  const void *fn = vjp_kernel(dim, p, cfg.variant, eb);
+  if (!fn) return hipErrorInvalidValue;
+  const int nb = launch_grid(fn, (A.n_elem + eb - 1) / eb, cfg.grid);
+  KArgs<double> a = A;
+  void *args[] = {&a};
+  return hipLaunchKernel(fn, dim3(nb), dim3(kT), args, 0, s);
 }
 
 }  // namespace sbp

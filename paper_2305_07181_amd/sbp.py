@@ -23,7 +23,8 @@ FP64, FP32 = 0, 1
 
 SYMBOLS = ["sbp_setup_mesh", "sbp_mesh_info", "sbp_residual", "sbp_residual_vjp", "sbp_rrk_step",
            "sbp_diagnostics", "sbp_check_device", "sbp_set_time", "sbp_destroy_mesh",
-           "sbp_last_error", "sbp_reference_operator", "sbp_use_graphs"]
+           "sbp_last_error", "sbp_reference_operator", "sbp_use_graphs", "sbp_autotune",
+           "sbp_get_launch_shape", "sbp_set_launch_shape"]
 
 
 class SbpError(RuntimeError):
@@ -59,6 +60,15 @@ class RRKReport(C.Structure):
                 ("entropy_rate_e", C.c_double), ("newton_iters", C.c_int32)]
 
 
+class TuneSlot(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("p", C.c_int32), ("variant", C.c_int32), ("grid", C.c_int32),
+                ("n_candidates", C.c_int32), ("ms_builtin", C.c_double), ("ms_best", C.c_double)]
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("n_slots", C.c_int32), ("slot", TuneSlot * 8)]
+
+
 def load_library(path: str = _LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} not found: build it with `python -m paper_2305_07181_amd.build`")
@@ -73,6 +83,9 @@ def load_library(path: str = _LIB_PATH):
     lib.sbp_check_device.argtypes = [P, P]
     lib.sbp_set_time.argtypes = [P, C.c_double]
     lib.sbp_use_graphs.argtypes = [P, C.c_int]
+    lib.sbp_autotune.argtypes = [P, P, P, C.POINTER(TuneReport), P]
+    lib.sbp_get_launch_shape.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.sbp_set_launch_shape.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
     lib.sbp_destroy_mesh.argtypes = [P]
     lib.sbp_last_error.restype = C.c_char_p
     lib.sbp_reference_operator.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -232,6 +245,29 @@ class Mesh:
         _check(_lib.sbp_rrk_step(self._h, _ptr(u), float(dt), float(cfl), C.byref(rep), _stream_ptr(stream)))
         return dict(gamma=rep.gamma_n, dt=rep.dt, t=rep.t, entropy_before=rep.entropy_before,
                     entropy_after=rep.entropy_after, e=rep.entropy_rate_e, iters=rep.newton_iters)
+
+    def autotune(self, u, lam=None, stream=None):
+        """sbp_autotune: pick the launch shape of every kernel slot by timing
+        (the VJP slots too when a cotangent is given).  Returns one dict per
+        slot: kind ("residual"/"vjp"), p (0: batched launch), variant, grid,
+        n_candidates, ms_builtin, ms_best."""
+        self._check_state(u)
+        rep = TuneReport()
+        _check(_lib.sbp_autotune(self._h, _ptr(u), _ptr(lam) if lam is not None else None, C.byref(rep),
+                                 _stream_ptr(stream)))
+        return [dict(kind=("residual", "vjp")[t.kind], p=t.p, variant=t.variant, grid=t.grid,
+                     n_candidates=t.n_candidates, ms_builtin=t.ms_builtin, ms_best=t.ms_best)
+                for t in rep.slot[:rep.n_slots]]
+
+    def launch_shape(self, kind="residual", p=0):
+        """(variant, grid) of one kernel slot (sbp_get_launch_shape)."""
+        v, g = C.c_int32(), C.c_int32()
+        _check(_lib.sbp_get_launch_shape(self._h, ("residual", "vjp").index(kind), int(p), C.byref(v), C.byref(g)))
+        return v.value, g.value
+
+    def set_launch_shape(self, kind="residual", p=0, variant=0, grid=1):
+        """Pin the launch shape of one kernel slot (sbp_set_launch_shape)."""
+        _check(_lib.sbp_set_launch_shape(self._h, ("residual", "vjp").index(kind), int(p), int(variant), int(grid)))
 
     def use_graphs(self, enable=True):
         _check(_lib.sbp_use_graphs(self._h, int(bool(enable))))
