@@ -49,6 +49,8 @@ def _args():
     ap.add_argument("--no-extras", action="store_true",
                     help="report only the headline step (used under a profiler)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the built-in launch shapes (skip sbp_autotune during setup)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -99,6 +101,14 @@ def _state_from_mesh(mesh, kind):
     return torch.from_numpy(u).cuda()
 
 
+def _tune(args, mesh, u, lam=None):
+    """sbp_autotune during setup (untimed): the launch shapes it keeps."""
+    if args.no_tune:
+        return []
+    return [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in t.items()}
+            for t in mesh.autotune(u, lam)]
+
+
 def _time_calls(fn, reps, warm):
     import torch
     for _ in range(warm):
@@ -129,6 +139,7 @@ def ns_rows(args):
     for name, prec in (("fp64", sbp.FP64), ("fp32", sbp.FP32)):
         m = sbp.Mesh(desc, 3, precision=prec, **kw)
         u = _state_from_mesh(m, "tgv")
+        row[f"tuned_{name}"] = _tune(args, m, u)
         r = torch.empty(u.shape, dtype=torch.float64 if prec == sbp.FP64 else torch.float32, device="cuda")
         med, _ = _time_calls(lambda: m.residual(u, r), 5, 2)
         row[f"residual_{name}_ms"] = med * 1e3
@@ -179,6 +190,7 @@ def batch_rows(args):
                       generator=torch.Generator(device="cuda").manual_seed(2000))
     r = torch.empty_like(ud)
     ubar = torch.empty_like(ud)
+    tuned = _tune(args, mesh, ud, lam)
     fmed, _ = _time_calls(lambda: mesh.residual(ud, r), max(5, args.steps // 2), 2)
     bmed, _ = _time_calls(lambda: mesh.vjp(ud, lam, ubar), max(5, args.steps // 2), 2)
     mesh.check_device()
@@ -187,7 +199,7 @@ def batch_rows(args):
     return dict(n_problems=48, n_elem=int(off[-1]), n_dof_nodes=ndof,
                 degrees={str(q): int(sum(1 for s in specs if s["p"] == q)) for q in (1, 2, 3, 4)},
                 forward_ms=fmed * 1e3, vjp_ms=bmed * 1e3, forward_elem_dof_per_s=ndof / fmed,
-                vjp_elem_dof_per_s=ndof / bmed, vjp_over_forward=bmed / fmed)
+                vjp_elem_dof_per_s=ndof / bmed, vjp_over_forward=bmed / fmed, tuned=tuned)
 
 
 def cpu_baseline(desc, ps, budget_s=20.0):
@@ -250,11 +262,14 @@ def main():
     ps = (1, 2, 3, 4)
     desc = wl.vortex2d_mesh(128, warp=0.05)
     ne = len(desc["elem_vert"])
-    meshes, states, outs = {}, {}, {}
+    meshes, states, outs, lams, tuned = {}, {}, {}, {}, {}
     for p in ps:
         meshes[p] = sbp.Mesh(desc, p)
         states[p] = _state_from_mesh(meshes[p], "vortex")
         outs[p] = torch.empty_like(states[p])
+        lams[p] = torch.randn(states[p].shape, dtype=torch.float64, device="cuda",
+                              generator=torch.Generator(device="cuda").manual_seed(2000 + p))
+        tuned[p] = _tune(args, meshes[p], states[p], lams[p])
     n_p = {p: int(meshes[p].elem_np[0]) for p in ps}
     dofs = sum(ne * n_p[p] for p in ps)
 
@@ -309,7 +324,8 @@ def main():
                                     "(P2 warp 0.05 L sin sin), isentropic vortex, entropy-split residual "
                                     "with EC SATs, FP64, one residual for each p = 1,2,3,4 per step",
                            n_elem=ne, degrees=list(ps), n_p=n_p,
-                           kernel_ms={p: kern[p] * 1e3 for p in ps}),
+                           kernel_ms={p: kern[p] * 1e3 for p in ps},
+                           launch_shapes={p: tuned[p] for p in ps}),
                roofline=roof)
     if not args.no_extras:
         extras = {}
@@ -318,6 +334,8 @@ def main():
             for name, kw in (("fp64_split", dict()), ("fp32_split", dict(precision=sbp.FP32)),
                              ("fp64_hadamard", dict(form=sbp.FORM_HADAMARD))):
                 msh = meshes[p] if name == "fp64_split" else sbp.Mesh(desc, p, **kw)
+                if msh is not meshes[p]:
+                    _tune(args, msh, states[p])
                 r = torch.empty(states[p].shape, dtype=torch.float32 if "fp32" in name else torch.float64,
                                 device="cuda")
                 med, _ = _time_calls(lambda: msh.residual(states[p], r), max(5, args.steps // 2), 2)
@@ -325,8 +343,7 @@ def main():
                 if msh is not meshes[p]:
                     msh.close()
             row["hadamard_over_split"] = row["fp64_hadamard"]["ms"] / row["fp64_split"]["ms"]
-            lam = torch.randn(states[p].shape, dtype=torch.float64, device="cuda",
-                              generator=torch.Generator(device="cuda").manual_seed(2000 + p))
+            lam = lams[p]
             ub = torch.empty_like(states[p])
             med, _ = _time_calls(lambda: meshes[p].vjp(states[p], lam, ub), max(5, args.steps // 2), 2)
             row["fp64_vjp"] = dict(ms=med * 1e3, elem_dof_per_s=ne * n_p[p] / med)
@@ -340,9 +357,14 @@ def main():
             m64 = sbp.Mesh(desc3, p, dissipation=True)
             u3 = _state_from_mesh(m64, "tgv")
             np3 = int(m64.elem_np[0])
+            lam3 = torch.randn(u3.shape, dtype=torch.float64, device="cuda",
+                               generator=torch.Generator(device="cuda").manual_seed(2100 + p))
+            row["tuned_fp64"] = _tune(args, m64, u3, lam3)
             for name, kw in (("fp64_split", dict()), ("fp32_split", dict(precision=sbp.FP32)),
                              ("fp64_hadamard", dict(form=sbp.FORM_HADAMARD))):
                 msh = m64 if name == "fp64_split" else sbp.Mesh(desc3, p, dissipation=True, **kw)
+                if msh is not m64:
+                    row[f"tuned_{name}"] = _tune(args, msh, u3)
                 r = torch.empty(u3.shape, dtype=torch.float32 if "fp32" in name else torch.float64, device="cuda")
                 med, _ = _time_calls(lambda: msh.residual(u3, r), 5, 2)
                 fl3, by3 = algorithmic_work(3, np3, {2: 6, 3: 12}[p], 4 if "fp32" in name else 8)
@@ -354,8 +376,6 @@ def main():
                     msh.close()
             row["hadamard_over_split"] = row["fp64_hadamard"]["ms"] / row["fp64_split"]["ms"]
             row["fp32_speedup"] = row["fp64_split"]["ms"] / row["fp32_split"]["ms"]
-            lam3 = torch.randn(u3.shape, dtype=torch.float64, device="cuda",
-                               generator=torch.Generator(device="cuda").manual_seed(2100 + p))
             ub3 = torch.empty_like(u3)
             med, _ = _time_calls(lambda: m64.vjp(u3, lam3, ub3), 5, 2)
             row["fp64_vjp"] = dict(ms=med * 1e3, elem_dof_per_s=ne3 * np3 / med)

@@ -163,9 +163,9 @@ typedef struct {
 /* Autotuner (not in the paper): for every kernel slot of the handle (each
  * degree class of sbp_residual, or its single batched launch on a 2D mesh
  * with several degrees; likewise of sbp_residual_vjp when lambda_dev != NULL)
- * time each launch shape -- kernel variant (3D entropy split: skew operators
- * in LDS or read through the caches; VJP: register budget of one or two
- * waves per SIMD) times persistent grid (1x or 2x the resident workgroups, or
+ * time each launch shape -- kernel variant (2D entropy split: one or two node
+ * rows per lane; 3D entropy split: skew operators in LDS or read through the
+ * caches; VJP: register budget of one or two waves per SIMD) times persistent grid (1x or 2x the resident workgroups, or
  * one workgroup per tile) -- on the state u_dev and keep the fastest for
  * later calls.  Results of all shapes agree up to the summation order of the
  * FP64 entropy rate.  Choices are remembered for the process per workload
@@ -179,8 +179,8 @@ int sbp_autotune(sbp_mesh *mesh, const void *u_dev, const void *lambda_dev, sbp_
 
 /* Read or pin the launch shape of one kernel slot: kind 0 residual, 1 VJP;
  * p the degree class, or 0 for the batched launch of a 2D mesh with several
- * degrees; variant < the slot's variant count (3D entropy split and VJP: 2,
- * otherwise 1); grid 0..64 as in sbp_tune_slot.  Not in the paper.
+ * degrees; variant < the slot's variant count (entropy split without the
+ * Navier-Stokes terms, and VJP: 2; otherwise 1); grid 0..64 as in sbp_tune_slot.  Not in the paper.
  * SBP_EINVAL for a slot the handle does not have or a value out of range. */
 int sbp_get_launch_shape(sbp_mesh *mesh, int32_t kind, int32_t p, int32_t *variant, int32_t *grid);
 int sbp_set_launch_shape(sbp_mesh *mesh, int32_t kind, int32_t p, int32_t variant, int32_t grid);

@@ -28,8 +28,9 @@ hipError_t launch_residual(int dim, int p, int form, const KArgs<double> &A, hip
 hipError_t launch_residual(int dim, int p, int form, const KArgs<float> &A, hipStream_t s, LaunchCfg cfg = {});
 // form_eff: 0 entropy split, 1 Hadamard, 2 entropy split with Navier-Stokes terms
 int residual_blocks(int dim, int p, int precision, int form_eff, int n_elem, LaunchCfg cfg = {});
-// kernel variants of a slot: 3D entropy split (Euler): skew operators in LDS
-// or read through the caches; otherwise one
+// kernel variants of a slot: 2D entropy split: one or two node rows per lane;
+// 3D entropy split (Euler): skew operators in LDS or read through the caches;
+// Hadamard and Navier-Stokes: one
 int residual_variants(int dim, int p, int precision, int form_eff);
 // 2D entropy split, every degree class in one persistent launch: cls[p-1] is
 // the class of degree p or null.  Workgroups of the launch (partial sums):

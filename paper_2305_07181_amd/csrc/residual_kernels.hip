@@ -648,21 +648,19 @@ __global__ __launch_bounds__(kThreads) void k_visc_q3(KArgs<T> A) {
 // (20 FMAs per pair).  On MI355X an FP64 MFMA has the throughput of the FP64
 // vector ALUs, and the contraction form of the same terms issues about five
 // times these flops (six column groups per direction for curved metrics,
-// 16-row padding), so the pair sums run on the vector ALUs: one lane per node
-// row, the skew operators in LDS, the tile's node values (f^(0), f^(1), w,
-// Lambda) in LDS rows of 16 values per node.
-template <int P, typename T> struct VTile2;
-template <typename T> struct VTile2<1, T> { static constexpr int EB = 42; };
-template <typename T> struct VTile2<2, T> { static constexpr int EB = 25; };
-template <typename T> struct VTile2<3, T> { static constexpr int EB = 14; };
-template <typename T> struct VTile2<4, T> { static constexpr int EB = 11; };
-
-template <int P, typename T>
+// 16-row padding), so the pair sums run on the vector ALUs: R node rows per
+// lane (rows k and k + n_p/2 for R = 2), the skew operators in LDS, the
+// tile's node values (f^(0), f^(1), w, Lambda) in LDS rows of 16 values per
+// node.  Every lane re-reads the 16 values of node j for each pair, so the
+// loop is bound by the LDS return bandwidth; with R = 2 each value read
+// feeds two rows (half the LDS bytes per FMA).
+template <int P, typename T, int R>
 struct Split2 {
   static constexpr int D = 2, NC = 4, NFAC = 3;
   static constexpr int NP = Shape<2, P>::NP, NF = Shape<2, P>::NF;
-  static constexpr int EB = VTile2<P, T>::EB;
-  static_assert(EB * NP <= kThreads, "one node per lane");
+  static_assert(NP % R == 0, "rows split evenly over the lanes of an element");
+  static constexpr int L = NP / R;            // lanes per element
+  static constexpr int EB = kThreads / L;     // elements per tile
   // node rows of 16 values; element blocks padded by 4 values so that the
   // rows of the elements sharing a wave fall in different LDS banks
   static constexpr int NDS = NP * 16 + 4;
@@ -671,102 +669,122 @@ struct Split2 {
     __align__(16) T nd[EB * NDS];  // per node: f0[4] f1[4] w[4] Lambda_00 _01 _10 _11
   };
 
-  __device__ static __forceinline__ void load_ops(const KArgs<T> &A, Lds &L) {
-    for (int x = threadIdx.x; x < 2 * NP * NP; x += kThreads) (&L.S[0][0][0])[x] = A.op.S[x];
+  __device__ static __forceinline__ void load_ops(const KArgs<T> &A, Lds &L_) {
+    for (int x = threadIdx.x; x < 2 * NP * NP; x += kThreads) (&L_.S[0][0][0])[x] = A.op.S[x];
   }
 
   // Residual of the elements [tile*EB, tile*EB + EB); ent accumulates w^T H r.
   // Call with the operators loaded (load_ops, then a barrier).
-  __device__ static __forceinline__ void tile(const KArgs<T> &A, Lds &L, int tl, double &ent) {
+  __device__ static __forceinline__ void tile(const KArgs<T> &A, Lds &L_, int tl, double &ent) {
     const int tid = threadIdx.x;
     const int e0 = tl * EB;
     const int ne = min(EB, A.n_elem - e0);
-    const bool act = tid < ne * NP;
-    const int e = tid / NP, i = tid % NP;
+    const int e = tid / L, k = tid % L;
+    const bool act = e < ne;
     const T cb = A.G.cb;
     const T hv = (T)0.5 * (cb - (T)1), he = (T)0.5 * (cb + (T)1);
-    Node<D, T> n;
-    T lam[4], J = (T)1, f0[NC], f1[NC];
+    Node<D, T> n[R];
+    T lam[R][4];
     if (act) {
       const double *g = A.geo + (size_t)(e0 + e) * 12;
-      T F[2][2] = {{0, 0}, {0, 0}};
 #pragma unroll
-      for (int a = 0; a < 6; ++a) {
-        const T d0 = A.op.dN[(0 * 6 + a) * NP + i], d1 = A.op.dN[(1 * 6 + a) * NP + i];
-        const T gx = (T)g[2 * a], gy = (T)g[2 * a + 1];
-        F[0][0] += d0 * gx;
-        F[0][1] += d1 * gx;
-        F[1][0] += d0 * gy;
-        F[1][1] += d1 * gy;
+      for (int q = 0; q < R; ++q) {
+        const int i = k + q * L;
+        T F[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+          const T d0 = A.op.dN[(0 * 6 + a) * NP + i], d1 = A.op.dN[(1 * 6 + a) * NP + i];
+          const T gx = (T)g[2 * a], gy = (T)g[2 * a + 1];
+          F[0][0] += d0 * gx;
+          F[0][1] += d1 * gx;
+          F[1][0] += d0 * gy;
+          F[1][1] += d1 * gy;
+        }
+        lam[q][0] = F[1][1];   // Lambda_00 = J dxi_0/dx_0
+        lam[q][1] = -F[1][0];  // Lambda_01
+        lam[q][2] = -F[0][1];  // Lambda_10
+        lam[q][3] = F[0][0];   // Lambda_11
+        const int uo = A.uoff[e0 + e];
+        T uu[NC], f0[NC], f1[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) uu[c] = (T)A.u[uo + c * NP + i];
+        node_from_u<D, T>(uu, A.G, n[q]);
+        if (!n[q].ok) atomicOr(A.err, 1);
+        flux_i<D, T>(n[q], uu[NC - 1], 0, f0);
+        flux_i<D, T>(n[q], uu[NC - 1], 1, f1);
+        T *v = L_.nd + e * NDS + i * 16;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          v[c] = f0[c];
+          v[4 + c] = f1[c];
+          v[8 + c] = n[q].w[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[12 + c] = lam[q][c];
       }
-      lam[0] = F[1][1];   // Lambda_00 = J dxi_0/dx_0
-      lam[1] = -F[1][0];  // Lambda_01
-      lam[2] = -F[0][1];  // Lambda_10
-      lam[3] = F[0][0];   // Lambda_11
-      J = F[0][0] * F[1][1] - F[0][1] * F[1][0];
-      const int uo = A.uoff[e0 + e];
-      T uu[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) uu[c] = (T)A.u[uo + c * NP + i];
-      node_from_u<D, T>(uu, A.G, n);
-      if (!n.ok) atomicOr(A.err, 1);
-      flux_i<D, T>(n, uu[NC - 1], 0, f0);
-      flux_i<D, T>(n, uu[NC - 1], 1, f1);
-      T *v = L.nd + e * NDS + i * 16;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        v[c] = f0[c];
-        v[4 + c] = f1[c];
-        v[8 + c] = n.w[c];
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) v[12 + q] = lam[q];
     }
     __syncthreads();
     if (act) {
-      T V[NC], X0[NC], X1[NC];
+      T V[R][NC], X0[R][NC], X1[R][NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) V[c] = X0[c] = X1[c] = (T)0;
+      for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) V[q][c] = X0[q][c] = X1[q][c] = (T)0;
 #pragma unroll 1
       for (int j = 0; j < NP; ++j) {
-        const T s0 = L.S[0][i][j], s1 = L.S[1][i][j];
-        const T *v = L.nd + e * NDS + j * 16;
-        const T c0 = s0 * (lam[0] + v[12]) + s1 * (lam[1] + v[13]);
-        const T c1 = s0 * (lam[2] + v[14]) + s1 * (lam[3] + v[15]);
+        const T *v = L_.nd + e * NDS + j * 16;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          V[c] += c0 * v[c] + c1 * v[4 + c];
-          X0[c] += c0 * v[8 + c];
-          X1[c] += c1 * v[8 + c];
+        for (int q = 0; q < R; ++q) {
+          const int i = k + q * L;
+          const T s0 = L_.S[0][i][j], s1 = L_.S[1][i][j];
+          const T c0 = s0 * (lam[q][0] + v[12]) + s1 * (lam[q][1] + v[13]);
+          const T c1 = s0 * (lam[q][2] + v[14]) + s1 * (lam[q][3] + v[15]);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            V[q][c] += c0 * v[c] + c1 * v[4 + c];
+            X0[q][c] += c0 * v[8 + c];
+            X1[q][c] += c1 * v[8 + c];
+          }
         }
       }
-      const T E0 = A.op.E[i], E1 = A.op.E[NP + i];
-      T avec[D];
-      avec[0] = lam[0] * E0 + lam[1] * E1;
-      avec[1] = lam[2] * E0 + lam[3] * E1;
-      const T H = J * (T)A.op.h[i];
-      const T iH = (T)1 / H;
-      T r[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) r[c] = iH * (hv * V[c] + he * (avec[0] * f0[c] + avec[1] * f1[c]));
+      for (int q = 0; q < R; ++q) {
+        const int i = k + q * L;
+        const T *v = L_.nd + e * NDS + i * 16;
+        const T E0 = A.op.E[i], E1 = A.op.E[NP + i];
+        T avec[D];
+        avec[0] = lam[q][0] * E0 + lam[q][1] * E1;
+        avec[1] = lam[q][2] * E0 + lam[q][3] * E1;
+        // J = F_00 F_11 - F_01 F_10 in terms of the cofactors
+        const T J = lam[q][3] * lam[q][0] - lam[q][2] * lam[q][1];
+        const T H = J * (T)A.op.h[i];
+        const T iH = (T)1 / H;
+        T r[NC];
 #pragma unroll
-      for (int dir = 0; dir < D; ++dir) {
-        T gg[NC], tt[NC];
+        for (int c = 0; c < NC; ++c) r[c] = iH * (hv * V[q][c] + he * (avec[0] * v[c] + avec[1] * v[4 + c]));
 #pragma unroll
-        for (int c = 0; c < NC; ++c) gg[c] = (T)0.5 * iH * ((dir == 0 ? X0[c] : X1[c]) + avec[dir] * n.w[c]);
-        jvp_flux<D, T>(n, A.G, dir, gg, tt);
+        for (int dir = 0; dir < D; ++dir) {
+          T gg[NC], tt[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) r[c] -= cb * tt[c];
+          for (int c = 0; c < NC; ++c)
+            gg[c] = (T)0.5 * iH * ((dir == 0 ? X0[q][c] : X1[q][c]) + avec[dir] * n[q].w[c]);
+          jvp_flux<D, T>(n[q], A.G, dir, gg, tt);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) r[c] -= cb * tt[c];
+        }
+        finish_node<D, NP, NF, T>(A, e0 + e, i, n[q], H, avec, r, ent);
       }
-      finish_node<D, NP, NF, T>(A, e0 + e, i, n, H, avec, r, ent);
     }
     __syncthreads();
   }
 };
 
-template <int P, typename T>
-__global__ __launch_bounds__(kThreads, P == 1 ? 2 : 3) void k_split2(KArgs<T> A) {
-  typedef Split2<P, T> K;
+// Rows per lane of the built-in 2D split variant; the autotuner may pick the other.
+template <int P, typename T> constexpr int split2_rows() { return 2; }
+
+template <int P, typename T, int R>
+__global__ __launch_bounds__(kThreads, R == 2 ? 2 : (P == 1 ? 2 : 3)) void k_split2(KArgs<T> A) {
+  typedef Split2<P, T, R> K;
   __shared__ typename K::Lds lds;
   K::load_ops(A, lds);
   __syncthreads();
@@ -781,10 +799,10 @@ __global__ __launch_bounds__(kThreads, P == 1 ? 2 : 3) void k_split2(KArgs<T> A)
 // restages the skew operators when its tile changes degree.
 template <typename T>
 constexpr size_t split2_lds_max() {
-  size_t m = sizeof(typename Split2<1, T>::Lds);
-  m = m > sizeof(typename Split2<2, T>::Lds) ? m : sizeof(typename Split2<2, T>::Lds);
-  m = m > sizeof(typename Split2<3, T>::Lds) ? m : sizeof(typename Split2<3, T>::Lds);
-  m = m > sizeof(typename Split2<4, T>::Lds) ? m : sizeof(typename Split2<4, T>::Lds);
+  size_t m = sizeof(typename Split2<1, T, split2_rows<1, T>()>::Lds);
+  m = m > sizeof(typename Split2<2, T, split2_rows<2, T>()>::Lds) ? m : sizeof(typename Split2<2, T, split2_rows<2, T>()>::Lds);
+  m = m > sizeof(typename Split2<3, T, split2_rows<3, T>()>::Lds) ? m : sizeof(typename Split2<3, T, split2_rows<3, T>()>::Lds);
+  m = m > sizeof(typename Split2<4, T, split2_rows<4, T>()>::Lds) ? m : sizeof(typename Split2<4, T, split2_rows<4, T>()>::Lds);
   return m;
 }
 
@@ -797,17 +815,17 @@ __global__ __launch_bounds__(kThreads, 2) void k_split2_batch(Batch2<T> Bt) {
     const int q = g < Bt.g0[1] ? 0 : (g < Bt.g0[2] ? 1 : (g < Bt.g0[3] ? 2 : 3));
     if (q != cur) {
       __syncthreads();
-      if (q == 0) Split2<1, T>::load_ops(Bt.c[0], *(typename Split2<1, T>::Lds *)raw);
-      else if (q == 1) Split2<2, T>::load_ops(Bt.c[1], *(typename Split2<2, T>::Lds *)raw);
-      else if (q == 2) Split2<3, T>::load_ops(Bt.c[2], *(typename Split2<3, T>::Lds *)raw);
-      else Split2<4, T>::load_ops(Bt.c[3], *(typename Split2<4, T>::Lds *)raw);
+      if (q == 0) Split2<1, T, split2_rows<1, T>()>::load_ops(Bt.c[0], *(typename Split2<1, T, split2_rows<1, T>()>::Lds *)raw);
+      else if (q == 1) Split2<2, T, split2_rows<2, T>()>::load_ops(Bt.c[1], *(typename Split2<2, T, split2_rows<2, T>()>::Lds *)raw);
+      else if (q == 2) Split2<3, T, split2_rows<3, T>()>::load_ops(Bt.c[2], *(typename Split2<3, T, split2_rows<3, T>()>::Lds *)raw);
+      else Split2<4, T, split2_rows<4, T>()>::load_ops(Bt.c[3], *(typename Split2<4, T, split2_rows<4, T>()>::Lds *)raw);
       __syncthreads();
       cur = q;
     }
-    if (q == 0) Split2<1, T>::tile(Bt.c[0], *(typename Split2<1, T>::Lds *)raw, g, ent);
-    else if (q == 1) Split2<2, T>::tile(Bt.c[1], *(typename Split2<2, T>::Lds *)raw, g - Bt.g0[1], ent);
-    else if (q == 2) Split2<3, T>::tile(Bt.c[2], *(typename Split2<3, T>::Lds *)raw, g - Bt.g0[2], ent);
-    else Split2<4, T>::tile(Bt.c[3], *(typename Split2<4, T>::Lds *)raw, g - Bt.g0[3], ent);
+    if (q == 0) Split2<1, T, split2_rows<1, T>()>::tile(Bt.c[0], *(typename Split2<1, T, split2_rows<1, T>()>::Lds *)raw, g, ent);
+    else if (q == 1) Split2<2, T, split2_rows<2, T>()>::tile(Bt.c[1], *(typename Split2<2, T, split2_rows<2, T>()>::Lds *)raw, g - Bt.g0[1], ent);
+    else if (q == 2) Split2<3, T, split2_rows<3, T>()>::tile(Bt.c[2], *(typename Split2<3, T, split2_rows<3, T>()>::Lds *)raw, g - Bt.g0[2], ent);
+    else Split2<4, T, split2_rows<4, T>()>::tile(Bt.c[3], *(typename Split2<4, T, split2_rows<4, T>()>::Lds *)raw, g - Bt.g0[3], ent);
   }
   block_sum_store(ent, Bt.ent_part);
 }
@@ -998,7 +1016,11 @@ static KernelRef residual_kernel(int dim, int p, int form_eff, int variant) {
 #define SBP_K2(PP)                                                                              \
   if (dim == 2 && p == PP) {                                                                    \
     if (form_eff == 1) return {reinterpret_cast<const void *>(&k_hadamard<2, PP, T>), HadTile<2, PP, T>::EB}; \
-    if (form_eff == 0) return {reinterpret_cast<const void *>(&k_split2<PP, T>), VTile2<PP, T>::EB};         \
+    if (form_eff == 0) {                                                                        \
+      if ((split2_rows<PP, T>() == 2) != (variant == 1))                                        \
+        return {reinterpret_cast<const void *>(&k_split2<PP, T, 2>), Split2<PP, T, 2>::EB};     \
+      return {reinterpret_cast<const void *>(&k_split2<PP, T, 1>), Split2<PP, T, 1>::EB};       \
+    }                                                                                           \
     return {nullptr, 0};                                                                        \
   }
   SBP_K2(1) SBP_K2(2) SBP_K2(3) SBP_K2(4)
@@ -1044,7 +1066,7 @@ int launch_grid(const void *kernel, int ntiles, int grid) {
 int residual_variants(int dim, int p, int precision, int form_eff) {
   (void)p;
   (void)precision;
-  return dim == 3 && form_eff == 0 ? 2 : 1;
+  return form_eff == 0 ? 2 : 1;
 }
 
 int residual_blocks(int dim, int p, int precision, int form_eff, int n_elem, LaunchCfg cfg) {
@@ -1085,10 +1107,10 @@ hipError_t launch_visc_q(int dim, int p, const KArgs<float> &A, hipStream_t s) {
 template <typename T>
 static int split2_ew(int p) {
   switch (p) {
-    case 1: return Split2<1, T>::EB;
-    case 2: return Split2<2, T>::EB;
-    case 3: return Split2<3, T>::EB;
-    default: return Split2<4, T>::EB;
+    case 1: return Split2<1, T, split2_rows<1, T>()>::EB;
+    case 2: return Split2<2, T, split2_rows<2, T>()>::EB;
+    case 3: return Split2<3, T, split2_rows<3, T>()>::EB;
+    default: return Split2<4, T, split2_rows<4, T>()>::EB;
   }
 }
 

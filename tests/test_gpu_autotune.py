@@ -43,17 +43,23 @@ def test_every_residual_launch_shape(dim, p, n, prec):
     err = rel_err_per_component(r0[els], ro)
     say("   built-in shape vs oracle", err.max())
     assert (err <= (1e-12 if prec == 0 else 2e-4)).all(), err  # FP32: the stated error bound
-    nvar = 2 if dim == 3 else 1
+    nvar = 2  # 2D: one or two node rows per lane; 3D: skew operators in LDS or via the caches
     for v in range(nvar):
         for g in GRIDS:
             mesh.set_launch_shape("residual", p, v, g)
             assert mesh.launch_shape("residual", p) == (v, g)
             r, e = mesh.residual(ud, entropy_rate=True)
             mesh.check_device()
-            d = np.abs(r.double().cpu().numpy() - r0).max() / np.abs(r0).max()
+            r = r.double().cpu().numpy()
+            d = np.abs(r - r0).max() / np.abs(r0).max()
             de = abs(float(e.cpu()[0]) - e0) / abs(e0)
-            say(f"   variant {v} grid {g}: residual diff {d:.1e}, entropy-rate diff {de:.1e}")
-            assert d <= 1e-15, (v, g, d)
+            eo = rel_err_per_component(r[els], ro).max()
+            say(f"   variant {v} grid {g}: vs oracle {eo:.1e}, vs built-in {d:.1e}, entropy rate {de:.1e}")
+            # the grid only changes which workgroup runs a tile (bitwise equal
+            # residual); the variants are different kernels of the same sums
+            # (FMA contraction may differ): rounding-level agreement
+            assert d <= (0.0 if v == 0 else (1e-13 if prec == 0 else 1e-6)), (v, g, d)
+            assert eo <= (1e-12 if prec == 0 else 2e-4), (v, g, eo)
             assert de <= 1e-11, (v, g, de)
     with pytest.raises(sbp.SbpError):
         mesh.set_launch_shape("residual", p, nvar, 1)
