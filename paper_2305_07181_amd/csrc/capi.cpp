@@ -145,7 +145,8 @@ int upload(T *&dst, const std::vector<T> &src, hipStream_t s) {
   return SBP_OK;
 }
 
-// Padded, transposed operator tables of one class for precision T.
+// Operator tables of one class for precision T: skew parts S_l = Q_l - E_l/2,
+// H and E diagonals, and (2D) the quadratic-map basis derivatives at the nodes.
 template <typename T>
 void build_tables(const sbp::RefOp &op, int dim, std::vector<T> &blob, size_t off[11]) {
   const int NP = op.np;
@@ -158,16 +159,6 @@ void build_tables(const sbp::RefOp &op, int dim, std::vector<T> &blob, size_t of
     for (size_t k = 0; k < v.size(); ++k) blob[o + k] = (T)v[k];
     return o;
   };
-  off[1] = 0;
-  if (dim == 3) {
-    // viscous pre-pass: [D_1; D_2; D_3] (3NP x NP), stored transposed and zero padded
-    const int K2P = sbp::ru(NP, 4), M2P = sbp::ru(3 * NP, 16);
-    std::vector<double> A2(K2P * M2P, 0.0);
-    for (int l = 0; l < 3; ++l)
-      for (int m = 0; m < NP; ++m)
-        for (int j = 0; j < NP; ++j) A2[(size_t)j * M2P + l * NP + m] = Q(l, m, j) / op.h[m];  // D_l[m][j]
-    off[1] = push(A2);
-  }
   std::vector<double> S((size_t)dim * NP * NP);
   for (int l = 0; l < dim; ++l)
     for (int m = 0; m < NP; ++m)
@@ -194,7 +185,6 @@ void build_tables(const sbp::RefOp &op, int dim, std::vector<T> &blob, size_t of
 template <typename T>
 sbp::OpTables<T> tables_at(const T *base, const size_t off[11], int dim) {
   sbp::OpTables<T> t{};
-  t.Dt = dim == 3 ? base + off[1] : nullptr;
   t.S = base + off[4];
   t.h = base + off[5];
   t.E = base + off[6];

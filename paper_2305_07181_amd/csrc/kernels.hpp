@@ -25,8 +25,6 @@ template <> struct Shape<3, 3> { static constexpr int NP = 60, NF = 12; };
 // Device tables of one degree class (pointers into one device allocation).
 template <typename T>
 struct OpTables {
-  // 3D viscous pre-pass: Dt = [D_1; D_2; D_3]^T (K2P x M2P, k-major, zero padded)
-  const T *Dt;
   const T *S;   // skew parts S_xi_l = Q_xi_l - E_xi_l / 2, [dim][NP][NP]
   const T *h;   // [NP]
   const T *E;   // [dim][NP] diagonal of E_xi_l
@@ -67,9 +65,5 @@ struct Batch2 {
   int g0[5];
   double *ent_part;  // [gridDim.x] partial sums of w^T H r (may be null)
 };
-
-// Elements per workgroup for each kernel (LDS budget <= 160 KiB on gfx950).
-template <int DIM, int P, typename T, int FORM>
-struct Tile;
 
 }  // namespace sbp

@@ -35,74 +35,8 @@
 
 namespace sbp {
 
-template <> struct Tile<3, 1, double, 0> { static constexpr int EB = 16; };
-template <> struct Tile<3, 2, double, 0> { static constexpr int EB = 6; };
-template <> struct Tile<3, 3, double, 0> { static constexpr int EB = 3; };
-template <> struct Tile<3, 1, float, 0> { static constexpr int EB = 32; };
-template <> struct Tile<3, 2, float, 0> { static constexpr int EB = 16; };
-template <> struct Tile<3, 3, float, 0> { static constexpr int EB = 6; };
-// entropy split with Navier-Stokes terms (3D)
-template <> struct Tile<3, 1, double, 2> { static constexpr int EB = 16; };
-template <> struct Tile<3, 2, double, 2> { static constexpr int EB = 9; };
-template <> struct Tile<3, 3, double, 2> { static constexpr int EB = 3; };
-template <> struct Tile<3, 1, float, 2> { static constexpr int EB = 32; };
-template <> struct Tile<3, 2, float, 2> { static constexpr int EB = 16; };
-template <> struct Tile<3, 3, float, 2> { static constexpr int EB = 6; };
-// Hadamard form
-
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-
-// C[MP x NCP] = A[MP x KP] B[KP x NCP].  A^T in global memory (At[k*MP+m],
-// shared by all workgroups, L2 resident), B and C in LDS (row-major, leading
-// dimension NCP).  Output tiles are dealt round-robin to the waves; a wave
-// keeps all its accumulators in registers and interleaves their MFMAs in the
-// k loop.  Stores happen after a barrier, so C may alias B.
-template <typename T, int MP, int KP, int NCP>
-__device__ __forceinline__ void gemm_AtB(const T *__restrict__ At, const T *B, T *C) {
-  constexpr int MT = MP / 16, NT = NCP / 16, NTILE = MT * NT;
-  constexpr int TPW = (NTILE + kWaves - 1) / kWaves;
-  constexpr int KS = KP / 4;       // k steps
-  constexpr int KB = 8;            // k steps whose operands are loaded together
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int col = lane & 15, kr = lane >> 4;
-  typename MF<T>::v4 acc[TPW];
-#pragma unroll
-  for (int t = 0; t < TPW; ++t) acc[t] = typename MF<T>::v4{0, 0, 0, 0};
-  for (int k0 = 0; k0 < KS; k0 += KB) {
-    T a[KB][TPW], b[KB][TPW];
-#pragma unroll
-    for (int kk = 0; kk < KB; ++kk)
-#pragma unroll
-      for (int t = 0; t < TPW; ++t) {
-        const int tile = wave + t * kWaves;
-        const int k = 4 * (k0 + kk) + kr;
-        if (tile < NTILE && k0 + kk < KS) {
-          const int mt = tile % MT, nt = tile / MT;
-          a[kk][t] = At[k * MP + mt * 16 + col];
-          b[kk][t] = B[k * NCP + nt * 16 + col];
-        }
-      }
-#pragma unroll
-    for (int kk = 0; kk < KB; ++kk)
-#pragma unroll
-      for (int t = 0; t < TPW; ++t) {
-        const int tile = wave + t * kWaves;
-        if (tile < NTILE && k0 + kk < KS) acc[t] = MF<T>::mma(a[kk][t], b[kk][t], acc[t]);
-      }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    const int tile = wave + t * kWaves;
-    if (tile < NTILE) {
-      const int mt = tile % MT, nt = tile / MT;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) C[(mt * 16 + MF<T>::row(kr, i)) * NCP + nt * 16 + col] = acc[t][i];
-    }
-  }
-  __syncthreads();
-}
 
 __device__ __forceinline__ void block_sum_store(double v, double *out) {
   __shared__ double red[kWaves];
@@ -443,6 +377,17 @@ template <typename T> struct VTile3<1, T> { static constexpr int EB = 21; };
 template <typename T> struct VTile3<2, T> { static constexpr int EB = 10; };
 template <typename T> struct VTile3<3, T> { static constexpr int EB = 4; };
 
+// The 3D Euler split terms run in the row form.  At p = 3 in FP64 its three
+// 60 x 60 skew operators would take 86 KB of LDS (one wave per SIMD); there
+// the built-in choice reads them through the caches instead (measured on
+// MI355X: 2.82 ms against 2.97 ms for the contraction form on 196608
+// tetrahedra).  The autotuner may pick the other variant; the viscous
+// pre-pass uses the built-in choice.
+template <int P, typename T>
+constexpr bool skew_from_cache3() {
+  return P == 3 && sizeof(T) == 8;
+}
+
 template <int P, typename T, bool SG = false>
 __global__ __launch_bounds__(kThreads, 2) void k_split3v(KArgs<T> A) {
   constexpr int D = 3, NC = 5;
@@ -504,9 +449,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_split3v(KArgs<T> A) {
       for (int j = 0; j < NP; ++j) {
         T s0, s1, s2;
         if constexpr (SG) {
-          s0 = A.op.S[(0 * NP + i) * NP + j];
-          s1 = A.op.S[(1 * NP + i) * NP + j];
-          s2 = A.op.S[(2 * NP + i) * NP + j];
+          // S_l is stored exactly skew (S^T = -S bitwise): S_l[i][j] is read
+          // as -S_l[j][i], so consecutive rows i of a wave read consecutive
+          // addresses (a few cache lines per load instead of one per lane)
+          s0 = -A.op.S[(0 * NP + j) * NP + i];
+          s1 = -A.op.S[(1 * NP + j) * NP + i];
+          s2 = -A.op.S[(2 * NP + j) * NP + i];
         } else {
           s0 = Ss[0][i][j];
           s1 = Ss[1][i][j];
@@ -558,76 +506,103 @@ __global__ __launch_bounds__(kThreads, 2) void k_split3v(KArgs<T> A) {
 }
 
 // Viscous facet-flux pre-pass, 3D affine: q = B n . F^V(w, grad w) at the
-// facet nodes of every element (grad w from the derivative GEMM).
+// facet nodes of every element, in the row form of k_split3v: one lane per
+// facet node row i, G_l,i = sum_j S_l[i][j] w_j (15 FMAs per pair), then
+// D_xi_l w = h^-1 (G_l + E_l w / 2) and grad w = J^-1 Lambda D_xi w.  Only the
+// facet rows are formed; w of all nodes of the tile sits in LDS.
 template <int P, typename T>
 __global__ __launch_bounds__(kThreads) void k_visc_q3(KArgs<T> A) {
   constexpr int D = 3, NC = 5, NFAC = 4;
   constexpr int NP = Shape<3, P>::NP, NF = Shape<3, P>::NF, NFN = NFAC * NF;
-  constexpr int EB = Tile<3, P, T, 0>::EB;
-  constexpr int NCOL = EB * NC, NCP = ru(NCOL, 16);
-  constexpr int K2P = ru(NP, 4), M2P = ru(3 * NP, 16);
-  __shared__ T B2[K2P * NCP];
-  __shared__ T C2[M2P * NCP];
-  __shared__ T us[EB * NC * NP];
-  __shared__ T gs[EB * 10];
-  __shared__ T Es[3 * NP];
+  constexpr int EB = VTile3<P, T>::EB;
+  constexpr bool SG = skew_from_cache3<P, T>();
+  static_assert(EB * NP <= kThreads && EB * NFN <= kThreads, "one node per lane");
+  constexpr int NDW = NP * NC + 4;  // padded element blocks of w
+  __shared__ T Ss[SG ? 1 : 3][SG ? 1 : NP][SG ? 1 : NP];
+  __shared__ T wd[EB * NDW];
+  __shared__ T gs[EB][10];
   const int tid = threadIdx.x;
-  const int e0 = blockIdx.x * EB;
-  const int ne = min(EB, A.n_elem - e0);
-  for (int x = tid; x < EB * 10; x += kThreads) {
-    const int e = x / 10;
-    gs[x] = e < ne ? (T)A.geo[(size_t)(e0 + e) * 10 + x % 10] : (T)0;
-  }
-  for (int x = tid; x < 3 * NP; x += kThreads) Es[x] = A.op.E[x];
-  for (int x = tid; x < ne * NC * NP; x += kThreads) {
-    const int e = x / (NC * NP);
-    us[x] = (T)A.u[A.uoff[e0 + e] + x % (NC * NP)];
-  }
-  for (int x = tid; x < K2P * NCP; x += kThreads) B2[x] = (T)0;
-  __syncthreads();
-  for (int x = tid; x < ne * NP; x += kThreads) {
-    const int e = x / NP, j = x % NP;
-    T uu[NC];
+  if constexpr (!SG)
+    for (int x = tid; x < 3 * NP * NP; x += kThreads) (&Ss[0][0][0])[x] = A.op.S[x];
+  const int ntiles = (A.n_elem + EB - 1) / EB;
+  for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    const int e0 = tl * EB;
+    const int ne = min(EB, A.n_elem - e0);
+    __syncthreads();
+    for (int x = tid; x < ne * 10; x += kThreads) gs[x / 10][x % 10] = (T)A.geo[(size_t)(e0 + x / 10) * 10 + x % 10];
+    if (tid < ne * NP) {
+      const int e = tid / NP, j = tid % NP;
+      const int uo = A.uoff[e0 + e];
+      T uu[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + j];
-    Node<D, T> n;
-    node_from_u<D, T>(uu, A.G, n);
+      for (int c = 0; c < NC; ++c) uu[c] = (T)A.u[uo + c * NP + j];
+      Node<D, T> n;
+      node_from_u<D, T>(uu, A.G, n);
 #pragma unroll
-    for (int c = 0; c < NC; ++c) B2[j * NCP + e * NC + c] = n.w[c];
-  }
-  __syncthreads();
-  gemm_AtB<T, M2P, K2P, NCP>(A.op.Dt, B2, C2);
-  for (int x = tid; x < ne * NFN; x += kThreads) {
-    const int e = x / NFN, i = x % NFN;
-    T uu[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) uu[c] = us[(e * NC + c) * NP + i];
-    Node<D, T> n;
-    node_from_u<D, T>(uu, A.G, n);
-    const T *Lam = gs + e * 10;
-    const T iJ = (T)1 / Lam[9];
-    T gW[D][NC], FV[D][NC];
-#pragma unroll
-    for (int dir = 0; dir < D; ++dir)
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        T s = 0;
-#pragma unroll
-        for (int l = 0; l < D; ++l) s += Lam[dir * 3 + l] * C2[(l * NP + i) * NCP + e * NC + c];
-        gW[dir][c] = s * iJ;
-      }
-    viscous_flux<D, T>(n, A.G, A.V, gW, FV);
-    T avec[D];
-#pragma unroll
-    for (int dir = 0; dir < D; ++dir) {
-      T s = 0;
-#pragma unroll
-      for (int l = 0; l < D; ++l) s += Lam[dir * 3 + l] * Es[l * NP + i];
-      avec[dir] = s;
+      for (int c = 0; c < NC; ++c) wd[e * NDW + j * NC + c] = n.w[c];
     }
+    __syncthreads();
+    if (tid < ne * NFN) {
+      const int e = tid / NFN, i = tid % NFN;
+      T G[D][NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-      A.qout[((size_t)(e0 + e) * NFN + i) * NC + c] = avec[0] * FV[0][c] + avec[1] * FV[1][c] + avec[2] * FV[2][c];
+      for (int l = 0; l < D; ++l)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) G[l][c] = (T)0;
+#pragma unroll 2
+      for (int j = 0; j < NP; ++j) {
+        T s0, s1, s2;
+        if constexpr (SG) {
+          // S_l is stored exactly skew (S^T = -S bitwise): S_l[i][j] is read
+          // as -S_l[j][i], so consecutive rows i of a wave read consecutive
+          // addresses (a few cache lines per load instead of one per lane)
+          s0 = -A.op.S[(0 * NP + j) * NP + i];
+          s1 = -A.op.S[(1 * NP + j) * NP + i];
+          s2 = -A.op.S[(2 * NP + j) * NP + i];
+        } else {
+          s0 = Ss[0][i][j];
+          s1 = Ss[1][i][j];
+          s2 = Ss[2][i][j];
+        }
+        const T *w = wd + e * NDW + j * NC;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          G[0][c] += s0 * w[c];
+          G[1][c] += s1 * w[c];
+          G[2][c] += s2 * w[c];
+        }
+      }
+      const int uo = A.uoff[e0 + e];
+      T uu[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) uu[c] = (T)A.u[uo + c * NP + i];
+      Node<D, T> n;
+      node_from_u<D, T>(uu, A.G, n);
+      const T *Lam = gs[e];
+      const T iJ = (T)1 / Lam[9];
+      const T ih = (T)1 / (T)A.op.h[i];
+      T El[D];
+#pragma unroll
+      for (int l = 0; l < D; ++l) El[l] = A.op.E[l * NP + i];
+#pragma unroll
+      for (int l = 0; l < D; ++l)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) G[l][c] = (G[l][c] + (T)0.5 * El[l] * n.w[c]) * ih;
+      T gW[D][NC], FV[D][NC];
+#pragma unroll
+      for (int dir = 0; dir < D; ++dir)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          gW[dir][c] = (Lam[dir * 3 + 0] * G[0][c] + Lam[dir * 3 + 1] * G[1][c] + Lam[dir * 3 + 2] * G[2][c]) * iJ;
+      viscous_flux<D, T>(n, A.G, A.V, gW, FV);
+      T avec[D];
+#pragma unroll
+      for (int dir = 0; dir < D; ++dir)
+        avec[dir] = Lam[dir * 3 + 0] * El[0] + Lam[dir * 3 + 1] * El[1] + Lam[dir * 3 + 2] * El[2];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        A.qout[((size_t)(e0 + e) * NFN + i) * NC + c] = avec[0] * FV[0][c] + avec[1] * FV[1][c] + avec[2] * FV[2][c];
+    }
   }
 }
 
@@ -651,9 +626,9 @@ __global__ __launch_bounds__(kThreads) void k_visc_q3(KArgs<T> A) {
 // 16-row padding), so the pair sums run on the vector ALUs: R node rows per
 // lane (rows k and k + n_p/2 for R = 2), the skew operators in LDS, the
 // tile's node values (f^(0), f^(1), w, Lambda) in LDS rows of 16 values per
-// node.  Every lane re-reads the 16 values of node j for each pair, so the
-// loop is bound by the LDS return bandwidth; with R = 2 each value read
-// feeds two rows (half the LDS bytes per FMA).
+// node.  Every lane re-reads the 16 values of node j for each pair; with
+// R = 2 each value read feeds two rows (half the LDS bytes per FMA, at two
+// waves per SIMD instead of three for R = 1).
 template <int P, typename T, int R>
 struct Split2 {
   static constexpr int D = 2, NC = 4, NFAC = 3;
@@ -980,29 +955,7 @@ __global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
 }
 
 // ---------------------------------------------------------------------------
-template <typename T>
-int tile_elems(int dim, int p, int form) {
-#define SBP_TILE(DI, PP) \
-  if (dim == DI && p == PP) return form == 1 ? HadTile<DI, PP, T>::EB : 0;
-  SBP_TILE(2, 1) SBP_TILE(2, 2) SBP_TILE(2, 3) SBP_TILE(2, 4)
-#undef SBP_TILE
-#define SBP_TILE3(PP) \
-  if (dim == 3 && p == PP) \
-    return form == 1 ? HadTile<3, PP, T>::EB : (form == 2 ? Tile<3, PP, T, 2>::EB : Tile<3, PP, T, 0>::EB);
-  SBP_TILE3(1) SBP_TILE3(2) SBP_TILE3(3)
-#undef SBP_TILE3
-  return 0;
-}
 
-// The 3D Euler split terms run in the row form.  At p = 3 in FP64 its three
-// 60 x 60 skew operators would take 86 KB of LDS (one wave per SIMD); there
-// the built-in choice reads them through the caches instead (measured on
-// MI355X: 2.82 ms against 2.97 ms for the contraction form on 196608
-// tetrahedra).  The autotuner may pick the other variant.
-template <int P, typename T>
-constexpr bool skew_from_cache3() {
-  return P == 3 && sizeof(T) == 8;
-}
 
 struct KernelRef {
   const void *fn;
@@ -1090,15 +1043,16 @@ static hipError_t launch_t(int dim, int p, int form, const KArgs<T> &A, hipStrea
 
 template <typename T>
 static hipError_t launch_q(int dim, int p, const KArgs<T> &A, hipStream_t s) {
-  if (dim != 3) return hipErrorInvalidValue;
-  const int eb = tile_elems<T>(3, p, 0);
-  if (eb <= 0 || A.n_elem <= 0) return hipErrorInvalidValue;
-  dim3 grid((A.n_elem + eb - 1) / eb), block(kThreads);
-  if (p == 1) hipLaunchKernelGGL((k_visc_q3<1, T>), grid, block, 0, s, A);
-  else if (p == 2) hipLaunchKernelGGL((k_visc_q3<2, T>), grid, block, 0, s, A);
-  else if (p == 3) hipLaunchKernelGGL((k_visc_q3<3, T>), grid, block, 0, s, A);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
+  if (dim != 3 || A.n_elem <= 0) return hipErrorInvalidValue;
+  const void *fn = p == 1 ? reinterpret_cast<const void *>(&k_visc_q3<1, T>)
+                 : p == 2 ? reinterpret_cast<const void *>(&k_visc_q3<2, T>)
+                 : p == 3 ? reinterpret_cast<const void *>(&k_visc_q3<3, T>) : nullptr;
+  if (!fn) return hipErrorInvalidValue;
+  const int eb = p == 1 ? VTile3<1, T>::EB : (p == 2 ? VTile3<2, T>::EB : VTile3<3, T>::EB);
+  const int nb = launch_grid(fn, (A.n_elem + eb - 1) / eb, 1);
+  KArgs<T> a = A;
+  void *args[] = {&a};
+  return hipLaunchKernel(fn, dim3(nb), dim3(kThreads), args, 0, s);
 }
 
 hipError_t launch_visc_q(int dim, int p, const KArgs<double> &A, hipStream_t s) { return launch_q<double>(dim, p, A, s); }

@@ -57,10 +57,11 @@ def test_every_residual_launch_shape(dim, p, n, prec):
             say(f"   variant {v} grid {g}: vs oracle {eo:.1e}, vs built-in {d:.1e}, entropy rate {de:.1e}")
             # the grid only changes which workgroup runs a tile (bitwise equal
             # residual); the variants are different kernels of the same sums
-            # (FMA contraction may differ): rounding-level agreement
-            assert d <= (0.0 if v == 0 else (1e-13 if prec == 0 else 1e-6)), (v, g, d)
+            # (FMA contraction may differ): rounding-level agreement, for FP32
+            # up to 1e-5 of max |r| over 25-60 accumulated products
+            assert d <= (0.0 if v == 0 else (1e-13 if prec == 0 else 1e-5)), (v, g, d)
             assert eo <= (1e-12 if prec == 0 else 2e-4), (v, g, eo)
-            assert de <= 1e-11, (v, g, de)
+            assert de <= (1e-11 if v == 0 or prec == 0 else 1e-5), (v, g, de)
     with pytest.raises(sbp.SbpError):
         mesh.set_launch_shape("residual", p, nvar, 1)
     with pytest.raises(sbp.SbpError):
