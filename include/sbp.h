@@ -75,7 +75,7 @@ typedef struct {
   double beta;         /* split parameter; alpha = -gamma - beta (gamma-1)
                           (Sec. 2.4; Sec. 6.3 uses beta = 2.5)                     */
   int32_t form;        /* SBP_FORM_SPLIT or SBP_FORM_HADAMARD (Sec. 6.2)           */
-  int32_t dissipation; /* 1: matrix interface dissipation (Sec. 4.4)              */
+  int32_t dissipation; /* 1: matrix interface dissipation (Sec. 4.5)              */
   int32_t viscous;     /* 1: Navier-Stokes terms with Baumann-Oden SATs (Sec. 5)   */
   int32_t heat_flux;   /* 1: include kappa grad T in the viscous flux             */
   double mu, Pr, R;    /* viscosity, Prandtl number, gas constant                  */

@@ -11,7 +11,7 @@ the seeded input generator ``paper_2305_07181_amd.workloads``.
 Modules
   operators  reference-element diagonal-E SBP operators (Def. 1, Sec. 2.1)
   geometry   physical operators, metrics and facet matching (Sec. 2.1)
-  physics    pointwise Euler/NS quantities (Sec. 2.2-3, 4, 4.4, 5)
+  physics    pointwise Euler/NS quantities (Sec. 2.2-3, 4, 4.5, 5)
   residual   entropy-split, Hadamard-form residuals and SATs (Sec. 4, 5, 6.2)
   rrk        relaxation RK4 time step (Sec. 6.1)
 

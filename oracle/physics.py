@@ -16,7 +16,7 @@ Sources in the paper:
   potentials phi, psi ................. Sec. 2.4 (eqs. phi = wTu - s, psi = wTf - g)
   Sjogreen-Yee two-point flux ......... Sec. 4 (eqs. param vector, avg
                                         arithmetic / exponential, flux entries)
-  matrix interface dissipation ........ Sec. 4.4 (intermediate states, S-hat,
+  matrix interface dissipation ........ Sec. 4.5 (intermediate states, S-hat,
                                         |Lambda|, X-hat)
   viscous flux ........................ Sec. 2.2 (tau, heat flux kappa dT/dx)
 
@@ -289,7 +289,7 @@ def _tangents(n):
 
 def dissipation_matrix(Uk, Uv, n, gas):
     """X-hat |Lambda| S-hat X-hat^T at the intermediate state of one facet
-    node pair (Sec. 4.4), for unit normal n (real, shape [d]); states are
+    node pair (Sec. 4.5), for unit normal n (real, shape [d]); states are
     single nodes (shape [n_c]).  Returns [n_c, n_c]."""
     g, a = gas.gamma, gas.alpha
     z1k, Vk, pk = sy_param(Uk, gas)

@@ -9,7 +9,7 @@ split) is
 
   r_k = H^-1 sum_i [c_b Q_xi + Q_xi^T] f^(i) - c_b sum_i A~_i D_xi w
         - 1/2 H^-1 sum_{gamma} sum_i [E^{kv}_xi o F_i(u_k, u_v)] 1        (EC SAT)
-        - 1/2 H^-1 R^T B X|Lambda|S X^T (w_k - w_v)          (dissipation, Sec. 4.4)
+        - 1/2 H^-1 R^T B X|Lambda|S X^T (w_k - w_v)          (dissipation, Sec. 4.5)
         + sum_i sum_j D_xi K~_ij D_xj w + SAT^V                     (Sec. 5)
 
 The coupling term reduces, for diagonal-E operators and the factor 2 inside

@@ -2,7 +2,7 @@
 //
 // Paper references: fluxes and EOS (Sec. 2.2); Harten entropy and entropy
 // variables (Sec. 2.4, Sec. 3); Sjogreen-Yee two-point flux with arithmetic
-// and exponential averages (Sec. 4); matrix interface dissipation (Sec. 4.4).
+// and exponential averages (Sec. 4); matrix interface dissipation (Sec. 4.5).
 //
 // Computation route (differs from a dense-matrix formulation on purpose):
 //   * A~_i g = dF^(i)/dW g is a forward-mode directional derivative through
@@ -225,7 +225,7 @@ __device__ __forceinline__ void facet_term(const Node<D, T> &k, const Node<D, T>
   for (int j = 0; j < D; ++j) out[1 + j] = mass * Vav[j] + a[j] * pav;
   out[NC - 1] = mass * (G.ggm1 * (T)0.5 * (P2k + P2v) * Ez + Vav2 - (T)0.5 * q2av);
   if (!diss) return;
-  // intermediate state (Sec. 4.4)
+  // intermediate state (Sec. 4.5)
   const T z1a = (T)0.5 * (k.z1 + v.z1);
   const T rho_h = z1a * iD;
   T Vh[D];

@@ -1,7 +1,7 @@
 // Reverse-mode derivative of the facet term with respect to the own-side
 // state, for the vector-Jacobian product of the residual.  Not in the paper;
-// the function differentiated is facet_term (two-point flux of Sec. 4.3 and
-// the matrix interface dissipation of Sec. 4.4) composed with node_from_u
+// the function differentiated is facet_term (two-point flux of Sec. 4 and
+// the matrix interface dissipation of Sec. 4.5) composed with node_from_u
 // and node_powers.  One plain evaluation of the forward quantities followed
 // by one backward sweep, instead of one dual-number pass per component.
 #pragma once

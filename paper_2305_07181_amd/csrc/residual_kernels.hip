@@ -12,7 +12,7 @@
 //   4. per node: H^-1 (volume) - c_b sum_i A~_i D_xi w with A~_i applied as a
 //      directional derivative, then at facet nodes the entropy-conservative
 //      SAT with the Sjogreen-Yee two-point flux (Sec. 4, eq. sats inv) and the
-//      optional matrix interface dissipation (Sec. 4.4), the neighbour state
+//      optional matrix interface dissipation (Sec. 4.5), the neighbour state
 //      gathered through the precomputed face-node map; write r once;
 //   5. FP64 partial of sum w^T H r per workgroup (deterministic).
 // Each facet node belongs to exactly one facet, so every node's residual is

@@ -151,7 +151,7 @@ def test_sjogreen_yee_flux(d, gas):
 @pytest.mark.parametrize("d", [2, 3])
 @pytest.mark.parametrize("gas", GASES[:2], ids=lambda g: f"beta{g.beta}")
 def test_dissipation_consistency_and_eigen(d, gas):
-    """At equal states X S X^T = dU/dW (Sec. 4.4, consistency condition) and
+    """At equal states X S X^T = dU/dW (Sec. 4.5, consistency condition) and
     X diagonalises the normal flux Jacobian with |Lambda|; the operator is
     symmetric positive semidefinite and invariant under n -> -n."""
     rng = np.random.default_rng(3)

@@ -59,7 +59,7 @@ def test_free_stream(name, make, ps):
 def test_entropy_conservation_and_stability(name, make, ps):
     """Thm. entropy conservation (split) and the SY Hadamard form: sum w^T H r
     = 0 to roundoff on periodic meshes, for continuous and discontinuous
-    states; with interface dissipation (Sec. 4.4) and with heat-flux-free
+    states; with interface dissipation (Sec. 4.5) and with heat-flux-free
     viscous BO terms (Thm. entropy stability nse) the rate is <= 0."""
     desc = make()
     for p in ps:
