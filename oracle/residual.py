@@ -15,8 +15,11 @@ split) is
 The coupling term reduces, for diagonal-E operators and the factor 2 inside
 F_i (eq. F 2-point), to -(B n . F*(u_k, u_v)) / H at every facet node.  The
 Hadamard form (Sec. 6.2, eq. weak form 2pt) replaces the first line by
--H^-1 sum_i [S_xi o F_i(u_k, u_k)] 1.  The strong form (Sec. 4, eqs. discrete
-entropy split and sats inv) is provided for the strong = weak cross-check.
+-H^-1 sum_i [S_xi o F_i(u_k, u_k)] 1.  The hybrid scheme (Sec. 4.4, Thm.
+switching hybrid) takes, element by element, either of the two volume terms
+with the same SATs (form 'hybrid', per-element flags 0 = split, 1 =
+Hadamard).  The strong form (Sec. 4, eqs. discrete entropy split and sats
+inv) is provided for the strong = weak cross-check.
 Baumann-Oden viscous SATs (Sec. 5.1, eq. bo sats): T1 = 0, T2 = T3 = B/2.
 
 Readings: the stray w_k^T in the printed Hadamard weak form is
@@ -27,8 +30,10 @@ entropy conservation sum w^T H r = 0 (Thm. entropy conservation) for the split
 and Hadamard forms, sum w^T H r <= 0 with dissipation and with heat-flux-free
 viscous terms, the per-element volume identity w^T H r_vol = sum_i 1^T E_xi
 psi^(i) (Lemma entropy conv volume), strong = weak, vanishing SATs for
-continuous states (Lemma sats vanish), Hadamard local conservation, and
-design-order truncation error on smooth states (Thm. high-order).
+continuous states (Lemma sats vanish), Hadamard local conservation, the
+hybrid scheme's entropy conservation with random flags (also switched between
+RRK steps) and local conservation on its Hadamard elements, and design-order
+truncation error on smooth states (Thm. high-order).
 """
 from __future__ import annotations
 
@@ -39,15 +44,20 @@ from .geometry import OracleMesh
 
 
 class OracleScheme:
-    """Residual evaluator.  form: 'split' (entropy split) or 'hadamard'."""
+    """Residual evaluator.  form: 'split' (entropy split), 'hadamard', or
+    'hybrid' with element_form[e] = 0 (split) or 1 (Hadamard) per element;
+    element_form may be reassigned between calls (switching between steps)."""
 
     def __init__(self, mesh: OracleMesh, gas: ph.Gas, form="split",
-                 dissipation=False, viscous=False):
-        if form not in ("split", "hadamard"):
+                 dissipation=False, viscous=False, element_form=None):
+        if form not in ("split", "hadamard", "hybrid"):
             raise ValueError(form)
+        if (form == "hybrid") != (element_form is not None):
+            raise ValueError("element_form is given exactly for the hybrid form")
         self.mesh = mesh
         self.gas = gas
         self.form = form
+        self.element_form = None if element_form is None else np.asarray(element_form, dtype=int)
         self.dissipation = bool(dissipation)
         self.viscous = bool(viscous)
         self.cb = 1.0 / (gas.beta + 1.0)
@@ -136,7 +146,8 @@ class OracleScheme:
         ops = mesh.ops
         geo = mesh.geometry(e)
         U = u[e]
-        if self.form == "split":
+        split = self.form == "split" or (self.form == "hybrid" and self.element_form[e] == 0)
+        if split:
             r = self.volume_split_strong(U, geo) if strong else self.volume_split(U, geo)
         else:
             if strong:

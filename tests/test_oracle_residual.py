@@ -164,6 +164,64 @@ def test_hadamard_conservation(name, make, ps):
             assert np.abs(H[e] @ r[e].T + flux_sum).max() < 1e-12 * np.abs(flux_sum).max()
 
 
+@pytest.mark.parametrize("name,make,ps", CASES, ids=IDS)
+def test_hybrid_entropy_conservation(name, make, ps):
+    """Thm. switching hybrid: with any per-element choice of the split or the
+    Hadamard volume term (same SATs) sum w^T H r = 0 to roundoff; all-split and
+    all-Hadamard flags reproduce the two schemes exactly."""
+    desc = make()
+    gas = ph.Gas()
+    for p in ps:
+        m = OracleMesh(desc, p)
+        rng = np.random.default_rng(100 + p)
+        for jitter in (0.0, 0.02):
+            u = cons_state(m, jitter=jitter)
+            for trial in range(2):
+                flags = rng.integers(0, 2, m.ne)
+                s = OracleScheme(m, gas, form="hybrid", element_form=flags)
+                r = s(u)
+                assert abs(s.entropy_rate(u, r)) <= rate_tol(s, u, r), (p, jitter, trial)
+        u = cons_state(m, jitter=0.02)
+        for val, form in ((0, "split"), (1, "hadamard")):
+            a = OracleScheme(m, gas, form="hybrid", element_form=np.full(m.ne, val))(u)
+            b = OracleScheme(m, gas, form=form)(u)
+            assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name,make,ps", CASES, ids=IDS)
+def test_hybrid_local_conservation(name, make, ps):
+    """Thm. switching hybrid: the elements on the Hadamard form conserve
+    locally, 1^T H_k r_k = -(sum over facet nodes of B n.F*), next to split
+    elements; a split element does not (the check is not vacuous)."""
+    desc = make()
+    gas = ph.Gas()
+    ops = None
+    for p in ps:
+        m = OracleMesh(desc, p)
+        ops = m.ops
+        u = cons_state(m, jitter=0.02)
+        flags = np.random.default_rng(200 + p).integers(0, 2, m.ne)
+        s = OracleScheme(m, gas, form="hybrid", element_form=flags)
+        r = s(u)
+        H = m.H_all()
+        worst_split = 0.0
+        for e in range(m.ne):
+            geo = m.geometry(e)
+            flux_sum = 0.0
+            for f in range(m.n_fac):
+                v, g = m.neighbor(e, f)
+                mk = ops["facet_nodes"][f]
+                mv = ops["facet_nodes"][g][m.facet_perm(e, f)]
+                Fs = ph.sy_flux(u[e][:, mk], u[v][:, mv], gas)
+                flux_sum = flux_sum + np.einsum("jd,dcj->c", geo["Bn"][f], Fs)
+            gap = np.abs(H[e] @ r[e].T + flux_sum).max() / np.abs(flux_sum).max()
+            if flags[e] == 1:
+                assert gap < 1e-12, (p, e, gap)
+            else:
+                worst_split = max(worst_split, gap)
+        assert worst_split > 1e-8, (p, worst_split)
+
+
 def _smooth(x, d):
     """A smooth periodic state on [0,1]^d, complex-step safe."""
     s = [np.sin(2 * np.pi * x[k]) for k in range(d)]

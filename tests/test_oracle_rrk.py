@@ -37,6 +37,23 @@ def test_fully_discrete_entropy_equality(dissipation):
         assert e < 0
 
 
+def test_hybrid_switched_between_steps_conserves_entropy():
+    """Thm. switching hybrid: the per-element choice of volume term may change
+    from one RRK step to the next without loss of entropy conservation."""
+    m, u = vortex_setup()
+    u = u * (1 + 0.01 * np.random.default_rng(1).standard_normal(u.shape))
+    rng = np.random.default_rng(5)
+    s = OracleScheme(m, ph.Gas(), form="hybrid", element_form=rng.integers(0, 2, m.ne))
+    dt = s.timestep(u, 0.1)
+    s0 = s.total_entropy(u)
+    for step in range(3):
+        s.element_form = rng.integers(0, 2, m.ne)
+        u, gamma, d, e = rrk.rrk4_step(s, u, dt)
+        assert 0.9 < gamma < 1.1
+    s1 = s.total_entropy(u)
+    assert abs(s1 - s0) < 3 * 64 * np.finfo(float).eps * abs(s0)
+
+
 def test_gamma_tends_to_one():
     """gamma_n = 1 + O(dt^p') as dt -> 0 (relaxation leaves RK4 order intact)."""
     m, u = vortex_setup()
