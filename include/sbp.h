@@ -138,6 +138,20 @@ int sbp_residual_vjp(sbp_mesh *mesh, const void *u_dev, const void *lambda_dev,
 int sbp_rrk_step(sbp_mesh *mesh, void *u_dev, double dt, double cfl,
                  sbp_rrk_report *rep, void *hip_stream);
 
+/* Hybrid scheme (Sec. 4.4, Thm. switching hybrid): per element the volume
+ * term of the entropy-split form (eq. weak form split) or of the Hadamard
+ * form (eq. weak form 2pt), with the same SATs; entropy conservation holds for
+ * any choice, and the elements on the Hadamard form conserve locally.
+ * form_dev: device array of n_elem bytes in the element order of the mesh
+ * description, 0 = entropy split, 1 = Hadamard; borrowed: every later
+ * sbp_residual and sbp_rrk_step reads it, so the caller may change its
+ * contents between calls (switching between time steps; a captured RK stage
+ * graph reads the same array).  NULL returns every element to phys.form.
+ * Values other than 0 and 1 leave the element's residual unwritten.
+ * SBP_ENOTSUP with the viscous terms; while it is set, sbp_residual_vjp
+ * returns SBP_ENOTSUP.  The FP64 entropy rate sums both launches. */
+int sbp_set_volume_form(sbp_mesh *mesh, const uint8_t *form_dev);
+
 /* enable != 0 (default): sbp_rrk_step replays its captured stage graph;
  * enable == 0: the stages are launched one by one (for callers that capture
  * the stream themselves).  Not in the paper.  SBP_EINVAL for a null handle. */

@@ -51,6 +51,7 @@ struct DegreeClass {
   int p = 0, np = 0, nf = 0, n_elem = 0;
   std::vector<int> elems;  // global element ids
   int *d_uoff = nullptr;
+  int *d_gid = nullptr;   // mesh element id of each element of the class
   double *d_geo = nullptr;
   int *d_nbr = nullptr;
   double *d_Hn = nullptr;
@@ -62,6 +63,7 @@ struct DegreeClass {
   void *d_q = nullptr;    // viscous: facet normal viscous fluxes
   int part_off = 0;       // offset of this class in the residual partial buffer
   int res_blocks = 0;     // partial sums reserved: the largest grid of any launch shape
+  int part_off_h = 0, res_blocks_h = 0;  // hybrid scheme: the Hadamard launch's partial sums
   sbp::LaunchCfg res_cfg, vjp_cfg;  // launch shapes (autotuner)
   int node_off_blk = 0;   // offset in the node partial buffers
   int node_blocks = 0;
@@ -83,6 +85,7 @@ struct sbp_mesh {
   int part_total = 0;
   int batch_blocks = 0;       // 2D entropy split with several degree classes: one launch
   int batch_grid = 1, vjp_batch_grid = 1;  // grid choices of the batched launches (autotuner)
+  const unsigned char *eform = nullptr;      // hybrid scheme: caller's per-element form flags
   double *d_npart = nullptr;  // node-kernel partials [(n_c+1) x node_total]
   int node_total = 0;
   double *d_scal = nullptr;   // device scalars
@@ -410,6 +413,7 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
     }
     int rc;
     if ((rc = upload(c.d_uoff, uoff, s))) return rc;
+    if ((rc = upload(c.d_gid, c.elems, s))) return rc;
     if ((rc = upload(c.d_geo, geo, s))) return rc;
     if ((rc = upload(c.d_nbr, nbr, s))) return rc;
     if ((rc = upload(c.d_Hn, hn, s))) return rc;
@@ -444,6 +448,15 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
     M->batch_blocks = std::max(sbp::residual2_batch_blocks(ne_p, 0, 0), sbp::residual2_batch_blocks(ne_p, 1, 0));
     part_total = std::max(part_total, M->batch_blocks);
   }
+  if (!ph->viscous)  // the hybrid scheme's second launch (the other volume form) per class
+    for (auto &c : M->cls) {
+      const int other = ph->form == SBP_FORM_SPLIT ? SBP_FORM_HADAMARD : SBP_FORM_SPLIT;
+      c.res_blocks_h = 0;
+      for (int pr = 0; pr < 2; ++pr)
+        c.res_blocks_h = std::max(c.res_blocks_h, sbp::residual_blocks(dim, c.p, pr, other, c.n_elem, {0, 1}));
+      c.part_off_h = part_total;
+      part_total += c.res_blocks_h;
+    }
   M->part_total = part_total;
   M->node_total = node_total;
   int rc;
@@ -485,6 +498,7 @@ sbp::KArgs<T> kargs(sbp_mesh *M, DegreeClass &c, const double *u, void *r, const
   A.geo = c.d_geo;
   A.nbr = c.d_nbr;
   A.uoff = c.d_uoff;
+  A.gid = c.d_gid;
   A.n_elem = c.n_elem;
   A.diss = ph.dissipation;
   A.op = op;
@@ -513,6 +527,32 @@ int residual_impl(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStr
         HIPCHK(sbp::launch_visc_q(M->dim, c.p, kargs<float>(M, c, u, r, c.op32), s));
     }
   }
+  // hybrid scheme (Sec. 4.4): the mesh's own form runs on the elements flagged
+  // with it, the other form on the rest, each with the shared SATs; the second
+  // launch keeps its partial sums apart
+  const bool hyb = M->eform != nullptr;
+  const int form_other = ph.form == SBP_FORM_SPLIT ? SBP_FORM_HADAMARD : SBP_FORM_SPLIT;
+  auto other_launch = [&](DegreeClass &c) -> int {
+    if (ph.precision == SBP_FP64) {
+      sbp::KArgs<double> A = kargs<double>(M, c, u, r, c.op64);
+      A.eform = M->eform;
+      A.form_id = form_other;
+      A.ent_part = M->d_part + c.part_off_h;
+      HIPCHK(sbp::launch_residual(M->dim, c.p, form_other, A, s, sbp::LaunchCfg{0, 1}));
+    } else {
+      sbp::KArgs<float> A = kargs<float>(M, c, u, r, c.op32);
+      A.eform = M->eform;
+      A.form_id = form_other;
+      A.ent_part = M->d_part + c.part_off_h;
+      HIPCHK(sbp::launch_residual(M->dim, c.p, form_other, A, s, sbp::LaunchCfg{0, 1}));
+    }
+    return SBP_OK;
+  };
+  auto other_blocks = [&](const DegreeClass &c) {
+    return sbp::residual_blocks(M->dim, c.p, ph.precision, form_other, c.n_elem, sbp::LaunchCfg{0, 1});
+  };
+  const int ncls = (int)M->cls.size();
+  int rc;
   if (M->batch_blocks > 0 && ph.form == SBP_FORM_SPLIT && !ph.viscous) {
     // every degree class in one persistent launch
     sbp::KArgs<double> a64[4];
@@ -522,9 +562,11 @@ int residual_impl(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStr
     for (auto &c : M->cls) {
       if (ph.precision == SBP_FP64) {
         a64[c.p - 1] = kargs<double>(M, c, u, r, c.op64);
+        a64[c.p - 1].eform = M->eform;
         p64[c.p - 1] = &a64[c.p - 1];
       } else {
         a32[c.p - 1] = kargs<float>(M, c, u, r, c.op32);
+        a32[c.p - 1].eform = M->eform;
         p32[c.p - 1] = &a32[c.p - 1];
       }
     }
@@ -532,28 +574,49 @@ int residual_impl(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStr
       HIPCHK(sbp::launch_residual2_batch(p64, M->d_part, s, M->batch_grid));
     else
       HIPCHK(sbp::launch_residual2_batch(p32, M->d_part, s, M->batch_grid));
+    if (hyb)
+      for (auto &c : M->cls)
+        if ((rc = other_launch(c))) return rc;
     if (ent_dev) {
       int ne_p[4] = {0, 0, 0, 0};
       for (auto &c : M->cls) ne_p[c.p - 1] = c.n_elem;
       const int nb = sbp::residual2_batch_blocks(ne_p, ph.precision == SBP_FP64 ? 0 : 1, M->batch_grid);
-      HIPCHK(sbp::launch_reduce(M->d_part, nb, 1, 0, ent_dev, s));
+      if (!hyb) {
+        HIPCHK(sbp::launch_reduce(M->d_part, nb, 1, 0, ent_dev, s));
+      } else {
+        HIPCHK(sbp::launch_reduce(M->d_part, nb, 1, 0, M->d_scal + SC_RED, s));
+        for (int ci = 0; ci < ncls; ++ci)
+          HIPCHK(sbp::launch_reduce(M->d_part + M->cls[ci].part_off_h, other_blocks(M->cls[ci]), 1, 0,
+                                    M->d_scal + SC_RED + 1 + ci, s));
+        HIPCHK(sbp::launch_reduce(M->d_scal + SC_RED, 1 + ncls, 1, 0, ent_dev, s));
+      }
     }
     return SBP_OK;
   }
   for (auto &c : M->cls) {
-    if (ph.precision == SBP_FP64)
-      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, kargs<double>(M, c, u, r, c.op64), s, c.res_cfg));
-    else
-      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, kargs<float>(M, c, u, r, c.op32), s, c.res_cfg));
+    if (ph.precision == SBP_FP64) {
+      sbp::KArgs<double> A = kargs<double>(M, c, u, r, c.op64);
+      A.eform = M->eform;
+      A.form_id = ph.form;
+      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, A, s, c.res_cfg));
+    } else {
+      sbp::KArgs<float> A = kargs<float>(M, c, u, r, c.op32);
+      A.eform = M->eform;
+      A.form_id = ph.form;
+      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, A, s, c.res_cfg));
+    }
+    if (hyb && (rc = other_launch(c))) return rc;
   }
   if (ent_dev) {
     const int form_eff = ph.viscous ? 2 : ph.form;
-    for (size_t ci = 0; ci < M->cls.size(); ++ci) {
+    for (int ci = 0; ci < ncls; ++ci) {
       auto &c = M->cls[ci];
       const int nb = sbp::residual_blocks(M->dim, c.p, ph.precision, form_eff, c.n_elem, c.res_cfg);
       HIPCHK(sbp::launch_reduce(M->d_part + c.part_off, nb, 1, 0, M->d_scal + SC_RED + ci, s));
+      if (hyb)
+        HIPCHK(sbp::launch_reduce(M->d_part + c.part_off_h, other_blocks(c), 1, 0, M->d_scal + SC_RED + ncls + ci, s));
     }
-    HIPCHK(sbp::launch_reduce(M->d_scal + SC_RED, (int)M->cls.size(), 1, 0, ent_dev, s));
+    HIPCHK(sbp::launch_reduce(M->d_scal + SC_RED, hyb ? 2 * ncls : ncls, 1, 0, ent_dev, s));
   }
   return SBP_OK;
 }
@@ -921,6 +984,8 @@ int sbp_residual_vjp(sbp_mesh *M, const void *u, const void *lam, void *ubar, vo
   const sbp_physics &ph = M->phys;
   if (ph.viscous || ph.form != SBP_FORM_SPLIT)
     return fail(SBP_ENOTSUP, "the VJP covers the entropy-split Euler residual (with or without dissipation)");
+  if (M->eform)
+    return fail(SBP_ENOTSUP, "the VJP covers the entropy-split form; clear the hybrid form flags first");
   if (M->dim == 2 && M->cls.size() > 1) {
     // every degree class in one persistent launch
     sbp::KArgs<double> a[4];
@@ -998,6 +1063,20 @@ sbp::LaunchCfg *find_slot(sbp_mesh *M, int kind, int p, int &nvar, int *&grid_on
 }
 
 }  // namespace
+
+int sbp_set_volume_form(sbp_mesh *M, const uint8_t *form_dev) {
+  if (!M) return fail(SBP_EINVAL, "null handle");
+  if (form_dev && M->phys.viscous)
+    return fail(SBP_ENOTSUP, "the hybrid scheme covers the Euler terms (no viscous terms)");
+  M->eform = form_dev;
+  // the captured RK stages hold the previous launches
+  if (M->rk_exec) {
+    (void)hipGraphExecDestroy(M->rk_exec);
+    M->rk_exec = nullptr;
+    M->rk_u = nullptr;
+  }
+  return SBP_OK;
+}
 
 int sbp_get_launch_shape(sbp_mesh *M, int32_t kind, int32_t p, int32_t *variant, int32_t *grid) {
   if (!M || (kind != 0 && kind != 1)) return fail(SBP_EINVAL, "bad handle or kind");
@@ -1126,6 +1205,7 @@ int sbp_destroy_mesh(sbp_mesh *M) {
   if (!M) return SBP_OK;
   for (auto &c : M->cls) {
     (void)hipFree(c.d_uoff);
+    (void)hipFree(c.d_gid);
     (void)hipFree(c.d_geo);
     (void)hipFree(c.d_nbr);
     (void)hipFree(c.d_Hn);

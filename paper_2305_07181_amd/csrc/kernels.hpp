@@ -54,7 +54,29 @@ struct KArgs {
   const double *lam;   // cotangent (state layout)
   double *ubar;        // result (state layout)
   const double *Hn;    // [n_elem*NP] diagonal of H_k
+  // hybrid scheme: volume form of every element of the mesh (0 entropy split,
+  // 1 Hadamard) in the mesh's element order, or null; the kernel of form
+  // form_id then skips the elements of the other form
+  const unsigned char *eform;
+  const int *gid;      // [n_elem] mesh element id of each element of the class
+  int form_id;
 };
+
+// Whether element e of the class runs in this kernel (hybrid scheme).
+template <typename T>
+__device__ __forceinline__ bool elem_on(const KArgs<T> &A, int e) {
+  return !A.eform || A.eform[A.gid[e]] == A.form_id;
+}
+
+// Whether any element of [e0, e0 + ne) runs in this kernel; the same answer
+// in every lane, so a workgroup may skip the tile as a whole.
+template <typename T>
+__device__ __forceinline__ bool tile_on(const KArgs<T> &A, int e0, int ne) {
+  if (!A.eform) return true;
+  for (int e = 0; e < ne; ++e)
+    if (elem_on(A, e0 + e)) return true;
+  return false;
+}
 
 // All degree classes of a 2D mesh in one launch: c[p-1] holds the arguments
 // of the class of degree p (n_elem = 0 if absent), g0[p-1] its first group in

@@ -412,7 +412,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_split3v(KArgs<T> A) {
   for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
     const int e0 = tl * EB;
     const int ne = min(EB, A.n_elem - e0);
-    const bool act = tid < ne * NP;
+    if (!tile_on(A, e0, ne)) continue;  // hybrid scheme: no element of this form
+    const bool act = tid < ne * NP && elem_on(A, e0 + e);
     __syncthreads();
     for (int x = tid; x < ne * 10; x += kThreads) gs[x / 10][x % 10] = (T)A.geo[(size_t)(e0 + x / 10) * 10 + x % 10];
     __syncthreads();
@@ -654,8 +655,9 @@ struct Split2 {
     const int tid = threadIdx.x;
     const int e0 = tl * EB;
     const int ne = min(EB, A.n_elem - e0);
+    if (!tile_on(A, e0, ne)) return;  // hybrid scheme: no element of this form
     const int e = tid / L, k = tid % L;
-    const bool act = e < ne;
+    const bool act = e < ne && elem_on(A, e0 + e);
     const T cb = A.G.cb;
     const T hv = (T)0.5 * (cb - (T)1), he = (T)0.5 * (cb + (T)1);
     Node<D, T> n[R];
@@ -848,6 +850,7 @@ __global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int e0 = tile * EB;
     const int ne = min(EB, A.n_elem - e0);
+    if (!tile_on(A, e0, ne)) continue;  // hybrid scheme: no element of this form
     __syncthreads();
     if constexpr (DIM == 3) {
       for (int x = tid; x < ne * 10; x += kThreads) gm[x / 10][x % 10] = (T)A.geo[(size_t)(e0 + x / 10) * 10 + x % 10];
@@ -858,6 +861,7 @@ __global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
       const int x = tid + kq * kThreads;
       if (x >= ne * NP) break;
       const int e = x / NP, j = x % NP;
+      if (!elem_on(A, e0 + e)) continue;
       const int uo = A.uoff[e0 + e];
       T uu[NC];
 #pragma unroll
@@ -896,6 +900,7 @@ __global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
       const int x = tid + kq * kThreads;
       if (x >= ne * NP) break;
       const int e = x / NP, m = x % NP;
+      if (!elem_on(A, e0 + e)) continue;
       const Node<D, T> &a = nodes[kq];
       T Lm[D][D], J;
       if constexpr (DIM == 2) {

@@ -24,7 +24,7 @@ FP64, FP32 = 0, 1
 SYMBOLS = ["sbp_setup_mesh", "sbp_mesh_info", "sbp_residual", "sbp_residual_vjp", "sbp_rrk_step",
            "sbp_diagnostics", "sbp_check_device", "sbp_set_time", "sbp_destroy_mesh",
            "sbp_last_error", "sbp_reference_operator", "sbp_use_graphs", "sbp_autotune",
-           "sbp_get_launch_shape", "sbp_set_launch_shape"]
+           "sbp_get_launch_shape", "sbp_set_launch_shape", "sbp_set_volume_form"]
 
 
 class SbpError(RuntimeError):
@@ -86,6 +86,7 @@ def load_library(path: str = _LIB_PATH):
     lib.sbp_autotune.argtypes = [P, P, P, C.POINTER(TuneReport), P]
     lib.sbp_get_launch_shape.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.sbp_set_launch_shape.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+    lib.sbp_set_volume_form.argtypes = [P, P]
     lib.sbp_destroy_mesh.argtypes = [P]
     lib.sbp_last_error.restype = C.c_char_p
     lib.sbp_reference_operator.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -268,6 +269,18 @@ class Mesh:
     def set_launch_shape(self, kind="residual", p=0, variant=0, grid=1):
         """Pin the launch shape of one kernel slot (sbp_set_launch_shape)."""
         _check(_lib.sbp_set_launch_shape(self._h, ("residual", "vjp").index(kind), int(p), int(variant), int(grid)))
+
+    def set_volume_form(self, flags=None):
+        """Hybrid scheme (sbp_set_volume_form): flags is a uint8 CUDA tensor of
+        n_elem values (0 entropy split, 1 Hadamard) that later residuals and
+        RRK steps read (its contents may change between calls), or None."""
+        import torch
+        if flags is not None:
+            if flags.dtype != torch.uint8 or not flags.is_cuda or not flags.is_contiguous() \
+                    or flags.numel() != self.n_elem:
+                raise ValueError("flags must be a contiguous uint8 CUDA tensor of n_elem values")
+        _check(_lib.sbp_set_volume_form(self._h, _ptr(flags) if flags is not None else None))
+        self._form_flags = flags   # keep the borrowed array alive
 
     def use_graphs(self, enable=True):
         _check(_lib.sbp_use_graphs(self._h, int(bool(enable))))

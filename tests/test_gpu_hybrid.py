@@ -1,0 +1,174 @@
+"""Hybrid scheme on the GPU (Sec. 4.4, Thm. switching hybrid): per-element
+volume form flags (0 entropy split, 1 Hadamard) against the oracle's hybrid
+residual, flags changed between calls and between RRK steps, batched problems,
+FP32, a mesh set up in the Hadamard form, and the VJP refusal."""
+import numpy as np
+import pytest
+
+from tests.gpu_common import rel_err_per_component, say, state
+
+pytestmark = pytest.mark.gpu
+
+
+def _flags(ne, seed):
+    return np.random.default_rng(seed).integers(0, 2, ne).astype(np.uint8)
+
+
+def _oracle(desc, p, flags, **kw):
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from oracle.residual import OracleScheme
+    m = OracleMesh(desc, p)
+    return m, OracleScheme(m, ph.Gas(), form="hybrid", element_form=flags, **kw)
+
+
+CASES = [(2, p, d) for p in (1, 2, 3, 4) for d in (False, True)] + [(3, p, d) for p in (1, 2, 3) for d in (False, True)]
+
+
+@pytest.mark.parametrize("dim,p,diss", CASES)
+def test_hybrid_vs_oracle(dim, p, diss):
+    import torch
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say(f"[hybrid] dim={dim} p={p} diss={diss}")
+    desc = wl.vortex2d_mesh(5, warp=0.05) if dim == 2 else wl.periodic_tet_mesh(2, 1.0)
+    flags = _flags(len(desc["elem_vert"]), 300 + 10 * dim + p)
+    m, sch = _oracle(desc, p, flags, dissipation=diss)
+    u = state(m, "random", seed=30 + p, jitter=0.01)
+    mesh = sbp.Mesh(desc, p, dissipation=diss)
+    fd = torch.from_numpy(flags).cuda()
+    mesh.set_volume_form(fd)
+    r, er = mesh.residual(torch.from_numpy(u).cuda(), entropy_rate=True)
+    mesh.check_device()
+    r = r.cpu().numpy()
+    ro = sch(u)
+    err = rel_err_per_component(r, ro)
+    say("   rel err per component", err.max(), "flags on Hadamard:", int(flags.sum()), "of", len(flags))
+    assert (err <= 1e-12).all(), err
+    from oracle import physics as ph
+    rate_o = sch.entropy_rate(u, ro)
+    scale = sum(np.sum(m.geometry(e)["H"][None, :] * np.abs(ph.entropy_vars(u[e], sch.gas) * ro[e]))
+                for e in range(m.ne))
+    assert abs(float(er.cpu()[0]) - rate_o) <= 1e-12 * scale
+    if not diss:
+        assert abs(float(er.cpu()[0])) <= 1e-12 * scale
+    mesh.close()
+
+
+def test_hybrid_flags_switched_between_calls():
+    """The flag array is read by every call: changing it in place switches the
+    elements; clearing it returns to the mesh's form."""
+    import torch
+    from oracle import physics as ph
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say("[hybrid] switch between calls")
+    desc = wl.vortex2d_mesh(6, warp=0.05)
+    ne = len(desc["elem_vert"])
+    fa, fb = _flags(ne, 41), _flags(ne, 42)
+    m, sch = _oracle(desc, 3, fa)
+    u = state(m, "random", seed=9, jitter=0.01)
+    ud = torch.from_numpy(u).cuda()
+    mesh = sbp.Mesh(desc, 3)
+    fd = torch.from_numpy(fa).cuda()
+    mesh.set_volume_form(fd)
+    ra = mesh.residual(ud).cpu().numpy()
+    fd.copy_(torch.from_numpy(fb))
+    rb = mesh.residual(ud).cpu().numpy()
+    mesh.set_volume_form(None)
+    rs = mesh.residual(ud).cpu().numpy()
+    mesh.check_device()
+    assert (rel_err_per_component(ra, sch(u)) <= 1e-12).all()
+    sch.element_form = fb
+    assert (rel_err_per_component(rb, sch(u)) <= 1e-12).all()
+    assert (rel_err_per_component(rs, OracleScheme(m, ph.Gas())(u)) <= 1e-12).all()
+    assert np.abs(ra - rb).max() > 1e-6 * np.abs(ra).max()  # the switch took effect
+    mesh.close()
+
+
+def test_hybrid_rrk_flags_switched_between_steps():
+    """RRK steps with the stage graph while the flags change between steps:
+    entropy conserved to the rounding level, as Thm. switching hybrid states."""
+    import torch
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say("[hybrid] RRK with switched flags")
+    desc = wl.vortex2d_mesh(8, warp=0.05)
+    ne = len(desc["elem_vert"])
+    m, _ = _oracle(desc, 2, _flags(ne, 1))
+    u = state(m, "vortex")
+    ud = torch.from_numpy(u).cuda()
+    mesh = sbp.Mesh(desc, 2)
+    fd = torch.from_numpy(_flags(ne, 50)).cuda()
+    mesh.set_volume_form(fd)
+    for step in range(4):
+        fd.copy_(torch.from_numpy(_flags(ne, 51 + step)))
+        rep = mesh.rrk_step(ud, cfl=0.1)
+        ds = rep["entropy_after"] - rep["entropy_before"]
+        scale = abs(rep["entropy_before"])
+        say(f"   step {step}: gamma {rep['gamma']:.15f} entropy change {ds / scale:.1e}")
+        assert 0.9 < rep["gamma"] < 1.1
+        assert abs(ds - rep["gamma"] * rep["e"]) <= 64 * 2.2e-16 * scale
+        assert abs(ds) <= 64 * 2.2e-16 * scale
+    mesh.check_device()
+    mesh.close()
+
+
+def test_hybrid_batched_problems():
+    import torch
+    from oracle import physics as ph
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import sbp
+    from tests.test_gpu_batch import SMALL, _batch, _flat, _split
+    say("[hybrid] batched 2D")
+    desc, deg, off, meshes, states = _batch(SMALL, 0.05)
+    ne = int(off[-1])
+    flags = _flags(ne, 77)
+    mesh = sbp.Mesh(desc, deg, problem_off=off)
+    fd = torch.from_numpy(flags).cuda()
+    mesh.set_volume_form(fd)
+    u = torch.from_numpy(_flat(mesh, off, states)).cuda()
+    r, er = mesh.residual(u, entropy_rate=True)
+    mesh.check_device()
+    parts = _split(mesh, off, r.cpu().numpy(), [s.shape for s in states])
+    total, scale = 0.0, 0.0
+    for b, (m, ub) in enumerate(zip(meshes, states)):
+        sch = OracleScheme(m, ph.Gas(), form="hybrid", element_form=flags[off[b]:off[b + 1]])
+        ro = sch(ub)
+        err = rel_err_per_component(parts[b], ro)
+        assert (err <= 1e-12).all(), (b, err)
+        total += sch.entropy_rate(ub, ro)
+        scale += np.sum(np.abs(ro))
+    assert abs(float(er.cpu()[0]) - total) <= 1e-12 * scale
+    with pytest.raises(sbp.SbpError) as ei:
+        mesh.vjp(u, torch.ones_like(u))
+    assert ei.value.code == sbp.SBP_ENOTSUP
+    mesh.set_volume_form(None)
+    mesh.vjp(u, torch.ones_like(u))
+    mesh.close()
+
+
+@pytest.mark.parametrize("dim,p", [(2, 4), (3, 2)])
+def test_hybrid_fp32_and_hadamard_mesh(dim, p):
+    """FP32 hybrid within the stated FP32 error; a mesh set up in the Hadamard
+    form runs the split form on the flagged-0 elements."""
+    import torch
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say(f"[hybrid] fp32 / hadamard mesh dim={dim} p={p}")
+    desc = wl.vortex2d_mesh(4, warp=0.05) if dim == 2 else wl.periodic_tet_mesh(2, 1.0)
+    flags = _flags(len(desc["elem_vert"]), 90 + p)
+    m, sch = _oracle(desc, p, flags, dissipation=True)
+    u = state(m, "random", seed=11, jitter=0.01)
+    ud = torch.from_numpy(u).cuda()
+    fd = torch.from_numpy(flags).cuda()
+    ro = sch(u)
+    m32 = sbp.Mesh(desc, p, dissipation=True, precision=sbp.FP32)
+    m32.set_volume_form(fd)
+    e32 = rel_err_per_component(m32.residual(ud).cpu().numpy(), ro)
+    say("   FP32 rel err", e32.max())
+    assert (e32 <= 2e-4).all(), e32
+    m32.close()
+    mh = sbp.Mesh(desc, p, dissipation=True, form=sbp.FORM_HADAMARD)
+    mh.set_volume_form(fd)
+    eh = rel_err_per_component(mh.residual(ud).cpu().numpy(), ro)
+    assert (eh <= 1e-12).all(), eh
+    mh.check_device()
+    mh.close()
