@@ -179,6 +179,27 @@ def ns_rows(args):
     return row
 
 
+def hybrid_rows(args, mesh, u, ne):
+    """Hybrid scheme (Sec. 4.4) on the 32768-triangle mesh, p = 4: the
+    residual with per-element flags -- a clustered region of the elements whose
+    centroid lies in x < 2 (about 10%, where a shock detector would flag) and
+    50% random flags (seed 7) -- against the pure split residual."""
+    import torch
+    x = mesh.node_coords().cpu().numpy().reshape(ne, 2, -1).mean(axis=2)
+    r = torch.empty_like(u)
+    base, _ = _time_calls(lambda: mesh.residual(u, r), max(5, args.steps // 2), 2)
+    row = dict(split_ms=base * 1e3)
+    patterns = dict(clustered=(x[:, 0] < 2.0), random50=np.random.default_rng(7).random(ne) < 0.5)
+    for name, sel in patterns.items():
+        fd = torch.from_numpy(sel.astype(np.uint8)).cuda()
+        mesh.set_volume_form(fd)
+        med, _ = _time_calls(lambda: mesh.residual(u, r), max(5, args.steps // 2), 2)
+        row[name] = dict(hadamard_elements=int(sel.sum()), ms=med * 1e3, over_split=med / base)
+    mesh.set_volume_form(None)
+    mesh.check_device()
+    return row
+
+
 def batch_rows(args):
     """48 independent periodic problems on [0,1]^2, p ~ U{1..4}, n_e ~ logU[256,
     16384] (seed 0), random smooth states (seed 1000+b): one batched forward
@@ -397,6 +418,7 @@ def main():
             m64.close()
             del u3, lam3, ub3
         extras["ns_tgv_82944_p3"] = ns_rows(args)
+        extras["hybrid_tri_p4"] = hybrid_rows(args, meshes[4], states[4], ne)
         extras["batch48"] = batch_rows(args)
         fw = sum(extras[f"tri_p{p}"]["fp64_split"]["ms"] for p in ps)
         bw = sum(extras[f"tri_p{p}"]["fp64_vjp"]["ms"] for p in ps)

@@ -227,6 +227,50 @@ def vortex2d_mesh(n: int = 8, warp: float = 0.0) -> dict:
     return periodic_tri_mesh(n, n, 20.0, 20.0, warp=warp)
 
 
+def paper_vortex2d_mesh(n: int) -> dict:
+    """Grid of the paper's 2D isentropic-vortex studies (Sec. 7.3): the
+    periodic box [0,20] x [-5,5] in n x n rectangles, each cut into two
+    triangles, with the quadratic geometry nodes (vertices and edge midpoints)
+    moved by the perturbation of eq. (curve 2d vortex),
+        x1 = x1^ + 1/8 cos(pi/20 (x1^ - 10)) cos(3 pi/10 x2^),
+        x2 = x2^ + 1/8 sin(pi/5 (x1 - 10)) cos(pi/10 x2^)   (x1 perturbed),
+    which vanishes on the box edges (conforming and periodic)."""
+    desc = periodic_tri_mesh(n, n, 20.0, 10.0)
+    vert = desc["vert_xyz"].copy()
+    vert[:, 1] -= 5.0
+    v = vert[desc["elem_vert"]]                            # [ne,3,2]
+    mids = np.stack([0.5 * (v[:, 0] + v[:, 1]), 0.5 * (v[:, 1] + v[:, 2]),
+                     0.5 * (v[:, 2] + v[:, 0])], 1)
+    g = np.concatenate([v, mids], 1)                       # [ne,6,2]
+    x1 = g[..., 0] + 0.125 * np.cos(np.pi / 20 * (g[..., 0] - 10)) * np.cos(0.3 * np.pi * g[..., 1])
+    x2 = g[..., 1] + 0.125 * np.sin(np.pi / 5 * (x1 - 10)) * np.cos(np.pi / 10 * g[..., 1])
+    desc["vert_xyz"] = vert
+    desc["p_geom"] = 2
+    desc["geom_nodes"] = np.ascontiguousarray(np.stack([x1, x2], -1))
+    return desc
+
+
+def paper_vortex2d(x, t=0.0, alpha=3.0, center=(5.0, 0.0), period=(20.0, 10.0), gamma=GAMMA):
+    """The 2D isentropic vortex of the paper's studies (Sec. 7.3): strength
+    alpha = 3, centre (5, 0) advected by the free stream (1, 0) on the periodic
+    box [0,20] x [-5,5] (minimum-image distance), velocity perturbation
+    alpha/(2 pi) exp(1 - r^2) (-(y - yc), x - xc) and, for radial
+    equilibrium, T = 1 - alpha^2 (gamma-1) / (16 gamma pi^2) exp(2 (1 - r^2)),
+    rho = T^(1/(gamma-1)), p = rho^gamma.  Returns (rho, V[2,...], p)."""
+    x = np.asarray(x, dtype=np.float64)
+    dx = x[0] - (center[0] + t)
+    dy = x[1] - center[1]
+    dx = dx - period[0] * np.round(dx / period[0])
+    dy = dy - period[1] * np.round(dy / period[1])
+    r2 = dx * dx + dy * dy
+    T = 1.0 - alpha * alpha * (gamma - 1.0) / (16.0 * gamma * math.pi ** 2) * np.exp(2.0 * (1.0 - r2))
+    rho = T ** (1.0 / (gamma - 1.0))
+    p = rho ** gamma
+    f = alpha / (2.0 * math.pi) * np.exp(1.0 - r2)
+    V = np.stack([1.0 - f * dy, f * dx], 0)
+    return rho, V, p
+
+
 def tgv_mesh(n: int) -> dict:
     """[0, 2 pi]^3, n^3 hexes x 6 tetrahedra (n=32: 196608; n=24: 82944)."""
     return periodic_tet_mesh(n, 2 * math.pi)

@@ -1,0 +1,48 @@
+"""The primary-conservation study (Sec. 4.3, Thm. conservation) through the
+library on small grids: the conserved sums it reports are the oracle's sums
+of the same states, the relaxation step keeps the entropy, and the errors
+fall with refinement."""
+import numpy as np
+import pytest
+
+from tests.gpu_common import say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_conserved_sums_match_oracle():
+    import torch
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say("[study] conserved sums")
+    desc = wl.paper_vortex2d_mesh(8)
+    m = OracleMesh(desc, 2)
+    x = m.node_coords()
+    rho, V, pr = wl.paper_vortex2d(np.moveaxis(x, 1, 0))
+    u = np.ascontiguousarray(np.moveaxis(wl.conservative(rho, V, pr), 0, 1))
+    mesh = sbp.Mesh(desc, 2)
+    ud = torch.from_numpy(u).cuda()
+    for _ in range(3):
+        mesh.rrk_step(ud, cfl=0.1)
+    d = mesh.diagnostics(ud)
+    mesh.check_device()
+    uf = ud.cpu().numpy()
+    H = m.H_all()
+    sums = np.einsum("en,ecn->c", H, uf)
+    s_o = sum(np.sum(H[e] * ph.entropy(uf[e], ph.Gas())) for e in range(m.ne))
+    say("   gpu", d, "oracle", s_o, sums)
+    assert abs(d[0] - s_o) <= 1e-13 * abs(s_o)
+    assert np.allclose(d[1:], sums, rtol=1e-13, atol=1e-13 * np.abs(sums).max())
+    mesh.close()
+
+
+def test_conservation_study_small():
+    from paper_2305_07181_amd import studies
+    say("[study] small grids")
+    rows = studies.conservation_study([8, 16], [2], tf=0.5, cfl=0.1, emit=say)
+    for r in rows:
+        assert abs(r["entropy_change"]) < 1e-12          # entropy conservative + relaxation
+        assert 0 < r["mass_error"] < 1e-2 and 0 < r["energy_error"] < 1e-2
+        assert r["t"] >= 0.5
+    assert rows[1]["mass_error"] < rows[0]["mass_error"]
