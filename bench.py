@@ -51,6 +51,8 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the built-in launch shapes (skip sbp_autotune during setup)")
+    ap.add_argument("--only-ns", action="store_true",
+                    help="run only the Navier-Stokes rows and print them (for counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -259,28 +261,38 @@ def cpu_baseline(desc, ps, budget_s=20.0):
             uu = np.moveaxis(wl.conservative(rho, V, pr), 0, 1)
             u = np.zeros((m.ne, m.n_c, m.n_p))
             u[need] = uu
-            sch = OracleScheme(m, ph.Gas())
             for e in need:
                 m.geometry(e)          # setup excluded from the timing (as in the paper)
-            t0 = time.perf_counter()
-            n = 0
-            while True:
-                for e in els:
-                    sch.element(u, int(e))
-                    n += 1
-                if time.perf_counter() - t0 > budget_s / len(ps):
-                    break
-            dt = time.perf_counter() - t0
-            per_p[p] = dict(sec_per_elem=dt / n, elems=n)
+            per_p[p] = {}
+            for form, share in (("split", 0.75), ("hadamard", 0.25)):
+                sch = OracleScheme(m, ph.Gas(), form=form)
+                t0 = time.perf_counter()
+                n = 0
+                while True:
+                    for e in els:
+                        sch.element(u, int(e))
+                        n += 1
+                    if time.perf_counter() - t0 > share * budget_s / len(ps):
+                        break
+                dt = time.perf_counter() - t0
+                per_p[p][form] = dict(sec_per_elem=dt / n, elems=n)
     ne = len(desc["elem_vert"])
     from oracle.operators import reference_operator
-    tot_time = sum(per_p[p]["sec_per_elem"] * ne for p in ps)
+    tot_time = sum(per_p[p]["split"]["sec_per_elem"] * ne for p in ps)
     dofs = sum(ne * reference_operator(2, p)["n_p"] for p in ps)
     return dict(value=dofs / tot_time, unit="elem-DOF/s", cores=1, kind="oracle",
                 sample=f"oracle (numpy, 1 thread) entropy-split FP64 residual of "
-                       f"{', '.join(str(per_p[p]['elems']) for p in ps)} element evaluations "
+                       f"{', '.join(str(per_p[p]['split']['elems']) for p in ps)} element evaluations "
                        f"(64 distinct elements per p, vortex state) on the 32768-triangle curved mesh, "
-                       f"p={list(ps)}; per-element time scaled to the full mesh per step")
+                       f"p={list(ps)}; per-element time scaled to the full mesh per step",
+                hadamard_over_split={p: per_p[p]["hadamard"]["sec_per_elem"] / per_p[p]["split"]["sec_per_elem"]
+                                     for p in ps},
+                hadamard_note="the oracle's Hadamard-form residual on the same elements, one thread.  "
+                              "The oracle is a plain reference, not a fast CPU code: its Hadamard form is "
+                              "vectorised over node pairs, its split form builds and inverts dense A~ "
+                              "matrices per node, so this ratio reflects the oracle, not the method (the "
+                              "paper's serial CPU code reports about 2x at p = 3 and 3x at p = 4 for its "
+                              "Ismail-Roe comparator; the GPU ratio is breakdown.tri_p*.hadamard_over_split)")
 
 
 def main():
@@ -292,6 +304,9 @@ def main():
     import torch
     from paper_2305_07181_amd import sbp, workloads as wl
     assert torch.cuda.is_available()
+    if args.only_ns:
+        print(json.dumps({"ns_tgv_82944_p3": ns_rows(args)}))
+        return
     ps = (1, 2, 3, 4)
     desc = wl.vortex2d_mesh(128, warp=0.05)
     ne = len(desc["elem_vert"])
