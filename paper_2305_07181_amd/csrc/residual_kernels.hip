@@ -464,7 +464,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_split3v(KArgs<T> A) {
         const T *v = nd + e * NDS + j * 20;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          V[c] += s0 * v[c] + s1 * v[5 + c] + s2 * v[10 + c];
+          V[c] += s0 * v[c];  // one FMA per product
+          V[c] += s1 * v[5 + c];
+          V[c] += s2 * v[10 + c];
           G[0][c] += s0 * v[15 + c];
           G[1][c] += s1 * v[15 + c];
           G[2][c] += s2 * v[15 + c];
@@ -718,7 +720,10 @@ struct Split2 {
           const T c1 = s0 * (lam[q][2] + v[14]) + s1 * (lam[q][3] + v[15]);
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
-            V[q][c] += c0 * v[c] + c1 * v[4 + c];
+            // one FMA per product (a sum of products added at once costs
+            // a multiply, an FMA and an add)
+            V[q][c] += c0 * v[c];
+            V[q][c] += c1 * v[4 + c];
             X0[q][c] += c0 * v[8 + c];
             X1[q][c] += c1 * v[8 + c];
           }

@@ -151,7 +151,9 @@ __global__ __launch_bounds__(kT, W) void k_vjp3v(KArgs<double> A) {
           Z[0][c] += s0 * v[c];
           Z[1][c] += s1 * v[c];
           Z[2][c] += s2 * v[c];
-          Vs[c] += s0 * v[5 + c] + s1 * v[10 + c] + s2 * v[15 + c];
+          Vs[c] += s0 * v[5 + c];  // one FMA per product
+          Vs[c] += s1 * v[10 + c];
+          Vs[c] += s2 * v[15 + c];
           Gw[0][c] += s0 * v[20 + c];
           Gw[1][c] += s1 * v[20 + c];
           Gw[2][c] += s2 * v[20 + c];
@@ -329,7 +331,8 @@ struct Vjp2 {
         for (int c = 0; c < NC; ++c) {
           Z0[c] += c0 * v[c];
           Z1[c] += c1 * v[c];
-          Vs[c] += c0 * v[4 + c] + c1 * v[8 + c];
+          Vs[c] += c0 * v[4 + c];  // one FMA per product
+          Vs[c] += c1 * v[8 + c];
           X0[c] += c0 * v[12 + c];
           X1[c] += c1 * v[12 + c];
         }
