@@ -1,27 +1,30 @@
 // Residual kernels of the entropy-split SBP-SAT scheme for gfx950 (CDNA4).
 //
-// One workgroup (4 wave64) handles a tile of EB elements of one degree class:
-//   1. stage u (and the element geometry) in LDS;
-//   2. pointwise: primitives, entropy variables w, fluxes f^(i) and their
-//      contravariant combinations, written as the B operand of the operator
-//      contractions (columns = element x component);
-//   3. MFMA contractions with the reference operators shared by all elements
-//      of the class (v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4): the volume
-//      operator M = c_b Q + Q^T (Sec. 6.2, eq. weak form split) and the
-//      derivative operators (D or Q) acting on w;
-//   4. per node: H^-1 (volume) - c_b sum_i A~_i D_xi w with A~_i applied as a
+// Every kernel is persistent: a workgroup (4 wave64) loops over tiles of
+// elements of one degree class.  Per tile:
+//   1. per node: primitives, entropy variables w, fluxes f^(i) (and their
+//      contravariant combinations), written to LDS rows;
+//   2. the volume term of Sec. 6.2, eq. weak form split, through the skew
+//      parts S_l = Q_l - E_l/2 of the reference operators shared by the class:
+//      - Euler terms (k_split2, k_split3v): per-node-pair sums on the vector
+//        ALUs, one lane per node row (2D: R rows per lane), S_l in LDS or
+//        read through the caches;
+//      - Navier-Stokes terms (k_split3<..., true>): MFMA contractions with
+//        columns = element x component (v_mfma_f64_16x16x4 / _f32_);
+//   3. per node: H^-1 (volume) - c_b sum_i A~_i D_xi w with A~_i applied as a
 //      directional derivative, then at facet nodes the entropy-conservative
 //      SAT with the Sjogreen-Yee two-point flux (Sec. 4, eq. sats inv) and the
 //      optional matrix interface dissipation (Sec. 4.5), the neighbour state
 //      gathered through the precomputed face-node map; write r once;
-//   5. FP64 partial of sum w^T H r per workgroup (deterministic).
+//   4. FP64 partial of sum w^T H r per workgroup (deterministic).
 // Each facet node belongs to exactly one facet, so every node's residual is
 // written by exactly one thread (no atomics, no second pass).
 //
-// The Hadamard-form comparator (Sec. 6.2, eq. weak form 2pt) evaluates every
-// node pair of an element once (upper triangle of S), stores the pair fluxes
-// in LDS and forms row sums in a fixed order (deterministic), then shares the
-// facet epilogue.
+// The Hadamard-form comparator (Sec. 6.2, eq. weak form 2pt, k_hadamard)
+// gives each lane one node row and sums the two-point fluxes of that row in a
+// fixed order (each pair evaluated from both of its rows), then shares the
+// facet epilogue.  In the hybrid scheme (Sec. 4.4) each kernel skips the
+// elements flagged for the other volume form.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
