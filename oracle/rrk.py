@@ -28,8 +28,10 @@ B = (1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0)
 C_STAGE = (0.0, 0.5, 0.5, 1.0)
 
 
-def rk4_direction(scheme, u, dt):
-    """Return (d, e) for one RK4 step from u."""
+def rk4_direction(scheme, u, dt, source=None, t=0.0):
+    """Return (d, e) for one RK4 step from u.  source(t) -> [ne, n_c, n_p]
+    (a manufactured-solution source, Sec. 7) is added to every stage
+    residual at the stage time t + c_i dt when given."""
     gas = scheme.gas
     H = scheme.mesh.H_all()
     d = np.zeros_like(u)
@@ -39,6 +41,8 @@ def rk4_direction(scheme, u, dt):
         if i > 0:
             y = u + C_STAGE[i] * dt * r
         r = scheme(y)
+        if source is not None:
+            r = r + source(t + C_STAGE[i] * dt)
         w = np.stack([ph.entropy_vars(y[k], gas) for k in range(len(y))], 0)
         e = e + dt * B[i] * np.sum(H[:, None, :] * w * r)
         d = d + dt * B[i] * r
@@ -75,8 +79,8 @@ def solve_gamma(scheme, u, d, e, lo=0.5, hi=1.5, max_iter=200):
     return 0.5 * (lo + hi)
 
 
-def rrk4_step(scheme, u, dt):
+def rrk4_step(scheme, u, dt, source=None, t=0.0):
     """One relaxation RK4 step; returns (u_new, gamma, d, e)."""
-    d, e = rk4_direction(scheme, u, dt)
+    d, e = rk4_direction(scheme, u, dt, source, t)
     gamma = solve_gamma(scheme, u, d, e)
     return u + gamma * d, gamma, d, e

@@ -271,6 +271,35 @@ def paper_vortex2d(x, t=0.0, alpha=3.0, center=(5.0, 0.0), period=(20.0, 10.0), 
     return rho, V, p
 
 
+def mms_mesh2d(n: int) -> dict:
+    """Grid of the paper's manufactured-solution study (Sec. 7): the periodic
+    box [-1,1]^2 in n x n squares, each cut into two triangles, with the
+    quadratic geometry nodes moved by the curving map of that study,
+        x_i = x^_i + 1/8 cos(pi/2 x^_i) prod_{j != i} sin(pi x^_j),
+    which fixes every point of the box edges (conforming and periodic)."""
+    desc = periodic_tri_mesh(n, n, 2.0, 2.0)
+    vert = desc["vert_xyz"] - 1.0
+    v = vert[desc["elem_vert"]]                            # [ne,3,2]
+    mids = np.stack([0.5 * (v[:, 0] + v[:, 1]), 0.5 * (v[:, 1] + v[:, 2]),
+                     0.5 * (v[:, 2] + v[:, 0])], 1)
+    g = np.concatenate([v, mids], 1)                       # [ne,6,2]
+    x1 = g[..., 0] + 0.125 * np.cos(0.5 * np.pi * g[..., 0]) * np.sin(np.pi * g[..., 1])
+    x2 = g[..., 1] + 0.125 * np.cos(0.5 * np.pi * g[..., 1]) * np.sin(np.pi * g[..., 0])
+    desc["vert_xyz"] = vert
+    desc["p_geom"] = 2
+    desc["geom_nodes"] = np.ascontiguousarray(np.stack([x1, x2], -1))
+    return desc
+
+
+def mms_mesh3d(n: int) -> dict:
+    """The periodic box [-1,1]^3 of the manufactured-solution study in n^3
+    cubes of six affine tetrahedra each (the study's curving map is not
+    applied: tetrahedra are affine here)."""
+    desc = periodic_tet_mesh(n, 2.0)
+    desc["vert_xyz"] = desc["vert_xyz"] - 1.0
+    return desc
+
+
 def tgv_mesh(n: int) -> dict:
     """[0, 2 pi]^3, n^3 hexes x 6 tetrahedra (n=32: 196608; n=24: 82944)."""
     return periodic_tet_mesh(n, 2 * math.pi)
