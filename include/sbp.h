@@ -152,6 +152,35 @@ int sbp_rrk_step(sbp_mesh *mesh, void *u_dev, double dt, double cfl,
  * returns SBP_ENOTSUP.  The FP64 entropy rate sums both launches. */
 int sbp_set_volume_form(sbp_mesh *mesh, const uint8_t *form_dev);
 
+/* Source terms of the manufactured-solution study (Sec. 7, manufactured
+ * solution for the compressible Navier-Stokes equations): the fields
+ *   rho = rho0 + a sin(pi (sum_i x_i - c t)),  V_i = V0 (every i),
+ *   p = (gamma - 1) (rho^2 - rho |V|^2 / 2)
+ * solve du/dt = r(u) + S(x, t) with S = du/dt + div F^I - div F^V of the
+ * fields (the heat flux enters when phys.viscous and phys.heat_flux; the
+ * stress vanishes for the constant velocity).
+ * kind SBP_SOURCE_NS_MMS: every later sbp_residual adds S at the handle's
+ * time (sbp_set_time), and sbp_rrk_step at each RK stage time t + c_i dt
+ * (the entropy rates then include w^T H S).  params = {rho0, a, c, V0}
+ * (host, read during the call), or NULL for the paper's {2, 0.1, 0.6, 1}.
+ * kind SBP_SOURCE_NONE removes the source.  SBP_EINVAL for an unknown kind,
+ * non-finite parameters, rho0 - |a| <= d V0^2 / 2 (the pressure would not
+ * stay positive) or a box side that is not a multiple of 2 (the fields have
+ * period 2 in every x_i). */
+enum { SBP_SOURCE_NONE = 0, SBP_SOURCE_NS_MMS = 1 };
+int sbp_set_source(sbp_mesh *mesh, int32_t kind, const double *params);
+
+/* u_dev (FP64, state layout) = the manufactured fields of the source set by
+ * sbp_set_source at the SBP nodes at time t.  SBP_EINVAL when no source is
+ * set.  Asynchronous on hip_stream. */
+int sbp_source_state(sbp_mesh *mesh, double t, void *u_dev, void *hip_stream);
+
+/* out_host[c] = sum_k (u_k - u*_k)^T H_k (u_k - u*_k) for each component c
+ * (n_c values), u* the manufactured fields at time t (the squared discrete
+ * L2 error of the study).  FP64; synchronises hip_stream.  SBP_EINVAL when
+ * no source is set. */
+int sbp_source_error(sbp_mesh *mesh, const void *u_dev, double t, double *out_host, void *hip_stream);
+
 /* enable != 0 (default): sbp_rrk_step replays its captured stage graph;
  * enable == 0: the stages are launched one by one (for callers that capture
  * the stream themselves).  Not in the paper.  SBP_EINVAL for a null handle. */

@@ -93,6 +93,9 @@ struct sbp_mesh {
   double *d_y = nullptr, *d_d = nullptr;
   void *d_r = nullptr;        // RK stage residual
   double t = 0.0;
+  double period[3] = {0.0, 0.0, 0.0};
+  int src_kind = 0;           // SBP_SOURCE_*: source added to every residual
+  sbp::SrcArgs src{};
   // RRK stages captured once as a HIP graph (per state pointer), replayed on
   // the caller's stream; captured on a private stream of default priority
   int use_graphs = 1;
@@ -106,6 +109,9 @@ namespace {
 constexpr int SC_ENT = 0;     // 4 stage entropy rates
 constexpr int SC_RED = 8;     // reduction outputs (up to 8)
 constexpr int SC_DT = 16;     // time step of the current RRK step
+constexpr int SC_T = 17;      // time at the start of the current RRK step
+constexpr int SC_TR = 18;     // time of a residual call (the handle's time)
+constexpr int SC_SRC = 20;    // entropy rates of the residual and of the source (2)
 constexpr int SC_TOTAL = 32;
 
 // --------------------------------------------------------------------------
@@ -486,6 +492,7 @@ sbp::NodeArgs node_args(const sbp_mesh *M, const DegreeClass &c, const double *u
   A.gamma = M->phys.gamma;
   A.beta = M->phys.beta;
   A.pstride = M->node_total;
+  A.xyz = M->d_node_xyz;
   return A;
 }
 
@@ -517,7 +524,7 @@ sbp::KArgs<T> kargs(sbp_mesh *M, DegreeClass &c, const double *u, void *r, const
   return A;
 }
 
-int residual_impl(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStream_t s) {
+int residual_core(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStream_t s) {
   const sbp_physics &ph = M->phys;
   if (ph.viscous) {
     for (auto &c : M->cls) {
@@ -621,6 +628,31 @@ int residual_impl(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStr
   return SBP_OK;
 }
 
+// The residual plus the manufactured source when one is set (Sec. 7), at
+// time *t0 + c * *dt (the RK stage times; t0 null: the handle's time).  The
+// entropy rate then sums w^T H r of both parts.
+int residual_impl(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStream_t s,
+                  const double *t0 = nullptr, const double *dt = nullptr, double c = 0.0) {
+  if (!M->src_kind) return residual_core(M, u, r, ent_dev, s);
+  int rc;
+  if ((rc = residual_core(M, u, r, ent_dev ? M->d_scal + SC_SRC : nullptr, s))) return rc;
+  if (!t0) {
+    HIPCHK(sbp::launch_scalar_set(M->d_scal + SC_TR, M->t, s));
+    t0 = M->d_scal + SC_TR;
+    dt = nullptr;
+  }
+  const int f32 = M->phys.precision == SBP_FP32;
+  for (auto &cl : M->cls) {
+    sbp::NodeArgs A = node_args(M, cl, u, nullptr);
+    HIPCHK(sbp::launch_source_add(A, M->src, r, f32, t0, dt, c, ent_dev ? M->d_npart + cl.node_off_blk : nullptr, s));
+  }
+  if (ent_dev) {
+    HIPCHK(sbp::launch_reduce(M->d_npart, M->node_total, 1, 0, M->d_scal + SC_SRC + 1, s));
+    HIPCHK(sbp::launch_reduce(M->d_scal + SC_SRC, 2, 1, 0, ent_dev, s));
+  }
+  return SBP_OK;
+}
+
 // Sum node-kernel partials of all classes; nv values.  Returns host values.
 int reduce_nodes(sbp_mesh *M, int nv, int op, double *host, hipStream_t s) {
   HIPCHK(sbp::launch_reduce(M->d_npart, M->node_total, nv, op, M->d_scal + SC_RED, s));
@@ -677,7 +709,7 @@ int rk_stages(sbp_mesh *M, const double *u, hipStream_t s) {
       HIPCHK(sbp::launch_axpy(M->d_y, u, M->d_r, f32, cst[i], n, s, dtp));
       y = M->d_y;
     }
-    if ((rc = residual_impl(M, y, M->d_r, M->d_scal + SC_ENT + i, s))) return rc;
+    if ((rc = residual_impl(M, y, M->d_r, M->d_scal + SC_ENT + i, s, M->d_scal + SC_T, dtp, cst[i]))) return rc;
     if (i == 0)
       HIPCHK(sbp::launch_axpy(M->d_d, nullptr, M->d_r, f32, b[i], n, s, dtp));
     else
@@ -956,6 +988,7 @@ int sbp_setup_mesh(const sbp_mesh_desc *desc, const sbp_physics *phys, void *hip
     sbp_destroy_mesh(M);
     return rc;
   }
+  for (int i = 0; i < desc->dim; ++i) M->period[i] = desc->period[i];
   *out = M;
   return SBP_OK;
 }
@@ -1078,6 +1111,61 @@ int sbp_set_volume_form(sbp_mesh *M, const uint8_t *form_dev) {
   return SBP_OK;
 }
 
+int sbp_set_source(sbp_mesh *M, int32_t kind, const double *params) {
+  if (!M) return fail(SBP_EINVAL, "null handle");
+  if (kind != SBP_SOURCE_NONE && kind != SBP_SOURCE_NS_MMS) return fail(SBP_EINVAL, "unknown source kind");
+  if (kind == SBP_SOURCE_NS_MMS) {
+    const double def[4] = {2.0, 0.1, 0.6, 1.0};
+    const double *q = params ? params : def;
+    for (int k = 0; k < 4; ++k)
+      if (!std::isfinite(q[k])) return fail(SBP_EINVAL, "source parameters must be finite");
+    if (!(q[0] - std::fabs(q[1]) > 0.0)) return fail(SBP_EINVAL, "need rho0 > |a|");
+    const double g = M->phys.gamma;
+    if (!(q[0] - std::fabs(q[1]) > 0.5 * M->dim * q[3] * q[3])) return fail(SBP_EINVAL, "need rho0 - |a| > d V0^2 / 2 (p > 0)");
+    for (int i = 0; i < M->dim; ++i) {
+      const double k = M->period[i] / 2.0;
+      if (!(std::fabs(k - std::round(k)) <= 1e-12 * k) || k < 0.5)
+        return fail(SBP_EINVAL, "the manufactured fields have period 2: box sides must be multiples of 2");
+    }
+    M->src.rho0 = q[0];
+    M->src.a = q[1];
+    M->src.c = q[2];
+    M->src.V0 = q[3];
+    const sbp_physics &ph = M->phys;
+    // kappa (gamma-1)/R with kappa = mu c_p / Pr, c_p = gamma R / (gamma-1)
+    M->src.heat = (ph.viscous && ph.heat_flux) ? ph.mu * g / ph.Pr : 0.0;
+  }
+  M->src_kind = kind;
+  // the captured RK stages hold the previous launches
+  if (M->rk_exec) {
+    (void)hipGraphExecDestroy(M->rk_exec);
+    M->rk_exec = nullptr;
+    M->rk_u = nullptr;
+  }
+  return SBP_OK;
+}
+
+int sbp_source_state(sbp_mesh *M, double t, void *u_dev, void *stream) {
+  if (!M || !u_dev) return fail(SBP_EINVAL, "null argument");
+  if (!M->src_kind) return fail(SBP_EINVAL, "no source set");
+  for (auto &c : M->cls) {
+    sbp::NodeArgs A = node_args(M, c, nullptr, nullptr);
+    HIPCHK(sbp::launch_source_state(A, M->src, t, (double *)u_dev, (hipStream_t)stream));
+  }
+  return SBP_OK;
+}
+
+int sbp_source_error(sbp_mesh *M, const void *u_dev, double t, double *out_host, void *stream) {
+  if (!M || !u_dev || !out_host) return fail(SBP_EINVAL, "null argument");
+  if (!M->src_kind) return fail(SBP_EINVAL, "no source set");
+  hipStream_t s = (hipStream_t)stream;
+  for (auto &c : M->cls) {
+    sbp::NodeArgs A = node_args(M, c, (const double *)u_dev, nullptr);
+    HIPCHK(sbp::launch_source_error(A, M->src, t, M->d_npart + c.node_off_blk, s));
+  }
+  return reduce_nodes(M, M->nc, 0, out_host, s);
+}
+
 int sbp_get_launch_shape(sbp_mesh *M, int32_t kind, int32_t p, int32_t *variant, int32_t *grid) {
   if (!M || (kind != 0 && kind != 1)) return fail(SBP_EINVAL, "bad handle or kind");
   int nvar = 0, *g = nullptr;
@@ -1135,6 +1223,7 @@ int sbp_rrk_step(sbp_mesh *M, void *u_dev, double dt, double cfl, sbp_rrk_report
   }
   const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
   HIPCHK(sbp::launch_scalar_set(M->d_scal + SC_DT, dt, s));
+  HIPCHK(sbp::launch_scalar_set(M->d_scal + SC_T, M->t, s));
   if ((rc = rk_stages_graph(M, u, s))) return rc;
   double ent[4];
   HIPCHK(hipMemcpyAsync(ent, M->d_scal + SC_ENT, sizeof(ent), hipMemcpyDeviceToHost, s));

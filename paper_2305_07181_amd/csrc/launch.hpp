@@ -58,6 +58,16 @@ struct NodeArgs {
   int n_elem, np, dim;
   double gamma, beta;
   int pstride;         // stride between the partial-sum rows of one launch
+  const double *xyz;   // node coordinates, element e at uoff[e]/n_c*dim, [dim][np]
+};
+
+// Manufactured solution of the Navier-Stokes study (Sec. 7):
+// rho = rho0 + a sin(pi (sum_i x_i - c t)), V_i = V0,
+// p = (gamma-1)(rho^2 - rho |V|^2/2); heat = kappa (gamma-1)/R when the heat
+// flux is part of the equations (else 0).
+struct SrcArgs {
+  double rho0, a, c, V0;
+  double heat;
 };
 constexpr int kNodeThreads = 256;
 inline int node_blocks(int n_elem, int np) { return (n_elem * np + kNodeThreads - 1) / kNodeThreads; }
@@ -69,6 +79,15 @@ hipError_t launch_entropy_gap(const NodeArgs &A, double g, double *part, hipStre
 hipError_t launch_diagnostics(const NodeArgs &A, double *part, hipStream_t s);
 // part[b] = min over the block's elements of hmin / max_nodes(|V| + a)
 hipError_t launch_dt(const NodeArgs &A, double *part, hipStream_t s);
+// r += S(x, t) at every node (S the manufactured source; r double or float),
+// t = *t0 + c * *dt (dt null: t = *t0); part (may be null): per workgroup
+// sum_nodes H w(u).S in FP64
+hipError_t launch_source_add(const NodeArgs &A, const SrcArgs &P, void *r, int r_f32, const double *t0,
+                             const double *dt, double c, double *part, hipStream_t s);
+// u = the manufactured state at time t (FP64)
+hipError_t launch_source_state(const NodeArgs &A, const SrcArgs &P, double t, double *u, hipStream_t s);
+// part[c*pstride + b] = sum_nodes H (u_c - u*_c)^2 at time t
+hipError_t launch_source_error(const NodeArgs &A, const SrcArgs &P, double t, double *part, hipStream_t s);
 // out[v] = reduction over part[v*nb + b], b < nb (op 0: sum, 1: min); fixed order.
 hipError_t launch_reduce(const double *part, int nb, int nv, int op, double *out, hipStream_t s);
 // y = x + a s z (x null: y = a s z), z double or float (z_f32), n doubles,

@@ -1,5 +1,6 @@
 // Time-integration kernels: relaxation RK4 stages, FP64 entropy sums, the
-// relaxation root function, the time step and diagnostics (Sec. 6.1, 7.1).
+// relaxation root function, the time step and diagnostics (Sec. 6.1, 7.1),
+// and the manufactured solution and source of the Navier-Stokes study (Sec. 7).
 //
 // All reductions are two-stage and deterministic: every workgroup writes one
 // partial per quantity, a single workgroup combines the partials in a fixed
@@ -159,6 +160,116 @@ __global__ __launch_bounds__(kT) void k_dt(NodeArgs A, double *part) {
   if (threadIdx.x == 0) part[blockIdx.x] = m;
 }
 
+// Manufactured solution of the Navier-Stokes study (Sec. 7) at one node:
+// with xi = pi (sum_i x_i - c t), g = d rho/dx_i = a pi cos xi (the same
+// for every i), d rho/dt = -c g and, for the constant velocity, the total
+// energy e = rho^2; the source du/dt + div F^I - div F^V is
+//   mass      (d V0 - c) g
+//   momentum  (V0 (d V0 - c) + dp/drho) g,   dp/drho = (gamma-1)(2 rho - d V0^2/2)
+//   energy    (d V0 (2 rho + dp/drho) - 2 c rho) g + heat d a pi^2 sin xi
+// (the stress vanishes; the heat flux kappa dT/dx_i with T = p/(rho R)
+// linear in rho gives the last term).
+template <int D>
+__device__ __forceinline__ void mms_node(const NodeArgs &A, const SrcArgs &P, int e, int j, double t, double *u,
+                                         double *S) {
+  const double *x = A.xyz + (size_t)(A.uoff[e] / (D + 2)) * D + j;
+  double sx = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) sx += x[i * A.np];
+  const double xi = M_PI * (sx - P.c * t);
+  double sn, cs;
+  sincos(xi, &sn, &cs);
+  const double rho = P.rho0 + P.a * sn;
+  const double q2 = D * P.V0 * P.V0;
+  if (u) {
+    u[0] = rho;
+#pragma unroll
+    for (int i = 0; i < D; ++i) u[1 + i] = rho * P.V0;
+    u[D + 1] = rho * rho;
+  }
+  if (S) {
+    const double g = P.a * M_PI * cs;
+    const double dp = (A.gamma - 1.0) * (2.0 * rho - 0.5 * q2);
+    const double dv = D * P.V0 - P.c;
+    S[0] = dv * g;
+#pragma unroll
+    for (int i = 0; i < D; ++i) S[1 + i] = (P.V0 * dv + dp) * g;
+    S[D + 1] = (D * P.V0 * (2.0 * rho + dp) - 2.0 * P.c * rho) * g + P.heat * D * P.a * M_PI * M_PI * sn;
+  }
+}
+
+template <int D, typename R>
+__global__ __launch_bounds__(kT) void k_source_add(NodeArgs A, SrcArgs P, R *r, const double *t0, const double *dt,
+                                                    double c, double *part) {
+  constexpr int NC = D + 2;
+  __shared__ double red[kT / 64];
+  const int x = blockIdx.x * kT + threadIdx.x;
+  double v = 0.0;
+  if (x < A.n_elem * A.np) {
+    const int e = x / A.np, j = x % A.np;
+    const double t = dt ? t0[0] + c * dt[0] : t0[0];
+    double S[NC];
+    mms_node<D>(A, P, e, j, t, nullptr, S);
+    const int base = A.uoff[e] + j;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) r[base + k * A.np] = (R)((double)r[base + k * A.np] + S[k]);
+    if (part) {
+      double u0[NC], w[NC], s;
+#pragma unroll
+      for (int k = 0; k < NC; ++k) u0[k] = A.u[base + k * A.np];
+      ent_state<D>(u0, A.gamma, A.beta, &s, w);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) v += w[k] * S[k];
+      v *= A.Hn[x];
+    }
+  }
+  if (part) {
+    const double sum = block_reduce_sum(v, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = sum;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kT) void k_source_state(NodeArgs A, SrcArgs P, double t, double *u) {
+  constexpr int NC = D + 2;
+  const int x = blockIdx.x * kT + threadIdx.x;
+  if (x < A.n_elem * A.np) {
+    const int e = x / A.np, j = x % A.np;
+    double ue[NC];
+    mms_node<D>(A, P, e, j, t, ue, nullptr);
+    const int base = A.uoff[e] + j;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) u[base + k * A.np] = ue[k];
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kT) void k_source_error(NodeArgs A, SrcArgs P, double t, double *part) {
+  constexpr int NC = D + 2;
+  __shared__ double red[kT / 64];
+  const int x = blockIdx.x * kT + threadIdx.x;
+  double v[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) v[k] = 0.0;
+  if (x < A.n_elem * A.np) {
+    const int e = x / A.np, j = x % A.np;
+    double ue[NC];
+    mms_node<D>(A, P, e, j, t, ue, nullptr);
+    const int base = A.uoff[e] + j;
+    const double H = A.Hn[x];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const double d = A.u[base + k * A.np] - ue[k];
+      v[k] = H * d * d;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const double sum = block_reduce_sum(v[k], red);
+    if (threadIdx.x == 0) part[k * A.pstride + blockIdx.x] = sum;
+  }
+}
+
 __global__ __launch_bounds__(kT) void k_reduce(const double *part, int nb, int op, double *out) {
   __shared__ double red[kT / 64];
   const int v = blockIdx.x;
@@ -232,6 +343,41 @@ hipError_t launch_dt(const NodeArgs &A, double *part, hipStream_t s) {
     hipLaunchKernelGGL(k_dt<2>, dim3(nb), dim3(kT), 0, s, A, part);
   else
     hipLaunchKernelGGL(k_dt<3>, dim3(nb), dim3(kT), 0, s, A, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_source_add(const NodeArgs &A, const SrcArgs &P, void *r, int r_f32, const double *t0,
+                             const double *dt, double c, double *part, hipStream_t s) {
+  const int nb = node_blocks(A.n_elem, A.np);
+  if (A.dim == 2) {
+    if (r_f32)
+      hipLaunchKernelGGL((k_source_add<2, float>), dim3(nb), dim3(kT), 0, s, A, P, (float *)r, t0, dt, c, part);
+    else
+      hipLaunchKernelGGL((k_source_add<2, double>), dim3(nb), dim3(kT), 0, s, A, P, (double *)r, t0, dt, c, part);
+  } else {
+    if (r_f32)
+      hipLaunchKernelGGL((k_source_add<3, float>), dim3(nb), dim3(kT), 0, s, A, P, (float *)r, t0, dt, c, part);
+    else
+      hipLaunchKernelGGL((k_source_add<3, double>), dim3(nb), dim3(kT), 0, s, A, P, (double *)r, t0, dt, c, part);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_source_state(const NodeArgs &A, const SrcArgs &P, double t, double *u, hipStream_t s) {
+  const int nb = node_blocks(A.n_elem, A.np);
+  if (A.dim == 2)
+    hipLaunchKernelGGL(k_source_state<2>, dim3(nb), dim3(kT), 0, s, A, P, t, u);
+  else
+    hipLaunchKernelGGL(k_source_state<3>, dim3(nb), dim3(kT), 0, s, A, P, t, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_source_error(const NodeArgs &A, const SrcArgs &P, double t, double *part, hipStream_t s) {
+  const int nb = node_blocks(A.n_elem, A.np);
+  if (A.dim == 2)
+    hipLaunchKernelGGL(k_source_error<2>, dim3(nb), dim3(kT), 0, s, A, P, t, part);
+  else
+    hipLaunchKernelGGL(k_source_error<3>, dim3(nb), dim3(kT), 0, s, A, P, t, part);
   return hipGetLastError();
 }
 

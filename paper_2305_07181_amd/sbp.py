@@ -20,11 +20,13 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsbp.so"
 SBP_OK, SBP_EINVAL, SBP_ENOMEM, SBP_EDEVICE, SBP_ENOTSUP, SBP_ENONPHYS, SBP_ERRK = 0, -1, -2, -3, -4, -5, -6
 FORM_SPLIT, FORM_HADAMARD = 0, 1
 FP64, FP32 = 0, 1
+SOURCE_NONE, SOURCE_NS_MMS = 0, 1
 
 SYMBOLS = ["sbp_setup_mesh", "sbp_mesh_info", "sbp_residual", "sbp_residual_vjp", "sbp_rrk_step",
            "sbp_diagnostics", "sbp_check_device", "sbp_set_time", "sbp_destroy_mesh",
            "sbp_last_error", "sbp_reference_operator", "sbp_use_graphs", "sbp_autotune",
-           "sbp_get_launch_shape", "sbp_set_launch_shape", "sbp_set_volume_form"]
+           "sbp_get_launch_shape", "sbp_set_launch_shape", "sbp_set_volume_form", "sbp_set_source",
+           "sbp_source_state", "sbp_source_error"]
 
 
 class SbpError(RuntimeError):
@@ -87,6 +89,9 @@ def load_library(path: str = _LIB_PATH):
     lib.sbp_get_launch_shape.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.sbp_set_launch_shape.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
     lib.sbp_set_volume_form.argtypes = [P, P]
+    lib.sbp_set_source.argtypes = [P, C.c_int32, P]
+    lib.sbp_source_state.argtypes = [P, C.c_double, P, P]
+    lib.sbp_source_error.argtypes = [P, P, C.c_double, P, P]
     lib.sbp_destroy_mesh.argtypes = [P]
     lib.sbp_last_error.restype = C.c_char_p
     lib.sbp_reference_operator.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -281,6 +286,32 @@ class Mesh:
                 raise ValueError("flags must be a contiguous uint8 CUDA tensor of n_elem values")
         _check(_lib.sbp_set_volume_form(self._h, _ptr(flags) if flags is not None else None))
         self._form_flags = flags   # keep the borrowed array alive
+
+    def set_source(self, kind=None, params=None):
+        """Manufactured-solution source (sbp_set_source): kind SOURCE_NS_MMS
+        (default) with params (rho0, a, c, V0) or None for the paper's
+        values; kind SOURCE_NONE removes it."""
+        kind = SOURCE_NS_MMS if kind is None else int(kind)
+        par = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+        if par is not None and par.shape != (4,):
+            raise ValueError("params must hold rho0, a, c, V0")
+        _check(_lib.sbp_set_source(self._h, kind, _dp(par) if par is not None else None))
+
+    def source_state(self, t, u=None, stream=None):
+        """The manufactured fields at the nodes at time t (sbp_source_state)."""
+        import torch
+        if u is None:
+            u = torch.empty(self.state_shape(), dtype=torch.float64, device="cuda")
+        self._check_state(u)
+        _check(_lib.sbp_source_state(self._h, float(t), _ptr(u), _stream_ptr(stream)))
+        return u
+
+    def source_error(self, u, t, stream=None):
+        """Per component sum_k (u_k - u*)^T H_k (u_k - u*) at time t (sbp_source_error)."""
+        self._check_state(u)
+        out = np.zeros(self.n_c)
+        _check(_lib.sbp_source_error(self._h, _ptr(u), float(t), _dp(out), _stream_ptr(stream)))
+        return out
 
     def use_graphs(self, enable=True):
         _check(_lib.sbp_use_graphs(self._h, int(bool(enable))))

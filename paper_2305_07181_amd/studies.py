@@ -2,6 +2,8 @@
 
     python -m paper_2305_07181_amd.studies conservation [--ns 60 80 100 120]
         [--ps 1 2 3 4] [--tf 2.0] [--cfl 0.1]
+    python -m paper_2305_07181_amd.studies mms --dim 3 [--ns 6 9 12 15]
+        [--ps 1 2 3] [--tf 0.001] [--steps 1000] [--mu 0.01]
 
 Primary conservation (Sec. 4.3, Thm. conservation; the grid study of Sec. 7.3,
 Table conservation): the 2D isentropic vortex of the paper's studies on its
@@ -12,9 +14,23 @@ mass and energy errors
     |sum_k 1^T H_k u_k (t_f) - sum_k 1^T H_k u_k (0)| / |sum_k 1^T H_k u_k (0)|
 
 are reported with their rates between consecutive grids (the run stops at
-the first step that reaches t_f; its time is reported).  Every step and
-every sum runs in the library (sbp_rrk_step, sbp_diagnostics); this module
-only builds the inputs and prints one JSON line per grid.
+the first step that reaches t_f; its time is reported).
+
+Manufactured solution (Sec. 7, the grid study of the manufactured solution
+for the compressible Navier-Stokes equations, Table nse accuracy): the
+fields rho = 2 + 0.1 sin(pi (sum_i x_i - 0.6 t)), V_i = 1 on [-1,1]^d start
+from their nodal values and are advanced with the source (sbp_set_source)
+by `steps` relaxation RK4 steps of dt = t_f / steps; the discrete L2 error
+sqrt(sum_c sum_k (u - u*)_c^T H_k (u - u*)_c) at the final time is
+reported with its rates.  In 2D the grids are the curved triangles of the
+study and the equations the Euler equations (the viscous terms of this
+library cover tetrahedra); in 3D the Navier-Stokes equations (mu, Pr = 0.71,
+R = 1, heat flux on, no interface dissipation) on affine tetrahedra (the
+study's curving map is not applied in 3D).
+
+Every step and every sum runs in the library (sbp_rrk_step,
+sbp_diagnostics, sbp_source_state, sbp_source_error); this module only
+builds the inputs and prints one JSON line per grid.
 """
 from __future__ import annotations
 
@@ -68,15 +84,62 @@ def conservation_study(ns, ps, tf=2.0, cfl=0.1, emit=print):
     return rows
 
 
+def mms_run(dim: int, n: int, p: int, tf: float = 1e-3, steps: int = 1000, mu: float = 0.01) -> dict:
+    from . import sbp, workloads as wl
+    desc = wl.mms_mesh2d(n) if dim == 2 else wl.mms_mesh3d(n)
+    viscous = dim == 3
+    mesh = sbp.Mesh(desc, p, viscous=viscous, mu=mu if viscous else 0.0, Pr=0.71, R=1.0)
+    mesh.set_source()
+    mesh.set_time(0.0)
+    u = mesh.source_state(0.0)
+    e0 = mesh.source_error(u, 0.0)
+    dt = tf / steps
+    t0 = time.perf_counter()
+    rep = None
+    for _ in range(steps):
+        rep = mesh.rrk_step(u, dt=dt)
+    e = mesh.source_error(u, rep["t"])
+    mesh.check_device()
+    out = dict(dim=dim, n=n, p=p, n_elem=int(mesh.n_elem), equations="navier-stokes" if viscous else "euler",
+               steps=steps, t=rep["t"], seconds=time.perf_counter() - t0,
+               l2_error=math.sqrt(float(e.sum())), l2_error_rho=math.sqrt(float(e[0])),
+               initial_error=math.sqrt(float(e0.sum())))
+    mesh.close()
+    return out
+
+
+def mms_study(dim, ns, ps, tf=1e-3, steps=1000, mu=0.01, emit=print):
+    rows = []
+    for p in ps:
+        prev = None
+        for n in ns:
+            r = mms_run(dim, n, p, tf, steps, mu)
+            if prev is not None:
+                r["rate"] = math.log(prev["l2_error"] / r["l2_error"]) / math.log(n / prev["n"])
+            emit(json.dumps(r))
+            rows.append(r)
+            prev = r
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["conservation"])
-    ap.add_argument("--ns", type=int, nargs="+", default=[60, 80, 100, 120])
-    ap.add_argument("--ps", type=int, nargs="+", default=[1, 2, 3, 4])
-    ap.add_argument("--tf", type=float, default=2.0)
+    ap.add_argument("study", choices=["conservation", "mms"])
+    ap.add_argument("--ns", type=int, nargs="+")
+    ap.add_argument("--ps", type=int, nargs="+")
+    ap.add_argument("--tf", type=float)
     ap.add_argument("--cfl", type=float, default=0.1)
+    ap.add_argument("--dim", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--mu", type=float, default=0.01)
     a = ap.parse_args(argv)
-    conservation_study(a.ns, a.ps, a.tf, a.cfl, emit=lambda s: print(s, flush=True))
+    emit = lambda s: print(s, flush=True)
+    if a.study == "conservation":
+        conservation_study(a.ns or [60, 80, 100, 120], a.ps or [1, 2, 3, 4], a.tf or 2.0, a.cfl, emit=emit)
+    else:
+        ns = a.ns or ([20, 30, 40, 50] if a.dim == 2 else [6, 9, 12, 15])
+        ps = a.ps or ([1, 2, 3, 4] if a.dim == 2 else [1, 2, 3])
+        mms_study(a.dim, ns, ps, a.tf or 1e-3, a.steps, a.mu, emit=emit)
 
 
 if __name__ == "__main__":

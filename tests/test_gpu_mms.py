@@ -1,0 +1,216 @@
+"""Manufactured-solution source on the GPU (Sec. 7, manufactured solution for
+the compressible Navier-Stokes equations) against the oracle: the fields at
+the nodes, the residual plus source and its entropy rate, relaxation RK4
+steps with the source at the stage times, the discrete L2 error, and the
+argument checks of sbp_set_source."""
+import numpy as np
+import pytest
+
+from tests.gpu_common import rel_err_per_component, say, term_scale
+
+pytestmark = pytest.mark.gpu
+
+MU = 0.05  # larger than the study's 0.01 so the heat-flux term is well above rounding
+
+
+def _setup(dim, p, viscous, precision=0, diss=False):
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import sbp, workloads as wl
+    desc = wl.mms_mesh2d(3) if dim == 2 else wl.mms_mesh3d(2)
+    m = OracleMesh(desc, p)
+    gas = ph.Gas(mu=MU if viscous else 0.0, Pr=0.71, R=1.0)
+    sch = OracleScheme(m, gas, dissipation=diss, viscous=viscous)
+    mesh = sbp.Mesh(desc, p, viscous=viscous, mu=MU if viscous else 0.0, Pr=0.71, R=1.0,
+                    dissipation=diss, precision=precision)
+    mesh.set_source()
+    return m, gas, sch, mesh
+
+
+def _fields(m, gas, t, viscous):
+    from oracle import mms
+    xs = np.moveaxis(m.node_coords(), 1, 0)
+    ue = np.ascontiguousarray(np.moveaxis(mms.state(xs, t, gas), 0, 1))
+    S = np.ascontiguousarray(np.moveaxis(mms.source(xs, t, gas, viscous=viscous), 0, 1))
+    return ue, S
+
+
+def _perturbed(ue, seed):
+    rng = np.random.default_rng(seed)
+    return ue * (1.0 + 0.01 * rng.standard_normal(ue.shape))
+
+
+def _sum_err(r_gpu, rv, S, sch, u):
+    """Per component max |r_gpu - (rv + S)| over the scale of the terms summed
+    into it: the source, and the flux terms of the residual (term_scale).  The
+    fields are close to a uniform flow, so the residual is small against its
+    terms and near the fields it also cancels against the source."""
+    num = np.abs(r_gpu - (rv + S)).max(axis=(0, 2))
+    den = np.maximum(term_scale(sch, u, range(u.shape[0])), np.abs(S).max(axis=(0, 2)))
+    return num / den
+
+
+CASES = [(2, p, False) for p in (1, 2, 3, 4)] + [(3, p, True) for p in (1, 2, 3)] + [(3, 2, False)]
+
+
+@pytest.mark.parametrize("dim,p,viscous", CASES)
+def test_source_state_and_residual_vs_oracle(dim, p, viscous):
+    import torch
+    from oracle import physics as ph
+    say(f"[mms] dim={dim} p={p} viscous={viscous}")
+    m, gas, sch, mesh = _setup(dim, p, viscous)
+    t = 0.3
+    ue, S = _fields(m, gas, t, viscous)
+    ug = mesh.source_state(t).cpu().numpy().reshape(ue.shape)
+    es = rel_err_per_component(ug, ue)
+    assert (es <= 1e-14).all(), es
+    u = _perturbed(ue, 10 + p)
+    mesh.set_time(t)
+    r, er = mesh.residual(torch.from_numpy(u).cuda(), entropy_rate=True)
+    mesh.check_device()
+    rv = sch(u)
+    ro = rv + S
+    err = _sum_err(r.cpu().numpy(), rv, S, sch, u)
+    say("   state err", es.max(), "residual+source rel err per component", err.max())
+    assert (err <= 1e-12).all(), err
+    w = np.stack([ph.entropy_vars(u[k], gas) for k in range(m.ne)], 0)
+    H = m.H_all()
+    rate_o = float(np.sum(H[:, None, :] * w * ro))
+    scale = float(np.sum(H[:, None, :] * np.abs(w) * (np.abs(rv) + np.abs(S))))
+    assert abs(float(er.cpu()[0]) - rate_o) <= 1e-12 * scale
+    mesh.close()
+
+
+@pytest.mark.parametrize("dim,p,viscous", [(2, 3, False), (3, 2, True)])
+def test_source_alone_and_time_taken_from_handle(dim, p, viscous):
+    """The library's source alone (residual with the source minus the
+    residual after SOURCE_NONE) against the oracle's source, at the handle's
+    time (sbp_set_time) for two times; the plain residual against the
+    oracle's."""
+    import torch
+    from paper_2305_07181_amd import sbp
+    say(f"[mms] source alone dim={dim} p={p}")
+    m, gas, sch, mesh = _setup(dim, p, viscous)
+    ue, _ = _fields(m, gas, 0.0, viscous)
+    u = torch.from_numpy(_perturbed(ue, 3)).cuda()
+    rs = {}
+    for t in (0.0, 0.7):
+        mesh.set_time(t)
+        rs[t] = mesh.residual(u).cpu().numpy()
+    mesh.set_source(sbp.SOURCE_NONE)
+    r0 = mesh.residual(u).cpu().numpy()
+    mesh.check_device()
+    un = u.cpu().numpy()
+    assert (_sum_err(r0, sch(un), np.zeros_like(r0), sch, un) <= 1e-12).all()
+    for t in (0.0, 0.7):
+        _, S = _fields(m, gas, t, viscous)
+        den = np.maximum(np.abs(r0).max(axis=(0, 2)), np.abs(S).max(axis=(0, 2)))
+        err = np.abs((rs[t] - r0) - S).max(axis=(0, 2)) / den
+        say(f"   t={t}: source rel err per component {err.max():.2e}")
+        assert (err <= 1e-13).all(), err
+    mesh.close()
+
+
+@pytest.mark.parametrize("dim,p,viscous", [(2, 2, False), (2, 4, False), (3, 1, True), (3, 3, True)])
+def test_rrk_steps_with_source_vs_oracle(dim, p, viscous):
+    """Relaxation RK4 with the source at the stage times t + c_i dt (captured
+    stage graph), two steps of fixed dt, against the oracle's steps.  As for
+    the source-free steps: the GPU's gamma is a root of the oracle's
+    r(gamma) within its rounding (|r| <= 8 eps sum H|s|) and agrees within
+    the root's conditioning kappa = 8 eps sum H|s| / |r'(gamma)|; the states
+    agree within sum_n (1e-12 + kappa_n max|d_n| / max|u|) per component."""
+    import torch
+    from oracle import mms, rrk
+    from oracle import physics as ph
+    say(f"[mms] rrk dim={dim} p={p} viscous={viscous}")
+    eps = np.finfo(float).eps
+    m, gas, sch, mesh = _setup(dim, p, viscous)
+    H = m.H_all()
+    xs = np.moveaxis(m.node_coords(), 1, 0)
+    src = lambda tt: np.moveaxis(mms.source(xs, tt, gas, viscous=viscous), 0, 1)
+    t0 = 0.1
+    ue, _ = _fields(m, gas, t0, viscous)
+    u = _perturbed(ue, 21)
+    ud = torch.from_numpy(u).cuda()
+    mesh.set_time(t0)
+    uo, to = u.copy(), t0
+    dt = 2e-3
+    bound = 0.0
+    for step in range(2):
+        rep = mesh.rrk_step(ud, dt=dt)
+        d, e = rrk.rk4_direction(sch, uo, dt, src, to)
+        g = rrk.solve_gamma(sch, uo, d, e)
+        s_abs = np.sum(H * np.abs(ph.entropy(np.moveaxis(uo, 1, 0), gas)))
+        w1 = np.stack([ph.entropy_vars(uo[k] + g * d[k], gas) for k in range(m.ne)])
+        kappa = 8 * eps * s_abs / abs(np.sum(H[:, None, :] * w1 * d) - e)
+        r_at_gpu = rrk.entropy_gap(sch, uo, d, e, rep["gamma"], H)
+        say(f"   step {step}: gamma gpu {rep['gamma']:.15f} oracle {g:.15f} (kappa {kappa:.1e})")
+        assert abs(r_at_gpu) <= 8 * eps * s_abs, (r_at_gpu, 8 * eps * s_abs)
+        assert abs(rep["gamma"] - g) <= kappa
+        uo = uo + g * d
+        to += g * dt
+        assert abs(rep["t"] - to) <= kappa * dt + 1e-15
+        bound += 1e-12 + kappa * np.abs(d).max() / np.abs(uo).max()
+    err = rel_err_per_component(ud.cpu().numpy(), uo)
+    say("   state rel err", err.max(), "bound", bound)
+    assert (err <= bound).all(), err
+    mesh.check_device()
+    mesh.close()
+
+
+def test_source_error_vs_oracle():
+    import torch
+    from oracle import mms
+    say("[mms] L2 error")
+    for dim, p in ((2, 3), (3, 2)):
+        m, gas, _, mesh = _setup(dim, p, dim == 3)
+        t = 0.45
+        ue, _ = _fields(m, gas, t, dim == 3)
+        u = _perturbed(ue, 5)
+        e = mesh.source_error(torch.from_numpy(u).cuda(), t)
+        eo = mms.l2_error(u, m.node_coords(), t, m.H_all(), gas)
+        assert np.abs(e - eo).max() <= 1e-12 * np.abs(eo).max(), (e, eo)
+        assert np.abs(mesh.source_error(torch.from_numpy(ue).cuda(), t)).max() <= 1e-28 * m.H_all().sum()
+        mesh.close()
+
+
+def test_source_fp32_residual():
+    import torch
+    say("[mms] FP32")
+    m, gas, sch, mesh = _setup(3, 2, True, precision=1)
+    t = 0.2
+    ue, S = _fields(m, gas, t, True)
+    u = _perturbed(ue, 8)
+    mesh.set_time(t)
+    r = mesh.residual(torch.from_numpy(u).cuda()).cpu().numpy()
+    err = _sum_err(r, sch(u), S, sch, u)
+    say("   FP32 rel err", err.max())
+    assert (err <= 2e-4).all(), err
+    mesh.check_device()
+    mesh.close()
+
+
+def test_set_source_argument_checks():
+    import torch
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say("[mms] argument checks")
+    mesh = sbp.Mesh(wl.periodic_tri_mesh(2, 2, 3.0), 1)
+    with pytest.raises(sbp.SbpError) as ei:      # box side 3: not a multiple of the period 2
+        mesh.set_source()
+    assert ei.value.code == sbp.SBP_EINVAL
+    with pytest.raises(sbp.SbpError) as ei:      # no source set
+        mesh.source_state(0.0)
+    assert ei.value.code == sbp.SBP_EINVAL
+    mesh.close()
+    mesh = sbp.Mesh(wl.mms_mesh2d(2), 1)
+    for kind, par in ((7, None), (sbp.SOURCE_NS_MMS, (0.1, 0.2, 0.6, 1.0)),
+                      (sbp.SOURCE_NS_MMS, (2.0, 0.1, float("nan"), 1.0)),
+                      (sbp.SOURCE_NS_MMS, (1.0, 0.1, 0.6, 1.0))):   # p < 0: rho0 - a <= d V0^2 / 2
+        with pytest.raises(sbp.SbpError) as ei:
+            mesh.set_source(kind, par)
+        assert ei.value.code == sbp.SBP_EINVAL
+    with pytest.raises(sbp.SbpError):
+        mesh.source_error(torch.zeros(mesh.state_shape(), dtype=torch.float64, device="cuda"), 0.0)
+    mesh.set_source(sbp.SOURCE_NS_MMS, (2.0, 0.1, 0.6, 1.0))
+    mesh.close()

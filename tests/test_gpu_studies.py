@@ -46,3 +46,19 @@ def test_conservation_study_small():
         assert 0 < r["mass_error"] < 1e-2 and 0 < r["energy_error"] < 1e-2
         assert r["t"] >= 0.5
     assert rows[1]["mass_error"] < rows[0]["mass_error"]
+
+
+@pytest.mark.parametrize("dim,p,ns", [(2, 2, (8, 16)), (3, 1, (4, 8))])
+def test_mms_study_small(dim, p, ns):
+    """Manufactured solution (Sec. 7) through the library on two small grids:
+    the nodal fields start exact, the error after 50 steps to t = 10^-3 falls
+    with refinement at least at the truncation order p of the operators (the
+    error this early is t times the truncation error)."""
+    from paper_2305_07181_amd import studies
+    say(f"[study] mms dim={dim} p={p}")
+    rows = studies.mms_study(dim, ns, [p], tf=1e-3, steps=50, emit=say)
+    for r in rows:
+        assert r["initial_error"] < 1e-13
+        assert abs(r["t"] - 1e-3) < 1e-9
+        assert 0 < r["l2_error"] < 1e-2
+    assert rows[1]["rate"] > p - 0.35, rows[1]["rate"]
