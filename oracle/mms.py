@@ -24,11 +24,22 @@ on).  The paper gives neither the period nor the source in closed form; the
 fields have period 2 in every x_i, so any periodic box with sides a multiple
 of 2 (the paper's [-1, 1]^d) carries them.
 
+The error of the grid studies follows the paper's accuracy section (Sec.
+7.3): the nodal solution is interpolated to a quadrature rule of degree
+3p + 1, the squared error integrated over each element and summed.  The
+paper does not say how n_p > dim P_p nodal values are interpolated; here it
+is the least-squares fit of degree p weighted by the reference diagonal
+norm h (exact for degree-p polynomials), evaluated at the points of a
+collapsed Gauss-Legendre rule exact to degree 3p + 1 on the unit simplex.
+
 Parity: pinned in tests/test_oracle_mms.py by fourth-order central
 differences of physics.flux and physics.viscous_flux applied to the fields
 (an independent route to the same source), by the vanishing source of a
 constant state (a = 0), and by the total energy rho^2 that the paper's
-pressure gives when |V|^2 = d.
+pressure gives when |V|^2 = d; the quadrature norm by exact monomial
+integrals on the simplex, exact reproduction of degree-p polynomials, a
+constant offset integrating to its square times the box volume on curved
+and affine grids, and the p + 1 decay of the interpolation error.
 """
 from __future__ import annotations
 
@@ -101,3 +112,74 @@ def l2_error(u, x, t, H, gas, par=PAPER):
     ue = state(np.moveaxis(x, 1, 0), t, gas, par)       # [n_c, ne, n_p]
     err = u - np.moveaxis(ue, 0, 1)
     return np.einsum("en,ecn->c", H, err * err)
+
+
+def simplex_rule(dim, k):
+    """Collapsed Gauss-Legendre rule on the unit simplex exact for total
+    degree k: points [nq, dim], weights [nq] (summing to 1/dim!)."""
+    q = (k + dim + 1) // 2          # 2q - 1 >= k + dim - 1
+    x, w = np.polynomial.legendre.leggauss(q)
+    t, wt = 0.5 * (x + 1.0), 0.5 * w
+    pts, wts = [], []
+    if dim == 2:
+        for i in range(q):
+            for j in range(q):
+                pts.append((t[i] * (1.0 - t[j]), t[j]))
+                wts.append(wt[i] * wt[j] * (1.0 - t[j]))
+    else:
+        for i in range(q):
+            for j in range(q):
+                for l in range(q):
+                    pts.append((t[i] * (1.0 - t[j]) * (1.0 - t[l]), t[j] * (1.0 - t[l]), t[l]))
+                    wts.append(wt[i] * wt[j] * wt[l] * (1.0 - t[j]) * (1.0 - t[l]) ** 2)
+    return np.array(pts), np.array(wts)
+
+
+def _monomials(xi, p):
+    dim = xi.shape[1]
+    cols = []
+    if dim == 2:
+        for a in range(p + 1):
+            for b in range(p + 1 - a):
+                cols.append(xi[:, 0] ** a * xi[:, 1] ** b)
+    else:
+        for a in range(p + 1):
+            for b in range(p + 1 - a):
+                for c in range(p + 1 - a - b):
+                    cols.append(xi[:, 0] ** a * xi[:, 1] ** b * xi[:, 2] ** c)
+    return np.stack(cols, 1)
+
+
+def interp_matrix(nodes, h, p, xq):
+    """[nq, n_p]: degree-p least-squares fit to nodal values, weighted by h,
+    evaluated at the points xq (reference coordinates)."""
+    V = _monomials(np.asarray(nodes), p)
+    sw = np.sqrt(np.asarray(h))[:, None]
+    P = np.linalg.lstsq(sw * V, np.diag(sw[:, 0]), rcond=None)[0]   # [N, n_p]
+    return _monomials(np.asarray(xq), p) @ P
+
+
+def l2_error_quadrature(u, mesh, exact):
+    """Per component sum_k integral over element k of (I u_k - u*)^2 with the
+    degree-(3p+1) rule; u[ne, n_c, n_p], mesh an OracleMesh, exact(x[d, n]) ->
+    [n_c, n]."""
+    from .geometry import _p2_basis
+    xq, wq = simplex_rule(mesh.dim, 3 * mesh.p + 1)
+    I = interp_matrix(mesh.ops["nodes"], mesh.ops["h"], mesh.p, xq)
+    if mesh.p_geom == 2:
+        N, dN = _p2_basis(xq)
+    out = np.zeros(mesh.n_c)
+    for e in range(mesh.ne):
+        if mesh.p_geom == 2:
+            g = np.asarray(mesh.geom_nodes[e], dtype=np.float64)        # [6, 2]
+            x = g.T @ N                                              # [2, nq]
+            F = np.einsum("ai,lan->iln", g, dN)                     # dx_i/dxi_l
+            J = F[0, 0] * F[1, 1] - F[0, 1] * F[1, 0]
+        else:
+            v = mesh.verts[mesh.elem[e]]                             # [d+1, d]
+            F = np.stack([v[l + 1] - v[0] for l in range(mesh.dim)], 1)
+            x = v[0][:, None] + F @ xq.T
+            J = np.full(len(wq), np.linalg.det(F))
+        err = u[e] @ I.T - exact(x)                                  # [n_c, nq]
+        out += np.sum(wq * J * err * err, axis=1)
+    return out

@@ -130,3 +130,76 @@ def test_source_keeps_discrete_solution_on_the_fields():
     drift = nstep * dt * np.sqrt(np.einsum("en,ecn->", H, src(0.0) ** 2))
     assert errs["with"] < 0.2 * drift, errs
     assert errs["without"] > 0.5 * drift and errs["flipped"] > 1.5 * drift, (errs, drift)
+
+
+@pytest.mark.parametrize("dim,k", [(2, 4), (2, 13), (3, 4), (3, 10)])
+def test_simplex_rule_integrates_monomials(dim, k):
+    """The collapsed rule integrates every monomial of degree <= k exactly
+    (a! b! [c!] / (a + b [+ c] + dim)! on the unit simplex)."""
+    from math import factorial
+    xq, wq = mms.simplex_rule(dim, k)
+    rng = range(k + 1)
+    for a in rng:
+        for b in rng:
+            for c in (range(k + 1) if dim == 3 else [0]):
+                if a + b + c > k:
+                    continue
+                val = np.sum(wq * xq[:, 0] ** a * xq[:, 1] ** b * (xq[:, 2] ** c if dim == 3 else 1.0))
+                ex = factorial(a) * factorial(b) * factorial(c) / factorial(a + b + c + dim)
+                assert abs(val - ex) <= 1e-14 * max(ex, 1e-3), (a, b, c, val, ex)
+
+
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 4), (3, 1), (3, 3)])
+def test_interp_matrix_reproduces_degree_p(dim, p):
+    from oracle.operators import reference_operator
+    op = reference_operator(dim, p)
+    xq, _ = mms.simplex_rule(dim, 3 * p + 1)
+    I = mms.interp_matrix(op["nodes"], op["h"], p, xq)
+    rng = np.random.default_rng(p)
+    coef = rng.standard_normal(dim + 1)
+    f = lambda x: coef[0] + sum(coef[1 + i] * x[:, i] for i in range(dim)) ** p
+    assert np.abs(I @ f(op["nodes"]) - f(xq)).max() < 1e-12
+    assert np.abs(I.sum(axis=1) - 1.0).max() < 1e-13
+
+
+@pytest.mark.parametrize("dim,p,curved", [(2, 1, False), (2, 3, False), (3, 2, False), (2, 1, True), (2, 4, True)])
+def test_quadrature_norm_of_offset_is_box_volume(dim, p, curved):
+    """u = (a field the interpolant reproduces) + c in one component: the
+    integrated squared error is c^2 times the box volume 2^d.  On affine
+    grids the field is a degree-p polynomial; on the curved 2D grid (which
+    tiles the same box; its P2 Jacobian is integrated exactly) a constant."""
+    from oracle.geometry import OracleMesh
+    from paper_2305_07181_amd import workloads as wl
+    if dim == 3:
+        desc = wl.mms_mesh3d(2)
+    elif curved:
+        desc = wl.mms_mesh2d(3)
+    else:
+        desc = wl.periodic_tri_mesh(3, 3, 2.0)
+    m = OracleMesh(desc, p)
+    q = 0 if curved else p
+    poly = lambda x: np.stack([1.0 + 0.3 * x[0] ** q] + [0.5 * x[i] ** q for i in range(dim)]
+                              + [2.0 + 0.1 * x[-1] ** q], 0)
+    u = np.stack([poly(m.node_coords()[e]) for e in range(m.ne)], 0)
+    c = 0.25
+    u[:, 1, :] += c
+    err = mms.l2_error_quadrature(u, m, poly)
+    assert abs(err[1] - c * c * 2.0 ** dim) < 1e-12, err
+    assert np.abs(np.delete(err, 1)).max() < 1e-24
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_quadrature_norm_of_nodal_fields_decays_at_p_plus_one(p):
+    """The fields sampled at the nodes differ from the fields between the
+    nodes by the interpolation error, which falls as h^(p+1)."""
+    from oracle.geometry import OracleMesh
+    from paper_2305_07181_amd import workloads as wl
+    gas = ph.Gas()
+    errs = []
+    for n in (6, 12):
+        m = OracleMesh(wl.mms_mesh2d(n), p)
+        xs = np.moveaxis(m.node_coords(), 1, 0)
+        u = np.ascontiguousarray(np.moveaxis(mms.state(xs, 0.2, gas), 0, 1))
+        errs.append(np.sqrt(mms.l2_error_quadrature(u, m, lambda x: mms.state(x, 0.2, gas)).sum()))
+    rate = np.log(errs[0] / errs[1]) / np.log(2.0)
+    assert p + 0.7 < rate < p + 1.5, (errs, rate)
