@@ -175,11 +175,20 @@ int sbp_set_source(sbp_mesh *mesh, int32_t kind, const double *params);
  * set.  Asynchronous on hip_stream. */
 int sbp_source_state(sbp_mesh *mesh, double t, void *u_dev, void *hip_stream);
 
-/* out_host[c] = sum_k (u_k - u*_k)^T H_k (u_k - u*_k) for each component c
- * (n_c values), u* the manufactured fields at time t (the squared discrete
- * L2 error of the study).  FP64; synchronises hip_stream.  SBP_EINVAL when
- * no source is set. */
-int sbp_source_error(sbp_mesh *mesh, const void *u_dev, double t, double *out_host, void *hip_stream);
+/* Squared L2 error against the manufactured fields u* at time t, per
+ * component c (n_c values in out_host):
+ *   norm SBP_NORM_QUADRATURE (the grid studies, Sec. 7.3): the nodal values
+ *     of each element are fitted by a polynomial of degree p (least squares
+ *     weighted by the reference norm h, exact for degree p) and the squared
+ *     error integrated with a collapsed Gauss-Legendre rule of degree 3p + 1
+ *     on the element's map (the curved map in 2D);
+ *   norm SBP_NORM_NODAL: sum_k (u_k - u*_k)^T H_k (u_k - u*_k) at the nodes.
+ * FP64; synchronises hip_stream.  The rule's device tables are built on the
+ * first quadrature call.  SBP_EINVAL when no source is set or for an unknown
+ * norm. */
+enum { SBP_NORM_NODAL = 0, SBP_NORM_QUADRATURE = 1 };
+int sbp_source_error(sbp_mesh *mesh, const void *u_dev, double t, int32_t norm, double *out_host,
+                     void *hip_stream);
 
 /* enable != 0 (default): sbp_rrk_step replays its captured stage graph;
  * enable == 0: the stages are launched one by one (for callers that capture

@@ -67,6 +67,8 @@ struct DegreeClass {
   sbp::LaunchCfg res_cfg, vjp_cfg;  // launch shapes (autotuner)
   int node_off_blk = 0;   // offset in the node partial buffers
   int node_blocks = 0;
+  double *d_eq = nullptr;  // error rule of the grid studies (built on first use)
+  int eq_nq = 0;
 };
 
 }  // namespace
@@ -1155,13 +1157,49 @@ int sbp_source_state(sbp_mesh *M, double t, void *u_dev, void *stream) {
   return SBP_OK;
 }
 
-int sbp_source_error(sbp_mesh *M, const void *u_dev, double t, double *out_host, void *stream) {
+// Device table of the error rule of class c: I [nq][np], w [nq] and, in 2D,
+// the quadratic map's basis and derivatives at the points.
+int ensure_error_rule(sbp_mesh *M, DegreeClass &c, hipStream_t s) {
+  if (c.d_eq) return SBP_OK;
+  const sbp::ErrRule &R = sbp::error_rule(M->dim, c.p);
+  std::vector<double> tab(R.I);
+  tab.insert(tab.end(), R.w.begin(), R.w.end());
+  if (M->dim == 2) {
+    std::vector<double> N((size_t)R.nq * 6), dN((size_t)2 * R.nq * 6);
+    for (int q = 0; q < R.nq; ++q) {
+      double n[6], d[2][6];
+      p2_basis(R.xi[2 * q], R.xi[2 * q + 1], n);
+      p2_dbasis(R.xi[2 * q], R.xi[2 * q + 1], d);
+      for (int a = 0; a < 6; ++a) {
+        N[(size_t)q * 6 + a] = n[a];
+        dN[(size_t)q * 6 + a] = d[0][a];
+        dN[(size_t)(R.nq + q) * 6 + a] = d[1][a];
+      }
+    }
+    tab.insert(tab.end(), N.begin(), N.end());
+    tab.insert(tab.end(), dN.begin(), dN.end());
+  }
+  int rc;
+  if ((rc = upload(c.d_eq, tab, s))) return rc;
+  HIPCHK(hipStreamSynchronize(s));  // tab is freed on return
+  c.eq_nq = R.nq;
+  return SBP_OK;
+}
+
+int sbp_source_error(sbp_mesh *M, const void *u_dev, double t, int32_t norm, double *out_host, void *stream) {
   if (!M || !u_dev || !out_host) return fail(SBP_EINVAL, "null argument");
   if (!M->src_kind) return fail(SBP_EINVAL, "no source set");
+  if (norm != SBP_NORM_NODAL && norm != SBP_NORM_QUADRATURE) return fail(SBP_EINVAL, "unknown norm");
   hipStream_t s = (hipStream_t)stream;
   for (auto &c : M->cls) {
     sbp::NodeArgs A = node_args(M, c, (const double *)u_dev, nullptr);
-    HIPCHK(sbp::launch_source_error(A, M->src, t, M->d_npart + c.node_off_blk, s));
+    if (norm == SBP_NORM_NODAL) {
+      HIPCHK(sbp::launch_source_error(A, M->src, t, M->d_npart + c.node_off_blk, s));
+    } else {
+      int rc;
+      if ((rc = ensure_error_rule(M, c, s))) return rc;
+      HIPCHK(sbp::launch_source_error_quad(A, M->src, t, c.d_eq, c.eq_nq, c.d_geo, M->d_npart + c.node_off_blk, s));
+    }
   }
   return reduce_nodes(M, M->nc, 0, out_host, s);
 }
@@ -1296,6 +1334,7 @@ int sbp_destroy_mesh(sbp_mesh *M) {
     (void)hipFree(c.d_uoff);
     (void)hipFree(c.d_gid);
     (void)hipFree(c.d_geo);
+    (void)hipFree(c.d_eq);
     (void)hipFree(c.d_nbr);
     (void)hipFree(c.d_Hn);
     (void)hipFree(c.d_hmin);

@@ -88,6 +88,12 @@ hipError_t launch_source_add(const NodeArgs &A, const SrcArgs &P, void *r, int r
 hipError_t launch_source_state(const NodeArgs &A, const SrcArgs &P, double t, double *u, hipStream_t s);
 // part[c*pstride + b] = sum_nodes H (u_c - u*_c)^2 at time t
 hipError_t launch_source_error(const NodeArgs &A, const SrcArgs &P, double t, double *part, hipStream_t s);
+// part[c*pstride + b] = per component sum of w_q J_q (I u - u*)^2 over the
+// elements and the points of the degree-(3p+1) error rule (tab: I [nq][np],
+// w [nq], 2D: N [nq][6], dN [2][nq][6] of the quadratic map); launched with
+// node_blocks(n_elem, np) workgroups like the other node kernels
+hipError_t launch_source_error_quad(const NodeArgs &A, const SrcArgs &P, double t, const double *tab, int nq,
+                                   const double *geo, double *part, hipStream_t s);
 // out[v] = reduction over part[v*nb + b], b < nb (op 0: sum, 1: min); fixed order.
 hipError_t launch_reduce(const double *part, int nb, int nv, int op, double *out, hipStream_t s);
 // y = x + a s z (x null: y = a s z), z double or float (z_f32), n doubles,

@@ -521,4 +521,94 @@ const RefOp &reference_operator(int dim, int p) {
   return res.first->second;
 }
 
+// Error rule of the grid studies (Sec. 7.3: the nodal solution interpolated
+// to a quadrature of degree 3p + 1).  Points of the collapsed Gauss-Legendre
+// product rule on the unit simplex, q points per direction with
+// 2q - 1 >= 3p + 1 + dim - 1 (the collapse adds dim - 1 to the degree in the
+// last variable); the map from nodal values is the degree-p least-squares
+// fit weighted by h, solved from its normal equations in long double.
+static ErrRule build_error_rule(int dim, int p) {
+  const RefOp &op = reference_operator(dim, p);
+  ErrRule R;
+  const int k = 3 * p + 1, q = (k + dim + 1) / 2;
+  std::vector<double> t, w;
+  gauss_legendre01(q, t, w);
+  if (dim == 2) {
+    for (int i = 0; i < q; ++i)
+      for (int j = 0; j < q; ++j) {
+        R.xi.push_back(t[i] * (1.0 - t[j]));
+        R.xi.push_back(t[j]);
+        R.w.push_back(w[i] * w[j] * (1.0 - t[j]));
+      }
+  } else {
+    for (int i = 0; i < q; ++i)
+      for (int j = 0; j < q; ++j)
+        for (int l = 0; l < q; ++l) {
+          R.xi.push_back(t[i] * (1.0 - t[j]) * (1.0 - t[l]));
+          R.xi.push_back(t[j] * (1.0 - t[l]));
+          R.xi.push_back(t[l]);
+          R.w.push_back(w[i] * w[j] * w[l] * (1.0 - t[j]) * (1.0 - t[l]) * (1.0 - t[l]));
+        }
+  }
+  R.nq = (int)R.w.size();
+  const auto mon = monomials(p, dim);
+  const int N = (int)mon.size(), np = op.np;
+  auto vand = [&](const double *x, int m) {
+    LD v = 1.0L;
+    for (int d = 0; d < dim; ++d)
+      for (int e = 0; e < mon[m][d]; ++e) v *= (LD)x[d];
+    return v;
+  };
+  // normal equations A c = V^T h f for all unit nodal vectors f at once:
+  // A = V^T h V [N][N], B = V^T h [N][np]
+  std::vector<LD> A((size_t)N * N, 0.0L), B((size_t)N * np, 0.0L);
+  for (int j = 0; j < np; ++j) {
+    const double *x = &op.nodes[(size_t)j * dim];
+    for (int a = 0; a < N; ++a) {
+      const LD va = vand(x, a) * (LD)op.h[j];
+      B[(size_t)a * np + j] = va;
+      for (int b = 0; b < N; ++b) A[(size_t)a * N + b] += va * vand(x, b);
+    }
+  }
+  // Gaussian elimination with partial pivoting: B <- A^-1 B
+  for (int c = 0; c < N; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < N; ++r)
+      if (std::fabs(A[(size_t)r * N + c]) > std::fabs(A[(size_t)piv * N + c])) piv = r;
+    if (piv != c) {
+      for (int b = 0; b < N; ++b) std::swap(A[(size_t)c * N + b], A[(size_t)piv * N + b]);
+      for (int b = 0; b < np; ++b) std::swap(B[(size_t)c * np + b], B[(size_t)piv * np + b]);
+    }
+    const LD d = A[(size_t)c * N + c];
+    for (int r = 0; r < N; ++r) {
+      if (r == c) continue;
+      const LD f = A[(size_t)r * N + c] / d;
+      if (f == 0.0L) continue;
+      for (int b = 0; b < N; ++b) A[(size_t)r * N + b] -= f * A[(size_t)c * N + b];
+      for (int b = 0; b < np; ++b) B[(size_t)r * np + b] -= f * B[(size_t)c * np + b];
+    }
+  }
+  for (int c = 0; c < N; ++c)
+    for (int b = 0; b < np; ++b) B[(size_t)c * np + b] /= A[(size_t)c * N + c];
+  R.I.assign((size_t)R.nq * np, 0.0);
+  for (int m = 0; m < R.nq; ++m)
+    for (int j = 0; j < np; ++j) {
+      LD s = 0.0L;
+      for (int a = 0; a < N; ++a) s += vand(&R.xi[(size_t)m * dim], a) * B[(size_t)a * np + j];
+      R.I[(size_t)m * np + j] = (double)s;
+    }
+  return R;
+}
+
+const ErrRule &error_rule(int dim, int p) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, ErrRule> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto key = std::make_pair(dim, p);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  auto res = cache.emplace(key, build_error_rule(dim, p));
+  return res.first->second;
+}
+
 }  // namespace sbp

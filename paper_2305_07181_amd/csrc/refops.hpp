@@ -18,4 +18,15 @@ struct RefOp {
 // Cached, thread-safe.  Throws std::invalid_argument for unsupported (dim,p).
 const RefOp &reference_operator(int dim, int p);
 
+// Quadrature of degree 3p + 1 on the unit simplex and the map from nodal
+// values to its points (the error norm of the grid studies).
+struct ErrRule {
+  int nq = 0;
+  std::vector<double> xi;  // [nq][dim] reference coordinates
+  std::vector<double> w;   // [nq]
+  std::vector<double> I;   // [nq][np]: degree-p fit weighted by h, at xi
+};
+// Cached, thread-safe; same (dim, p) range as reference_operator.
+const ErrRule &error_rule(int dim, int p);
+
 }  // namespace sbp

@@ -170,12 +170,7 @@ __global__ __launch_bounds__(kT) void k_dt(NodeArgs A, double *part) {
 // (the stress vanishes; the heat flux kappa dT/dx_i with T = p/(rho R)
 // linear in rho gives the last term).
 template <int D>
-__device__ __forceinline__ void mms_node(const NodeArgs &A, const SrcArgs &P, int e, int j, double t, double *u,
-                                         double *S) {
-  const double *x = A.xyz + (size_t)(A.uoff[e] / (D + 2)) * D + j;
-  double sx = 0.0;
-#pragma unroll
-  for (int i = 0; i < D; ++i) sx += x[i * A.np];
+__device__ __forceinline__ void mms_point(double sx, double gamma, const SrcArgs &P, double t, double *u, double *S) {
   const double xi = M_PI * (sx - P.c * t);
   double sn, cs;
   sincos(xi, &sn, &cs);
@@ -189,13 +184,24 @@ __device__ __forceinline__ void mms_node(const NodeArgs &A, const SrcArgs &P, in
   }
   if (S) {
     const double g = P.a * M_PI * cs;
-    const double dp = (A.gamma - 1.0) * (2.0 * rho - 0.5 * q2);
+    const double dp = (gamma - 1.0) * (2.0 * rho - 0.5 * q2);
     const double dv = D * P.V0 - P.c;
     S[0] = dv * g;
 #pragma unroll
     for (int i = 0; i < D; ++i) S[1 + i] = (P.V0 * dv + dp) * g;
     S[D + 1] = (D * P.V0 * (2.0 * rho + dp) - 2.0 * P.c * rho) * g + P.heat * D * P.a * M_PI * M_PI * sn;
   }
+}
+
+// the fields (u) and source (S) at SBP node j of element e (either may be null)
+template <int D>
+__device__ __forceinline__ void mms_node(const NodeArgs &A, const SrcArgs &P, int e, int j, double t, double *u,
+                                         double *S) {
+  const double *x = A.xyz + (size_t)(A.uoff[e] / (D + 2)) * D + j;
+  double sx = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) sx += x[i * A.np];
+  mms_point<D>(sx, A.gamma, P, t, u, S);
 }
 
 template <int D, typename R>
@@ -226,6 +232,72 @@ __global__ __launch_bounds__(kT) void k_source_add(NodeArgs A, SrcArgs P, R *r, 
   if (part) {
     const double sum = block_reduce_sum(v, red);
     if (threadIdx.x == 0) part[blockIdx.x] = sum;
+  }
+}
+
+// The error of the grid studies (Sec. 7.3): per component sum over elements
+// and points q of a degree-(3p+1) rule of w_q J_q (I u - u*)^2(x_q), with I
+// the degree-p fit from the nodes to the points.  One thread per (element,
+// point), grid-stride over the class.  tab: I [nq][np], w [nq] and, in 2D,
+// the quadratic map's basis N [nq][6] and its derivatives dN [2][nq][6] at
+// the points (x_q and J_q from the element's map nodes geo[e][6][2]); in 3D
+// the affine map is reproduced by I applied to the node coordinates and J
+// is the element's constant (geo[e][9]).
+template <int D>
+__global__ __launch_bounds__(kT) void k_source_error_quad(NodeArgs A, SrcArgs P, double t, const double *tab, int nq,
+                                                           const double *geo, double *part) {
+  constexpr int NC = D + 2;
+  __shared__ double red[kT / 64];
+  const double *I = tab, *W = tab + (size_t)nq * A.np;
+  const double *N = W + nq, *dN = N + (size_t)nq * 6;
+  double v[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) v[k] = 0.0;
+  const long long total = (long long)A.n_elem * nq;
+  for (long long idx = blockIdx.x * (long long)kT + threadIdx.x; idx < total; idx += (long long)gridDim.x * kT) {
+    const int e = (int)(idx / nq), q = (int)(idx % nq);
+    const int base = A.uoff[e];
+    const double *Iq = I + (size_t)q * A.np;
+    double uq[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) uq[k] = 0.0;
+    for (int j = 0; j < A.np; ++j) {
+      const double c = Iq[j];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) uq[k] += c * A.u[base + k * A.np + j];
+    }
+    double sx = 0.0, J;
+    if (D == 2) {
+      const double *g = geo + (size_t)e * 12;
+      double F[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+      for (int a = 0; a < 6; ++a) {
+        const double n = N[q * 6 + a], d0 = dN[q * 6 + a], d1 = dN[(nq + q) * 6 + a];
+        sx += n * (g[2 * a] + g[2 * a + 1]);
+        F[0][0] += d0 * g[2 * a];
+        F[0][1] += d1 * g[2 * a];
+        F[1][0] += d0 * g[2 * a + 1];
+        F[1][1] += d1 * g[2 * a + 1];
+      }
+      J = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+    } else {
+      const double *xn = A.xyz + (size_t)(base / NC) * D;
+      for (int i = 0; i < D; ++i)
+        for (int j = 0; j < A.np; ++j) sx += Iq[j] * xn[i * A.np + j];
+      J = geo[(size_t)e * 10 + 9];
+    }
+    double ue[NC];
+    mms_point<D>(sx, A.gamma, P, t, ue, nullptr);
+    const double wj = W[q] * J;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const double d = uq[k] - ue[k];
+      v[k] += wj * d * d;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const double sum = block_reduce_sum(v[k], red);
+    if (threadIdx.x == 0) part[k * A.pstride + blockIdx.x] = sum;
   }
 }
 
@@ -369,6 +441,16 @@ hipError_t launch_source_state(const NodeArgs &A, const SrcArgs &P, double t, do
     hipLaunchKernelGGL(k_source_state<2>, dim3(nb), dim3(kT), 0, s, A, P, t, u);
   else
     hipLaunchKernelGGL(k_source_state<3>, dim3(nb), dim3(kT), 0, s, A, P, t, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_source_error_quad(const NodeArgs &A, const SrcArgs &P, double t, const double *tab, int nq,
+                                   const double *geo, double *part, hipStream_t s) {
+  const int nb = node_blocks(A.n_elem, A.np);
+  if (A.dim == 2)
+    hipLaunchKernelGGL(k_source_error_quad<2>, dim3(nb), dim3(kT), 0, s, A, P, t, tab, nq, geo, part);
+  else
+    hipLaunchKernelGGL(k_source_error_quad<3>, dim3(nb), dim3(kT), 0, s, A, P, t, tab, nq, geo, part);
   return hipGetLastError();
 }
 

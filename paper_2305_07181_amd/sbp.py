@@ -21,6 +21,7 @@ SBP_OK, SBP_EINVAL, SBP_ENOMEM, SBP_EDEVICE, SBP_ENOTSUP, SBP_ENONPHYS, SBP_ERRK
 FORM_SPLIT, FORM_HADAMARD = 0, 1
 FP64, FP32 = 0, 1
 SOURCE_NONE, SOURCE_NS_MMS = 0, 1
+NORM_NODAL, NORM_QUADRATURE = 0, 1
 
 SYMBOLS = ["sbp_setup_mesh", "sbp_mesh_info", "sbp_residual", "sbp_residual_vjp", "sbp_rrk_step",
            "sbp_diagnostics", "sbp_check_device", "sbp_set_time", "sbp_destroy_mesh",
@@ -91,7 +92,7 @@ def load_library(path: str = _LIB_PATH):
     lib.sbp_set_volume_form.argtypes = [P, P]
     lib.sbp_set_source.argtypes = [P, C.c_int32, P]
     lib.sbp_source_state.argtypes = [P, C.c_double, P, P]
-    lib.sbp_source_error.argtypes = [P, P, C.c_double, P, P]
+    lib.sbp_source_error.argtypes = [P, P, C.c_double, C.c_int32, P, P]
     lib.sbp_destroy_mesh.argtypes = [P]
     lib.sbp_last_error.restype = C.c_char_p
     lib.sbp_reference_operator.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -306,11 +307,16 @@ class Mesh:
         _check(_lib.sbp_source_state(self._h, float(t), _ptr(u), _stream_ptr(stream)))
         return u
 
-    def source_error(self, u, t, stream=None):
-        """Per component sum_k (u_k - u*)^T H_k (u_k - u*) at time t (sbp_source_error)."""
+    def source_error(self, u, t, norm="quadrature", stream=None):
+        """Per component squared L2 error against the manufactured fields at
+        time t (sbp_source_error): norm "quadrature" (degree-p fit integrated
+        with a degree 3p+1 rule, the paper's studies) or "nodal" (H norm)."""
         self._check_state(u)
+        kinds = {"nodal": NORM_NODAL, "quadrature": NORM_QUADRATURE}
+        if norm not in kinds:
+            raise ValueError("norm must be 'nodal' or 'quadrature'")
         out = np.zeros(self.n_c)
-        _check(_lib.sbp_source_error(self._h, _ptr(u), float(t), _dp(out), _stream_ptr(stream)))
+        _check(_lib.sbp_source_error(self._h, _ptr(u), float(t), kinds[norm], _dp(out), _stream_ptr(stream)))
         return out
 
     def use_graphs(self, enable=True):

@@ -168,10 +168,20 @@ def test_source_error_vs_oracle():
         t = 0.45
         ue, _ = _fields(m, gas, t, dim == 3)
         u = _perturbed(ue, 5)
-        e = mesh.source_error(torch.from_numpy(u).cuda(), t)
+        ud = torch.from_numpy(u).cuda()
+        e = mesh.source_error(ud, t, norm="nodal")
         eo = mms.l2_error(u, m.node_coords(), t, m.H_all(), gas)
         assert np.abs(e - eo).max() <= 1e-12 * np.abs(eo).max(), (e, eo)
-        assert np.abs(mesh.source_error(torch.from_numpy(ue).cuda(), t)).max() <= 1e-28 * m.H_all().sum()
+        assert np.abs(mesh.source_error(torch.from_numpy(ue).cuda(), t, norm="nodal")).max() <= 1e-28 * m.H_all().sum()
+        # the studies' norm: degree-p fit integrated with a degree 3p+1 rule
+        exact = lambda x: mms.state(x, t, gas)
+        for uu in (u, ue):
+            eq = mesh.source_error(torch.from_numpy(uu).cuda(), t)
+            eqo = mms.l2_error_quadrature(uu, m, exact)
+            say(f"   dim={dim} quadrature norm gpu {eq.sum():.6e} oracle {eqo.sum():.6e}")
+            assert np.abs(eq - eqo).max() <= 1e-12 * np.abs(eqo).max(), (eq, eqo)
+        with pytest.raises(ValueError):
+            mesh.source_error(ud, t, norm="max")
         mesh.close()
 
 
@@ -210,7 +220,8 @@ def test_set_source_argument_checks():
         with pytest.raises(sbp.SbpError) as ei:
             mesh.set_source(kind, par)
         assert ei.value.code == sbp.SBP_EINVAL
-    with pytest.raises(sbp.SbpError):
-        mesh.source_error(torch.zeros(mesh.state_shape(), dtype=torch.float64, device="cuda"), 0.0)
+    for norm in ("nodal", "quadrature"):
+        with pytest.raises(sbp.SbpError):
+            mesh.source_error(torch.zeros(mesh.state_shape(), dtype=torch.float64, device="cuda"), 0.0, norm)
     mesh.set_source(sbp.SOURCE_NS_MMS, (2.0, 0.1, 0.6, 1.0))
     mesh.close()
