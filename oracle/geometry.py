@@ -49,6 +49,29 @@ def _p2_basis(xi):
     return N, dN
 
 
+P2_TET_EDGES = ((0, 1), (1, 2), (0, 2), (0, 3), (1, 3), (2, 3))
+
+
+def _p2_basis3(xi):
+    """Quadratic Lagrange basis on the reference tetrahedron, node order
+    v0..v3 then the edge midpoints in P2_TET_EDGES order; returns
+    (N[10,n], dN[3,10,n])."""
+    n = xi.shape[0]
+    lam = [1.0 - xi[:, 0] - xi[:, 1] - xi[:, 2], xi[:, 0], xi[:, 1], xi[:, 2]]
+    dl = np.array([[-1.0, -1.0, -1.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    N = np.zeros((10, n))
+    dN = np.zeros((3, 10, n))
+    for a in range(4):
+        N[a] = lam[a] * (2 * lam[a] - 1)
+        for l in range(3):
+            dN[l, a] = (4 * lam[a] - 1) * dl[a, l]
+    for q, (a, b) in enumerate(P2_TET_EDGES):
+        N[4 + q] = 4 * lam[a] * lam[b]
+        for l in range(3):
+            dN[l, 4 + q] = 4 * (dl[a, l] * lam[b] + lam[a] * dl[b, l])
+    return N, dN
+
+
 def _wrap_key(c, period, res=1 << 22):
     return tuple(int(round(c[i] / period[i] * res)) % res for i in range(len(c)))
 
@@ -134,12 +157,12 @@ class OracleMesh:
             F = np.stack([v[l + 1] - v[0] for l in range(dim)], 1)  # F[i,l] = dx_i/dxi_l
             x = v[0][None, :] + xi @ F.T
             Fn = np.broadcast_to(F, (n_p, dim, dim)).copy()
-        elif self.p_geom == 2 and dim == 2:
-            g = np.asarray(self.geom_nodes[e], dtype=np.float64)  # [6,2]
-            N, dN = _p2_basis(xi)
+        elif self.p_geom == 2:
+            g = np.asarray(self.geom_nodes[e], dtype=np.float64)  # [6,2] or [10,3]
+            N, dN = _p2_basis(xi) if dim == 2 else _p2_basis3(xi)
             x = N.T @ g
-            Fn = np.zeros((n_p, 2, 2))
-            for l in range(2):
+            Fn = np.zeros((n_p, dim, dim))
+            for l in range(dim):
                 Fn[:, :, l] = dN[l].T @ g
         else:
             raise ValueError("unsupported geometry")
@@ -177,8 +200,8 @@ class OracleMesh:
             F = np.stack([v[:, l + 1] - v[:, 0] for l in range(self.dim)], 2)  # [n, i, l]
             x = v[:, 0][:, None, :] + np.einsum("jl,nil->nji", xi, F)
         else:
-            N, _ = _p2_basis(xi)
-            g = np.asarray(self.geom_nodes, dtype=np.float64)[els]   # [n,6,2]
+            N, _ = _p2_basis(xi) if self.dim == 2 else _p2_basis3(xi)
+            g = np.asarray(self.geom_nodes, dtype=np.float64)[els]   # [n,6,2] or [n,10,3]
             x = np.einsum("aj,nai->nji", N, g)
         return np.ascontiguousarray(np.transpose(x, (0, 2, 1)))
 

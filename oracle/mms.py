@@ -163,18 +163,18 @@ def l2_error_quadrature(u, mesh, exact):
     """Per component sum_k integral over element k of (I u_k - u*)^2 with the
     degree-(3p+1) rule; u[ne, n_c, n_p], mesh an OracleMesh, exact(x[d, n]) ->
     [n_c, n]."""
-    from .geometry import _p2_basis
+    from .geometry import _p2_basis, _p2_basis3
     xq, wq = simplex_rule(mesh.dim, 3 * mesh.p + 1)
     I = interp_matrix(mesh.ops["nodes"], mesh.ops["h"], mesh.p, xq)
     if mesh.p_geom == 2:
-        N, dN = _p2_basis(xq)
+        N, dN = _p2_basis(xq) if mesh.dim == 2 else _p2_basis3(xq)
     out = np.zeros(mesh.n_c)
     for e in range(mesh.ne):
         if mesh.p_geom == 2:
-            g = np.asarray(mesh.geom_nodes[e], dtype=np.float64)        # [6, 2]
-            x = g.T @ N                                              # [2, nq]
-            F = np.einsum("ai,lan->iln", g, dN)                     # dx_i/dxi_l
-            J = F[0, 0] * F[1, 1] - F[0, 1] * F[1, 0]
+            g = np.asarray(mesh.geom_nodes[e], dtype=np.float64)        # [6, 2] or [10, 3]
+            x = g.T @ N                                              # [d, nq]
+            F = np.einsum("ai,lan->nil", g, dN)                     # dx_i/dxi_l per point
+            J = np.linalg.det(F)
         else:
             v = mesh.verts[mesh.elem[e]]                             # [d+1, d]
             F = np.stack([v[l + 1] - v[0] for l in range(mesh.dim)], 1)

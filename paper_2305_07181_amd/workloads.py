@@ -300,6 +300,45 @@ def mms_mesh3d(n: int) -> dict:
     return desc
 
 
+# Edge midpoints of the quadratic tetrahedron, in the order of its map nodes
+# 4..9 (after the four vertices).
+P2_TET_EDGES = ((0, 1), (1, 2), (0, 2), (0, 3), (1, 3), (2, 3))
+
+
+def _tet_p2_nodes(desc):
+    v = desc["vert_xyz"][desc["elem_vert"]]                  # [ne,4,3]
+    mids = np.stack([0.5 * (v[:, a] + v[:, b]) for a, b in P2_TET_EDGES], 1)
+    return np.concatenate([v, mids], 1)                      # [ne,10,3]
+
+
+def curved_tet_mesh(n: int, L: float, warp: float) -> dict:
+    """Periodic [0,L]^3 in n^3 cubes of six tetrahedra with quadratic maps:
+    the map nodes (vertices and edge midpoints) are moved by
+        delta = warp * L * sin(2 pi x/L) sin(2 pi y/L) sin(2 pi z/L)
+    added to every coordinate, which vanishes on the box faces (conforming
+    and periodic)."""
+    desc = periodic_tet_mesh(n, L)
+    g = _tet_p2_nodes(desc)
+    s = np.sin(2 * np.pi * g / L)
+    dlt = warp * L * s[..., 0] * s[..., 1] * s[..., 2]
+    desc["p_geom"] = 2
+    desc["geom_nodes"] = np.ascontiguousarray(g + dlt[..., None])
+    return desc
+
+
+def paper_vortex3d_mesh(n: int) -> dict:
+    """Grid of the paper's 3D isentropic-vortex study (Sec. 7.3): the
+    periodic box [-10,10]^3 in n^3 cubes of six tetrahedra, the quadratic map
+    nodes moved by x_i = x^_i + 0.05 sin(pi x^_i / 2) (eq. curve 3d vortex),
+    which fixes the box faces."""
+    desc = periodic_tet_mesh(n, 20.0)
+    desc["vert_xyz"] = desc["vert_xyz"] - 10.0
+    g = _tet_p2_nodes(desc)
+    desc["p_geom"] = 2
+    desc["geom_nodes"] = np.ascontiguousarray(g + 0.05 * np.sin(0.5 * np.pi * g))
+    return desc
+
+
 def tgv_mesh(n: int) -> dict:
     """[0, 2 pi]^3, n^3 hexes x 6 tetrahedra (n=32: 196608; n=24: 82944)."""
     return periodic_tet_mesh(n, 2 * math.pi)

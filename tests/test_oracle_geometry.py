@@ -15,7 +15,9 @@ def _monos(deg, dim):
 
 MESHES = [("tri-affine", lambda: wl.periodic_tri_mesh(3, 2, 2.0, 1.5), (1, 2, 3, 4)),
           ("tri-curved", lambda: wl.vortex2d_mesh(3, warp=0.05), (1, 2, 3, 4)),
-          ("tet-affine", lambda: wl.periodic_tet_mesh(2, 1.3), (1, 2, 3))]
+          ("tet-affine", lambda: wl.periodic_tet_mesh(2, 1.3), (1, 2, 3)),
+          # quadratic maps need p >= 2 in 3D (Assumption 1: p_geom <= floor(p/2) + 1)
+          ("tet-curved", lambda: wl.curved_tet_mesh(2, 1.3, 0.03), (2, 3))]
 
 
 @pytest.mark.parametrize("name,make,ps", MESHES, ids=[m[0] for m in MESHES])

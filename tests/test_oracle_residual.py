@@ -31,7 +31,8 @@ def rate_tol(scheme, u, r):
 
 CASES = [("tri-affine", lambda: wl.periodic_tri_mesh(3, 3, 2.0), [1, 2, 3, 4]),
          ("tri-curved", lambda: wl.vortex2d_mesh(3, warp=0.05), [1, 2, 3, 4]),
-         ("tet-affine", lambda: wl.periodic_tet_mesh(2, 1.0), [1, 2, 3])]
+         ("tet-affine", lambda: wl.periodic_tet_mesh(2, 1.0), [1, 2, 3]),
+         ("tet-curved", lambda: wl.curved_tet_mesh(2, 1.0, 0.03), [2, 3])]
 IDS = [c[0] for c in CASES]
 
 
@@ -325,3 +326,19 @@ def test_viscous_truncation_error():
             errs.append(np.sqrt(np.sum(H[:, None, :] * (r - ex) ** 2)))
         rate = np.log2(errs[0] / errs[1])
         assert rate > p - 1.25, (p, errs, rate)
+
+
+def test_truncation_error_curved_tets():
+    """Curved tetrahedra (quadratic maps, p = 2, the lowest degree Assumption
+    1 allows): r(u_exact) + div F falls with refinement at about the design
+    order (1.85 between the two coarse grids n = 2, 4)."""
+    gas = ph.Gas()
+    errs = []
+    for n in (2, 4):
+        m = OracleMesh(wl.curved_tet_mesh(n, 1.0, 0.03), 2)
+        x = m.node_coords()
+        u = np.stack([_smooth(x[e], 3) for e in range(m.ne)], 0)
+        r = OracleScheme(m, gas)(u)
+        ex = np.stack([_exact_divergence(x[e], 3, gas) for e in range(m.ne)], 0)
+        errs.append(np.sqrt(np.sum(m.H_all()[:, None, :] * (r - ex) ** 2)))
+    assert np.log(errs[0] / errs[1]) / np.log(2.0) > 1.6, errs
