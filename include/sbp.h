@@ -57,9 +57,11 @@ typedef struct {
   int32_t n_vert, n_elem;
   const double *vert_xyz;      /* [n_vert][dim], host                             */
   const int32_t *elem_vert;    /* [n_elem][dim+1], positively oriented            */
-  int32_t p_geom;              /* 1 affine; 2 quadratic map (2D only)             */
-  const double *geom_nodes;    /* [n_elem][6][2] P2 map nodes (v0,v1,v2,m01,m12,m20),
-                                  or NULL when p_geom == 1                        */
+  int32_t p_geom;              /* 1 affine; 2 quadratic map (3D: degrees p >= 2,
+                                  Assumption 1; entropy-split Euler terms only)   */
+  const double *geom_nodes;    /* 2D: [n_elem][6][2] P2 map nodes (v0,v1,v2,m01,m12,m20);
+                                  3D: [n_elem][10][3] (v0..v3, m01,m12,m02,m03,m13,m23);
+                                  NULL when p_geom == 1                           */
   const double *period;        /* [dim] periodic box lengths                      */
   const int32_t *elem_degree;  /* [n_elem] SBP degree p (2D: 1..4, 3D: 1..3),
                                   uniform inside each problem                     */
@@ -105,7 +107,12 @@ typedef struct {
 } sbp_rrk_report;
 
 /* Build a mesh handle: reference operators (Def. 1), metrics, facet matching,
- * device tables.  `hip_stream` is used for the uploads.  Paper: Sec. 2.1. */
+ * device tables.  `hip_stream` is used for the uploads.  Paper: Sec. 2.1.
+ * Curved tetrahedra (p_geom 2 in 3D) need every degree >= 2 (Assumption 1:
+ * p_geom <= floor(p/2) + 1), else SBP_EINVAL; with them the viscous terms
+ * and the Hadamard form return SBP_ENOTSUP here, and sbp_residual_vjp,
+ * sbp_set_volume_form and the quadrature norm of sbp_source_error return
+ * SBP_ENOTSUP. */
 int sbp_setup_mesh(const sbp_mesh_desc *desc, const sbp_physics *phys,
                    void *hip_stream, sbp_mesh **out);
 

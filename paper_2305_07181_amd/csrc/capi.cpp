@@ -96,6 +96,7 @@ struct sbp_mesh {
   void *d_r = nullptr;        // RK stage residual
   double t = 0.0;
   double period[3] = {0.0, 0.0, 0.0};
+  int curved3 = 0;            // tetrahedra with quadratic maps (per-node metrics)
   int src_kind = 0;           // SBP_SOURCE_*: source added to every residual
   sbp::SrcArgs src{};
   // RRK stages captured once as a HIP graph (per state pointer), replayed on
@@ -107,6 +108,14 @@ struct sbp_mesh {
 };
 
 namespace {
+
+// Kernel family of the residual: 0 entropy split, 1 Hadamard, 2 entropy
+// split with the Navier-Stokes terms, 3 entropy split on curved tetrahedra.
+int form_eff_of(const sbp_mesh *M) {
+  if (M->phys.viscous) return 2;
+  if (M->curved3) return 3;
+  return M->phys.form;
+}
 
 constexpr int SC_ENT = 0;     // 4 stage entropy rates
 constexpr int SC_RED = 8;     // reduction outputs (up to 8)
@@ -128,6 +137,24 @@ void p2_dbasis(double x, double y, double dN[2][6]) {
       const int a = pr[q][0], b = pr[q][1];
       dN[k][3 + q] = 4.0 * (dl[a][k] * l[b] + l[a] * dl[b][k]);
     }
+  }
+}
+
+// Quadratic tetrahedron: vertices 0..3, then the edge midpoints of the
+// edges (0,1) (1,2) (0,2) (0,3) (1,3) (2,3); derivatives dN[l][a] = dN_a/dxi_l.
+const int kP2TetEdges[6][2] = {{0, 1}, {1, 2}, {0, 2}, {0, 3}, {1, 3}, {2, 3}};
+
+void p2t_basis(const double *xi, double N[10], double dN[3][10]) {
+  const double l[4] = {1.0 - xi[0] - xi[1] - xi[2], xi[0], xi[1], xi[2]};
+  const double dl[4][3] = {{-1.0, -1.0, -1.0}, {1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+  for (int a = 0; a < 4; ++a) {
+    N[a] = l[a] * (2.0 * l[a] - 1.0);
+    for (int k = 0; k < 3; ++k) dN[k][a] = (4.0 * l[a] - 1.0) * dl[a][k];
+  }
+  for (int q = 0; q < 6; ++q) {
+    const int a = kP2TetEdges[q][0], b = kP2TetEdges[q][1];
+    N[4 + q] = 4.0 * l[a] * l[b];
+    for (int k = 0; k < 3; ++k) dN[k][4 + q] = 4.0 * (dl[a][k] * l[b] + l[a] * dl[b][k]);
   }
 }
 
@@ -188,7 +215,14 @@ void build_tables(const sbp::RefOp &op, int dim, std::vector<T> &blob, size_t of
         for (int a = 0; a < 6; ++a) dN[((size_t)k * 6 + a) * NP + j] = d[k][a];
     }
   } else {
-    dN.assign(1, 0.0);
+    // quadratic tetrahedral maps: [3][10][NP]
+    dN.assign((size_t)3 * 10 * NP, 0.0);
+    for (int j = 0; j < NP; ++j) {
+      double n[10], d[3][10];
+      p2t_basis(&op.nodes[(size_t)3 * j], n, d);
+      for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < 10; ++a) dN[((size_t)k * 10 + a) * NP + j] = d[k][a];
+    }
   }
   off[7] = push(dN);
 }
@@ -290,8 +324,30 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
         xe[1 * np + j] = x[1];
         Hn[M->node_off[e] + j] = J * op.h[j];
       }
+    } else if (D->p_geom == 2) {
+      // quadratic map: metric cofactors and J at every node (geo: the ten map nodes)
+      double gn[10][3];
+      for (int a = 0; a < 10; ++a)
+        for (int i = 0; i < 3; ++i) {
+          gn[a][i] = D->geom_nodes[((size_t)e * 10 + a) * 3 + i];
+          geo3.push_back(gn[a][i]);
+        }
+      for (int j = 0; j < np; ++j) {
+        double N[10], dN[3][10], F[3][3] = {}, x[3] = {};
+        p2t_basis(&op.nodes[(size_t)3 * j], N, dN);
+        for (int a = 0; a < 10; ++a)
+          for (int i = 0; i < 3; ++i) {
+            x[i] += N[a] * gn[a][i];
+            for (int l = 0; l < 3; ++l) F[i][l] += dN[l][a] * gn[a][i];
+          }
+        const double J = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) -
+                         F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
+                         F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+        if (!(J > 0)) return fail(SBP_EINVAL, "non-positive Jacobian (element " + std::to_string(e) + ")");
+        for (int i = 0; i < 3; ++i) xe[i * np + j] = x[i];
+        Hn[M->node_off[e] + j] = J * op.h[j];
+      }
     } else {
-      if (D->p_geom != 1) return fail(SBP_ENOTSUP, "3D curved maps are not supported");
       double F[3][3];
       for (int i = 0; i < 3; ++i)
         for (int l = 0; l < 3; ++l) F[i][l] = g[l + 1][i] - g[0][i];
@@ -378,14 +434,15 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
   std::vector<int> local_of(ne, -1);
   for (auto &c : M->cls)
     for (size_t k = 0; k < c.elems.size(); ++k) local_of[c.elems[k]] = (int)k;
-  const int form_eff = ph->viscous ? 2 : ph->form;
+  M->curved3 = dim == 3 && D->p_geom == 2;
+  const int form_eff = form_eff_of(M);
   for (auto &c : M->cls) {
     c.n_elem = (int)c.elems.size();
     const sbp::RefOp &op = sbp::reference_operator(dim, c.p);
     const int np = c.np, nf = c.nf;
     std::vector<int> uoff(c.n_elem), nbr((size_t)c.n_elem * nv * nf), nbrq((size_t)c.n_elem * nv * nf);
     std::vector<double> geo, hn((size_t)c.n_elem * np), hm(c.n_elem);
-    const int gsz = dim == 2 ? 12 : 10;
+    const int gsz = dim == 2 ? 12 : (D->p_geom == 2 ? 30 : 10);
     for (int k = 0; k < c.n_elem; ++k) {
       const int e = c.elems[k];
       uoff[k] = (int)(M->node_off[e] * M->nc);
@@ -515,6 +572,7 @@ sbp::KArgs<T> kargs(sbp_mesh *M, DegreeClass &c, const double *u, void *r, const
   A.ent_part = M->d_part + c.part_off;
   A.err = M->d_err;
   A.visc = ph.viscous;
+  A.curved = M->curved3;
   A.nbrq = c.d_nbrq;
   if (ph.viscous) {
     A.V.mu = (T)ph.mu;
@@ -617,7 +675,7 @@ int residual_core(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStr
     if (hyb && (rc = other_launch(c))) return rc;
   }
   if (ent_dev) {
-    const int form_eff = ph.viscous ? 2 : ph.form;
+    const int form_eff = form_eff_of(M);
     for (int ci = 0; ci < ncls; ++ci) {
       auto &c = M->cls[ci];
       const int nb = sbp::residual_blocks(M->dim, c.p, ph.precision, form_eff, c.n_elem, c.res_cfg);
@@ -859,7 +917,7 @@ int tune_slot(int nvar, F run, hipStream_t s, sbp::LaunchCfg &best, sbp_tune_slo
 int autotune_impl(sbp_mesh *M, const double *u, const double *lam, sbp_tune_report *rep, hipStream_t s) {
   const sbp_physics &ph = M->phys;
   const int f32 = ph.precision == SBP_FP32;
-  const int form_eff = ph.viscous ? 2 : ph.form;
+  const int form_eff = form_eff_of(M);
   sbp_tune_report local{};
   sbp_tune_report &R = rep ? *rep : local;
   R.n_slots = 0;
@@ -914,7 +972,7 @@ int autotune_impl(sbp_mesh *M, const double *u, const double *lam, sbp_tune_repo
       tune_store(tune_key(M, TUNE_RES, c.p, c.n_elem), c.res_cfg);
     }
   }
-  if (lam && !ph.viscous && ph.form == SBP_FORM_SPLIT) {
+  if (lam && !ph.viscous && ph.form == SBP_FORM_SPLIT && !M->curved3) {
     auto vargs = [&](DegreeClass &c) {
       sbp::KArgs<double> A = kargs<double>(M, c, u, nullptr, c.op64);
       A.lam = lam;
@@ -966,8 +1024,16 @@ int sbp_setup_mesh(const sbp_mesh_desc *desc, const sbp_physics *phys, void *hip
   if (desc->n_elem <= 0 || desc->n_vert <= 0 || !desc->vert_xyz || !desc->elem_vert || !desc->period ||
       !desc->elem_degree)
     return fail(SBP_EINVAL, "incomplete mesh description");
-  if (desc->p_geom != 1 && !(desc->p_geom == 2 && desc->dim == 2 && desc->geom_nodes))
-    return fail(SBP_ENOTSUP, "p_geom must be 1, or 2 with geom_nodes in 2D");
+  if (desc->p_geom != 1 && !(desc->p_geom == 2 && desc->geom_nodes))
+    return fail(SBP_ENOTSUP, "p_geom must be 1, or 2 with geom_nodes");
+  if (desc->dim == 3 && desc->p_geom == 2) {
+    // Assumption 1: a quadratic map in 3D needs p >= 2 (p_geom <= floor(p/2) + 1)
+    for (int e = 0; e < desc->n_elem; ++e)
+      if (desc->elem_degree[e] < 2)
+        return fail(SBP_EINVAL, "quadratic tetrahedral maps need degree p >= 2 (Assumption 1)");
+    if (phys->viscous || phys->form != SBP_FORM_SPLIT)
+      return fail(SBP_ENOTSUP, "curved tetrahedra: the entropy-split Euler residual only");
+  }
   if (desc->n_problems < 1) return fail(SBP_EINVAL, "n_problems must be >= 1");
   for (int i = 0; i < desc->dim; ++i)
     if (!(desc->period[i] > 0)) return fail(SBP_EINVAL, "period must be positive");
@@ -1019,6 +1085,7 @@ int sbp_residual_vjp(sbp_mesh *M, const void *u, const void *lam, void *ubar, vo
   const sbp_physics &ph = M->phys;
   if (ph.viscous || ph.form != SBP_FORM_SPLIT)
     return fail(SBP_ENOTSUP, "the VJP covers the entropy-split Euler residual (with or without dissipation)");
+  if (M->curved3) return fail(SBP_ENOTSUP, "the VJP covers affine tetrahedra");
   if (M->eform)
     return fail(SBP_ENOTSUP, "the VJP covers the entropy-split form; clear the hybrid form flags first");
   if (M->dim == 2 && M->cls.size() > 1) {
@@ -1079,8 +1146,8 @@ namespace {
 sbp::LaunchCfg *find_slot(sbp_mesh *M, int kind, int p, int &nvar, int *&grid_only) {
   grid_only = nullptr;
   const sbp_physics &ph = M->phys;
-  const int form_eff = ph.viscous ? 2 : ph.form;
-  if (kind == TUNE_VJP && (ph.viscous || ph.form != SBP_FORM_SPLIT)) return nullptr;
+  const int form_eff = form_eff_of(M);
+  if (kind == TUNE_VJP && (ph.viscous || ph.form != SBP_FORM_SPLIT || M->curved3)) return nullptr;
   const bool batched = kind == TUNE_RES ? (M->batch_blocks > 0 && ph.form == SBP_FORM_SPLIT && !ph.viscous)
                                         : (M->dim == 2 && M->cls.size() > 1);
   if (batched) {
@@ -1103,6 +1170,7 @@ int sbp_set_volume_form(sbp_mesh *M, const uint8_t *form_dev) {
   if (!M) return fail(SBP_EINVAL, "null handle");
   if (form_dev && M->phys.viscous)
     return fail(SBP_ENOTSUP, "the hybrid scheme covers the Euler terms (no viscous terms)");
+  if (form_dev && M->curved3) return fail(SBP_ENOTSUP, "the hybrid scheme covers affine tetrahedra");
   M->eform = form_dev;
   // the captured RK stages hold the previous launches
   if (M->rk_exec) {
@@ -1190,6 +1258,8 @@ int sbp_source_error(sbp_mesh *M, const void *u_dev, double t, int32_t norm, dou
   if (!M || !u_dev || !out_host) return fail(SBP_EINVAL, "null argument");
   if (!M->src_kind) return fail(SBP_EINVAL, "no source set");
   if (norm != SBP_NORM_NODAL && norm != SBP_NORM_QUADRATURE) return fail(SBP_EINVAL, "unknown norm");
+  if (norm == SBP_NORM_QUADRATURE && M->curved3)
+    return fail(SBP_ENOTSUP, "the quadrature norm covers triangles and affine tetrahedra");
   hipStream_t s = (hipStream_t)stream;
   for (auto &c : M->cls) {
     sbp::NodeArgs A = node_args(M, c, (const double *)u_dev, nullptr);

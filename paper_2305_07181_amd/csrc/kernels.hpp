@@ -28,14 +28,15 @@ struct OpTables {
   const T *S;   // skew parts S_xi_l = Q_xi_l - E_xi_l / 2, [dim][NP][NP]
   const T *h;   // [NP]
   const T *E;   // [dim][NP] diagonal of E_xi_l
-  const T *dN;  // 2D: [2][6][NP] derivatives of the quadratic map basis at the nodes
+  const T *dN;  // derivatives of the quadratic map basis at the nodes: 2D [2][6][NP], 3D [3][10][NP]
 };
 
 template <typename T>
 struct KArgs {
   const double *u;     // state (FP64)
   T *r;                // residual (T)
-  const double *geo;   // 2D: [n_elem][12] map nodes; 3D: [n_elem][10] Lambda (row i, col l), J
+  const double *geo;   // 2D: [n_elem][12] map nodes; 3D affine: [n_elem][10] Lambda (row i,
+                       // col l), J; 3D curved: [n_elem][10][3] quadratic map nodes
   const int *nbr;      // [n_elem][NFAC*NF] u offset of the matching neighbour node (component 0)
   const int *uoff;     // [n_elem] u offset of each element of the class
   int n_elem;
@@ -46,6 +47,7 @@ struct KArgs {
   int *err;            // non-physical state flag
   // Navier-Stokes terms (Baumann-Oden SATs)
   int visc;
+  int curved;          // 3D: quadratic maps (metrics from geo and op.dN per node)
   ViscC<T> V;
   const T *q;          // [n_elem][NFAC*NF][n_c] facet normal viscous fluxes B n . F^V
   T *qout;             // written by the facet-flux pre-pass

@@ -511,6 +511,145 @@ __global__ __launch_bounds__(kThreads, 2) void k_split3v(KArgs<T> A) {
   block_sum_store(ent, A.ent_part);
 }
 
+// Entropy split, tetrahedra with quadratic maps (Assumption 1: p >= 2).  At
+// every node the metric cofactors Lambda_il = J dxi_l/dx_i and J follow from
+// the element's ten map nodes and the map basis derivatives at the node.
+// The node-pair sums take the metric average of the two nodes, as on curved
+// triangles:
+//   V_i    = sum_j sum_l S_l[i][j] sum_m (Lambda_ml(i) + Lambda_ml(j)) f^(m)_j
+//   X_k,i  = sum_j sum_l S_l[i][j] (Lambda_kl(i) + Lambda_kl(j)) w_j
+//   vol    = (c_b-1)/2 V + (c_b+1)/2 sum_m a_m f^(m),  a_m = sum_l Lambda_ml E_l
+//   D_xk w = (X_k + a_k w) / (2 H),  H = J h.
+// One lane per node row; node values of the tile (fluxes, w, Lambda) in LDS;
+// the skew operators are read through the caches (rows read transposed, S
+// being stored exactly skew).
+template <int P, typename T>
+__global__ __launch_bounds__(kThreads, 2) void k_split3c(KArgs<T> A) {
+  constexpr int D = 3, NC = 5;
+  constexpr int NP = Shape<3, P>::NP, NF = Shape<3, P>::NF;
+  constexpr int EB = VTile3<P, T>::EB;
+  static_assert(EB * NP <= kThreads, "one node per lane");
+  // per node: f^(1)[5] f^(2)[5] f^(3)[5] w[5] Lambda[9] (odd stride: rows of
+  // the lanes of a wave fall in different banks)
+  constexpr int NV = 29;
+  constexpr int NDS = NP * NV;
+  __shared__ T nd[EB * NDS];
+  __shared__ T gs[EB][30];
+  const int tid = threadIdx.x;
+  const T cb = A.G.cb;
+  const T hv = (T)0.5 * (cb - (T)1), he = (T)0.5 * (cb + (T)1);
+  double ent = 0.0;
+  const int ntiles = (A.n_elem + EB - 1) / EB;
+  const int e = tid / NP, i = tid % NP;
+  for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    const int e0 = tl * EB;
+    const int ne = min(EB, A.n_elem - e0);
+    const bool act = tid < ne * NP;
+    __syncthreads();
+    for (int x = tid; x < ne * 30; x += kThreads) gs[x / 30][x % 30] = (T)A.geo[(size_t)(e0 + x / 30) * 30 + x % 30];
+    __syncthreads();
+    Node<D, T> n;
+    T f[D][NC], L[D][D], J = (T)1;
+    if (act) {
+      // F_kl = dx_k/dxi_l at node i; Lambda = cofactor matrix of F
+      T F[D][D];
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int l = 0; l < D; ++l) F[k][l] = (T)0;
+      const T *g = gs[e];
+#pragma unroll
+      for (int a = 0; a < 10; ++a) {
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+          const T d = A.op.dN[(l * 10 + a) * NP + i];
+#pragma unroll
+          for (int k = 0; k < D; ++k) F[k][l] += d * g[a * 3 + k];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+          const int k1 = (k + 1) % 3, k2 = (k + 2) % 3, l1 = (l + 1) % 3, l2 = (l + 2) % 3;
+          L[k][l] = F[k1][l1] * F[k2][l2] - F[k1][l2] * F[k2][l1];
+        }
+      J = F[0][0] * L[0][0] + F[0][1] * L[0][1] + F[0][2] * L[0][2];
+      const int uo = A.uoff[e0 + e];
+      T uu[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) uu[c] = (T)A.u[uo + c * NP + i];
+      node_from_u<D, T>(uu, A.G, n);
+      if (!n.ok) atomicOr(A.err, 1);
+#pragma unroll
+      for (int m = 0; m < D; ++m) flux_i<D, T>(n, uu[NC - 1], m, f[m]);
+      T *v = nd + e * NDS + i * NV;
+#pragma unroll
+      for (int m = 0; m < D; ++m)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[m * NC + c] = f[m][c];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[15 + c] = n.w[c];
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int l = 0; l < D; ++l) v[20 + k * 3 + l] = L[k][l];
+    }
+    __syncthreads();
+    if (act) {
+      T V[NC], X[D][NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        V[c] = (T)0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) X[k][c] = (T)0;
+      }
+#pragma unroll 1
+      for (int j = 0; j < NP; ++j) {
+        const T s0 = -A.op.S[(0 * NP + j) * NP + i];
+        const T s1 = -A.op.S[(1 * NP + j) * NP + i];
+        const T s2 = -A.op.S[(2 * NP + j) * NP + i];
+        const T *v = nd + e * NDS + j * NV;
+        T cm[D];
+#pragma unroll
+        for (int m = 0; m < D; ++m)
+          cm[m] = s0 * (L[m][0] + v[20 + m * 3 + 0]) + s1 * (L[m][1] + v[20 + m * 3 + 1]) +
+                  s2 * (L[m][2] + v[20 + m * 3 + 2]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          V[c] += cm[0] * v[c];  // one FMA per product
+          V[c] += cm[1] * v[5 + c];
+          V[c] += cm[2] * v[10 + c];
+          X[0][c] += cm[0] * v[15 + c];
+          X[1][c] += cm[1] * v[15 + c];
+          X[2][c] += cm[2] * v[15 + c];
+        }
+      }
+      const T H = J * (T)A.op.h[i], iH = (T)1 / H;
+      T El[D], avec[D];
+#pragma unroll
+      for (int l = 0; l < D; ++l) El[l] = A.op.E[l * NP + i];
+#pragma unroll
+      for (int m = 0; m < D; ++m) avec[m] = L[m][0] * El[0] + L[m][1] * El[1] + L[m][2] * El[2];
+      T r[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        r[c] = iH * (hv * V[c] + he * (avec[0] * f[0][c] + avec[1] * f[1][c] + avec[2] * f[2][c]));
+#pragma unroll
+      for (int dir = 0; dir < D; ++dir) {
+        T gg[NC], tt[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) gg[c] = (T)0.5 * iH * (X[dir][c] + avec[dir] * n.w[c]);
+        jvp_flux<D, T>(n, A.G, dir, gg, tt);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) r[c] -= cb * tt[c];
+      }
+      finish_node<D, NP, NF, T>(A, e0 + e, i, n, H, avec, r, ent);
+    }
+  }
+  block_sum_store(ent, A.ent_part);
+}
+
 // Viscous facet-flux pre-pass, 3D affine: q = B n . F^V(w, grad w) at the
 // facet nodes of every element, in the row form of k_split3v: one lane per
 // facet node row i, G_l,i = sum_j S_l[i][j] w_j (15 FMAs per pair), then
@@ -977,6 +1116,13 @@ struct KernelRef {
 
 // Kernel of a residual slot; form_eff 0: entropy split (Euler), 1: Hadamard,
 // 2: entropy split with the Navier-Stokes terms.
+// Curved tetrahedra (form_eff 3): quadratic maps need p >= 2.
+template <int P, typename T>
+static KernelRef curved3_kernel() {
+  if constexpr (P >= 2) return {reinterpret_cast<const void *>(&k_split3c<P, T>), VTile3<P, T>::EB};
+  return {nullptr, 0};
+}
+
 template <typename T>
 static KernelRef residual_kernel(int dim, int p, int form_eff, int variant) {
 #define SBP_K2(PP)                                                                              \
@@ -995,6 +1141,7 @@ static KernelRef residual_kernel(int dim, int p, int form_eff, int variant) {
   if (dim == 3 && p == PP) {                                                                    \
     if (form_eff == 1) return {reinterpret_cast<const void *>(&k_hadamard<3, PP, T>), HadTile<3, PP, T>::EB}; \
     if (form_eff == 2) return {reinterpret_cast<const void *>(&k_split3<PP, T, true>), 3 * Wave3<PP, T>::CT}; \
+    if (form_eff == 3) return curved3_kernel<PP, T>();                                         \
     const bool sg = skew_from_cache3<PP, T>() != (variant == 1);                                \
     return {sg ? reinterpret_cast<const void *>(&k_split3v<PP, T, true>)                        \
                : reinterpret_cast<const void *>(&k_split3v<PP, T, false>),                      \
@@ -1045,8 +1192,8 @@ int residual_blocks(int dim, int p, int precision, int form_eff, int n_elem, Lau
 
 template <typename T>
 static hipError_t launch_t(int dim, int p, int form, const KArgs<T> &A, hipStream_t s, LaunchCfg cfg) {
-  if (A.visc && (dim != 3 || form != 0)) return hipErrorInvalidValue;
-  const KernelRef k = residual_kernel<T>(dim, p, A.visc ? 2 : form, cfg.variant);
+  if ((A.visc || A.curved) && (dim != 3 || form != 0)) return hipErrorInvalidValue;
+  const KernelRef k = residual_kernel<T>(dim, p, A.visc ? 2 : (A.curved ? 3 : form), cfg.variant);
   if (!k.fn || A.n_elem <= 0) return hipErrorInvalidValue;
   const int nb = launch_grid(k.fn, (A.n_elem + k.eb - 1) / k.eb, cfg.grid);
   KArgs<T> a = A;

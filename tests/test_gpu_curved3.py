@@ -1,0 +1,153 @@
+"""Entropy split on tetrahedra with quadratic maps (Assumption 1: p >= 2)
+against the oracle: residual and entropy rate (FP64, ± dissipation), FP32,
+free stream, sampled elements of the paper's 3D vortex grid, relaxation RK4
+steps, and the refusals of the paths this geometry does not cover."""
+import numpy as np
+import pytest
+
+from tests.gpu_common import rel_err_per_component, say, state, term_scale
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(p, diss, precision=0, desc=None):
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import sbp, workloads as wl
+    desc = wl.curved_tet_mesh(2, 1.0, 0.03) if desc is None else desc
+    m = OracleMesh(desc, p)
+    sch = OracleScheme(m, ph.Gas(), dissipation=diss)
+    mesh = sbp.Mesh(desc, p, dissipation=diss, precision=precision)
+    return m, sch, mesh
+
+
+@pytest.mark.parametrize("p,diss", [(2, False), (2, True), (3, False), (3, True)])
+def test_curved_tets_vs_oracle(p, diss):
+    import torch
+    from oracle import physics as ph
+    say(f"[curved3] p={p} diss={diss}")
+    m, sch, mesh = _setup(p, diss)
+    u = state(m, "random", seed=40 + p, jitter=0.01)
+    r, er = mesh.residual(torch.from_numpy(u).cuda(), entropy_rate=True)
+    mesh.check_device()
+    ro = sch(u)
+    err = rel_err_per_component(r.cpu().numpy(), ro)
+    say("   rel err per component", err.max())
+    assert (err <= 1e-12).all(), err
+    rate_o = sch.entropy_rate(u, ro)
+    scale = sum(np.sum(m.geometry(e)["H"][None, :] * np.abs(ph.entropy_vars(u[e], sch.gas) * ro[e]))
+                for e in range(m.ne))
+    assert abs(float(er.cpu()[0]) - rate_o) <= 1e-12 * scale
+    if not diss:
+        assert abs(float(er.cpu()[0])) <= 1e-12 * scale   # entropy conservative on curved elements
+    mesh.close()
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_curved_tets_fp32(p):
+    import torch
+    from paper_2305_07181_amd import sbp
+    say(f"[curved3] FP32 p={p}")
+    m, sch, mesh = _setup(p, True, precision=sbp.FP32)
+    u = state(m, "random", seed=7, jitter=0.01)
+    r = mesh.residual(torch.from_numpy(u).cuda()).cpu().numpy()
+    err = rel_err_per_component(r, sch(u))
+    say("   FP32 rel err", err.max())
+    assert (err <= 2e-4).all(), err
+    mesh.check_device()
+    mesh.close()
+
+
+def test_curved_tets_free_stream():
+    """A uniform state has zero residual (discrete metric identities of the
+    quadratic map at p >= 2), to the rounding of the summed terms."""
+    import torch
+    say("[curved3] free stream")
+    for p in (2, 3):
+        m, sch, mesh = _setup(p, True)
+        u = np.zeros((m.ne, 5, m.n_p))
+        u[:, 0], u[:, 1], u[:, 2], u[:, 3] = 1.2, 0.3, -0.2, 0.1
+        u[:, 4] = 2.5 + 0.5 * (0.09 + 0.04 + 0.01) / 1.2
+        r = mesh.residual(torch.from_numpy(u).cuda()).cpu().numpy()
+        sc = term_scale(sch, u, range(m.ne))
+        say(f"   p={p}: max |r| / term scale", (np.abs(r).max(axis=(0, 2)) / sc).max())
+        assert (np.abs(r).max(axis=(0, 2)) <= 1e-13 * sc).all()
+        mesh.close()
+
+
+def test_paper_vortex3d_grid_sampled():
+    """The paper's curved 3D vortex grid (6^3 x 6 tetrahedra, p = 3, eq. curve
+    3d vortex) with a smooth state: sampled elements against the oracle."""
+    import torch
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say("[curved3] paper vortex grid, sampled")
+    desc = wl.paper_vortex3d_mesh(6)
+    m = OracleMesh(desc, 3)
+    sch = OracleScheme(m, ph.Gas(), dissipation=True)
+    u = state(m, "random", seed=12)
+    mesh = sbp.Mesh(desc, 3, dissipation=True)
+    r = mesh.residual(torch.from_numpy(u).cuda()).cpu().numpy()
+    mesh.check_device()
+    els = np.random.default_rng(3).choice(m.ne, 16, replace=False)
+    ro = sch(u, elements=els)
+    sc = term_scale(sch, u, els)
+    err = np.abs(r[els] - ro).max(axis=(0, 2)) / sc
+    say("   err / term scale", err.max(), " (plain rel:", rel_err_per_component(r[els], ro).max(), ")")
+    assert (err <= 1e-12).all(), err
+    mesh.close()
+
+
+def test_curved_tets_rrk_steps():
+    """Two relaxation RK4 steps on curved tetrahedra: the state follows the
+    oracle's steps and the entropy is conserved per step."""
+    import torch
+    from oracle import rrk
+    say("[curved3] RRK")
+    m, sch, mesh = _setup(2, False)
+    u = state(m, "random", seed=5, jitter=0.005)
+    ud = torch.from_numpy(u).cuda()
+    uo = u.copy()
+    dt = 2e-3
+    for step in range(2):
+        rep = mesh.rrk_step(ud, dt=dt)
+        uo, g, _, _ = rrk.rrk4_step(sch, uo, dt)
+        ds = rep["entropy_after"] - rep["entropy_before"]
+        say(f"   step {step}: gamma {rep['gamma']:.15f} oracle {g:.15f} entropy change {ds:.2e}")
+        assert abs(ds) <= 64 * 2.2e-16 * abs(rep["entropy_before"])
+    err = rel_err_per_component(ud.cpu().numpy(), uo)
+    say("   state rel err", err.max())
+    assert (err <= 1e-10).all(), err
+    mesh.check_device()
+    mesh.close()
+
+
+def test_curved_tets_refusals():
+    import torch
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say("[curved3] refusals")
+    desc = wl.curved_tet_mesh(2, 2.0, 0.03)
+    with pytest.raises(sbp.SbpError) as ei:          # Assumption 1: p >= 2
+        sbp.Mesh(desc, 1)
+    assert ei.value.code == sbp.SBP_EINVAL
+    for kw in (dict(viscous=True, mu=0.01), dict(form=sbp.FORM_HADAMARD)):
+        with pytest.raises(sbp.SbpError) as ei:
+            sbp.Mesh(desc, 2, **kw)
+        assert ei.value.code == sbp.SBP_ENOTSUP
+    mesh = sbp.Mesh(desc, 2)
+    u = torch.ones(mesh.state_shape(), dtype=torch.float64, device="cuda")
+    with pytest.raises(sbp.SbpError) as ei:
+        mesh.vjp(u, u)
+    assert ei.value.code == sbp.SBP_ENOTSUP
+    with pytest.raises(sbp.SbpError) as ei:
+        mesh.set_volume_form(torch.zeros(mesh.n_elem, dtype=torch.uint8, device="cuda"))
+    assert ei.value.code == sbp.SBP_ENOTSUP
+    mesh.set_source()
+    with pytest.raises(sbp.SbpError) as ei:
+        mesh.source_error(mesh.source_state(0.0), 0.0)
+    assert ei.value.code == sbp.SBP_ENOTSUP
+    mesh.source_error(mesh.source_state(0.0), 0.0, norm="nodal")
+    mesh.close()
