@@ -549,7 +549,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_split3c(KArgs<T> A) {
     for (int x = tid; x < ne * 30; x += kThreads) gs[x / 30][x % 30] = (T)A.geo[(size_t)(e0 + x / 30) * 30 + x % 30];
     __syncthreads();
     Node<D, T> n;
-    T f[D][NC], L[D][D], J = (T)1;
+    T L[D][D], J = (T)1;
     if (act) {
       // F_kl = dx_k/dxi_l at node i; Lambda = cofactor matrix of F
       T F[D][D];
@@ -581,13 +581,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_split3c(KArgs<T> A) {
       for (int c = 0; c < NC; ++c) uu[c] = (T)A.u[uo + c * NP + i];
       node_from_u<D, T>(uu, A.G, n);
       if (!n.ok) atomicOr(A.err, 1);
-#pragma unroll
-      for (int m = 0; m < D; ++m) flux_i<D, T>(n, uu[NC - 1], m, f[m]);
+      // the fluxes go to LDS only (read back after the pair loop: fewer live
+      // registers across it)
       T *v = nd + e * NDS + i * NV;
 #pragma unroll
-      for (int m = 0; m < D; ++m)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) v[m * NC + c] = f[m][c];
+      for (int m = 0; m < D; ++m) flux_i<D, T>(n, uu[NC - 1], m, v + m * NC);
 #pragma unroll
       for (int c = 0; c < NC; ++c) v[15 + c] = n.w[c];
 #pragma unroll
@@ -631,10 +629,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_split3c(KArgs<T> A) {
       for (int l = 0; l < D; ++l) El[l] = A.op.E[l * NP + i];
 #pragma unroll
       for (int m = 0; m < D; ++m) avec[m] = L[m][0] * El[0] + L[m][1] * El[1] + L[m][2] * El[2];
+      const T *fi = nd + e * NDS + i * NV;
       T r[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c)
-        r[c] = iH * (hv * V[c] + he * (avec[0] * f[0][c] + avec[1] * f[1][c] + avec[2] * f[2][c]));
+        r[c] = iH * (hv * V[c] + he * (avec[0] * fi[c] + avec[1] * fi[NC + c] + avec[2] * fi[2 * NC + c]));
 #pragma unroll
       for (int dir = 0; dir < D; ++dir) {
         T gg[NC], tt[NC];
