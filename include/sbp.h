@@ -110,9 +110,8 @@ typedef struct {
  * device tables.  `hip_stream` is used for the uploads.  Paper: Sec. 2.1.
  * Curved tetrahedra (p_geom 2 in 3D) need every degree >= 2 (Assumption 1:
  * p_geom <= floor(p/2) + 1), else SBP_EINVAL; with them the viscous terms
- * and the Hadamard form return SBP_ENOTSUP here, and sbp_residual_vjp,
- * sbp_set_volume_form and the quadrature norm of sbp_source_error return
- * SBP_ENOTSUP. */
+ * and the Hadamard form return SBP_ENOTSUP here, and sbp_residual_vjp and
+ * sbp_set_volume_form return SBP_ENOTSUP. */
 int sbp_setup_mesh(const sbp_mesh_desc *desc, const sbp_physics *phys,
                    void *hip_stream, sbp_mesh **out);
 
@@ -170,14 +169,22 @@ int sbp_set_volume_form(sbp_mesh *mesh, const uint8_t *form_dev);
  * time (sbp_set_time), and sbp_rrk_step at each RK stage time t + c_i dt
  * (the entropy rates then include w^T H S).  params = {rho0, a, c, V0}
  * (host, read during the call), or NULL for the paper's {2, 0.1, 0.6, 1}.
+ * kind SBP_SOURCE_VORTEX3D selects the 3D isentropic vortex of the accuracy
+ * study (Sec. 7.3; r^2 = x1^2 + (x2 - t)^2, g = exp(1 - r^2),
+ * rho = (1 - 2/25 (gamma-1) g)^(1/(gamma-1)), V = (-2/5 (x2-t) g^(1/2),
+ * 1 + 2/5 x1 g^(1/2), 0), p = rho^gamma / gamma): an exact solution of the
+ * Euler equations, so no source term is added; it only sets the fields of
+ * sbp_source_state and sbp_source_error (3D meshes, params ignored; the
+ * fields decay like exp(-r^2), so a box such as the paper's [-10,10]^3 is
+ * periodic to rounding).
  * kind SBP_SOURCE_NONE removes the source.  SBP_EINVAL for an unknown kind,
  * non-finite parameters, rho0 - |a| <= d V0^2 / 2 (the pressure would not
  * stay positive) or a box side that is not a multiple of 2 (the fields have
  * period 2 in every x_i). */
-enum { SBP_SOURCE_NONE = 0, SBP_SOURCE_NS_MMS = 1 };
+enum { SBP_SOURCE_NONE = 0, SBP_SOURCE_NS_MMS = 1, SBP_SOURCE_VORTEX3D = 2 };
 int sbp_set_source(sbp_mesh *mesh, int32_t kind, const double *params);
 
-/* u_dev (FP64, state layout) = the manufactured fields of the source set by
+/* u_dev (FP64, state layout) = the fields of the source set by
  * sbp_set_source at the SBP nodes at time t.  SBP_EINVAL when no source is
  * set.  Asynchronous on hip_stream. */
 int sbp_source_state(sbp_mesh *mesh, double t, void *u_dev, void *hip_stream);
@@ -188,7 +195,7 @@ int sbp_source_state(sbp_mesh *mesh, double t, void *u_dev, void *hip_stream);
  *     of each element are fitted by a polynomial of degree p (least squares
  *     weighted by the reference norm h, exact for degree p) and the squared
  *     error integrated with a collapsed Gauss-Legendre rule of degree 3p + 1
- *     on the element's map (the curved map in 2D);
+ *     on the element's map (affine or quadratic);
  *   norm SBP_NORM_NODAL: sum_k (u_k - u*_k)^T H_k (u_k - u*_k) at the nodes.
  * FP64; synchronises hip_stream.  The rule's device tables are built on the
  * first quadrature call.  SBP_EINVAL when no source is set or for an unknown

@@ -39,7 +39,8 @@ constant state (a = 0), and by the total energy rho^2 that the paper's
 pressure gives when |V|^2 = d; the quadrature norm by exact monomial
 integrals on the simplex, exact reproduction of degree-p polynomials, a
 constant offset integrating to its square times the box volume on curved
-and affine grids, and the p + 1 decay of the interpolation error.
+and affine grids, and the p + 1 decay of the interpolation error; the 3D vortex by the
+Euler equations it satisfies (fourth-order differences of physics.flux).
 """
 from __future__ import annotations
 
@@ -112,6 +113,25 @@ def l2_error(u, x, t, H, gas, par=PAPER):
     ue = state(np.moveaxis(x, 1, 0), t, gas, par)       # [n_c, ne, n_p]
     err = u - np.moveaxis(ue, 0, 1)
     return np.einsum("en,ecn->c", H, err * err)
+
+
+def vortex3d_state(x, t, gas):
+    """The 3D isentropic vortex of the accuracy study (Sec. 7.3) at points
+    x[3, ...], time t: with r^2 = x1^2 + (x2 - t)^2 and g = exp(1 - r^2),
+      rho = (1 - 2/25 (gamma - 1) g)^(1/(gamma - 1)),
+      V = (-2/5 (x2 - t) g^(1/2), 1 + 2/5 x1 g^(1/2), 0),
+      e = rho^gamma / (gamma (gamma - 1)) + rho |V|^2 / 2  (p = rho^gamma / gamma).
+    The printed exponent of V_1 is garbled; it is read as that of V_2 (the
+    vortex centred on the x2 axis, advected along x2 at unit speed)."""
+    g = gas.gamma
+    y = x[1] - t
+    ex = np.exp(1.0 - x[0] ** 2 - y ** 2)
+    rho = (1.0 - 2.0 / 25.0 * (g - 1.0) * ex) ** (1.0 / (g - 1.0))
+    V1 = -0.4 * y * np.sqrt(ex)
+    V2 = 1.0 + 0.4 * x[0] * np.sqrt(ex)
+    p = rho ** g / g
+    e = p / (g - 1.0) + 0.5 * rho * (V1 * V1 + V2 * V2)
+    return np.stack([rho, rho * V1, rho * V2, 0.0 * rho, e], 0)
 
 
 def simplex_rule(dim, k):

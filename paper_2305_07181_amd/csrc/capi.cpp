@@ -693,7 +693,8 @@ int residual_core(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStr
 // entropy rate then sums w^T H r of both parts.
 int residual_impl(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStream_t s,
                   const double *t0 = nullptr, const double *dt = nullptr, double c = 0.0) {
-  if (!M->src_kind) return residual_core(M, u, r, ent_dev, s);
+  // the vortex is an exact Euler solution: no source term
+  if (!M->src_kind || M->src_kind == SBP_SOURCE_VORTEX3D) return residual_core(M, u, r, ent_dev, s);
   int rc;
   if ((rc = residual_core(M, u, r, ent_dev ? M->d_scal + SC_SRC : nullptr, s))) return rc;
   if (!t0) {
@@ -1183,7 +1184,10 @@ int sbp_set_volume_form(sbp_mesh *M, const uint8_t *form_dev) {
 
 int sbp_set_source(sbp_mesh *M, int32_t kind, const double *params) {
   if (!M) return fail(SBP_EINVAL, "null handle");
-  if (kind != SBP_SOURCE_NONE && kind != SBP_SOURCE_NS_MMS) return fail(SBP_EINVAL, "unknown source kind");
+  if (kind != SBP_SOURCE_NONE && kind != SBP_SOURCE_NS_MMS && kind != SBP_SOURCE_VORTEX3D)
+    return fail(SBP_EINVAL, "unknown source kind");
+  if (kind == SBP_SOURCE_VORTEX3D && M->dim != 3) return fail(SBP_EINVAL, "the 3D vortex needs a 3D mesh");
+  M->src.kind = kind;
   if (kind == SBP_SOURCE_NS_MMS) {
     const double def[4] = {2.0, 0.1, 0.6, 1.0};
     const double *q = params ? params : def;
@@ -1246,6 +1250,18 @@ int ensure_error_rule(sbp_mesh *M, DegreeClass &c, hipStream_t s) {
     }
     tab.insert(tab.end(), N.begin(), N.end());
     tab.insert(tab.end(), dN.begin(), dN.end());
+  } else if (M->curved3) {
+    std::vector<double> N((size_t)R.nq * 10), dN((size_t)3 * R.nq * 10);
+    for (int q = 0; q < R.nq; ++q) {
+      double n[10], d[3][10];
+      p2t_basis(&R.xi[(size_t)3 * q], n, d);
+      for (int a = 0; a < 10; ++a) {
+        N[(size_t)q * 10 + a] = n[a];
+        for (int l = 0; l < 3; ++l) dN[((size_t)l * R.nq + q) * 10 + a] = d[l][a];
+      }
+    }
+    tab.insert(tab.end(), N.begin(), N.end());
+    tab.insert(tab.end(), dN.begin(), dN.end());
   }
   int rc;
   if ((rc = upload(c.d_eq, tab, s))) return rc;
@@ -1258,8 +1274,6 @@ int sbp_source_error(sbp_mesh *M, const void *u_dev, double t, int32_t norm, dou
   if (!M || !u_dev || !out_host) return fail(SBP_EINVAL, "null argument");
   if (!M->src_kind) return fail(SBP_EINVAL, "no source set");
   if (norm != SBP_NORM_NODAL && norm != SBP_NORM_QUADRATURE) return fail(SBP_EINVAL, "unknown norm");
-  if (norm == SBP_NORM_QUADRATURE && M->curved3)
-    return fail(SBP_ENOTSUP, "the quadrature norm covers triangles and affine tetrahedra");
   hipStream_t s = (hipStream_t)stream;
   for (auto &c : M->cls) {
     sbp::NodeArgs A = node_args(M, c, (const double *)u_dev, nullptr);
@@ -1268,7 +1282,8 @@ int sbp_source_error(sbp_mesh *M, const void *u_dev, double t, int32_t norm, dou
     } else {
       int rc;
       if ((rc = ensure_error_rule(M, c, s))) return rc;
-      HIPCHK(sbp::launch_source_error_quad(A, M->src, t, c.d_eq, c.eq_nq, c.d_geo, M->d_npart + c.node_off_blk, s));
+      HIPCHK(sbp::launch_source_error_quad(A, M->src, t, c.d_eq, c.eq_nq, c.d_geo, M->curved3,
+                                           M->d_npart + c.node_off_blk, s));
     }
   }
   return reduce_nodes(M, M->nc, 0, out_host, s);

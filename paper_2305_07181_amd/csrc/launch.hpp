@@ -68,6 +68,8 @@ struct NodeArgs {
 struct SrcArgs {
   double rho0, a, c, V0;
   double heat;
+  int kind;  // 1: the manufactured solution above; 2: the 3D isentropic vortex of
+             // the accuracy study (an exact Euler solution, no source)
 };
 constexpr int kNodeThreads = 256;
 inline int node_blocks(int n_elem, int np) { return (n_elem * np + kNodeThreads - 1) / kNodeThreads; }
@@ -90,10 +92,11 @@ hipError_t launch_source_state(const NodeArgs &A, const SrcArgs &P, double t, do
 hipError_t launch_source_error(const NodeArgs &A, const SrcArgs &P, double t, double *part, hipStream_t s);
 // part[c*pstride + b] = per component sum of w_q J_q (I u - u*)^2 over the
 // elements and the points of the degree-(3p+1) error rule (tab: I [nq][np],
-// w [nq], 2D: N [nq][6], dN [2][nq][6] of the quadratic map); launched with
+// w [nq], for quadratic maps (2D always; 3D when curved) N [nq][NG],
+// dN [dim][nq][NG] of the map basis, NG = 6 or 10); launched with
 // node_blocks(n_elem, np) workgroups like the other node kernels
 hipError_t launch_source_error_quad(const NodeArgs &A, const SrcArgs &P, double t, const double *tab, int nq,
-                                   const double *geo, double *part, hipStream_t s);
+                                   const double *geo, int curved, double *part, hipStream_t s);
 // out[v] = reduction over part[v*nb + b], b < nb (op 0: sum, 1: min); fixed order.
 hipError_t launch_reduce(const double *part, int nb, int nv, int op, double *out, hipStream_t s);
 // y = x + a s z (x null: y = a s z), z double or float (z_f32), n doubles,

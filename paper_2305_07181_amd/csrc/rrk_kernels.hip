@@ -193,15 +193,55 @@ __device__ __forceinline__ void mms_point(double sx, double gamma, const SrcArgs
   }
 }
 
-// the fields (u) and source (S) at SBP node j of element e (either may be null)
+// The 3D isentropic vortex of the accuracy study (Sec. 7.3), an exact Euler
+// solution: with r^2 = x1^2 + (x2 - t)^2 and g = exp(1 - r^2),
+// rho = (1 - 2/25 (gamma-1) g)^(1/(gamma-1)), V = (-2/5 (x2-t) g^(1/2),
+// 1 + 2/5 x1 g^(1/2), 0), p = rho^gamma / gamma.
+__device__ __forceinline__ void vortex3_point(const double *x, double t, double gamma, double *u) {
+  const double y = x[1] - t;
+  const double g = exp(1.0 - x[0] * x[0] - y * y), sg = sqrt(g);
+  const double lr = log(1.0 - 0.08 * (gamma - 1.0) * g) / (gamma - 1.0);
+  const double rho = exp(lr);
+  const double V1 = -0.4 * y * sg, V2 = 1.0 + 0.4 * x[0] * sg;
+  const double p = exp(gamma * lr) / gamma;
+  u[0] = rho;
+  u[1] = rho * V1;
+  u[2] = rho * V2;
+  u[3] = 0.0;
+  u[4] = p / (gamma - 1.0) + 0.5 * rho * (V1 * V1 + V2 * V2);
+}
+
+// the fields of the study selected by P.kind at the point x[D]
+template <int D>
+__device__ __forceinline__ void fields_at(const double *x, double t, const SrcArgs &P, double gamma, double *u) {
+  if constexpr (D == 3) {
+    if (P.kind == 2) {
+      vortex3_point(x, t, gamma, u);
+      return;
+    }
+  }
+  double sx = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) sx += x[i];
+  mms_point<D>(sx, gamma, P, t, u, nullptr);
+}
+
+// the source (S, manufactured solution) or the fields (u) at SBP node j of
+// element e (either may be null; S only for the manufactured solution)
 template <int D>
 __device__ __forceinline__ void mms_node(const NodeArgs &A, const SrcArgs &P, int e, int j, double t, double *u,
                                          double *S) {
-  const double *x = A.xyz + (size_t)(A.uoff[e] / (D + 2)) * D + j;
-  double sx = 0.0;
+  const double *xn = A.xyz + (size_t)(A.uoff[e] / (D + 2)) * D + j;
+  double x[D];
 #pragma unroll
-  for (int i = 0; i < D; ++i) sx += x[i * A.np];
-  mms_point<D>(sx, A.gamma, P, t, u, S);
+  for (int i = 0; i < D; ++i) x[i] = xn[i * A.np];
+  if (u) fields_at<D>(x, t, P, A.gamma, u);
+  if (S) {
+    double sx = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) sx += x[i];
+    mms_point<D>(sx, A.gamma, P, t, nullptr, S);
+  }
 }
 
 template <int D, typename R>
@@ -238,18 +278,19 @@ __global__ __launch_bounds__(kT) void k_source_add(NodeArgs A, SrcArgs P, R *r, 
 // The error of the grid studies (Sec. 7.3): per component sum over elements
 // and points q of a degree-(3p+1) rule of w_q J_q (I u - u*)^2(x_q), with I
 // the degree-p fit from the nodes to the points.  One thread per (element,
-// point), grid-stride over the class.  tab: I [nq][np], w [nq] and, in 2D,
-// the quadratic map's basis N [nq][6] and its derivatives dN [2][nq][6] at
-// the points (x_q and J_q from the element's map nodes geo[e][6][2]); in 3D
-// the affine map is reproduced by I applied to the node coordinates and J
-// is the element's constant (geo[e][9]).
+// point), grid-stride over the class.  tab: I [nq][np], w [nq] and, for
+// quadratic maps, the map basis N [nq][NG] and its derivatives dN [D][nq][NG]
+// at the points (NG = 6 map nodes in 2D, 10 in 3D; x_q and J_q from the
+// element's map nodes geo[e][NG][D]); on affine tetrahedra the map is
+// reproduced by I applied to the node coordinates and J is the element's
+// constant (geo[e][9]).
 template <int D>
 __global__ __launch_bounds__(kT) void k_source_error_quad(NodeArgs A, SrcArgs P, double t, const double *tab, int nq,
-                                                           const double *geo, double *part) {
-  constexpr int NC = D + 2;
+                                                           const double *geo, int curved, double *part) {
+  constexpr int NC = D + 2, NG = D == 2 ? 6 : 10;
   __shared__ double red[kT / 64];
   const double *I = tab, *W = tab + (size_t)nq * A.np;
-  const double *N = W + nq, *dN = N + (size_t)nq * 6;
+  const double *N = W + nq, *dN = N + (size_t)nq * NG;
   double v[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) v[k] = 0.0;
@@ -266,27 +307,38 @@ __global__ __launch_bounds__(kT) void k_source_error_quad(NodeArgs A, SrcArgs P,
 #pragma unroll
       for (int k = 0; k < NC; ++k) uq[k] += c * A.u[base + k * A.np + j];
     }
-    double sx = 0.0, J;
-    if (D == 2) {
-      const double *g = geo + (size_t)e * 12;
-      double F[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-      for (int a = 0; a < 6; ++a) {
-        const double n = N[q * 6 + a], d0 = dN[q * 6 + a], d1 = dN[(nq + q) * 6 + a];
-        sx += n * (g[2 * a] + g[2 * a + 1]);
-        F[0][0] += d0 * g[2 * a];
-        F[0][1] += d1 * g[2 * a];
-        F[1][0] += d0 * g[2 * a + 1];
-        F[1][1] += d1 * g[2 * a + 1];
+    double x[D], J;
+#pragma unroll
+    for (int i = 0; i < D; ++i) x[i] = 0.0;
+    if (D == 2 || curved) {
+      const double *g = geo + (size_t)e * NG * D;
+      double F[D][D];
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int l = 0; l < D; ++l) F[i][l] = 0.0;
+      for (int a = 0; a < NG; ++a) {
+        const double n = N[q * NG + a];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          x[i] += n * g[a * D + i];
+#pragma unroll
+          for (int l = 0; l < D; ++l) F[i][l] += dN[(l * nq + q) * NG + a] * g[a * D + i];
+        }
       }
-      J = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+      if constexpr (D == 2)
+        J = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+      else
+        J = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
+            F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
     } else {
       const double *xn = A.xyz + (size_t)(base / NC) * D;
       for (int i = 0; i < D; ++i)
-        for (int j = 0; j < A.np; ++j) sx += Iq[j] * xn[i * A.np + j];
+        for (int j = 0; j < A.np; ++j) x[i] += Iq[j] * xn[i * A.np + j];
       J = geo[(size_t)e * 10 + 9];
     }
     double ue[NC];
-    mms_point<D>(sx, A.gamma, P, t, ue, nullptr);
+    fields_at<D>(x, t, P, A.gamma, ue);
     const double wj = W[q] * J;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
@@ -445,12 +497,12 @@ hipError_t launch_source_state(const NodeArgs &A, const SrcArgs &P, double t, do
 }
 
 hipError_t launch_source_error_quad(const NodeArgs &A, const SrcArgs &P, double t, const double *tab, int nq,
-                                   const double *geo, double *part, hipStream_t s) {
+                                   const double *geo, int curved, double *part, hipStream_t s) {
   const int nb = node_blocks(A.n_elem, A.np);
   if (A.dim == 2)
-    hipLaunchKernelGGL(k_source_error_quad<2>, dim3(nb), dim3(kT), 0, s, A, P, t, tab, nq, geo, part);
+    hipLaunchKernelGGL(k_source_error_quad<2>, dim3(nb), dim3(kT), 0, s, A, P, t, tab, nq, geo, curved, part);
   else
-    hipLaunchKernelGGL(k_source_error_quad<3>, dim3(nb), dim3(kT), 0, s, A, P, t, tab, nq, geo, part);
+    hipLaunchKernelGGL(k_source_error_quad<3>, dim3(nb), dim3(kT), 0, s, A, P, t, tab, nq, geo, curved, part);
   return hipGetLastError();
 }
 

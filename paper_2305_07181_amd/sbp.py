@@ -20,7 +20,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsbp.so"
 SBP_OK, SBP_EINVAL, SBP_ENOMEM, SBP_EDEVICE, SBP_ENOTSUP, SBP_ENONPHYS, SBP_ERRK = 0, -1, -2, -3, -4, -5, -6
 FORM_SPLIT, FORM_HADAMARD = 0, 1
 FP64, FP32 = 0, 1
-SOURCE_NONE, SOURCE_NS_MMS = 0, 1
+SOURCE_NONE, SOURCE_NS_MMS, SOURCE_VORTEX3D = 0, 1, 2
 NORM_NODAL, NORM_QUADRATURE = 0, 1
 
 SYMBOLS = ["sbp_setup_mesh", "sbp_mesh_info", "sbp_residual", "sbp_residual_vjp", "sbp_rrk_step",
@@ -289,9 +289,10 @@ class Mesh:
         self._form_flags = flags   # keep the borrowed array alive
 
     def set_source(self, kind=None, params=None):
-        """Manufactured-solution source (sbp_set_source): kind SOURCE_NS_MMS
-        (default) with params (rho0, a, c, V0) or None for the paper's
-        values; kind SOURCE_NONE removes it."""
+        """Fields and source of a study (sbp_set_source): kind SOURCE_NS_MMS
+        (default; the manufactured solution, params (rho0, a, c, V0) or None
+        for the paper's values), SOURCE_VORTEX3D (the 3D isentropic vortex,
+        no source term) or SOURCE_NONE."""
         kind = SOURCE_NS_MMS if kind is None else int(kind)
         par = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
         if par is not None and par.shape != (4,):

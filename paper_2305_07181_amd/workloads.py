@@ -326,13 +326,19 @@ def curved_tet_mesh(n: int, L: float, warp: float) -> dict:
     return desc
 
 
-def paper_vortex3d_mesh(n: int) -> dict:
+def paper_vortex3d_mesh(n: int, quadratic: bool = True) -> dict:
     """Grid of the paper's 3D isentropic-vortex study (Sec. 7.3): the
-    periodic box [-10,10]^3 in n^3 cubes of six tetrahedra, the quadratic map
-    nodes moved by x_i = x^_i + 0.05 sin(pi x^_i / 2) (eq. curve 3d vortex),
-    which fixes the box faces."""
+    periodic box [-10,10]^3 in n^3 cubes of six tetrahedra, moved by
+    x_i = x^_i + 0.05 sin(pi x^_i / 2) (eq. curve 3d vortex), which fixes the
+    box faces: the quadratic map nodes (quadratic=True, degrees p >= 2), or
+    only the vertices of affine tetrahedra (p = 1, the map degree Assumption
+    1 allows there)."""
     desc = periodic_tet_mesh(n, 20.0)
     desc["vert_xyz"] = desc["vert_xyz"] - 10.0
+    if not quadratic:
+        v = desc["vert_xyz"]
+        desc["vert_xyz"] = np.ascontiguousarray(v + 0.05 * np.sin(0.5 * np.pi * v))
+        return desc
     g = _tet_p2_nodes(desc)
     desc["p_geom"] = 2
     desc["geom_nodes"] = np.ascontiguousarray(g + 0.05 * np.sin(0.5 * np.pi * g))

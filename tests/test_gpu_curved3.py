@@ -1,7 +1,8 @@
 """Entropy split on tetrahedra with quadratic maps (Assumption 1: p >= 2)
 against the oracle: residual and entropy rate (FP64, ± dissipation), FP32,
 free stream, sampled elements of the paper's 3D vortex grid, relaxation RK4
-steps, and the refusals of the paths this geometry does not cover."""
+steps, the 3D vortex of the accuracy study with the studies' error norm,
+and the refusals of the paths this geometry does not cover."""
 import numpy as np
 import pytest
 
@@ -145,9 +146,56 @@ def test_curved_tets_refusals():
     with pytest.raises(sbp.SbpError) as ei:
         mesh.set_volume_form(torch.zeros(mesh.n_elem, dtype=torch.uint8, device="cuda"))
     assert ei.value.code == sbp.SBP_ENOTSUP
-    mesh.set_source()
-    with pytest.raises(sbp.SbpError) as ei:
-        mesh.source_error(mesh.source_state(0.0), 0.0)
-    assert ei.value.code == sbp.SBP_ENOTSUP
-    mesh.source_error(mesh.source_state(0.0), 0.0, norm="nodal")
     mesh.close()
+
+
+@pytest.mark.parametrize("p,quadratic", [(1, False), (2, True), (3, True)])
+def test_vortex3d_fields_and_error_norm(p, quadratic):
+    """The 3D vortex of the accuracy study: its nodal fields, the studies'
+    error norm on affine and curved tetrahedra against the oracle's, and no
+    source term (the residual is the plain one)."""
+    import torch
+    from oracle import mms
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say(f"[curved3] vortex3d p={p} quadratic={quadratic}")
+    desc = wl.paper_vortex3d_mesh(3, quadratic=quadratic)
+    m = OracleMesh(desc, p)
+    gas = ph.Gas()
+    mesh = sbp.Mesh(desc, p)
+    u_plain = None
+    t = 0.4
+    xs = np.moveaxis(m.node_coords(), 1, 0)
+    ue = np.ascontiguousarray(np.moveaxis(mms.vortex3d_state(xs, t, gas), 0, 1))
+    up = np.ascontiguousarray(ue * (1.0 + 0.01 * np.random.default_rng(p).standard_normal(ue.shape)))
+    ud = torch.from_numpy(up).cuda()
+    u_plain = mesh.residual(ud).cpu().numpy()
+    mesh.set_source(sbp.SOURCE_VORTEX3D)
+    ug = mesh.source_state(t).cpu().numpy().reshape(ue.shape)
+    assert (rel_err_per_component(ug[:, [0, 1, 2, 4]], ue[:, [0, 1, 2, 4]]) <= 1e-14).all()
+    assert np.abs(ug[:, 3]).max() == 0.0
+    assert np.array_equal(mesh.residual(ud).cpu().numpy(), u_plain)
+    exact = lambda x: mms.vortex3d_state(x, t, gas)
+    for uu in (up, ue):
+        e = mesh.source_error(torch.from_numpy(uu).cuda(), t)
+        eo = mms.l2_error_quadrature(uu, m, exact)
+        say(f"   quadrature norm gpu {e.sum():.6e} oracle {eo.sum():.6e}")
+        assert np.abs(e - eo).max() <= 1e-12 * np.abs(eo).max(), (e, eo)
+    mesh.check_device()
+    mesh.close()
+
+
+def test_vortex3d_study_runs():
+    """A short run of the vortex study on a coarse grid: entropy conserved
+    without dissipation, removed with it, errors finite."""
+    from paper_2305_07181_amd import studies
+    say("[curved3] vortex3d study, coarse")
+    for diss in (False, True):
+        r = studies.vortex3d_run(4, 2, diss, tf=0.2)
+        say("  ", r)
+        assert r["t"] >= 0.2 and 0 < r["l2_error"] < 10.0
+        if diss:
+            assert r["entropy_change"] < 0
+        else:
+            assert abs(r["entropy_change"]) < 1e-12

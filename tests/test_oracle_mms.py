@@ -203,3 +203,33 @@ def test_quadrature_norm_of_nodal_fields_decays_at_p_plus_one(p):
         errs.append(np.sqrt(mms.l2_error_quadrature(u, m, lambda x: mms.state(x, 0.2, gas)).sum()))
     rate = np.log(errs[0] / errs[1]) / np.log(2.0)
     assert p + 0.7 < rate < p + 1.5, (errs, rate)
+
+
+def test_vortex3d_solves_the_euler_equations():
+    """The 3D vortex of the accuracy study (with the reading of its garbled
+    V_1 exponent) satisfies du/dt + div F = 0: fourth-order differences of
+    the oracle's fluxes vanish to the difference error; the misread
+    exponent (x1 - t)^2 in V_1 does not."""
+    gas = ph.Gas()
+    x = np.random.default_rng(4).uniform(-2.0, 2.0, (3, 16))
+    U = lambda xx, tt: mms.vortex3d_state(xx, tt, gas)
+    R = _d4(U, x, 0.3, "t")
+    for i in range(3):
+        R = R + _d4(lambda xx, tt: ph.flux(U(xx, tt), i, gas), x, 0.3, i)
+    assert np.abs(R).max() < 1e-8, np.abs(R).max()
+    assert np.abs(U(x, 0.3)[3]).max() == 0.0
+
+    def misread(xx, tt):
+        u = U(xx, tt)
+        y = xx[1] - tt
+        V1 = -0.4 * y * np.exp(0.5 * (1.0 - (xx[0] - tt) ** 2 - xx[0] ** 2))
+        u2 = u.copy()
+        u2[1] = u[0] * V1
+        V = u2[1:4] / u[0]
+        p = u[0] ** gas.gamma / gas.gamma
+        u2[4] = p / (gas.gamma - 1.0) + 0.5 * u[0] * np.sum(V * V, 0)
+        return u2
+    R2 = _d4(misread, x, 0.3, "t")
+    for i in range(3):
+        R2 = R2 + _d4(lambda xx, tt: ph.flux(misread(xx, tt), i, gas), x, 0.3, i)
+    assert np.abs(R2).max() > 1e-3
