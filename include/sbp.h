@@ -177,11 +177,19 @@ int sbp_set_volume_form(sbp_mesh *mesh, const uint8_t *form_dev);
  * sbp_source_state and sbp_source_error (3D meshes, params ignored; the
  * fields decay like exp(-r^2), so a box such as the paper's [-10,10]^3 is
  * periodic to rounding).
+ * kind SBP_SOURCE_VORTEX2D selects the 2D isentropic vortex of the accuracy
+ * study (Sec. 7.3): strength alpha, centre (xc + t, yc) advected by the free
+ * stream (1, 0), minimum-image distance in the mesh's periodic box,
+ * f = alpha/(2 pi) exp(1 - r^2), V = (1 - f dy, f dx),
+ * T = 1 - alpha^2 (gamma-1)/(16 gamma pi^2) exp(2 (1 - r^2)),
+ * rho = T^(1/(gamma-1)), p = rho^gamma; params = {alpha, xc, yc} or NULL for
+ * the paper's {3, 5, 0}; no source term (2D meshes; SBP_EINVAL if the
+ * temperature at the centre would not be positive).
  * kind SBP_SOURCE_NONE removes the source.  SBP_EINVAL for an unknown kind,
  * non-finite parameters, rho0 - |a| <= d V0^2 / 2 (the pressure would not
  * stay positive) or a box side that is not a multiple of 2 (the fields have
  * period 2 in every x_i). */
-enum { SBP_SOURCE_NONE = 0, SBP_SOURCE_NS_MMS = 1, SBP_SOURCE_VORTEX3D = 2 };
+enum { SBP_SOURCE_NONE = 0, SBP_SOURCE_NS_MMS = 1, SBP_SOURCE_VORTEX3D = 2, SBP_SOURCE_VORTEX2D = 3 };
 int sbp_set_source(sbp_mesh *mesh, int32_t kind, const double *params);
 
 /* u_dev (FP64, state layout) = the fields of the source set by

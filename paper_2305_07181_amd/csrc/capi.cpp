@@ -693,8 +693,8 @@ int residual_core(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStr
 // entropy rate then sums w^T H r of both parts.
 int residual_impl(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStream_t s,
                   const double *t0 = nullptr, const double *dt = nullptr, double c = 0.0) {
-  // the vortex is an exact Euler solution: no source term
-  if (!M->src_kind || M->src_kind == SBP_SOURCE_VORTEX3D) return residual_core(M, u, r, ent_dev, s);
+  // the vortices are exact Euler solutions: no source term
+  if (M->src_kind != SBP_SOURCE_NS_MMS) return residual_core(M, u, r, ent_dev, s);
   int rc;
   if ((rc = residual_core(M, u, r, ent_dev ? M->d_scal + SC_SRC : nullptr, s))) return rc;
   if (!t0) {
@@ -1184,10 +1184,26 @@ int sbp_set_volume_form(sbp_mesh *M, const uint8_t *form_dev) {
 
 int sbp_set_source(sbp_mesh *M, int32_t kind, const double *params) {
   if (!M) return fail(SBP_EINVAL, "null handle");
-  if (kind != SBP_SOURCE_NONE && kind != SBP_SOURCE_NS_MMS && kind != SBP_SOURCE_VORTEX3D)
+  if (kind != SBP_SOURCE_NONE && kind != SBP_SOURCE_NS_MMS && kind != SBP_SOURCE_VORTEX3D &&
+      kind != SBP_SOURCE_VORTEX2D)
     return fail(SBP_EINVAL, "unknown source kind");
   if (kind == SBP_SOURCE_VORTEX3D && M->dim != 3) return fail(SBP_EINVAL, "the 3D vortex needs a 3D mesh");
-  M->src.kind = kind;
+  if (kind == SBP_SOURCE_VORTEX2D) {
+    if (M->dim != 2) return fail(SBP_EINVAL, "the 2D vortex needs a 2D mesh");
+    const double def[3] = {3.0, 5.0, 0.0};
+    const double *q = params ? params : def;
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(q[k])) return fail(SBP_EINVAL, "vortex parameters must be finite");
+    // T > 0 at the centre: alpha^2 (gamma-1) e^2 / (16 gamma pi^2) < 1
+    const double g = M->phys.gamma, e = std::exp(1.0);
+    if (!(q[0] * q[0] * (g - 1.0) * e * e / (16.0 * g * M_PI * M_PI) < 1.0))
+      return fail(SBP_EINVAL, "vortex too strong (negative temperature at its centre)");
+    M->src.alpha = q[0];
+    M->src.xc = q[1];
+    M->src.yc = q[2];
+    M->src.px = M->period[0];
+    M->src.py = M->period[1];
+  }
   if (kind == SBP_SOURCE_NS_MMS) {
     const double def[4] = {2.0, 0.1, 0.6, 1.0};
     const double *q = params ? params : def;
@@ -1209,6 +1225,7 @@ int sbp_set_source(sbp_mesh *M, int32_t kind, const double *params) {
     // kappa (gamma-1)/R with kappa = mu c_p / Pr, c_p = gamma R / (gamma-1)
     M->src.heat = (ph.viscous && ph.heat_flux) ? ph.mu * g / ph.Pr : 0.0;
   }
+  M->src.kind = kind;
   M->src_kind = kind;
   // the captured RK stages hold the previous launches
   if (M->rk_exec) {

@@ -69,7 +69,10 @@ struct SrcArgs {
   double rho0, a, c, V0;
   double heat;
   int kind;  // 1: the manufactured solution above; 2: the 3D isentropic vortex of
-             // the accuracy study (an exact Euler solution, no source)
+             // the accuracy study (an exact Euler solution, no source); 3: the 2D
+             // isentropic vortex of the accuracy study (idem)
+  double alpha, xc, yc;  // 2D vortex: strength and centre at t = 0
+  double px, py;         // 2D vortex: box periods (minimum-image distance)
 };
 constexpr int kNodeThreads = 256;
 inline int node_blocks(int n_elem, int np) { return (n_elem * np + kNodeThreads - 1) / kNodeThreads; }

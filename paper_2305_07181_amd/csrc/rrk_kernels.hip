@@ -211,12 +211,38 @@ __device__ __forceinline__ void vortex3_point(const double *x, double t, double 
   u[4] = p / (gamma - 1.0) + 0.5 * rho * (V1 * V1 + V2 * V2);
 }
 
+// The 2D isentropic vortex of the accuracy study (Sec. 7.3): centre
+// (xc + t, yc) advected by the free stream (1, 0), minimum-image distance in
+// the periodic box, r^2 = dx^2 + dy^2, f = alpha/(2 pi) exp(1 - r^2):
+// V = (1 - f dy, f dx), T = 1 - alpha^2 (gamma-1)/(16 gamma pi^2) exp(2(1 - r^2)),
+// rho = T^(1/(gamma-1)), p = rho^gamma.
+__device__ __forceinline__ void vortex2_point(const double *x, double t, const SrcArgs &P, double gamma, double *u) {
+  double dx = x[0] - (P.xc + t), dy = x[1] - P.yc;
+  dx -= P.px * rint(dx / P.px);
+  dy -= P.py * rint(dy / P.py);
+  const double e1 = exp(1.0 - dx * dx - dy * dy);
+  const double T = 1.0 - P.alpha * P.alpha * (gamma - 1.0) / (16.0 * gamma * M_PI * M_PI) * e1 * e1;
+  const double lr = log(T) / (gamma - 1.0);
+  const double rho = exp(lr), p = exp(gamma * lr);
+  const double f = P.alpha / (2.0 * M_PI) * e1;
+  const double V0 = 1.0 - f * dy, V1 = f * dx;
+  u[0] = rho;
+  u[1] = rho * V0;
+  u[2] = rho * V1;
+  u[3] = p / (gamma - 1.0) + 0.5 * rho * (V0 * V0 + V1 * V1);
+}
+
 // the fields of the study selected by P.kind at the point x[D]
 template <int D>
 __device__ __forceinline__ void fields_at(const double *x, double t, const SrcArgs &P, double gamma, double *u) {
   if constexpr (D == 3) {
     if (P.kind == 2) {
       vortex3_point(x, t, gamma, u);
+      return;
+    }
+  } else {
+    if (P.kind == 3) {
+      vortex2_point(x, t, P, gamma, u);
       return;
     }
   }

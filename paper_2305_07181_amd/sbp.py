@@ -20,7 +20,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsbp.so"
 SBP_OK, SBP_EINVAL, SBP_ENOMEM, SBP_EDEVICE, SBP_ENOTSUP, SBP_ENONPHYS, SBP_ERRK = 0, -1, -2, -3, -4, -5, -6
 FORM_SPLIT, FORM_HADAMARD = 0, 1
 FP64, FP32 = 0, 1
-SOURCE_NONE, SOURCE_NS_MMS, SOURCE_VORTEX3D = 0, 1, 2
+SOURCE_NONE, SOURCE_NS_MMS, SOURCE_VORTEX3D, SOURCE_VORTEX2D = 0, 1, 2, 3
 NORM_NODAL, NORM_QUADRATURE = 0, 1
 
 SYMBOLS = ["sbp_setup_mesh", "sbp_mesh_info", "sbp_residual", "sbp_residual_vjp", "sbp_rrk_step",
@@ -291,12 +291,15 @@ class Mesh:
     def set_source(self, kind=None, params=None):
         """Fields and source of a study (sbp_set_source): kind SOURCE_NS_MMS
         (default; the manufactured solution, params (rho0, a, c, V0) or None
-        for the paper's values), SOURCE_VORTEX3D (the 3D isentropic vortex,
-        no source term) or SOURCE_NONE."""
+        for the paper's values), SOURCE_VORTEX3D or SOURCE_VORTEX2D (the
+        isentropic vortices of the accuracy studies, no source term; the 2D
+        one takes (alpha, xc, yc)) or SOURCE_NONE."""
         kind = SOURCE_NS_MMS if kind is None else int(kind)
         par = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
-        if par is not None and par.shape != (4,):
-            raise ValueError("params must hold rho0, a, c, V0")
+        need = {SOURCE_NS_MMS: 4, SOURCE_VORTEX2D: 3}.get(kind)
+        if par is not None and need is not None and par.shape != (need,):
+            raise ValueError("params: (rho0, a, c, V0) for the manufactured solution, "
+                             "(alpha, xc, yc) for the 2D vortex")
         _check(_lib.sbp_set_source(self._h, kind, _dp(par) if par is not None else None))
 
     def source_state(self, t, u=None, stream=None):

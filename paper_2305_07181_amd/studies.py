@@ -4,6 +4,8 @@
         [--ps 1 2 3 4] [--tf 2.0] [--cfl 0.1]
     python -m paper_2305_07181_amd.studies mms --dim 3 [--ns 6 9 12 15]
         [--ps 1 2 3] [--tf 0.001] [--steps 1000] [--mu 0.01]
+    python -m paper_2305_07181_amd.studies vortex2d [--ns 60 80 100 120]
+        [--ps 1 2 3 4] [--tf 2.0] [--cfl 0.1]
     python -m paper_2305_07181_amd.studies vortex3d [--ns 15 20 25 30]
         [--ps 1 2 3] [--tf 1.0] [--cfl 0.25]
 
@@ -32,6 +34,12 @@ study and the equations the Euler equations (the viscous terms of this
 library cover tetrahedra); in 3D the Navier-Stokes equations (mu, Pr = 0.71,
 R = 1, heat flux on, no interface dissipation) on affine tetrahedra (the
 study's curving map is not applied in 3D).
+
+2D isentropic vortex (Sec. 7.3, Table accuracy vortex 2d): the vortex of
+sbp_set_source(SOURCE_VORTEX2D) on the curved grids n^2 x 2 of the
+conservation study, conservative and dissipative SATs, relaxation RK4 at
+CFL 0.1 until the first step at or past t_f = 2, the error in the paper's
+norm at the time reached.
 
 3D isentropic vortex (Sec. 7.3, Table accuracy vortex 3d): the vortex of
 sbp_set_source(SOURCE_VORTEX3D) on the paper's curved grids n^3 x 6 of
@@ -138,11 +146,14 @@ def mms_study(dim, ns, ps, tf=1e-3, steps=1000, mu=0.01, emit=print):
     return rows
 
 
-def vortex3d_run(n: int, p: int, dissipation: bool, tf: float = 1.0, cfl: float = 0.25) -> dict:
+def vortex_run(dim: int, n: int, p: int, dissipation: bool, tf: float, cfl: float) -> dict:
     from . import sbp, workloads as wl
-    desc = wl.paper_vortex3d_mesh(n, quadratic=p >= 2)
+    if dim == 2:
+        desc = wl.paper_vortex2d_mesh(n)
+    else:
+        desc = wl.paper_vortex3d_mesh(n, quadratic=p >= 2)
     mesh = sbp.Mesh(desc, p, dissipation=dissipation)
-    mesh.set_source(sbp.SOURCE_VORTEX3D)
+    mesh.set_source(sbp.SOURCE_VORTEX2D if dim == 2 else sbp.SOURCE_VORTEX3D)
     mesh.set_time(0.0)
     u = mesh.source_state(0.0)
     d0 = mesh.diagnostics(u)
@@ -154,20 +165,24 @@ def vortex3d_run(n: int, p: int, dissipation: bool, tf: float = 1.0, cfl: float 
     e = mesh.source_error(u, t, "quadrature")
     d1 = mesh.diagnostics(u)
     mesh.check_device()
-    out = dict(n=n, p=p, n_elem=int(mesh.n_elem), dissipation=dissipation, steps=steps, t=t, seconds=secs,
-               l2_error=math.sqrt(float(e.sum())), entropy_change=(d1[0] - d0[0]) / abs(d0[0]))
+    out = dict(dim=dim, n=n, p=p, n_elem=int(mesh.n_elem), dissipation=dissipation, steps=steps, t=t,
+               seconds=secs, l2_error=math.sqrt(float(e.sum())), entropy_change=(d1[0] - d0[0]) / abs(d0[0]))
     mesh.close()
     return out
 
 
-def vortex3d_study(ns, ps, tf=1.0, cfl=0.25, emit=print):
+def vortex3d_run(n: int, p: int, dissipation: bool, tf: float = 1.0, cfl: float = 0.25) -> dict:
+    return vortex_run(3, n, p, dissipation, tf, cfl)
+
+
+def vortex_study(dim, ns, ps, tf, cfl, emit=print):
     rows = []
     for p in ps:
         for diss in (False, True):
             prev = None
             for n in ns:
-                r = vortex3d_run(n, p, diss, tf, cfl)
-                if prev is not None:   # h = (volume / n_e)^(1/3) falls as 1/n
+                r = vortex_run(dim, n, p, diss, tf, cfl)
+                if prev is not None:   # h = (volume / n_e)^(1/d) falls as 1/n
                     r["rate"] = math.log(prev["l2_error"] / r["l2_error"]) / math.log(n / prev["n"])
                 emit(json.dumps(r))
                 rows.append(r)
@@ -177,7 +192,7 @@ def vortex3d_study(ns, ps, tf=1.0, cfl=0.25, emit=print):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["conservation", "mms", "vortex3d"])
+    ap.add_argument("study", choices=["conservation", "mms", "vortex2d", "vortex3d"])
     ap.add_argument("--ns", type=int, nargs="+")
     ap.add_argument("--ps", type=int, nargs="+")
     ap.add_argument("--tf", type=float)
@@ -190,8 +205,10 @@ def main(argv=None):
     if a.study == "conservation":
         conservation_study(a.ns or [60, 80, 100, 120], a.ps or [1, 2, 3, 4], a.tf or 2.0, a.cfl, emit=emit)
     elif a.study == "vortex3d":
-        vortex3d_study(a.ns or [15, 20, 25, 30], a.ps or [1, 2, 3], a.tf or 1.0, a.cfl if a.cfl != 0.1 else 0.25,
-                       emit=emit)
+        vortex_study(3, a.ns or [15, 20, 25, 30], a.ps or [1, 2, 3], a.tf or 1.0, a.cfl if a.cfl != 0.1 else 0.25,
+                     emit=emit)
+    elif a.study == "vortex2d":
+        vortex_study(2, a.ns or [60, 80, 100, 120], a.ps or [1, 2, 3, 4], a.tf or 2.0, a.cfl, emit=emit)
     else:
         ns = a.ns or ([20, 30, 40, 50] if a.dim == 2 else [6, 9, 12, 15])
         ps = a.ps or ([1, 2, 3, 4] if a.dim == 2 else [1, 2, 3])

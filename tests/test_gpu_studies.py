@@ -64,3 +64,60 @@ def test_mms_study_small(dim, p, ns):
         assert 0 < r["l2_error"] < 1.0 and 0 < r["l2_error_nodal"] < 1e-2
     assert rows[1]["rate"] > p + 0.5, rows[1]["rate"]
     assert rows[1]["rate_nodal"] > p - 0.35, rows[1]["rate_nodal"]
+
+
+def test_vortex2d_fields_and_error_norm():
+    """The 2D vortex of the accuracy study: nodal fields against the input
+    generator's, the studies' error norm against the oracle's on the curved
+    grid, no source term."""
+    import torch
+    from oracle import mms
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say("[study] vortex2d fields and norm")
+    desc = wl.paper_vortex2d_mesh(8)
+    for p in (1, 4):
+        m = OracleMesh(desc, p)
+        gas = ph.Gas()
+        t = 0.7
+        exact = lambda x: _cons(*wl.paper_vortex2d(x, t))
+        xs = np.moveaxis(m.node_coords(), 1, 0)
+        ue = np.ascontiguousarray(np.moveaxis(exact(xs), 0, 1))
+        mesh = sbp.Mesh(desc, p)
+        up = np.ascontiguousarray(ue * (1.0 + 0.01 * np.random.default_rng(p).standard_normal(ue.shape)))
+        ud = torch.from_numpy(up).cuda()
+        r0 = mesh.residual(ud).cpu().numpy()
+        mesh.set_source(sbp.SOURCE_VORTEX2D)
+        ug = mesh.source_state(t).cpu().numpy().reshape(ue.shape)
+        err = np.abs(ug - ue).max(axis=(0, 2)) / np.abs(ue).max(axis=(0, 2))
+        assert (err <= 1e-14).all(), err
+        assert np.array_equal(mesh.residual(ud).cpu().numpy(), r0)
+        for uu in (up, ue):
+            e = mesh.source_error(torch.from_numpy(uu).cuda(), t)
+            eo = mms.l2_error_quadrature(uu, m, exact)
+            say(f"   p={p} quadrature norm gpu {e.sum():.6e} oracle {eo.sum():.6e}")
+            assert np.abs(e - eo).max() <= 1e-12 * np.abs(eo).max(), (e, eo)
+        mesh.check_device()
+        mesh.close()
+
+
+def _cons(rho, V, p):
+    from paper_2305_07181_amd import workloads as wl
+    return wl.conservative(rho, V, p)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_vortex2d_rates_small(p):
+    """The 2D vortex on two grids (20^2 x 2, 40^2 x 2) to t = 0.5: the
+    error in the studies' norm falls at a rate in [p - 0.2, p + 1.2], the
+    accuracy pin for the entropy-conservative scheme."""
+    from paper_2305_07181_amd import studies
+    say(f"[study] vortex2d rates p={p}")
+    rows = studies.vortex_study(2, [20, 40], [p], 0.5, 0.1, emit=say)
+    for r in rows:
+        rate = r.get("rate")
+        if rate is not None:
+            assert p - 0.2 <= rate <= p + 1.2, rate
+        if not r["dissipation"]:
+            assert abs(r["entropy_change"]) < 1e-12
