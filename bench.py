@@ -299,7 +299,7 @@ def main():
     args = _args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding "
-              f"is a design in DESIGN.md, not a measured path", file=sys.stderr)
+              f"is a design only, not a measured path", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2305_07181_amd import sbp, workloads as wl

@@ -41,7 +41,7 @@ enum sbp_status {
   SBP_EINVAL = -1,   /* invalid argument (reported at once, nothing launched) */
   SBP_ENOMEM = -2,   /* device or host allocation failed */
   SBP_EDEVICE = -3,  /* HIP runtime error */
-  SBP_ENOTSUP = -4,  /* combination not supported by this build */
+  SBP_ENOTSUP = -4,  /* combination not supported by this library */
   SBP_ENONPHYS = -5, /* rho <= 0, p <= 0 or NaN seen on the device */
   SBP_ERRK = -6      /* relaxation parameter not bracketed / not converged */
 };

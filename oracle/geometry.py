@@ -5,10 +5,10 @@ Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may use
 this module.
 
 Sec. 2.1 defines the physical operators only through Def. 1 and Assumption 1
-and refers to the literature for curved elements.  The reading taken here
-(listed in DESIGN.md):
-  * the element map is affine (p_geom = 1) or, in 2D, quadratic through the
-    vertices and edge midpoints (p_geom = 2 <= p + 1, Assumption 1);
+and refers to the literature for curved elements.  The reading taken here:
+  * the element map is affine (p_geom = 1) or quadratic through the vertices
+    and edge midpoints (p_geom = 2; Assumption 1 allows it for p >= 1 in 2D
+    and p >= 2 in 3D);
   * metric terms Lambda_{il} = J d(xi_l)/d(x_i) (cofactors of dx/dxi) at the
     SBP nodes, H_k = diag(J) H_ref;
   * Q_{x_i,k} = 1/2 sum_l (Lambda_il Q_xi_l + Q_xi_l Lambda_il) with the

@@ -20,7 +20,7 @@ Sources in the paper:
                                         |Lambda|, X-hat)
   viscous flux ........................ Sec. 2.2 (tau, heat flux kappa dT/dx)
 
-Readings of the paper taken here (each listed in the design doc):
+Readings of the paper taken here:
   * exponential average near equal arguments: series in eps=(a-b)/(a+b)
     for |eps| <= 1e-2, direct formula otherwise;
   * 3D eigenvectors X-hat: the two printed shear columns are replaced by

@@ -22,7 +22,7 @@ Hadamard).  The strong form (Sec. 4, eqs. discrete entropy split and sats
 inv) is provided for the strong = weak cross-check.
 Baumann-Oden viscous SATs (Sec. 5.1, eq. bo sats): T1 = 0, T2 = T3 = B/2.
 
-Readings (DESIGN.md): the stray w_k^T in the printed Hadamard weak form is
+Readings: the stray w_k^T in the printed Hadamard weak form is
 dropped; the coupling sums run over the facets of element k.
 
 Parity: pinned by tests/test_oracle_residual.py: free-stream preservation,

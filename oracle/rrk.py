@@ -9,7 +9,7 @@ e = dt sum_i b_i w_i^T H r_i, and gamma_n solving
     1^T H s(u_n + gamma d) - 1^T H s(u_n) - gamma e = 0
 by bisection; u_{n+1} = u_n + gamma_n d.
 
-Readings (DESIGN.md): classical RK4 tableau; the equality is solved also with
+Readings: classical RK4 tableau; the equality is solved also with
 dissipation; bracket [0.5, 1.5]; bisection stops when the midpoint equals an
 endpoint; the entropy difference is summed node by node; t_{n+1} = t_n +
 gamma_n dt.

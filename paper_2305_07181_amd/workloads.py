@@ -294,7 +294,7 @@ def mms_mesh2d(n: int) -> dict:
 def mms_mesh3d(n: int) -> dict:
     """The periodic box [-1,1]^3 of the manufactured-solution study in n^3
     cubes of six affine tetrahedra each (the study's curving map is not
-    applied: tetrahedra are affine here)."""
+    applied: the viscous terms run on affine tetrahedra)."""
     desc = periodic_tet_mesh(n, 2.0)
     desc["vert_xyz"] = desc["vert_xyz"] - 1.0
     return desc

@@ -1,6 +1,6 @@
 """GPU parity of the HIP residual against the CPU oracle (through the C ABI).
 
-Tolerances (derived in the design doc):
+Tolerances:
   * FP64: max_nodes |r_gpu - r_orc|_c <= 1e-12 max_nodes |r_orc|_c per
     conserved variable; for the low-Mach Taylor-Green state the denominator
     is the magnitude of the summed terms (the residual is ~1e-2 of them).
