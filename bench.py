@@ -449,7 +449,8 @@ def main():
         desc3c = wl.curved_tet_mesh(32, 2.0 * np.pi, 0.02)
         for p in (2, 3):
             row = {}
-            for name, kw in (("fp64_split", dict()), ("fp32_split", dict(precision=sbp.FP32))):
+            for name, kw in (("fp64_split", dict()), ("fp32_split", dict(precision=sbp.FP32)),
+                             ("fp64_hadamard", dict(form=sbp.FORM_HADAMARD))):
                 msh = sbp.Mesh(desc3c, p, dissipation=True, **kw)
                 u3 = _state_from_mesh(msh, "tgv")
                 np3 = int(msh.elem_np[0])
@@ -463,6 +464,7 @@ def main():
             aff = extras[f"tet_p{p}_tgv_196608"]
             row["curved_over_affine_fp64"] = row["fp64_split"]["ms"] / aff["fp64_split"]["ms"]
             row["curved_over_affine_fp32"] = row["fp32_split"]["ms"] / aff["fp32_split"]["ms"]
+            row["hadamard_over_split"] = row["fp64_hadamard"]["ms"] / row["fp64_split"]["ms"]
             extras[f"tet_p{p}_tgv_196608_curved"] = row
         extras["ns_tgv_82944_p3"] = ns_rows(args)
         extras["hybrid_tri_p4"] = hybrid_rows(args, meshes[4], states[4], ne)

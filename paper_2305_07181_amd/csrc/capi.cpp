@@ -110,11 +110,14 @@ struct sbp_mesh {
 namespace {
 
 // Kernel family of the residual: 0 entropy split, 1 Hadamard, 2 entropy
-// split with the Navier-Stokes terms, 3 entropy split on curved tetrahedra.
+// split with the Navier-Stokes terms, 3 and 4 entropy split and Hadamard on
+// curved tetrahedra.
+int curved_eff(const sbp_mesh *M, int form) {
+  return M->curved3 ? (form == SBP_FORM_SPLIT ? 3 : 4) : form;
+}
 int form_eff_of(const sbp_mesh *M) {
   if (M->phys.viscous) return 2;
-  if (M->curved3) return 3;
-  return M->phys.form;
+  return curved_eff(M, M->phys.form);
 }
 
 constexpr int SC_ENT = 0;     // 4 stage entropy rates
@@ -518,7 +521,7 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
       const int other = ph->form == SBP_FORM_SPLIT ? SBP_FORM_HADAMARD : SBP_FORM_SPLIT;
       c.res_blocks_h = 0;
       for (int pr = 0; pr < 2; ++pr)
-        c.res_blocks_h = std::max(c.res_blocks_h, sbp::residual_blocks(dim, c.p, pr, other, c.n_elem, {0, 1}));
+        c.res_blocks_h = std::max(c.res_blocks_h, sbp::residual_blocks(dim, c.p, pr, curved_eff(M, other), c.n_elem, {0, 1}));
       c.part_off_h = part_total;
       part_total += c.res_blocks_h;
     }
@@ -616,7 +619,7 @@ int residual_core(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStr
     return SBP_OK;
   };
   auto other_blocks = [&](const DegreeClass &c) {
-    return sbp::residual_blocks(M->dim, c.p, ph.precision, form_other, c.n_elem, sbp::LaunchCfg{0, 1});
+    return sbp::residual_blocks(M->dim, c.p, ph.precision, curved_eff(M, form_other), c.n_elem, sbp::LaunchCfg{0, 1});
   };
   const int ncls = (int)M->cls.size();
   int rc;
@@ -1032,8 +1035,7 @@ int sbp_setup_mesh(const sbp_mesh_desc *desc, const sbp_physics *phys, void *hip
     for (int e = 0; e < desc->n_elem; ++e)
       if (desc->elem_degree[e] < 2)
         return fail(SBP_EINVAL, "quadratic tetrahedral maps need degree p >= 2 (Assumption 1)");
-    if (phys->viscous || phys->form != SBP_FORM_SPLIT)
-      return fail(SBP_ENOTSUP, "curved tetrahedra: the entropy-split Euler residual only");
+    if (phys->viscous) return fail(SBP_ENOTSUP, "curved tetrahedra: the Euler terms only");
   }
   if (desc->n_problems < 1) return fail(SBP_EINVAL, "n_problems must be >= 1");
   for (int i = 0; i < desc->dim; ++i)
@@ -1171,7 +1173,6 @@ int sbp_set_volume_form(sbp_mesh *M, const uint8_t *form_dev) {
   if (!M) return fail(SBP_EINVAL, "null handle");
   if (form_dev && M->phys.viscous)
     return fail(SBP_ENOTSUP, "the hybrid scheme covers the Euler terms (no viscous terms)");
-  if (form_dev && M->curved3) return fail(SBP_ENOTSUP, "the hybrid scheme covers affine tetrahedra");
   M->eform = form_dev;
   // the captured RK stages hold the previous launches
   if (M->rk_exec) {

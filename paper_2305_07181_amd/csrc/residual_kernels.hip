@@ -544,7 +544,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_split3c(KArgs<T> A) {
   for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
     const int e0 = tl * EB;
     const int ne = min(EB, A.n_elem - e0);
-    const bool act = tid < ne * NP;
+    if (!tile_on(A, e0, ne)) continue;  // hybrid scheme: no element of this form
+    const bool act = tid < ne * NP && elem_on(A, e0 + e);
     __syncthreads();
     for (int x = tid; x < ne * 30; x += kThreads) gs[x / 30][x % 30] = (T)A.geo[(size_t)(e0 + x / 30) * 30 + x % 30];
     __syncthreads();
@@ -977,18 +978,22 @@ template <> struct HadTile<3, 1, float> { static constexpr int EB = 21; };
 template <> struct HadTile<3, 2, float> { static constexpr int EB = 20; };
 template <> struct HadTile<3, 3, float> { static constexpr int EB = 8; };
 
-template <int DIM, int P, typename T>
+// CURVED (3D): quadratic tetrahedral maps, metrics per node from the ten map
+// nodes as in k_split3c, and the metric average of the two nodes per pair.
+template <int DIM, int P, typename T, bool CURVED = false>
 __global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
   constexpr int D = DIM, NC = D + 2;
   constexpr int NP = Shape<DIM, P>::NP, NF = Shape<DIM, P>::NF;
   constexpr int EB = HadTile<DIM, P, T>::EB;
   constexpr int NV = D + 4;  // V, p, z1, P1, P2
   constexpr int NT = (EB * NP + kThreads - 1) / kThreads;
-  constexpr int NM = DIM == 2 ? 5 : 1;
+  constexpr bool PN = DIM == 2 || CURVED;  // metrics per node
+  constexpr int NM = DIM == 2 ? 5 : (CURVED ? 10 : 1);
   __shared__ T Ss[D][NP][NP];
   __shared__ T nd[NV][EB][NP];
-  __shared__ T met[NM][EB][DIM == 2 ? NP : 1];  // 2D: Lambda_00, _01, _10, _11, J per node
-  __shared__ T gm[EB][10];                      // 3D: Lambda (row i, col l), J per element
+  // per node: 2D Lambda_00, _01, _10, _11, J; curved 3D Lambda (row i, col l), J
+  __shared__ T met[NM][EB][PN ? NP : 1];
+  __shared__ T gm[EB][CURVED ? 30 : 10];  // 3D: Lambda, J per element (affine) or the map nodes (curved)
   const int tid = threadIdx.x;
   for (int x = tid; x < D * NP * NP; x += kThreads) (&Ss[0][0][0])[x] = A.op.S[x];
   double ent = 0.0;
@@ -999,7 +1004,9 @@ __global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
     if (!tile_on(A, e0, ne)) continue;  // hybrid scheme: no element of this form
     __syncthreads();
     if constexpr (DIM == 3) {
-      for (int x = tid; x < ne * 10; x += kThreads) gm[x / 10][x % 10] = (T)A.geo[(size_t)(e0 + x / 10) * 10 + x % 10];
+      constexpr int GS = CURVED ? 30 : 10;
+      for (int x = tid; x < ne * GS; x += kThreads) gm[x / GS][x % GS] = (T)A.geo[(size_t)(e0 + x / GS) * GS + x % GS];
+      if constexpr (CURVED) __syncthreads();  // the map nodes feed the per-node metrics below
     }
     Node<D, T> nodes[NT];
 #pragma unroll
@@ -1038,6 +1045,31 @@ __global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
         met[2][e][j] = -F[0][1];
         met[3][e][j] = F[0][0];
         met[4][e][j] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+      } else if constexpr (CURVED) {
+        T F[3][3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int l = 0; l < 3; ++l) F[k][l] = (T)0;
+#pragma unroll
+        for (int q = 0; q < 10; ++q)
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            const T d = A.op.dN[(l * 10 + q) * NP + j];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) F[k][l] += d * gm[e][q * 3 + k];
+          }
+        T J = (T)0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            const int k1 = (k + 1) % 3, k2 = (k + 2) % 3, l1 = (l + 1) % 3, l2 = (l + 2) % 3;
+            const T c = F[k1][l1] * F[k2][l2] - F[k1][l2] * F[k2][l1];
+            met[k * 3 + l][e][j] = c;
+            if (k == 0) J += F[0][l] * c;
+          }
+        met[9][e][j] = J;
       }
     }
     __syncthreads();
@@ -1053,6 +1085,10 @@ __global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) Lm[q / 2][q % 2] = met[q][e][m];
         J = met[4][e][m];
+      } else if constexpr (CURVED) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Lm[q / 3][q % 3] = met[q][e][m];
+        J = met[9][e][m];
       } else {
 #pragma unroll
         for (int q = 0; q < 9; ++q) Lm[q / 3][q % 3] = gm[e][q];
@@ -1076,7 +1112,8 @@ __global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
           T s = 0;
 #pragma unroll
           for (int l = 0; l < D; ++l) {
-            const T lsum = DIM == 2 ? Lm[i][l] + met[i * 2 + l][e][nn] : (T)2 * Lm[i][l];
+            const T lsum = DIM == 2 ? Lm[i][l] + met[i * 2 + l][e][nn]
+                                    : (CURVED ? Lm[i][l] + met[i * 3 + l][e][nn] : (T)2 * Lm[i][l]);
             s += Ss[l][m][nn] * lsum;
           }
           cvec[i] = s;
@@ -1114,11 +1151,18 @@ struct KernelRef {
 };
 
 // Kernel of a residual slot; form_eff 0: entropy split (Euler), 1: Hadamard,
-// 2: entropy split with the Navier-Stokes terms.
+// 2: entropy split with the Navier-Stokes terms, 3 and 4: entropy split and
+// Hadamard on curved tetrahedra.
 // Curved tetrahedra (form_eff 3): quadratic maps need p >= 2.
 template <int P, typename T>
 static KernelRef curved3_kernel() {
   if constexpr (P >= 2) return {reinterpret_cast<const void *>(&k_split3c<P, T>), VTile3<P, T>::EB};
+  return {nullptr, 0};
+}
+
+template <int P, typename T>
+static KernelRef curved3_hadamard_kernel() {
+  if constexpr (P >= 2) return {reinterpret_cast<const void *>(&k_hadamard<3, P, T, true>), HadTile<3, P, T>::EB};
   return {nullptr, 0};
 }
 
@@ -1141,6 +1185,7 @@ static KernelRef residual_kernel(int dim, int p, int form_eff, int variant) {
     if (form_eff == 1) return {reinterpret_cast<const void *>(&k_hadamard<3, PP, T>), HadTile<3, PP, T>::EB}; \
     if (form_eff == 2) return {reinterpret_cast<const void *>(&k_split3<PP, T, true>), 3 * Wave3<PP, T>::CT}; \
     if (form_eff == 3) return curved3_kernel<PP, T>();                                         \
+    if (form_eff == 4) return curved3_hadamard_kernel<PP, T>();                                \
     const bool sg = skew_from_cache3<PP, T>() != (variant == 1);                                \
     return {sg ? reinterpret_cast<const void *>(&k_split3v<PP, T, true>)                        \
                : reinterpret_cast<const void *>(&k_split3v<PP, T, false>),                      \
@@ -1191,8 +1236,10 @@ int residual_blocks(int dim, int p, int precision, int form_eff, int n_elem, Lau
 
 template <typename T>
 static hipError_t launch_t(int dim, int p, int form, const KArgs<T> &A, hipStream_t s, LaunchCfg cfg) {
-  if ((A.visc || A.curved) && (dim != 3 || form != 0)) return hipErrorInvalidValue;
-  const KernelRef k = residual_kernel<T>(dim, p, A.visc ? 2 : (A.curved ? 3 : form), cfg.variant);
+  if (A.visc && (dim != 3 || form != 0)) return hipErrorInvalidValue;
+  if (A.curved && dim != 3) return hipErrorInvalidValue;
+  const int fe = A.visc ? 2 : (A.curved ? (form == 0 ? 3 : 4) : form);
+  const KernelRef k = residual_kernel<T>(dim, p, fe, cfg.variant);
   if (!k.fn || A.n_elem <= 0) return hipErrorInvalidValue;
   const int nb = launch_grid(k.fn, (A.n_elem + k.eb - 1) / k.eb, cfg.grid);
   KArgs<T> a = A;

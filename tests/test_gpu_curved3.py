@@ -134,19 +134,62 @@ def test_curved_tets_refusals():
     with pytest.raises(sbp.SbpError) as ei:          # Assumption 1: p >= 2
         sbp.Mesh(desc, 1)
     assert ei.value.code == sbp.SBP_EINVAL
-    for kw in (dict(viscous=True, mu=0.01), dict(form=sbp.FORM_HADAMARD)):
-        with pytest.raises(sbp.SbpError) as ei:
-            sbp.Mesh(desc, 2, **kw)
-        assert ei.value.code == sbp.SBP_ENOTSUP
+    with pytest.raises(sbp.SbpError) as ei:
+        sbp.Mesh(desc, 2, viscous=True, mu=0.01)
+    assert ei.value.code == sbp.SBP_ENOTSUP
     mesh = sbp.Mesh(desc, 2)
     u = torch.ones(mesh.state_shape(), dtype=torch.float64, device="cuda")
     with pytest.raises(sbp.SbpError) as ei:
         mesh.vjp(u, u)
     assert ei.value.code == sbp.SBP_ENOTSUP
-    with pytest.raises(sbp.SbpError) as ei:
-        mesh.set_volume_form(torch.zeros(mesh.n_elem, dtype=torch.uint8, device="cuda"))
-    assert ei.value.code == sbp.SBP_ENOTSUP
     mesh.close()
+
+
+@pytest.mark.parametrize("p,diss", [(2, False), (3, True)])
+def test_curved_tets_hadamard_and_hybrid(p, diss):
+    """The Hadamard form on curved tetrahedra (metric average of the two
+    nodes per pair) against the oracle, with local conservation; and the
+    hybrid scheme with random per-element flags against the oracle's."""
+    import torch
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say(f"[curved3] Hadamard / hybrid p={p} diss={diss}")
+    desc = wl.curved_tet_mesh(2, 1.0, 0.03)
+    m = OracleMesh(desc, p)
+    u = state(m, "random", seed=60 + p, jitter=0.01)
+    ud = torch.from_numpy(u).cuda()
+    mh = sbp.Mesh(desc, p, dissipation=diss, form=sbp.FORM_HADAMARD)
+    rh = mh.residual(ud).cpu().numpy()
+    mh.check_device()
+    ro = OracleScheme(m, ph.Gas(), form="hadamard", dissipation=diss)(u)
+    err = rel_err_per_component(rh, ro)
+    say("   Hadamard rel err", err.max())
+    assert (err <= 1e-12).all(), err
+    if not diss:
+        # global conservation: sum_k 1^T H_k r_k = 0 per component
+        H = m.H_all()
+        tot = np.einsum("en,ecn->c", H, rh)
+        scale = np.einsum("en,ecn->c", H, np.abs(rh))
+        assert (np.abs(tot) <= 1e-13 * scale).all(), tot / scale
+    mh.close()
+    flags = np.random.default_rng(p).integers(0, 2, m.ne).astype(np.uint8)
+    ms = sbp.Mesh(desc, p, dissipation=diss)
+    fd = torch.from_numpy(flags).cuda()
+    ms.set_volume_form(fd)
+    r, er = ms.residual(ud, entropy_rate=True)
+    ms.check_device()
+    sch = OracleScheme(m, ph.Gas(), form="hybrid", element_form=flags, dissipation=diss)
+    ro = sch(u)
+    err = rel_err_per_component(r.cpu().numpy(), ro)
+    say("   hybrid rel err", err.max(), "flags", int(flags.sum()), "of", m.ne)
+    assert (err <= 1e-12).all(), err
+    rate_o = sch.entropy_rate(u, ro)
+    scale = sum(np.sum(m.geometry(e)["H"][None, :] * np.abs(ph.entropy_vars(u[e], sch.gas) * ro[e]))
+                for e in range(m.ne))
+    assert abs(float(er.cpu()[0]) - rate_o) <= 1e-12 * scale
+    ms.close()
 
 
 @pytest.mark.parametrize("p,quadratic", [(1, False), (2, True), (3, True)])
