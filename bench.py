@@ -37,8 +37,8 @@ PEAK_F32 = 157.3e12
 # (profiles/k_split2_tri32768_hbm_bytes.md); valid only for the kernel sources
 # they were taken on (sha256 prefix of the concatenated sources below).
 TRAFFIC_SOURCES = ["residual_kernels.hip", "device_physics.hpp", "mfma.hpp", "kernels.hpp"]
-TRAFFIC_SHA = "8f7473e858ed653a"  # kernel_source_hash() of the profiled build
-TRAFFIC_BYTES = {1: 26.28e6, 2: 42.24e6, 3: 68.27e6, 4: 79.98e6}  # k_split2<p, double, 2>
+TRAFFIC_SHA = "f8f39133ab109111"  # kernel_source_hash() of the profiled build
+TRAFFIC_BYTES = {1: 26.09e6, 2: 42.74e6, 3: 69.74e6, 4: 81.55e6}  # k_split2<p, double, 2>
 
 
 def _args():
