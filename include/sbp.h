@@ -110,8 +110,8 @@ typedef struct {
  * device tables.  `hip_stream` is used for the uploads.  Paper: Sec. 2.1.
  * Curved tetrahedra (p_geom 2 in 3D) need every degree >= 2 (Assumption 1:
  * p_geom <= floor(p/2) + 1), else SBP_EINVAL; with them the viscous terms
- * return SBP_ENOTSUP here and sbp_residual_vjp returns SBP_ENOTSUP (the
- * entropy-split and Hadamard forms and the hybrid flags are available). */
+ * return SBP_ENOTSUP (the Euler terms in both forms, the hybrid flags and the
+ * VJP are available). */
 int sbp_setup_mesh(const sbp_mesh_desc *desc, const sbp_physics *phys,
                    void *hip_stream, sbp_mesh **out);
 

@@ -976,7 +976,7 @@ int autotune_impl(sbp_mesh *M, const double *u, const double *lam, sbp_tune_repo
       tune_store(tune_key(M, TUNE_RES, c.p, c.n_elem), c.res_cfg);
     }
   }
-  if (lam && !ph.viscous && ph.form == SBP_FORM_SPLIT && !M->curved3) {
+  if (lam && !ph.viscous && ph.form == SBP_FORM_SPLIT) {
     auto vargs = [&](DegreeClass &c) {
       sbp::KArgs<double> A = kargs<double>(M, c, u, nullptr, c.op64);
       A.lam = lam;
@@ -1088,7 +1088,6 @@ int sbp_residual_vjp(sbp_mesh *M, const void *u, const void *lam, void *ubar, vo
   const sbp_physics &ph = M->phys;
   if (ph.viscous || ph.form != SBP_FORM_SPLIT)
     return fail(SBP_ENOTSUP, "the VJP covers the entropy-split Euler residual (with or without dissipation)");
-  if (M->curved3) return fail(SBP_ENOTSUP, "the VJP covers affine tetrahedra");
   if (M->eform)
     return fail(SBP_ENOTSUP, "the VJP covers the entropy-split form; clear the hybrid form flags first");
   if (M->dim == 2 && M->cls.size() > 1) {
@@ -1150,7 +1149,7 @@ sbp::LaunchCfg *find_slot(sbp_mesh *M, int kind, int p, int &nvar, int *&grid_on
   grid_only = nullptr;
   const sbp_physics &ph = M->phys;
   const int form_eff = form_eff_of(M);
-  if (kind == TUNE_VJP && (ph.viscous || ph.form != SBP_FORM_SPLIT || M->curved3)) return nullptr;
+  if (kind == TUNE_VJP && (ph.viscous || ph.form != SBP_FORM_SPLIT)) return nullptr;
   const bool batched = kind == TUNE_RES ? (M->batch_blocks > 0 && ph.form == SBP_FORM_SPLIT && !ph.viscous)
                                         : (M->dim == 2 && M->cls.size() > 1);
   if (batched) {

@@ -479,6 +479,196 @@ int vjp_variants(int dim, int p) {
   return 2;
 }
 
+// VJP on tetrahedra with quadratic maps (Assumption 1: p >= 2): the curved-
+// triangle derivation (Vjp2) in 3D.  Per node the metric cofactors Lambda
+// and J from the element's ten map nodes; per pair
+// c_m = sum_l S_l[j][k] (Lambda_ml(j) + Lambda_ml(k)), and
+// Z_m += c_m mu_k, V_s += sum_m c_m s_m,k, X_m += c_m w_k; then the volume
+// term sum_i A_i^T ((1 - c_b)/2 Z_i + (1 + c_b)/2 a_i mu), the
+// non-conservative terms and the facet adjoint as on curved triangles.  S_l
+// through the caches (rows read transposed, S being stored exactly skew).
+template <int P, int W>
+__global__ __launch_bounds__(kT, W) void k_vjp3c(KArgs<double> A) {
+  constexpr int D = 3, NC = 5, NFAC = 4;
+  constexpr int NP = Shape<3, P>::NP, NF = Shape<3, P>::NF, NFN = NFAC * NF;
+  constexpr int EB = VTileV3<P>::EB;
+  static_assert(EB * NP <= kT, "one node per lane");
+  constexpr int NV = 34;  // per node: mu[5] s_1..3[15] w[5] Lambda[9]
+  constexpr int NDS = NP * NV;
+  __shared__ double nd[EB * NDS];
+  __shared__ double gs[EB][30];
+  const int tid = threadIdx.x;
+  const GasC<double> &G = A.G;
+  const GasC<Dual<double>> GD = dual_gas(G);
+  const double cb = G.cb, he = 0.5 * (1.0 + cb), hz = 0.5 * (1.0 - cb);
+  const int ntiles = (A.n_elem + EB - 1) / EB;
+  const int e = tid / NP, j = tid % NP;
+  for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    const int e0 = tl * EB;
+    const int ne = min(EB, A.n_elem - e0);
+    const bool act = tid < ne * NP;
+    const int eg = e0 + e;
+    __syncthreads();
+    for (int x = tid; x < ne * 30; x += kT) gs[x / 30][x % 30] = A.geo[(size_t)(e0 + x / 30) * 30 + x % 30];
+    __syncthreads();
+    double uu[NC], lm[NC], L[D][D], H = 1.0, s[D][NC];
+    Node<D, double> n;
+    if (act) {
+      double F[D][D];
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int l = 0; l < D; ++l) F[k][l] = 0.0;
+      const double *g = gs[e];
+#pragma unroll
+      for (int a = 0; a < 10; ++a)
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+          const double d = A.op.dN[(l * 10 + a) * NP + j];
+#pragma unroll
+          for (int k = 0; k < D; ++k) F[k][l] += d * g[a * 3 + k];
+        }
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+          const int k1 = (k + 1) % 3, k2 = (k + 2) % 3, l1 = (l + 1) % 3, l2 = (l + 2) % 3;
+          L[k][l] = F[k1][l1] * F[k2][l2] - F[k1][l2] * F[k2][l1];
+        }
+      H = (F[0][0] * L[0][0] + F[0][1] * L[0][1] + F[0][2] * L[0][2]) * A.op.h[j];
+      const int uo = A.uoff[eg];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        uu[c] = A.u[uo + c * NP + j];
+        lm[c] = A.lam[uo + c * NP + j];
+      }
+      node_from_u<D, double>(uu, G, n);
+      if (!n.ok) atomicOr(A.err, 1);
+#pragma unroll
+      for (int i = 0; i < D; ++i) jvp_flux<D, double>(n, G, i, lm, s[i]);
+      const double iH = 1.0 / H;
+      double *v = nd + e * NDS + j * NV;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        v[c] = lm[c] * iH;
+#pragma unroll
+        for (int i = 0; i < D; ++i) v[5 + i * NC + c] = s[i][c] * iH;
+        v[20 + c] = n.w[c];
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int l = 0; l < D; ++l) v[25 + k * 3 + l] = L[k][l];
+    }
+    __syncthreads();
+    if (act) {
+      double Z[D][NC], Vs[NC], X[D][NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        Vs[c] = 0.0;
+#pragma unroll
+        for (int m = 0; m < D; ++m) Z[m][c] = X[m][c] = 0.0;
+      }
+#pragma unroll 1
+      for (int k = 0; k < NP; ++k) {
+        const double s0 = -A.op.S[(0 * NP + k) * NP + j];
+        const double s1 = -A.op.S[(1 * NP + k) * NP + j];
+        const double s2 = -A.op.S[(2 * NP + k) * NP + j];
+        const double *v = nd + e * NDS + k * NV;
+        double cm[D];
+#pragma unroll
+        for (int m = 0; m < D; ++m)
+          cm[m] = s0 * (L[m][0] + v[25 + m * 3 + 0]) + s1 * (L[m][1] + v[25 + m * 3 + 1]) +
+                  s2 * (L[m][2] + v[25 + m * 3 + 2]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+#pragma unroll
+          for (int m = 0; m < D; ++m) {
+            Z[m][c] += cm[m] * v[c];  // one FMA per product
+            Vs[c] += cm[m] * v[5 + m * NC + c];
+            X[m][c] += cm[m] * v[20 + c];
+          }
+        }
+      }
+      double ak[D];
+#pragma unroll
+      for (int m = 0; m < D; ++m) {
+        double t = 0.0;
+#pragma unroll
+        for (int l = 0; l < D; ++l) t += L[m][l] * A.op.E[l * NP + j];
+        ak[m] = t;
+      }
+      const double iH = 1.0 / H;
+      double ub[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) ub[c] = 0.0;
+      // volume: sum_i A_i^T z_i, z_i = (1 - c_b)/2 Z_i + (1 + c_b)/2 a_i mu
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        double zi[NC], o[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) zi[c] = hz * Z[i][c] + he * ak[i] * lm[c] * iH;
+        flux_jac_T<D, double>(n, G, uu[NC - 1], i, zi, o);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ub[c] += o[c];
+      }
+      // non-conservative: y = sum_i Q_xi^T s_i + sum_i d/de A~_i(w + e g_i) lambda,
+      // sum_i Q_xi^T s_i = -V_s/2 + 1/2 sum_i a_i s_i,  g_i = H^-1 (X_i + a_i w)/2
+      double y[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) y[c] = -0.5 * Vs[c] + 0.5 * iH * (ak[0] * s[0][c] + ak[1] * s[1][c] + ak[2] * s[2][c]);
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        double gi[NC], du[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) gi[c] = 0.5 * iH * (X[i][c] + ak[i] * n.w[c]);
+        dU_from_dW<D, double>(n, G, gi, du);
+        Dual<double> xd[NC], lmd[NC], hv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          xd[c] = Dual<double>(uu[c], du[c]);
+          lmd[c] = Dual<double>(lm[c]);
+        }
+        Node<D, Dual<double>> ndu;
+        node_from_u<D, Dual<double>>(xd, GD, ndu);
+        jvp_flux<D, Dual<double>>(ndu, GD, i, lmd, hv);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) y[c] += hv[c].d;
+      }
+      double wy[NC];
+      dWdU_apply<D>(uu, y, GD, wy);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) ub[c] -= cb * wy[c];
+      // facet SATs: one gradient of this node's SAT with the combined
+      // cotangent lambda_k/H_k - lambda_v/H_v (the neighbour's SAT is its negative)
+      if (j < NFN) {
+        const int off = A.nbr[(size_t)eg * NFN + j];
+        double uv[NC], lv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          uv[c] = A.u[off + c * NP];
+          lv[c] = A.lam[off + c * NP];
+        }
+        const int q = A.nbrq[(size_t)eg * NFN + j];
+        const double Hv = A.Hn[(size_t)(q / NFN) * NP + q % NFN];
+        double mu[NC], g1[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) mu[c] = lm[c] * iH - lv[c] / Hv;
+        Node<D, double> nk = n, nv;
+        node_powers<D, double>(G, nk);
+        node_from_u<D, double>(uv, G, nv);
+        node_powers<D, double>(G, nv);
+        facet_grad_rev<D>(nk, nv, ak, mu, G, A.diss != 0, g1);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ub[c] -= g1[c];
+      }
+      const int uo = A.uoff[eg];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) A.ubar[uo + c * NP + j] = ub[c];
+    }
+  }
+}
+
 namespace {
 
 // kernel of a VJP slot: variant 0 the built-in register budget, 1 the other
@@ -504,12 +694,25 @@ const void *vjp_kernel(int dim, int p, int variant, int &eb) {
   return nullptr;
 }
 
+// curved tetrahedra: built-in W = 1 (the per-node metrics and three
+// accumulator sets need the larger register budget)
+const void *vjp3c_kernel(int p, int variant, int &eb) {
+  eb = p == 2 ? VTileV3<2>::EB : VTileV3<3>::EB;
+  if (p == 2) return variant == 1 ? reinterpret_cast<const void *>(&k_vjp3c<2, 2>)
+                                  : reinterpret_cast<const void *>(&k_vjp3c<2, 1>);
+  if (p == 3) return variant == 1 ? reinterpret_cast<const void *>(&k_vjp3c<3, 2>)
+                                  : reinterpret_cast<const void *>(&k_vjp3c<3, 1>);
+  eb = 0;
+  return nullptr;
+}
+
 }  // namespace
 
 hipError_t launch_vjp(int dim, int p, const KArgs<double> &A, hipStream_t s, LaunchCfg cfg) {
   if (A.n_elem <= 0) return hipSuccess;
   int eb = 0;
-  const void *fn = vjp_kernel(dim, p, cfg.variant, eb);
+  const void *fn = A.curved ? (dim == 3 ? vjp3c_kernel(p, cfg.variant, eb) : nullptr)
+                            : vjp_kernel(dim, p, cfg.variant, eb);
   if (!fn) return hipErrorInvalidValue;
   const int nb = launch_grid(fn, (A.n_elem + eb - 1) / eb, cfg.grid);
   KArgs<double> a = A;

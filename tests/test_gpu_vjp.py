@@ -36,6 +36,37 @@ def test_vjp_3d_vs_oracle(p, diss):
     assert err <= 1e-12, err
 
 
+@pytest.mark.parametrize("p", [2, 3])
+@pytest.mark.parametrize("diss", [False, True])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_vjp_curved_tets_vs_oracle(p, diss, variant):
+    """Tetrahedra with quadratic maps: both register budgets of the VJP
+    kernel against the oracle's complex-step Jacobian on sampled elements."""
+    import torch
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from oracle.jacobian import vjp_elements
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say(f"[vjp3d curved] p={p} diss={diss} variant={variant}")
+    desc = wl.curved_tet_mesh(2, 1.0, 0.03)
+    m = OracleMesh(desc, p)
+    u = state(m, "random", seed=16, jitter=0.01)
+    lam = np.random.default_rng(2100 + p).standard_normal(u.shape)
+    mesh = sbp.Mesh(desc, p, dissipation=diss)
+    mesh.set_launch_shape("vjp", p, variant, 1)
+    ub = mesh.vjp(torch.from_numpy(u).cuda(), torch.from_numpy(lam).cuda()).cpu().numpy()
+    mesh.check_device()
+    mesh.close()
+    sch = OracleScheme(m, ph.Gas(), dissipation=diss)
+    els = [0, 17, 33, 47]
+    ref = vjp_elements(sch, u, lam, els)
+    scale = max(np.abs(ref[e]).max() for e in els)
+    err = max(np.abs(ub[e] - ref[e]).max() for e in els) / scale
+    say("   rel err", err)
+    assert err <= 1e-12, err
+
+
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
 @pytest.mark.parametrize("diss", [False, True])
 def test_vjp_2d_curved_vs_oracle(p, diss):
