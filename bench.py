@@ -458,6 +458,14 @@ def main():
                 r = torch.empty(u3.shape, dtype=torch.float32 if "fp32" in name else torch.float64, device="cuda")
                 med, _ = _time_calls(lambda: msh.residual(u3, r), 5, 2)
                 row[name] = dict(ms=med * 1e3, elem_dof_per_s=ne3 * np3 / med)
+                if name == "fp64_split":
+                    lam3 = torch.randn(u3.shape, dtype=torch.float64, device="cuda",
+                                       generator=torch.Generator(device="cuda").manual_seed(2200 + p))
+                    row["tuned_fp64_vjp"] = _tune(args, msh, u3, lam3)
+                    ub3 = torch.empty_like(u3)
+                    med, _ = _time_calls(lambda: msh.vjp(u3, lam3, ub3), 5, 2)
+                    row["fp64_vjp"] = dict(ms=med * 1e3, elem_dof_per_s=ne3 * np3 / med)
+                    del lam3, ub3
                 msh.check_device()
                 msh.close()
                 del u3, r
@@ -465,6 +473,7 @@ def main():
             row["curved_over_affine_fp64"] = row["fp64_split"]["ms"] / aff["fp64_split"]["ms"]
             row["curved_over_affine_fp32"] = row["fp32_split"]["ms"] / aff["fp32_split"]["ms"]
             row["hadamard_over_split"] = row["fp64_hadamard"]["ms"] / row["fp64_split"]["ms"]
+            row["vjp_over_forward"] = row["fp64_vjp"]["ms"] / row["fp64_split"]["ms"]
             extras[f"tet_p{p}_tgv_196608_curved"] = row
         extras["ns_tgv_82944_p3"] = ns_rows(args)
         extras["hybrid_tri_p4"] = hybrid_rows(args, meshes[4], states[4], ne)
