@@ -46,3 +46,55 @@ def test_reference_operator_matches_oracle(dim, p):
     assert np.abs(a["facet_w"] - b["facet_w"]).max() < 1e-15
     scale = np.abs(b["Q"]).max()
     assert np.abs(a["Q"] - b["Q"]).max() < 1e-13 * scale
+
+
+def test_null_handles_and_invalid_setups_are_errors():
+    """Every call that takes a handle refuses a null one with SBP_EINVAL (and
+    a message), before touching a device; sbp_setup_mesh refuses invalid
+    descriptions during its host-side checks: a bad dimension, and a
+    quadratic tetrahedral map at degree 1 (Assumption 1)."""
+    import ctypes as C
+    from paper_2305_07181_amd import sbp, workloads as wl
+    lib = sbp._lib
+    null = None
+    buf = (C.c_double * 8)()
+    calls = {
+        "sbp_mesh_info": lambda: lib.sbp_mesh_info(null, None),
+        "sbp_residual": lambda: lib.sbp_residual(null, buf, buf, None, None),
+        "sbp_residual_vjp": lambda: lib.sbp_residual_vjp(null, buf, buf, buf, None),
+        "sbp_rrk_step": lambda: lib.sbp_rrk_step(null, buf, C.c_double(0.1), C.c_double(0.1), None, None),
+        "sbp_diagnostics": lambda: lib.sbp_diagnostics(null, buf, buf, None),
+        "sbp_check_device": lambda: lib.sbp_check_device(null, None),
+        "sbp_set_time": lambda: lib.sbp_set_time(null, C.c_double(1.0)),
+        "sbp_use_graphs": lambda: lib.sbp_use_graphs(null, 1),
+        "sbp_autotune": lambda: lib.sbp_autotune(null, buf, None, None, None),
+        "sbp_get_launch_shape": lambda: lib.sbp_get_launch_shape(null, 0, 1, None, None),
+        "sbp_set_launch_shape": lambda: lib.sbp_set_launch_shape(null, 0, 1, 0, 1),
+        "sbp_set_volume_form": lambda: lib.sbp_set_volume_form(null, None),
+        "sbp_set_source": lambda: lib.sbp_set_source(null, 1, None),
+        "sbp_source_state": lambda: lib.sbp_source_state(null, C.c_double(0.0), buf, None),
+        "sbp_source_error": lambda: lib.sbp_source_error(null, buf, C.c_double(0.0), 1, buf, None),
+    }
+    for name, call in calls.items():
+        assert call() == sbp.SBP_EINVAL, name
+        assert lib.sbp_last_error(), name
+    assert lib.sbp_destroy_mesh(null) == sbp.SBP_OK
+    # invalid descriptions, refused by the host checks
+    out = C.c_void_p()
+    ph = sbp.Physics(1.4, 2.5, 0, 0, 0, 1, 0.0, 0.71, 1.0, 0)
+    assert lib.sbp_setup_mesh(None, C.byref(ph), None, C.byref(out)) == sbp.SBP_EINVAL
+    desc = wl.curved_tet_mesh(2, 1.0, 0.03)
+    vert = np.ascontiguousarray(desc["vert_xyz"], dtype=np.float64)
+    elem = np.ascontiguousarray(desc["elem_vert"], dtype=np.int32)
+    period = np.ascontiguousarray(desc["period"], dtype=np.float64)
+    geom = np.ascontiguousarray(desc["geom_nodes"], dtype=np.float64)
+    deg = np.ones(len(elem), dtype=np.int32)
+    d = sbp.MeshDesc()
+    d.dim, d.n_vert, d.n_elem = 3, len(vert), len(elem)
+    d.vert_xyz, d.elem_vert, d.period, d.elem_degree = sbp._dp(vert), sbp._ip(elem), sbp._dp(period), sbp._ip(deg)
+    d.p_geom, d.geom_nodes, d.n_problems = 2, sbp._dp(geom), 1
+    assert lib.sbp_setup_mesh(C.byref(d), C.byref(ph), None, C.byref(out)) == sbp.SBP_EINVAL
+    assert b"Assumption 1" in lib.sbp_last_error()
+    d.dim = 4
+    assert lib.sbp_setup_mesh(C.byref(d), C.byref(ph), None, C.byref(out)) == sbp.SBP_EINVAL
+    assert not out.value
