@@ -36,6 +36,7 @@ struct GasC {
   T ja, jb_inv;          // (1-alpha-gamma)/(alpha+gamma), (alpha+gamma)/(1-gamma)
   T sfac;                // (gamma-1)(gamma+alpha)/(gamma alpha)
   T ggm1;                // gamma/(gamma-1)
+  T gm1_a;               // (gamma-1)/alpha
   ExpAvgC<T> e1, e2;     // exponential averages of z1 (r1) and p (r2)
 };
 
@@ -75,6 +76,7 @@ __host__ GasC<T> make_gas(double gamma, double beta) {
   G.jb_inv = (T)((alpha + gamma) / (1.0 - gamma));
   G.sfac = (T)((gamma - 1.0) * (gamma + alpha) / (gamma * alpha));
   G.ggm1 = (T)(gamma / (gamma - 1.0));
+  G.gm1_a = (T)((gamma - 1.0) / alpha);
   G.e1 = make_exp_avg<T>(-gamma / alpha);
   G.e2 = make_exp_avg<T>((1.0 - gamma) / alpha);
   return G;
@@ -157,8 +159,8 @@ __device__ __forceinline__ void jvp_flux(const Node<D, T> &n, const GasC<T> &G, 
     Vg += n.V[k] * g[1 + k];
   }
   const T theta = n.p / n.rho;
-  const T c1 = G.gm1 / G.a * iWn;  // (gamma-1)/(alpha W_nc)
-  const T dtheta = c1 * (g[0] + Vg) + (-theta + (T)0.5 * G.gm1 / G.a * q2) * iWn * g[D + 1];
+  const T c1 = G.gm1_a * iWn;  // (gamma-1)/(alpha W_nc)
+  const T dtheta = c1 * (g[0] + Vg) + (-theta + (T)0.5 * G.gm1_a * q2) * iWn * g[D + 1];
   // ln(-W_nc) = ja ln(theta) + jb ln(rho)
   const T drho = n.rho * (g[D + 1] * iWn - G.ja * dtheta / theta) * G.jb_inv;
   const T dp = theta * drho + n.rho * dtheta;
@@ -313,11 +315,11 @@ __device__ __forceinline__ void dtheta_dW(const Node<D, T> &n, const GasC<T> &G,
   T q2 = 0;
 #pragma unroll
   for (int k = 0; k < D; ++k) q2 += n.V[k] * n.V[k];
-  const T c1 = G.gm1 / G.a * iWn;
+  const T c1 = G.gm1_a * iWn;
   out[0] = c1;
 #pragma unroll
   for (int k = 0; k < D; ++k) out[1 + k] = c1 * n.V[k];
-  out[D + 1] = (-(n.p / n.rho) + (T)0.5 * G.gm1 / G.a * q2) * iWn;
+  out[D + 1] = (-(n.p / n.rho) + (T)0.5 * G.gm1_a * q2) * iWn;
 }
 
 // Viscous flux F^{V(i)}, i = 0..D-1, from the entropy-variable gradient
@@ -413,8 +415,8 @@ __device__ __forceinline__ void dU_from_dW(const Node<D, T> &n, const GasC<T> &G
     Vg += n.V[k] * g[1 + k];
   }
   const T theta = n.p / n.rho;
-  const T c1 = G.gm1 / G.a * iWn;
-  const T dtheta = c1 * (g[0] + Vg) + (-theta + (T)0.5 * G.gm1 / G.a * q2) * iWn * g[D + 1];
+  const T c1 = G.gm1_a * iWn;
+  const T dtheta = c1 * (g[0] + Vg) + (-theta + (T)0.5 * G.gm1_a * q2) * iWn * g[D + 1];
   const T drho = n.rho * (g[D + 1] * iWn - G.ja * dtheta / theta) * G.jb_inv;
   const T dp = theta * drho + n.rho * dtheta;
   T VdV = 0;

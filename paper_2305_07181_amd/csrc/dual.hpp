@@ -65,6 +65,7 @@ __host__ __device__ GasC<Dual<T>> dual_gas(const GasC<T> &G) {
   H.jb_inv = G.jb_inv;
   H.sfac = G.sfac;
   H.ggm1 = G.ggm1;
+  H.gm1_a = G.gm1_a;
   const ExpAvgC<T> *src[2] = {&G.e1, &G.e2};
   ExpAvgC<Dual<T>> *dst[2] = {&H.e1, &H.e2};
   for (int q = 0; q < 2; ++q) {
