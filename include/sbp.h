@@ -127,7 +127,9 @@ int sbp_residual(sbp_mesh *mesh, const void *u_dev, void *r_dev,
                  double *entropy_rate_dev, void *hip_stream);
 
 /* ubar = (dr/du)^T lambda (vector-Jacobian product of sbp_residual).  Not in
- * the paper.  Layouts as for sbp_residual, all FP64. */
+ * the paper.  Layouts as for sbp_residual, all FP64.  Euler terms (with or
+ * without dissipation) in either volume form; SBP_ENOTSUP with the viscous
+ * terms or while hybrid form flags are set. */
 int sbp_residual_vjp(sbp_mesh *mesh, const void *u_dev, const void *lambda_dev,
                      void *ubar_dev, void *hip_stream);
 

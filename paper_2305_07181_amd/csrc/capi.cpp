@@ -1086,10 +1086,19 @@ int sbp_residual(sbp_mesh *M, const void *u, void *r, double *ent_dev, void *str
 int sbp_residual_vjp(sbp_mesh *M, const void *u, const void *lam, void *ubar, void *stream) {
   if (!M || !u || !lam || !ubar) return fail(SBP_EINVAL, "null argument");
   const sbp_physics &ph = M->phys;
-  if (ph.viscous || ph.form != SBP_FORM_SPLIT)
-    return fail(SBP_ENOTSUP, "the VJP covers the entropy-split Euler residual (with or without dissipation)");
+  if (ph.viscous) return fail(SBP_ENOTSUP, "the VJP covers the Euler residual (with or without dissipation)");
   if (M->eform)
-    return fail(SBP_ENOTSUP, "the VJP covers the entropy-split form; clear the hybrid form flags first");
+    return fail(SBP_ENOTSUP, "the VJP covers one volume form per mesh; clear the hybrid form flags first");
+  if (ph.form == SBP_FORM_HADAMARD) {
+    for (auto &c : M->cls) {
+      sbp::KArgs<double> A = kargs<double>(M, c, (const double *)u, nullptr, c.op64);
+      A.lam = (const double *)lam;
+      A.ubar = (double *)ubar;
+      A.Hn = c.d_Hn;
+      HIPCHK(sbp::launch_vjp_hadamard(M->dim, c.p, A, (hipStream_t)stream));
+    }
+    return SBP_OK;
+  }
   if (M->dim == 2 && M->cls.size() > 1) {
     // every degree class in one persistent launch
     sbp::KArgs<double> a[4];

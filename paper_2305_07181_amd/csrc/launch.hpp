@@ -45,6 +45,9 @@ hipError_t launch_visc_q(int dim, int p, const KArgs<float> &A, hipStream_t s);
 // Variants: register budget of one or two waves per SIMD.
 hipError_t launch_vjp(int dim, int p, const KArgs<double> &A, hipStream_t s, LaunchCfg cfg = {});
 int vjp_variants(int dim, int p);
+// VJP of the Hadamard form (A.curved selects the curved-tetrahedron kernel);
+// elements of the other form are skipped (hybrid scheme, A.eform/A.form_id)
+hipError_t launch_vjp_hadamard(int dim, int p, const KArgs<double> &A, hipStream_t s);
 // 2D, every degree class in one persistent launch (cls[p-1] or null)
 hipError_t launch_vjp2_batch(const KArgs<double> *const cls[4], hipStream_t s, int grid = 1);
 

@@ -669,6 +669,190 @@ __global__ __launch_bounds__(kT, W) void k_vjp3c(KArgs<double> A) {
   }
 }
 
+// VJP of the Hadamard form (the comparator, eq. weak form 2pt; not in the
+// paper).  With r_a = -H_a^-1 sum_{n != a} c_an . F*(u_a, u_n),
+// c_an = sum_l S_l[a][n] (Lambda_.l(a) + Lambda_.l(n)), the two-point flux
+// symmetric in its arguments and c_na = -c_an, the contributions of row a
+// and of the other rows to u_a combine into one gradient per pair of a's own
+// two-point flux with the cotangent lambda_a/H_a - lambda_n/H_n (as for the
+// facet SATs):
+//   ubar_a = -sum_{n != a} grad_{u_a}[c_an . F*(u_a, u_n)]^T (lambda_a/H_a - lambda_n/H_n)
+// plus the facet SAT adjoint.  One lane per node row; node values (V, p, z1,
+// the flux powers, lambda/H) and per-node metrics of the tile in LDS; S_l
+// through the caches (rows read transposed, S being stored exactly skew).
+// The kernel skips the elements of the other form (hybrid scheme).
+template <int DIM, int P, bool CURVED>
+__global__ __launch_bounds__(kT) void k_vjp_had(KArgs<double> A) {
+  constexpr int D = DIM, NC = D + 2, NFAC = D + 1;
+  constexpr int NP = Shape<DIM, P>::NP, NF = Shape<DIM, P>::NF, NFN = NFAC * NF;
+  constexpr int EB = kT / NP;
+  constexpr bool PN = DIM == 2 || CURVED;         // metrics per node
+  constexpr int NM = D * D + 1;                   // Lambda (row i, col l), J
+  constexpr int NG = DIM == 2 ? 12 : (CURVED ? 30 : 10);
+  constexpr int NV = D + 4;                       // V, p, z1, P1, P2
+  __shared__ double nd[NV + NC][EB][NP];           // ... and lambda / H
+  __shared__ double met[PN ? NM : 1][EB][PN ? NP : 1];
+  __shared__ double gs[EB][NG];
+  const int tid = threadIdx.x;
+  const int e = tid / NP, a = tid % NP;
+  const GasC<double> &G = A.G;
+  const int ntiles = (A.n_elem + EB - 1) / EB;
+  for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    const int e0 = tl * EB;
+    const int ne = min(EB, A.n_elem - e0);
+    if (!tile_on(A, e0, ne)) continue;  // hybrid scheme: no element of this form
+    const bool act = tid < ne * NP && elem_on(A, e0 + e);
+    const int eg = e0 + e;
+    __syncthreads();
+    for (int x = tid; x < ne * NG; x += kT) gs[x / NG][x % NG] = A.geo[(size_t)(e0 + x / NG) * NG + x % NG];
+    __syncthreads();
+    Node<D, double> n;
+    double lm[NC], L[D][D], H = 1.0, ak[D];
+    if (act) {
+      double J;
+      if constexpr (DIM == 2) {
+        const double *g = gs[e];
+        double F[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          const double d0 = A.op.dN[(0 * 6 + q) * NP + a], d1 = A.op.dN[(1 * 6 + q) * NP + a];
+          F[0][0] += d0 * g[2 * q];
+          F[0][1] += d1 * g[2 * q];
+          F[1][0] += d0 * g[2 * q + 1];
+          F[1][1] += d1 * g[2 * q + 1];
+        }
+        L[0][0] = F[1][1];
+        L[0][1] = -F[1][0];
+        L[1][0] = -F[0][1];
+        L[1][1] = F[0][0];
+        J = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+      } else if constexpr (CURVED) {
+        double F[3][3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int l = 0; l < 3; ++l) F[k][l] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 10; ++q)
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            const double d = A.op.dN[(l * 10 + q) * NP + a];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) F[k][l] += d * gs[e][q * 3 + k];
+          }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            const int k1 = (k + 1) % 3, k2 = (k + 2) % 3, l1 = (l + 1) % 3, l2 = (l + 2) % 3;
+            L[k][l] = F[k1][l1] * F[k2][l2] - F[k1][l2] * F[k2][l1];
+          }
+        J = F[0][0] * L[0][0] + F[0][1] * L[0][1] + F[0][2] * L[0][2];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int l = 0; l < 3; ++l) L[k][l] = gs[e][k * 3 + l];
+        J = gs[e][9];
+      }
+      if constexpr (PN) {
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+#pragma unroll
+          for (int l = 0; l < D; ++l) met[k * D + l][e][a] = L[k][l];
+      }
+      H = J * A.op.h[a];
+      const int uo = A.uoff[eg];
+      double uu[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        uu[c] = A.u[uo + c * NP + a];
+        lm[c] = A.lam[uo + c * NP + a];
+      }
+      node_from_u<D, double>(uu, G, n);
+      if (!n.ok) atomicOr(A.err, 1);
+      node_powers<D, double>(G, n);
+#pragma unroll
+      for (int i = 0; i < D; ++i) nd[i][e][a] = n.V[i];
+      nd[D][e][a] = n.p;
+      nd[D + 1][e][a] = n.z1;
+      nd[D + 2][e][a] = n.P1;
+      nd[D + 3][e][a] = n.P2;
+      const double iH = 1.0 / H;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) nd[NV + c][e][a] = lm[c] * iH;
+#pragma unroll
+      for (int m = 0; m < D; ++m) {
+        double t = 0.0;
+#pragma unroll
+        for (int l = 0; l < D; ++l) t += L[m][l] * A.op.E[l * NP + a];
+        ak[m] = t;
+      }
+    }
+    __syncthreads();
+    if (act) {
+      double ub[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) ub[c] = 0.0;
+      for (int nn = 0; nn < NP; ++nn) {
+        if (nn == a) continue;
+        Node<D, double> b;
+#pragma unroll
+        for (int i = 0; i < D; ++i) b.V[i] = nd[i][e][nn];
+        b.p = nd[D][e][nn];
+        b.z1 = nd[D + 1][e][nn];
+        b.P1 = nd[D + 2][e][nn];
+        b.P2 = nd[D + 3][e][nn];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) b.w[c] = 0.0;  // read only with dissipation
+        double sl[D];
+#pragma unroll
+        for (int l = 0; l < D; ++l) sl[l] = -A.op.S[(l * NP + nn) * NP + a];  // S_l[a][nn]
+        double cvec[D], mu[NC], g[NC];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          double t = 0.0;
+#pragma unroll
+          for (int l = 0; l < D; ++l) {
+            const double lsum = PN ? L[i][l] + met[i * D + l][e][PN ? nn : 0] : 2.0 * L[i][l];
+            t += sl[l] * lsum;
+          }
+          cvec[i] = t;
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) mu[c] = nd[NV + c][e][a] - nd[NV + c][e][nn];
+        facet_grad_rev<D>(n, b, cvec, mu, G, false, g);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ub[c] -= g[c];
+      }
+      // facet SATs: as in the entropy-split VJP
+      if (a < NFN) {
+        const int off = A.nbr[(size_t)eg * NFN + a];
+        double uv[NC], lv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          uv[c] = A.u[off + c * NP];
+          lv[c] = A.lam[off + c * NP];
+        }
+        const int q = A.nbrq[(size_t)eg * NFN + a];
+        const double Hv = A.Hn[(size_t)(q / NFN) * NP + q % NFN];
+        double mu[NC], g1[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) mu[c] = lm[c] / H - lv[c] / Hv;
+        Node<D, double> nv;
+        node_from_u<D, double>(uv, G, nv);
+        node_powers<D, double>(G, nv);
+        facet_grad_rev<D>(n, nv, ak, mu, G, A.diss != 0, g1);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ub[c] -= g1[c];
+      }
+      const int uo = A.uoff[eg];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) A.ubar[uo + c * NP + a] = ub[c];
+    }
+  }
+}
+
 namespace {
 
 // kernel of a VJP slot: variant 0 the built-in register budget, 1 the other
@@ -707,6 +891,25 @@ const void *vjp3c_kernel(int p, int variant, int &eb) {
 }
 
 }  // namespace
+
+hipError_t launch_vjp_hadamard(int dim, int p, const KArgs<double> &A, hipStream_t s) {
+  if (A.n_elem <= 0) return hipSuccess;
+  const void *fn = nullptr;
+  int eb = 0;
+#define SBP_VH(DD, PP, CC)                                                              \
+  if (dim == DD && p == PP && (A.curved != 0) == CC) {                                   \
+    fn = reinterpret_cast<const void *>(&k_vjp_had<DD, PP, CC>);                          \
+    eb = kT / Shape<DD, PP>::NP;                                                          \
+  }
+  SBP_VH(2, 1, false) SBP_VH(2, 2, false) SBP_VH(2, 3, false) SBP_VH(2, 4, false)
+  SBP_VH(3, 1, false) SBP_VH(3, 2, false) SBP_VH(3, 3, false) SBP_VH(3, 2, true) SBP_VH(3, 3, true)
+#undef SBP_VH
+  if (!fn) return hipErrorInvalidValue;
+  const int nb = launch_grid(fn, (A.n_elem + eb - 1) / eb, 1);
+  KArgs<double> a = A;
+  void *args[] = {&a};
+  return hipLaunchKernel(fn, dim3(nb), dim3(kT), args, 0, s);
+}
 
 hipError_t launch_vjp(int dim, int p, const KArgs<double> &A, hipStream_t s, LaunchCfg cfg) {
   if (A.n_elem <= 0) return hipSuccess;

@@ -146,3 +146,38 @@ def test_vjp_finite_difference_and_cost():
     say("   fd", fd, "ad", ad, "rel", abs(fd - ad) / abs(ad))
     assert abs(fd - ad) <= 1e-6 * abs(ad)
     mesh.close()
+
+
+HAD_CASES = ([("tri", p, d) for p in (1, 2, 3, 4) for d in (False, True)]
+             + [("tet", p, d) for p in (1, 2, 3) for d in (False, True)]
+             + [("tet-curved", p, d) for p in (2, 3) for d in (False, True)])
+
+
+@pytest.mark.parametrize("mesh_kind,p,diss", HAD_CASES)
+def test_vjp_hadamard_vs_oracle(mesh_kind, p, diss):
+    """VJP of the Hadamard form (curved triangles, affine and curved
+    tetrahedra, with and without dissipation) against the oracle's
+    complex-step Jacobian of its Hadamard residual on sampled elements."""
+    import torch
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from oracle.jacobian import vjp_elements
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say(f"[vjp hadamard] {mesh_kind} p={p} diss={diss}")
+    desc = {"tri": lambda: wl.vortex2d_mesh(4, warp=0.05), "tet": lambda: wl.periodic_tet_mesh(2, 1.0),
+            "tet-curved": lambda: wl.curved_tet_mesh(2, 1.0, 0.03)}[mesh_kind]()
+    m = OracleMesh(desc, p)
+    u = state(m, "random", seed=26, jitter=0.01)
+    lam = np.random.default_rng(2300 + p).standard_normal(u.shape)
+    mesh = sbp.Mesh(desc, p, dissipation=diss, form=sbp.FORM_HADAMARD)
+    ub = mesh.vjp(torch.from_numpy(u).cuda(), torch.from_numpy(lam).cuda()).cpu().numpy()
+    mesh.check_device()
+    mesh.close()
+    sch = OracleScheme(m, ph.Gas(), form="hadamard", dissipation=diss)
+    els = [0, 11, 23, 31]
+    ref = vjp_elements(sch, u, lam, els)
+    scale = max(np.abs(ref[e]).max() for e in els)
+    err = max(np.abs(ub[e] - ref[e]).max() for e in els) / scale
+    say("   rel err", err)
+    assert err <= 1e-12, err
