@@ -128,8 +128,8 @@ int sbp_residual(sbp_mesh *mesh, const void *u_dev, void *r_dev,
 
 /* ubar = (dr/du)^T lambda (vector-Jacobian product of sbp_residual).  Not in
  * the paper.  Layouts as for sbp_residual, all FP64.  Euler terms (with or
- * without dissipation) in either volume form; SBP_ENOTSUP with the viscous
- * terms or while hybrid form flags are set. */
+ * without dissipation) in either volume form and with the hybrid form flags;
+ * SBP_ENOTSUP with the viscous terms. */
 int sbp_residual_vjp(sbp_mesh *mesh, const void *u_dev, const void *lambda_dev,
                      void *ubar_dev, void *hip_stream);
 
@@ -156,8 +156,8 @@ int sbp_rrk_step(sbp_mesh *mesh, void *u_dev, double dt, double cfl,
  * contents between calls (switching between time steps; a captured RK stage
  * graph reads the same array).  NULL returns every element to phys.form.
  * Values other than 0 and 1 leave the element's residual unwritten.
- * SBP_ENOTSUP with the viscous terms; while it is set, sbp_residual_vjp
- * returns SBP_ENOTSUP.  The FP64 entropy rate sums both launches. */
+ * SBP_ENOTSUP with the viscous terms.  sbp_residual_vjp follows the flags.
+ * The FP64 entropy rate sums both launches. */
 int sbp_set_volume_form(sbp_mesh *mesh, const uint8_t *form_dev);
 
 /* Source terms of the manufactured-solution study (Sec. 7, manufactured

@@ -1087,15 +1087,24 @@ int sbp_residual_vjp(sbp_mesh *M, const void *u, const void *lam, void *ubar, vo
   if (!M || !u || !lam || !ubar) return fail(SBP_EINVAL, "null argument");
   const sbp_physics &ph = M->phys;
   if (ph.viscous) return fail(SBP_ENOTSUP, "the VJP covers the Euler residual (with or without dissipation)");
-  if (M->eform)
-    return fail(SBP_ENOTSUP, "the VJP covers one volume form per mesh; clear the hybrid form flags first");
-  if (ph.form == SBP_FORM_HADAMARD) {
+  if (M->eform || ph.form == SBP_FORM_HADAMARD) {
+    // Hadamard form, or the hybrid scheme: each form's kernel takes the
+    // elements flagged with it (both kernels for every class)
+    const hipStream_t s = (hipStream_t)stream;
     for (auto &c : M->cls) {
       sbp::KArgs<double> A = kargs<double>(M, c, (const double *)u, nullptr, c.op64);
       A.lam = (const double *)lam;
       A.ubar = (double *)ubar;
       A.Hn = c.d_Hn;
-      HIPCHK(sbp::launch_vjp_hadamard(M->dim, c.p, A, (hipStream_t)stream));
+      A.eform = M->eform;
+      for (int form : {SBP_FORM_SPLIT, SBP_FORM_HADAMARD}) {
+        if (!M->eform && form != ph.form) continue;
+        A.form_id = form;
+        if (form == SBP_FORM_HADAMARD)
+          HIPCHK(sbp::launch_vjp_hadamard(M->dim, c.p, A, s));
+        else
+          HIPCHK(sbp::launch_vjp(M->dim, c.p, A, s, c.vjp_cfg));
+      }
     }
     return SBP_OK;
   }

@@ -88,8 +88,9 @@ __global__ __launch_bounds__(kT, W) void k_vjp3v(KArgs<double> A) {
   for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
     const int e0 = tl * EB;
     const int ne = min(EB, A.n_elem - e0);
-    const bool act = tid < ne * NP;
+    if (!tile_on(A, e0, ne)) continue;  // hybrid scheme: no element of this form
     const int eg = e0 + e;
+    const bool act = tid < ne * NP && elem_on(A, eg);
     __syncthreads();
     for (int x = tid; x < ne * 10; x += kT) gs[x / 10][x % 10] = A.geo[(size_t)(e0 + x / 10) * 10 + x % 10];
     __syncthreads();
@@ -271,8 +272,9 @@ struct Vjp2 {
     const int tid = threadIdx.x;
     const int e0 = tl * EB;
     const int ne = min(EB, A.n_elem - e0);
-    const bool act = tid < ne * NP;
+    if (!tile_on(A, e0, ne)) return;  // hybrid scheme: no element of this form
     const int e = tid / NP, j = tid % NP, eg = e0 + e;
+    const bool act = tid < ne * NP && elem_on(A, eg);
     const GasC<double> &G = A.G;
     const GasC<Dual<double>> GD = dual_gas(G);
     const double cb = G.cb, he = 0.5 * (1.0 + cb), hz = 0.5 * (1.0 - cb);
@@ -506,8 +508,9 @@ __global__ __launch_bounds__(kT, W) void k_vjp3c(KArgs<double> A) {
   for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
     const int e0 = tl * EB;
     const int ne = min(EB, A.n_elem - e0);
-    const bool act = tid < ne * NP;
+    if (!tile_on(A, e0, ne)) continue;  // hybrid scheme: no element of this form
     const int eg = e0 + e;
+    const bool act = tid < ne * NP && elem_on(A, eg);
     __syncthreads();
     for (int x = tid; x < ne * 30; x += kT) gs[x / 30][x % 30] = A.geo[(size_t)(e0 + x / 30) * 30 + x % 30];
     __syncthreads();

@@ -1,7 +1,7 @@
 """Hybrid scheme on the GPU (Sec. 4.4, Thm. switching hybrid): per-element
 volume form flags (0 entropy split, 1 Hadamard) against the oracle's hybrid
 residual, flags changed between calls and between RRK steps, batched problems,
-FP32, a mesh set up in the Hadamard form, and the VJP refusal."""
+FP32, a mesh set up in the Hadamard form, and the VJP with flags set."""
 import numpy as np
 import pytest
 
@@ -138,9 +138,23 @@ def test_hybrid_batched_problems():
         total += sch.entropy_rate(ub, ro)
         scale += np.sum(np.abs(ro))
     assert abs(float(er.cpu()[0]) - total) <= 1e-12 * scale
-    with pytest.raises(sbp.SbpError) as ei:
-        mesh.vjp(u, torch.ones_like(u))
-    assert ei.value.code == sbp.SBP_ENOTSUP
+    # the VJP follows the flags: each form's kernel on its own elements
+    from oracle.jacobian import vjp_elements
+    lam = torch.randn(u.shape, dtype=torch.float64, device="cuda",
+                      generator=torch.Generator(device="cuda").manual_seed(5))
+    ub = mesh.vjp(u, lam).cpu().numpy()
+    mesh.check_device()
+    lparts = _split(mesh, off, lam.cpu().numpy(), [s_.shape for s_ in states])
+    uparts = _split(mesh, off, ub, [s_.shape for s_ in states])
+    for b in (0, 1):
+        m = meshes[b]
+        sch = OracleScheme(m, ph.Gas(), form="hybrid", element_form=flags[off[b]:off[b + 1]])
+        els = [0, m.ne // 2, m.ne - 1]
+        ref = vjp_elements(sch, states[b], lparts[b], els)
+        sc = max(np.abs(ref[e]).max() for e in els)
+        err = max(np.abs(uparts[b][e] - ref[e]).max() for e in els) / sc
+        say(f"   hybrid VJP problem {b}: rel err {err:.2e}")
+        assert err <= 1e-12, err
     mesh.set_volume_form(None)
     mesh.vjp(u, torch.ones_like(u))
     mesh.close()

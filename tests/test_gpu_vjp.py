@@ -181,3 +181,36 @@ def test_vjp_hadamard_vs_oracle(mesh_kind, p, diss):
     err = max(np.abs(ub[e] - ref[e]).max() for e in els) / scale
     say("   rel err", err)
     assert err <= 1e-12, err
+
+
+@pytest.mark.parametrize("mesh_kind,p,diss", [("tri", 3, False), ("tri", 4, True), ("tet", 2, True),
+                                              ("tet-curved", 3, False)])
+def test_vjp_hybrid_vs_oracle(mesh_kind, p, diss):
+    """VJP with random per-element form flags (the hybrid scheme) against the
+    oracle's complex-step Jacobian of its hybrid residual."""
+    import torch
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from oracle.jacobian import vjp_elements
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say(f"[vjp hybrid] {mesh_kind} p={p} diss={diss}")
+    desc = {"tri": lambda: wl.vortex2d_mesh(4, warp=0.05), "tet": lambda: wl.periodic_tet_mesh(2, 1.0),
+            "tet-curved": lambda: wl.curved_tet_mesh(2, 1.0, 0.03)}[mesh_kind]()
+    m = OracleMesh(desc, p)
+    flags = np.random.default_rng(40 + p).integers(0, 2, m.ne).astype(np.uint8)
+    u = state(m, "random", seed=36, jitter=0.01)
+    lam = np.random.default_rng(2400 + p).standard_normal(u.shape)
+    mesh = sbp.Mesh(desc, p, dissipation=diss)
+    fd = torch.from_numpy(flags).cuda()
+    mesh.set_volume_form(fd)
+    ub = mesh.vjp(torch.from_numpy(u).cuda(), torch.from_numpy(lam).cuda()).cpu().numpy()
+    mesh.check_device()
+    mesh.close()
+    sch = OracleScheme(m, ph.Gas(), form="hybrid", element_form=flags, dissipation=diss)
+    els = [0, 5, 11, 23, 31]
+    ref = vjp_elements(sch, u, lam, els)
+    scale = max(np.abs(ref[e]).max() for e in els)
+    err = max(np.abs(ub[e] - ref[e]).max() for e in els) / scale
+    say("   rel err", err, "flags on Hadamard:", int(flags.sum()), "of", m.ne)
+    assert err <= 1e-12, err
