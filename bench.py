@@ -402,6 +402,11 @@ def main():
                                 device="cuda")
                 med, _ = _time_calls(lambda: msh.residual(states[p], r), max(5, args.steps // 2), 2)
                 row[name] = dict(ms=med * 1e3, elem_dof_per_s=ne * n_p[p] / med)
+                if name == "fp64_hadamard":
+                    ubh = torch.empty_like(states[p])
+                    med, _ = _time_calls(lambda: msh.vjp(states[p], lams[p], ubh), max(5, args.steps // 2), 2)
+                    row["fp64_hadamard_vjp"] = dict(ms=med * 1e3, elem_dof_per_s=ne * n_p[p] / med)
+                    del ubh
                 if msh is not meshes[p]:
                     msh.close()
             row["hadamard_over_split"] = row["fp64_hadamard"]["ms"] / row["fp64_split"]["ms"]
