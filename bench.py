@@ -38,7 +38,7 @@ PEAK_F32 = 157.3e12
 # they were taken on (sha256 prefix of the concatenated sources below).
 TRAFFIC_SOURCES = ["residual_kernels.hip", "device_physics.hpp", "mfma.hpp", "kernels.hpp"]
 TRAFFIC_SHA = "158e05e9a0c859fa"  # kernel_source_hash() of the profiled build
-TRAFFIC_BYTES = {1: 26.14e6, 2: 42.09e6, 3: 69.74e6, 4: 81.58e6}  # k_split2<p, double, 2>
+TRAFFIC_BYTES = {1: 26.02e6, 2: 41.99e6, 3: 69.59e6, 4: 81.47e6}  # k_split2<p, double, 2>
 
 
 def _args():
