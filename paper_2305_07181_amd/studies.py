@@ -5,7 +5,7 @@
     python -m paper_2305_07181_amd.studies mms --dim 3 [--ns 6 9 12 15]
         [--ps 1 2 3] [--tf 0.001] [--steps 1000] [--mu 0.01]
     python -m paper_2305_07181_amd.studies vortex2d [--ns 60 80 100 120]
-        [--ps 1 2 3 4] [--tf 2.0] [--cfl 0.1]
+        [--ps 1 2 3 4] [--tf 2.0] [--cfl 0.1] [--hadamard]
     python -m paper_2305_07181_amd.studies vortex3d [--ns 15 20 25 30]
         [--ps 1 2 3] [--tf 1.0] [--cfl 0.25]
 
@@ -146,13 +146,13 @@ def mms_study(dim, ns, ps, tf=1e-3, steps=1000, mu=0.01, emit=print):
     return rows
 
 
-def vortex_run(dim: int, n: int, p: int, dissipation: bool, tf: float, cfl: float) -> dict:
+def vortex_run(dim: int, n: int, p: int, dissipation: bool, tf: float, cfl: float, hadamard: bool = False) -> dict:
     from . import sbp, workloads as wl
     if dim == 2:
         desc = wl.paper_vortex2d_mesh(n)
     else:
         desc = wl.paper_vortex3d_mesh(n, quadratic=p >= 2)
-    mesh = sbp.Mesh(desc, p, dissipation=dissipation)
+    mesh = sbp.Mesh(desc, p, dissipation=dissipation, form=sbp.FORM_HADAMARD if hadamard else sbp.FORM_SPLIT)
     mesh.set_source(sbp.SOURCE_VORTEX2D if dim == 2 else sbp.SOURCE_VORTEX3D)
     mesh.set_time(0.0)
     u = mesh.source_state(0.0)
@@ -165,7 +165,8 @@ def vortex_run(dim: int, n: int, p: int, dissipation: bool, tf: float, cfl: floa
     e = mesh.source_error(u, t, "quadrature")
     d1 = mesh.diagnostics(u)
     mesh.check_device()
-    out = dict(dim=dim, n=n, p=p, n_elem=int(mesh.n_elem), dissipation=dissipation, steps=steps, t=t,
+    out = dict(dim=dim, n=n, p=p, n_elem=int(mesh.n_elem), form="hadamard" if hadamard else "split",
+               dissipation=dissipation, steps=steps, t=t,
                seconds=secs, l2_error=math.sqrt(float(e.sum())), entropy_change=(d1[0] - d0[0]) / abs(d0[0]))
     mesh.close()
     return out
@@ -175,13 +176,13 @@ def vortex3d_run(n: int, p: int, dissipation: bool, tf: float = 1.0, cfl: float 
     return vortex_run(3, n, p, dissipation, tf, cfl)
 
 
-def vortex_study(dim, ns, ps, tf, cfl, emit=print):
+def vortex_study(dim, ns, ps, tf, cfl, emit=print, hadamard=False):
     rows = []
     for p in ps:
         for diss in (False, True):
             prev = None
             for n in ns:
-                r = vortex_run(dim, n, p, diss, tf, cfl)
+                r = vortex_run(dim, n, p, diss, tf, cfl, hadamard)
                 if prev is not None:   # h = (volume / n_e)^(1/d) falls as 1/n
                     r["rate"] = math.log(prev["l2_error"] / r["l2_error"]) / math.log(n / prev["n"])
                 emit(json.dumps(r))
@@ -200,15 +201,17 @@ def main(argv=None):
     ap.add_argument("--dim", type=int, default=3)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--mu", type=float, default=0.01)
+    ap.add_argument("--hadamard", action="store_true", help="vortex studies: the Hadamard form (comparator)")
     a = ap.parse_args(argv)
     emit = lambda s: print(s, flush=True)
     if a.study == "conservation":
         conservation_study(a.ns or [60, 80, 100, 120], a.ps or [1, 2, 3, 4], a.tf or 2.0, a.cfl, emit=emit)
     elif a.study == "vortex3d":
         vortex_study(3, a.ns or [15, 20, 25, 30], a.ps or [1, 2, 3], a.tf or 1.0, a.cfl if a.cfl != 0.1 else 0.25,
-                     emit=emit)
+                     emit=emit, hadamard=a.hadamard)
     elif a.study == "vortex2d":
-        vortex_study(2, a.ns or [60, 80, 100, 120], a.ps or [1, 2, 3, 4], a.tf or 2.0, a.cfl, emit=emit)
+        vortex_study(2, a.ns or [60, 80, 100, 120], a.ps or [1, 2, 3, 4], a.tf or 2.0, a.cfl, emit=emit,
+                     hadamard=a.hadamard)
     else:
         ns = a.ns or ([20, 30, 40, 50] if a.dim == 2 else [6, 9, 12, 15])
         ps = a.ps or ([1, 2, 3, 4] if a.dim == 2 else [1, 2, 3])
