@@ -6,7 +6,9 @@ the benchmark times (the autotuner's choice on the same handle):
   * the Taylor-Green grid, 32^3 x 6 = 196608 tetrahedra, p = 2, 3 with matrix
     dissipation (the same four);
   * the Navier-Stokes Taylor-Green grid, 24^3 x 6 = 82944 tetrahedra, p = 3,
-    heat flux and matrix dissipation on (FP64 and FP32).
+    heat flux and matrix dissipation on (FP64 and FP32);
+  * the 48-problem mixed-degree batch, 190202 triangles (residual, VJP and
+    the finite-difference check of the whole batch).
 
 The oracle evaluates sampled elements one by one (their facet neighbours'
 states enter through the SATs); the inputs are the oracle's node coordinates
@@ -218,3 +220,67 @@ def test_ns_tgv82944_sampled():
         mesh.check_device()
         _check_sampled(r.double().cpu().numpy(), ro, sch, u, els, tol, what)
         mesh.close()
+
+
+def test_batch48_sampled():
+    """The 48-problem batch (p ~ U{1..4}, n_e ~ logU[256, 16384], seed 0;
+    190202 triangles in one persistent launch per call), tuned as the
+    benchmark does: the residual on sampled elements of one problem of each
+    degree and of the largest one, the VJP on two elements of each, and the
+    finite-difference check of the whole batch (lambda ~ N(0,1), step 1e-6)."""
+    import torch
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from oracle.jacobian import vjp_elements
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say("[full batch48]")
+    specs = wl.batch_problem_specs(48, 0)
+    desc, deg, off = wl.batch_mesh(specs)
+    meshes, states = [], []
+    for b, sp in enumerate(specs):
+        m = OracleMesh(wl.sub_mesh(desc, off[b], off[b + 1]), sp["p"])
+        meshes.append(m)
+        states.append(state(m, "batch", seed=1000 + b))
+    lams = [np.random.default_rng(2000 + b).standard_normal(s.shape) for b, s in enumerate(states)]
+    dirs = [np.random.default_rng(3000 + b).standard_normal(s.shape) * np.abs(s) for b, s in enumerate(states)]
+    mesh = sbp.Mesh(desc, deg, problem_off=off)
+    nc = int(mesh.n_c)
+    lo = [int(mesh.node_off[off[b]]) * nc for b in range(len(specs) + 1)]
+    assert all(lo[b + 1] - lo[b] == states[b].size for b in range(len(specs)))   # no padding
+
+    def flat(parts):          # elements of one problem are contiguous, one n_p each
+        out = np.zeros(int(mesh.n_nodes) * nc)
+        for b, a in enumerate(parts):
+            out[lo[b]:lo[b + 1]] = a.ravel()
+        return torch.from_numpy(out).cuda()
+
+    def part(x, b):
+        return x[lo[b]:lo[b + 1]].reshape(states[b].shape)
+
+    u, lam, v = flat(states), flat(lams), flat(dirs)
+    _tuned(mesh, u, lam)
+    r = mesh.residual(u).cpu().numpy()
+    ub = mesh.vjp(u, lam).cpu().numpy()
+    mesh.check_device()
+    pick = sorted({[s["p"] for s in specs].index(q) for q in (1, 2, 3, 4)}
+                  | {int(np.argmax([m.ne for m in meshes]))})
+    for b in pick:
+        m = meshes[b]
+        sch = OracleScheme(m, ph.Gas())
+        els = _sample(m.ne, 8, 500 + b)
+        ro = sch(states[b], elements=els)
+        _check_sampled(part(r, b), ro, sch, states[b], els, TOL64, f"problem {b} p={specs[b]['p']} ne={m.ne}")
+        vel = els[:2]
+        ref = vjp_elements(sch, states[b], lams[b], vel)
+        sc = max(np.abs(ref[e]).max() for e in vel)
+        err = max(np.abs(part(ub, b)[e] - ref[e]).max() for e in vel) / sc
+        say(f"   problem {b}: VJP rel err {err:.2e}")
+        assert err <= TOL64, (b, err)
+    h = 1e-6
+    fd = float(torch.sum(lam * (mesh.residual(u + h * v) - mesh.residual(u - h * v))) / (2 * h))
+    ad = float(torch.sum(v * torch.from_numpy(ub).cuda()))
+    say(f"   FD {fd:.12e} VJP {ad:.12e} rel {abs(fd - ad) / abs(ad):.2e}")
+    assert abs(fd - ad) <= 1e-6 * abs(ad)
+    mesh.check_device()
+    mesh.close()
