@@ -262,7 +262,12 @@ int sbp_get_launch_shape(sbp_mesh *mesh, int32_t kind, int32_t p, int32_t *varia
 int sbp_set_launch_shape(sbp_mesh *mesh, int32_t kind, int32_t p, int32_t variant, int32_t grid);
 
 /* FP64 diagnostics on the device, results copied to host (synchronises):
- * out[0] = 1^T H s(u); out[1..n_c] = sum_k 1^T H_k u_k per component. */
+ * out[0] = 1^T H s(u); out[1..n_c] = sum_k 1^T H_k u_k per component;
+ * out[n_c + 1] = sum_k 1^T H_k (rho |V|^2 / 2), the kinetic energy whose
+ * scaled form E_k = out[n_c + 1] / (rho_0 |Omega|) the viscous Taylor-Green
+ * study follows (Sec. 7.5).  out_host holds n_c + 2 doubles, caller-owned;
+ * u_dev is a state laid out as for sbp_residual.  Null arguments give
+ * SBP_EINVAL. */
 int sbp_diagnostics(sbp_mesh *mesh, const void *u_dev, double *out_host,
                     void *hip_stream);
 

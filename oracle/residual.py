@@ -33,7 +33,10 @@ psi^(i) (Lemma entropy conv volume), strong = weak, vanishing SATs for
 continuous states (Lemma sats vanish), Hadamard local conservation, the
 hybrid scheme's entropy conservation with random flags (also switched between
 RRK steps) and local conservation on its Hadamard elements, and design-order
-truncation error on smooth states (Thm. high-order).
+truncation error on smooth states (Thm. high-order).  The kinetic energy:
+tests/test_oracle_tgv.py (a uniform flow gives rho |V|^2 / 2 times the
+volume; the Taylor-Green initial field gives E_k -> 1/8, its closed form,
+under refinement).
 """
 from __future__ import annotations
 
@@ -227,6 +230,16 @@ class OracleScheme:
         """s = 1^T H_g s(u)."""
         return sum(np.sum(self.mesh.geometry(e)["H"] * ph.entropy(u[e], self.gas))
                    for e in range(self.mesh.ne))
+
+    def kinetic_energy(self, u):
+        """1^T H_g (rho |V|^2 / 2): the integral whose scaled form
+        E_k = (1 / (rho_0 |Omega|)) int rho V.V / 2 the viscous Taylor-Green
+        study reports (Sec. 7.5)."""
+        tot = 0.0
+        for e in range(self.mesh.ne):
+            rho, V, _ = ph.primitive(u[e], self.gas)
+            tot = tot + np.sum(self.mesh.geometry(e)["H"] * 0.5 * rho * np.sum(V * V, axis=0))
+        return tot
 
     def timestep(self, u, cfl):
         """dt = CFL min_k h_min,k / |lambda|_max,k (Sec. 7.1)."""

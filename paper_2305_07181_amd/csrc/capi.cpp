@@ -88,7 +88,7 @@ struct sbp_mesh {
   int batch_blocks = 0;       // 2D entropy split with several degree classes: one launch
   int batch_grid = 1, vjp_batch_grid = 1;  // grid choices of the batched launches (autotuner)
   const unsigned char *eform = nullptr;      // hybrid scheme: caller's per-element form flags
-  double *d_npart = nullptr;  // node-kernel partials [(n_c+1) x node_total]
+  double *d_npart = nullptr;  // node-kernel partials [(n_c+2) x node_total]
   int node_total = 0;
   double *d_scal = nullptr;   // device scalars
   int *d_err = nullptr;
@@ -531,7 +531,7 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
   if ((rc = upload(M->d_node_xyz, xyz, s))) return rc;
   if ((rc = upload(M->d_node_h, Hn, s))) return rc;
   HIPCHK(hipMalloc((void **)&M->d_part, sizeof(double) * std::max(1, part_total)));
-  HIPCHK(hipMalloc((void **)&M->d_npart, sizeof(double) * (M->nc + 1) * std::max(1, node_total)));
+  HIPCHK(hipMalloc((void **)&M->d_npart, sizeof(double) * (M->nc + 2) * std::max(1, node_total)));
   HIPCHK(hipMalloc((void **)&M->d_scal, sizeof(double) * SC_TOTAL));
   HIPCHK(hipMemsetAsync(M->d_scal, 0, sizeof(double) * SC_TOTAL, s));
   HIPCHK(hipMalloc((void **)&M->d_err, sizeof(int)));
@@ -813,7 +813,7 @@ int diagnostics_impl(sbp_mesh *M, const double *u, double *out, hipStream_t s) {
     sbp::NodeArgs A = node_args(M, c, u, nullptr);
     HIPCHK(sbp::launch_diagnostics(A, M->d_npart + c.node_off_blk, s));
   }
-  return reduce_nodes(M, M->nc + 1, 0, out, s);
+  return reduce_nodes(M, M->nc + 2, 0, out, s);
 }
 
 // --------------------------------------------------------------------------

@@ -110,9 +110,9 @@ __global__ __launch_bounds__(kT) void k_diagnostics(NodeArgs A, double *part) {
   constexpr int NC = D + 2;
   __shared__ double red[kT / 64];
   const int x = blockIdx.x * kT + threadIdx.x;
-  double v[NC + 1];
+  double v[NC + 2];
 #pragma unroll
-  for (int c = 0; c <= NC; ++c) v[c] = 0.0;
+  for (int c = 0; c <= NC + 1; ++c) v[c] = 0.0;
   if (x < A.n_elem * A.np) {
     const int e = x / A.np, j = x % A.np;
     const int base = A.uoff[e] + j;
@@ -125,9 +125,14 @@ __global__ __launch_bounds__(kT) void k_diagnostics(NodeArgs A, double *part) {
     v[0] = H * s;
 #pragma unroll
     for (int c = 0; c < NC; ++c) v[1 + c] = H * u0[c];
+    // kinetic energy rho |V|^2 / 2 = |rho V|^2 / (2 rho)
+    double m2 = 0.0;
+#pragma unroll
+    for (int i = 1; i <= D; ++i) m2 += u0[i] * u0[i];
+    v[NC + 1] = H * (0.5 * m2 / u0[0]);
   }
 #pragma unroll
-  for (int c = 0; c <= NC; ++c) {
+  for (int c = 0; c <= NC + 1; ++c) {
     const double t = block_reduce_sum(v[c], red);
     if (threadIdx.x == 0) part[c * A.pstride + blockIdx.x] = t;
   }

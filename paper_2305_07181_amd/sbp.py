@@ -327,7 +327,10 @@ class Mesh:
         _check(_lib.sbp_use_graphs(self._h, int(bool(enable))))
 
     def diagnostics(self, u, stream=None):
-        out = np.zeros(self.n_c + 1)
+        """sbp_diagnostics: [sum H s, sum H u per component (n_c values),
+        sum H rho |V|^2 / 2]."""
+        self._check_state(u)
+        out = np.zeros(self.n_c + 2)
         _check(_lib.sbp_diagnostics(self._h, _ptr(u), _dp(out), _stream_ptr(stream)))
         return out
 

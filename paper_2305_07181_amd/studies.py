@@ -8,6 +8,8 @@
         [--ps 1 2 3 4] [--tf 2.0] [--cfl 0.1] [--hadamard]
     python -m paper_2305_07181_amd.studies vortex3d [--ns 15 20 25 30]
         [--ps 1 2 3] [--tf 1.0] [--cfl 0.25]
+    python -m paper_2305_07181_amd.studies tgv [--ns 24] [--ps 3] [--steps 100]
+        [--cfl 0.1] [--re 1600] [--fp64]
 
 Primary conservation (Sec. 4.3, Thm. conservation; the grid study of Sec. 7.3,
 Table conservation): the 2D isentropic vortex of the paper's studies on its
@@ -47,6 +49,11 @@ sbp_set_source(SOURCE_VORTEX3D) on the paper's curved grids n^3 x 6 of
 tetrahedra for p = 1), entropy conservative and with matrix dissipation,
 relaxation RK4 at CFL 0.25 until the first step at or past t_f = 1; the
 error in the paper's norm at the time reached, with rates.
+
+Viscous Taylor-Green vortex (Sec. 7.5): the history of the scaled kinetic
+energy and of the total entropy over a number of relaxation RK4 steps on
+n^3 x 6 tetrahedra (the paper compares the dissipation rate with reference
+DNS data, which is not reproduced here).
 
 Every step and every sum runs in the library (sbp_rrk_step,
 sbp_diagnostics, sbp_source_state, sbp_source_error); this module only
@@ -191,9 +198,49 @@ def vortex_study(dim, ns, ps, tf, cfl, emit=print, hadamard=False):
     return rows
 
 
+def tgv_run(n: int = 24, p: int = 3, steps: int = 100, re: float = 1600.0, cfl: float = 0.1,
+            precision: str = "fp32", emit=None) -> dict:
+    """Viscous Taylor-Green vortex (Sec. 7.5) on n^3 x 6 tetrahedra of
+    [0, 2 pi]^3, M = 0.1, Pr = 0.71, mu = 1 / Re, heat flux and matrix
+    dissipation on, relaxation RK4 (captured stage graph) at the given CFL:
+    the scaled kinetic energy E_k = sum H rho |V|^2 / 2 / (rho_0 |Omega|) and
+    the total entropy after every step, and the dissipation rate
+    epsilon = -dE_k/dt from second-order differences of the history on its
+    (variable) time points."""
+    import torch
+    from . import sbp, workloads as wl
+    desc = wl.tgv_mesh(n)
+    mesh = sbp.Mesh(desc, p, precision=sbp.FP32 if precision == "fp32" else sbp.FP64, dissipation=True,
+                    viscous=True, heat_flux=True, mu=1.0 / re, Pr=0.71, R=1.0)
+    x = mesh.node_coords().cpu().numpy().reshape(mesh.n_elem, 3, -1)
+    rho, V, pr = wl.taylor_green(np.moveaxis(x, 1, 0))
+    u = torch.from_numpy(np.ascontiguousarray(np.moveaxis(wl.conservative(rho, V, pr), 0, 1))).cuda()
+    vol = (2.0 * math.pi) ** 3
+    nc = mesh.n_c
+    d = mesh.diagnostics(u)
+    ts, eks, ss, gammas = [0.0], [d[nc + 1] / vol], [d[0]], []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        rep = mesh.rrk_step(u, cfl=cfl)
+        d = mesh.diagnostics(u)
+        ts.append(rep["t"])
+        eks.append(d[nc + 1] / vol)
+        ss.append(d[0])
+        gammas.append(rep["gamma"])
+        if emit is not None and (k + 1) % 10 == 0:
+            emit(json.dumps(dict(step=k + 1, t=ts[-1], E_k=eks[-1], entropy=ss[-1], gamma=rep["gamma"])))
+    secs = time.perf_counter() - t0
+    mesh.check_device()
+    mesh.close()
+    t, ek = np.array(ts), np.array(eks)
+    eps = -np.gradient(ek, t)      # second order on non-uniform points, one-sided at the ends
+    return dict(n=n, p=p, n_elem=6 * n ** 3, precision=precision, re=re, cfl=cfl, steps=steps, seconds=secs,
+                t=ts, E_k=eks, entropy=ss, epsilon=eps.tolist(), gamma_min=min(gammas), gamma_max=max(gammas))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["conservation", "mms", "vortex2d", "vortex3d"])
+    ap.add_argument("study", choices=["conservation", "mms", "vortex2d", "vortex3d", "tgv"])
     ap.add_argument("--ns", type=int, nargs="+")
     ap.add_argument("--ps", type=int, nargs="+")
     ap.add_argument("--tf", type=float)
@@ -202,6 +249,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--mu", type=float, default=0.01)
     ap.add_argument("--hadamard", action="store_true", help="vortex studies: the Hadamard form (comparator)")
+    ap.add_argument("--re", type=float, default=1600.0, help="tgv: Reynolds number")
+    ap.add_argument("--fp64", action="store_true", help="tgv: FP64 residuals (default FP32)")
     a = ap.parse_args(argv)
     emit = lambda s: print(s, flush=True)
     if a.study == "conservation":
@@ -209,6 +258,12 @@ def main(argv=None):
     elif a.study == "vortex3d":
         vortex_study(3, a.ns or [15, 20, 25, 30], a.ps or [1, 2, 3], a.tf or 1.0, a.cfl if a.cfl != 0.1 else 0.25,
                      emit=emit, hadamard=a.hadamard)
+    elif a.study == "tgv":
+        for n in a.ns or [24]:
+            for p in a.ps or [3]:
+                r = tgv_run(n, p, a.steps if a.steps != 1000 else 100, a.re, a.cfl,
+                            "fp64" if a.fp64 else "fp32", emit=emit)
+                emit(json.dumps(r))
     elif a.study == "vortex2d":
         vortex_study(2, a.ns or [60, 80, 100, 120], a.ps or [1, 2, 3, 4], a.tf or 2.0, a.cfl, emit=emit,
                      hadamard=a.hadamard)

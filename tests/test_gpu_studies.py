@@ -1,7 +1,8 @@
 """The primary-conservation study (Sec. 4.3, Thm. conservation) through the
 library on small grids: the conserved sums it reports are the oracle's sums
 of the same states, the relaxation step keeps the entropy, and the errors
-fall with refinement."""
+fall with refinement; the kinetic energy of the diagnostics and the
+Taylor-Green history (Sec. 7.5)."""
 import numpy as np
 import pytest
 
@@ -33,7 +34,7 @@ def test_conserved_sums_match_oracle():
     s_o = sum(np.sum(H[e] * ph.entropy(uf[e], ph.Gas())) for e in range(m.ne))
     say("   gpu", d, "oracle", s_o, sums)
     assert abs(d[0] - s_o) <= 1e-13 * abs(s_o)
-    assert np.allclose(d[1:], sums, rtol=1e-13, atol=1e-13 * np.abs(sums).max())
+    assert np.allclose(d[1:1 + m.n_c], sums, rtol=1e-13, atol=1e-13 * np.abs(sums).max())
     mesh.close()
 
 
@@ -121,3 +122,70 @@ def test_vortex2d_rates_small(p):
             assert p - 0.2 <= rate <= p + 1.2, rate
         if not r["dissipation"]:
             assert abs(r["entropy_change"]) < 1e-12
+
+
+@pytest.mark.parametrize("dim,p", [(2, 3), (3, 2), (3, 3)])
+def test_diagnostics_kinetic_energy_vs_oracle(dim, p):
+    """sbp_diagnostics against the oracle: total entropy, the conserved sums
+    and the kinetic energy sum H rho |V|^2 / 2 of the Taylor-Green study."""
+    import torch
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import sbp, workloads as wl
+    from tests.gpu_common import state
+    say(f"[diagnostics] dim={dim} p={p}")
+    desc = wl.vortex2d_mesh(4, warp=0.05) if dim == 2 else wl.tgv_mesh(3)
+    m = OracleMesh(desc, p)
+    u = state(m, "vortex" if dim == 2 else "tgv", seed=3, jitter=0.01)
+    mesh = sbp.Mesh(desc, p)
+    d = mesh.diagnostics(torch.from_numpy(u).cuda())
+    mesh.check_device()
+    mesh.close()
+    sch = OracleScheme(m, ph.Gas())
+    H = m.H_all()
+    ref = np.concatenate([[sch.total_entropy(u)], np.einsum("en,ecn->c", H, u), [sch.kinetic_energy(u)]])
+    # the momentum sums of the symmetric fields nearly cancel: their error is
+    # taken relative to the sum of magnitudes (V3 = 0 in the Taylor-Green
+    # field: that sum and its scale are zero)
+    scale = np.concatenate([[abs(ref[0])], np.einsum("en,ecn->c", H, np.abs(u)), [ref[-1]]])
+    err = np.abs(d - ref) / np.maximum(scale, np.finfo(float).tiny)
+    say("   rel err", err)
+    assert d.shape == (m.n_c + 2,) and (err <= 1e-13).all(), err
+
+
+def test_tgv_history_small():
+    """The Taylor-Green history on 3^3 x 6 tetrahedra, p = 2, FP64, Re = 100:
+    E_k starts at the oracle's value of the nodal initial field and falls at
+    every step (epsilon > 0)."""
+    import math
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import studies, workloads as wl
+    from tests.gpu_common import state
+    say("[tgv history]")
+    r = studies.tgv_run(3, 2, steps=6, re=100.0, cfl=0.1, precision="fp64")
+    say("   E_k", r["E_k"], "epsilon", r["epsilon"])
+    m = OracleMesh(wl.tgv_mesh(3), 2)
+    ek0 = OracleScheme(m, ph.Gas()).kinetic_energy(state(m, "tgv")) / (2 * math.pi) ** 3
+    assert abs(r["E_k"][0] - ek0) <= 1e-13 * ek0
+    assert all(b < a for a, b in zip(r["E_k"], r["E_k"][1:]))
+    assert min(r["epsilon"]) > 0 and len(r["t"]) == 7
+
+
+def test_tgv_dissipation_rate_closed_form():
+    """The Navier-Stokes Taylor-Green grid of the benchmark (24^3 x 6
+    tetrahedra, p = 3, FP32 residuals, Re = 1600): over the first 20 steps
+    the dissipation rate -dE_k/dt stays at its incompressible value at t = 0,
+    nu <|omega|^2> = 3 / (4 Re) (the initial vorticity has mean square 3/4),
+    within 2% (compressibility at M = 0.1 enters at O(M^2))."""
+    import numpy as np
+    from paper_2305_07181_amd import studies
+    say("[tgv epsilon]")
+    r = studies.tgv_run(24, 3, steps=20, re=1600.0, cfl=0.1)
+    eps = np.array(r["epsilon"])
+    ref = 3.0 / (4.0 * 1600.0)
+    say(f"   epsilon mean {eps.mean():.6e} min {eps.min():.6e} max {eps.max():.6e}, 3/(4 Re) {ref:.6e}")
+    assert abs(r["E_k"][0] - 0.125) <= 1e-12
+    assert np.abs(eps / ref - 1.0).max() <= 0.02
