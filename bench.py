@@ -178,6 +178,14 @@ def ns_rows(args):
             row["entropy_nonincreasing"] = bool(all(q["entropy_after"] <= q["entropy_before"] for q in reps))
             row["dt"] = float(reps[-1]["dt"])
     m.close()
+    # the history of the Taylor-Green study over 100 steps at CFL 0.1
+    # (Sec. 7.5): scaled kinetic energy, dissipation rate, total entropy
+    from paper_2305_07181_amd import studies
+    h = studies.tgv_run(24, 3, steps=100, re=1600.0, cfl=0.1)
+    row["history_100_steps"] = dict(cfl=0.1, seconds=h["seconds"], t_end=h["t"][-1], E_k_start=h["E_k"][0],
+                                    E_k_end=h["E_k"][-1], epsilon_min=min(h["epsilon"]),
+                                    epsilon_max=max(h["epsilon"]), epsilon_incompressible_t0=3.0 / (4.0 * 1600.0),
+                                    entropy_change_rel=(h["entropy"][-1] - h["entropy"][0]) / abs(h["entropy"][0]))
     return row
 
 
