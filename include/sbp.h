@@ -75,7 +75,7 @@ typedef struct {
 typedef struct {
   double gamma;        /* ratio of specific heats (Sec. 2.2: 7/5)                  */
   double beta;         /* split parameter; alpha = -gamma - beta (gamma-1)
-                          (Sec. 2.4; Sec. 6.3 uses beta = 2.5)                     */
+                          (Sec. 2.4; Sec. 6.4 uses beta = 2.5)                     */
   int32_t form;        /* SBP_FORM_SPLIT or SBP_FORM_HADAMARD (Sec. 6.2)           */
   int32_t dissipation; /* 1: matrix interface dissipation (Sec. 4.5)              */
   int32_t viscous;     /* 1: Navier-Stokes terms with Baumann-Oden SATs (Sec. 5)   */
@@ -151,11 +151,11 @@ int sbp_rrk_step(sbp_mesh *mesh, void *u_dev, double dt, double cfl,
  * form (eq. weak form 2pt), with the same SATs; entropy conservation holds for
  * any choice, and the elements on the Hadamard form conserve locally.
  * form_dev: device array of n_elem bytes in the element order of the mesh
- * description, 0 = entropy split, 1 = Hadamard; borrowed: every later
- * sbp_residual and sbp_rrk_step reads it, so the caller may change its
- * contents between calls (switching between time steps; a captured RK stage
- * graph reads the same array).  NULL returns every element to phys.form.
- * Values other than 0 and 1 leave the element's residual unwritten.
+ * description, 0 = entropy split, any nonzero byte = Hadamard; borrowed:
+ * every later sbp_residual and sbp_rrk_step reads it, so the caller may
+ * change its contents between calls (switching between time steps; a
+ * captured RK stage graph reads the same array).  NULL returns every element
+ * to phys.form.
  * SBP_ENOTSUP with the viscous terms.  sbp_residual_vjp follows the flags.
  * The FP64 entropy rate sums both launches. */
 int sbp_set_volume_form(sbp_mesh *mesh, const uint8_t *form_dev);

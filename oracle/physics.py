@@ -43,7 +43,7 @@ import numpy as np
 
 
 class Gas:
-    """gamma and the split parameter beta (Sec. 2.4, Sec. 6.3: beta = 2.5)."""
+    """gamma and the split parameter beta (Sec. 2.4; Sec. 6.4, Robustness: beta = 2.5)."""
 
     def __init__(self, gamma=1.4, beta=2.5, mu=0.0, Pr=0.71, R=1.0, heat_flux=True):
         self.gamma = float(gamma)

@@ -36,7 +36,9 @@ RRK steps) and local conservation on its Hadamard elements, and design-order
 truncation error on smooth states (Thm. high-order).  The kinetic energy:
 tests/test_oracle_tgv.py (a uniform flow gives rho |V|^2 / 2 times the
 volume; the Taylor-Green initial field gives E_k -> 1/8, its closed form,
-under refinement).
+under refinement).  The time step (Sec. 7.1): tests/test_oracle_timestep.py
+(closed-form h_min of the Gauss-Legendre edge nodes on uniform grids, the
+ratio under refinement, the fastest and the smallest element deciding).
 """
 from __future__ import annotations
 

@@ -808,12 +808,14 @@ int rk_stages_graph(sbp_mesh *M, const double *u, hipStream_t s) {
   return SBP_OK;
 }
 
-int diagnostics_impl(sbp_mesh *M, const double *u, double *out, hipStream_t s) {
+// The first nv of the n_c + 2 diagnostics (total entropy, conserved sums,
+// kinetic energy) into out[0..nv).
+int diagnostics_impl(sbp_mesh *M, const double *u, double *out, hipStream_t s, int nv) {
   for (auto &c : M->cls) {
     sbp::NodeArgs A = node_args(M, c, u, nullptr);
     HIPCHK(sbp::launch_diagnostics(A, M->d_npart + c.node_off_blk, s));
   }
-  return reduce_nodes(M, M->nc + 2, 0, out, s);
+  return reduce_nodes(M, nv, 0, out, s);
 }
 
 // --------------------------------------------------------------------------
@@ -1135,7 +1137,7 @@ int sbp_residual_vjp(sbp_mesh *M, const void *u, const void *lam, void *ubar, vo
 
 int sbp_diagnostics(sbp_mesh *M, const void *u, double *out_host, void *stream) {
   if (!M || !u || !out_host) return fail(SBP_EINVAL, "null argument");
-  return diagnostics_impl(M, (const double *)u, out_host, (hipStream_t)stream);
+  return diagnostics_impl(M, (const double *)u, out_host, (hipStream_t)stream, M->nc + 2);
 }
 
 int sbp_check_device(sbp_mesh *M, void *stream) {
@@ -1428,19 +1430,20 @@ int sbp_rrk_step(sbp_mesh *M, void *u_dev, double dt, double cfl, sbp_rrk_report
   }
   if (it >= 100) return fail(SBP_ERRK, "relaxation root solve did not converge");
   if (!(g > 0.5 && g < 1.5)) return fail(SBP_ERRK, "relaxation parameter outside [0.5, 1.5]");
-  double diag0[1 + 5] = {0}, diag1[1 + 5] = {0};
+  // the report needs the total entropy only (the first diagnostic)
+  double ent0 = 0.0, ent1 = 0.0;
   if (rep) {
-    if ((rc = diagnostics_impl(M, u, diag0, s))) return rc;
+    if ((rc = diagnostics_impl(M, u, &ent0, s, 1))) return rc;
   }
   HIPCHK(sbp::launch_accum(u, M->d_d, 0, g, n, s));
   M->t += g * dt;
   if (rep) {
-    if ((rc = diagnostics_impl(M, u, diag1, s))) return rc;
+    if ((rc = diagnostics_impl(M, u, &ent1, s, 1))) return rc;
     rep->gamma_n = g;
     rep->dt = dt;
     rep->t = M->t;
-    rep->entropy_before = diag0[0];
-    rep->entropy_after = diag1[0];
+    rep->entropy_before = ent0;
+    rep->entropy_after = ent1;
     rep->entropy_rate_e = e;
     rep->newton_iters = it + 1;
   }

@@ -64,10 +64,12 @@ struct KArgs {
   int form_id;
 };
 
-// Whether element e of the class runs in this kernel (hybrid scheme).
+// Whether element e of the class runs in this kernel (hybrid scheme).  Any
+// nonzero flag byte selects the Hadamard form, so exactly one of the two
+// kernels writes each element's residual whatever the caller's bytes are.
 template <typename T>
 __device__ __forceinline__ bool elem_on(const KArgs<T> &A, int e) {
-  return !A.eform || A.eform[A.gid[e]] == A.form_id;
+  return !A.eform || (A.eform[A.gid[e]] != 0) == (A.form_id != 0);
 }
 
 // Whether any element of [e0, e0 + ne) runs in this kernel; the same answer

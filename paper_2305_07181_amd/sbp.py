@@ -230,19 +230,27 @@ class Mesh:
 
     def residual(self, u, r=None, entropy_rate=False, stream=None):
         import torch
-        if r is None:
-            dt = torch.float64 if self.precision == FP64 else torch.float32
-            r = torch.empty(u.shape, dtype=dt, device=u.device)
         self._check_state(u)
+        rdt = torch.float64 if self.precision == FP64 else torch.float32
+        if r is None:
+            r = torch.empty(u.shape, dtype=rdt, device=u.device)
+        else:
+            self._check_state(r, rdt, "r", u.device)
         er = torch.zeros(1, dtype=torch.float64, device=u.device) if entropy_rate else None
         _check(_lib.sbp_residual(self._h, _ptr(u), _ptr(r), _ptr(er) if er is not None else None,
                                  _stream_ptr(stream)))
         return (r, er) if entropy_rate else r
 
     def vjp(self, u, lam, ubar=None, stream=None):
+        """sbp_residual_vjp: ubar = (dr/du)^T lam, all FP64 (also on FP32
+        meshes: the VJP kernels compute in FP64)."""
         import torch
+        self._check_state(u)
+        self._check_state(lam, torch.float64, "cotangent", u.device)
         if ubar is None:
             ubar = torch.empty_like(u)
+        else:
+            self._check_state(ubar, torch.float64, "ubar", u.device)
         _check(_lib.sbp_residual_vjp(self._h, _ptr(u), _ptr(lam), _ptr(ubar), _stream_ptr(stream)))
         return ubar
 
@@ -340,12 +348,17 @@ class Mesh:
     def set_time(self, t):
         _check(_lib.sbp_set_time(self._h, float(t)))
 
-    def _check_state(self, u):
+    def _check_state(self, u, dtype=None, what="state", device=None):
+        """Raise ValueError unless u is a contiguous CUDA tensor of the state
+        size with the given dtype (float64 by default) on `device`."""
         import torch
-        if u.dtype != torch.float64 or not u.is_cuda or not u.is_contiguous():
-            raise ValueError("state must be a contiguous float64 CUDA tensor")
+        dtype = torch.float64 if dtype is None else dtype
+        if not isinstance(u, torch.Tensor) or u.dtype != dtype or not u.is_cuda or not u.is_contiguous():
+            raise ValueError(f"{what} must be a contiguous {dtype} CUDA tensor")
+        if device is not None and u.device != device:
+            raise ValueError(f"{what} is on {u.device}, the state on {device}")
         if u.numel() != self.n_nodes * self.n_c:
-            raise ValueError(f"state has {u.numel()} values, expected {self.n_nodes * self.n_c}")
+            raise ValueError(f"{what} has {u.numel()} values, expected {self.n_nodes * self.n_c}")
 
     def close(self):
         if self._h:
@@ -357,3 +370,32 @@ class Mesh:
             self.close()
         except Exception:
             pass
+
+
+class Residual(torch.autograd.Function):
+    """r = du/dt of a mesh handle as a differentiable torch operation:
+    forward calls sbp_residual, backward calls sbp_residual_vjp (the
+    hand-written vector-Jacobian kernels).  Only argument marshalling happens
+    here; the cotangent is passed to the library as FP64 (the VJP kernels
+    compute in FP64 also for FP32 meshes).  Use through :func:`residual`."""
+
+    @staticmethod
+    def forward(ctx, u, mesh):
+        ud = u.detach()
+        ctx.mesh = mesh
+        ctx.save_for_backward(ud)
+        return mesh.residual(ud)
+
+    @staticmethod
+    @torch.autograd.function.once_differentiable
+    def backward(ctx, grad_r):
+        (u,) = ctx.saved_tensors
+        lam = grad_r
+        if lam.dtype != torch.float64 or not lam.is_contiguous():
+            lam = lam.to(torch.float64).contiguous()
+        return ctx.mesh.vjp(u, lam), None
+
+
+def residual(mesh: "Mesh", u):
+    """Differentiable residual r(u) of `mesh` (see :class:`Residual`)."""
+    return Residual.apply(u, mesh)

@@ -186,3 +186,37 @@ def test_hybrid_fp32_and_hadamard_mesh(dim, p):
     assert (eh <= 1e-12).all(), eh
     mh.check_device()
     mh.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_hybrid_any_nonzero_flag_is_hadamard(dim):
+    """Flag bytes other than 0 and 1 select the Hadamard form: the residual and
+    the VJP equal those of the same flags written as 0/1, bitwise, and every
+    element's residual is written (the output buffer starts as NaN)."""
+    import torch
+    from oracle.geometry import OracleMesh
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say(f"[hybrid] nonzero flag bytes dim={dim}")
+    desc = wl.vortex2d_mesh(4, warp=0.05) if dim == 2 else wl.periodic_tet_mesh(2, 1.0)
+    p = 3 if dim == 2 else 2
+    ne = len(desc["elem_vert"])
+    rng = np.random.default_rng(77 + dim)
+    bytes_ = rng.integers(0, 256, ne).astype(np.uint8)
+    bytes_[rng.integers(0, ne, ne // 3)] = 0
+    flags01 = (bytes_ != 0).astype(np.uint8)
+    m = OracleMesh(desc, p)
+    u = torch.from_numpy(state(m, "random", seed=44, jitter=0.01)).cuda()
+    lam = torch.from_numpy(rng.standard_normal(tuple(u.shape))).cuda()
+    mesh = sbp.Mesh(desc, p)
+    out = {}
+    for name, f in (("bytes", bytes_), ("01", flags01)):
+        fd = torch.from_numpy(f).cuda()
+        mesh.set_volume_form(fd)
+        r = torch.full(tuple(u.shape), float("nan"), dtype=torch.float64, device=u.device)
+        mesh.residual(u, r=r)
+        out[name] = (r.clone(), mesh.vjp(u, lam))
+    mesh.check_device()
+    mesh.close()
+    assert not torch.isnan(out["bytes"][0]).any()
+    assert torch.equal(out["bytes"][0], out["01"][0])
+    assert torch.equal(out["bytes"][1], out["01"][1])

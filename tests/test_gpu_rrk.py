@@ -173,3 +173,27 @@ def test_rrk_navier_stokes_tgv_first_steps_vs_oracle():
     assert (err <= bound).all(), (err, bound)
     mesh.check_device()
     mesh.close()
+
+
+@pytest.mark.parametrize("viscous", [False, True])
+def test_rrk_report_entropies_3d(viscous):
+    """The step's report in 3D (n_c + 2 = 7 diagnostics exist; the step
+    reduces only the total entropy): entropy_before and entropy_after are
+    bitwise the total entropy sbp_diagnostics gives before and after."""
+    import torch
+    from oracle.geometry import OracleMesh
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say(f"[rrk report 3d] viscous={viscous}")
+    desc = wl.tgv_mesh(2)
+    m = OracleMesh(desc, 2)
+    ud = torch.from_numpy(state(m, "tgv")).cuda()
+    kw = dict(viscous=True, mu=1.0 / 1600) if viscous else {}
+    mesh = sbp.Mesh(desc, 2, dissipation=True, **kw)
+    for _ in range(2):
+        d0 = mesh.diagnostics(ud)
+        rep = mesh.rrk_step(ud, cfl=0.1)
+        d1 = mesh.diagnostics(ud)
+        assert len(d0) == 7
+        assert rep["entropy_before"] == d0[0] and rep["entropy_after"] == d1[0]
+        assert rep["entropy_after"] <= rep["entropy_before"]
+    mesh.close()
