@@ -126,6 +126,22 @@ int sbp_mesh_info(sbp_mesh *mesh, sbp_info *out);
 int sbp_residual(sbp_mesh *mesh, const void *u_dev, void *r_dev,
                  double *entropy_rate_dev, void *hip_stream);
 
+/* The same residual as sbp_residual, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the call allocates nothing; its device scratch (the
+ * entropy rate's per-workgroup partial sums, reduction scalars and, with the
+ * manufactured source, the node partials) lives in one static device array of
+ * 2^17 doubles (1 MiB) per GPU, held until the process ends.  Arguments,
+ * layouts and results as for sbp_residual (bitwise the same values).
+ * SBP_EINVAL when the mesh needs more scratch than the array holds (meshes of
+ * up to about 10^5 workgroup tiles; the message gives both sizes).  Every call
+ * on a GPU shares that GPU's array and leaves its contents behind: calls that
+ * overlap on one GPU (other streams, other threads) race and must be ordered
+ * by the caller.  Nothing in the array needs to start at zero.  Not in the
+ * paper. */
+int sbp_residual_noalloc(sbp_mesh *mesh, const void *u_dev, void *r_dev,
+                         double *entropy_rate_dev, void *hip_stream);
+
 /* ubar = (dr/du)^T lambda (vector-Jacobian product of sbp_residual).  Not in
  * the paper.  Layouts as for sbp_residual, all FP64.  Euler terms (with or
  * without dissipation) in either volume form and with the hybrid form flags;

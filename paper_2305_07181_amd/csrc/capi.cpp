@@ -587,7 +587,23 @@ sbp::KArgs<T> kargs(sbp_mesh *M, DegreeClass &c, const double *u, void *r, const
   return A;
 }
 
-int residual_core(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStream_t s) {
+// Device scratch of one residual evaluation: the per-workgroup partial sums
+// of the entropy rate (part, M->part_total values), the reduction and time
+// scalars (scal, SC_TOTAL values) and the node-kernel partials of the
+// manufactured source's entropy rate (npart, M->node_total values).  The
+// handle's own buffers serve sbp_residual and the RK stages; the static
+// scratch array serves sbp_residual_noalloc.  Every value is written before
+// it is read within one evaluation, so nothing needs clearing.
+struct Work {
+  double *part, *scal, *npart;
+};
+Work handle_work(const sbp_mesh *M) { return Work{M->d_part, M->d_scal, M->d_npart}; }
+size_t work_doubles(const sbp_mesh *M) {
+  return (size_t)std::max(1, M->part_total) + SC_TOTAL +
+         (M->src_kind == SBP_SOURCE_NS_MMS ? (size_t)std::max(1, M->node_total) : 0);
+}
+
+int residual_core(sbp_mesh *M, const Work &W, const double *u, void *r, double *ent_dev, hipStream_t s) {
   const sbp_physics &ph = M->phys;
   if (ph.viscous) {
     for (auto &c : M->cls) {
@@ -607,13 +623,13 @@ int residual_core(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStr
       sbp::KArgs<double> A = kargs<double>(M, c, u, r, c.op64);
       A.eform = M->eform;
       A.form_id = form_other;
-      A.ent_part = M->d_part + c.part_off_h;
+      A.ent_part = W.part + c.part_off_h;
       HIPCHK(sbp::launch_residual(M->dim, c.p, form_other, A, s, sbp::LaunchCfg{0, 1}));
     } else {
       sbp::KArgs<float> A = kargs<float>(M, c, u, r, c.op32);
       A.eform = M->eform;
       A.form_id = form_other;
-      A.ent_part = M->d_part + c.part_off_h;
+      A.ent_part = W.part + c.part_off_h;
       HIPCHK(sbp::launch_residual(M->dim, c.p, form_other, A, s, sbp::LaunchCfg{0, 1}));
     }
     return SBP_OK;
@@ -641,9 +657,9 @@ int residual_core(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStr
       }
     }
     if (ph.precision == SBP_FP64)
-      HIPCHK(sbp::launch_residual2_batch(p64, M->d_part, s, M->batch_grid));
+      HIPCHK(sbp::launch_residual2_batch(p64, W.part, s, M->batch_grid));
     else
-      HIPCHK(sbp::launch_residual2_batch(p32, M->d_part, s, M->batch_grid));
+      HIPCHK(sbp::launch_residual2_batch(p32, W.part, s, M->batch_grid));
     if (hyb)
       for (auto &c : M->cls)
         if ((rc = other_launch(c))) return rc;
@@ -652,13 +668,13 @@ int residual_core(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStr
       for (auto &c : M->cls) ne_p[c.p - 1] = c.n_elem;
       const int nb = sbp::residual2_batch_blocks(ne_p, ph.precision == SBP_FP64 ? 0 : 1, M->batch_grid);
       if (!hyb) {
-        HIPCHK(sbp::launch_reduce(M->d_part, nb, 1, 0, ent_dev, s));
+        HIPCHK(sbp::launch_reduce(W.part, nb, 1, 0, ent_dev, s));
       } else {
-        HIPCHK(sbp::launch_reduce(M->d_part, nb, 1, 0, M->d_scal + SC_RED, s));
+        HIPCHK(sbp::launch_reduce(W.part, nb, 1, 0, W.scal + SC_RED, s));
         for (int ci = 0; ci < ncls; ++ci)
-          HIPCHK(sbp::launch_reduce(M->d_part + M->cls[ci].part_off_h, other_blocks(M->cls[ci]), 1, 0,
-                                    M->d_scal + SC_RED + 1 + ci, s));
-        HIPCHK(sbp::launch_reduce(M->d_scal + SC_RED, 1 + ncls, 1, 0, ent_dev, s));
+          HIPCHK(sbp::launch_reduce(W.part + M->cls[ci].part_off_h, other_blocks(M->cls[ci]), 1, 0,
+                                    W.scal + SC_RED + 1 + ci, s));
+        HIPCHK(sbp::launch_reduce(W.scal + SC_RED, 1 + ncls, 1, 0, ent_dev, s));
       }
     }
     return SBP_OK;
@@ -666,11 +682,13 @@ int residual_core(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStr
   for (auto &c : M->cls) {
     if (ph.precision == SBP_FP64) {
       sbp::KArgs<double> A = kargs<double>(M, c, u, r, c.op64);
+      A.ent_part = W.part + c.part_off;
       A.eform = M->eform;
       A.form_id = ph.form;
       HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, A, s, c.res_cfg));
     } else {
       sbp::KArgs<float> A = kargs<float>(M, c, u, r, c.op32);
+      A.ent_part = W.part + c.part_off;
       A.eform = M->eform;
       A.form_id = ph.form;
       HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, A, s, c.res_cfg));
@@ -682,11 +700,11 @@ int residual_core(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStr
     for (int ci = 0; ci < ncls; ++ci) {
       auto &c = M->cls[ci];
       const int nb = sbp::residual_blocks(M->dim, c.p, ph.precision, form_eff, c.n_elem, c.res_cfg);
-      HIPCHK(sbp::launch_reduce(M->d_part + c.part_off, nb, 1, 0, M->d_scal + SC_RED + ci, s));
+      HIPCHK(sbp::launch_reduce(W.part + c.part_off, nb, 1, 0, W.scal + SC_RED + ci, s));
       if (hyb)
-        HIPCHK(sbp::launch_reduce(M->d_part + c.part_off_h, other_blocks(c), 1, 0, M->d_scal + SC_RED + ncls + ci, s));
+        HIPCHK(sbp::launch_reduce(W.part + c.part_off_h, other_blocks(c), 1, 0, W.scal + SC_RED + ncls + ci, s));
     }
-    HIPCHK(sbp::launch_reduce(M->d_scal + SC_RED, hyb ? 2 * ncls : ncls, 1, 0, ent_dev, s));
+    HIPCHK(sbp::launch_reduce(W.scal + SC_RED, hyb ? 2 * ncls : ncls, 1, 0, ent_dev, s));
   }
   return SBP_OK;
 }
@@ -694,25 +712,25 @@ int residual_core(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStr
 // The residual plus the manufactured source when one is set (Sec. 7), at
 // time *t0 + c * *dt (the RK stage times; t0 null: the handle's time).  The
 // entropy rate then sums w^T H r of both parts.
-int residual_impl(sbp_mesh *M, const double *u, void *r, double *ent_dev, hipStream_t s,
+int residual_impl(sbp_mesh *M, const Work &W, const double *u, void *r, double *ent_dev, hipStream_t s,
                   const double *t0 = nullptr, const double *dt = nullptr, double c = 0.0) {
   // the vortices are exact Euler solutions: no source term
-  if (M->src_kind != SBP_SOURCE_NS_MMS) return residual_core(M, u, r, ent_dev, s);
+  if (M->src_kind != SBP_SOURCE_NS_MMS) return residual_core(M, W, u, r, ent_dev, s);
   int rc;
-  if ((rc = residual_core(M, u, r, ent_dev ? M->d_scal + SC_SRC : nullptr, s))) return rc;
+  if ((rc = residual_core(M, W, u, r, ent_dev ? W.scal + SC_SRC : nullptr, s))) return rc;
   if (!t0) {
-    HIPCHK(sbp::launch_scalar_set(M->d_scal + SC_TR, M->t, s));
-    t0 = M->d_scal + SC_TR;
+    HIPCHK(sbp::launch_scalar_set(W.scal + SC_TR, M->t, s));
+    t0 = W.scal + SC_TR;
     dt = nullptr;
   }
   const int f32 = M->phys.precision == SBP_FP32;
   for (auto &cl : M->cls) {
     sbp::NodeArgs A = node_args(M, cl, u, nullptr);
-    HIPCHK(sbp::launch_source_add(A, M->src, r, f32, t0, dt, c, ent_dev ? M->d_npart + cl.node_off_blk : nullptr, s));
+    HIPCHK(sbp::launch_source_add(A, M->src, r, f32, t0, dt, c, ent_dev ? W.npart + cl.node_off_blk : nullptr, s));
   }
   if (ent_dev) {
-    HIPCHK(sbp::launch_reduce(M->d_npart, M->node_total, 1, 0, M->d_scal + SC_SRC + 1, s));
-    HIPCHK(sbp::launch_reduce(M->d_scal + SC_SRC, 2, 1, 0, ent_dev, s));
+    HIPCHK(sbp::launch_reduce(W.npart, M->node_total, 1, 0, W.scal + SC_SRC + 1, s));
+    HIPCHK(sbp::launch_reduce(W.scal + SC_SRC, 2, 1, 0, ent_dev, s));
   }
   return SBP_OK;
 }
@@ -773,7 +791,8 @@ int rk_stages(sbp_mesh *M, const double *u, hipStream_t s) {
       HIPCHK(sbp::launch_axpy(M->d_y, u, M->d_r, f32, cst[i], n, s, dtp));
       y = M->d_y;
     }
-    if ((rc = residual_impl(M, y, M->d_r, M->d_scal + SC_ENT + i, s, M->d_scal + SC_T, dtp, cst[i]))) return rc;
+    if ((rc = residual_impl(M, handle_work(M), y, M->d_r, M->d_scal + SC_ENT + i, s, M->d_scal + SC_T, dtp, cst[i])))
+      return rc;
     if (i == 0)
       HIPCHK(sbp::launch_axpy(M->d_d, nullptr, M->d_r, f32, b[i], n, s, dtp));
     else
@@ -1017,6 +1036,36 @@ int autotune_impl(sbp_mesh *M, const double *u, const double *lam, sbp_tune_repo
   return check_err(M, s);
 }
 
+// Scratch of sbp_residual_noalloc: a fixed device array that every
+// allocation-free residual on a GPU shares (each device holds its own copy
+// until the process ends).  In host code `scratch` names a host-side shadow,
+// not device memory: only the address hipGetSymbolAddress returns for the
+// current device may be handed to kernels.
+constexpr size_t kScratchDoubles = (size_t)1 << 17;  // 1 MiB per device
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, resolved once per device
+// (at mesh setup, or at the first allocation-free call on a device).
+int scratch_address(double **out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SBP_EDEVICE, "device index out of range for the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SBP_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = (double *)p;
+  }
+  *out = g_scratch_dev[dev];
+  return SBP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1062,6 +1111,11 @@ int sbp_setup_mesh(const sbp_mesh_desc *desc, const sbp_physics *phys, void *hip
     return rc;
   }
   for (int i = 0; i < desc->dim; ++i) M->period[i] = desc->period[i];
+  double *scr = nullptr;  // the allocation-free residual's scratch on this device
+  if ((rc = scratch_address(&scr))) {
+    sbp_destroy_mesh(M);
+    return rc;
+  }
   *out = M;
   return SBP_OK;
 }
@@ -1082,7 +1136,23 @@ int sbp_mesh_info(sbp_mesh *M, sbp_info *out) {
 
 int sbp_residual(sbp_mesh *M, const void *u, void *r, double *ent_dev, void *stream) {
   if (!M || !u || !r) return fail(SBP_EINVAL, "null argument");
-  return residual_impl(M, (const double *)u, r, ent_dev, (hipStream_t)stream);
+  return residual_impl(M, handle_work(M), (const double *)u, r, ent_dev, (hipStream_t)stream);
+}
+
+int sbp_residual_noalloc(sbp_mesh *M, const void *u, void *r, double *ent_dev, void *stream) {
+  if (!M || !u || !r) return fail(SBP_EINVAL, "null argument");
+  const size_t need = work_doubles(M);
+  if (need > kScratchDoubles)
+    return fail(SBP_EINVAL, "sbp_residual_noalloc: the mesh needs " + std::to_string(need) +
+                                " scratch doubles, more than the " + std::to_string(kScratchDoubles) +
+                                " of the static scratch array; use sbp_residual");
+  double *scr = nullptr;
+  int rc;
+  if ((rc = scratch_address(&scr))) return rc;
+  // layout: [part_total partials | SC_TOTAL scalars | node partials (source only)]
+  const size_t np = (size_t)std::max(1, M->part_total);
+  const Work W{scr, scr + np, scr + np + SC_TOTAL};
+  return residual_impl(M, W, (const double *)u, r, ent_dev, (hipStream_t)stream);
 }
 
 int sbp_residual_vjp(sbp_mesh *M, const void *u, const void *lam, void *ubar, void *stream) {

@@ -27,7 +27,7 @@ SYMBOLS = ["sbp_setup_mesh", "sbp_mesh_info", "sbp_residual", "sbp_residual_vjp"
            "sbp_diagnostics", "sbp_check_device", "sbp_set_time", "sbp_destroy_mesh",
            "sbp_last_error", "sbp_reference_operator", "sbp_use_graphs", "sbp_autotune",
            "sbp_get_launch_shape", "sbp_set_launch_shape", "sbp_set_volume_form", "sbp_set_source",
-           "sbp_source_state", "sbp_source_error"]
+           "sbp_source_state", "sbp_source_error", "sbp_residual_noalloc"]
 
 
 class SbpError(RuntimeError):
@@ -81,6 +81,7 @@ def load_library(path: str = _LIB_PATH):
     lib.sbp_mesh_info.argtypes = [P, C.POINTER(Info)]
     lib.sbp_residual.argtypes = [P, P, P, P, P]
     lib.sbp_residual_vjp.argtypes = [P, P, P, P, P]
+    lib.sbp_residual_noalloc.argtypes = [P, P, P, P, P]
     lib.sbp_rrk_step.argtypes = [P, P, C.c_double, C.c_double, C.POINTER(RRKReport), P]
     lib.sbp_diagnostics.argtypes = [P, P, C.POINTER(C.c_double), P]
     lib.sbp_check_device.argtypes = [P, P]
@@ -240,6 +241,21 @@ class Mesh:
         _check(_lib.sbp_residual(self._h, _ptr(u), _ptr(r), _ptr(er) if er is not None else None,
                                  _stream_ptr(stream)))
         return (r, er) if entropy_rate else r
+
+    def residual_noalloc(self, u, r, entropy_rate=None, stream=None):
+        """sbp_residual_noalloc: the residual into the caller's r (and the
+        entropy rate into the caller's one-element float64 tensor), with the
+        library's device scratch in its static array (no allocation)."""
+        import torch
+        self._check_state(u)
+        self._check_state(r, torch.float64 if self.precision == FP64 else torch.float32, "r", u.device)
+        if entropy_rate is not None and (entropy_rate.dtype != torch.float64 or not entropy_rate.is_cuda
+                                         or entropy_rate.numel() < 1):
+            raise ValueError("entropy_rate must be a float64 CUDA tensor of at least one value")
+        _check(_lib.sbp_residual_noalloc(self._h, _ptr(u), _ptr(r),
+                                         _ptr(entropy_rate) if entropy_rate is not None else None,
+                                         _stream_ptr(stream)))
+        return r
 
     def vjp(self, u, lam, ubar=None, stream=None):
         """sbp_residual_vjp: ubar = (dr/du)^T lam, all FP64 (also on FP32
