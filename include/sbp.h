@@ -58,7 +58,7 @@ typedef struct {
   const double *vert_xyz;      /* [n_vert][dim], host                             */
   const int32_t *elem_vert;    /* [n_elem][dim+1], positively oriented            */
   int32_t p_geom;              /* 1 affine; 2 quadratic map (3D: degrees p >= 2,
-                                  Assumption 1; entropy-split Euler terms only)   */
+                                  Assumption 1)                                   */
   const double *geom_nodes;    /* 2D: [n_elem][6][2] P2 map nodes (v0,v1,v2,m01,m12,m20);
                                   3D: [n_elem][10][3] (v0..v3, m01,m12,m02,m03,m13,m23);
                                   NULL when p_geom == 1                           */
@@ -109,9 +109,9 @@ typedef struct {
 /* Build a mesh handle: reference operators (Def. 1), metrics, facet matching,
  * device tables.  `hip_stream` is used for the uploads.  Paper: Sec. 2.1.
  * Curved tetrahedra (p_geom 2 in 3D) need every degree >= 2 (Assumption 1:
- * p_geom <= floor(p/2) + 1), else SBP_EINVAL; with them the viscous terms
- * return SBP_ENOTSUP (the Euler terms in both forms, the hybrid flags and the
- * VJP are available). */
+ * p_geom <= floor(p/2) + 1), else SBP_EINVAL.  The viscous terms (Sec. 5)
+ * need the entropy-split form (else SBP_ENOTSUP) and run on triangles and
+ * tetrahedra, affine or curved. */
 int sbp_setup_mesh(const sbp_mesh_desc *desc, const sbp_physics *phys,
                    void *hip_stream, sbp_mesh **out);
 

@@ -111,12 +111,13 @@ namespace {
 
 // Kernel family of the residual: 0 entropy split, 1 Hadamard, 2 entropy
 // split with the Navier-Stokes terms, 3 and 4 entropy split and Hadamard on
-// curved tetrahedra.
+// curved tetrahedra, 5 entropy split with the Navier-Stokes terms on curved
+// tetrahedra.
 int curved_eff(const sbp_mesh *M, int form) {
   return M->curved3 ? (form == SBP_FORM_SPLIT ? 3 : 4) : form;
 }
 int form_eff_of(const sbp_mesh *M) {
-  if (M->phys.viscous) return 2;
+  if (M->phys.viscous) return M->curved3 ? 5 : 2;
   return curved_eff(M, M->phys.form);
 }
 
@@ -1086,7 +1087,6 @@ int sbp_setup_mesh(const sbp_mesh_desc *desc, const sbp_physics *phys, void *hip
     for (int e = 0; e < desc->n_elem; ++e)
       if (desc->elem_degree[e] < 2)
         return fail(SBP_EINVAL, "quadratic tetrahedral maps need degree p >= 2 (Assumption 1)");
-    if (phys->viscous) return fail(SBP_ENOTSUP, "curved tetrahedra: the Euler terms only");
   }
   if (desc->n_problems < 1) return fail(SBP_EINVAL, "n_problems must be >= 1");
   for (int i = 0; i < desc->dim; ++i)
@@ -1094,8 +1094,8 @@ int sbp_setup_mesh(const sbp_mesh_desc *desc, const sbp_physics *phys, void *hip
   if (!(phys->gamma > 1.0) || !(phys->beta > 0.0)) return fail(SBP_EINVAL, "need gamma > 1 and beta > 0");
   if (phys->form != SBP_FORM_SPLIT && phys->form != SBP_FORM_HADAMARD) return fail(SBP_EINVAL, "bad form");
   if (phys->precision != SBP_FP64 && phys->precision != SBP_FP32) return fail(SBP_EINVAL, "bad precision");
-  if (phys->viscous && (desc->dim != 3 || phys->form != SBP_FORM_SPLIT))
-    return fail(SBP_ENOTSUP, "viscous terms are available for the entropy-split form on tetrahedra");
+  if (phys->viscous && phys->form != SBP_FORM_SPLIT)
+    return fail(SBP_ENOTSUP, "viscous terms are available for the entropy-split form");
   if (phys->viscous && !(phys->mu >= 0.0 && phys->Pr > 0.0 && phys->R > 0.0))
     return fail(SBP_EINVAL, "viscous terms need mu >= 0, Pr > 0, R > 0");
   sbp_mesh *M = new (std::nothrow) sbp_mesh();

@@ -175,16 +175,85 @@ __device__ __forceinline__ void jvp_flux(const Node<D, T> &n, const GasC<T> &G, 
   out[D + 1] = dV[i] * ep + n.V[i] * (G.ggm1 * dp + (T)0.5 * q2 * drho + n.rho * VdV);
 }
 
+// sum_i A~_i g_i = sum_i dF^(i)/dW [g_i] for all D directions at once (the
+// same derivative as jvp_flux), with the node's reciprocals iWn = 1/W_nc and
+// itheta = rho/p given, so that no division is left per direction.
+template <int D, typename T>
+__device__ __forceinline__ void jvp_flux_sum(const Node<D, T> &n, const GasC<T> &G, T iWn, T itheta,
+                                             const T (*g)[D + 2], T *out) {
+  constexpr int NC = D + 2;
+  T q2 = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) q2 += n.V[k] * n.V[k];
+  const T theta = n.p / n.rho;
+  const T c1 = G.gm1_a * iWn;  // (gamma-1)/(alpha W_nc)
+  const T c2 = (-theta + (T)0.5 * G.gm1_a * q2) * iWn;
+  const T ep = G.ggm1 * n.p + (T)0.5 * n.rho * q2;  // e + p
+#pragma unroll
+  for (int c = 0; c < NC; ++c) out[c] = (T)0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const T *gi = g[i];
+    T dV[D];
+    T Vg = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      dV[k] = -(gi[1 + k] + n.V[k] * gi[NC - 1]) * iWn;
+      Vg += n.V[k] * gi[1 + k];
+    }
+    const T dtheta = c1 * (gi[0] + Vg) + c2 * gi[NC - 1];
+    const T drho = n.rho * (gi[NC - 1] * iWn - G.ja * dtheta * itheta) * G.jb_inv;
+    const T dp = theta * drho + n.rho * dtheta;
+    T VdV = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) VdV += n.V[k] * dV[k];
+    out[0] += drho * n.V[i] + n.rho * dV[i];
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      out[1 + j] += drho * n.V[i] * n.V[j] + n.rho * (dV[i] * n.V[j] + n.V[i] * dV[j]) + (j == i ? dp : (T)0);
+    out[NC - 1] += dV[i] * ep + n.V[i] * (G.ggm1 * dp + (T)0.5 * q2 * drho + n.rho * VdV);
+  }
+}
+
+// Largest |eps| = |a - b| / (a + b) for which the exponential average takes
+// its series form.  The direct quotient loses about -log10|eps| digits to
+// cancellation and the series' truncation error is about |eps|^10: 1e-2
+// keeps both near 1e-14 in FP64; in FP32 the quotient would lose two of its
+// seven digits there, so the series (still exact to ~1e-10 at 0.1) runs up
+// to 0.1.
+template <typename T>
+__device__ __forceinline__ constexpr T exp_avg_series_max() {
+  return sizeof(T) == 4 ? (T)0.1 : (T)1e-2;
+}
+
 // Exponential average {x^{r-1}}_e = (a^r - b^r) / (r (a - b)) from values
 // a, b and their r-th powers; near a = b the series form
 //   m^{r-1} [1 + sum_k C(r,2k+1)/r eps^{2k}],  m = (a+b)/2,  eps = (a-b)/(a+b),
 // with m^{r-1} = (a^r / a) (1 + delta)^{r-1}, delta = (b - a)/(2a),
-// |delta| < 0.0102, the binomial series summed to delta^9 (remainder < 1e-19).
+// the binomial series summed to delta^9 (FP64: |delta| < 0.0102, remainder
+// < 1e-19; FP32: |delta| < 0.1, remainder < 1e-10).
+template <typename T>
+__device__ __forceinline__ T exp_avg_ia(T a, T b, T ar, T br, T ia, const ExpAvgC<T> &C) {
+  const T s = a + b;
+  const T eps = (a - b) / s;
+  if (dabs(eps) <= exp_avg_series_max<T>()) {
+    const T dl = (T)0.5 * (b - a) * ia;
+    T bin = C.bn[8];
+#pragma unroll
+    for (int k = 7; k >= 0; --k) bin = C.bn[k] + dl * bin;
+    bin = (T)1 + dl * bin;
+    const T e2 = eps * eps;
+    return ar * ia * bin * ((T)1 + e2 * (C.c[0] + e2 * (C.c[1] + e2 * (C.c[2] + e2 * C.c[3]))));
+  }
+  return (ar - br) / (C.r * (a - b));
+}
+
+// The same with 1/a computed here.
 template <typename T>
 __device__ __forceinline__ T exp_avg(T a, T b, T ar, T br, const ExpAvgC<T> &C) {
   const T s = a + b;
   const T eps = (a - b) / s;
-  if (dabs(eps) <= (T)1e-2) {
+  if (dabs(eps) <= exp_avg_series_max<T>()) {
     const T ia = (T)1 / a;
     const T dl = (T)0.5 * (b - a) * ia;
     T bin = C.bn[8];
@@ -203,11 +272,12 @@ __device__ __forceinline__ T exp_avg(T a, T b, T ar, T br, const ExpAvgC<T> &C) 
 // The residual receives -out / H_m.
 template <int D, typename T>
 __device__ __forceinline__ void facet_term(const Node<D, T> &k, const Node<D, T> &v, const T *a,
-                                           const GasC<T> &G, bool diss, T *out) {
+                                           const GasC<T> &G, bool diss, T *out, T ip_k = (T)0, T iz1_k = (T)0) {
   constexpr int NC = D + 2;
   const T P1k = k.P1, P1v = v.P1, P2k = k.P2, P2v = v.P2;
-  const T Ep = exp_avg(k.p, v.p, P2k, P2v, G.e2);
-  const T Ez = exp_avg(k.z1, v.z1, P1k, P1v, G.e1);
+  // own-side reciprocals 1/p_k and 1/z1_k, if the caller has them
+  const T Ep = ip_k != (T)0 ? exp_avg_ia(k.p, v.p, P2k, P2v, ip_k, G.e2) : exp_avg(k.p, v.p, P2k, P2v, G.e2);
+  const T Ez = iz1_k != (T)0 ? exp_avg_ia(k.z1, v.z1, P1k, P1v, iz1_k, G.e1) : exp_avg(k.z1, v.z1, P1k, P1v, G.e1);
   const T Dn = (T)0.5 * (P1k + P1v) * Ep;
   const T iD = (T)1 / Dn;
   T an = 0;  // a . {z1 V} / D

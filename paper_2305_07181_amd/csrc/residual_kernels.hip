@@ -774,7 +774,7 @@ __global__ __launch_bounds__(kThreads) void k_visc_q3(KArgs<T> A) {
 // node.  Every lane re-reads the 16 values of node j for each pair; with
 // R = 2 each value read feeds two rows (half the LDS bytes per FMA, at two
 // waves per SIMD instead of three for R = 1).
-template <int P, typename T, int R>
+template <int P, typename T, int R, bool EF = false>
 struct Split2 {
   static constexpr int D = 2, NC = 4, NFAC = 3;
   static constexpr int NP = Shape<2, P>::NP, NF = Shape<2, P>::NF;
@@ -901,20 +901,181 @@ struct Split2 {
     }
     __syncthreads();
   }
+
+  // The same residual with the facet SATs evaluated before the pair sums:
+  // the neighbour index and state loads are issued with the element's own
+  // loads at the start of the tile, so their latency overlaps the node work
+  // instead of following the pair loop; only the facet term (n_c values per
+  // row) and the node quantities of the combine stay live across the loop.
+  __device__ static __forceinline__ void tile_early(const KArgs<T> &A, Lds &L_, int tl, double &ent) {
+    constexpr int NFN = NFAC * NF;
+    const int tid = threadIdx.x;
+    const int e0 = tl * EB;
+    const int ne = min(EB, A.n_elem - e0);
+    if (!tile_on(A, e0, ne)) return;  // hybrid scheme: no element of this form
+    const int e = tid / L, k = tid % L;
+    const bool act = e < ne && elem_on(A, e0 + e);
+    const T cb = A.G.cb;
+    const T hv = (T)0.5 * (cb - (T)1), he = (T)0.5 * (cb + (T)1);
+    Node<D, T> n[R];
+    T lam[R][4];
+    T ft[R][NC];
+    T iWn[R], ith[R], ipk[R];  // 1/W_nc = -1/z1, rho/p and 1/p of the row's node
+    if (act) {
+      const int eg = e0 + e;
+      const int uo = A.uoff[eg];
+      // loads first: own node states, neighbour offsets, then neighbour states
+      T uu[R][NC], uv[R][NC];
+      int nb[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int i = k + q * L;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) uu[q][c] = (T)A.u[uo + c * NP + i];
+        nb[q] = i < NFN ? A.nbr[(size_t)eg * NFN + i] : -1;
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) uv[q][c] = nb[q] >= 0 ? (T)A.u[nb[q] + c * NP] : uu[q][c];
+      const double *g = A.geo + (size_t)eg * 12;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int i = k + q * L;
+        T F[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+          const T d0 = A.op.dN[(0 * 6 + a) * NP + i], d1 = A.op.dN[(1 * 6 + a) * NP + i];
+          const T gx = (T)g[2 * a], gy = (T)g[2 * a + 1];
+          F[0][0] += d0 * gx;
+          F[0][1] += d1 * gx;
+          F[1][0] += d0 * gy;
+          F[1][1] += d1 * gy;
+        }
+        lam[q][0] = F[1][1];   // Lambda_00 = J dxi_0/dx_0
+        lam[q][1] = -F[1][0];  // Lambda_01
+        lam[q][2] = -F[0][1];  // Lambda_10
+        lam[q][3] = F[0][0];   // Lambda_11
+        T f0[NC], f1[NC];
+        node_from_u<D, T>(uu[q], A.G, n[q]);
+        if (!n[q].ok) atomicOr(A.err, 1);
+        iWn[q] = (T)1 / n[q].w[NC - 1];
+        ipk[q] = (T)1 / n[q].p;
+        ith[q] = n[q].rho * ipk[q];
+        flux_i<D, T>(n[q], uu[q][NC - 1], 0, f0);
+        flux_i<D, T>(n[q], uu[q][NC - 1], 1, f1);
+        T *v = L_.nd + e * NDS + i * 16;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          v[c] = f0[c];
+          v[4 + c] = f1[c];
+          v[8 + c] = n[q].w[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[12 + c] = lam[q][c];
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ft[q][c] = (T)0;
+        if (nb[q] >= 0) {
+          const int i = k + q * L;
+          const T E0 = A.op.E[i], E1 = A.op.E[NP + i];
+          T avec[D];
+          avec[0] = lam[q][0] * E0 + lam[q][1] * E1;
+          avec[1] = lam[q][2] * E0 + lam[q][3] * E1;
+          Node<D, T> nv;
+          node_from_u<D, T>(uv[q], A.G, nv);
+          if (!nv.ok) atomicOr(A.err, 1);
+          node_powers<D, T>(A.G, nv);
+          Node<D, T> nk = n[q];
+          node_powers<D, T>(A.G, nk);
+          facet_term<D, T>(nk, nv, avec, A.G, A.diss != 0, ft[q], ipk[q], -iWn[q]);
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {
+      T V[R][NC], X0[R][NC], X1[R][NC];
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) V[q][c] = X0[q][c] = X1[q][c] = (T)0;
+#pragma unroll 1
+      for (int j = 0; j < NP; ++j) {
+        const T *v = L_.nd + e * NDS + j * 16;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int i = k + q * L;
+          const T s0 = L_.S[0][i][j], s1 = L_.S[1][i][j];
+          const T c0 = s0 * (lam[q][0] + v[12]) + s1 * (lam[q][1] + v[13]);
+          const T c1 = s0 * (lam[q][2] + v[14]) + s1 * (lam[q][3] + v[15]);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            V[q][c] += c0 * v[c];
+            V[q][c] += c1 * v[4 + c];
+            X0[q][c] += c0 * v[8 + c];
+            X1[q][c] += c1 * v[8 + c];
+          }
+        }
+      }
+      const int uo = A.uoff[e0 + e];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int i = k + q * L;
+        const T *v = L_.nd + e * NDS + i * 16;
+        const T E0 = A.op.E[i], E1 = A.op.E[NP + i];
+        T avec[D];
+        avec[0] = lam[q][0] * E0 + lam[q][1] * E1;
+        avec[1] = lam[q][2] * E0 + lam[q][3] * E1;
+        const T J = lam[q][3] * lam[q][0] - lam[q][2] * lam[q][1];
+        const T H = J * (T)A.op.h[i];
+        const T iH = (T)1 / H;
+        T r[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) r[c] = iH * (hv * V[q][c] + he * (avec[0] * v[c] + avec[1] * v[4 + c]));
+        {
+          T gg[D][NC], tt[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            gg[0][c] = (T)0.5 * iH * (X0[q][c] + avec[0] * n[q].w[c]);
+            gg[1][c] = (T)0.5 * iH * (X1[q][c] + avec[1] * n[q].w[c]);
+          }
+          jvp_flux_sum<D, T>(n[q], A.G, iWn[q], ith[q], gg, tt);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) r[c] -= cb * tt[c];
+        }
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          r[c] -= ft[q][c] * iH;
+          A.r[uo + c * NP + i] = r[c];
+          s += (double)n[q].w[c] * (double)r[c];
+        }
+        ent += (double)H * s;
+      }
+    }
+    __syncthreads();
+  }
 };
 
 // Rows per lane of the built-in 2D split variant; the autotuner may pick the other.
 template <int P, typename T> constexpr int split2_rows() { return 2; }
 
-template <int P, typename T, int R>
+template <int P, typename T, int R, bool EF = false>
 __global__ __launch_bounds__(kThreads, R == 2 ? 2 : (P == 1 ? 2 : 3)) void k_split2(KArgs<T> A) {
-  typedef Split2<P, T, R> K;
+  typedef Split2<P, T, R, EF> K;
   __shared__ typename K::Lds lds;
   K::load_ops(A, lds);
   __syncthreads();
   double ent = 0.0;
   const int ntiles = (A.n_elem + K::EB - 1) / K::EB;
-  for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) K::tile(A, lds, tl, ent);
+  for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    if constexpr (EF)
+      K::tile_early(A, lds, tl, ent);
+    else
+      K::tile(A, lds, tl, ent);
+  }
   block_sum_store(ent, A.ent_part);
 }
 
@@ -1143,7 +1304,561 @@ __global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
 }
 
 // ---------------------------------------------------------------------------
+// Navier-Stokes terms on triangles (affine or quadratic maps) and on
+// tetrahedra with quadratic maps, in the row form of k_split2 / k_split3c.
+// With D_xi = H^-1 Q_xi, Q_xi = K_i + a_i/2 (K_i the metric-averaged skew
+// part, a_i = sum_l Lambda_il E_l) and the Baumann-Oden term
+// y'_j = -1/2 H^-1 y_j at the facet nodes (y_j = sum_i K~_ij^T (B n_i (w_k -
+// w_v)), Sec. 5, eq. bo sats):
+//   sum_i D_xi F^V(i) - 1/2 H^-1 sum_j D_xj^T y_j
+//     = H^-1 [ sum_i K_i (F^V(i) - y'_i) + 1/2 sum_i a_i (F^V(i) + y'_i) ],
+// and per node pair K_i z_i at row m = 1/2 sum_n c_i(m, n) z_i,n with the
+// metric-averaged coefficients c_i(m, n) = sum_l S_l[m][n] (Lambda_il(m) +
+// Lambda_il(n)) of the Euler pair sums.  So the viscous residual is a second
+// pass of node-pair sums over Z_i = F^V(i) - y'_i, after the first pass has
+// given D_x w = (X + a w) / (2 H) at every node.  The facet flux jump
+// -1/2 H^-1 (q_k + q_v), q = B n . F^V from each side's own gradient, reads
+// the facet fluxes that the pre-pass (k_visc_q2 / k_visc_q3c) wrote.
+//
+// One lane per node row; per node in LDS: fluxes (then Z), w, Lambda.
 
+// Pre-pass on triangles: q = B n . F^V at the facet nodes of every element.
+template <int P, typename T>
+__global__ __launch_bounds__(kThreads) void k_visc_q2(KArgs<T> A) {
+  constexpr int D = 2, NC = 4, NFAC = 3;
+  constexpr int NP = Shape<2, P>::NP, NF = Shape<2, P>::NF, NFN = NFAC * NF;
+  constexpr int EB = kThreads / NP;
+  constexpr int NV = 8;  // w[4], Lambda[4]
+  constexpr int NDS = NP * NV + 2;
+  __shared__ T nd[EB * NDS];
+  const int tid = threadIdx.x;
+  const int e = tid / NP, i = tid % NP;
+  const int ntiles = (A.n_elem + EB - 1) / EB;
+  for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    const int e0 = tl * EB;
+    const int ne = min(EB, A.n_elem - e0);
+    const bool act = e < ne;
+    Node<D, T> n;
+    T lam[4];
+    __syncthreads();
+    if (act) {
+      const double *g = A.geo + (size_t)(e0 + e) * 12;
+      T F[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        const T d0 = A.op.dN[(0 * 6 + a) * NP + i], d1 = A.op.dN[(1 * 6 + a) * NP + i];
+        const T gx = (T)g[2 * a], gy = (T)g[2 * a + 1];
+        F[0][0] += d0 * gx;
+        F[0][1] += d1 * gx;
+        F[1][0] += d0 * gy;
+        F[1][1] += d1 * gy;
+      }
+      lam[0] = F[1][1];
+      lam[1] = -F[1][0];
+      lam[2] = -F[0][1];
+      lam[3] = F[0][0];
+      const int uo = A.uoff[e0 + e];
+      T uu[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) uu[c] = (T)A.u[uo + c * NP + i];
+      node_from_u<D, T>(uu, A.G, n);
+      T *v = nd + e * NDS + i * NV;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[c] = n.w[c];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[4 + c] = lam[c];
+    }
+    __syncthreads();
+    if (act && i < NFN) {
+      T X0[NC], X1[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) X0[c] = X1[c] = (T)0;
+#pragma unroll 2
+      for (int j = 0; j < NP; ++j) {
+        // S_l is stored exactly skew: S_l[i][j] read as -S_l[j][i]
+        const T s0 = -A.op.S[(0 * NP + j) * NP + i], s1 = -A.op.S[(1 * NP + j) * NP + i];
+        const T *v = nd + e * NDS + j * NV;
+        const T c0 = s0 * (lam[0] + v[4]) + s1 * (lam[1] + v[5]);
+        const T c1 = s0 * (lam[2] + v[6]) + s1 * (lam[3] + v[7]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          X0[c] += c0 * v[c];
+          X1[c] += c1 * v[c];
+        }
+      }
+      const T E0 = A.op.E[i], E1 = A.op.E[NP + i];
+      T avec[D];
+      avec[0] = lam[0] * E0 + lam[1] * E1;
+      avec[1] = lam[2] * E0 + lam[3] * E1;
+      const T J = lam[3] * lam[0] - lam[2] * lam[1];
+      const T iH = (T)1 / (J * (T)A.op.h[i]);
+      T gW[D][NC], FV[D][NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        gW[0][c] = (T)0.5 * iH * (X0[c] + avec[0] * n.w[c]);
+        gW[1][c] = (T)0.5 * iH * (X1[c] + avec[1] * n.w[c]);
+      }
+      viscous_flux<D, T>(n, A.G, A.V, gW, FV);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        A.qout[((size_t)(e0 + e) * NFN + i) * NC + c] = avec[0] * FV[0][c] + avec[1] * FV[1][c];
+    }
+  }
+}
+
+// Entropy split with the Navier-Stokes terms on triangles.
+template <int P, typename T>
+__global__ __launch_bounds__(kThreads) void k_visc2(KArgs<T> A) {
+  constexpr int D = 2, NC = 4, NFAC = 3;
+  constexpr int NP = Shape<2, P>::NP, NF = Shape<2, P>::NF, NFN = NFAC * NF;
+  constexpr int EB = kThreads / NP;
+  constexpr int NDS = NP * 16 + 4;  // per node: f0[4] f1[4] (later Z_0, Z_1) w[4] Lambda[4]
+  __shared__ __align__(16) T nd[EB * NDS];
+  __shared__ T Ss[2][NP][NP];
+  const int tid = threadIdx.x;
+  for (int x = tid; x < 2 * NP * NP; x += kThreads) (&Ss[0][0][0])[x] = A.op.S[x];
+  const T cb = A.G.cb;
+  const T hv = (T)0.5 * (cb - (T)1), he = (T)0.5 * (cb + (T)1);
+  const int e = tid / NP, i = tid % NP;
+  double ent = 0.0;
+  const int ntiles = (A.n_elem + EB - 1) / EB;
+  for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    const int e0 = tl * EB;
+    const int ne = min(EB, A.n_elem - e0);
+    const bool act = e < ne;
+    Node<D, T> n;
+    T lam[4];
+    __syncthreads();
+    if (act) {
+      const double *g = A.geo + (size_t)(e0 + e) * 12;
+      T F[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        const T d0 = A.op.dN[(0 * 6 + a) * NP + i], d1 = A.op.dN[(1 * 6 + a) * NP + i];
+        const T gx = (T)g[2 * a], gy = (T)g[2 * a + 1];
+        F[0][0] += d0 * gx;
+        F[0][1] += d1 * gx;
+        F[1][0] += d0 * gy;
+        F[1][1] += d1 * gy;
+      }
+      lam[0] = F[1][1];
+      lam[1] = -F[1][0];
+      lam[2] = -F[0][1];
+      lam[3] = F[0][0];
+      const int uo = A.uoff[e0 + e];
+      T uu[NC], f0[NC], f1[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) uu[c] = (T)A.u[uo + c * NP + i];
+      node_from_u<D, T>(uu, A.G, n);
+      if (!n.ok) atomicOr(A.err, 1);
+      flux_i<D, T>(n, uu[NC - 1], 0, f0);
+      flux_i<D, T>(n, uu[NC - 1], 1, f1);
+      T *v = nd + e * NDS + i * 16;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        v[c] = f0[c];
+        v[4 + c] = f1[c];
+        v[8 + c] = n.w[c];
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[12 + c] = lam[c];
+    }
+    __syncthreads();
+    T r[NC], Pv[NC], Z[D][NC];
+    T H = (T)1, iH = (T)1, avec[D] = {(T)0, (T)0};
+    if (act) {
+      T V[NC], X0[NC], X1[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) V[c] = X0[c] = X1[c] = (T)0;
+#pragma unroll 1
+      for (int j = 0; j < NP; ++j) {
+        const T *v = nd + e * NDS + j * 16;
+        const T s0 = Ss[0][i][j], s1 = Ss[1][i][j];
+        const T c0 = s0 * (lam[0] + v[12]) + s1 * (lam[1] + v[13]);
+        const T c1 = s0 * (lam[2] + v[14]) + s1 * (lam[3] + v[15]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          V[c] += c0 * v[c];
+          V[c] += c1 * v[4 + c];
+          X0[c] += c0 * v[8 + c];
+          X1[c] += c1 * v[8 + c];
+        }
+      }
+      const T E0 = A.op.E[i], E1 = A.op.E[NP + i];
+      avec[0] = lam[0] * E0 + lam[1] * E1;
+      avec[1] = lam[2] * E0 + lam[3] * E1;
+      const T J = lam[3] * lam[0] - lam[2] * lam[1];
+      H = J * (T)A.op.h[i];
+      iH = (T)1 / H;
+      const T *vi = nd + e * NDS + i * 16;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) r[c] = iH * (hv * V[c] + he * (avec[0] * vi[c] + avec[1] * vi[4 + c]));
+      T gW[D][NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        gW[0][c] = (T)0.5 * iH * (X0[c] + avec[0] * n.w[c]);
+        gW[1][c] = (T)0.5 * iH * (X1[c] + avec[1] * n.w[c]);
+      }
+#pragma unroll
+      for (int dir = 0; dir < D; ++dir) {
+        T tt[NC];
+        jvp_flux<D, T>(n, A.G, dir, gW[dir], tt);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) r[c] -= cb * tt[c];
+      }
+      T FV[D][NC], yp[D][NC];
+      viscous_flux<D, T>(n, A.G, A.V, gW, FV);
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) yp[k][c] = (T)0;
+      if (i < NFN) {
+        const int off = A.nbr[(size_t)(e0 + e) * NFN + i];
+        T uv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) uv[c] = (T)A.u[off + c * NP];
+        Node<D, T> nv;
+        node_from_u<D, T>(uv, A.G, nv);
+        T dw[NC], y[D][NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) dw[c] = n.w[c] - nv.w[c];
+        viscous_adjoint_facet<D, T>(n, A.G, A.V, avec, dw, y);
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) yp[k][c] = (T)(-0.5) * iH * y[k][c];
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        Z[0][c] = FV[0][c] - yp[0][c];
+        Z[1][c] = FV[1][c] - yp[1][c];
+        Pv[c] = (T)0.5 * (avec[0] * (FV[0][c] + yp[0][c]) + avec[1] * (FV[1][c] + yp[1][c]));
+      }
+    }
+    __syncthreads();  // every lane is done with the fluxes of pass one
+    if (act) {
+      T *v = nd + e * NDS + i * 16;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        v[c] = Z[0][c];
+        v[4 + c] = Z[1][c];
+      }
+    }
+    __syncthreads();
+    if (act) {
+      T W[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) W[c] = (T)0;
+#pragma unroll 1
+      for (int j = 0; j < NP; ++j) {
+        const T *v = nd + e * NDS + j * 16;
+        const T s0 = Ss[0][i][j], s1 = Ss[1][i][j];
+        const T c0 = s0 * (lam[0] + v[12]) + s1 * (lam[1] + v[13]);
+        const T c1 = s0 * (lam[2] + v[14]) + s1 * (lam[3] + v[15]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          W[c] += c0 * v[c];
+          W[c] += c1 * v[4 + c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) r[c] += iH * ((T)0.5 * W[c] + Pv[c]);
+      if (i < NFN) {
+        const T *qk = A.q + ((size_t)(e0 + e) * NFN + i) * NC;
+        const T *qv = A.q + (size_t)A.nbrq[(size_t)(e0 + e) * NFN + i] * NC;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) r[c] -= (T)0.5 * (qk[c] + qv[c]) * iH;
+      }
+      finish_node<D, NP, NF, T>(A, e0 + e, i, n, H, avec, r, ent);
+    }
+  }
+  block_sum_store(ent, A.ent_part);
+}
+
+// Metric cofactors Lambda (L[k][l] = J dxi_l/dx_k) and J at node i of a
+// tetrahedron with a quadratic map (ten map nodes g[a*3 + k]).
+template <int NP, typename T>
+__device__ __forceinline__ void curved3_metrics(const KArgs<T> &A, const T *g, int i, T L[3][3], T &J) {
+  T F[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) F[k][l] = (T)0;
+#pragma unroll
+  for (int a = 0; a < 10; ++a) {
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const T d = A.op.dN[(l * 10 + a) * NP + i];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) F[k][l] += d * g[a * 3 + k];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const int k1 = (k + 1) % 3, k2 = (k + 2) % 3, l1 = (l + 1) % 3, l2 = (l + 2) % 3;
+      L[k][l] = F[k1][l1] * F[k2][l2] - F[k1][l2] * F[k2][l1];
+    }
+  J = F[0][0] * L[0][0] + F[0][1] * L[0][1] + F[0][2] * L[0][2];
+}
+
+// Pre-pass on tetrahedra with quadratic maps: q = B n . F^V at the facet nodes.
+template <int P, typename T>
+__global__ __launch_bounds__(kThreads) void k_visc_q3c(KArgs<T> A) {
+  constexpr int D = 3, NC = 5, NFAC = 4;
+  constexpr int NP = Shape<3, P>::NP, NF = Shape<3, P>::NF, NFN = NFAC * NF;
+  constexpr int EB = VTile3<P, T>::EB;
+  static_assert(EB * NP <= kThreads, "one node per lane");
+  constexpr int NV = 15;  // w[5], Lambda[9], pad
+  constexpr int NDS = NP * NV;
+  __shared__ T nd[EB * NDS];
+  __shared__ T gs[EB][30];
+  const int tid = threadIdx.x;
+  const int e = tid / NP, i = tid % NP;
+  const int ntiles = (A.n_elem + EB - 1) / EB;
+  for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    const int e0 = tl * EB;
+    const int ne = min(EB, A.n_elem - e0);
+    const bool act = tid < ne * NP;
+    __syncthreads();
+    for (int x = tid; x < ne * 30; x += kThreads) gs[x / 30][x % 30] = (T)A.geo[(size_t)(e0 + x / 30) * 30 + x % 30];
+    __syncthreads();
+    Node<D, T> n;
+    T L[D][D], J = (T)1;
+    if (act) {
+      curved3_metrics<NP, T>(A, gs[e], i, L, J);
+      const int uo = A.uoff[e0 + e];
+      T uu[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) uu[c] = (T)A.u[uo + c * NP + i];
+      node_from_u<D, T>(uu, A.G, n);
+      T *v = nd + e * NDS + i * NV;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[c] = n.w[c];
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int l = 0; l < D; ++l) v[5 + k * 3 + l] = L[k][l];
+    }
+    __syncthreads();
+    if (act && i < NFN) {
+      T X[D][NC];
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) X[k][c] = (T)0;
+#pragma unroll 1
+      for (int j = 0; j < NP; ++j) {
+        const T s0 = -A.op.S[(0 * NP + j) * NP + i];
+        const T s1 = -A.op.S[(1 * NP + j) * NP + i];
+        const T s2 = -A.op.S[(2 * NP + j) * NP + i];
+        const T *v = nd + e * NDS + j * NV;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          const T ck = s0 * (L[k][0] + v[5 + k * 3 + 0]) + s1 * (L[k][1] + v[5 + k * 3 + 1]) +
+                       s2 * (L[k][2] + v[5 + k * 3 + 2]);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) X[k][c] += ck * v[c];
+        }
+      }
+      T El[D], avec[D];
+#pragma unroll
+      for (int l = 0; l < D; ++l) El[l] = A.op.E[l * NP + i];
+#pragma unroll
+      for (int m = 0; m < D; ++m) avec[m] = L[m][0] * El[0] + L[m][1] * El[1] + L[m][2] * El[2];
+      const T iH = (T)1 / (J * (T)A.op.h[i]);
+      T gW[D][NC], FV[D][NC];
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) gW[k][c] = (T)0.5 * iH * (X[k][c] + avec[k] * n.w[c]);
+      viscous_flux<D, T>(n, A.G, A.V, gW, FV);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        A.qout[((size_t)(e0 + e) * NFN + i) * NC + c] = avec[0] * FV[0][c] + avec[1] * FV[1][c] + avec[2] * FV[2][c];
+    }
+  }
+}
+
+// Entropy split with the Navier-Stokes terms on tetrahedra with quadratic maps.
+template <int P, typename T>
+__global__ __launch_bounds__(kThreads) void k_visc3c(KArgs<T> A) {
+  constexpr int D = 3, NC = 5, NFAC = 4;
+  constexpr int NP = Shape<3, P>::NP, NF = Shape<3, P>::NF, NFN = NFAC * NF;
+  constexpr int EB = VTile3<P, T>::EB;
+  static_assert(EB * NP <= kThreads, "one node per lane");
+  constexpr int NV = 29;  // f^(1..3)[15] (later Z_1..Z_3), w[5], Lambda[9]
+  constexpr int NDS = NP * NV;
+  __shared__ T nd[EB * NDS];
+  __shared__ T gs[EB][30];
+  const int tid = threadIdx.x;
+  const T cb = A.G.cb;
+  const T hv = (T)0.5 * (cb - (T)1), he = (T)0.5 * (cb + (T)1);
+  double ent = 0.0;
+  const int ntiles = (A.n_elem + EB - 1) / EB;
+  const int e = tid / NP, i = tid % NP;
+  for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    const int e0 = tl * EB;
+    const int ne = min(EB, A.n_elem - e0);
+    const bool act = tid < ne * NP;
+    __syncthreads();
+    for (int x = tid; x < ne * 30; x += kThreads) gs[x / 30][x % 30] = (T)A.geo[(size_t)(e0 + x / 30) * 30 + x % 30];
+    __syncthreads();
+    Node<D, T> n;
+    T L[D][D], J = (T)1;
+    if (act) {
+      curved3_metrics<NP, T>(A, gs[e], i, L, J);
+      const int uo = A.uoff[e0 + e];
+      T uu[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) uu[c] = (T)A.u[uo + c * NP + i];
+      node_from_u<D, T>(uu, A.G, n);
+      if (!n.ok) atomicOr(A.err, 1);
+      T *v = nd + e * NDS + i * NV;
+#pragma unroll
+      for (int m = 0; m < D; ++m) flux_i<D, T>(n, uu[NC - 1], m, v + m * NC);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[15 + c] = n.w[c];
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int l = 0; l < D; ++l) v[20 + k * 3 + l] = L[k][l];
+    }
+    __syncthreads();
+    T r[NC], Pv[NC], Z[D][NC];
+    T H = (T)1, iH = (T)1, avec[D] = {(T)0, (T)0, (T)0};
+    if (act) {
+      T V[NC], X[D][NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        V[c] = (T)0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) X[k][c] = (T)0;
+      }
+#pragma unroll 1
+      for (int j = 0; j < NP; ++j) {
+        const T s0 = -A.op.S[(0 * NP + j) * NP + i];
+        const T s1 = -A.op.S[(1 * NP + j) * NP + i];
+        const T s2 = -A.op.S[(2 * NP + j) * NP + i];
+        const T *v = nd + e * NDS + j * NV;
+        T cm[D];
+#pragma unroll
+        for (int m = 0; m < D; ++m)
+          cm[m] = s0 * (L[m][0] + v[20 + m * 3 + 0]) + s1 * (L[m][1] + v[20 + m * 3 + 1]) +
+                  s2 * (L[m][2] + v[20 + m * 3 + 2]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          V[c] += cm[0] * v[c];
+          V[c] += cm[1] * v[5 + c];
+          V[c] += cm[2] * v[10 + c];
+          X[0][c] += cm[0] * v[15 + c];
+          X[1][c] += cm[1] * v[15 + c];
+          X[2][c] += cm[2] * v[15 + c];
+        }
+      }
+      H = J * (T)A.op.h[i];
+      iH = (T)1 / H;
+      T El[D];
+#pragma unroll
+      for (int l = 0; l < D; ++l) El[l] = A.op.E[l * NP + i];
+#pragma unroll
+      for (int m = 0; m < D; ++m) avec[m] = L[m][0] * El[0] + L[m][1] * El[1] + L[m][2] * El[2];
+      const T *fi = nd + e * NDS + i * NV;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        r[c] = iH * (hv * V[c] + he * (avec[0] * fi[c] + avec[1] * fi[NC + c] + avec[2] * fi[2 * NC + c]));
+      T gW[D][NC];
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) gW[k][c] = (T)0.5 * iH * (X[k][c] + avec[k] * n.w[c]);
+#pragma unroll
+      for (int dir = 0; dir < D; ++dir) {
+        T tt[NC];
+        jvp_flux<D, T>(n, A.G, dir, gW[dir], tt);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) r[c] -= cb * tt[c];
+      }
+      T FV[D][NC], yp[D][NC];
+      viscous_flux<D, T>(n, A.G, A.V, gW, FV);
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) yp[k][c] = (T)0;
+      if (i < NFN) {
+        const int off = A.nbr[(size_t)(e0 + e) * NFN + i];
+        T uv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) uv[c] = (T)A.u[off + c * NP];
+        Node<D, T> nv;
+        node_from_u<D, T>(uv, A.G, nv);
+        T dw[NC], y[D][NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) dw[c] = n.w[c] - nv.w[c];
+        viscous_adjoint_facet<D, T>(n, A.G, A.V, avec, dw, y);
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) yp[k][c] = (T)(-0.5) * iH * y[k][c];
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        T s = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          Z[k][c] = FV[k][c] - yp[k][c];
+          s += avec[k] * (FV[k][c] + yp[k][c]);
+        }
+        Pv[c] = (T)0.5 * s;
+      }
+    }
+    __syncthreads();  // every lane is done with the fluxes of pass one
+    if (act) {
+      T *v = nd + e * NDS + i * NV;
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[k * NC + c] = Z[k][c];
+    }
+    __syncthreads();
+    if (act) {
+      T W[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) W[c] = (T)0;
+#pragma unroll 1
+      for (int j = 0; j < NP; ++j) {
+        const T s0 = -A.op.S[(0 * NP + j) * NP + i];
+        const T s1 = -A.op.S[(1 * NP + j) * NP + i];
+        const T s2 = -A.op.S[(2 * NP + j) * NP + i];
+        const T *v = nd + e * NDS + j * NV;
+        T cm[D];
+#pragma unroll
+        for (int m = 0; m < D; ++m)
+          cm[m] = s0 * (L[m][0] + v[20 + m * 3 + 0]) + s1 * (L[m][1] + v[20 + m * 3 + 1]) +
+                  s2 * (L[m][2] + v[20 + m * 3 + 2]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          W[c] += cm[0] * v[c];
+          W[c] += cm[1] * v[5 + c];
+          W[c] += cm[2] * v[10 + c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) r[c] += iH * ((T)0.5 * W[c] + Pv[c]);
+      if (i < NFN) {
+        const T *qk = A.q + ((size_t)(e0 + e) * NFN + i) * NC;
+        const T *qv = A.q + (size_t)A.nbrq[(size_t)(e0 + e) * NFN + i] * NC;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) r[c] -= (T)0.5 * (qk[c] + qv[c]) * iH;
+      }
+      finish_node<D, NP, NF, T>(A, e0 + e, i, n, H, avec, r, ent);
+    }
+  }
+  block_sum_store(ent, A.ent_part);
+}
+
+// ---------------------------------------------------------------------------
 
 struct KernelRef {
   const void *fn;
@@ -1166,12 +1881,23 @@ static KernelRef curved3_hadamard_kernel() {
   return {nullptr, 0};
 }
 
+template <int P, typename T>
+static KernelRef curved3_visc_kernel() {
+  if constexpr (P >= 2) return {reinterpret_cast<const void *>(&k_visc3c<P, T>), VTile3<P, T>::EB};
+  return {nullptr, 0};
+}
+
 template <typename T>
 static KernelRef residual_kernel(int dim, int p, int form_eff, int variant) {
 #define SBP_K2(PP)                                                                              \
   if (dim == 2 && p == PP) {                                                                    \
     if (form_eff == 1) return {reinterpret_cast<const void *>(&k_hadamard<2, PP, T>), HadTile<2, PP, T>::EB}; \
+    if (form_eff == 2) return {reinterpret_cast<const void *>(&k_visc2<PP, T>), kThreads / Shape<2, PP>::NP}; \
     if (form_eff == 0) {                                                                        \
+      if (variant == 2)                                                                         \
+        return {reinterpret_cast<const void *>(&k_split2<PP, T, 2, true>), Split2<PP, T, 2>::EB}; \
+      if (variant == 3)                                                                         \
+        return {reinterpret_cast<const void *>(&k_split2<PP, T, 1, true>), Split2<PP, T, 1>::EB}; \
       if ((split2_rows<PP, T>() == 2) != (variant == 1))                                        \
         return {reinterpret_cast<const void *>(&k_split2<PP, T, 2>), Split2<PP, T, 2>::EB};     \
       return {reinterpret_cast<const void *>(&k_split2<PP, T, 1>), Split2<PP, T, 1>::EB};       \
@@ -1186,6 +1912,7 @@ static KernelRef residual_kernel(int dim, int p, int form_eff, int variant) {
     if (form_eff == 2) return {reinterpret_cast<const void *>(&k_split3<PP, T, true>), 3 * Wave3<PP, T>::CT}; \
     if (form_eff == 3) return curved3_kernel<PP, T>();                                         \
     if (form_eff == 4) return curved3_hadamard_kernel<PP, T>();                                \
+    if (form_eff == 5) return curved3_visc_kernel<PP, T>();                                    \
     const bool sg = skew_from_cache3<PP, T>() != (variant == 1);                                \
     return {sg ? reinterpret_cast<const void *>(&k_split3v<PP, T, true>)                        \
                : reinterpret_cast<const void *>(&k_split3v<PP, T, false>),                      \
@@ -1223,7 +1950,8 @@ int launch_grid(const void *kernel, int ntiles, int grid) {
 int residual_variants(int dim, int p, int precision, int form_eff) {
   (void)p;
   (void)precision;
-  return form_eff == 0 ? 2 : 1;
+  if (form_eff != 0) return 1;
+  return dim == 2 ? 4 : 2;
 }
 
 int residual_blocks(int dim, int p, int precision, int form_eff, int n_elem, LaunchCfg cfg) {
@@ -1236,9 +1964,9 @@ int residual_blocks(int dim, int p, int precision, int form_eff, int n_elem, Lau
 
 template <typename T>
 static hipError_t launch_t(int dim, int p, int form, const KArgs<T> &A, hipStream_t s, LaunchCfg cfg) {
-  if (A.visc && (dim != 3 || form != 0)) return hipErrorInvalidValue;
+  if (A.visc && form != 0) return hipErrorInvalidValue;
   if (A.curved && dim != 3) return hipErrorInvalidValue;
-  const int fe = A.visc ? 2 : (A.curved ? (form == 0 ? 3 : 4) : form);
+  const int fe = A.visc ? (A.curved ? 5 : 2) : (A.curved ? (form == 0 ? 3 : 4) : form);
   const KernelRef k = residual_kernel<T>(dim, p, fe, cfg.variant);
   if (!k.fn || A.n_elem <= 0) return hipErrorInvalidValue;
   const int nb = launch_grid(k.fn, (A.n_elem + k.eb - 1) / k.eb, cfg.grid);
@@ -1249,12 +1977,27 @@ static hipError_t launch_t(int dim, int p, int form, const KArgs<T> &A, hipStrea
 
 template <typename T>
 static hipError_t launch_q(int dim, int p, const KArgs<T> &A, hipStream_t s) {
-  if (dim != 3 || A.n_elem <= 0) return hipErrorInvalidValue;
-  const void *fn = p == 1 ? reinterpret_cast<const void *>(&k_visc_q3<1, T>)
-                 : p == 2 ? reinterpret_cast<const void *>(&k_visc_q3<2, T>)
-                 : p == 3 ? reinterpret_cast<const void *>(&k_visc_q3<3, T>) : nullptr;
+  if (A.n_elem <= 0) return hipErrorInvalidValue;
+  const void *fn = nullptr;
+  int eb = 0;
+  if (dim == 2) {
+    fn = p == 1 ? reinterpret_cast<const void *>(&k_visc_q2<1, T>)
+       : p == 2 ? reinterpret_cast<const void *>(&k_visc_q2<2, T>)
+       : p == 3 ? reinterpret_cast<const void *>(&k_visc_q2<3, T>)
+       : p == 4 ? reinterpret_cast<const void *>(&k_visc_q2<4, T>) : nullptr;
+    eb = p >= 1 && p <= 4 ? kThreads / (p == 1 ? Shape<2, 1>::NP : p == 2 ? Shape<2, 2>::NP
+                                       : p == 3 ? Shape<2, 3>::NP : Shape<2, 4>::NP) : 0;
+  } else if (A.curved) {
+    fn = p == 2 ? reinterpret_cast<const void *>(&k_visc_q3c<2, T>)
+       : p == 3 ? reinterpret_cast<const void *>(&k_visc_q3c<3, T>) : nullptr;
+    eb = p == 2 ? VTile3<2, T>::EB : VTile3<3, T>::EB;
+  } else {
+    fn = p == 1 ? reinterpret_cast<const void *>(&k_visc_q3<1, T>)
+       : p == 2 ? reinterpret_cast<const void *>(&k_visc_q3<2, T>)
+       : p == 3 ? reinterpret_cast<const void *>(&k_visc_q3<3, T>) : nullptr;
+    eb = p == 1 ? VTile3<1, T>::EB : (p == 2 ? VTile3<2, T>::EB : VTile3<3, T>::EB);
+  }
   if (!fn) return hipErrorInvalidValue;
-  const int eb = p == 1 ? VTile3<1, T>::EB : (p == 2 ? VTile3<2, T>::EB : VTile3<3, T>::EB);
   const int nb = launch_grid(fn, (A.n_elem + eb - 1) / eb, 1);
   KArgs<T> a = A;
   void *args[] = {&a};

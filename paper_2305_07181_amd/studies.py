@@ -2,8 +2,8 @@
 
     python -m paper_2305_07181_amd.studies conservation [--ns 60 80 100 120]
         [--ps 1 2 3 4] [--tf 2.0] [--cfl 0.1]
-    python -m paper_2305_07181_amd.studies mms --dim 3 [--ns 6 9 12 15]
-        [--ps 1 2 3] [--tf 0.001] [--steps 1000] [--mu 0.01]
+    python -m paper_2305_07181_amd.studies mms --dim 2|3 [--ns 6 9 12 15]
+        [--ps 1 2 3] [--tf 0.001] [--steps 1000] [--mu 0.01] [--euler]
     python -m paper_2305_07181_amd.studies vortex2d [--ns 60 80 100 120]
         [--ps 1 2 3 4] [--tf 2.0] [--cfl 0.1] [--hadamard]
     python -m paper_2305_07181_amd.studies vortex3d [--ns 15 20 25 30]
@@ -31,11 +31,12 @@ of the paper's accuracy section (Sec. 7.3: the nodal solution interpolated
 to a quadrature of degree 3p + 1, the squared error integrated and summed
 over the elements and components, sbp_source_error with the quadrature
 norm) and the nodal H-norm error sqrt(sum_c sum_k (u - u*)_c^T H_k
-(u - u*)_c) at the final time are reported with their rates.  In 2D the grids are the curved triangles of the
-study and the equations the Euler equations (the viscous terms of this
-library cover tetrahedra); in 3D the Navier-Stokes equations (mu, Pr = 0.71,
-R = 1, heat flux on, no interface dissipation) on affine tetrahedra (the
-study's curving map is not applied in 3D).
+(u - u*)_c) at the final time are reported with their rates.  The
+equations are the Navier-Stokes equations (mu, Pr = 0.71, R = 1, heat flux
+on, Baumann-Oden SATs, no interface dissipation; --euler: the Euler
+equations) on the study's curved grids: triangles and tetrahedra with
+quadratic maps (in 3D at p = 1 the map moves the vertices of affine
+tetrahedra, the map degree Assumption 1 allows).
 
 2D isentropic vortex (Sec. 7.3, Table accuracy vortex 2d): the vortex of
 sbp_set_source(SOURCE_VORTEX2D) on the curved grids n^2 x 2 of the
@@ -111,10 +112,12 @@ def conservation_study(ns, ps, tf=2.0, cfl=0.1, emit=print):
     return rows
 
 
-def mms_run(dim: int, n: int, p: int, tf: float = 1e-3, steps: int = 1000, mu: float = 0.01) -> dict:
+def mms_run(dim: int, n: int, p: int, tf: float = 1e-3, steps: int = 1000, mu: float = 0.01,
+            viscous: bool = True) -> dict:
     from . import sbp, workloads as wl
-    desc = wl.mms_mesh2d(n) if dim == 2 else wl.mms_mesh3d(n)
-    viscous = dim == 3
+    # the study's curved grids; in 3D at p = 1 the curving map moves the
+    # vertices of affine tetrahedra (the map degree Assumption 1 allows there)
+    desc = wl.mms_mesh2d(n) if dim == 2 else wl.mms_mesh3d(n, curve="quadratic" if p >= 2 else "vertices")
     mesh = sbp.Mesh(desc, p, viscous=viscous, mu=mu if viscous else 0.0, Pr=0.71, R=1.0)
     mesh.set_source()
     mesh.set_time(0.0)
@@ -137,12 +140,12 @@ def mms_run(dim: int, n: int, p: int, tf: float = 1e-3, steps: int = 1000, mu: f
     return out
 
 
-def mms_study(dim, ns, ps, tf=1e-3, steps=1000, mu=0.01, emit=print):
+def mms_study(dim, ns, ps, tf=1e-3, steps=1000, mu=0.01, emit=print, viscous=True):
     rows = []
     for p in ps:
         prev = None
         for n in ns:
-            r = mms_run(dim, n, p, tf, steps, mu)
+            r = mms_run(dim, n, p, tf, steps, mu, viscous)
             if prev is not None:
                 f = math.log(n / prev["n"])   # h = (volume / n_e)^(1/d) falls as 1/n
                 r["rate"] = math.log(prev["l2_error"] / r["l2_error"]) / f
@@ -251,6 +254,7 @@ def main(argv=None):
     ap.add_argument("--hadamard", action="store_true", help="vortex studies: the Hadamard form (comparator)")
     ap.add_argument("--re", type=float, default=1600.0, help="tgv: Reynolds number")
     ap.add_argument("--fp64", action="store_true", help="tgv: FP64 residuals (default FP32)")
+    ap.add_argument("--euler", action="store_true", help="mms: the Euler equations (no viscous terms)")
     a = ap.parse_args(argv)
     emit = lambda s: print(s, flush=True)
     if a.study == "conservation":
@@ -270,7 +274,7 @@ def main(argv=None):
     else:
         ns = a.ns or ([20, 30, 40, 50] if a.dim == 2 else [6, 9, 12, 15])
         ps = a.ps or ([1, 2, 3, 4] if a.dim == 2 else [1, 2, 3])
-        mms_study(a.dim, ns, ps, a.tf or 1e-3, a.steps, a.mu, emit=emit)
+        mms_study(a.dim, ns, ps, a.tf or 1e-3, a.steps, a.mu, emit=emit, viscous=not a.euler)
 
 
 if __name__ == "__main__":

@@ -291,12 +291,32 @@ def mms_mesh2d(n: int) -> dict:
     return desc
 
 
-def mms_mesh3d(n: int) -> dict:
+def mms_mesh3d(n: int, curve: str = "none") -> dict:
     """The periodic box [-1,1]^3 of the manufactured-solution study in n^3
-    cubes of six affine tetrahedra each (the study's curving map is not
-    applied: the viscous terms run on affine tetrahedra)."""
+    cubes of six tetrahedra each.  curve: "none" (affine tetrahedra),
+    "quadratic" (the study's curving map
+        x_i = x^_i + 1/8 cos(pi/2 x^_i) prod_{j != i} sin(pi x^_j)
+    applied to the quadratic map nodes, vertices and edge midpoints; degrees
+    p >= 2) or "vertices" (the map applied to the vertices of affine
+    tetrahedra, the map degree Assumption 1 allows at p = 1).  The map fixes
+    every point of the box faces (conforming and periodic)."""
     desc = periodic_tet_mesh(n, 2.0)
     desc["vert_xyz"] = desc["vert_xyz"] - 1.0
+
+    def curved(x):
+        s = np.sin(np.pi * x)
+        c = np.cos(0.5 * np.pi * x)
+        return np.stack([x[..., 0] + 0.125 * c[..., 0] * s[..., 1] * s[..., 2],
+                         x[..., 1] + 0.125 * c[..., 1] * s[..., 0] * s[..., 2],
+                         x[..., 2] + 0.125 * c[..., 2] * s[..., 0] * s[..., 1]], -1)
+
+    if curve == "vertices":
+        desc["vert_xyz"] = np.ascontiguousarray(curved(desc["vert_xyz"]))
+    elif curve == "quadratic":
+        desc["p_geom"] = 2
+        desc["geom_nodes"] = np.ascontiguousarray(curved(_tet_p2_nodes(desc)))
+    elif curve != "none":
+        raise ValueError(curve)
     return desc
 
 

@@ -6,7 +6,7 @@ the same workload starts from that choice."""
 import numpy as np
 import pytest
 
-from tests.gpu_common import rel_err_per_component, say, state
+from tests.gpu_common import rel_err_per_component, say, state, term_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -24,7 +24,8 @@ def _setup(dim, p, n, precision, seed):
 
 # enough elements that one resident set of workgroups does not cover every
 # tile (grid 1 and 2 differ from one workgroup per tile)
-@pytest.mark.parametrize("dim,p,n,prec", [(3, 3, 8, 0), (3, 2, 12, 1), (3, 1, 12, 0), (2, 4, 64, 0)])
+@pytest.mark.parametrize("dim,p,n,prec", [(3, 3, 8, 0), (3, 2, 12, 1), (3, 1, 12, 0), (2, 4, 64, 0),
+                                          (2, 1, 64, 0), (2, 2, 48, 1), (2, 3, 48, 0), (2, 4, 40, 1)])
 def test_every_residual_launch_shape(dim, p, n, prec):
     import torch
     from oracle import physics as ph
@@ -39,11 +40,25 @@ def test_every_residual_launch_shape(dim, p, n, prec):
     r0 = r0.double().cpu().numpy()
     e0 = float(e0.cpu()[0])
     els = [0, 1, m.ne // 2, m.ne - 1]
-    ro = OracleScheme(m, ph.Gas(), dissipation=True)(u, elements=els)
-    err = rel_err_per_component(r0[els], ro)
+    sch = OracleScheme(m, ph.Gas(), dissipation=True)
+    ro = sch(u, elements=els)
+    if prec == 0:
+        def vs_oracle(r):
+            return rel_err_per_component(r[els], ro)
+    else:
+        # FP32: the error against the scale of the summed terms (the 1%
+        # jitter makes the residual ~1/100 of its terms on the finer grids)
+        sc = term_scale(sch, u, els)
+
+        def vs_oracle(r):
+            return np.abs(r[els] - ro).max(axis=(0, 2)) / sc
+    err = vs_oracle(r0)
     say("   built-in shape vs oracle", err.max())
-    assert (err <= (1e-12 if prec == 0 else 2e-4)).all(), err  # FP32: the stated error bound
-    nvar = 2  # 2D: one or two node rows per lane; 3D: skew operators in LDS or via the caches
+    tol = 1e-12 if prec == 0 else 1e-5
+    assert (err <= tol).all(), err
+    # 2D: one or two node rows per lane, facet SATs after or before the pair
+    # sums; 3D: skew operators in LDS or via the caches
+    nvar = 4 if dim == 2 else 2
     for v in range(nvar):
         for g in GRIDS:
             mesh.set_launch_shape("residual", p, v, g)
@@ -53,14 +68,14 @@ def test_every_residual_launch_shape(dim, p, n, prec):
             r = r.double().cpu().numpy()
             d = np.abs(r - r0).max() / np.abs(r0).max()
             de = abs(float(e.cpu()[0]) - e0) / abs(e0)
-            eo = rel_err_per_component(r[els], ro).max()
+            eo = vs_oracle(r).max()
             say(f"   variant {v} grid {g}: vs oracle {eo:.1e}, vs built-in {d:.1e}, entropy rate {de:.1e}")
             # the grid only changes which workgroup runs a tile (bitwise equal
             # residual); the variants are different kernels of the same sums
             # (FMA contraction may differ): rounding-level agreement, for FP32
             # up to 1e-5 of max |r| over 25-60 accumulated products
             assert d <= (0.0 if v == 0 else (1e-13 if prec == 0 else 1e-5)), (v, g, d)
-            assert eo <= (1e-12 if prec == 0 else 2e-4), (v, g, eo)
+            assert eo <= tol, (v, g, eo)
             assert de <= (1e-11 if v == 0 or prec == 0 else 1e-5), (v, g, de)
     with pytest.raises(sbp.SbpError):
         mesh.set_launch_shape("residual", p, nvar, 1)

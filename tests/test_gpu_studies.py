@@ -49,7 +49,7 @@ def test_conservation_study_small():
     assert rows[1]["mass_error"] < rows[0]["mass_error"]
 
 
-@pytest.mark.parametrize("dim,p,ns", [(2, 2, (8, 16)), (3, 1, (4, 8))])
+@pytest.mark.parametrize("dim,p,ns", [(2, 2, (8, 16)), (3, 1, (4, 8)), (3, 2, (3, 6))])
 def test_mms_study_small(dim, p, ns):
     """Manufactured solution (Sec. 7) through the library on two small grids:
     the nodal fields start exact; after 50 steps to t = 10^-3 the studies'
