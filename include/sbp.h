@@ -143,9 +143,12 @@ int sbp_residual_noalloc(sbp_mesh *mesh, const void *u_dev, void *r_dev,
                          double *entropy_rate_dev, void *hip_stream);
 
 /* ubar = (dr/du)^T lambda (vector-Jacobian product of sbp_residual).  Not in
- * the paper.  Layouts as for sbp_residual, all FP64.  Euler terms (with or
- * without dissipation) in either volume form and with the hybrid form flags;
- * SBP_ENOTSUP with the viscous terms. */
+ * the paper.  Layouts as for sbp_residual, all FP64 (also on FP32 meshes: the
+ * VJP kernels compute in FP64).  Every residual the library evaluates: Euler
+ * terms with or without dissipation in either volume form and with the
+ * hybrid form flags, and the Navier-Stokes terms (viscous flux with heat
+ * flux, Baumann-Oden SATs), on affine and curved elements.  Asynchronous on
+ * hip_stream. */
 int sbp_residual_vjp(sbp_mesh *mesh, const void *u_dev, const void *lambda_dev,
                      void *ubar_dev, void *hip_stream);
 

@@ -61,6 +61,7 @@ struct DegreeClass {
   sbp::OpTables<float> op32{};
   int *d_nbrq = nullptr;  // viscous: neighbour q index per facet node
   void *d_q = nullptr;    // viscous: facet normal viscous fluxes
+  double *d_vq = nullptr; // viscous VJP: s and mu at the facet nodes
   int part_off = 0;       // offset of this class in the residual partial buffer
   int res_blocks = 0;     // partial sums reserved: the largest grid of any launch shape
   int part_off_h = 0, res_blocks_h = 0;  // hybrid scheme: the Hadamard launch's partial sums
@@ -488,7 +489,10 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
     if ((rc = upload(c.d_Hn, hn, s))) return rc;
     if ((rc = upload(c.d_hmin, hm, s))) return rc;
     if ((rc = upload(c.d_nbrq, nbrq, s))) return rc;
-    if (ph->viscous) HIPCHK(hipMalloc(&c.d_q, sizeof(double) * (size_t)c.n_elem * nv * nf * M->nc));
+    if (ph->viscous) {
+      HIPCHK(hipMalloc(&c.d_q, sizeof(double) * (size_t)c.n_elem * nv * nf * M->nc));
+      HIPCHK(hipMalloc((void **)&c.d_vq, sizeof(double) * (size_t)c.n_elem * nv * nf * 2 * M->nc));
+    }
     std::vector<double> b64;
     std::vector<float> b32;
     size_t o64[11], o32[11];
@@ -1051,6 +1055,8 @@ double *g_scratch_dev[kMaxDevices] = {};
 
 // Device address of `scratch` on the current device, resolved once per device
 // (at mesh setup, or at the first allocation-free call on a device).
+int vjp_euler(sbp_mesh *M, const void *u, const void *lam, void *ubar, hipStream_t stream);
+
 int scratch_address(double **out) {
   int dev = -1;
   HIPCHK(hipGetDevice(&dev));
@@ -1158,7 +1164,27 @@ int sbp_residual_noalloc(sbp_mesh *M, const void *u, void *r, double *ent_dev, v
 int sbp_residual_vjp(sbp_mesh *M, const void *u, const void *lam, void *ubar, void *stream) {
   if (!M || !u || !lam || !ubar) return fail(SBP_EINVAL, "null argument");
   const sbp_physics &ph = M->phys;
-  if (ph.viscous) return fail(SBP_ENOTSUP, "the VJP covers the Euler residual (with or without dissipation)");
+  int rc = vjp_euler(M, u, lam, ubar, (hipStream_t)stream);
+  if (rc || !ph.viscous) return rc;
+  // the Navier-Stokes terms add their VJP to the Euler terms'
+  for (auto &c : M->cls) {
+    sbp::KArgs<double> A = kargs<double>(M, c, (const double *)u, nullptr, c.op64);
+    A.lam = (const double *)lam;
+    A.ubar = (double *)ubar;
+    A.Hn = c.d_Hn;
+    HIPCHK(sbp::launch_vjp_viscous(M->dim, c.p, A, c.d_vq, (hipStream_t)stream));
+  }
+  return SBP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// ubar = (dr/du)^T lambda of the Euler terms (both volume forms, hybrid flags,
+// dissipation).
+int vjp_euler(sbp_mesh *M, const void *u, const void *lam, void *ubar, hipStream_t stream) {
+  const sbp_physics &ph = M->phys;
   if (M->eform || ph.form == SBP_FORM_HADAMARD) {
     // Hadamard form, or the hybrid scheme: each form's kernel takes the
     // elements flagged with it (both kernels for every class)
@@ -1204,6 +1230,10 @@ int sbp_residual_vjp(sbp_mesh *M, const void *u, const void *lam, void *ubar, vo
   }
   return SBP_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int sbp_diagnostics(sbp_mesh *M, const void *u, double *out_host, void *stream) {
   if (!M || !u || !out_host) return fail(SBP_EINVAL, "null argument");
@@ -1534,6 +1564,7 @@ int sbp_destroy_mesh(sbp_mesh *M) {
     (void)hipFree(c.d_ops);
     (void)hipFree(c.d_nbrq);
     (void)hipFree(c.d_q);
+    (void)hipFree(c.d_vq);
   }
   (void)hipFree(M->d_node_xyz);
   (void)hipFree(M->d_node_h);

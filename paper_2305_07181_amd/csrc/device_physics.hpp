@@ -431,6 +431,45 @@ __device__ __forceinline__ void viscous_flux(const Node<D, T> &n, const GasC<T> 
   }
 }
 
+// gbar_j = sum_i K~_ij^T z_i for j = 0..D-1: the adjoint of viscous_flux
+// with respect to its gradient argument (F^V(i) = sum_j K~_ij dW/dx_j) for
+// cotangents z_i of F^V(i).  Reverse sweep of viscous_flux:
+//   tbar_ik = z_i,V_k + z_i,E V_k,  Tbar_i = kappa z_i,E,
+//   dVbar_ji = mu (tbar_ij + tbar_ji) - 2/3 mu delta_ij sum_k tbar_kk,
+//   gbar_j,V_m = -dVbar_jm / W_nc,  gbar_j,E = -sum_m V_m dVbar_jm / W_nc,
+//   gbar_j += (dT/dW) Tbar_j / R.
+template <int D, typename T>
+__device__ __forceinline__ void viscous_flux_adjoint(const Node<D, T> &n, const GasC<T> &G, const ViscC<T> &Vc,
+                                                     const T z[D][D + 2], T gbar[D][D + 2]) {
+  constexpr int NC = D + 2;
+  const T iWn = (T)1 / n.w[NC - 1];
+  T dth[NC];
+  dtheta_dW<D, T>(n, G, dth);
+  T tb[D][D];
+  T tr = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) tb[i][k] = z[i][1 + k] + z[i][NC - 1] * n.V[k];
+#pragma unroll
+  for (int i = 0; i < D; ++i) tr += tb[i][i];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    T dvb[D];
+    T s = 0;
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+      dvb[m] = Vc.mu * (tb[j][m] + tb[m][j] - (m == j ? (T)(2.0 / 3.0) * tr : (T)0));
+      s += n.V[m] * dvb[m];
+    }
+    const T be = Vc.kappa * z[j][NC - 1] / Vc.R;
+    gbar[j][0] = be * dth[0];
+#pragma unroll
+    for (int m = 0; m < D; ++m) gbar[j][1 + m] = -dvb[m] * iWn + be * dth[1 + m];
+    gbar[j][NC - 1] = -s * iWn + be * dth[NC - 1];
+  }
+}
+
 // y_j = sum_i K~_ij^T (a_i dw) for j = 0..D-1, where K~_ij g is the viscous
 // flux F^V(i) produced by the gradient dW/dx_j = g alone.  With
 // vt = dw_V + dw_E V and the gradient maps dV/dW, dT/dW:

@@ -50,6 +50,11 @@ int vjp_variants(int dim, int p);
 hipError_t launch_vjp_hadamard(int dim, int p, const KArgs<double> &A, hipStream_t s);
 // 2D, every degree class in one persistent launch (cls[p-1] or null)
 hipError_t launch_vjp2_batch(const KArgs<double> *const cls[4], hipStream_t s, int grid = 1);
+// VJP of the Navier-Stokes terms, added to A.ubar (after the Euler terms'
+// VJP): a pre-pass writes s = B n . F^V(w, D_x mu) and mu = H^-1 lambda at
+// every facet node into sbuf ([n_elem][NFAC*NF][2 n_c] doubles), then the
+// main kernel reads both sides' values
+hipError_t launch_vjp_viscous(int dim, int p, const KArgs<double> &A, double *sbuf, hipStream_t s);
 
 // Per-node pointwise work over one degree class.
 struct NodeArgs {

@@ -893,6 +893,387 @@ const void *vjp3c_kernel(int p, int variant, int &eb) {
   return nullptr;
 }
 
+// ---------------------------------------------------------------------------
+// VJP of the Navier-Stokes terms (Sec. 5, eqs. sats visc, bo sats), added to
+// the VJP of the Euler terms.  With mu = H^-1 lambda, Q_xi = K_i + a_i/2 the
+// metric-averaged physical operators and y'_i = -1/2 H^-1 y_i, the viscous
+// part of lambda^T r is
+//   sum_i (Q_xi^T mu)^T F^V(i)(w, g)            g_j = D_xj w
+//   - 1/2 sum_facet (w_k - w_v)^T s,            s = a . F^V(w, nu), nu_i = D_xi mu
+//   - 1/2 sum_facet mu^T (q_k + q_v),           q = a . F^V(w, g) of each side
+// (F^V(i) = sum_j K~_ij g_j is linear in the gradient; a_i = B n_i).  Its
+// derivative: the cotangent of F^V(i) at a node is alpha_i = Q_xi^T mu plus,
+// at facet nodes, a_i qbar with qbar = -1/2 (mu_k + mu_v) (each side's q
+// enters both residuals); through the gradient, sum_j D_xj^T gbar_j with
+// gbar_j = sum_i K~_ij^T alpha_i (viscous_flux_adjoint); through the node
+// state at fixed gradients, dual numbers (the Hessian-vector terms, with the
+// facet weight -1/2 a_i (w_k - w_v) on F^V(w, nu)); and through the jump
+// w_k - w_v, -1/2 s_k + 1/2 s_v at the facet node.  nu is a function of
+// lambda alone.  A pre-pass writes s and mu at every facet node so that each
+// side reads the other's.
+//
+// Metrics per node, GM: 0 triangles (quadratic or affine map, 12 map-node
+// coordinates), 1 affine tetrahedra (Lambda and J per element), 2
+// tetrahedra with quadratic maps (30 map-node coordinates).  Every operator
+// application is a metric-averaged node-pair sum over the reference skew
+// operators (c_k(i, j) = sum_l S_l[i][j] (Lambda_kl(i) + Lambda_kl(j)),
+// K_k at row i = 1/2 sum_j c_k(i, j)); one lane per node row.
+
+template <int D, int NP, int GM>
+__device__ __forceinline__ void vnode_metrics(const KArgs<double> &A, int eg, int i, double L[D][D], double &J) {
+  if constexpr (GM == 0) {
+    const double *g = A.geo + (size_t)eg * 12;
+    double F[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      const double d0 = A.op.dN[(0 * 6 + a) * NP + i], d1 = A.op.dN[(1 * 6 + a) * NP + i];
+      F[0][0] += d0 * g[2 * a];
+      F[0][1] += d1 * g[2 * a];
+      F[1][0] += d0 * g[2 * a + 1];
+      F[1][1] += d1 * g[2 * a + 1];
+    }
+    L[0][0] = F[1][1];
+    L[0][1] = -F[1][0];
+    L[D - 1][0] = -F[0][1];
+    L[D - 1][D - 1] = F[0][0];
+    J = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  } else if constexpr (GM == 1) {
+    const double *g = A.geo + (size_t)eg * 10;
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+      for (int l = 0; l < D; ++l) L[k][l] = g[k * 3 + l];
+    J = g[9];
+  } else {
+    const double *g = A.geo + (size_t)eg * 30;
+    double F[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) F[k][l] = 0.0;
+#pragma unroll
+    for (int a = 0; a < 10; ++a)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        const double d = A.op.dN[(l * 10 + a) * NP + i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) F[k][l] += d * g[a * 3 + k];
+      }
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+      for (int l = 0; l < D; ++l) {
+        const int k1 = (k + 1) % 3, k2 = (k + 2) % 3, l1 = (l + 1) % 3, l2 = (l + 2) % 3;
+        L[k][l] = F[k1][l1] * F[k2][l2] - F[k1][l2] * F[k2][l1];
+      }
+    J = F[0][0] * L[0][0] + F[0][1] * L[0][1] + F[0][2] * L[0][D - 1];
+  }
+}
+
+// c_k(i, j) for k < D from the skew operators (read transposed through the
+// caches: S is stored exactly skew) and the metrics of rows i and j.
+template <int D, int NP>
+__device__ __forceinline__ void vpair_coef(const KArgs<double> &A, int i, int j, const double L[D][D],
+                                           const double *Lj, double c[D]) {
+  double sl[D];
+#pragma unroll
+  for (int l = 0; l < D; ++l) sl[l] = -A.op.S[(l * NP + j) * NP + i];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    double t = 0.0;
+#pragma unroll
+    for (int l = 0; l < D; ++l) t += sl[l] * (L[k][l] + Lj[k * D + l]);
+    c[k] = t;
+  }
+}
+
+template <int D, int P, int GM>
+__global__ __launch_bounds__(kT) void k_vjpv_pre(KArgs<double> A, double *sb) {
+  constexpr int NC = D + 2, NFAC = D + 1;
+  constexpr int NP = Shape<D, P>::NP, NF = Shape<D, P>::NF, NFN = NFAC * NF;
+  constexpr int EB = kT / NP;
+  constexpr int NV = NC + D * D + 1;  // mu, Lambda (odd stride in 3D)
+  __shared__ double nd[EB * NP * NV];
+  const int tid = threadIdx.x;
+  const int e = tid / NP, i = tid % NP;
+  const ViscC<double> Vc = A.V;
+  const int ntiles = (A.n_elem + EB - 1) / EB;
+  for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    const int e0 = tl * EB;
+    const int ne = min(EB, A.n_elem - e0);
+    const int eg = e0 + e;
+    const bool act = e < ne;
+    double L[D][D], J = 1.0, H = 1.0, mu[NC];
+    Node<D, double> n;
+    __syncthreads();
+    if (act) {
+      vnode_metrics<D, NP, GM>(A, eg, i, L, J);
+      H = J * A.op.h[i];
+      const int uo = A.uoff[eg];
+      double uu[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        uu[c] = A.u[uo + c * NP + i];
+        mu[c] = A.lam[uo + c * NP + i] / H;
+      }
+      node_from_u<D, double>(uu, A.G, n);
+      double *v = nd + (e * NP + i) * NV;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[c] = mu[c];
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int l = 0; l < D; ++l) v[NC + k * D + l] = L[k][l];
+    }
+    __syncthreads();
+    if (act && i < NFN) {
+      double X[D][NC];
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) X[k][c] = 0.0;
+#pragma unroll 1
+      for (int j = 0; j < NP; ++j) {
+        const double *v = nd + (e * NP + j) * NV;
+        double ck[D];
+        vpair_coef<D, NP>(A, i, j, L, v + NC, ck);
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) X[k][c] += ck[k] * v[c];
+      }
+      double a[D], nu[D][NC], FV[D][NC];
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int l = 0; l < D; ++l) t += L[k][l] * A.op.E[l * NP + i];
+        a[k] = t;
+      }
+      const double iH = 1.0 / H;
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) nu[k][c] = 0.5 * iH * (X[k][c] + a[k] * mu[c]);
+      viscous_flux<D, double>(n, A.G, Vc, nu, FV);
+      double *o = sb + ((size_t)eg * NFN + i) * 2 * NC;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) t += a[k] * FV[k][c];
+        o[c] = t;
+        o[NC + c] = mu[c];
+      }
+    }
+  }
+}
+
+template <int D, int P, int GM>
+__global__ __launch_bounds__(kT) void k_vjpv(KArgs<double> A, const double *sb) {
+  constexpr int NC = D + 2, NFAC = D + 1;
+  constexpr int NP = Shape<D, P>::NP, NF = Shape<D, P>::NF, NFN = NFAC * NF;
+  constexpr int EB = kT / NP;
+  // per node: w, mu, Lambda, z_1..z_D (z = H^-1 gbar)
+  constexpr int OW = 0, OM = NC, OL = 2 * NC, OZ = 2 * NC + D * D;
+  constexpr int NV = OZ + D * NC + 1;
+  __shared__ double nd[EB * NP * NV];
+  const int tid = threadIdx.x;
+  const int e = tid / NP, i = tid % NP;
+  const GasC<double> &G = A.G;
+  const GasC<Dual<double>> GD = dual_gas(G);
+  const ViscC<double> Vc = A.V;
+  ViscC<Dual<double>> VD;
+  VD.mu = Vc.mu;
+  VD.kappa = Vc.kappa;
+  VD.R = Vc.R;
+  const int ntiles = (A.n_elem + EB - 1) / EB;
+  for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    const int e0 = tl * EB;
+    const int ne = min(EB, A.n_elem - e0);
+    const int eg = e0 + e;
+    const bool act = e < ne;
+    double L[D][D], J = 1.0, H = 1.0, uu[NC], mu[NC];
+    Node<D, double> n;
+    __syncthreads();
+    if (act) {
+      vnode_metrics<D, NP, GM>(A, eg, i, L, J);
+      H = J * A.op.h[i];
+      const int uo = A.uoff[eg];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        uu[c] = A.u[uo + c * NP + i];
+        mu[c] = A.lam[uo + c * NP + i] / H;
+      }
+      node_from_u<D, double>(uu, G, n);
+      double *v = nd + (e * NP + i) * NV;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        v[OW + c] = n.w[c];
+        v[OM + c] = mu[c];
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int l = 0; l < D; ++l) v[OL + k * D + l] = L[k][l];
+    }
+    __syncthreads();
+    double z[D][NC], wl[NC], ud[NC], a[D];
+    if (act) {
+      double Xw[D][NC], Xm[D][NC];
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Xw[k][c] = Xm[k][c] = 0.0;
+#pragma unroll 1
+      for (int j = 0; j < NP; ++j) {
+        const double *v = nd + (e * NP + j) * NV;
+        double ck[D];
+        vpair_coef<D, NP>(A, i, j, L, v + OL, ck);
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            Xw[k][c] += ck[k] * v[OW + c];
+            Xm[k][c] += ck[k] * v[OM + c];
+          }
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int l = 0; l < D; ++l) t += L[k][l] * A.op.E[l * NP + i];
+        a[k] = t;
+      }
+      const double iH = 1.0 / H;
+      double g[D][NC], al[D][NC], nu[D][NC], ze[D][NC];
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          g[k][c] = 0.5 * iH * (Xw[k][c] + a[k] * n.w[c]);
+          al[k][c] = 0.5 * (a[k] * mu[c] - Xm[k][c]);
+          nu[k][c] = 0.5 * iH * (Xm[k][c] + a[k] * mu[c]);
+          ze[k][c] = 0.0;
+        }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) wl[c] = 0.0;
+      const bool fac = i < NFN;
+      if (fac) {
+        const size_t fi = (size_t)eg * NFN + i;
+        const int off = A.nbr[fi];
+        double uv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) uv[c] = A.u[off + c * NP];
+        Node<D, double> nv;
+        node_from_u<D, double>(uv, G, nv);
+        const double *sv = sb + (size_t)A.nbrq[fi] * 2 * NC;
+        const double *sk = sb + fi * 2 * NC;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const double qb = -0.5 * (mu[c] + sv[NC + c]);
+          const double dw = n.w[c] - nv.w[c];
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            al[k][c] += a[k] * qb;
+            ze[k][c] = -0.5 * a[k] * dw;
+          }
+          wl[c] = 0.5 * (sv[c] - sk[c]);
+        }
+      }
+      double gb[D][NC];
+      viscous_flux_adjoint<D, double>(n, G, Vc, al, gb);
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) z[k][c] = iH * gb[k][c];
+      // state derivative at fixed gradients (dual numbers, one pass per
+      // component of u): alpha_i . F^V(i)(u; g) + facet -1/2 a_i dw . F^V(i)(u; nu)
+#pragma unroll 1
+      for (int q = 0; q < NC; ++q) {
+        Dual<double> x[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[c] = Dual<double>(uu[c], c == q ? 1.0 : 0.0);
+        Node<D, Dual<double>> nq;
+        node_from_u<D, Dual<double>>(x, GD, nq);
+        Dual<double> gq[D][NC], F[D][NC];
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) gq[k][c] = Dual<double>(g[k][c]);
+        viscous_flux<D, Dual<double>>(nq, GD, VD, gq, F);
+        double dphi = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) dphi += al[k][c] * F[k][c].d;
+        if (fac) {
+#pragma unroll
+          for (int k = 0; k < D; ++k)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) gq[k][c] = Dual<double>(nu[k][c]);
+          viscous_flux<D, Dual<double>>(nq, GD, VD, gq, F);
+#pragma unroll
+          for (int k = 0; k < D; ++k)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) dphi += ze[k][c] * F[k][c].d;
+        }
+        ud[q] = dphi;
+      }
+      double *v = nd + (e * NP + i) * NV;
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[OZ + k * NC + c] = z[k][c];
+    }
+    __syncthreads();
+    if (act) {
+      // sum_j D_xj^T gbar_j = sum_j Q_xj^T z_j = -1/2 sum_n c_j(i, n) z_j,n + 1/2 sum_j a_j z_j,i
+      double T[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) t += a[k] * z[k][c];
+        T[c] = 0.5 * t;
+      }
+#pragma unroll 1
+      for (int j = 0; j < NP; ++j) {
+        const double *v = nd + (e * NP + j) * NV;
+        double ck[D];
+        vpair_coef<D, NP>(A, i, j, L, v + OL, ck);
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) T[c] -= 0.5 * ck[k] * v[OZ + k * NC + c];
+      }
+      double wb[NC], du[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) wb[c] = T[c] + wl[c];
+      dWdU_apply<D>(uu, wb, GD, du);
+      const int uo = A.uoff[eg];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) A.ubar[uo + c * NP + i] += du[c] + ud[c];
+    }
+  }
+}
+
+template <int D, int P, int GM>
+hipError_t launch_vjpv_t(const KArgs<double> &A, double *sb, hipStream_t s) {
+  constexpr int EB = kT / Shape<D, P>::NP;
+  const int ntiles = (A.n_elem + EB - 1) / EB;
+  const void *f0 = reinterpret_cast<const void *>(&k_vjpv_pre<D, P, GM>);
+  const void *f1 = reinterpret_cast<const void *>(&k_vjpv<D, P, GM>);
+  KArgs<double> a = A;
+  double *sp = sb;
+  const double *cs = sb;
+  void *args0[] = {&a, &sp};
+  hipError_t e = hipLaunchKernel(f0, dim3(launch_grid(f0, ntiles, 1)), dim3(kT), args0, 0, s);
+  if (e != hipSuccess) return e;
+  void *args1[] = {&a, &cs};
+  return hipLaunchKernel(f1, dim3(launch_grid(f1, ntiles, 1)), dim3(kT), args1, 0, s);
+}
+
 }  // namespace
 
 hipError_t launch_vjp_hadamard(int dim, int p, const KArgs<double> &A, hipStream_t s) {
@@ -924,6 +1305,32 @@ hipError_t launch_vjp(int dim, int p, const KArgs<double> &A, hipStream_t s, Lau
   KArgs<double> a = A;
   void *args[] = {&a};
   return hipLaunchKernel(fn, dim3(nb), dim3(kT), args, 0, s);
+}
+
+hipError_t launch_vjp_viscous(int dim, int p, const KArgs<double> &A, double *sbuf, hipStream_t s) {
+  if (A.n_elem <= 0) return hipSuccess;
+  if (dim == 2) {
+    switch (p) {
+      case 1: return launch_vjpv_t<2, 1, 0>(A, sbuf, s);
+      case 2: return launch_vjpv_t<2, 2, 0>(A, sbuf, s);
+      case 3: return launch_vjpv_t<2, 3, 0>(A, sbuf, s);
+      case 4: return launch_vjpv_t<2, 4, 0>(A, sbuf, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (A.curved) {
+    switch (p) {
+      case 2: return launch_vjpv_t<3, 2, 2>(A, sbuf, s);
+      case 3: return launch_vjpv_t<3, 3, 2>(A, sbuf, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (p) {
+    case 1: return launch_vjpv_t<3, 1, 1>(A, sbuf, s);
+    case 2: return launch_vjpv_t<3, 2, 1>(A, sbuf, s);
+    case 3: return launch_vjpv_t<3, 3, 1>(A, sbuf, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace sbp
