@@ -51,6 +51,7 @@ struct DegreeClass {
   int p = 0, np = 0, nf = 0, n_elem = 0;
   std::vector<int> elems;  // global element ids
   int *d_uoff = nullptr;
+  int u_dense = 0, u_base = 0;  // d_uoff[k] == u_base + k n_c n_p for every k
   int *d_gid = nullptr;   // mesh element id of each element of the class
   double *d_geo = nullptr;
   int *d_nbr = nullptr;
@@ -92,6 +93,11 @@ struct sbp_mesh {
   double *d_npart = nullptr;  // node-kernel partials [(n_c+2) x node_total]
   int node_total = 0;
   double *d_scal = nullptr;   // device scalars
+  void *d_eac = nullptr;      // exponential-average constants [2] per precision (FP64 then FP32)
+  // 2D meshes of several degrees: the argument blocks of the degree classes
+  // ([4] by degree, static fields) for the batched launches
+  sbp::KArgs<double> *d_bcls64 = nullptr;
+  sbp::KArgs<float> *d_bcls32 = nullptr;
   int *d_err = nullptr;
   double *d_y = nullptr, *d_d = nullptr;
   void *d_r = nullptr;        // RK stage residual
@@ -121,6 +127,11 @@ int form_eff_of(const sbp_mesh *M) {
   if (M->phys.viscous) return M->curved3 ? 5 : 2;
   return curved_eff(M, M->phys.form);
 }
+
+// device table of the pointwise constants read at their use: per precision
+// (FP64 at 0, FP32 at kEacPrec) the exponential-average constants, then at
+// kEacJump the binomial coefficients of the node powers
+constexpr size_t kEacPrec = 1024, kEacJump = 512;
 
 constexpr int SC_ENT = 0;     // 4 stage entropy rates
 constexpr int SC_RED = 8;     // reduction outputs (up to 8)
@@ -243,6 +254,9 @@ sbp::OpTables<T> tables_at(const T *base, const size_t off[11], int dim) {
 }
 
 void apply_tuned(sbp_mesh *M);
+
+template <typename T>
+sbp::KArgs<T> kargs(sbp_mesh *M, DegreeClass &c, const double *u, void *r, const sbp::OpTables<T> &op);
 
 int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp_mesh *M) {
   const int dim = D->dim;
@@ -482,6 +496,10 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
       }
     }
     int rc;
+    c.u_base = uoff.empty() ? 0 : uoff[0];
+    c.u_dense = 1;
+    for (int k = 0; k < c.n_elem; ++k)
+      if (uoff[k] != c.u_base + k * M->nc * np) c.u_dense = 0;
     if ((rc = upload(c.d_uoff, uoff, s))) return rc;
     if ((rc = upload(c.d_gid, c.elems, s))) return rc;
     if ((rc = upload(c.d_geo, geo, s))) return rc;
@@ -537,10 +555,35 @@ int setup_impl(const sbp_mesh_desc *D, const sbp_physics *ph, hipStream_t s, sbp
   if ((rc = upload(M->d_node_h, Hn, s))) return rc;
   HIPCHK(hipMalloc((void **)&M->d_part, sizeof(double) * std::max(1, part_total)));
   HIPCHK(hipMalloc((void **)&M->d_npart, sizeof(double) * (M->nc + 2) * std::max(1, node_total)));
+  {
+    const sbp::GasC<double> g64 = sbp::make_gas<double>(ph->gamma, ph->beta);
+    const sbp::GasC<float> g32 = sbp::make_gas<float>(ph->gamma, ph->beta);
+    const sbp::ExpAvgC<double> e64[2] = {g64.e1, g64.e2};
+    const sbp::ExpAvgC<float> e32[2] = {g32.e1, g32.e2};
+    const sbp::JumpC<double> j64 = sbp::make_jump<double>(ph->gamma, ph->beta);
+    const sbp::JumpC<float> j32 = sbp::make_jump<float>(ph->gamma, ph->beta);
+    static_assert(sizeof(e64) <= kEacJump && sizeof(j64) <= kEacPrec - kEacJump, "constant table layout");
+    HIPCHK(hipMalloc(&M->d_eac, 2 * kEacPrec));
+    char *base = (char *)M->d_eac;
+    HIPCHK(hipMemcpy(base, e64, sizeof(e64), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(base + kEacJump, &j64, sizeof(j64), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(base + kEacPrec, e32, sizeof(e32), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(base + kEacPrec + kEacJump, &j32, sizeof(j32), hipMemcpyHostToDevice));
+  }
   HIPCHK(hipMalloc((void **)&M->d_scal, sizeof(double) * SC_TOTAL));
   HIPCHK(hipMemsetAsync(M->d_scal, 0, sizeof(double) * SC_TOTAL, s));
   HIPCHK(hipMalloc((void **)&M->d_err, sizeof(int)));
   HIPCHK(hipMemsetAsync(M->d_err, 0, sizeof(int), s));
+  if (M->batch_blocks > 0 || (dim == 2 && M->cls.size() > 1)) {
+    std::vector<sbp::KArgs<double>> b64(4);
+    std::vector<sbp::KArgs<float>> b32(4);
+    for (auto &c : M->cls) {
+      b64[c.p - 1] = kargs<double>(M, c, nullptr, nullptr, c.op64);
+      b32[c.p - 1] = kargs<float>(M, c, nullptr, nullptr, c.op32);
+    }
+    if ((rc = upload(M->d_bcls64, b64, s))) return rc;
+    if ((rc = upload(M->d_bcls32, b32, s))) return rc;
+  }
   HIPCHK(hipStreamSynchronize(s));
   apply_tuned(M);
   return SBP_OK;
@@ -572,11 +615,17 @@ sbp::KArgs<T> kargs(sbp_mesh *M, DegreeClass &c, const double *u, void *r, const
   A.geo = c.d_geo;
   A.nbr = c.d_nbr;
   A.uoff = c.d_uoff;
+  A.u_dense = c.u_dense;
+  A.u_base = c.u_base;
   A.gid = c.d_gid;
+  A.Hn = c.d_Hn;
   A.n_elem = c.n_elem;
   A.diss = ph.dissipation;
   A.op = op;
   A.G = sbp::make_gas<T>(ph.gamma, ph.beta);
+  const char *eac = (const char *)M->d_eac + (sizeof(T) == 8 ? 0 : kEacPrec);
+  A.eac = (const sbp::ExpAvgC<T> *)eac;
+  A.jc = (const sbp::JumpC<T> *)(eac + kEacJump);
   A.ent_part = M->d_part + c.part_off;
   A.err = M->d_err;
   A.visc = ph.viscous;
@@ -662,9 +711,9 @@ int residual_core(sbp_mesh *M, const Work &W, const double *u, void *r, double *
       }
     }
     if (ph.precision == SBP_FP64)
-      HIPCHK(sbp::launch_residual2_batch(p64, W.part, s, M->batch_grid));
+      HIPCHK(sbp::launch_residual2_batch(p64, M->d_bcls64, W.part, s, M->batch_grid));
     else
-      HIPCHK(sbp::launch_residual2_batch(p32, W.part, s, M->batch_grid));
+      HIPCHK(sbp::launch_residual2_batch(p32, M->d_bcls32, W.part, s, M->batch_grid));
     if (hyb)
       for (auto &c : M->cls)
         if ((rc = other_launch(c))) return rc;
@@ -982,8 +1031,8 @@ int autotune_impl(sbp_mesh *M, const double *u, const double *lam, sbp_tune_repo
     }
     sbp::LaunchCfg cfg{0, M->batch_grid};
     auto run = [&](sbp::LaunchCfg k) {
-      return f32 ? sbp::launch_residual2_batch(p32, M->d_part, s, k.grid)
-                 : sbp::launch_residual2_batch(p64, M->d_part, s, k.grid);
+      return f32 ? sbp::launch_residual2_batch(p32, M->d_bcls32, M->d_part, s, k.grid)
+                 : sbp::launch_residual2_batch(p64, M->d_bcls64, M->d_part, s, k.grid);
     };
     if ((rc = tune_slot(1, run, s, cfg, next_slot(TUNE_RES, 0)))) return rc;
     M->batch_grid = cfg.grid;
@@ -1018,7 +1067,7 @@ int autotune_impl(sbp_mesh *M, const double *u, const double *lam, sbp_tune_repo
         pa[c.p - 1] = &a[c.p - 1];
       }
       sbp::LaunchCfg cfg{0, M->vjp_batch_grid};
-      auto run = [&](sbp::LaunchCfg k) { return sbp::launch_vjp2_batch(pa, s, k.grid); };
+      auto run = [&](sbp::LaunchCfg k) { return sbp::launch_vjp2_batch(pa, M->d_bcls64, s, k.grid); };
       if ((rc = tune_slot(1, run, s, cfg, next_slot(TUNE_VJP, 0)))) return rc;
       M->vjp_batch_grid = cfg.grid;
       tune_store(tune_key(M, TUNE_VJP, 0, M->n_elem), cfg);
@@ -1218,7 +1267,7 @@ int vjp_euler(sbp_mesh *M, const void *u, const void *lam, void *ubar, hipStream
       A.Hn = c.d_Hn;
       pa[c.p - 1] = &A;
     }
-    HIPCHK(sbp::launch_vjp2_batch(pa, (hipStream_t)stream, M->vjp_batch_grid));
+    HIPCHK(sbp::launch_vjp2_batch(pa, M->d_bcls64, (hipStream_t)stream, M->vjp_batch_grid));
     return SBP_OK;
   }
   for (auto &c : M->cls) {
@@ -1571,6 +1620,9 @@ int sbp_destroy_mesh(sbp_mesh *M) {
   (void)hipFree(M->d_part);
   (void)hipFree(M->d_npart);
   (void)hipFree(M->d_scal);
+  (void)hipFree(M->d_eac);
+  (void)hipFree(M->d_bcls64);
+  (void)hipFree(M->d_bcls32);
   (void)hipFree(M->d_err);
   (void)hipFree(M->d_y);
   (void)hipFree(M->d_d);

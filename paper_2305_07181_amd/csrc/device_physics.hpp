@@ -95,6 +95,7 @@ __device__ __forceinline__ float dabs(float x) { return fabsf(x); }
 template <int D, typename T>
 struct Node {
   T rho, V[D], p;
+  T irho;       // 1/rho
   T lrho, lp, lz1;  // logarithms of rho, p, z1
   T z1;         // (rho/p)(p rho^-gamma)^(1/(alpha+gamma)) = -W_nc
   T P1, P2;     // z1^r1, p^r2 (powers entering the two-point flux averages)
@@ -107,6 +108,7 @@ __device__ __forceinline__ void node_from_u(const T *u, const GasC<T> &G, Node<D
   n.rho = u[0];
   T q2 = 0;
   T irho = (T)1 / n.rho;
+  n.irho = irho;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
     n.V[i] = u[1 + i] * irho;
@@ -125,6 +127,86 @@ __device__ __forceinline__ void node_from_u(const T *u, const GasC<T> &G, Node<D
 #pragma unroll
   for (int i = 0; i < D; ++i) n.w[1 + i] = n.z1 * n.V[i];
   n.w[D + 1] = -n.z1;
+}
+
+// Binomial coefficients C(e, k), k = 1..9, of (1 + x)^e for the exponents of
+// the node powers: z1 = rho^ea p^eb (ln z1 = ea ln rho + eb ln p), z1^r1,
+// p^r2.  Used to carry a node's powers over to a nearby state.
+template <typename T>
+struct JumpC {
+  T ea[9], eb[9], r1[9], r2[9];
+};
+
+template <typename T>
+__host__ JumpC<T> make_jump(double gamma, double beta) {
+  const double alpha = -gamma - beta * (gamma - 1.0);
+  const double inv_apg = 1.0 / (alpha + gamma);
+  const double ex[4] = {1.0 - gamma * inv_apg, inv_apg - 1.0, -gamma / alpha, (1.0 - gamma) / alpha};
+  JumpC<T> J;
+  T *dst[4] = {J.ea, J.eb, J.r1, J.r2};
+  for (int q = 0; q < 4; ++q) {
+    double c = 1.0;
+    for (int k = 1; k <= 9; ++k) {
+      c *= (ex[q] - (k - 1)) / k;
+      dst[q][k - 1] = (T)c;
+    }
+  }
+  return J;
+}
+
+// (1 + x)^e by its binomial series to degree 9 (coefficients C(e, 1..9)).
+template <typename T>
+__device__ __forceinline__ T binom9(const T *C, T x) {
+  T t = C[8];
+#pragma unroll
+  for (int k = 7; k >= 0; --k) t = C[k] + x * t;
+  return (T)1 + x * t;
+}
+
+// Largest |rho_v/rho_k - 1| and |p_v/p_k - 1| for which node_near carries
+// the powers over by series: the ratio of the z1 values then stays within
+// about 0.022 (FP64) or 0.22 (FP32) of 1, where the degree-9 remainders are
+// ~1e-19 and ~1e-9 of the value.
+template <typename T>
+__device__ __forceinline__ constexpr T near_max() {
+  return sizeof(T) == 4 ? (T)0.05 : (T)0.005;
+}
+
+// The node state of conservative values u for the two-point flux (primitives,
+// z1, z1^r1, p^r2, w; the logarithms are not set) when u is close to the
+// node k with powers: z1 = z1_k (1 + dr)^ea (1 + dp)^eb, z1^r1 = z1_k^r1
+// (z1 / z1_k)^r1, p^r2 = p_k^r2 (1 + dp)^r2 with dr = rho/rho_k - 1,
+// dp = p/p_k - 1 -- no transcendental function.  irho_k = 1/rho_k,
+// ip_k = 1/p_k.  Returns false, leaving the powers unset, when a ratio is
+// outside the series' range (the caller then takes node_from_u and
+// node_powers).
+template <int D, typename T>
+__device__ __forceinline__ bool node_near(const T *u, const Node<D, T> &k, T irho_k, T ip_k, const GasC<T> &G,
+                                          const JumpC<T> &Jc, Node<D, T> &n) {
+  n.rho = u[0];
+  T q2 = 0;
+  const T irho = (T)1 / n.rho;
+  n.irho = irho;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    n.V[i] = u[1 + i] * irho;
+    q2 += n.V[i] * n.V[i];
+  }
+  n.p = G.gm1 * (u[D + 1] - (T)0.5 * n.rho * q2);
+  n.ok = (n.rho > (T)0) && (n.p > (T)0) && (n.rho < (T)1e300) && (n.p < (T)1e300);
+  const T dr = n.rho * irho_k - (T)1, dp = n.p * ip_k - (T)1;
+  if (!(dabs(dr) <= near_max<T>() && dabs(dp) <= near_max<T>())) return false;
+  const T zr = binom9(Jc.ea, dr) * binom9(Jc.eb, dp);
+  n.lrho = n.lp = n.lz1 = (T)0;
+  n.z1 = k.z1 * zr;
+  n.P1 = k.P1 * binom9(Jc.r1, zr - (T)1);
+  n.P2 = k.P2 * binom9(Jc.r2, dp);
+  const T theta = n.p * irho;
+  n.w[0] = n.z1 * (G.wfirst * theta - (T)0.5 * q2);
+#pragma unroll
+  for (int i = 0; i < D; ++i) n.w[1 + i] = n.z1 * n.V[i];
+  n.w[D + 1] = -n.z1;
+  return true;
 }
 
 // z1^r1 and p^r2, needed only by the two-point flux at facet nodes and in the
@@ -271,13 +353,14 @@ __device__ __forceinline__ T exp_avg(T a, T b, T ar, T br, const ExpAvgC<T> &C) 
 //   out = a . F*(u_k, u_v)  [+ 1/2 |a| X|Lambda|S X^T (w_k - w_v)]
 // The residual receives -out / H_m.
 template <int D, typename T>
-__device__ __forceinline__ void facet_term(const Node<D, T> &k, const Node<D, T> &v, const T *a,
-                                           const GasC<T> &G, bool diss, T *out, T ip_k = (T)0, T iz1_k = (T)0) {
+__device__ __forceinline__ void facet_term_c(const Node<D, T> &k, const Node<D, T> &v, const T *a,
+                                             const GasC<T> &G, const ExpAvgC<T> &C1, const ExpAvgC<T> &C2,
+                                             bool diss, T *out, T ip_k, T iz1_k) {
   constexpr int NC = D + 2;
   const T P1k = k.P1, P1v = v.P1, P2k = k.P2, P2v = v.P2;
   // own-side reciprocals 1/p_k and 1/z1_k, if the caller has them
-  const T Ep = ip_k != (T)0 ? exp_avg_ia(k.p, v.p, P2k, P2v, ip_k, G.e2) : exp_avg(k.p, v.p, P2k, P2v, G.e2);
-  const T Ez = iz1_k != (T)0 ? exp_avg_ia(k.z1, v.z1, P1k, P1v, iz1_k, G.e1) : exp_avg(k.z1, v.z1, P1k, P1v, G.e1);
+  const T Ep = ip_k != (T)0 ? exp_avg_ia(k.p, v.p, P2k, P2v, ip_k, C2) : exp_avg(k.p, v.p, P2k, P2v, C2);
+  const T Ez = iz1_k != (T)0 ? exp_avg_ia(k.z1, v.z1, P1k, P1v, iz1_k, C1) : exp_avg(k.z1, v.z1, P1k, P1v, C1);
   const T Dn = (T)0.5 * (P1k + P1v) * Ep;
   const T iD = (T)1 / Dn;
   T an = 0;  // a . {z1 V} / D
@@ -360,6 +443,13 @@ __device__ __forceinline__ void facet_term(const Node<D, T> &k, const Node<D, T>
   const T hb = (T)0.5 * B;
 #pragma unroll
   for (int c = 0; c < NC; ++c) out[c] += hb * y[c];
+}
+
+// The same with the exponential-average constants of the gas block.
+template <int D, typename T>
+__device__ __forceinline__ void facet_term(const Node<D, T> &k, const Node<D, T> &v, const T *a,
+                                           const GasC<T> &G, bool diss, T *out, T ip_k = (T)0, T iz1_k = (T)0) {
+  facet_term_c<D, T>(k, v, a, G, G.e1, G.e2, diss, out, ip_k, iz1_k);
 }
 
 // Harten entropy S = beta rho (p rho^-gamma)^(1/(alpha+gamma)) in FP64.

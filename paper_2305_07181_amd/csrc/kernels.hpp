@@ -39,6 +39,7 @@ struct KArgs {
                        // col l), J; 3D curved: [n_elem][10][3] quadratic map nodes
   const int *nbr;      // [n_elem][NFAC*NF] u offset of the matching neighbour node (component 0)
   const int *uoff;     // [n_elem] u offset of each element of the class
+  int u_dense, u_base; // u_dense: uoff[e] == u_base + e n_c n_p for every e (no lookup needed)
   int n_elem;
   int diss;
   OpTables<T> op;
@@ -62,6 +63,36 @@ struct KArgs {
   const unsigned char *eform;
   const int *gid;      // [n_elem] mesh element id of each element of the class
   int form_id;
+  // the exponential-average constants of G (G.e1, G.e2) in device memory:
+  // kernels that read them at their use instead of holding them in scalar
+  // registers for the whole launch
+  const ExpAvgC<T> *eac;
+  const JumpC<T> *jc;  // binomial coefficients of the node powers (node_near)
+};
+
+// Tile order of a persistent workgroup.  The chip dispatches workgroups to
+// its 8 XCDs (each with its own L2) round-robin by workgroup index, so
+// workgroup b runs on XCD b mod 8.  When the grid is a multiple of 8, each
+// XCD takes one contiguous eighth of the tiles: an element's facet
+// neighbours (nearby element indices on the structured grids) are then read
+// by the same XCD, from its L2, instead of from another XCD's memory.
+constexpr int kXcds = 8;
+struct TileSeq {
+  int t, step, end;
+  __device__ __forceinline__ explicit TileSeq(int ntiles) {
+    const int b = blockIdx.x, G = gridDim.x;
+    if (G % kXcds == 0) {
+      const int per = (ntiles + kXcds - 1) / kXcds;
+      const int x = b % kXcds;
+      t = x * per + b / kXcds;
+      step = G / kXcds;
+      end = min(ntiles, (x + 1) * per);
+    } else {
+      t = b;
+      step = G;
+      end = ntiles;
+    }
+  }
 };
 
 // Whether element e of the class runs in this kernel (hybrid scheme).  Any
@@ -82,14 +113,34 @@ __device__ __forceinline__ bool tile_on(const KArgs<T> &A, int e0, int ne) {
   return false;
 }
 
-// All degree classes of a 2D mesh in one launch: c[p-1] holds the arguments
-// of the class of degree p (n_elem = 0 if absent), g0[p-1] its first group in
-// the launch-wide group index, g0[4] the number of groups.
+// All degree classes of a 2D mesh in one launch: cls[p-1] (device memory,
+// written at mesh setup) holds the argument block of the class of degree p
+// (n_elem = 0 if absent) without the per-call pointers, which follow here;
+// g0[p-1] is the class's first group in the launch-wide group index, g0[4]
+// the number of groups.  Reading the blocks from memory where a tile needs
+// them keeps the four classes' arguments out of the scalar registers.
 template <typename T>
 struct Batch2 {
-  KArgs<T> c[4];
+  const KArgs<T> *cls;
+  const double *u;
+  T *r;
+  const unsigned char *eform;
+  const double *lam;
+  double *ubar;
   int g0[5];
   double *ent_part;  // [gridDim.x] partial sums of w^T H r (may be null)
 };
+
+// The argument block of class q of a batched launch with the call's pointers.
+template <typename T>
+__device__ __forceinline__ KArgs<T> batch_args(const Batch2<T> &Bt, int q) {
+  KArgs<T> A = Bt.cls[q];
+  A.u = Bt.u;
+  A.r = Bt.r;
+  A.eform = Bt.eform;
+  A.lam = Bt.lam;
+  A.ubar = Bt.ubar;
+  return A;
+}
 
 }  // namespace sbp

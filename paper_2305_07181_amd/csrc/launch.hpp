@@ -35,8 +35,12 @@ int residual_variants(int dim, int p, int precision, int form_eff);
 // 2D entropy split, every degree class in one persistent launch: cls[p-1] is
 // the class of degree p or null.  Workgroups of the launch (partial sums):
 int residual2_batch_blocks(const int n_elem_of_p[4], int precision, int grid = 1);
-hipError_t launch_residual2_batch(const KArgs<double> *const cls[4], double *ent_part, hipStream_t s, int grid = 1);
-hipError_t launch_residual2_batch(const KArgs<float> *const cls[4], double *ent_part, hipStream_t s, int grid = 1);
+// cls_dev: the classes' argument blocks in device memory ([4], by degree;
+// the per-call pointers u, r, eform are taken from cls)
+hipError_t launch_residual2_batch(const KArgs<double> *const cls[4], const KArgs<double> *cls_dev, double *ent_part,
+                                  hipStream_t s, int grid = 1);
+hipError_t launch_residual2_batch(const KArgs<float> *const cls[4], const KArgs<float> *cls_dev, double *ent_part,
+                                  hipStream_t s, int grid = 1);
 // Viscous facet-flux pre-pass (3D): A.qout[(e*NFAC*NF + m)*n_c + c] = B n . F^V
 hipError_t launch_visc_q(int dim, int p, const KArgs<double> &A, hipStream_t s);
 hipError_t launch_visc_q(int dim, int p, const KArgs<float> &A, hipStream_t s);
@@ -49,7 +53,8 @@ int vjp_variants(int dim, int p);
 // elements of the other form are skipped (hybrid scheme, A.eform/A.form_id)
 hipError_t launch_vjp_hadamard(int dim, int p, const KArgs<double> &A, hipStream_t s);
 // 2D, every degree class in one persistent launch (cls[p-1] or null)
-hipError_t launch_vjp2_batch(const KArgs<double> *const cls[4], hipStream_t s, int grid = 1);
+hipError_t launch_vjp2_batch(const KArgs<double> *const cls[4], const KArgs<double> *cls_dev, hipStream_t s,
+                             int grid = 1);
 // VJP of the Navier-Stokes terms, added to A.ubar (after the Euler terms'
 // VJP): a pre-pass writes s = B n . F^V(w, D_x mu) and mu = H^-1 lambda at
 // every facet node into sbuf ([n_elem][NFAC*NF][2 n_c] doubles), then the

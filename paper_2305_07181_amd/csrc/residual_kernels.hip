@@ -774,7 +774,7 @@ __global__ __launch_bounds__(kThreads) void k_visc_q3(KArgs<T> A) {
 // node.  Every lane re-reads the 16 values of node j for each pair; with
 // R = 2 each value read feeds two rows (half the LDS bytes per FMA, at two
 // waves per SIMD instead of three for R = 1).
-template <int P, typename T, int R, bool EF = false>
+template <int P, typename T, int R, int EF = 0>
 struct Split2 {
   static constexpr int D = 2, NC = 4, NFAC = 3;
   static constexpr int NP = Shape<2, P>::NP, NF = Shape<2, P>::NF;
@@ -907,12 +907,53 @@ struct Split2 {
   // loads at the start of the tile, so their latency overlaps the node work
   // instead of following the pair loop; only the facet term (n_c values per
   // row) and the node quantities of the combine stay live across the loop.
-  __device__ static __forceinline__ void tile_early(const KArgs<T> &A, Lds &L_, int tl, double &ent) {
+  // Neighbour data of one tile's facet rows, loaded ahead of the tile (EF 3):
+  // face-node offsets and the neighbour states.
+  struct Pref {
+    int t;
+    int nb[R];
+    T uv[R][NC];
+  };
+
+  // Face-node offsets of tile tl for this lane's rows (-1: not a facet row).
+  __device__ static __forceinline__ void pref_nb(const KArgs<T> &A, int tl, int nb[R]) {
+    constexpr int NFN = NFAC * NF;
+    const int e = threadIdx.x / L, k = threadIdx.x % L;
+    const int e0 = tl * EB;
+    const bool ok = tl >= 0 && e < min(EB, A.n_elem - e0);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int i = k + q * L;
+      nb[q] = (ok && i < NFN) ? A.nbr[(size_t)(e0 + e) * NFN + i] : -1;
+    }
+  }
+
+  __device__ static __forceinline__ void pref_uv(const KArgs<T> &A, Pref &pf) {
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) pf.uv[q][c] = pf.nb[q] >= 0 ? (T)A.u[pf.nb[q] + c * NP] : (T)0;
+  }
+
+  __device__ static __forceinline__ void tile_early(const KArgs<T> &A, Lds &L_, int tl, double &ent,
+                                                    Pref *pf = nullptr, int next = -1) {
     constexpr int NFN = NFAC * NF;
     const int tid = threadIdx.x;
     const int e0 = tl * EB;
     const int ne = min(EB, A.n_elem - e0);
-    if (!tile_on(A, e0, ne)) return;  // hybrid scheme: no element of this form
+    // EF 3: the next tile's face-node offsets now, its neighbour states
+    // during this tile's pair loop
+    int nbn[R];
+    if constexpr (EF == 3) pref_nb(A, next, nbn);
+    if (!tile_on(A, e0, ne)) {  // hybrid scheme: no element of this form
+      if constexpr (EF == 3) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) pf->nb[q] = nbn[q];
+        pref_uv(A, *pf);
+        pf->t = next;
+      }
+      return;
+    }
     const int e = tid / L, k = tid % L;
     const bool act = e < ne && elem_on(A, e0 + e);
     const T cb = A.G.cb;
@@ -923,21 +964,8 @@ struct Split2 {
     T iWn[R], ith[R], ipk[R];  // 1/W_nc = -1/z1, rho/p and 1/p of the row's node
     if (act) {
       const int eg = e0 + e;
-      const int uo = A.uoff[eg];
-      // loads first: own node states, neighbour offsets, then neighbour states
       T uu[R][NC], uv[R][NC];
       int nb[R];
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const int i = k + q * L;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) uu[q][c] = (T)A.u[uo + c * NP + i];
-        nb[q] = i < NFN ? A.nbr[(size_t)eg * NFN + i] : -1;
-      }
-#pragma unroll
-      for (int q = 0; q < R; ++q)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) uv[q][c] = nb[q] >= 0 ? (T)A.u[nb[q] + c * NP] : uu[q][c];
       const double *g = A.geo + (size_t)eg * 12;
 #pragma unroll
       for (int q = 0; q < R; ++q) {
@@ -956,6 +984,43 @@ struct Split2 {
         lam[q][1] = -F[1][0];  // Lambda_01
         lam[q][2] = -F[0][1];  // Lambda_10
         lam[q][3] = F[0][0];   // Lambda_11
+      }
+      if constexpr (EF == 2) {
+        // the state loads after the metric tables: the memory counter is
+        // waited on in issue order, so the metrics need not wait for them;
+        // the neighbour gathers go last (the node states need not wait for
+        // them either)
+        const int uo = A.u_dense ? A.u_base + eg * (NC * NP) : A.uoff[eg];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int i = k + q * L;
+          nb[q] = i < NFN ? A.nbr[(size_t)eg * NFN + i] : -1;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) uu[q][c] = (T)A.u[uo + c * NP + i];
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) uv[q][c] = nb[q] >= 0 ? (T)A.u[nb[q] + c * NP] : uu[q][c];
+      }
+      if constexpr (EF == 3) {
+        // the neighbour data came with the previous tile
+        const int uo = A.u_dense ? A.u_base + eg * (NC * NP) : A.uoff[eg];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int i = k + q * L;
+          nb[q] = pf->nb[q];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) uu[q][c] = (T)A.u[uo + c * NP + i];
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) uv[q][c] = nb[q] >= 0 ? pf->uv[q][c] : uu[q][c];
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int i = k + q * L;
         T f0[NC], f1[NC];
         node_from_u<D, T>(uu[q], A.G, n[q]);
         if (!n[q].ok) atomicOr(A.err, 1);
@@ -974,25 +1039,49 @@ struct Split2 {
 #pragma unroll
         for (int c = 0; c < 4; ++c) v[12 + c] = lam[q][c];
       }
+      {
+        // every row evaluates its facet term without branching on whether it
+        // is a facet node (interior rows pair with themselves and discard the
+        // result), stage by stage across the rows: the rows' transcendental
+        // chains are independent and interleave
+        Node<D, T> nv[R], nk[R];
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
+        for (int q = 0; q < R; ++q) {
+          nk[q] = n[q];
+          node_powers<D, T>(A.G, nk[q]);
+        }
+        // the neighbour's powers follow from the node's by series when the
+        // interface jump is small (a continuous state), else from its own
+        // logarithms
 #pragma unroll
-        for (int c = 0; c < NC; ++c) ft[q][c] = (T)0;
-        if (nb[q] >= 0) {
+        for (int q = 0; q < R; ++q) {
+          if (!node_near<D, T>(uv[q], nk[q], n[q].irho, ipk[q], A.G, *A.jc, nv[q])) {
+            node_from_u<D, T>(uv[q], A.G, nv[q]);
+            node_powers<D, T>(A.G, nv[q]);
+          }
+          if (nb[q] >= 0 && !nv[q].ok) atomicOr(A.err, 1);
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
           const int i = k + q * L;
           const T E0 = A.op.E[i], E1 = A.op.E[NP + i];
           T avec[D];
           avec[0] = lam[q][0] * E0 + lam[q][1] * E1;
           avec[1] = lam[q][2] * E0 + lam[q][3] * E1;
-          Node<D, T> nv;
-          node_from_u<D, T>(uv[q], A.G, nv);
-          if (!nv.ok) atomicOr(A.err, 1);
-          node_powers<D, T>(A.G, nv);
-          Node<D, T> nk = n[q];
-          node_powers<D, T>(A.G, nk);
-          facet_term<D, T>(nk, nv, avec, A.G, A.diss != 0, ft[q], ipk[q], -iWn[q]);
+          T f[NC];
+          facet_term_c<D, T>(nk[q], nv[q], avec, A.G, A.eac[0], A.eac[1], A.diss != 0, f, ipk[q], -iWn[q]);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) ft[q][c] = nb[q] >= 0 ? f[c] : (T)0;
         }
       }
+    }
+    if constexpr (EF == 3) {
+      // this tile's neighbour data is consumed: load the next tile's, to
+      // arrive during the pair loop
+#pragma unroll
+      for (int q = 0; q < R; ++q) pf->nb[q] = nbn[q];
+      pref_uv(A, *pf);
+      pf->t = next;
     }
     __syncthreads();
     if (act) {
@@ -1019,7 +1108,7 @@ struct Split2 {
           }
         }
       }
-      const int uo = A.uoff[e0 + e];
+      const int uo = A.u_dense ? A.u_base + (e0 + e) * (NC * NP) : A.uoff[e0 + e];
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const int i = k + q * L;
@@ -1062,7 +1151,7 @@ struct Split2 {
 // Rows per lane of the built-in 2D split variant; the autotuner may pick the other.
 template <int P, typename T> constexpr int split2_rows() { return 2; }
 
-template <int P, typename T, int R, bool EF = false>
+template <int P, typename T, int R, int EF = 0>
 __global__ __launch_bounds__(kThreads, R == 2 ? 2 : (P == 1 ? 2 : 3)) void k_split2(KArgs<T> A) {
   typedef Split2<P, T, R, EF> K;
   __shared__ typename K::Lds lds;
@@ -1070,11 +1159,21 @@ __global__ __launch_bounds__(kThreads, R == 2 ? 2 : (P == 1 ? 2 : 3)) void k_spl
   __syncthreads();
   double ent = 0.0;
   const int ntiles = (A.n_elem + K::EB - 1) / K::EB;
-  for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
-    if constexpr (EF)
-      K::tile_early(A, lds, tl, ent);
-    else
-      K::tile(A, lds, tl, ent);
+  if constexpr (EF == 3) {
+    typename K::Pref pf;
+    TileSeq ts(ntiles);
+    pf.t = ts.t < ts.end ? ts.t : -1;
+    K::pref_nb(A, pf.t, pf.nb);
+    K::pref_uv(A, pf);
+    for (; ts.t < ts.end; ts.t += ts.step)
+      K::tile_early(A, lds, ts.t, ent, &pf, ts.t + ts.step < ts.end ? ts.t + ts.step : -1);
+  } else {
+    for (TileSeq ts(ntiles); ts.t < ts.end; ts.t += ts.step) {
+      if constexpr (EF != 0)
+        K::tile_early(A, lds, ts.t, ent);
+      else
+        K::tile(A, lds, ts.t, ent);
+    }
   }
   block_sum_store(ent, A.ent_part);
 }
@@ -1100,17 +1199,17 @@ __global__ __launch_bounds__(kThreads, 2) void k_split2_batch(Batch2<T> Bt) {
     const int q = g < Bt.g0[1] ? 0 : (g < Bt.g0[2] ? 1 : (g < Bt.g0[3] ? 2 : 3));
     if (q != cur) {
       __syncthreads();
-      if (q == 0) Split2<1, T, split2_rows<1, T>()>::load_ops(Bt.c[0], *(typename Split2<1, T, split2_rows<1, T>()>::Lds *)raw);
-      else if (q == 1) Split2<2, T, split2_rows<2, T>()>::load_ops(Bt.c[1], *(typename Split2<2, T, split2_rows<2, T>()>::Lds *)raw);
-      else if (q == 2) Split2<3, T, split2_rows<3, T>()>::load_ops(Bt.c[2], *(typename Split2<3, T, split2_rows<3, T>()>::Lds *)raw);
-      else Split2<4, T, split2_rows<4, T>()>::load_ops(Bt.c[3], *(typename Split2<4, T, split2_rows<4, T>()>::Lds *)raw);
+      if (q == 0) Split2<1, T, split2_rows<1, T>()>::load_ops(batch_args(Bt, 0), *(typename Split2<1, T, split2_rows<1, T>()>::Lds *)raw);
+      else if (q == 1) Split2<2, T, split2_rows<2, T>()>::load_ops(batch_args(Bt, 1), *(typename Split2<2, T, split2_rows<2, T>()>::Lds *)raw);
+      else if (q == 2) Split2<3, T, split2_rows<3, T>()>::load_ops(batch_args(Bt, 2), *(typename Split2<3, T, split2_rows<3, T>()>::Lds *)raw);
+      else Split2<4, T, split2_rows<4, T>()>::load_ops(batch_args(Bt, 3), *(typename Split2<4, T, split2_rows<4, T>()>::Lds *)raw);
       __syncthreads();
       cur = q;
     }
-    if (q == 0) Split2<1, T, split2_rows<1, T>()>::tile(Bt.c[0], *(typename Split2<1, T, split2_rows<1, T>()>::Lds *)raw, g, ent);
-    else if (q == 1) Split2<2, T, split2_rows<2, T>()>::tile(Bt.c[1], *(typename Split2<2, T, split2_rows<2, T>()>::Lds *)raw, g - Bt.g0[1], ent);
-    else if (q == 2) Split2<3, T, split2_rows<3, T>()>::tile(Bt.c[2], *(typename Split2<3, T, split2_rows<3, T>()>::Lds *)raw, g - Bt.g0[2], ent);
-    else Split2<4, T, split2_rows<4, T>()>::tile(Bt.c[3], *(typename Split2<4, T, split2_rows<4, T>()>::Lds *)raw, g - Bt.g0[3], ent);
+    if (q == 0) Split2<1, T, split2_rows<1, T>(), 2>::tile_early(batch_args(Bt, 0), *(typename Split2<1, T, split2_rows<1, T>(), 2>::Lds *)raw, g, ent);
+    else if (q == 1) Split2<2, T, split2_rows<2, T>(), 2>::tile_early(batch_args(Bt, 1), *(typename Split2<2, T, split2_rows<2, T>(), 2>::Lds *)raw, g - Bt.g0[1], ent);
+    else if (q == 2) Split2<3, T, split2_rows<3, T>(), 2>::tile_early(batch_args(Bt, 2), *(typename Split2<3, T, split2_rows<3, T>(), 2>::Lds *)raw, g - Bt.g0[2], ent);
+    else Split2<4, T, split2_rows<4, T>(), 2>::tile_early(batch_args(Bt, 3), *(typename Split2<4, T, split2_rows<4, T>(), 2>::Lds *)raw, g - Bt.g0[3], ent);
   }
   block_sum_store(ent, Bt.ent_part);
 }
@@ -1894,13 +1993,14 @@ static KernelRef residual_kernel(int dim, int p, int form_eff, int variant) {
     if (form_eff == 1) return {reinterpret_cast<const void *>(&k_hadamard<2, PP, T>), HadTile<2, PP, T>::EB}; \
     if (form_eff == 2) return {reinterpret_cast<const void *>(&k_visc2<PP, T>), kThreads / Shape<2, PP>::NP}; \
     if (form_eff == 0) {                                                                        \
-      if (variant == 2)                                                                         \
-        return {reinterpret_cast<const void *>(&k_split2<PP, T, 2, true>), Split2<PP, T, 2>::EB}; \
-      if (variant == 3)                                                                         \
-        return {reinterpret_cast<const void *>(&k_split2<PP, T, 1, true>), Split2<PP, T, 1>::EB}; \
-      if ((split2_rows<PP, T>() == 2) != (variant == 1))                                        \
-        return {reinterpret_cast<const void *>(&k_split2<PP, T, 2>), Split2<PP, T, 2>::EB};     \
-      return {reinterpret_cast<const void *>(&k_split2<PP, T, 1>), Split2<PP, T, 1>::EB};       \
+      /* variant 0 (built-in): FP64 facet SATs before the pair sums with the next */            \
+      /* tile's neighbour states loaded ahead; FP32 SATs after the pair sums (fewer */           \
+      /* registers, four waves per SIMD); 1: one row per lane, SATs first; 2: the other */     \
+      if (variant == 1)                                                                         \
+        return {reinterpret_cast<const void *>(&k_split2<PP, T, 1, 3>), Split2<PP, T, 1>::EB};  \
+      if ((variant == 2) == (sizeof(T) == 8))                                                   \
+        return {reinterpret_cast<const void *>(&k_split2<PP, T, 2, 0>), Split2<PP, T, 2>::EB};  \
+      return {reinterpret_cast<const void *>(&k_split2<PP, T, 2, 3>), Split2<PP, T, 2>::EB};    \
     }                                                                                           \
     return {nullptr, 0};                                                                        \
   }
@@ -1942,7 +2042,10 @@ int resident_blocks(const void *kernel) {
 
 int launch_grid(const void *kernel, int ntiles, int grid) {
   if (ntiles <= 0) return 0;
-  if (grid <= 0) return ntiles;
+  // one workgroup per tile, rounded up to a multiple of the XCD count (the
+  // kernels' TileSeq then gives each XCD a contiguous eighth of the tiles;
+  // surplus workgroups find no tile)
+  if (grid <= 0) return ntiles < kXcds ? ntiles : (ntiles + kXcds - 1) / kXcds * kXcds;
   const long long cap = (long long)grid * resident_blocks(kernel);
   return (int)std::min<long long>(ntiles, cap);
 }
@@ -1951,7 +2054,7 @@ int residual_variants(int dim, int p, int precision, int form_eff) {
   (void)p;
   (void)precision;
   if (form_eff != 0) return 1;
-  return dim == 2 ? 4 : 2;
+  return dim == 2 ? 3 : 2;
 }
 
 int residual_blocks(int dim, int p, int precision, int form_eff, int n_elem, LaunchCfg cfg) {
@@ -2035,26 +2138,34 @@ int residual2_batch_blocks(const int n_elem_of_p[4], int precision, int grid) {
 }
 
 template <typename T>
-static hipError_t launch_batch2_t(const KArgs<T> *const cls[4], double *ent_part, hipStream_t s, int grid) {
+static hipError_t launch_batch2_t(const KArgs<T> *const cls[4], const KArgs<T> *cls_dev, double *ent_part,
+                                  hipStream_t s, int grid) {
   Batch2<T> Bt{};
   int ne[4];
+  const KArgs<T> *any = nullptr;
   for (int q = 0; q < 4; ++q) {
     ne[q] = cls[q] ? cls[q]->n_elem : 0;
-    if (cls[q]) Bt.c[q] = *cls[q];
+    if (cls[q]) any = cls[q];
   }
   const int ng = batch_groups<T>(ne, Bt.g0);
-  if (ng == 0) return hipSuccess;
+  if (ng == 0 || !any) return hipSuccess;
+  Bt.cls = cls_dev;
+  Bt.u = any->u;
+  Bt.r = any->r;
+  Bt.eform = any->eform;
   Bt.ent_part = ent_part;
   const int nb = residual2_batch_blocks(ne, sizeof(T) == 8 ? 0 : 1, grid);
   hipLaunchKernelGGL((k_split2_batch<T>), dim3(nb), dim3(kThreads), 0, s, Bt);
   return hipGetLastError();
 }
 
-hipError_t launch_residual2_batch(const KArgs<double> *const cls[4], double *ent_part, hipStream_t s, int grid) {
-  return launch_batch2_t<double>(cls, ent_part, s, grid);
+hipError_t launch_residual2_batch(const KArgs<double> *const cls[4], const KArgs<double> *cls_dev, double *ent_part,
+                                  hipStream_t s, int grid) {
+  return launch_batch2_t<double>(cls, cls_dev, ent_part, s, grid);
 }
-hipError_t launch_residual2_batch(const KArgs<float> *const cls[4], double *ent_part, hipStream_t s, int grid) {
-  return launch_batch2_t<float>(cls, ent_part, s, grid);
+hipError_t launch_residual2_batch(const KArgs<float> *const cls[4], const KArgs<float> *cls_dev, double *ent_part,
+                                  hipStream_t s, int grid) {
+  return launch_batch2_t<float>(cls, cls_dev, ent_part, s, grid);
 }
 
 hipError_t launch_residual(int dim, int p, int form, const KArgs<double> &A, hipStream_t s, LaunchCfg cfg) {

@@ -444,32 +444,38 @@ __global__ __launch_bounds__(kT) void k_vjp2_batch(Batch2<double> Bt) {
     const int q = g < Bt.g0[1] ? 0 : (g < Bt.g0[2] ? 1 : (g < Bt.g0[3] ? 2 : 3));
     if (q != cur) {
       __syncthreads();
-      if (q == 0) Vjp2<1>::load_ops(Bt.c[0], *(Vjp2<1>::Lds *)raw);
-      else if (q == 1) Vjp2<2>::load_ops(Bt.c[1], *(Vjp2<2>::Lds *)raw);
-      else if (q == 2) Vjp2<3>::load_ops(Bt.c[2], *(Vjp2<3>::Lds *)raw);
-      else Vjp2<4>::load_ops(Bt.c[3], *(Vjp2<4>::Lds *)raw);
+      if (q == 0) Vjp2<1>::load_ops(batch_args(Bt, 0), *(Vjp2<1>::Lds *)raw);
+      else if (q == 1) Vjp2<2>::load_ops(batch_args(Bt, 1), *(Vjp2<2>::Lds *)raw);
+      else if (q == 2) Vjp2<3>::load_ops(batch_args(Bt, 2), *(Vjp2<3>::Lds *)raw);
+      else Vjp2<4>::load_ops(batch_args(Bt, 3), *(Vjp2<4>::Lds *)raw);
       __syncthreads();
       cur = q;
     }
-    if (q == 0) Vjp2<1>::tile(Bt.c[0], *(Vjp2<1>::Lds *)raw, g);
-    else if (q == 1) Vjp2<2>::tile(Bt.c[1], *(Vjp2<2>::Lds *)raw, g - Bt.g0[1]);
-    else if (q == 2) Vjp2<3>::tile(Bt.c[2], *(Vjp2<3>::Lds *)raw, g - Bt.g0[2]);
-    else Vjp2<4>::tile(Bt.c[3], *(Vjp2<4>::Lds *)raw, g - Bt.g0[3]);
+    if (q == 0) Vjp2<1>::tile(batch_args(Bt, 0), *(Vjp2<1>::Lds *)raw, g);
+    else if (q == 1) Vjp2<2>::tile(batch_args(Bt, 1), *(Vjp2<2>::Lds *)raw, g - Bt.g0[1]);
+    else if (q == 2) Vjp2<3>::tile(batch_args(Bt, 2), *(Vjp2<3>::Lds *)raw, g - Bt.g0[2]);
+    else Vjp2<4>::tile(batch_args(Bt, 3), *(Vjp2<4>::Lds *)raw, g - Bt.g0[3]);
   }
 }
 
 }  // namespace
 
-hipError_t launch_vjp2_batch(const KArgs<double> *const cls[4], hipStream_t s, int grid) {
+hipError_t launch_vjp2_batch(const KArgs<double> *const cls[4], const KArgs<double> *cls_dev, hipStream_t s, int grid) {
   Batch2<double> Bt{};
   Bt.g0[0] = 0;
   const int eb[4] = {VTileV2<1>::EB, VTileV2<2>::EB, VTileV2<3>::EB, VTileV2<4>::EB};
+  const KArgs<double> *any = nullptr;
   for (int q = 0; q < 4; ++q) {
     const int ne = cls[q] ? cls[q]->n_elem : 0;
-    if (cls[q]) Bt.c[q] = *cls[q];
+    if (cls[q]) any = cls[q];
     Bt.g0[q + 1] = Bt.g0[q] + (ne + eb[q] - 1) / eb[q];
   }
-  if (Bt.g0[4] == 0) return hipSuccess;
+  if (Bt.g0[4] == 0 || !any) return hipSuccess;
+  Bt.cls = cls_dev;
+  Bt.u = any->u;
+  Bt.eform = any->eform;
+  Bt.lam = any->lam;
+  Bt.ubar = any->ubar;
   const int nb = launch_grid(reinterpret_cast<const void *>(&k_vjp2_batch), Bt.g0[4], grid);
   hipLaunchKernelGGL(k_vjp2_batch, dim3(nb), dim3(kT), 0, s, Bt);
   return hipGetLastError();

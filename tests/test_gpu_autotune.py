@@ -56,9 +56,10 @@ def test_every_residual_launch_shape(dim, p, n, prec):
     say("   built-in shape vs oracle", err.max())
     tol = 1e-12 if prec == 0 else 1e-5
     assert (err <= tol).all(), err
-    # 2D: one or two node rows per lane, facet SATs after or before the pair
-    # sums; 3D: skew operators in LDS or via the caches
-    nvar = 4 if dim == 2 else 2
+    # 2D: two or one node rows per lane with the facet SATs before the pair
+    # sums, or two rows with the SATs after them; 3D: skew operators in LDS
+    # or via the caches
+    nvar = 3 if dim == 2 else 2
     for v in range(nvar):
         for g in GRIDS:
             mesh.set_launch_shape("residual", p, v, g)
@@ -66,7 +67,12 @@ def test_every_residual_launch_shape(dim, p, n, prec):
             r, e = mesh.residual(ud, entropy_rate=True)
             mesh.check_device()
             r = r.double().cpu().numpy()
-            d = np.abs(r - r0).max() / np.abs(r0).max()
+            if prec == 0:
+                d = np.abs(r - r0).max() / np.abs(r0).max()
+            else:
+                # FP32 kernels of different operation order: against the
+                # summed-term scale, as for the oracle comparison
+                d = (np.abs(r[els] - r0[els]).max(axis=(0, 2)) / sc).max()
             de = abs(float(e.cpu()[0]) - e0) / abs(e0)
             eo = vs_oracle(r).max()
             say(f"   variant {v} grid {g}: vs oracle {eo:.1e}, vs built-in {d:.1e}, entropy rate {de:.1e}")
@@ -76,7 +82,9 @@ def test_every_residual_launch_shape(dim, p, n, prec):
             # up to 1e-5 of max |r| over 25-60 accumulated products
             assert d <= (0.0 if v == 0 else (1e-13 if prec == 0 else 1e-5)), (v, g, d)
             assert eo <= tol, (v, g, eo)
-            assert de <= (1e-11 if v == 0 or prec == 0 else 1e-5), (v, g, de)
+            # FP32: the dissipative rate of the 1%-jittered state is a small
+            # difference of single-precision residual values
+            assert de <= (1e-11 if v == 0 or prec == 0 else 1e-4), (v, g, de)
     with pytest.raises(sbp.SbpError):
         mesh.set_launch_shape("residual", p, nvar, 1)
     with pytest.raises(sbp.SbpError):

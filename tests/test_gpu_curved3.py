@@ -133,8 +133,8 @@ def test_curved_tets_refusals():
     with pytest.raises(sbp.SbpError) as ei:          # Assumption 1: p >= 2
         sbp.Mesh(desc, 1)
     assert ei.value.code == sbp.SBP_EINVAL
-    with pytest.raises(sbp.SbpError) as ei:
-        sbp.Mesh(desc, 2, viscous=True, mu=0.01)
+    with pytest.raises(sbp.SbpError) as ei:          # viscous terms: the entropy-split form only
+        sbp.Mesh(desc, 2, viscous=True, mu=0.01, form=sbp.FORM_HADAMARD)
     assert ei.value.code == sbp.SBP_ENOTSUP
 
 
