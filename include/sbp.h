@@ -155,13 +155,17 @@ int sbp_residual_vjp(sbp_mesh *mesh, const void *u_dev, const void *lambda_dev,
 /* One relaxation RK4 step in place (Sec. 6.1, eqs. rrk4 gamma_n, rrk_update).
  * dt > 0: use it; dt <= 0: dt = cfl * min_k h_min,k / |lambda|_max,k
  * (Sec. 7.1).  rep may be NULL.  Synchronises hip_stream.
- * The four RK stages (residuals, stage states, direction d) are captured once
- * per state pointer as a HIP graph on a private stream of the handle and
- * replayed on hip_stream (see sbp_use_graphs).  The relaxation parameter is
- * the root near 1 of sum H [s(u + g d) - s(u)] - g e, e = dt sum_i b_i w_i^T H
- * r_i, found by Newton steps from g = 1 safeguarded by bisection on [0.5,
- * 1.5]; SBP_ERRK if the root is not bracketed there.  On any error u is left
- * unchanged. */
+ * The relaxation parameter is the root near 1 of sum H [s(u + g d) - s(u)] -
+ * g e, e = dt sum_i b_i w_i^T H r_i, found by Newton steps from g = 1
+ * safeguarded by bisection on [0.5, 1.5].  The whole step (step size, the
+ * four RK stages, up to 8 Newton steps on device scalars, the update and the
+ * report's entropy sums) is one device sequence with no host round trip,
+ * captured once per state pointer and report flag as a HIP graph on a
+ * private stream of the handle and replayed on hip_stream (see
+ * sbp_use_graphs); the host reads its scalars once at the end.  If those
+ * Newton steps have not settled, the host continues the solve (u still
+ * unchanged) and evaluates the bracket; SBP_ERRK if the root is not
+ * bracketed there.  On any error u is left unchanged. */
 int sbp_rrk_step(sbp_mesh *mesh, void *u_dev, double dt, double cfl,
                  sbp_rrk_report *rep, void *hip_stream);
 
@@ -259,8 +263,9 @@ typedef struct {
  * degree class of sbp_residual, or its single batched launch on a 2D mesh
  * with several degrees; likewise of sbp_residual_vjp when lambda_dev != NULL)
  * time each launch shape -- kernel variant (2D entropy split: one or two node
- * rows per lane; 3D entropy split: skew operators in LDS or read through the
- * caches; VJP: register budget of one or two waves per SIMD) times persistent grid (1x or 2x the resident workgroups, or
+ * rows per lane, the next tile's neighbour data loaded ahead or not; 3D
+ * entropy split: skew operators in LDS or read through the caches; VJP:
+ * register budget of one or two waves per SIMD) times persistent grid (1x or 2x the resident workgroups, or
  * one workgroup per tile) -- on the state u_dev and keep the fastest for
  * later calls.  Results of all shapes agree up to the summation order of the
  * FP64 entropy rate.  Choices are remembered for the process per workload
@@ -275,7 +280,8 @@ int sbp_autotune(sbp_mesh *mesh, const void *u_dev, const void *lambda_dev, sbp_
 /* Read or pin the launch shape of one kernel slot: kind 0 residual, 1 VJP;
  * p the degree class, or 0 for the batched launch of a 2D mesh with several
  * degrees; variant < the slot's variant count (entropy split without the
- * Navier-Stokes terms, and VJP: 2; otherwise 1); grid 0..64 as in sbp_tune_slot.  Not in the paper.
+ * Navier-Stokes terms: 3 on triangles, 2 on tetrahedra; VJP: 2; otherwise 1);
+ * grid 0..64 as in sbp_tune_slot.  Not in the paper.
  * SBP_EINVAL for a slot the handle does not have or a value out of range. */
 int sbp_get_launch_shape(sbp_mesh *mesh, int32_t kind, int32_t p, int32_t *variant, int32_t *grid);
 int sbp_set_launch_shape(sbp_mesh *mesh, int32_t kind, int32_t p, int32_t variant, int32_t grid);

@@ -106,12 +106,14 @@ struct sbp_mesh {
   int curved3 = 0;            // tetrahedra with quadratic maps (per-node metrics)
   int src_kind = 0;           // SBP_SOURCE_*: source added to every residual
   sbp::SrcArgs src{};
-  // RRK stages captured once as a HIP graph (per state pointer), replayed on
-  // the caller's stream; captured on a private stream of default priority
+  // RRK steps captured once as a HIP graph (per state pointer and report
+  // mode), replayed on the caller's stream; captured on a private stream of
+  // default priority
   int use_graphs = 1;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t rk_exec = nullptr;
   const void *rk_u = nullptr;
+  int rk_rep = -1;
 };
 
 namespace {
@@ -133,13 +135,14 @@ int form_eff_of(const sbp_mesh *M) {
 // kEacJump the binomial coefficients of the node powers
 constexpr size_t kEacPrec = 1024, kEacJump = 512;
 
-constexpr int SC_ENT = 0;     // 4 stage entropy rates
+constexpr int SC_ENT = sbp::RK_ENT;  // 4 stage entropy rates
 constexpr int SC_RED = 8;     // reduction outputs (up to 8)
-constexpr int SC_DT = 16;     // time step of the current RRK step
+constexpr int SC_DT = sbp::RK_DT;    // time step of the current RRK step
 constexpr int SC_T = 17;      // time at the start of the current RRK step
 constexpr int SC_TR = 18;     // time of a residual call (the handle's time)
 constexpr int SC_SRC = 20;    // entropy rates of the residual and of the source (2)
-constexpr int SC_TOTAL = 32;
+constexpr int SC_TOTAL = sbp::RK_TOTAL;  // 22.. hold the device relaxation solve (sbp::RK_*)
+static_assert(SC_SRC + 2 <= sbp::RK_DTIN && SC_T < SC_TR && SC_RED + 8 <= SC_DT, "scalar slots overlap");
 
 // --------------------------------------------------------------------------
 // geometry helpers
@@ -855,16 +858,100 @@ int rk_stages(sbp_mesh *M, const double *u, hipStream_t s) {
   return SBP_OK;
 }
 
-int rk_stages_graph(sbp_mesh *M, const double *u, hipStream_t s) {
-  if (!M->use_graphs) return rk_stages(M, u, s);
-  if (M->rk_exec && M->rk_u != (const void *)u) {
-    (void)hipGraphExecDestroy(M->rk_exec);
-    M->rk_exec = nullptr;
+// One relaxation RK4 step on the device (Sec. 6.1): the step size (Sec.
+// 7.1; the requested one when positive), the four stages, e, kNewtonSteps
+// safeguarded Newton steps for the relaxation root (the steps after the
+// root is found do nothing), u += gamma d, and with a report the total
+// entropy before and after.  No host round trip: the host reads the
+// scalars once afterwards.
+constexpr int kNewtonSteps = 8;
+
+int rrk_device(sbp_mesh *M, double *u, bool report, hipStream_t s) {
+  double *rk = M->d_scal;
+  for (auto &c : M->cls) HIPCHK(sbp::launch_dt(node_args(M, c, u, nullptr), M->d_npart + c.node_off_blk, s, rk));
+  HIPCHK(sbp::launch_reduce(M->d_npart, M->node_total, 1, 1, rk + sbp::RK_GAP, s));
+  HIPCHK(sbp::launch_rrk_dt(rk + sbp::RK_GAP, rk, s));
+  int rc;
+  if ((rc = rk_stages(M, u, s))) return rc;
+  HIPCHK(sbp::launch_rrk_init(rk, s));
+  if (report) {
+    for (auto &c : M->cls) HIPCHK(sbp::launch_diagnostics(node_args(M, c, u, nullptr), M->d_npart + c.node_off_blk, s));
+    HIPCHK(sbp::launch_reduce(M->d_npart, M->node_total, 1, 0, rk + sbp::RK_S0, s));
   }
+  for (int it = 0; it < kNewtonSteps; ++it) {
+    for (auto &c : M->cls)
+      HIPCHK(sbp::launch_entropy_gap(node_args(M, c, u, M->d_d), 0.0, M->d_npart + c.node_off_blk, s, rk));
+    HIPCHK(sbp::launch_reduce(M->d_npart, M->node_total, 3, 0, rk + sbp::RK_GAP, s));
+    HIPCHK(sbp::launch_rrk_newton(rk + sbp::RK_GAP, rk, s));
+  }
+  HIPCHK(sbp::launch_rrk_update(u, M->d_d, rk, M->d_err, M->n_dof, s));
+  if (report) {
+    for (auto &c : M->cls) HIPCHK(sbp::launch_diagnostics(node_args(M, c, u, nullptr), M->d_npart + c.node_off_blk, s));
+    HIPCHK(sbp::launch_reduce(M->d_npart, M->node_total, 1, 0, rk + sbp::RK_S1, s));
+  }
+  return SBP_OK;
+}
+
+// The relaxation root on the host: Newton from g = 1, stopped once |r(g)| is
+// at the rounding level of its evaluation (eps sum H |s|) or the step
+// stalls; the bracket [0.5, 1.5] is evaluated if a Newton step leaves it
+// (then bisection safeguards).  The fallback of the device solve; u is
+// read, not changed.  iters receives the number of evaluations.
+int relaxation_host(sbp_mesh *M, const double *u, double e, double &g, double &iters, hipStream_t s) {
+  constexpr double eps = 2.220446049250313e-16;
+  double lo = 0.5, hi = 1.5;
+  g = 1.0;
+  bool bracketed = false;
+  double fv[3];
+  int it = 0, rc;
+  for (; it < 100; ++it) {
+    if ((rc = entropy_gap(M, u, M->d_d, g, fv, s))) return rc;
+    const double f = fv[0] - g * e;
+    const double df = fv[1] - e;
+    if (std::fabs(f) <= eps * fv[2]) break;
+    if (bracketed) {
+      if (f < 0.0) lo = g; else hi = g;
+    }
+    double gn = g - f / df;
+    if (!(df > 0.0) || !(gn > lo && gn < hi)) {
+      if (!bracketed) {
+        double fb[3];
+        if ((rc = entropy_gap(M, u, M->d_d, lo, fb, s))) return rc;
+        const double flo = fb[0] - lo * e;
+        if ((rc = entropy_gap(M, u, M->d_d, hi, fb, s))) return rc;
+        const double fhi = fb[0] - hi * e;
+        if (!(flo < 0.0 && fhi > 0.0)) return fail(SBP_ERRK, "relaxation root not bracketed in [0.5, 1.5]");
+        bracketed = true;
+        if (f < 0.0) lo = g; else hi = g;
+      }
+      if (!(df > 0.0) || !(gn > lo && gn < hi)) gn = 0.5 * (lo + hi);
+    }
+    if (gn == g || std::fabs(gn - g) <= eps * g || (bracketed && hi - lo <= 4.0 * eps * g)) {
+      g = gn;
+      break;
+    }
+    g = gn;
+  }
+  if (it >= 100) return fail(SBP_ERRK, "relaxation root solve did not converge");
+  if (!(g > 0.5 && g < 1.5)) return fail(SBP_ERRK, "relaxation parameter outside [0.5, 1.5]");
+  iters = it + 1;
+  return SBP_OK;
+}
+
+void drop_rk_graph(sbp_mesh *M) {
+  if (M->rk_exec) (void)hipGraphExecDestroy(M->rk_exec);
+  M->rk_exec = nullptr;
+  M->rk_u = nullptr;
+  M->rk_rep = -1;
+}
+
+int rrk_device_graph(sbp_mesh *M, double *u, bool report, hipStream_t s) {
+  if (!M->use_graphs) return rrk_device(M, u, report, s);
+  if (M->rk_exec && (M->rk_u != (const void *)u || M->rk_rep != (int)report)) drop_rk_graph(M);
   if (!M->rk_exec) {
     if (!M->cap_stream) HIPCHK(hipStreamCreateWithFlags(&M->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(M->cap_stream, hipStreamCaptureModeThreadLocal));
-    const int rc = rk_stages(M, u, M->cap_stream);
+    const int rc = rrk_device(M, u, report, M->cap_stream);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(M->cap_stream, &graph);
     if (rc) {
@@ -876,6 +963,7 @@ int rk_stages_graph(sbp_mesh *M, const double *u, hipStream_t s) {
     (void)hipGraphDestroy(graph);
     HIPCHK(ei);
     M->rk_u = u;
+    M->rk_rep = (int)report;
   }
   HIPCHK(hipGraphLaunch(M->rk_exec, s));
   return SBP_OK;
@@ -1081,11 +1169,7 @@ int autotune_impl(sbp_mesh *M, const double *u, const double *lam, sbp_tune_repo
     }
   }
   // the captured RK stages hold the old launch shapes
-  if (M->rk_exec) {
-    (void)hipGraphExecDestroy(M->rk_exec);
-    M->rk_exec = nullptr;
-    M->rk_u = nullptr;
-  }
+  drop_rk_graph(M);
   HIPCHK(hipStreamSynchronize(s));
   return check_err(M, s);
 }
@@ -1297,11 +1381,7 @@ int sbp_check_device(sbp_mesh *M, void *stream) {
 int sbp_use_graphs(sbp_mesh *M, int enable) {
   if (!M) return fail(SBP_EINVAL, "null argument");
   M->use_graphs = enable ? 1 : 0;
-  if (!M->use_graphs && M->rk_exec) {
-    (void)hipGraphExecDestroy(M->rk_exec);
-    M->rk_exec = nullptr;
-    M->rk_u = nullptr;
-  }
+  if (!M->use_graphs) drop_rk_graph(M);
   return SBP_OK;
 }
 
@@ -1343,11 +1423,7 @@ int sbp_set_volume_form(sbp_mesh *M, const uint8_t *form_dev) {
     return fail(SBP_ENOTSUP, "the hybrid scheme covers the Euler terms (no viscous terms)");
   M->eform = form_dev;
   // the captured RK stages hold the previous launches
-  if (M->rk_exec) {
-    (void)hipGraphExecDestroy(M->rk_exec);
-    M->rk_exec = nullptr;
-    M->rk_u = nullptr;
-  }
+  drop_rk_graph(M);
   return SBP_OK;
 }
 
@@ -1397,11 +1473,7 @@ int sbp_set_source(sbp_mesh *M, int32_t kind, const double *params) {
   M->src.kind = kind;
   M->src_kind = kind;
   // the captured RK stages hold the previous launches
-  if (M->rk_exec) {
-    (void)hipGraphExecDestroy(M->rk_exec);
-    M->rk_exec = nullptr;
-    M->rk_u = nullptr;
-  }
+  drop_rk_graph(M);
   return SBP_OK;
 }
 
@@ -1494,11 +1566,7 @@ int sbp_set_launch_shape(sbp_mesh *M, int32_t kind, int32_t p, int32_t variant, 
   if (grid < 0 || grid > 64) return fail(SBP_EINVAL, "grid must be 0..64");
   if (c) *c = sbp::LaunchCfg{variant, grid};
   else *g = grid;
-  if (M->rk_exec) {
-    (void)hipGraphExecDestroy(M->rk_exec);
-    M->rk_exec = nullptr;
-    M->rk_u = nullptr;
-  }
+  drop_rk_graph(M);
   return SBP_OK;
 }
 
@@ -1510,91 +1578,46 @@ int sbp_set_time(sbp_mesh *M, double t) {
 
 int sbp_rrk_step(sbp_mesh *M, void *u_dev, double dt, double cfl, sbp_rrk_report *rep, void *stream) {
   if (!M || !u_dev) return fail(SBP_EINVAL, "null argument");
+  if (!(dt > 0.0) && !(cfl > 0.0)) return fail(SBP_EINVAL, "need dt > 0 or cfl > 0");
   hipStream_t s = (hipStream_t)stream;
   double *u = (double *)u_dev;
-  const long long n = M->n_dof;
-  const int f32 = M->phys.precision == SBP_FP32;
   int rc;
   if ((rc = ensure_rk_buffers(M))) return rc;
-  if (!(dt > 0.0)) {
-    if (!(cfl > 0.0)) return fail(SBP_EINVAL, "need dt > 0 or cfl > 0");
-    for (auto &c : M->cls) {
-      sbp::NodeArgs A = node_args(M, c, u, nullptr);
-      HIPCHK(sbp::launch_dt(A, M->d_npart + c.node_off_blk, s));
-    }
-    double hmin_over_lam;
-    if ((rc = reduce_nodes(M, 1, 1, &hmin_over_lam, s))) return rc;
-    dt = cfl * hmin_over_lam;
-    if (!(dt > 0.0) || !std::isfinite(dt)) {
-      if ((rc = check_err(M, s))) return rc;
-      return fail(SBP_ENONPHYS, "time step is not positive (non-physical state)");
-    }
-  }
-  const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
-  HIPCHK(sbp::launch_scalar_set(M->d_scal + SC_DT, dt, s));
+  // the whole step on the device (one captured graph), then one read-back
+  HIPCHK(sbp::launch_scalar_set(M->d_scal + sbp::RK_DTIN, dt > 0.0 ? dt : 0.0, s));
+  HIPCHK(sbp::launch_scalar_set(M->d_scal + sbp::RK_CFL, cfl, s));
   HIPCHK(sbp::launch_scalar_set(M->d_scal + SC_T, M->t, s));
-  if ((rc = rk_stages_graph(M, u, s))) return rc;
-  double ent[4];
-  HIPCHK(hipMemcpyAsync(ent, M->d_scal + SC_ENT, sizeof(ent), hipMemcpyDeviceToHost, s));
+  if ((rc = rrk_device_graph(M, u, rep != nullptr, s))) return rc;
+  double k[sbp::RK_TOTAL];
+  HIPCHK(hipMemcpyAsync(k, M->d_scal, sizeof(k), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if ((rc = check_err(M, s))) return rc;
-  double e = 0.0;
-  for (int i = 0; i < 4; ++i) e += dt * b[i] * ent[i];
-  // relaxation parameter: root near 1 of r(g) = sum H [s(u + g d) - s(u)] - g e.
-  // Newton from g = 1, stopped once |r(g)| reaches the rounding level of its
-  // evaluation (eps sum H |s|) or the step stalls; the bracket [0.5, 1.5] is
-  // evaluated only if a Newton step leaves it (then bisection safeguards).
-  constexpr double eps = 2.220446049250313e-16;
-  double lo = 0.5, hi = 1.5, g = 1.0;
-  bool bracketed = false;
-  double fv[3];
-  int it = 0;
-  for (; it < 100; ++it) {
-    if ((rc = entropy_gap(M, u, M->d_d, g, fv, s))) return rc;
-    const double f = fv[0] - g * e;
-    const double df = fv[1] - e;
-    if (std::fabs(f) <= eps * fv[2]) break;
-    if (bracketed) {
-      if (f < 0.0) lo = g; else hi = g;
-    }
-    double gn = g - f / df;
-    if (!(df > 0.0) || !(gn > lo && gn < hi)) {
-      if (!bracketed) {
-        double fb[3];
-        if ((rc = entropy_gap(M, u, M->d_d, lo, fb, s))) return rc;
-        const double flo = fb[0] - lo * e;
-        if ((rc = entropy_gap(M, u, M->d_d, hi, fb, s))) return rc;
-        const double fhi = fb[0] - hi * e;
-        if (!(flo < 0.0 && fhi > 0.0)) return fail(SBP_ERRK, "relaxation root not bracketed in [0.5, 1.5]");
-        bracketed = true;
-        if (f < 0.0) lo = g; else hi = g;
-      }
-      if (!(df > 0.0) || !(gn > lo && gn < hi)) gn = 0.5 * (lo + hi);
-    }
-    if (gn == g || std::fabs(gn - g) <= eps * g || (bracketed && hi - lo <= 4.0 * eps * g)) {
-      g = gn;
-      break;
-    }
-    g = gn;
+  if (k[sbp::RK_BAD] != 0.0) return fail(SBP_ENONPHYS, "time step is not positive (non-physical state)");
+  dt = k[sbp::RK_DT];
+  const double e = k[sbp::RK_E];
+  double g = k[sbp::RK_G];
+  const double done = k[sbp::RK_DONE];
+  int iters = (int)k[sbp::RK_IT];
+  double ent0 = k[sbp::RK_S0], ent1 = k[sbp::RK_S1];
+  if (!((done == 1.0 || done == 2.0) && g > 0.5 && g < 1.5)) {
+    // the device steps did not settle inside the bracket: the host solve
+    // (Newton with bisection on an evaluated bracket), u still unchanged
+    double extra = 0;
+    if ((rc = relaxation_host(M, u, e, g, extra, s))) return rc;
+    iters += (int)extra;
+    if (rep && (rc = diagnostics_impl(M, u, &ent0, s, 1))) return rc;
+    HIPCHK(sbp::launch_accum(u, M->d_d, 0, g, M->n_dof, s));
+    if (rep && (rc = diagnostics_impl(M, u, &ent1, s, 1))) return rc;
   }
-  if (it >= 100) return fail(SBP_ERRK, "relaxation root solve did not converge");
-  if (!(g > 0.5 && g < 1.5)) return fail(SBP_ERRK, "relaxation parameter outside [0.5, 1.5]");
-  // the report needs the total entropy only (the first diagnostic)
-  double ent0 = 0.0, ent1 = 0.0;
-  if (rep) {
-    if ((rc = diagnostics_impl(M, u, &ent0, s, 1))) return rc;
-  }
-  HIPCHK(sbp::launch_accum(u, M->d_d, 0, g, n, s));
   M->t += g * dt;
   if (rep) {
-    if ((rc = diagnostics_impl(M, u, &ent1, s, 1))) return rc;
     rep->gamma_n = g;
     rep->dt = dt;
     rep->t = M->t;
     rep->entropy_before = ent0;
     rep->entropy_after = ent1;
     rep->entropy_rate_e = e;
-    rep->newton_iters = it + 1;
+    rep->newton_iters = iters;
   }
   HIPCHK(hipStreamSynchronize(s));
   return check_err(M, s);

@@ -90,13 +90,36 @@ struct SrcArgs {
 constexpr int kNodeThreads = 256;
 inline int node_blocks(int n_elem, int np) { return (n_elem * np + kNodeThreads - 1) / kNodeThreads; }
 
+// Device scalars of the relaxation RK step (indices into the handle's
+// scalar array): the four stage entropy rates, dt, the requested dt (> 0) or
+// the CFL number, e, gamma and its bracket, r(gamma), its rounding level,
+// the solve's state (0 running, 1 |r| at rounding level, 2 stalled, 3 no
+// valid dt), iterations, the total entropy before and after, a non-positive
+// dt flag, the reduced entropy gap (3 values).
+enum {
+  RK_ENT = 0, RK_DT = 16, RK_DTIN = 22, RK_CFL = 23, RK_E = 24, RK_G = 25, RK_LO = 26, RK_HI = 27,
+  RK_F = 28, RK_TOL = 29, RK_DONE = 30, RK_IT = 31, RK_S0 = 32, RK_S1 = 33, RK_BAD = 34, RK_GAP = 40,
+  RK_TOTAL = 48
+};
+
 // part[v*pstride + b], v = 0,1,2: sum_nodes H [s(u + g d) - s(u)], sum_nodes H w(u + g d).d,
-// sum_nodes H |s(u + g d)|
-hipError_t launch_entropy_gap(const NodeArgs &A, double g, double *part, hipStream_t s);
+// sum_nodes H |s(u + g d)|; with rk non-null g = rk[RK_G], and nothing is
+// done once rk[RK_DONE] != 0
+hipError_t launch_entropy_gap(const NodeArgs &A, double g, double *part, hipStream_t s, const double *rk = nullptr);
+// rk[RK_DT] = rk[RK_DTIN] > 0 ? rk[RK_DTIN] : rk[RK_CFL] * hmin_over_lam[0]; rk[RK_BAD] if not positive
+hipError_t launch_rrk_dt(const double *hmin_over_lam, double *rk, hipStream_t s);
+// e from the stage entropy rates, gamma = 1, bracket [0.5, 1.5]
+hipError_t launch_rrk_init(double *rk, hipStream_t s);
+// one safeguarded Newton step of the relaxation root from the reduced gap
+hipError_t launch_rrk_newton(const double *gap, double *rk, hipStream_t s);
+// u += gamma d if the device solve ended inside the bracket and *err == 0
+hipError_t launch_rrk_update(double *u, const double *d, const double *rk, const int *err, long long n,
+                             hipStream_t s);
 // part[v*pstride + b], v = 0: sum H s(u); v = 1..n_c: sum H u_c
 hipError_t launch_diagnostics(const NodeArgs &A, double *part, hipStream_t s);
-// part[b] = min over the block's elements of hmin / max_nodes(|V| + a)
-hipError_t launch_dt(const NodeArgs &A, double *part, hipStream_t s);
+// part[b] = min over the block's elements of hmin / max_nodes(|V| + a);
+// nothing is done when rk is non-null and rk[RK_DTIN] > 0
+hipError_t launch_dt(const NodeArgs &A, double *part, hipStream_t s, const double *rk = nullptr);
 // r += S(x, t) at every node (S the manufactured source; r double or float),
 // t = *t0 + c * *dt (dt null: t = *t0); part (may be null): per workgroup
 // sum_nodes H w(u).S in FP64

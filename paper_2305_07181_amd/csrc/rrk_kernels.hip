@@ -69,9 +69,15 @@ __device__ __forceinline__ bool ent_state(const double *u, double g, double beta
 }
 
 template <int D>
-__global__ __launch_bounds__(kT) void k_entropy_gap(NodeArgs A, double gam, double *part) {
+__global__ __launch_bounds__(kT) void k_entropy_gap(NodeArgs A, double gam, double *part, const double *rk) {
   constexpr int NC = D + 2;
   __shared__ double red[kT / 64];
+  // device relaxation solve: gamma from the device scalars, nothing to do
+  // once the root is found (the partials are then not read)
+  if (rk) {
+    if (rk[RK_DONE] != 0.0) return;
+    gam = rk[RK_G];
+  }
   const int x = blockIdx.x * kT + threadIdx.x;
   double a = 0.0, b = 0.0, m = 0.0;
   if (x < A.n_elem * A.np) {
@@ -141,7 +147,8 @@ __global__ __launch_bounds__(kT) void k_diagnostics(NodeArgs A, double *part) {
 // One thread per node computes |V| + a; the element minimum of
 // hmin / lambda_max equals min over its nodes of hmin / (|V| + a).
 template <int D>
-__global__ __launch_bounds__(kT) void k_dt(NodeArgs A, double *part) {
+__global__ __launch_bounds__(kT) void k_dt(NodeArgs A, double *part, const double *rk) {
+  if (rk && rk[RK_DTIN] > 0.0) return;  // the step size is given
   constexpr int NC = D + 2;
   __shared__ double red[kT / 64];
   const int x = blockIdx.x * kT + threadIdx.x;
@@ -453,6 +460,69 @@ __global__ __launch_bounds__(kT) void k_accum(double *y, const Z *z, double a, c
     y[i] += as * (double)z[i];
 }
 
+// Relaxation solve on the device (Sec. 6.1, eq. rrk4 gamma_n): the scalars
+// rk[RK_*] (see launch.hpp) hold dt, the stage entropy rates, gamma, the
+// bracket and the state of the iteration.
+__global__ void k_rrk_dt(const double *hmin_over_lam, double *rk) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double dt = rk[RK_DTIN] > 0.0 ? rk[RK_DTIN] : rk[RK_CFL] * hmin_over_lam[0];
+  rk[RK_DT] = dt;
+  rk[RK_BAD] = (dt > 0.0 && dt < INFINITY) ? 0.0 : 1.0;
+}
+
+// e = dt sum_i b_i w_i^T H r_i; gamma = 1 in the bracket [0.5, 1.5]
+__global__ void k_rrk_init(double *rk) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+  double e = 0.0;
+  for (int i = 0; i < 4; ++i) e += rk[RK_DT] * b[i] * rk[RK_ENT + i];
+  rk[RK_E] = e;
+  rk[RK_G] = 1.0;
+  rk[RK_LO] = 0.5;
+  rk[RK_HI] = 1.5;
+  rk[RK_DONE] = rk[RK_BAD] != 0.0 ? 3.0 : 0.0;
+  rk[RK_IT] = 0.0;
+  rk[RK_F] = 0.0;
+}
+
+// One Newton step on r(g) = sum H [s(u + g d) - s(u)] - g e from the reduced
+// gap[3] = {sum H [s(u + g d) - s(u)], sum H w(u + g d).d, sum H |s(u + g d)|}:
+// stop once |r| is at the rounding level of its evaluation (eps sum H |s|),
+// DONE = 1, or once the step stalls, DONE = 2; the bracket follows the sign
+// of r (r < 0 below the root); a step leaving it or a non-increasing r
+// bisects instead.
+__global__ void k_rrk_newton(const double *gap, double *rk) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (rk[RK_DONE] != 0.0) return;
+  constexpr double eps = 2.220446049250313e-16;
+  const double g = rk[RK_G], e = rk[RK_E];
+  const double f = gap[0] - g * e, df = gap[1] - e;
+  rk[RK_IT] += 1.0;
+  rk[RK_F] = f;
+  rk[RK_TOL] = eps * gap[2];
+  if (fabs(f) <= eps * gap[2]) {
+    rk[RK_DONE] = 1.0;
+    return;
+  }
+  if (f < 0.0) rk[RK_LO] = g; else rk[RK_HI] = g;
+  const double lo = rk[RK_LO], hi = rk[RK_HI];
+  double gn = g - f / df;
+  if (!(df > 0.0) || !(gn > lo && gn < hi)) gn = 0.5 * (lo + hi);
+  if (gn == g || fabs(gn - g) <= eps * g || hi - lo <= 4.0 * eps * g) rk[RK_DONE] = 2.0;
+  rk[RK_G] = gn;
+}
+
+// u += g d once the solve has ended inside the bracket and no kernel of the
+// step has flagged a non-physical state (else u is left unchanged: for the
+// host's safeguarded solve, or for the error return)
+__global__ __launch_bounds__(kT) void k_rrk_update(double *u, const double *d, const double *rk, const int *err,
+                                                   long long n) {
+  const double done = rk[RK_DONE], g = rk[RK_G];
+  if (!(done == 1.0 || done == 2.0) || !(g > 0.5 && g < 1.5) || *err != 0) return;
+  for (long long i = blockIdx.x * (long long)kT + threadIdx.x; i < n; i += (long long)gridDim.x * kT)
+    u[i] += g * d[i];
+}
+
 __global__ void k_scalar_set(double *out, double v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = v;
 }
@@ -474,12 +544,12 @@ int grid_for(long long n) {
 
 }  // namespace
 
-hipError_t launch_entropy_gap(const NodeArgs &A, double g, double *part, hipStream_t s) {
+hipError_t launch_entropy_gap(const NodeArgs &A, double g, double *part, hipStream_t s, const double *rk) {
   const int nb = node_blocks(A.n_elem, A.np);
   if (A.dim == 2)
-    hipLaunchKernelGGL(k_entropy_gap<2>, dim3(nb), dim3(kT), 0, s, A, g, part);
+    hipLaunchKernelGGL(k_entropy_gap<2>, dim3(nb), dim3(kT), 0, s, A, g, part, rk);
   else
-    hipLaunchKernelGGL(k_entropy_gap<3>, dim3(nb), dim3(kT), 0, s, A, g, part);
+    hipLaunchKernelGGL(k_entropy_gap<3>, dim3(nb), dim3(kT), 0, s, A, g, part, rk);
   return hipGetLastError();
 }
 
@@ -492,12 +562,12 @@ hipError_t launch_diagnostics(const NodeArgs &A, double *part, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_dt(const NodeArgs &A, double *part, hipStream_t s) {
+hipError_t launch_dt(const NodeArgs &A, double *part, hipStream_t s, const double *rk) {
   const int nb = node_blocks(A.n_elem, A.np);
   if (A.dim == 2)
-    hipLaunchKernelGGL(k_dt<2>, dim3(nb), dim3(kT), 0, s, A, part);
+    hipLaunchKernelGGL(k_dt<2>, dim3(nb), dim3(kT), 0, s, A, part, rk);
   else
-    hipLaunchKernelGGL(k_dt<3>, dim3(nb), dim3(kT), 0, s, A, part);
+    hipLaunchKernelGGL(k_dt<3>, dim3(nb), dim3(kT), 0, s, A, part, rk);
   return hipGetLastError();
 }
 
@@ -576,6 +646,27 @@ hipError_t launch_scalar_set(double *out, double v, hipStream_t s) {
 
 hipError_t launch_scalar_combine(const double *in, const double *coef_dev, int nk, double *out, hipStream_t s) {
   hipLaunchKernelGGL(k_scalar_combine, dim3(1), dim3(64), 0, s, in, coef_dev, nk, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rrk_dt(const double *hmin_over_lam, double *rk, hipStream_t s) {
+  hipLaunchKernelGGL(k_rrk_dt, dim3(1), dim3(64), 0, s, hmin_over_lam, rk);
+  return hipGetLastError();
+}
+
+hipError_t launch_rrk_init(double *rk, hipStream_t s) {
+  hipLaunchKernelGGL(k_rrk_init, dim3(1), dim3(64), 0, s, rk);
+  return hipGetLastError();
+}
+
+hipError_t launch_rrk_newton(const double *gap, double *rk, hipStream_t s) {
+  hipLaunchKernelGGL(k_rrk_newton, dim3(1), dim3(64), 0, s, gap, rk);
+  return hipGetLastError();
+}
+
+hipError_t launch_rrk_update(double *u, const double *d, const double *rk, const int *err, long long n,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_rrk_update, dim3(grid_for(n)), dim3(kT), 0, s, u, d, rk, err, n);
   return hipGetLastError();
 }
 

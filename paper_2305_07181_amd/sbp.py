@@ -270,8 +270,13 @@ class Mesh:
         _check(_lib.sbp_residual_vjp(self._h, _ptr(u), _ptr(lam), _ptr(ubar), _stream_ptr(stream)))
         return ubar
 
-    def rrk_step(self, u, dt=0.0, cfl=0.1, stream=None):
+    def rrk_step(self, u, dt=0.0, cfl=0.1, stream=None, report=True):
+        """sbp_rrk_step; returns the step report as a dict, or None with
+        report=False (then the entropy sums are not computed)."""
         self._check_state(u)
+        if not report:
+            _check(_lib.sbp_rrk_step(self._h, _ptr(u), float(dt), float(cfl), None, _stream_ptr(stream)))
+            return None
         rep = RRKReport()
         _check(_lib.sbp_rrk_step(self._h, _ptr(u), float(dt), float(cfl), C.byref(rep), _stream_ptr(stream)))
         return dict(gamma=rep.gamma_n, dt=rep.dt, t=rep.t, entropy_before=rep.entropy_before,

@@ -197,3 +197,51 @@ def test_rrk_report_entropies_3d(viscous):
         assert rep["entropy_before"] == d0[0] and rep["entropy_after"] == d1[0]
         assert rep["entropy_after"] <= rep["entropy_before"]
     mesh.close()
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_rrk_without_report_same_state(graphs):
+    """sbp_rrk_step with a null report (a second captured sequence, without the
+    entropy sums) advances u bit-identically to the step with a report."""
+    import torch
+    from oracle.geometry import OracleMesh
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say(f"[rrk no report] graphs={graphs}")
+    desc = wl.vortex2d_mesh(6, warp=0.05)
+    m = OracleMesh(desc, 3)
+    u = torch.from_numpy(state(m, "vortex")).cuda()
+    ma = sbp.Mesh(desc, 3, dissipation=True)
+    mb = sbp.Mesh(desc, 3, dissipation=True)
+    ma.use_graphs(graphs)
+    mb.use_graphs(graphs)
+    ua, ub = u.clone(), u.clone()
+    for _ in range(3):
+        rep = ma.rrk_step(ua, cfl=0.2)
+        assert mb.rrk_step(ub, cfl=0.2, report=False) is None
+        assert torch.equal(ua, ub)
+        assert rep["iters"] >= 1 and 0.5 < rep["gamma"] < 1.5
+    ma.close()
+    mb.close()
+
+
+def test_rrk_nonphysical_state_leaves_u_unchanged():
+    """A state with negative pressure at one node: the step returns
+    SBP_ENONPHYS and u keeps its bytes (the device update is skipped when a
+    kernel of the step has flagged the state)."""
+    import torch
+    from oracle.geometry import OracleMesh
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say("[rrk nonphys]")
+    desc = wl.vortex2d_mesh(4)
+    m = OracleMesh(desc, 2)
+    u = state(m, "vortex")
+    u[5, 3, 1] = 0.0                       # energy 0 -> negative pressure
+    mesh = sbp.Mesh(desc, 2, dissipation=True)
+    ud = torch.from_numpy(u).cuda()
+    u0 = ud.clone()
+    with pytest.raises(sbp.SbpError) as ei:
+        mesh.rrk_step(ud, dt=1e-3)
+    assert ei.value.code == sbp.SBP_ENONPHYS
+    assert torch.equal(ud, u0)
+    mesh.check_device()                    # flag cleared
+    mesh.close()
