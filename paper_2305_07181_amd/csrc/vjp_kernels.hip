@@ -94,12 +94,12 @@ __global__ __launch_bounds__(kT, W) void k_vjp3v(KArgs<double> A) {
     __syncthreads();
     for (int x = tid; x < ne * 10; x += kT) gs[x / 10][x % 10] = A.geo[(size_t)(e0 + x / 10) * 10 + x % 10];
     __syncthreads();
-    double uu[NC], lm[NC];
     Node<D, double> n;
     const double *Lam = gs[act ? e : 0];
     const double J = Lam[9], iJ = 1.0 / J;
     const double h = A.op.h[i], ih = 1.0 / h, iH = iJ * ih;
     if (act) {
+      double uu[NC], lm[NC];
       const int uo = A.uoff[eg];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -159,6 +159,15 @@ __global__ __launch_bounds__(kT, W) void k_vjp3v(KArgs<double> A) {
           Gw[1][c] += s1 * v[20 + c];
           Gw[2][c] += s2 * v[20 + c];
         }
+      }
+      // this node's state and cotangent: re-read after the pair loop (from
+      // L1/L2) rather than held in registers across it
+      const int uo = A.uoff[eg];
+      double uu[NC], lm[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        uu[c] = A.u[uo + c * NP + i];
+        lm[c] = A.lam[uo + c * NP + i];
       }
       const double *v = nd + e * NDS + i * 25;
       double El[D], ak[D];
@@ -229,7 +238,7 @@ __global__ __launch_bounds__(kT, W) void k_vjp3v(KArgs<double> A) {
         const double Hv = A.Hn[(size_t)(q / NFN) * NP + q % NFN];
         double mu[NC], g1[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) mu[c] = lm[c] * iH - lv[c] / Hv;
+        for (int c = 0; c < NC; ++c) mu[c] = v[c] - lv[c] / Hv;
         Node<D, double> nk = n, nv;
         node_powers<D, double>(G, nk);
         node_from_u<D, double>(uv, G, nv);
@@ -238,7 +247,6 @@ __global__ __launch_bounds__(kT, W) void k_vjp3v(KArgs<double> A) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) ub[c] -= g1[c];
       }
-      const int uo = A.uoff[eg];
 #pragma unroll
       for (int c = 0; c < NC; ++c) A.ubar[uo + c * NP + i] = ub[c];
     }
@@ -278,9 +286,10 @@ struct Vjp2 {
     const GasC<double> &G = A.G;
     const GasC<Dual<double>> GD = dual_gas(G);
     const double cb = G.cb, he = 0.5 * (1.0 + cb), hz = 0.5 * (1.0 - cb);
-    double uu[NC], lm[NC], lam[4], H = 1.0, s[D][NC];
+    double lam[4], H = 1.0;
     Node<D, double> n;
     if (act) {
+      double uu[NC], lm[NC], s[D][NC];
       const double *g = A.geo + (size_t)eg * 12;
       double F[2][2] = {{0, 0}, {0, 0}};
 #pragma unroll
@@ -339,6 +348,16 @@ struct Vjp2 {
           X1[c] += c1 * v[12 + c];
         }
       }
+      // this node's state, cotangent and s_i: re-read after the pair loop
+      // (from L1/L2 and LDS) rather than held in registers across it
+      const int uo = A.uoff[eg];
+      const double *vo = L.nd + e * NDS + j * 20;  // lambda/H, s_0/H, s_1/H, w
+      double uu[NC], lm[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        uu[c] = A.u[uo + c * NP + j];
+        lm[c] = A.lam[uo + c * NP + j];
+      }
       const double E0 = A.op.E[j], E1 = A.op.E[NP + j];
       double ak[D];
       ak[0] = lam[0] * E0 + lam[1] * E1;
@@ -352,7 +371,7 @@ struct Vjp2 {
       for (int i = 0; i < D; ++i) {
         double zi[NC], o[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) zi[c] = hz * (i == 0 ? Z0[c] : Z1[c]) + he * ak[i] * lm[c] * iH;
+        for (int c = 0; c < NC; ++c) zi[c] = hz * (i == 0 ? Z0[c] : Z1[c]) + he * ak[i] * vo[c];
         flux_jac_T<D, double>(n, G, uu[NC - 1], i, zi, o);
 #pragma unroll
         for (int c = 0; c < NC; ++c) ub[c] += o[c];
@@ -361,7 +380,7 @@ struct Vjp2 {
       // sum_i Q_xi^T s_i = -V_s/2 + 1/2 sum_i a_i s_i,  g_i = H^-1 (X_i + a_i w)/2
       double y[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) y[c] = -0.5 * Vs[c] + 0.5 * iH * (ak[0] * s[0][c] + ak[1] * s[1][c]);
+      for (int c = 0; c < NC; ++c) y[c] = -0.5 * Vs[c] + 0.5 * (ak[0] * vo[4 + c] + ak[1] * vo[8 + c]);
 #pragma unroll
       for (int i = 0; i < D; ++i) {
         double gi[NC], du[NC];
@@ -398,7 +417,7 @@ struct Vjp2 {
         const double Hv = A.Hn[(size_t)(q / NFN) * NP + q % NFN];
         double mu[NC], g1[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) mu[c] = lm[c] * iH - lv[c] / Hv;
+        for (int c = 0; c < NC; ++c) mu[c] = vo[c] - lv[c] / Hv;
         Node<D, double> nk = n, nv;
         node_powers<D, double>(G, nk);
         node_from_u<D, double>(uv, G, nv);
@@ -407,7 +426,6 @@ struct Vjp2 {
 #pragma unroll
         for (int c = 0; c < NC; ++c) ub[c] -= g1[c];
       }
-      const int uo = A.uoff[eg];
 #pragma unroll
       for (int c = 0; c < NC; ++c) A.ubar[uo + c * NP + j] = ub[c];
     }
