@@ -203,20 +203,23 @@ def _tune(args, mesh, u, lam=None):
 
 
 def _time_calls(fn, reps, warm):
-    """Median and mean duration of single calls, HIP events on torch's current
-    stream (the stream the library launches on)."""
+    """Mean duration of one call over `reps` back-to-back calls between two
+    HIP events on torch's current stream (the stream the library launches
+    on); events around every single call would add an event packet and its
+    dispatch gap (about 6 us on MI355X) to each."""
     import torch
     for _ in range(warm):
         fn()
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    for a, b in ev:
-        a.record()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
         fn()
-        b.record()
+    b.record()
     torch.cuda.synchronize()
-    t = np.array([a.elapsed_time(b) for a, b in ev]) * 1e-3
-    return float(np.median(t)), float(np.mean(t))
+    t = a.elapsed_time(b) * 1e-3 / reps
+    return float(t), float(t)
 
 
 def _variant(mesh, kind, p):
@@ -246,7 +249,7 @@ class Runner:
         self.calls = []
 
     def reps(self, big=False):
-        return 5 if big else max(5, self.args.steps // 2)
+        return 5 if big else max(10, self.args.steps)
 
     def measure(self, key, fn, mesh=None, slot=None, big=False):
         """Median call time (timing mode) or marker-bracketed probe runs; slot
@@ -266,6 +269,7 @@ class Runner:
                     nvar += 1
                 except Exception:
                     break
+        print(f"[probe] {key} ({nvar} variant{'s' if nvar > 1 else ''})", file=sys.stderr, flush=True)
         for v in range(nvar):
             if nvar > 1:
                 mesh.set_launch_shape(slot[0], slot[1], v, g0)
@@ -837,38 +841,35 @@ def main():
         for p in ps:
             meshes[p].residual(states[p], outs[p])
     torch.cuda.synchronize()
-    # the dominant kernel (the highest degree) is bracketed by HIP events on the
-    # stream the kernels run on (torch's current stream) inside the timed
-    # region; events around every launch would add about 20 us per step
+    # the dominant kernel (the highest degree) is timed inside the timed
+    # region by HIP events attached to its dispatches (sbp_time_launches: the
+    # kernel's own start and end; the runtime still leaves a gap of a few
+    # microseconds before each such dispatch, so only this kernel is timed);
+    # two stream events bracket the whole region
     dom = max(ps)
-    evs = []
+    meshes[dom].time_launches(args.steps)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record()
     for _ in range(args.steps):
         for p in ps:
-            if p == dom:
-                a = torch.cuda.Event(enable_timing=True)
-                b = torch.cuda.Event(enable_timing=True)
-                a.record()
-                meshes[p].residual(states[p], outs[p])
-                b.record()
-                evs.append((a, b))
-            else:
-                meshes[p].residual(states[p], outs[p])
+            meshes[p].residual(states[p], outs[p])
     t1.record()
     torch.cuda.synchronize()
     total = t0.elapsed_time(t1) * 1e-3
     ms_per_step = total / args.steps * 1e3
     value = dofs / (total / args.steps)
-    kern = {dom: float(np.mean([a.elapsed_time(b) for a, b in evs])) * 1e-3}
+    ms = meshes[dom].launch_times(args.steps)
+    meshes[dom].time_launches(0)
+    assert len(ms) == args.steps
+    kern = {dom: float(np.mean(ms)) * 1e-3}
     for p in ps:
         meshes[p].check_device()
-    # the other degrees' launch times, after the timed region
+    # the other degrees' kernels after the timed region, back to back
     for p in ps:
         if p != dom:
-            kern[p], _ = _time_calls(lambda: meshes[p].residual(states[p], outs[p]), max(5, args.steps), 2)
+            kern[p], _ = _time_calls(lambda: meshes[p].residual(states[p], outs[p]), max(10, args.steps), 2)
     n_f = sbp.reference_operator(2, dom)["n_f"]
     fl, by = work_split(2, n_p[dom], n_f)
     dom_variant = _variant(meshes[dom], "residual", dom)
@@ -887,8 +888,9 @@ def main():
                                     "with EC SATs, FP64, one residual for each p = 1,2,3,4 per step",
                            n_elem=ne, degrees=list(ps), n_p=n_p,
                            kernel_ms={p: kern[p] * 1e3 for p in ps},
-                           kernel_ms_note=f"p={dom}: mean over the timed launches (HIP events); other p: "
-                                          f"median of separate launches after the timed region",
+                           kernel_ms_note=f"p={dom}: mean kernel duration of its launches in the timed "
+                                          f"region (HIP events attached to the dispatches); other p: mean of "
+                                          f"back-to-back launches after the timed region",
                            launch_shapes={p: tuned[p] for p in ps}),
                roofline=roof)
     if not args.no_extras:

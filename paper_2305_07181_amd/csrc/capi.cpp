@@ -110,6 +110,11 @@ struct sbp_mesh {
   // mode), replayed on the caller's stream; captured on a private stream of
   // default priority
   int use_graphs = 1;
+  // launch timing of sbp_residual (sbp_time_launches): event pairs attached
+  // to the degree classes' residual dispatches, in call order
+  std::vector<hipEvent_t> tev;
+  int tev_n = 0;
+  bool timing_call = false;   // set inside sbp_residual only (never under capture)
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t rk_exec = nullptr;
   const void *rk_u = nullptr;
@@ -737,18 +742,24 @@ int residual_core(sbp_mesh *M, const Work &W, const double *u, void *r, double *
     return SBP_OK;
   }
   for (auto &c : M->cls) {
+    sbp::LaunchCfg cfg = c.res_cfg;
+    if (M->timing_call && 2 * (size_t)M->tev_n + 1 < M->tev.size()) {
+      cfg.t0 = M->tev[2 * M->tev_n];
+      cfg.t1 = M->tev[2 * M->tev_n + 1];
+      ++M->tev_n;
+    }
     if (ph.precision == SBP_FP64) {
       sbp::KArgs<double> A = kargs<double>(M, c, u, r, c.op64);
       A.ent_part = W.part + c.part_off;
       A.eform = M->eform;
       A.form_id = ph.form;
-      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, A, s, c.res_cfg));
+      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, A, s, cfg));
     } else {
       sbp::KArgs<float> A = kargs<float>(M, c, u, r, c.op32);
       A.ent_part = W.part + c.part_off;
       A.eform = M->eform;
       A.form_id = ph.form;
-      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, A, s, c.res_cfg));
+      HIPCHK(sbp::launch_residual(M->dim, c.p, ph.form, A, s, cfg));
     }
     if (hyb && (rc = other_launch(c))) return rc;
   }
@@ -1275,7 +1286,37 @@ int sbp_mesh_info(sbp_mesh *M, sbp_info *out) {
 
 int sbp_residual(sbp_mesh *M, const void *u, void *r, double *ent_dev, void *stream) {
   if (!M || !u || !r) return fail(SBP_EINVAL, "null argument");
-  return residual_impl(M, handle_work(M), (const double *)u, r, ent_dev, (hipStream_t)stream);
+  M->timing_call = !M->tev.empty();
+  const int rc = residual_impl(M, handle_work(M), (const double *)u, r, ent_dev, (hipStream_t)stream);
+  M->timing_call = false;
+  return rc;
+}
+
+int sbp_time_launches(sbp_mesh *M, int capacity) {
+  if (!M || capacity < 0 || capacity > 65536) return fail(SBP_EINVAL, "null handle or capacity outside 0..65536");
+  for (hipEvent_t e : M->tev) (void)hipEventDestroy(e);
+  M->tev.clear();
+  M->tev_n = 0;
+  for (int i = 0; i < 2 * capacity; ++i) {
+    hipEvent_t e = nullptr;
+    HIPCHK(hipEventCreate(&e));
+    M->tev.push_back(e);
+  }
+  return SBP_OK;
+}
+
+int sbp_launch_times(sbp_mesh *M, double *ms_out, int max, int *n_out) {
+  if (!M || !n_out || (max > 0 && !ms_out)) return fail(SBP_EINVAL, "null argument");
+  const int n = std::min(M->tev_n, std::max(0, max));
+  for (int i = 0; i < n; ++i) {
+    HIPCHK(hipEventSynchronize(M->tev[2 * i + 1]));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, M->tev[2 * i], M->tev[2 * i + 1]));
+    ms_out[i] = ms;
+  }
+  *n_out = n;
+  M->tev_n = 0;
+  return SBP_OK;
 }
 
 int sbp_residual_noalloc(sbp_mesh *M, const void *u, void *r, double *ent_dev, void *stream) {
@@ -1625,6 +1666,7 @@ int sbp_rrk_step(sbp_mesh *M, void *u_dev, double dt, double cfl, sbp_rrk_report
 
 int sbp_destroy_mesh(sbp_mesh *M) {
   if (!M) return SBP_OK;
+  for (hipEvent_t e : M->tev) (void)hipEventDestroy(e);
   for (auto &c : M->cls) {
     (void)hipFree(c.d_uoff);
     (void)hipFree(c.d_gid);

@@ -25,6 +25,7 @@
 // fixed order (each pair evaluated from both of its rows), then shares the
 // facet epilogue.  In the hybrid scheme (Sec. 4.4) each kernel skips the
 // elements flagged for the other volume form.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -2075,6 +2076,7 @@ static hipError_t launch_t(int dim, int p, int form, const KArgs<T> &A, hipStrea
   const int nb = launch_grid(k.fn, (A.n_elem + k.eb - 1) / k.eb, cfg.grid);
   KArgs<T> a = A;
   void *args[] = {&a};
+  if (cfg.t0 && cfg.t1) return hipExtLaunchKernel(k.fn, dim3(nb), dim3(kThreads), args, 0, s, cfg.t0, cfg.t1, 0);
   return hipLaunchKernel(k.fn, dim3(nb), dim3(kThreads), args, 0, s);
 }
 

@@ -27,7 +27,8 @@ SYMBOLS = ["sbp_setup_mesh", "sbp_mesh_info", "sbp_residual", "sbp_residual_vjp"
            "sbp_diagnostics", "sbp_check_device", "sbp_set_time", "sbp_destroy_mesh",
            "sbp_last_error", "sbp_reference_operator", "sbp_use_graphs", "sbp_autotune",
            "sbp_get_launch_shape", "sbp_set_launch_shape", "sbp_set_volume_form", "sbp_set_source",
-           "sbp_source_state", "sbp_source_error", "sbp_residual_noalloc"]
+           "sbp_source_state", "sbp_source_error", "sbp_residual_noalloc", "sbp_time_launches",
+           "sbp_launch_times"]
 
 
 class SbpError(RuntimeError):
@@ -95,6 +96,8 @@ def load_library(path: str = _LIB_PATH):
     lib.sbp_source_state.argtypes = [P, C.c_double, P, P]
     lib.sbp_source_error.argtypes = [P, P, C.c_double, C.c_int32, P, P]
     lib.sbp_destroy_mesh.argtypes = [P]
+    lib.sbp_time_launches.argtypes = [P, C.c_int32]
+    lib.sbp_launch_times.argtypes = [P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32)]
     lib.sbp_last_error.restype = C.c_char_p
     lib.sbp_reference_operator.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                            C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -354,6 +357,19 @@ class Mesh:
 
     def use_graphs(self, enable=True):
         _check(_lib.sbp_use_graphs(self._h, int(bool(enable))))
+
+    def time_launches(self, capacity):
+        """sbp_time_launches: record the residual kernels' own durations of
+        the next `capacity` launches of sbp_residual (0: stop)."""
+        _check(_lib.sbp_time_launches(self._h, int(capacity)))
+
+    def launch_times(self, max_n=65536):
+        """sbp_launch_times: the recorded kernel durations in ms (waits for
+        them), oldest first; clears the record."""
+        out = np.zeros(max(1, int(max_n)))
+        n = C.c_int32()
+        _check(_lib.sbp_launch_times(self._h, _dp(out), int(max_n), C.byref(n)))
+        return out[:n.value].copy()
 
     def diagnostics(self, u, stream=None):
         """sbp_diagnostics: [sum H s, sum H u per component (n_c values),

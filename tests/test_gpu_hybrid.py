@@ -51,6 +51,15 @@ def test_hybrid_vs_oracle(dim, p, diss):
     assert abs(float(er.cpu()[0]) - rate_o) <= 1e-12 * scale
     if not diss:
         assert abs(float(er.cpu()[0])) <= 1e-12 * scale
+    if dim == 2:
+        # every launch variant of the split kernel with the same flags
+        for v in range(1, 3):
+            mesh.set_launch_shape("residual", p, v, 1)
+            rv = mesh.residual(torch.from_numpy(u).cuda())
+            mesh.check_device()
+            errv = rel_err_per_component(rv.cpu().numpy(), ro)
+            say(f"   variant {v}: rel err {errv.max():.1e}")
+            assert (errv <= 1e-12).all(), (v, errv)
     mesh.close()
 
 
