@@ -70,6 +70,22 @@ struct KArgs {
   const JumpC<T> *jc;  // binomial coefficients of the node powers (node_near)
 };
 
+// Map-node coordinate idx of an element (g: its FP64 map nodes) for the
+// metric sums F = sum_a dN_a g_a, with `first` the index of the same
+// coordinate of the element's first map node.  In FP32 the coordinate is
+// taken relative to that node, in FP64 before rounding: the basis
+// derivatives sum to zero, so F is unchanged in exact arithmetic, and the
+// small differences keep FP32's digits (absolute coordinates of O(10)
+// against an element size of O(0.1) would lose about seven bits of every
+// metric term).  FP64 takes the coordinates as they are.
+template <typename T>
+__device__ __forceinline__ T map_node(const double *g, int idx, int first) {
+  if constexpr (sizeof(T) == 4)
+    return (T)(g[idx] - g[first]);
+  else
+    return (T)g[idx];
+}
+
 // Tile order of a persistent workgroup.  The chip dispatches workgroups to
 // its 8 XCDs (each with its own L2) round-robin by workgroup index, so
 // workgroup b runs on XCD b mod 8.  When the grid is a multiple of 8, each

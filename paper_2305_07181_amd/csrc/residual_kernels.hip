@@ -548,7 +548,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_split3c(KArgs<T> A) {
     if (!tile_on(A, e0, ne)) continue;  // hybrid scheme: no element of this form
     const bool act = tid < ne * NP && elem_on(A, e0 + e);
     __syncthreads();
-    for (int x = tid; x < ne * 30; x += kThreads) gs[x / 30][x % 30] = (T)A.geo[(size_t)(e0 + x / 30) * 30 + x % 30];
+    for (int x = tid; x < ne * 30; x += kThreads) gs[x / 30][x % 30] = map_node<T>(A.geo + (size_t)(e0 + x / 30) * 30, x % 30, x % 3);
     __syncthreads();
     Node<D, T> n;
     T L[D][D], J = (T)1;
@@ -816,7 +816,7 @@ struct Split2 {
 #pragma unroll
         for (int a = 0; a < 6; ++a) {
           const T d0 = A.op.dN[(0 * 6 + a) * NP + i], d1 = A.op.dN[(1 * 6 + a) * NP + i];
-          const T gx = (T)g[2 * a], gy = (T)g[2 * a + 1];
+          const T gx = map_node<T>(g, 2 * a, 0), gy = map_node<T>(g, 2 * a + 1, 1);
           F[0][0] += d0 * gx;
           F[0][1] += d1 * gx;
           F[1][0] += d0 * gy;
@@ -975,7 +975,7 @@ struct Split2 {
 #pragma unroll
         for (int a = 0; a < 6; ++a) {
           const T d0 = A.op.dN[(0 * 6 + a) * NP + i], d1 = A.op.dN[(1 * 6 + a) * NP + i];
-          const T gx = (T)g[2 * a], gy = (T)g[2 * a + 1];
+          const T gx = map_node<T>(g, 2 * a, 0), gy = map_node<T>(g, 2 * a + 1, 1);
           F[0][0] += d0 * gx;
           F[0][1] += d1 * gx;
           F[1][0] += d0 * gy;
@@ -1266,7 +1266,9 @@ __global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
     __syncthreads();
     if constexpr (DIM == 3) {
       constexpr int GS = CURVED ? 30 : 10;
-      for (int x = tid; x < ne * GS; x += kThreads) gm[x / GS][x % GS] = (T)A.geo[(size_t)(e0 + x / GS) * GS + x % GS];
+      for (int x = tid; x < ne * GS; x += kThreads)
+        gm[x / GS][x % GS] = CURVED ? map_node<T>(A.geo + (size_t)(e0 + x / GS) * GS, x % GS, x % 3)
+                                    : (T)A.geo[(size_t)(e0 + x / GS) * GS + x % GS];
       if constexpr (CURVED) __syncthreads();  // the map nodes feed the per-node metrics below
     }
     Node<D, T> nodes[NT];
@@ -1296,10 +1298,11 @@ __global__ __launch_bounds__(kThreads) void k_hadamard(KArgs<T> A) {
 #pragma unroll
         for (int a = 0; a < 6; ++a) {
           const T d0 = A.op.dN[(0 * 6 + a) * NP + j], d1 = A.op.dN[(1 * 6 + a) * NP + j];
-          F[0][0] += d0 * (T)g[2 * a];
-          F[0][1] += d1 * (T)g[2 * a];
-          F[1][0] += d0 * (T)g[2 * a + 1];
-          F[1][1] += d1 * (T)g[2 * a + 1];
+          const T gx = map_node<T>(g, 2 * a, 0), gy = map_node<T>(g, 2 * a + 1, 1);
+          F[0][0] += d0 * gx;
+          F[0][1] += d1 * gx;
+          F[1][0] += d0 * gy;
+          F[1][1] += d1 * gy;
         }
         met[0][e][j] = F[1][1];
         met[1][e][j] = -F[1][0];
@@ -1447,7 +1450,7 @@ __global__ __launch_bounds__(kThreads) void k_visc_q2(KArgs<T> A) {
 #pragma unroll
       for (int a = 0; a < 6; ++a) {
         const T d0 = A.op.dN[(0 * 6 + a) * NP + i], d1 = A.op.dN[(1 * 6 + a) * NP + i];
-        const T gx = (T)g[2 * a], gy = (T)g[2 * a + 1];
+        const T gx = map_node<T>(g, 2 * a, 0), gy = map_node<T>(g, 2 * a + 1, 1);
         F[0][0] += d0 * gx;
         F[0][1] += d1 * gx;
         F[1][0] += d0 * gy;
@@ -1535,7 +1538,7 @@ __global__ __launch_bounds__(kThreads) void k_visc2(KArgs<T> A) {
 #pragma unroll
       for (int a = 0; a < 6; ++a) {
         const T d0 = A.op.dN[(0 * 6 + a) * NP + i], d1 = A.op.dN[(1 * 6 + a) * NP + i];
-        const T gx = (T)g[2 * a], gy = (T)g[2 * a + 1];
+        const T gx = map_node<T>(g, 2 * a, 0), gy = map_node<T>(g, 2 * a + 1, 1);
         F[0][0] += d0 * gx;
         F[0][1] += d1 * gx;
         F[1][0] += d0 * gy;
@@ -1722,7 +1725,7 @@ __global__ __launch_bounds__(kThreads) void k_visc_q3c(KArgs<T> A) {
     const int ne = min(EB, A.n_elem - e0);
     const bool act = tid < ne * NP;
     __syncthreads();
-    for (int x = tid; x < ne * 30; x += kThreads) gs[x / 30][x % 30] = (T)A.geo[(size_t)(e0 + x / 30) * 30 + x % 30];
+    for (int x = tid; x < ne * 30; x += kThreads) gs[x / 30][x % 30] = map_node<T>(A.geo + (size_t)(e0 + x / 30) * 30, x % 30, x % 3);
     __syncthreads();
     Node<D, T> n;
     T L[D][D], J = (T)1;
@@ -1803,7 +1806,7 @@ __global__ __launch_bounds__(kThreads) void k_visc3c(KArgs<T> A) {
     const int ne = min(EB, A.n_elem - e0);
     const bool act = tid < ne * NP;
     __syncthreads();
-    for (int x = tid; x < ne * 30; x += kThreads) gs[x / 30][x % 30] = (T)A.geo[(size_t)(e0 + x / 30) * 30 + x % 30];
+    for (int x = tid; x < ne * 30; x += kThreads) gs[x / 30][x % 30] = map_node<T>(A.geo + (size_t)(e0 + x / 30) * 30, x % 30, x % 3);
     __syncthreads();
     Node<D, T> n;
     T L[D][D], J = (T)1;
