@@ -45,35 +45,35 @@ PEAK_F32 = 157.3e12        # FLOP/s (vector and dense MFMA)
 # `bench.py --probe-kernels`, calibrated against a plain device copy; see
 # profiles/hbm_bytes_all_families.md), keyed "<row>/<name>/v<variant>".
 # Valid only for the kernel sources they were taken on (TRAFFIC_SHA).
-TRAFFIC_SHA = "f15a7fea40228f20"
+TRAFFIC_SHA = "2ed8a9a730c5787f"
 TRAFFIC = {
-    "batch48/fwd/v0": 2.88e+08,
+    "batch48/fwd/v0": 2.881e+08,
     "batch48/vjp/v0": 5.152e+08,
     "jitter_p1/fp64_split/v0": 2.561e+07,
     "jitter_p1/fp64_split/v1": 1.731e+07,
-    "jitter_p1/fp64_split/v2": 2.636e+07,
+    "jitter_p1/fp64_split/v2": 2.633e+07,
     "jitter_p2/fp64_split/v0": 2.654e+07,
     "jitter_p2/fp64_split/v1": 2.636e+07,
-    "jitter_p2/fp64_split/v2": 2.668e+07,
+    "jitter_p2/fp64_split/v2": 2.669e+07,
     "jitter_p3/fp64_split/v0": 4.419e+07,
     "jitter_p3/fp64_split/v1": 4.398e+07,
-    "jitter_p3/fp64_split/v2": 4.434e+07,
+    "jitter_p3/fp64_split/v2": 4.435e+07,
     "jitter_p4/fp64_split/v0": 5.322e+07,
     "jitter_p4/fp64_split/v1": 5.304e+07,
-    "jitter_p4/fp64_split/v2": 5.39e+07,
+    "jitter_p4/fp64_split/v2": 5.388e+07,
     "ns_tgv_82944_p3/fp32_residual/v0": 7.988e+08,
     "ns_tgv_82944_p3/fp64_residual/v0": 1.23e+09,
-    "ns_tgv_82944_p3/fp64_vjp/v0": 5.451e+09,
-    "tet_p2_tgv_196608/fp32_split/v0": 6.686e+08,
-    "tet_p2_tgv_196608/fp32_split/v1": 6.975e+08,
-    "tet_p2_tgv_196608/fp64_hadamard/v0": 7.257e+08,
+    "ns_tgv_82944_p3/fp64_vjp/v0": 5.449e+09,
+    "tet_p2_tgv_196608/fp32_split/v0": 6.68e+08,
+    "tet_p2_tgv_196608/fp32_split/v1": 6.971e+08,
+    "tet_p2_tgv_196608/fp64_hadamard/v0": 7.26e+08,
     "tet_p2_tgv_196608/fp64_split/v0": 7.29e+08,
     "tet_p2_tgv_196608/fp64_split/v1": 7.294e+08,
-    "tet_p2_tgv_196608/fp64_vjp/v0": 3.448e+09,
+    "tet_p2_tgv_196608/fp64_vjp/v0": 3.446e+09,
     "tet_p2_tgv_196608/fp64_vjp/v1": 1.34e+09,
-    "tet_p2_tgv_196608_curved/fp32_split/v0": 7.28e+08,
+    "tet_p2_tgv_196608_curved/fp32_split/v0": 7.273e+08,
     "tet_p2_tgv_196608_curved/fp64_hadamard/v0": 7.223e+08,
-    "tet_p2_tgv_196608_curved/fp64_split/v0": 7.615e+08,
+    "tet_p2_tgv_196608_curved/fp64_split/v0": 7.614e+08,
     "tet_p2_tgv_196608_curved/fp64_vjp/v0": 1.373e+09,
     "tet_p2_tgv_196608_curved/fp64_vjp/v1": 5.657e+09,
     "tet_p3_tgv_196608/fp32_split/v0": 1.146e+09,
@@ -81,7 +81,7 @@ TRAFFIC = {
     "tet_p3_tgv_196608/fp64_hadamard/v0": 1.243e+09,
     "tet_p3_tgv_196608/fp64_split/v0": 1.393e+09,
     "tet_p3_tgv_196608/fp64_split/v1": 1.386e+09,
-    "tet_p3_tgv_196608/fp64_vjp/v0": 7.438e+09,
+    "tet_p3_tgv_196608/fp64_vjp/v0": 7.442e+09,
     "tet_p3_tgv_196608/fp64_vjp/v1": 2.418e+09,
     "tet_p3_tgv_196608_curved/fp32_split/v0": 1.186e+09,
     "tet_p3_tgv_196608_curved/fp64_hadamard/v0": 1.278e+09,
@@ -91,36 +91,36 @@ TRAFFIC = {
     "tri_p1/fp32_split/v0": 2.243e+07,
     "tri_p1/fp32_split/v1": 2.246e+07,
     "tri_p1/fp32_split/v2": 2.229e+07,
-    "tri_p1/fp64_hadamard/v0": 2.606e+07,
+    "tri_p1/fp64_hadamard/v0": 2.605e+07,
     "tri_p1/fp64_hadamard_vjp/v0": 4.683e+07,
     "tri_p1/fp64_split/v0": 2.558e+07,
     "tri_p1/fp64_split/v1": 1.73e+07,
-    "tri_p1/fp64_split/v2": 2.653e+07,
+    "tri_p1/fp64_split/v2": 2.655e+07,
     "tri_p1/fp64_vjp/v0": 1.214e+08,
     "tri_p1/fp64_vjp/v1": 4.689e+07,
-    "tri_p2/fp32_split/v0": 3.558e+07,
+    "tri_p2/fp32_split/v0": 3.57e+07,
     "tri_p2/fp32_split/v1": 2.106e+07,
     "tri_p2/fp32_split/v2": 3.355e+07,
-    "tri_p2/fp64_hadamard/v0": 4.084e+07,
+    "tri_p2/fp64_hadamard/v0": 4.085e+07,
     "tri_p2/fp64_hadamard_vjp/v0": 7.22e+07,
     "tri_p2/fp64_split/v0": 2.65e+07,
     "tri_p2/fp64_split/v1": 2.633e+07,
-    "tri_p2/fp64_split/v2": 2.678e+07,
-    "tri_p2/fp64_vjp/v0": 7.274e+07,
-    "tri_p2/fp64_vjp/v1": 7.247e+07,
-    "tri_p3/fp32_split/v0": 3.555e+07,
+    "tri_p2/fp64_split/v2": 2.676e+07,
+    "tri_p2/fp64_vjp/v0": 7.276e+07,
+    "tri_p2/fp64_vjp/v1": 7.244e+07,
+    "tri_p3/fp32_split/v0": 3.534e+07,
     "tri_p3/fp32_split/v1": 3.445e+07,
-    "tri_p3/fp32_split/v2": 3.454e+07,
-    "tri_p3/fp64_hadamard/v0": 6.695e+07,
+    "tri_p3/fp32_split/v2": 3.456e+07,
+    "tri_p3/fp64_hadamard/v0": 6.694e+07,
     "tri_p3/fp64_hadamard_vjp/v0": 1.182e+08,
     "tri_p3/fp64_split/v0": 4.416e+07,
     "tri_p3/fp64_split/v1": 4.396e+07,
     "tri_p3/fp64_split/v2": 4.434e+07,
     "tri_p3/fp64_vjp/v0": 1.291e+08,
     "tri_p3/fp64_vjp/v1": 1.183e+08,
-    "tri_p4/fp32_split/v0": 4.322e+07,
-    "tri_p4/fp32_split/v1": 4.141e+07,
-    "tri_p4/fp32_split/v2": 4.15e+07,
+    "tri_p4/fp32_split/v0": 4.288e+07,
+    "tri_p4/fp32_split/v1": 4.14e+07,
+    "tri_p4/fp32_split/v2": 4.151e+07,
     "tri_p4/fp64_hadamard/v0": 7.114e+07,
     "tri_p4/fp64_hadamard_vjp/v0": 1.215e+08,
     "tri_p4/fp64_split/v0": 5.319e+07,
@@ -924,10 +924,9 @@ def main():
             meshes[p].residual(states[p], outs[p])
     torch.cuda.synchronize()
     # the dominant kernel (the highest degree) is timed inside the timed
-    # region by HIP events attached to its dispatches (sbp_time_launches: the
-    # kernel's own start and end; the runtime still leaves a gap of a few
-    # microseconds before each such dispatch, so only this kernel is timed);
-    # two stream events bracket the whole region
+    # region by the kernel itself (sbp_time_launches: its earliest workgroup
+    # start and latest workgroup end on the device clock, no packets in the
+    # stream); two stream events bracket the whole region
     dom = max(ps)
     meshes[dom].time_launches(args.steps)
     t0 = torch.cuda.Event(enable_timing=True)
@@ -971,8 +970,9 @@ def main():
                            n_elem=ne, degrees=list(ps), n_p=n_p,
                            kernel_ms={p: kern[p] * 1e3 for p in ps},
                            kernel_ms_note=f"p={dom}: mean kernel duration of its launches in the timed "
-                                          f"region (HIP events attached to the dispatches); other p: mean of "
-                                          f"back-to-back launches after the timed region",
+                                          f"region (first workgroup start to last workgroup end, recorded by "
+                                          f"the kernel on the device clock); other p: mean of back-to-back "
+                                          f"launches after the timed region",
                            launch_shapes={p: tuned[p] for p in ps}),
                roofline=roof)
     if not args.no_extras:

@@ -286,22 +286,22 @@ int sbp_autotune(sbp_mesh *mesh, const void *u_dev, const void *lambda_dev, sbp_
 int sbp_get_launch_shape(sbp_mesh *mesh, int32_t kind, int32_t p, int32_t *variant, int32_t *grid);
 int sbp_set_launch_shape(sbp_mesh *mesh, int32_t kind, int32_t p, int32_t variant, int32_t grid);
 
-/* Launch timing (not in the paper; for benchmarks and profilers).
- * sbp_time_launches(mesh, capacity): from now on every sbp_residual call on
- * the handle records the start and end of each degree class's residual
- * kernel (not the batched launch of a 2D mesh with several degrees, the
- * Navier-Stokes facet pre-pass or the second kernel of the hybrid scheme),
- * in call order, until capacity launches are recorded; HIP events attached
- * to the kernel dispatch itself (hipExtLaunchKernel): the durations are
- * those of the kernels (the runtime still idles a few microseconds before
- * each timed dispatch, so time only what must be timed).  capacity 0
- * stops the recording; any call discards earlier records.  Other entry
- * points (RK steps, the allocation-free residual, the autotuner) are never
- * timed.  SBP_EINVAL for a null handle or capacity outside 0..65536.
- * sbp_launch_times(mesh, ms_out, max, n_out): waits for the recorded
- * launches, writes the first min(recorded, max) durations in milliseconds to
- * ms_out (host, caller-owned) and their count to *n_out, and clears the
- * record (recording continues). */
+/* Launch timing (not in the paper; for benchmarks and profilers) of the
+ * entropy-split residual kernel on triangles (meshes of one degree, Euler
+ * terms).  sbp_time_launches(mesh, capacity): from now on every sbp_residual
+ * call on the handle records the earliest workgroup start and the latest
+ * workgroup end of its kernel on the device's constant-rate clock
+ * (hipDeviceAttributeWallClockRate), in call order, until capacity launches
+ * are recorded; the kernel writes them itself, so the stream carries no
+ * extra packets.  capacity 0 stops the recording; any call discards earlier
+ * records; allocates the record (2 x 8 bytes per launch) and synchronises
+ * the device.  Other entry points (RK steps, the allocation-free residual,
+ * the autotuner) are never timed.  SBP_EINVAL for a null handle or capacity
+ * outside 0..65536; SBP_ENOTSUP (capacity > 0) for other meshes.
+ * sbp_launch_times(mesh, ms_out, max, n_out): synchronises the device,
+ * writes the first min(recorded, max) durations in milliseconds to ms_out
+ * (host, caller-owned) and their count to *n_out, and clears the record
+ * (recording continues). */
 int sbp_time_launches(sbp_mesh *mesh, int32_t capacity);
 int sbp_launch_times(sbp_mesh *mesh, double *ms_out, int32_t max, int32_t *n_out);
 

@@ -68,6 +68,9 @@ struct KArgs {
   // registers for the whole launch
   const ExpAvgC<T> *eac;
   const JumpC<T> *jc;  // binomial coefficients of the node powers (node_near)
+  // launch timing (2D entropy split): [0] earliest workgroup start, [1] latest
+  // workgroup end on the device's constant-rate clock, or null
+  unsigned long long *tstamp;
 };
 
 // Map-node coordinate idx of an element (g: its FP64 map nodes) for the

@@ -14,9 +14,6 @@ struct LaunchCfg {
   int variant = 0;  // 0: the built-in choice; 1: the alternative (see *_variants)
   int grid = 1;     // k > 0: k x (CUs x resident workgroups per CU), capped at
                     // one workgroup per tile; 0: one workgroup per tile
-  // optional events attached to the dispatch itself (start and end of the
-  // kernel, no packets of their own in the stream): launch timing
-  hipEvent_t t0 = nullptr, t1 = nullptr;
 };
 constexpr int kGridChoices[3] = {1, 2, 0};
 

@@ -25,7 +25,6 @@
 // fixed order (each pair evaluated from both of its rows), then shares the
 // facet epilogue.  In the hybrid scheme (Sec. 4.4) each kernel skips the
 // elements flagged for the other volume form.
-#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1156,6 +1155,9 @@ template <int P, typename T, int R, int EF = 0>
 __global__ __launch_bounds__(kThreads, R == 2 ? 2 : (P == 1 ? 2 : 3)) void k_split2(KArgs<T> A) {
   typedef Split2<P, T, R, EF> K;
   __shared__ typename K::Lds lds;
+  // launch timing: the earliest workgroup start and the latest workgroup end
+  // on the device's constant-rate clock
+  if (A.tstamp && threadIdx.x == 0) atomicMin(&A.tstamp[0], (unsigned long long)wall_clock64());
   K::load_ops(A, lds);
   __syncthreads();
   double ent = 0.0;
@@ -1177,6 +1179,7 @@ __global__ __launch_bounds__(kThreads, R == 2 ? 2 : (P == 1 ? 2 : 3)) void k_spl
     }
   }
   block_sum_store(ent, A.ent_part);
+  if (A.tstamp && threadIdx.x == 0) atomicMax(&A.tstamp[1], (unsigned long long)wall_clock64());
 }
 
 // All degree classes of a 2D mesh (batched problems) in one persistent
@@ -2079,7 +2082,6 @@ static hipError_t launch_t(int dim, int p, int form, const KArgs<T> &A, hipStrea
   const int nb = launch_grid(k.fn, (A.n_elem + k.eb - 1) / k.eb, cfg.grid);
   KArgs<T> a = A;
   void *args[] = {&a};
-  if (cfg.t0 && cfg.t1) return hipExtLaunchKernel(k.fn, dim3(nb), dim3(kThreads), args, 0, s, cfg.t0, cfg.t1, 0);
   return hipLaunchKernel(k.fn, dim3(nb), dim3(kThreads), args, 0, s);
 }
 

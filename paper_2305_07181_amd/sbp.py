@@ -359,8 +359,8 @@ class Mesh:
         _check(_lib.sbp_use_graphs(self._h, int(bool(enable))))
 
     def time_launches(self, capacity):
-        """sbp_time_launches: record the residual kernels' own durations of
-        the next `capacity` launches of sbp_residual (0: stop)."""
+        """sbp_time_launches: the 2D entropy-split kernel records its own
+        start and end for the next `capacity` sbp_residual calls (0: stop)."""
         _check(_lib.sbp_time_launches(self._h, int(capacity)))
 
     def launch_times(self, max_n=65536):
