@@ -37,7 +37,7 @@ def test_every_residual_launch_shape(dim, p, n, prec):
     ud = torch.from_numpy(u).cuda()
     assert mesh.launch_shape("residual", p) == (0, 1)
     r0, e0 = mesh.residual(ud, entropy_rate=True)
-    r0 = r0.double().cpu().numpy()
+    r0 = r0.cpu().double().numpy()
     e0 = float(e0.cpu()[0])
     els = [0, 1, m.ne // 2, m.ne - 1]
     sch = OracleScheme(m, ph.Gas(), dissipation=True)
@@ -66,7 +66,7 @@ def test_every_residual_launch_shape(dim, p, n, prec):
             assert mesh.launch_shape("residual", p) == (v, g)
             r, e = mesh.residual(ud, entropy_rate=True)
             mesh.check_device()
-            r = r.double().cpu().numpy()
+            r = r.cpu().double().numpy()
             if prec == 0:
                 d = np.abs(r - r0).max() / np.abs(r0).max()
             else:

@@ -130,7 +130,7 @@ def test_tri32768_sampled(p):
         r = mesh.residual(ud)
         mesh.check_device()
         ro2 = ro if sch2 is sch else sch2(u, elements=els)
-        _check_sampled(r.double().cpu().numpy(), ro2, sch2, u, els, tol, what)
+        _check_sampled(r.cpu().double().numpy(), ro2, sch2, u, els, tol, what)
         mesh.close()
 
 
@@ -178,7 +178,7 @@ def _tet_residual(p):
         r = mesh.residual(ud)
         mesh.check_device()
         ro2 = ro if sch2 is sch else sch2(u, elements=els)
-        _check_sampled(r.double().cpu().numpy(), ro2, sch2, u, els, tol, what)
+        _check_sampled(r.cpu().double().numpy(), ro2, sch2, u, els, tol, what)
         mesh.close()
 
 
@@ -257,7 +257,7 @@ def test_ns_tgv82944_sampled():
         _tuned(mesh, ud)
         r = mesh.residual(ud)
         mesh.check_device()
-        _check_sampled(r.double().cpu().numpy(), ro, sch, u, els, tol, what)
+        _check_sampled(r.cpu().double().numpy(), ro, sch, u, els, tol, what)
         mesh.close()
 
 

@@ -30,7 +30,7 @@ def _gpu_residual(desc, p, u, **kw):
     r, er = mesh.residual(ud, entropy_rate=True)
     torch.cuda.synchronize()
     mesh.check_device()
-    out = r.double().cpu().numpy(), float(er.cpu()[0])
+    out = r.cpu().double().numpy(), float(er.cpu()[0])
     mesh.close()
     return out
 
@@ -211,7 +211,7 @@ def test_parity_navier_stokes_tgv_fp32():
     u = state(m, "tgv")
     for prec, tol in ((sbp.FP64, TOL64), (sbp.FP32, 2e-6)):
         mesh = sbp.Mesh(desc, 3, dissipation=True, viscous=True, mu=1.0 / 1600, precision=prec)
-        r = mesh.residual(torch.from_numpy(u).cuda()).double().cpu().numpy()
+        r = mesh.residual(torch.from_numpy(u).cuda()).cpu().double().numpy()
         mesh.close()
         ro = sch(u)
         sc = term_scale(sch, u, list(range(m.ne)))

@@ -76,7 +76,7 @@ def test_navier_stokes_fp32_and_free_stream(kind, p):
     u = state(m, "random", seed=24, jitter=0.01)
     kw = dict(dissipation=True, viscous=True, mu=0.05, Pr=0.71, R=1.0)
     mesh = sbp.Mesh(desc, p, precision=sbp.FP32, **kw)
-    r = mesh.residual(torch.from_numpy(u).cuda()).double().cpu().numpy()
+    r = mesh.residual(torch.from_numpy(u).cuda()).cpu().double().numpy()
     mesh.check_device()
     mesh.close()
     els = list(range(m.ne))
