@@ -137,8 +137,10 @@ int sbp_residual(sbp_mesh *mesh, const void *u_dev, void *r_dev,
  * up to about 10^5 workgroup tiles; the message gives both sizes).  Every call
  * on a GPU shares that GPU's array and leaves its contents behind: calls that
  * overlap on one GPU (other streams, other threads) race and must be ordered
- * by the caller.  Nothing in the array needs to start at zero.  Not in the
- * paper. */
+ * by the caller.  Nothing in the array needs to start at zero.  The facet
+ * viscous fluxes that the two kernels of a Navier-Stokes residual exchange
+ * live in a buffer of the handle, allocated by sbp_setup_mesh, so calls on
+ * one handle must not overlap either.  Not in the paper. */
 int sbp_residual_noalloc(sbp_mesh *mesh, const void *u_dev, void *r_dev,
                          double *entropy_rate_dev, void *hip_stream);
 
