@@ -7,8 +7,9 @@ reported baseline.
 
 One timed step = one FP64 entropy-split residual evaluation for each degree
 p = 1..4 on the curved periodic 128x128x2 = 32768-triangle mesh (isentropic
-vortex state, inputs resident in HBM).  value = sum_p n_elem n_p(p) / step
-time.  The breakdown gives, per family (2D, 3D affine and curved
+vortex state, inputs resident in HBM), the four in one batched launch (one
+mesh holding four independent copies of the grid, one per degree).  value =
+sum_p n_elem n_p(p) / step time.  The breakdown gives, per family (2D, 3D affine and curved
 tetrahedra, Navier-Stokes, the 48-problem batch), the FP64 and FP32 entropy
 split, the Hadamard form and the VJP, each with its launch time and roofline
 (algorithmic flops and bytes per element, the bound, the fraction of peak,
@@ -45,49 +46,50 @@ PEAK_F32 = 157.3e12        # FLOP/s (vector and dense MFMA)
 # `bench.py --probe-kernels`, calibrated against a plain device copy; see
 # profiles/hbm_bytes_all_families.md), keyed "<row>/<name>/v<variant>".
 # Valid only for the kernel sources they were taken on (TRAFFIC_SHA).
-TRAFFIC_SHA = "0c41bcabfcc6c4f8"
+TRAFFIC_SHA = "7575f5c45d528dc8"
 TRAFFIC = {
     "batch48/fwd/v0": 2.881e+08,
     "batch48/vjp/v0": 5.152e+08,
     "jitter_p1/fp64_split/v0": 2.562e+07,
     "jitter_p1/fp64_split/v1": 1.732e+07,
-    "jitter_p1/fp64_split/v2": 2.592e+07,
+    "jitter_p1/fp64_split/v2": 2.616e+07,
     "jitter_p2/fp64_split/v0": 2.658e+07,
     "jitter_p2/fp64_split/v1": 2.637e+07,
-    "jitter_p2/fp64_split/v2": 2.673e+07,
+    "jitter_p2/fp64_split/v2": 2.672e+07,
     "jitter_p3/fp64_split/v0": 4.416e+07,
     "jitter_p3/fp64_split/v1": 4.397e+07,
-    "jitter_p3/fp64_split/v2": 4.439e+07,
+    "jitter_p3/fp64_split/v2": 4.434e+07,
     "jitter_p4/fp64_split/v0": 5.323e+07,
     "jitter_p4/fp64_split/v1": 5.305e+07,
-    "jitter_p4/fp64_split/v2": 5.389e+07,
-    "ns_tgv_82944_p3/fp32_residual/v0": 7.991e+08,
+    "jitter_p4/fp64_split/v2": 5.386e+07,
+    "ns_tgv_82944_p3/fp32_residual/v0": 7.989e+08,
     "ns_tgv_82944_p3/fp64_residual/v0": 1.23e+09,
-    "ns_tgv_82944_p3/fp64_vjp/v0": 5.449e+09,
-    "tet_p2_tgv_196608/fp32_split/v0": 6.681e+08,
-    "tet_p2_tgv_196608/fp32_split/v1": 6.976e+08,
-    "tet_p2_tgv_196608/fp64_hadamard/v0": 7.266e+08,
-    "tet_p2_tgv_196608/fp64_split/v0": 7.289e+08,
-    "tet_p2_tgv_196608/fp64_split/v1": 7.293e+08,
-    "tet_p2_tgv_196608/fp64_vjp/v0": 3.456e+09,
+    "ns_tgv_82944_p3/fp64_vjp/v0": 5.445e+09,
+    "tet_p2_tgv_196608/fp32_split/v0": 6.686e+08,
+    "tet_p2_tgv_196608/fp32_split/v1": 6.983e+08,
+    "tet_p2_tgv_196608/fp64_hadamard/v0": 7.245e+08,
+    "tet_p2_tgv_196608/fp64_split/v0": 7.29e+08,
+    "tet_p2_tgv_196608/fp64_split/v1": 7.296e+08,
+    "tet_p2_tgv_196608/fp64_vjp/v0": 3.451e+09,
     "tet_p2_tgv_196608/fp64_vjp/v1": 1.34e+09,
-    "tet_p2_tgv_196608_curved/fp32_split/v0": 7.259e+08,
-    "tet_p2_tgv_196608_curved/fp64_hadamard/v0": 7.223e+08,
-    "tet_p2_tgv_196608_curved/fp64_split/v0": 7.616e+08,
+    "tet_p2_tgv_196608_curved/fp32_split/v0": 7.262e+08,
+    "tet_p2_tgv_196608_curved/fp64_hadamard/v0": 7.22e+08,
+    "tet_p2_tgv_196608_curved/fp64_split/v0": 7.618e+08,
     "tet_p2_tgv_196608_curved/fp64_vjp/v0": 1.373e+09,
-    "tet_p2_tgv_196608_curved/fp64_vjp/v1": 5.657e+09,
-    "tet_p3_tgv_196608/fp32_split/v0": 1.146e+09,
-    "tet_p3_tgv_196608/fp32_split/v1": 1.192e+09,
-    "tet_p3_tgv_196608/fp64_hadamard/v0": 1.243e+09,
+    "tet_p2_tgv_196608_curved/fp64_vjp/v1": 5.66e+09,
+    "tet_p3_tgv_196608/fp32_split/v0": 1.147e+09,
+    "tet_p3_tgv_196608/fp32_split/v1": 1.193e+09,
+    "tet_p3_tgv_196608/fp64_hadamard/v0": 1.242e+09,
     "tet_p3_tgv_196608/fp64_split/v0": 1.393e+09,
     "tet_p3_tgv_196608/fp64_split/v1": 1.386e+09,
-    "tet_p3_tgv_196608/fp64_vjp/v0": 7.429e+09,
+    "tet_p3_tgv_196608/fp64_vjp/v0": 7.439e+09,
     "tet_p3_tgv_196608/fp64_vjp/v1": 2.418e+09,
     "tet_p3_tgv_196608_curved/fp32_split/v0": 1.186e+09,
     "tet_p3_tgv_196608_curved/fp64_hadamard/v0": 1.277e+09,
     "tet_p3_tgv_196608_curved/fp64_split/v0": 1.425e+09,
     "tet_p3_tgv_196608_curved/fp64_vjp/v0": 2.453e+09,
     "tet_p3_tgv_196608_curved/fp64_vjp/v1": 1.396e+10,
+    "tri_batch4/fwd/v0": 2.047e+08,
     "tri_p1/fp32_split/v0": 2.242e+07,
     "tri_p1/fp32_split/v1": 2.245e+07,
     "tri_p1/fp32_split/v2": 2.23e+07,
@@ -95,38 +97,38 @@ TRAFFIC = {
     "tri_p1/fp64_hadamard_vjp/v0": 4.683e+07,
     "tri_p1/fp64_split/v0": 2.559e+07,
     "tri_p1/fp64_split/v1": 1.73e+07,
-    "tri_p1/fp64_split/v2": 2.601e+07,
+    "tri_p1/fp64_split/v2": 2.606e+07,
     "tri_p1/fp64_vjp/v0": 1.214e+08,
     "tri_p1/fp64_vjp/v1": 4.689e+07,
-    "tri_p2/fp32_split/v0": 3.561e+07,
+    "tri_p2/fp32_split/v0": 3.564e+07,
     "tri_p2/fp32_split/v1": 2.106e+07,
-    "tri_p2/fp32_split/v2": 3.356e+07,
-    "tri_p2/fp64_hadamard/v0": 4.086e+07,
+    "tri_p2/fp32_split/v2": 3.355e+07,
+    "tri_p2/fp64_hadamard/v0": 4.1e+07,
     "tri_p2/fp64_hadamard_vjp/v0": 7.22e+07,
     "tri_p2/fp64_split/v0": 2.654e+07,
     "tri_p2/fp64_split/v1": 2.635e+07,
     "tri_p2/fp64_split/v2": 2.676e+07,
-    "tri_p2/fp64_vjp/v0": 7.269e+07,
-    "tri_p2/fp64_vjp/v1": 7.247e+07,
+    "tri_p2/fp64_vjp/v0": 7.273e+07,
+    "tri_p2/fp64_vjp/v1": 7.244e+07,
     "tri_p3/fp32_split/v0": 3.534e+07,
     "tri_p3/fp32_split/v1": 3.445e+07,
     "tri_p3/fp32_split/v2": 3.455e+07,
-    "tri_p3/fp64_hadamard/v0": 6.694e+07,
+    "tri_p3/fp64_hadamard/v0": 6.685e+07,
     "tri_p3/fp64_hadamard_vjp/v0": 1.182e+08,
     "tri_p3/fp64_split/v0": 4.412e+07,
     "tri_p3/fp64_split/v1": 4.395e+07,
-    "tri_p3/fp64_split/v2": 4.435e+07,
+    "tri_p3/fp64_split/v2": 4.438e+07,
     "tri_p3/fp64_vjp/v0": 1.291e+08,
     "tri_p3/fp64_vjp/v1": 1.183e+08,
-    "tri_p4/fp32_split/v0": 4.29e+07,
+    "tri_p4/fp32_split/v0": 4.293e+07,
     "tri_p4/fp32_split/v1": 4.14e+07,
-    "tri_p4/fp32_split/v2": 4.149e+07,
-    "tri_p4/fp64_hadamard/v0": 7.114e+07,
+    "tri_p4/fp32_split/v2": 4.15e+07,
+    "tri_p4/fp64_hadamard/v0": 7.119e+07,
     "tri_p4/fp64_hadamard_vjp/v0": 1.215e+08,
     "tri_p4/fp64_split/v0": 5.32e+07,
     "tri_p4/fp64_split/v1": 5.303e+07,
-    "tri_p4/fp64_split/v2": 5.392e+07,
-    "tri_p4/fp64_vjp/v0": 1.317e+08,
+    "tri_p4/fp64_split/v2": 5.387e+07,
+    "tri_p4/fp64_vjp/v0": 1.313e+08,
     "tri_p4/fp64_vjp/v1": 1.216e+08,
 }
 KERNEL_SOURCES = ["residual_kernels.hip", "vjp_kernels.hip", "rrk_kernels.hip", "device_physics.hpp",
@@ -274,6 +276,26 @@ def _state_from_mesh(mesh, kind, seed=0, jitter=0.0, L=20.0):
         # independent node values on the two sides of every facet
         u = u * (1.0 + jitter * np.random.default_rng(seed + 7).standard_normal(u.shape))
     return torch.from_numpy(np.ascontiguousarray(u)).cuda()
+
+
+def headline_mesh(desc, ps):
+    """One mesh of len(ps) independent copies of the grid `desc`, copy b of
+    degree ps[b] (a mesh of several degree classes: one batched launch per
+    residual), and the vortex state on it."""
+    import torch
+    from paper_2305_07181_amd import sbp, workloads as wl
+    d4, deg, off = wl.copies_mesh(desc, ps)
+    mesh = sbp.Mesh(d4, deg, problem_off=off)
+    x = mesh.node_coords().cpu().numpy()
+    u = np.zeros(int(mesh.n_nodes * mesh.n_c))
+    for b in range(len(ps)):
+        n_p = int(mesh.elem_np[off[b]])
+        e0, e1 = int(off[b]), int(off[b + 1])
+        lo, hi = int(mesh.node_off[e0]), int(mesh.node_off[e1])
+        X = np.moveaxis(x[lo * 2:hi * 2].reshape(e1 - e0, 2, n_p), 1, 0)
+        rho, V, pr = wl.isentropic_vortex(X)
+        u[lo * 4:hi * 4] = np.moveaxis(wl.conservative(rho, V, pr), 0, 1).ravel()
+    return mesh, torch.from_numpy(u).cuda()
 
 
 def _tune(args, mesh, u, lam=None):
@@ -901,7 +923,17 @@ def main():
         print(json.dumps({"tri": tri_rows(R, desc, meshes, states, lams)}))
         return
 
+    # the headline step: the four degrees' residuals as one batched launch
+    # (the four copies of the grid are independent problems of one mesh)
+    mb, ub = headline_mesh(desc, ps)
+    rb = torch.empty_like(ub)
+    tuned_b = _tune(args, mb, ub)
+    ne_b = int(mb.n_elem)
+    dofs = int(mb.n_nodes)
+    assert dofs == sum(ne * n_p[p] for p in ps)
+
     if R.probe:
+        R.measure("tri_batch4/fwd", lambda: mb.residual(ub, rb), mb, ("residual", 0))
         out = tri_rows(R, desc, meshes, states, lams)
         jitter_rows(R, desc)
         tet_rows(R, False)
@@ -915,110 +947,68 @@ def main():
         R.write()
         for p in ps:
             meshes[p].close()
+        mb.close()
         print(json.dumps(dict(probe_calls=len(R.calls), source_hash=kernel_source_hash())))
         return
 
-    def step_ms(reps=30, tries=3):
-        """Fastest of `tries` timings of `reps` back-to-back steps (ms/step)."""
-        best = None
-        for _ in range(tries):
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            for p in ps:
-                meshes[p].residual(states[p], outs[p])
-            a.record()
-            for _ in range(reps):
-                for p in ps:
-                    meshes[p].residual(states[p], outs[p])
-            b.record()
-            torch.cuda.synchronize()
-            t = a.elapsed_time(b) / reps
-            best = t if best is None else min(best, t)
-        return best
-
-    # setup (untimed): the autotuner times each degree's shapes on their own,
-    # launch after launch; the step runs the four kernels in turn, so each
-    # degree's shape is then checked in the step itself (one pass over the
-    # degrees, a shape kept only if the step gets faster by more than 1%)
-    step_shapes = {}
-    if not args.no_tune:
-        base = step_ms()
-        for p in sorted(ps, reverse=True):
-            v0, g0 = meshes[p].launch_shape("residual", p)
-            best = (base, v0, g0)
-            v = 0
-            while True:
-                try:
-                    meshes[p].set_launch_shape("residual", p, v, 1)
-                except Exception:
-                    break
-                for g in (1, 2, 0):
-                    meshes[p].set_launch_shape("residual", p, v, g)
-                    t = step_ms()
-                    if t < 0.99 * best[0]:
-                        best = (t, v, g)
-                v += 1
-            meshes[p].set_launch_shape("residual", p, best[1], best[2])
-            base = best[0]
-            step_shapes[p] = dict(variant=best[1], grid=best[2])
     for _ in range(args.warmup):
-        for p in ps:
-            meshes[p].residual(states[p], outs[p])
+        mb.residual(ub, rb)
     torch.cuda.synchronize()
-    # the dominant kernel (the highest degree) is timed inside the timed
-    # region by the kernel itself (sbp_time_launches: its earliest workgroup
-    # start and latest workgroup end on the device clock, no packets in the
-    # stream); two stream events bracket the whole region
-    dom = max(ps)
-    meshes[dom].time_launches(args.steps)
+    # the step's one launch is timed inside the timed region by the kernel
+    # itself (sbp_time_launches: its earliest workgroup start and latest
+    # workgroup end on the device clock, no packets in the stream); two stream
+    # events bracket the whole region
+    mb.time_launches(args.steps)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record()
     for _ in range(args.steps):
-        for p in ps:
-            meshes[p].residual(states[p], outs[p])
+        mb.residual(ub, rb)
     t1.record()
     torch.cuda.synchronize()
     total = t0.elapsed_time(t1) * 1e-3
     ms_per_step = total / args.steps * 1e3
     value = dofs / (total / args.steps)
-    ms = meshes[dom].launch_times(args.steps)
-    meshes[dom].time_launches(0)
+    ms = mb.launch_times(args.steps)
+    mb.time_launches(0)
     assert len(ms) == args.steps
-    kern = {dom: float(np.mean(ms)) * 1e-3}
+    kern_b = float(np.mean(ms)) * 1e-3
+    mb.check_device()
+    # each degree alone (its own mesh and launch), after the timed region
+    kern = {}
     for p in ps:
-        meshes[p].check_device()
-    # the other degrees' kernels after the timed region, back to back
+        kern[p], _ = _time_calls(lambda: meshes[p].residual(states[p], outs[p]), max(10, args.steps), 2)
+    fl = by = 0.0
     for p in ps:
-        if p != dom:
-            kern[p], _ = _time_calls(lambda: meshes[p].residual(states[p], outs[p]), max(10, args.steps), 2)
-    n_f = sbp.reference_operator(2, dom)["n_f"]
-    fl, by = work_split(2, n_p[dom], n_f)
-    dom_variant = _variant(meshes[dom], "residual", dom)
+        f1, b1 = work_split(2, n_p[p], sbp.reference_operator(2, p)["n_f"])
+        fl += f1 * ne
+        by += b1 * ne
     # the 2D kernel runs its pair sums and pointwise work on the FP64 vector
     # ALUs (256 CUs x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s)
-    roof = roofline(fl, by, ne, kern[dom], PEAK_F64, "alu", f"tri_p{dom}/fp64_split", dom_variant,
-                    f"k_split2<{dom},double,*> (2D entropy split, p={dom}, launch variant {dom_variant}), "
-                    f"{ne} elements per launch")
-    roof["work_note"] = ("4 d n_c n_p^2 operator flops + 500 flops per node pointwise; bytes: u, r, map nodes, "
-                         "face-node map, offset")
+    roof = roofline(fl / ne_b, by / ne_b, ne_b, kern_b, PEAK_F64, "alu", "tri_batch4/fwd",
+                    _variant(mb, "residual", 0),
+                    f"k_split2_batch<double> (2D entropy split, the four degrees p = 1..4 of the 32768-triangle "
+                    f"grid in one launch, {ne_b} elements)")
+    roof["work_note"] = ("per element of each degree: 4 d n_c n_p^2 operator flops + 500 flops per node pointwise; "
+                         "bytes: u, r, map nodes, face-node map, offset; work_per_element is the mean over the "
+                         "four degrees")
     out = dict(metric=METRIC, value=value, unit="elem-DOF/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=ms_per_step, higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f64", data="synthetic",
                config=dict(workload="2D Euler, curved periodic [0,20]^2 mesh 128x128x2 = 32768 triangles "
                                     "(P2 warp 0.05 L sin sin), isentropic vortex, entropy-split residual "
-                                    "with EC SATs, FP64, one residual for each p = 1,2,3,4 per step",
+                                    "with EC SATs, FP64, one residual for each p = 1,2,3,4 per step, the four "
+                                    "in one batched launch (one mesh of four independent copies of the grid)",
                            n_elem=ne, degrees=list(ps), n_p=n_p,
+                           step_kernel_ms=kern_b * 1e3,
                            kernel_ms={p: kern[p] * 1e3 for p in ps},
-                           kernel_ms_note=f"p={dom}: mean kernel duration of its launches in the timed "
-                                          f"region (first workgroup start to last workgroup end, recorded by "
-                                          f"the kernel on the device clock); other p: mean of back-to-back "
-                                          f"launches after the timed region",
-                           launch_shapes={p: tuned[p] for p in ps},
-                           step_shapes=step_shapes,
-                           step_shapes_note="residual shapes used in the timed step: the autotuner's, "
-                                            "then each degree's checked in the step itself"),
+                           kernel_ms_note="step_kernel_ms: mean duration of the step's one launch in the timed "
+                                          "region (first workgroup start to last workgroup end, recorded by the "
+                                          "kernel on the device clock); kernel_ms: each degree alone on its own "
+                                          "mesh, mean of back-to-back launches after the timed region",
+                           launch_shape=tuned_b,
+                           launch_shapes={p: tuned[p] for p in ps}),
                roofline=roof)
     if not args.no_extras:
         extras = tri_rows(R, desc, meshes, states, lams)
@@ -1063,6 +1053,7 @@ def main():
         out["cpu_baseline"] = cpu
     for p in ps:
         meshes[p].close()
+    mb.close()
     print(json.dumps(out))
 
 

@@ -289,10 +289,11 @@ int sbp_get_launch_shape(sbp_mesh *mesh, int32_t kind, int32_t p, int32_t *varia
 int sbp_set_launch_shape(sbp_mesh *mesh, int32_t kind, int32_t p, int32_t variant, int32_t grid);
 
 /* Launch timing (not in the paper; for benchmarks and profilers) of the
- * entropy-split residual kernel on triangles (meshes of one degree, Euler
- * terms).  sbp_time_launches(mesh, capacity): from now on every sbp_residual
- * call on the handle records the earliest workgroup start and the latest
- * workgroup end of its kernel on the device's constant-rate clock
+ * entropy-split residual kernels on triangles (Euler terms; one launch per
+ * degree class, or the one batched launch of a mesh of several degrees).
+ * sbp_time_launches(mesh, capacity): from now on every sbp_residual call on
+ * the handle records, per launch, the earliest workgroup start and the
+ * latest workgroup end of the kernel on the device's constant-rate clock
  * (hipDeviceAttributeWallClockRate), in call order, until capacity launches
  * are recorded; the kernel writes them itself, so the stream carries no
  * extra packets.  capacity 0 stops the recording; any call discards earlier

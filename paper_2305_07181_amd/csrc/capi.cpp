@@ -707,14 +707,19 @@ int residual_core(sbp_mesh *M, const Work &W, const double *u, void *r, double *
     sbp::KArgs<float> a32[4];
     const sbp::KArgs<double> *p64[4] = {nullptr, nullptr, nullptr, nullptr};
     const sbp::KArgs<float> *p32[4] = {nullptr, nullptr, nullptr, nullptr};
+    // launch timing: one slot for the one launch
+    unsigned long long *ts = nullptr;
+    if (M->timing_call && M->t_n < M->t_cap) ts = M->d_tstamp + 2 * (size_t)M->t_n++;
     for (auto &c : M->cls) {
       if (ph.precision == SBP_FP64) {
         a64[c.p - 1] = kargs<double>(M, c, u, r, c.op64);
         a64[c.p - 1].eform = M->eform;
+        a64[c.p - 1].tstamp = ts;
         p64[c.p - 1] = &a64[c.p - 1];
       } else {
         a32[c.p - 1] = kargs<float>(M, c, u, r, c.op32);
         a32[c.p - 1].eform = M->eform;
+        a32[c.p - 1].tstamp = ts;
         p32[c.p - 1] = &a32[c.p - 1];
       }
     }
@@ -1316,8 +1321,8 @@ int reset_tstamp(sbp_mesh *M) {
 int sbp_time_launches(sbp_mesh *M, int capacity) {
   if (!M || capacity < 0 || capacity > 65536) return fail(SBP_EINVAL, "null handle or capacity outside 0..65536");
   const sbp_physics &ph = M->phys;
-  if (capacity > 0 && (M->dim != 2 || ph.form != SBP_FORM_SPLIT || ph.viscous || M->batch_blocks > 0))
-    return fail(SBP_ENOTSUP, "launch timing covers the entropy-split kernel of meshes of triangles of one degree");
+  if (capacity > 0 && (M->dim != 2 || ph.form != SBP_FORM_SPLIT || ph.viscous))
+    return fail(SBP_ENOTSUP, "launch timing covers the entropy-split kernels of triangle meshes (Euler terms)");
   HIPCHK(hipDeviceSynchronize());
   (void)hipFree(M->d_tstamp);
   M->d_tstamp = nullptr;

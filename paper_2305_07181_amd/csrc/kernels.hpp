@@ -148,6 +148,7 @@ struct Batch2 {
   double *ubar;
   int g0[5];
   double *ent_part;  // [gridDim.x] partial sums of w^T H r (may be null)
+  unsigned long long *tstamp;  // launch timing as KArgs::tstamp, or null
 };
 
 // The argument block of class q of a batched launch with the call's pointers.

@@ -1197,6 +1197,7 @@ constexpr size_t split2_lds_max() {
 template <typename T>
 __global__ __launch_bounds__(kThreads, 2) void k_split2_batch(Batch2<T> Bt) {
   __shared__ __align__(16) unsigned char raw[split2_lds_max<T>()];
+  if (Bt.tstamp && threadIdx.x == 0) atomicMin(&Bt.tstamp[0], (unsigned long long)wall_clock64());
   double ent = 0.0;
   int cur = -1;
   for (int g = blockIdx.x; g < Bt.g0[4]; g += gridDim.x) {
@@ -1216,6 +1217,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_split2_batch(Batch2<T> Bt) {
     else Split2<4, T, split2_rows<4, T>(), 2>::tile_early(batch_args(Bt, 3), *(typename Split2<4, T, split2_rows<4, T>(), 2>::Lds *)raw, g - Bt.g0[3], ent);
   }
   block_sum_store(ent, Bt.ent_part);
+  if (Bt.tstamp && threadIdx.x == 0) atomicMax(&Bt.tstamp[1], (unsigned long long)wall_clock64());
 }
 
 // ---------------------------------------------------------------------------
@@ -2161,6 +2163,7 @@ static hipError_t launch_batch2_t(const KArgs<T> *const cls[4], const KArgs<T> *
   Bt.r = any->r;
   Bt.eform = any->eform;
   Bt.ent_part = ent_part;
+  Bt.tstamp = any->tstamp;
   const int nb = residual2_batch_blocks(ne, sizeof(T) == 8 ? 0 : 1, grid);
   hipLaunchKernelGGL((k_split2_batch<T>), dim3(nb), dim3(kThreads), 0, s, Bt);
   return hipGetLastError();

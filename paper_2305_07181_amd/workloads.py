@@ -407,6 +407,25 @@ def batch_mesh(specs, warp: float = 0.0):
     return desc, np.concatenate(degs), np.array(off, dtype=np.int32)
 
 
+def copies_mesh(desc: dict, degrees):
+    """One mesh description of len(degrees) independent copies of a 2D mesh
+    with quadratic maps (its own vertices per copy, the same period), copy b
+    of degree degrees[b].  Returns (desc, degree[n_elem], problem_off[n + 1])
+    as ``batch_mesh``."""
+    verts, elems, geoms, degs, off = [], [], [], [], [0]
+    nv = 0
+    for p in degrees:
+        verts.append(desc["vert_xyz"])
+        elems.append(desc["elem_vert"] + nv)
+        nv += len(desc["vert_xyz"])
+        geoms.append(desc["geom_nodes"])
+        degs.append(np.full(len(desc["elem_vert"]), p, dtype=np.int32))
+        off.append(off[-1] + len(desc["elem_vert"]))
+    out = dict(dim=2, vert_xyz=np.concatenate(verts), elem_vert=np.concatenate(elems).astype(np.int32),
+               period=desc["period"], p_geom=2, geom_nodes=np.concatenate(geoms))
+    return out, np.concatenate(degs), np.array(off, dtype=np.int32)
+
+
 def sub_mesh(desc: dict, lo: int, hi: int) -> dict:
     """Elements [lo, hi) of a batched description as a mesh of their own."""
     ev = desc["elem_vert"][lo:hi]

@@ -237,6 +237,48 @@ def test_jittered_state_plain_relative_error(kind, p):
         assert (err <= TOL64).all(), (form, err)
 
 
+def test_headline_four_degrees_one_launch():
+    """The benchmark's timed step: the 32768-triangle grid at p = 1..4 as four
+    independent copies in one mesh (one batched launch), tuned as the
+    benchmark does; sampled elements of every copy against the oracle (the
+    summed-term scale of the smooth vortex state) and the entropy rate of the
+    whole mesh (no dissipation: zero to rounding)."""
+    import torch
+    from oracle import physics as ph
+    from oracle.geometry import OracleMesh
+    from oracle.residual import OracleScheme
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say("[full headline, four degrees in one launch]")
+    desc = wl.vortex2d_mesh(128, warp=0.05)
+    ps = (1, 2, 3, 4)
+    d4, deg, off = wl.copies_mesh(desc, ps)
+    oms = {p: OracleMesh(desc, p) for p in ps}
+    us = {p: state(oms[p], "vortex") for p in ps}
+    mesh = sbp.Mesh(d4, deg, problem_off=off)
+    nc = int(mesh.n_c)
+    lo = [int(mesh.node_off[off[b]]) * nc for b in range(len(ps) + 1)]
+    u = np.concatenate([us[p].ravel() for p in ps])
+    assert all(lo[b + 1] - lo[b] == us[p].size for b, p in enumerate(ps))
+    ud = torch.from_numpy(u).cuda()
+    _tuned(mesh, ud)
+    r, er = mesh.residual(ud, entropy_rate=True)
+    mesh.check_device()
+    r = r.cpu().numpy()
+    scale = 0.0
+    for b, p in enumerate(ps):
+        m = oms[p]
+        sch = OracleScheme(m, ph.Gas())
+        els = _sample(m.ne, 12, 60 + p)
+        ro = sch(us[p], elements=els)
+        rp = r[lo[b]:lo[b + 1]].reshape(us[p].shape)
+        _check_sampled(rp, ro, sch, us[p], els, TOL64, f"copy {b} p={p}")
+        w = ph.entropy_vars(np.moveaxis(us[p], 1, 0), sch.gas)
+        scale += float(np.sum(m.H_all()[None] * np.abs(w) * np.abs(np.moveaxis(rp, 1, 0))))
+    say(f"   entropy rate {float(er.cpu()[0]):.3e}, scale {scale:.3e}")
+    assert abs(float(er.cpu()[0])) <= 1e-12 * scale
+    mesh.close()
+
+
 def test_ns_tgv82944_sampled():
     """The Navier-Stokes Taylor-Green grid, p = 3, Re = 1600, Pr = 0.71, heat
     flux and matrix dissipation: FP64 and FP32 residuals on sampled elements."""

@@ -40,9 +40,29 @@ def test_launch_times_record_the_residual_kernels():
         mesh.close()
 
 
+def test_launch_timing_batched_launch():
+    """A mesh of several degrees: one record per call (its one batched launch)."""
+    import torch
+    from oracle.geometry import OracleMesh
+    from paper_2305_07181_amd import sbp, workloads as wl
+    say("[timing] batched launch")
+    desc = wl.vortex2d_mesh(8, warp=0.05)
+    d4, deg, off = wl.copies_mesh(desc, (1, 3))
+    parts = [state(OracleMesh(desc, p), "random", seed=6 + p, jitter=0.01) for p in (1, 3)]
+    u = torch.from_numpy(np.concatenate([q.ravel() for q in parts])).cuda()
+    mesh = sbp.Mesh(d4, deg, problem_off=off)
+    r0 = mesh.residual(u)
+    mesh.time_launches(8)
+    rs = [mesh.residual(u) for _ in range(3)]
+    ms = mesh.launch_times()
+    assert len(ms) == 3 and (ms > 0).all()
+    assert all(torch.equal(r, r0) for r in rs)
+    mesh.check_device()
+    mesh.close()
+
+
 def test_launch_timing_refused_where_not_recorded():
-    """Tetrahedra, the Hadamard form and a batch of several degrees run other
-    kernels: SBP_ENOTSUP."""
+    """Tetrahedra and the Hadamard form run other kernels: SBP_ENOTSUP."""
     from paper_2305_07181_amd import sbp, workloads as wl
     say("[timing] refusals")
     cases = [(wl.periodic_tet_mesh(2, 1.0), 2, {}), (wl.vortex2d_mesh(4), 2, dict(form=sbp.FORM_HADAMARD))]
