@@ -91,6 +91,23 @@ __device__ __forceinline__ float dsqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double dabs(double x) { return fabs(x); }
 __device__ __forceinline__ float dabs(float x) { return fabsf(x); }
 
+// 1/x of a nonzero finite FP64 value by Newton's iteration on f(r) = 1/r - x,
+// r <- r + r (1 - x r), started from the hardware reciprocal estimate: each
+// step squares the relative error, and two leave the result within about one
+// unit in the last place.  Five dependent instructions in place of the
+// correctly rounded division sequence (about ten); the residual's quotients
+// of positive state quantities (1/rho, 1/p, 1/W_nc, 1/H, the averages'
+// denominators) take it.  FP32 keeps its division.
+__device__ __forceinline__ double drcp(double x) {
+  const double r0 = __builtin_amdgcn_rcp(x);
+  const double r1 = fma(r0, fma(-x, r0, 1.0), r0);
+  return fma(r1, fma(-x, r1, 1.0), r1);
+}
+__device__ __forceinline__ float drcp(float x) { return 1.0f / x; }
+// other arithmetic types (the dual numbers of the forward-mode derivatives)
+template <typename T>
+__device__ __forceinline__ T drcp(const T &x) { return (T)1 / x; }
+
 // Node quantities shared by the volume and facet terms.
 template <int D, typename T>
 struct Node {
@@ -107,7 +124,7 @@ template <int D, typename T>
 __device__ __forceinline__ void node_from_u(const T *u, const GasC<T> &G, Node<D, T> &n) {
   n.rho = u[0];
   T q2 = 0;
-  T irho = (T)1 / n.rho;
+  T irho = drcp(n.rho);
   n.irho = irho;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
@@ -185,7 +202,7 @@ __device__ __forceinline__ bool node_near(const T *u, const Node<D, T> &k, T irh
                                           const JumpC<T> &Jc, Node<D, T> &n) {
   n.rho = u[0];
   T q2 = 0;
-  const T irho = (T)1 / n.rho;
+  const T irho = drcp(n.rho);
   n.irho = irho;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
@@ -267,7 +284,7 @@ __device__ __forceinline__ void jvp_flux_sum(const Node<D, T> &n, const GasC<T> 
   T q2 = 0;
 #pragma unroll
   for (int k = 0; k < D; ++k) q2 += n.V[k] * n.V[k];
-  const T theta = n.p / n.rho;
+  const T theta = n.p * n.irho;
   const T c1 = G.gm1_a * iWn;  // (gamma-1)/(alpha W_nc)
   const T c2 = (-theta + (T)0.5 * G.gm1_a * q2) * iWn;
   const T ep = G.ggm1 * n.p + (T)0.5 * n.rho * q2;  // e + p
@@ -317,7 +334,7 @@ __device__ __forceinline__ constexpr T exp_avg_series_max() {
 template <typename T>
 __device__ __forceinline__ T exp_avg_ia(T a, T b, T ar, T br, T ia, const ExpAvgC<T> &C) {
   const T s = a + b;
-  const T eps = (a - b) / s;
+  const T eps = (a - b) * drcp(s);
   if (dabs(eps) <= exp_avg_series_max<T>()) {
     const T dl = (T)0.5 * (b - a) * ia;
     T bin = C.bn[8];
@@ -334,7 +351,7 @@ __device__ __forceinline__ T exp_avg_ia(T a, T b, T ar, T br, T ia, const ExpAvg
 template <typename T>
 __device__ __forceinline__ T exp_avg(T a, T b, T ar, T br, const ExpAvgC<T> &C) {
   const T s = a + b;
-  const T eps = (a - b) / s;
+  const T eps = (a - b) * drcp(s);
   if (dabs(eps) <= exp_avg_series_max<T>()) {
     const T ia = (T)1 / a;
     const T dl = (T)0.5 * (b - a) * ia;
@@ -362,7 +379,7 @@ __device__ __forceinline__ void facet_term_c(const Node<D, T> &k, const Node<D, 
   const T Ep = ip_k != (T)0 ? exp_avg_ia(k.p, v.p, P2k, P2v, ip_k, C2) : exp_avg(k.p, v.p, P2k, P2v, C2);
   const T Ez = iz1_k != (T)0 ? exp_avg_ia(k.z1, v.z1, P1k, P1v, iz1_k, C1) : exp_avg(k.z1, v.z1, P1k, P1v, C1);
   const T Dn = (T)0.5 * (P1k + P1v) * Ep;
-  const T iD = (T)1 / Dn;
+  const T iD = drcp(Dn);
   T an = 0;  // a . {z1 V} / D
   T Vav[D];
   T q2av = 0, Vav2 = 0;

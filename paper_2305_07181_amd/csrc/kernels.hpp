@@ -151,10 +151,33 @@ struct Batch2 {
   unsigned long long *tstamp;  // launch timing as KArgs::tstamp, or null
 };
 
+// A pointer read from memory, marked as one into global memory (the device
+// allocations of a mesh handle).  The compiler takes a pointer it loads for a
+// flat one, and flat loads also count against the LDS wait counter, so every
+// LDS wait would wait for them as well.  The route through an integer is one
+// the address-space inference follows and later passes do not fold away.
+template <typename P>
+__device__ __forceinline__ P *as_global(P *p) {
+  return (P *)(__attribute__((address_space(1))) P *)(unsigned long long)p;
+}
+
 // The argument block of class q of a batched launch with the call's pointers.
 template <typename T>
 __device__ __forceinline__ KArgs<T> batch_args(const Batch2<T> &Bt, int q) {
   KArgs<T> A = Bt.cls[q];
+  A.geo = as_global(A.geo);
+  A.nbr = as_global(A.nbr);
+  A.nbrq = as_global(A.nbrq);
+  A.uoff = as_global(A.uoff);
+  A.gid = as_global(A.gid);
+  A.Hn = as_global(A.Hn);
+  A.op.S = as_global(A.op.S);
+  A.op.h = as_global(A.op.h);
+  A.op.E = as_global(A.op.E);
+  A.op.dN = as_global(A.op.dN);
+  A.err = as_global(A.err);
+  A.eac = as_global(A.eac);
+  A.jc = as_global(A.jc);
   A.u = Bt.u;
   A.r = Bt.r;
   A.eform = Bt.eform;

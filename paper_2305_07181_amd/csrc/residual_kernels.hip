@@ -784,13 +784,19 @@ struct Split2 {
   // node rows of 16 values; element blocks padded by 4 values so that the
   // rows of the elements sharing a wave fall in different LDS banks
   static constexpr int NDS = NP * 16 + 4;
+  // S[j][i] = (S_0[i][j], S_1[i][j]): a row's two entries in one read, the
+  // rows of consecutive lanes at consecutive addresses
+  typedef HIP_vector_type<T, 2> T2;
   struct Lds {
-    T S[2][NP][NP];
+    T2 S[NP][NP];
     __align__(16) T nd[EB * NDS];  // per node: f0[4] f1[4] w[4] Lambda_00 _01 _10 _11
   };
 
   __device__ static __forceinline__ void load_ops(const KArgs<T> &A, Lds &L_) {
-    for (int x = threadIdx.x; x < 2 * NP * NP; x += kThreads) (&L_.S[0][0][0])[x] = A.op.S[x];
+    for (int x = threadIdx.x; x < NP * NP; x += kThreads) {
+      const int i = x / NP, j = x % NP;
+      L_.S[j][i] = T2(A.op.S[x], A.op.S[NP * NP + x]);
+    }
   }
 
   // Residual of the elements [tile*EB, tile*EB + EB); ent accumulates w^T H r.
@@ -851,13 +857,14 @@ struct Split2 {
       for (int q = 0; q < R; ++q)
 #pragma unroll
         for (int c = 0; c < NC; ++c) V[q][c] = X0[q][c] = X1[q][c] = (T)0;
-#pragma unroll 1
+#pragma unroll 2
       for (int j = 0; j < NP; ++j) {
         const T *v = L_.nd + e * NDS + j * 16;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
           const int i = k + q * L;
-          const T s0 = L_.S[0][i][j], s1 = L_.S[1][i][j];
+          const T2 sp = L_.S[j][i];
+          const T s0 = sp.x, s1 = sp.y;
           const T c0 = s0 * (lam[q][0] + v[12]) + s1 * (lam[q][1] + v[13]);
           const T c1 = s0 * (lam[q][2] + v[14]) + s1 * (lam[q][3] + v[15]);
 #pragma unroll
@@ -882,7 +889,7 @@ struct Split2 {
         // J = F_00 F_11 - F_01 F_10 in terms of the cofactors
         const T J = lam[q][3] * lam[q][0] - lam[q][2] * lam[q][1];
         const T H = J * (T)A.op.h[i];
-        const T iH = (T)1 / H;
+        const T iH = drcp(H);
         T r[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) r[c] = iH * (hv * V[q][c] + he * (avec[0] * v[c] + avec[1] * v[4 + c]));
@@ -1024,8 +1031,8 @@ struct Split2 {
         T f0[NC], f1[NC];
         node_from_u<D, T>(uu[q], A.G, n[q]);
         if (!n[q].ok) atomicOr(A.err, 1);
-        iWn[q] = (T)1 / n[q].w[NC - 1];
-        ipk[q] = (T)1 / n[q].p;
+        iWn[q] = drcp(n[q].w[NC - 1]);
+        ipk[q] = drcp(n[q].p);
         ith[q] = n[q].rho * ipk[q];
         flux_i<D, T>(n[q], uu[q][NC - 1], 0, f0);
         flux_i<D, T>(n[q], uu[q][NC - 1], 1, f1);
@@ -1090,13 +1097,14 @@ struct Split2 {
       for (int q = 0; q < R; ++q)
 #pragma unroll
         for (int c = 0; c < NC; ++c) V[q][c] = X0[q][c] = X1[q][c] = (T)0;
-#pragma unroll 1
+#pragma unroll 2
       for (int j = 0; j < NP; ++j) {
         const T *v = L_.nd + e * NDS + j * 16;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
           const int i = k + q * L;
-          const T s0 = L_.S[0][i][j], s1 = L_.S[1][i][j];
+          const T2 sp = L_.S[j][i];
+          const T s0 = sp.x, s1 = sp.y;
           const T c0 = s0 * (lam[q][0] + v[12]) + s1 * (lam[q][1] + v[13]);
           const T c1 = s0 * (lam[q][2] + v[14]) + s1 * (lam[q][3] + v[15]);
 #pragma unroll
@@ -1119,7 +1127,7 @@ struct Split2 {
         avec[1] = lam[q][2] * E0 + lam[q][3] * E1;
         const T J = lam[q][3] * lam[q][0] - lam[q][2] * lam[q][1];
         const T H = J * (T)A.op.h[i];
-        const T iH = (T)1 / H;
+        const T iH = drcp(H);
         T r[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) r[c] = iH * (hv * V[q][c] + he * (avec[0] * v[c] + avec[1] * v[4 + c]));
@@ -1195,7 +1203,7 @@ constexpr size_t split2_lds_max() {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads, 2) void k_split2_batch(Batch2<T> Bt) {
+__global__ __launch_bounds__(kThreads, sizeof(T) == 8 ? 2 : 3) void k_split2_batch(Batch2<T> Bt) {
   __shared__ __align__(16) unsigned char raw[split2_lds_max<T>()];
   if (Bt.tstamp && threadIdx.x == 0) atomicMin(&Bt.tstamp[0], (unsigned long long)wall_clock64());
   double ent = 0.0;
