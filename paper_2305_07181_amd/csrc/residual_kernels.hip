@@ -1191,8 +1191,10 @@ __global__ __launch_bounds__(kThreads, R == 2 ? 2 : (P == 1 ? 2 : 3)) void k_spl
 }
 
 // All degree classes of a 2D mesh (batched problems) in one persistent
-// launch: the tile index runs over the classes in degree order; a workgroup
-// restages the skew operators when its tile changes degree.
+// launch: the tile index runs over the classes from the highest degree down
+// (the costliest tiles are dispatched first and the launch ends on the
+// cheapest, which shortens its tail); a workgroup restages the skew
+// operators when its tile changes degree.
 template <typename T>
 constexpr size_t split2_lds_max() {
   size_t m = sizeof(typename Split2<1, T, split2_rows<1, T>()>::Lds);
@@ -1208,7 +1210,8 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 8 ? 2 : 3) void k_split2_bat
   if (Bt.tstamp && threadIdx.x == 0) atomicMin(&Bt.tstamp[0], (unsigned long long)wall_clock64());
   double ent = 0.0;
   int cur = -1;
-  for (int g = blockIdx.x; g < Bt.g0[4]; g += gridDim.x) {
+  for (int gi = blockIdx.x; gi < Bt.g0[4]; gi += gridDim.x) {
+    const int g = Bt.g0[4] - 1 - gi;
     const int q = g < Bt.g0[1] ? 0 : (g < Bt.g0[2] ? 1 : (g < Bt.g0[3] ? 2 : 3));
     if (q != cur) {
       __syncthreads();
