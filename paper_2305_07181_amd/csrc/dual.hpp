@@ -26,7 +26,7 @@ template <typename T> __device__ __forceinline__ Dual<T> operator-(Dual<T> a, Du
 template <typename T> __device__ __forceinline__ Dual<T> operator-(Dual<T> a) { return {-a.v, -a.d}; }
 template <typename T> __device__ __forceinline__ Dual<T> operator*(Dual<T> a, Dual<T> b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
 template <typename T> __device__ __forceinline__ Dual<T> operator/(Dual<T> a, Dual<T> b) {
-  const T ib = (T)1 / b.v;
+  const T ib = drcp(b.v);
   const T q = a.v * ib;
   return {q, (a.d - q * b.d) * ib};
 }
@@ -39,10 +39,10 @@ __device__ __forceinline__ Dual<double> dexp(Dual<double> a) {
   const double e = exp(a.v);
   return {e, e * a.d};
 }
-__device__ __forceinline__ Dual<double> dlog(Dual<double> a) { return {log(a.v), a.d / a.v}; }
+__device__ __forceinline__ Dual<double> dlog(Dual<double> a) { return {log(a.v), a.d * drcp(a.v)}; }
 __device__ __forceinline__ Dual<double> dsqrt(Dual<double> a) {
   const double s = sqrt(a.v);
-  return {s, a.d / (2.0 * s)};
+  return {s, 0.5 * a.d * drcp(s)};
 }
 // |x| with derivative sign(x) (0 at x = 0)
 __device__ __forceinline__ Dual<double> dabs(Dual<double> a) {

@@ -16,9 +16,9 @@ namespace sbp {
 __device__ __forceinline__ void exp_avg_d(double a, double b, double ar, double br, const ExpAvgC<double> &C,
                                           double &E, double &dE_da, double &dE_dar) {
   const double s = a + b;
-  const double eps = (a - b) / s;
+  const double eps = (a - b) * drcp(s);
   if (fabs(eps) <= 1e-2) {
-    const double ia = 1.0 / a;
+    const double ia = drcp(a);
     const double dl = 0.5 * (b - a) * ia;
     // B(dl) = 1 + dl q(dl), q = sum_k bn[k] dl^k (Horner with derivative)
     double q = C.bn[8], qd = 0.0;
@@ -59,7 +59,7 @@ __device__ __forceinline__ void facet_grad_rev(const Node<D, double> &k, const N
   exp_avg_d(k.p, v.p, P2k, P2v, G.e2, Ep, Ep_a, Ep_ar);
   exp_avg_d(k.z1, v.z1, P1k, P1v, G.e1, Ez, Ez_a, Ez_ar);
   const double Dn = 0.5 * (P1k + P1v) * Ep;
-  const double iD = 1.0 / Dn;
+  const double iD = drcp(Dn);
   double an = 0.0, Vav[D], Vav2 = 0.0, q2av = 0.0;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
@@ -250,7 +250,7 @@ __device__ __forceinline__ void facet_grad_rev(const Node<D, double> &k, const N
   // ---- backward through node_powers and node_from_u
   double blz1 = bP1 * G.r1 * P1k;
   double blp = bP2 * G.r2 * P2k;
-  const double irho = 1.0 / k.rho;
+  const double irho = drcp(k.rho);
   const double theta = k.p * irho;
   double q2 = 0.0;
 #pragma unroll

@@ -603,7 +603,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_split3c(KArgs<T> A) {
 #pragma unroll
         for (int k = 0; k < D; ++k) X[k][c] = (T)0;
       }
-#pragma unroll 1
+#pragma unroll (P >= 3 ? 2 : 1)
       for (int j = 0; j < NP; ++j) {
         const T s0 = -A.op.S[(0 * NP + j) * NP + i];
         const T s1 = -A.op.S[(1 * NP + j) * NP + i];

@@ -96,8 +96,8 @@ __global__ __launch_bounds__(kT, W) void k_vjp3v(KArgs<double> A) {
     __syncthreads();
     Node<D, double> n;
     const double *Lam = gs[act ? e : 0];
-    const double J = Lam[9], iJ = 1.0 / J;
-    const double h = A.op.h[i], ih = 1.0 / h, iH = iJ * ih;
+    const double J = Lam[9], iJ = drcp(J);
+    const double h = A.op.h[i], ih = drcp(h), iH = iJ * ih;
     if (act) {
       double uu[NC], lm[NC];
       const int uo = A.uoff[eg];
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kT, W) void k_vjp3v(KArgs<double> A) {
 #pragma unroll
         for (int l = 0; l < D; ++l) Z[l][c] = Gw[l][c] = 0.0;
       }
-#pragma unroll 1
+#pragma unroll (P >= 3 ? 2 : 1)
       for (int j = 0; j < NP; ++j) {
         double s0, s1, s2;
         if constexpr (SG) {
@@ -267,13 +267,18 @@ struct Vjp2 {
   static constexpr int EB = VTileV2<P>::EB;
   static_assert(EB * NP <= kT, "one node per lane");
   static constexpr int NDS = NP * 20 + 4;  // padded element blocks (LDS banks)
+  // S[k][j] = (S_0[j][k], S_1[j][k]): a row's two entries in one read, the
+  // rows of consecutive lanes at consecutive addresses
   struct Lds {
-    double S[2][NP][NP];
+    double2 S[NP][NP];
     double nd[EB * NDS];  // per node: mu[4] s_0[4] s_1[4] w[4] Lambda_00 _01 _10 _11
   };
 
   __device__ static __forceinline__ void load_ops(const KArgs<double> &A, Lds &L) {
-    for (int x = threadIdx.x; x < 2 * NP * NP; x += kT) (&L.S[0][0][0])[x] = A.op.S[x];
+    for (int x = threadIdx.x; x < NP * NP; x += kT) {
+      const int j = x / NP, k = x % NP;
+      L.S[k][j] = double2(A.op.S[x], A.op.S[NP * NP + x]);
+    }
   }
 
   __device__ static __forceinline__ void tile(const KArgs<double> &A, Lds &L, int tl) {
@@ -315,7 +320,7 @@ struct Vjp2 {
       if (!n.ok) atomicOr(A.err, 1);
 #pragma unroll
       for (int i = 0; i < D; ++i) jvp_flux<D, double>(n, G, i, lm, s[i]);
-      const double iH = 1.0 / H;
+      const double iH = drcp(H);
       double *v = L.nd + e * NDS + j * 20;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -332,9 +337,10 @@ struct Vjp2 {
       double Z0[NC], Z1[NC], Vs[NC], X0[NC], X1[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) Z0[c] = Z1[c] = Vs[c] = X0[c] = X1[c] = 0.0;
-#pragma unroll 1
+#pragma unroll 2
       for (int k = 0; k < NP; ++k) {
-        const double s0 = L.S[0][j][k], s1 = L.S[1][j][k];
+        const double2 sp = L.S[k][j];
+        const double s0 = sp.x, s1 = sp.y;
         const double *v = L.nd + e * NDS + k * 20;
         const double c0 = s0 * (lam[0] + v[16]) + s1 * (lam[1] + v[17]);
         const double c1 = s0 * (lam[2] + v[18]) + s1 * (lam[3] + v[19]);
@@ -362,7 +368,7 @@ struct Vjp2 {
       double ak[D];
       ak[0] = lam[0] * E0 + lam[1] * E1;
       ak[1] = lam[2] * E0 + lam[3] * E1;
-      const double iH = 1.0 / H;
+      const double iH = drcp(H);
       double ub[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) ub[c] = 0.0;
@@ -573,7 +579,7 @@ __global__ __launch_bounds__(kT, W) void k_vjp3c(KArgs<double> A) {
       if (!n.ok) atomicOr(A.err, 1);
 #pragma unroll
       for (int i = 0; i < D; ++i) jvp_flux<D, double>(n, G, i, lm, s[i]);
-      const double iH = 1.0 / H;
+      const double iH = drcp(H);
       double *v = nd + e * NDS + j * NV;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -596,7 +602,7 @@ __global__ __launch_bounds__(kT, W) void k_vjp3c(KArgs<double> A) {
 #pragma unroll
         for (int m = 0; m < D; ++m) Z[m][c] = X[m][c] = 0.0;
       }
-#pragma unroll 1
+#pragma unroll (P >= 3 ? 2 : 1)
       for (int k = 0; k < NP; ++k) {
         const double s0 = -A.op.S[(0 * NP + k) * NP + j];
         const double s1 = -A.op.S[(1 * NP + k) * NP + j];
@@ -625,7 +631,7 @@ __global__ __launch_bounds__(kT, W) void k_vjp3c(KArgs<double> A) {
         for (int l = 0; l < D; ++l) t += L[m][l] * A.op.E[l * NP + j];
         ak[m] = t;
       }
-      const double iH = 1.0 / H;
+      const double iH = drcp(H);
       double ub[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) ub[c] = 0.0;
@@ -805,7 +811,7 @@ __global__ __launch_bounds__(kT) void k_vjp_had(KArgs<double> A) {
       nd[D + 1][e][a] = n.z1;
       nd[D + 2][e][a] = n.P1;
       nd[D + 3][e][a] = n.P2;
-      const double iH = 1.0 / H;
+      const double iH = drcp(H);
 #pragma unroll
       for (int c = 0; c < NC; ++c) nd[NV + c][e][a] = lm[c] * iH;
 #pragma unroll
@@ -1074,7 +1080,7 @@ __global__ __launch_bounds__(kT) void k_vjpv_pre(KArgs<double> A, double *sb) {
         for (int l = 0; l < D; ++l) t += L[k][l] * A.op.E[l * NP + i];
         a[k] = t;
       }
-      const double iH = 1.0 / H;
+      const double iH = drcp(H);
 #pragma unroll
       for (int k = 0; k < D; ++k)
 #pragma unroll
@@ -1169,7 +1175,7 @@ __global__ __launch_bounds__(kT) void k_vjpv(KArgs<double> A, const double *sb) 
         for (int l = 0; l < D; ++l) t += L[k][l] * A.op.E[l * NP + i];
         a[k] = t;
       }
-      const double iH = 1.0 / H;
+      const double iH = drcp(H);
       double g[D][NC], al[D][NC], nu[D][NC], ze[D][NC];
 #pragma unroll
       for (int k = 0; k < D; ++k)
