@@ -1,8 +1,10 @@
 """sbp_residual_noalloc (the residual for callers that cannot allocate: its
 scratch lives in the library's static device array) against sbp_residual:
 two calls in a row, the second on a smaller mesh, bitwise equal residuals
-and entropy rates; the hybrid flags and the manufactured source (whose
-entropy rate uses the node partials in the same array) included."""
+and entropy rates; the hybrid flags, the manufactured source (whose
+entropy rate uses the node partials in the same array) and a mesh of four
+degree classes (one batched launch, its per-workgroup partials in the same
+array) included."""
 import numpy as np
 import pytest
 
@@ -19,6 +21,38 @@ def _pair(mesh, u, **kw):
     mesh.residual_noalloc(u, r, e)
     torch.cuda.synchronize()
     return r_ref, e_ref, r, e
+
+
+def _batch_state(mesh, off):
+    """Vortex state on each copy of a mesh of grid copies (workloads.copies_mesh)."""
+    from paper_2305_07181_amd import workloads as wl
+    x = mesh.node_coords().cpu().numpy()
+    u = np.zeros(int(mesh.n_nodes * mesh.n_c))
+    for b in range(len(off) - 1):
+        n_p = int(mesh.elem_np[off[b]])
+        e0, e1 = int(off[b]), int(off[b + 1])
+        lo, hi = int(mesh.node_off[e0]), int(mesh.node_off[e1])
+        X = np.moveaxis(x[lo * 2:hi * 2].reshape(e1 - e0, 2, n_p), 1, 0)
+        rho, V, pr = wl.isentropic_vortex(X)
+        u[lo * 4:hi * 4] = np.moveaxis(wl.conservative(rho, V, pr), 0, 1).ravel()
+    return u
+
+
+def test_noalloc_batched_launch_two_calls():
+    import torch
+    from paper_2305_07181_amd import sbp, workloads as wl
+    for n in (8, 4):                    # second call: a smaller input
+        say(f"[noalloc] tri-batch p=1..4 n={n}")
+        desc, deg, off = wl.copies_mesh(wl.vortex2d_mesh(n, warp=0.05), (1, 2, 3, 4))
+        mesh = sbp.Mesh(desc, deg, problem_off=off)
+        u = _batch_state(mesh, off)
+        ud = torch.from_numpy(u * (1 + 0.01 * np.random.default_rng(n).standard_normal(u.shape))).cuda()
+        r_ref, e_ref, r, e = _pair(mesh, ud)
+        mesh.check_device()
+        assert torch.equal(r, r_ref), float((r - r_ref).abs().max())
+        assert torch.equal(e, e_ref), (float(e), float(e_ref))
+        say("   bitwise equal; entropy rate", float(e))
+        mesh.close()
 
 
 @pytest.mark.parametrize("case", ["tri-split", "tet-hybrid", "tet-ns-source"])
