@@ -46,88 +46,88 @@ PEAK_F32 = 157.3e12        # FLOP/s (vector and dense MFMA)
 # `bench.py --probe-kernels`, calibrated against a plain device copy; see
 # profiles/hbm_bytes_all_families.md), keyed "<row>/<name>/v<variant>".
 # Valid only for the kernel sources they were taken on (TRAFFIC_SHA).
-TRAFFIC_SHA = "2a575da308c50363"
+TRAFFIC_SHA = "3af9f721533f8a49"
 TRAFFIC = {
-    "batch48/fwd/v0": 2.878e+08,
+    "batch48/fwd/v0": 1.999e+08,
     "batch48/vjp/v0": 5.152e+08,
     "jitter_p1/fp64_split/v0": 2.56e+07,
     "jitter_p1/fp64_split/v1": 1.731e+07,
-    "jitter_p1/fp64_split/v2": 2.599e+07,
+    "jitter_p1/fp64_split/v2": 2.581e+07,
     "jitter_p2/fp64_split/v0": 2.654e+07,
     "jitter_p2/fp64_split/v1": 2.638e+07,
-    "jitter_p2/fp64_split/v2": 2.674e+07,
+    "jitter_p2/fp64_split/v2": 2.676e+07,
     "jitter_p3/fp64_split/v0": 4.416e+07,
     "jitter_p3/fp64_split/v1": 4.398e+07,
-    "jitter_p3/fp64_split/v2": 4.435e+07,
+    "jitter_p3/fp64_split/v2": 4.448e+07,
     "jitter_p4/fp64_split/v0": 5.323e+07,
     "jitter_p4/fp64_split/v1": 5.305e+07,
-    "jitter_p4/fp64_split/v2": 5.397e+07,
-    "ns_tgv_82944_p3/fp32_residual/v0": 7.988e+08,
+    "jitter_p4/fp64_split/v2": 5.396e+07,
+    "ns_tgv_82944_p3/fp32_residual/v0": 7.99e+08,
     "ns_tgv_82944_p3/fp64_residual/v0": 1.23e+09,
-    "ns_tgv_82944_p3/fp64_vjp/v0": 5.227e+09,
+    "ns_tgv_82944_p3/fp64_vjp/v0": 5.228e+09,
     "tet_p2_tgv_196608/fp32_split/v0": 6.686e+08,
-    "tet_p2_tgv_196608/fp32_split/v1": 6.987e+08,
-    "tet_p2_tgv_196608/fp64_hadamard/v0": 7.248e+08,
-    "tet_p2_tgv_196608/fp64_split/v0": 7.291e+08,
-    "tet_p2_tgv_196608/fp64_split/v1": 7.297e+08,
-    "tet_p2_tgv_196608/fp64_vjp/v0": 3.115e+09,
-    "tet_p2_tgv_196608/fp64_vjp/v1": 1.341e+09,
-    "tet_p2_tgv_196608_curved/fp32_split/v0": 7.256e+08,
+    "tet_p2_tgv_196608/fp32_split/v1": 6.979e+08,
+    "tet_p2_tgv_196608/fp64_hadamard/v0": 7.25e+08,
+    "tet_p2_tgv_196608/fp64_split/v0": 7.29e+08,
+    "tet_p2_tgv_196608/fp64_split/v1": 7.296e+08,
+    "tet_p2_tgv_196608/fp64_vjp/v0": 3.121e+09,
+    "tet_p2_tgv_196608/fp64_vjp/v1": 1.34e+09,
+    "tet_p2_tgv_196608_curved/fp32_split/v0": 7.267e+08,
     "tet_p2_tgv_196608_curved/fp64_hadamard/v0": 7.22e+08,
     "tet_p2_tgv_196608_curved/fp64_split/v0": 7.618e+08,
     "tet_p2_tgv_196608_curved/fp64_vjp/v0": 1.373e+09,
-    "tet_p2_tgv_196608_curved/fp64_vjp/v1": 5.801e+09,
-    "tet_p3_tgv_196608/fp32_split/v0": 1.146e+09,
+    "tet_p2_tgv_196608_curved/fp64_vjp/v1": 5.8e+09,
+    "tet_p3_tgv_196608/fp32_split/v0": 1.147e+09,
     "tet_p3_tgv_196608/fp32_split/v1": 1.192e+09,
-    "tet_p3_tgv_196608/fp64_hadamard/v0": 1.243e+09,
+    "tet_p3_tgv_196608/fp64_hadamard/v0": 1.242e+09,
     "tet_p3_tgv_196608/fp64_split/v0": 1.393e+09,
     "tet_p3_tgv_196608/fp64_split/v1": 1.386e+09,
-    "tet_p3_tgv_196608/fp64_vjp/v0": 6.806e+09,
+    "tet_p3_tgv_196608/fp64_vjp/v0": 6.811e+09,
     "tet_p3_tgv_196608/fp64_vjp/v1": 2.419e+09,
     "tet_p3_tgv_196608_curved/fp32_split/v0": 1.181e+09,
-    "tet_p3_tgv_196608_curved/fp64_hadamard/v0": 1.277e+09,
+    "tet_p3_tgv_196608_curved/fp64_hadamard/v0": 1.276e+09,
     "tet_p3_tgv_196608_curved/fp64_split/v0": 1.426e+09,
     "tet_p3_tgv_196608_curved/fp64_vjp/v0": 2.453e+09,
     "tet_p3_tgv_196608_curved/fp64_vjp/v1": 1.413e+10,
-    "tri_batch4/fwd/v0": 2.045e+08,
-    "tri_p1/fp32_split/v0": 2.245e+07,
+    "tri_batch4/fwd/v0": 1.437e+08,
+    "tri_p1/fp32_split/v0": 2.244e+07,
     "tri_p1/fp32_split/v1": 2.246e+07,
     "tri_p1/fp32_split/v2": 2.23e+07,
     "tri_p1/fp64_hadamard/v0": 2.603e+07,
     "tri_p1/fp64_hadamard_vjp/v0": 4.681e+07,
     "tri_p1/fp64_split/v0": 2.556e+07,
     "tri_p1/fp64_split/v1": 1.73e+07,
-    "tri_p1/fp64_split/v2": 2.6e+07,
-    "tri_p1/fp64_vjp/v0": 1.235e+08,
+    "tri_p1/fp64_split/v2": 2.601e+07,
+    "tri_p1/fp64_vjp/v0": 1.238e+08,
     "tri_p1/fp64_vjp/v1": 4.688e+07,
-    "tri_p2/fp32_split/v0": 3.559e+07,
+    "tri_p2/fp32_split/v0": 3.562e+07,
     "tri_p2/fp32_split/v1": 2.106e+07,
     "tri_p2/fp32_split/v2": 3.355e+07,
-    "tri_p2/fp64_hadamard/v0": 4.083e+07,
+    "tri_p2/fp64_hadamard/v0": 4.084e+07,
     "tri_p2/fp64_hadamard_vjp/v0": 7.22e+07,
     "tri_p2/fp64_split/v0": 2.65e+07,
     "tri_p2/fp64_split/v1": 2.636e+07,
     "tri_p2/fp64_split/v2": 2.672e+07,
-    "tri_p2/fp64_vjp/v0": 7.503e+07,
+    "tri_p2/fp64_vjp/v0": 7.502e+07,
     "tri_p2/fp64_vjp/v1": 7.224e+07,
-    "tri_p3/fp32_split/v0": 3.542e+07,
+    "tri_p3/fp32_split/v0": 3.536e+07,
     "tri_p3/fp32_split/v1": 3.445e+07,
     "tri_p3/fp32_split/v2": 3.455e+07,
-    "tri_p3/fp64_hadamard/v0": 6.65e+07,
+    "tri_p3/fp64_hadamard/v0": 6.654e+07,
     "tri_p3/fp64_hadamard_vjp/v0": 1.182e+08,
     "tri_p3/fp64_split/v0": 4.413e+07,
     "tri_p3/fp64_split/v1": 4.397e+07,
     "tri_p3/fp64_split/v2": 4.437e+07,
     "tri_p3/fp64_vjp/v0": 1.214e+08,
     "tri_p3/fp64_vjp/v1": 1.183e+08,
-    "tri_p4/fp32_split/v0": 4.299e+07,
+    "tri_p4/fp32_split/v0": 4.282e+07,
     "tri_p4/fp32_split/v1": 4.141e+07,
     "tri_p4/fp32_split/v2": 4.15e+07,
-    "tri_p4/fp64_hadamard/v0": 7.072e+07,
+    "tri_p4/fp64_hadamard/v0": 7.07e+07,
     "tri_p4/fp64_hadamard_vjp/v0": 1.215e+08,
     "tri_p4/fp64_split/v0": 5.319e+07,
     "tri_p4/fp64_split/v1": 5.304e+07,
-    "tri_p4/fp64_split/v2": 5.414e+07,
+    "tri_p4/fp64_split/v2": 5.413e+07,
     "tri_p4/fp64_vjp/v0": 1.248e+08,
     "tri_p4/fp64_vjp/v1": 1.216e+08,
 }

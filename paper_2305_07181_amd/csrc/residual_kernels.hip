@@ -1191,10 +1191,8 @@ __global__ __launch_bounds__(kThreads, R == 2 ? 2 : (P == 1 ? 2 : 3)) void k_spl
 }
 
 // All degree classes of a 2D mesh (batched problems) in one persistent
-// launch: the tile index runs over the classes from the highest degree down
-// (the costliest tiles are dispatched first and the launch ends on the
-// cheapest, which shortens its tail); a workgroup restages the skew
-// operators when its tile changes degree.
+// launch; a workgroup restages the skew operators when its tile changes
+// degree.
 template <typename T>
 constexpr size_t split2_lds_max() {
   size_t m = sizeof(typename Split2<1, T, split2_rows<1, T>()>::Lds);
@@ -1210,9 +1208,42 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 8 ? 2 : 3) void k_split2_bat
   if (Bt.tstamp && threadIdx.x == 0) atomicMin(&Bt.tstamp[0], (unsigned long long)wall_clock64());
   double ent = 0.0;
   int cur = -1;
-  for (int gi = blockIdx.x; gi < Bt.g0[4]; gi += gridDim.x) {
-    const int g = Bt.g0[4] - 1 - gi;
-    const int q = g < Bt.g0[1] ? 0 : (g < Bt.g0[2] ? 1 : (g < Bt.g0[3] ? 2 : 3));
+  // Tile order: with a grid that is a multiple of the XCD count, each XCD
+  // takes a contiguous share of every degree class (the facet neighbours of
+  // its elements then mostly sit in its own L2), chains its shares from the
+  // highest degree down (the costliest tiles first, the launch's tail made
+  // of the cheapest), and its workgroups deal the chain round-robin, so the
+  // work per workgroup is even to one tile whatever the classes cost.
+  const bool xa = gridDim.x % kXcds == 0;
+  const int nx = xa ? kXcds : 1, x = xa ? blockIdx.x % kXcds : 0;
+  const int lg = gridDim.x / nx, lb = xa ? blockIdx.x / kXcds : blockIdx.x;
+  int beg[4], len[4], total = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int n = Bt.g0[c + 1] - Bt.g0[c];
+    const int per = (n + nx - 1) / nx;
+    beg[c] = min(n, x * per);
+    len[c] = min(n, beg[c] + per) - beg[c];
+    total += len[c];
+  }
+  for (int pos = lb; pos < total; pos += lg) {
+    // the class of chain position pos (pos < total, so one of the four)
+    int q, t = pos;
+    if (t < len[3]) {
+      q = 3;
+      t += beg[3];
+    } else if ((t -= len[3]) < len[2]) {
+      q = 2;
+      t += beg[2];
+    } else if ((t -= len[2]) < len[1]) {
+      q = 1;
+      t += beg[1];
+    } else {
+      t -= len[1];
+      q = 0;
+      t += beg[0];
+    }
+    const int g = Bt.g0[q] + t;
     if (q != cur) {
       __syncthreads();
       if (q == 0) Split2<1, T, split2_rows<1, T>()>::load_ops(batch_args(Bt, 0), *(typename Split2<1, T, split2_rows<1, T>()>::Lds *)raw);
